@@ -1,0 +1,223 @@
+"""CPU oracle for the 2D vortex-particle FMM evaluation -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never does: it must not
+route through the oracle or fall back to the CPU.
+
+The arithmetic lives in ``fmm_oracle.c`` (plain FP64 C, OpenMP over independent
+outputs), written from Knepley, "Removing the Barrier to Scalability in Parallel
+FMM" (arXiv:1008.2410).  This wrapper only marshals numpy arrays and, for the
+adjoint (O4), combines oracle outputs per the chain rule.
+
+Levels (see the C file's header for the readings of points the paper leaves open):
+  direct        O1  exact O(N^2) regularised Biot-Savart sum (eqs. regB-S2DGau,
+                    discBiotS2D)
+  split_direct  O2  exact kernel on the 3x3 leaf neighbourhood, singular kernel
+                    elsewhere (the far-field substitution after eq. discBiotS2D)
+  fmm           O3  FMM stages 1-10 (Fig. fmmStages), unscaled textbook operators
+  fmm_grad      O4  gradient of L(u) through O3: dL/dGamma and dL/dx_eval
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "fmm_oracle.c")
+_lib = None
+
+ORC_OK, ORC_EINVAL, ORC_ENOMEM, ORC_ERANGE = 0, -1, -2, -4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = False) -> str:
+    """Compile fmm_oracle.c with gcc into liboracle.so (in place)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", _SO + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        Ci = ctypes.c_int
+        lib.orc_root_box.argtypes = [I64, P, P]
+        lib.orc_root_box.restype = None
+        lib.orc_bin.argtypes = [I64, P, Ci, P, P, P]
+        lib.orc_direct.argtypes = [I64, P, I64, P, P, D, P]
+        lib.orc_direct.restype = None
+        lib.orc_split_direct.argtypes = [I64, P, P, P, I64, P, P, P, P, D, P]
+        lib.orc_split_direct.restype = None
+        lib.orc_fmm.argtypes = [I64, P, P, I64, P, D, Ci, P, Ci, P, P]
+        lib.orc_fmm_jacobian.argtypes = [I64, P, P, I64, P, D, Ci, P, Ci, P, P]
+        lib.orc_leaf_counts.argtypes = [I64, P, Ci, P, P]
+        lib.orc_cover_level.argtypes = [Ci, Ci, Ci, Ci, Ci]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _check(rc: int, what: str):
+    if rc != ORC_OK:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def root_box(xy) -> tuple:
+    xy = _f64(xy, (-1, 2))
+    out = np.zeros(3)
+    _load().orc_root_box(xy.shape[0], _ptr(xy), _ptr(out))
+    return tuple(float(v) for v in out)
+
+
+def resolve_root(xy, root) -> tuple:
+    return root_box(xy) if root is None else tuple(float(v) for v in root)
+
+
+def bin_leaves(xy, depth: int, root=None):
+    """Leaf coordinates (ix, iy) of each point (stage 2)."""
+    xy = _f64(xy, (-1, 2))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    ix = np.zeros(xy.shape[0], dtype=np.int32)
+    iy = np.zeros(xy.shape[0], dtype=np.int32)
+    _check(_load().orc_bin(xy.shape[0], _ptr(xy), depth, _ptr(r), _ptr(ix), _ptr(iy)), "orc_bin")
+    return ix, iy
+
+
+def leaf_counts(xy, depth: int, root=None) -> np.ndarray:
+    """Particles per leaf, shape (2^L, 2^L) indexed [iy, ix]."""
+    xy = _f64(xy, (-1, 2))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    c = np.zeros((1 << depth) * (1 << depth), dtype=np.int64)
+    _check(_load().orc_leaf_counts(xy.shape[0], _ptr(xy), depth, _ptr(r), _ptr(c)), "orc_leaf_counts")
+    return c.reshape(1 << depth, 1 << depth)
+
+
+def cover_level(depth: int, t: tuple, s: tuple) -> int:
+    return int(_load().orc_cover_level(depth, t[0], t[1], s[0], s[1]))
+
+
+def direct(xy, gamma, sigma: float, targets=None) -> np.ndarray:
+    """O1: velocities (N_t, 2) at ``targets`` (default: the particles themselves)."""
+    xy = _f64(xy, (-1, 2))
+    g = _f64(gamma, (-1,))
+    t = xy if targets is None else _f64(targets, (-1, 2))
+    uv = np.zeros((t.shape[0], 2))
+    _load().orc_direct(t.shape[0], _ptr(t), xy.shape[0], _ptr(xy), _ptr(g), float(sigma), _ptr(uv))
+    return uv
+
+
+def split_direct(xy, gamma, sigma: float, depth: int, root=None, targets=None) -> np.ndarray:
+    """O2: exact kernel for sources in the target leaf's 3x3 neighbourhood, singular kernel
+    (1/|z|^2 form) for all other sources."""
+    xy = _f64(xy, (-1, 2))
+    g = _f64(gamma, (-1,))
+    r = resolve_root(xy, root)
+    t = xy if targets is None else _f64(targets, (-1, 2))
+    six, siy = bin_leaves(xy, depth, r)
+    tix, tiy = bin_leaves(t, depth, r)
+    uv = np.zeros((t.shape[0], 2))
+    _load().orc_split_direct(t.shape[0], _ptr(t), _ptr(tix), _ptr(tiy), xy.shape[0], _ptr(xy),
+                             _ptr(six), _ptr(siy), _ptr(g), float(sigma), _ptr(uv))
+    return uv
+
+
+def charges(gamma) -> np.ndarray:
+    """Complex charges c_j = -i Gamma_j / (2 pi) (the factor of the multipole coefficients)."""
+    return (-1j / (2.0 * math.pi)) * np.asarray(gamma, dtype=np.float64)
+
+
+def fmm(xy, q, sigma: float, depth: int, p: int, root=None, targets=None):
+    """O3 with complex charges q: returns (W_near, W_far), complex arrays of the conjugate
+    velocity W = u - i v at the targets (default: the particles)."""
+    xy = _f64(xy, (-1, 2))
+    qc = np.ascontiguousarray(q, dtype=np.complex128)
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    t = xy if targets is None else _f64(targets, (-1, 2))
+    wn = np.zeros(t.shape[0], dtype=np.complex128)
+    wf = np.zeros(t.shape[0], dtype=np.complex128)
+    _check(_load().orc_fmm(xy.shape[0], _ptr(xy), _ptr(qc), t.shape[0], _ptr(t), float(sigma), depth,
+                           _ptr(r), p, _ptr(wn), _ptr(wf)), "orc_fmm")
+    return wn, wf
+
+
+def w_to_uv(w: np.ndarray) -> np.ndarray:
+    """Stage 10 output convention: (u, v) = (Re W, -Im W)."""
+    return np.stack([w.real, -w.imag], axis=1)
+
+
+def fmm_velocity(xy, gamma, sigma: float, depth: int, p: int, root=None, targets=None,
+                 parts: bool = False):
+    """O3 velocities (N_t, 2): stage 10 sums the near and far parts."""
+    wn, wf = fmm(xy, charges(gamma), sigma, depth, p, root, targets)
+    if parts:
+        return w_to_uv(wn), w_to_uv(wf)
+    return w_to_uv(wn + wf)
+
+
+def fmm_jacobian(xy, gamma, sigma: float, depth: int, p: int, root=None, targets=None):
+    """d(u, v)/d(x, y) of the O3 field at the targets with the sources fixed, as
+    (J_near, J_far), each (N_t, 2, 2) with J[i] = [[du/dx, du/dy], [dv/dx, dv/dy]]."""
+    xy = _f64(xy, (-1, 2))
+    g = _f64(gamma, (-1,))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    t = xy if targets is None else _f64(targets, (-1, 2))
+    jn = np.zeros((t.shape[0], 4))
+    jf = np.zeros((t.shape[0], 4))
+    _check(_load().orc_fmm_jacobian(xy.shape[0], _ptr(xy), _ptr(g), t.shape[0], _ptr(t), float(sigma),
+                                    depth, _ptr(r), p, _ptr(jn), _ptr(jf)), "orc_fmm_jacobian")
+    return jn.reshape(-1, 2, 2), jf.reshape(-1, 2, 2)
+
+
+def fmm_grad(xy, gamma, sigma: float, depth: int, p: int, dl_duv, root=None):
+    """O4: gradient of a loss L(u) through the O3 velocities at the particles.
+
+    dl_duv (N, 2) holds dL/du_i, dL/dv_i.  With q_i = dL/du_i + i dL/dv_i, the FMM
+    operator A (W = A c) is antisymmetric (A_ij = -A_ji: symmetric neighbour and
+    interaction lists, square truncation l, m < p, exact M2M/L2L), so the transpose
+    pass is the same FMM run with charges q, and
+        dL/dGamma_j = Re( sum_i q_i A_ij (-i/2pi) ) = -Im( (A q)_j ) / (2 pi).
+    dL/dx_eval_i = J_i^T dL/duv_i with J the Jacobian of (u, v) at the evaluation
+    point (sources held fixed).
+    Returns (dL/dGamma (N,), dL/dx_eval (N, 2))."""
+    g = np.asarray(dl_duv, dtype=np.float64).reshape(-1, 2)
+    q = g[:, 0] + 1j * g[:, 1]
+    wn, wf = fmm(xy, q, sigma, depth, p, root)
+    dgamma = -(wn + wf).imag / (2.0 * math.pi)
+    jn, jf = fmm_jacobian(xy, gamma, sigma, depth, p, root)
+    jac = jn + jf
+    dx = np.einsum("nij,ni->nj", jac, g)
+    return dgamma, dx
+
+
+def pair_count(counts: np.ndarray) -> int:
+    """Ordered near-field pairs (j != i) summed over targets: sum_T n_T sum_{S in N(T)} n_S - N."""
+    c = np.asarray(counts, dtype=np.int64)
+    pad = np.pad(c, 1)
+    n1 = c.shape[0]
+    nb = sum(pad[1 + a:1 + a + n1, 1 + b:1 + b + n1] for a in (-1, 0, 1) for b in (-1, 0, 1))
+    return int((c * nb).sum() - c.sum())

@@ -1,0 +1,298 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a closed-form
+flow, an exact invariant, a count the paper prints, brute force, or the
+convergence behaviour the method guarantees.  A dropped term, a wrong sign or
+index, or a transposed operand anywhere in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+from paper_1008_2410_amd import workloads as W
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------------------
+# O1: the regularised kernel and the direct sum (eqs. zeta, regB-S2DGau, discBiotS2D)
+# ---------------------------------------------------------------------------------------
+
+def test_single_blob_is_gaussian_vortex(oracle_mod):
+    """One Gaussian blob of eq. zeta with circulation G at the origin: by Stokes' theorem the
+    circulation enclosed by a circle of radius r is G (1 - exp(-r^2/(2 sigma^2))), so the flow
+    is azimuthal (counter-clockwise for G > 0) with speed G (1 - exp(-r^2/(2 sigma^2)))/(2 pi r)."""
+    sigma, G = 0.07, 1.7
+    r = np.array([1e-3, 0.01, 0.05, 0.07, 0.1, 0.3, 1.0, 5.0])
+    th = np.linspace(0.3, 5.9, r.size)
+    tgt = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    uv = oracle_mod.direct(np.zeros((1, 2)), np.array([G]), sigma, targets=tgt)
+    speed = G * (1.0 - np.exp(-r * r / (2 * sigma * sigma))) / (2 * math.pi * r)
+    expect = np.stack([-np.sin(th) * speed, np.cos(th) * speed], axis=1)
+    np.testing.assert_allclose(uv, expect, rtol=1e-13, atol=0)
+
+
+def test_point_vortex_limit(oracle_mod):
+    """Far from the core the blob acts as a point vortex: u = G/(2 pi r) e_theta."""
+    sigma, G = 1e-4, -0.3
+    tgt = np.array([[0.3, 0.4], [-1.0, 2.0]])
+    uv = oracle_mod.direct(np.array([[0.0, 0.0]]), np.array([G]), sigma, targets=tgt)
+    r = np.hypot(tgt[:, 0], tgt[:, 1])
+    expect = G / (2 * math.pi * r * r)[:, None] * np.stack([-tgt[:, 1], tgt[:, 0]], axis=1)
+    np.testing.assert_allclose(uv, expect, rtol=1e-14)
+
+
+def test_lamb_oseen_lattice_closed_form(oracle_mod):
+    """Lamb-Oseen vorticity omega = exp(-r^2/a)/(a pi), a = 0.01, sampled on an unjittered
+    lattice with Gamma_i = omega(x_i) h^2 and blobs of core sigma = 1.5h.  The blob-smoothed
+    vorticity is the convolution of two Gaussians, itself Lamb-Oseen with a' = a + 2 sigma^2,
+    whose velocity is u_theta(r) = (1 - exp(-r^2/a'))/(2 pi r); the lattice quadrature error
+    decays like exp(-2 pi^2 (sigma/h)^2), far below roundoff."""
+    w = W.lattice_lamb_oseen(side=256, jitter=0.0)
+    t = rng(7).uniform(0.35, 0.65, size=(64, 2))
+    uv = oracle_mod.direct(w.xy, w.gamma, w.sigma, targets=t)
+    d = t - 0.5
+    r = np.hypot(d[:, 0], d[:, 1])
+    a2 = W.LAMB_OSEEN_RC2 + 2 * w.sigma ** 2
+    speed = (1.0 - np.exp(-r * r / a2)) / (2 * math.pi * r)
+    expect = np.stack([-d[:, 1] / r * speed, d[:, 0] / r * speed], axis=1)
+    assert rel_l2(uv, expect) < 1e-12
+
+
+def test_linear_impulse_invariant(oracle_mod):
+    """sum_i Gamma_i u_i = 0: each pair's contributions cancel because K(-z) = -K(z).
+    Holds to roundoff for O1, O2 and for O3 (antisymmetric truncated FMM operator)."""
+    w = W.uniform_lamb_oseen(n=2000, seed=11)
+    g = w.gamma * np.where(rng(3).random(w.n) < 0.5, -1.0, 1.0)   # signed field
+    results = {
+        "O1": oracle_mod.direct(w.xy, g, w.sigma),
+        "O2": oracle_mod.split_direct(w.xy, g, w.sigma, 4, w.root_box),
+        "O3p6": oracle_mod.fmm_velocity(w.xy, g, w.sigma, 4, 6, w.root_box),
+        "O3p13": oracle_mod.fmm_velocity(w.xy, g, w.sigma, 5, 13, w.root_box),
+    }
+    for name, uv in results.items():
+        imp = (g[:, None] * uv).sum(axis=0)
+        scale = (np.abs(g)[:, None] * np.abs(uv)).sum()
+        assert np.abs(imp).max() < 1e-14 * scale, name
+
+
+# ---------------------------------------------------------------------------------------
+# O2 / O3: the FMM
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("depth,n", [(2, 64), (3, 200), (4, 600)])
+def test_fmm_brute_force_high_order(oracle_mod, depth, n):
+    """At p = 30 the truncated expansions reproduce the split direct sum (O2) -- exact kernel
+    near, singular kernel far -- to near roundoff.  Depth 2 exercises M2L alone; depths 3-4
+    add the M2M and L2L chains."""
+    r = rng(100 + depth)
+    xy = r.random((n, 2))
+    g = r.standard_normal(n)
+    sigma = 0.02
+    o2 = oracle_mod.split_direct(xy, g, sigma, depth, (0.0, 0.0, 1.0))
+    o3 = oracle_mod.fmm_velocity(xy, g, sigma, depth, 30, (0.0, 0.0, 1.0))
+    assert rel_l2(o3, o2) < 1e-11
+
+
+def test_fmm_truncation_decays_geometrically(oracle_mod):
+    """rel-L2(O3(p), O2) falls geometrically in p (the far series converge at a rate set by
+    the separation of interaction-list cells); fitted ratio per order < 0.6 and monotone."""
+    w = W.uniform_lamb_oseen(n=3000, seed=21)
+    o2 = oracle_mod.split_direct(w.xy, w.gamma, w.sigma, 4, w.root_box)
+    ps = np.arange(4, 21, 2)
+    errs = np.array([rel_l2(oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, 4, int(p), w.root_box), o2)
+                     for p in ps])
+    assert np.all(np.diff(errs) < 0), errs
+    slope = np.polyfit(ps, np.log(errs), 1)[0]
+    assert math.exp(slope) < 0.6, math.exp(slope)
+
+
+def test_near_far_split_matches_direct_when_all_near(oracle_mod):
+    """Depth 1: every leaf is adjacent to every other, so the FMM is the exact direct sum."""
+    r = rng(5)
+    xy = r.random((300, 2))
+    g = r.standard_normal(300)
+    o1 = oracle_mod.direct(xy, g, 0.05)
+    o3 = oracle_mod.fmm_velocity(xy, g, 0.05, 1, 8, (0.0, 0.0, 1.0))
+    assert rel_l2(o3, o1) < 1e-14
+
+
+def test_kernel_substitution_small_when_boxes_large(oracle_mod):
+    """The far field uses the singular kernel; the substitution error shrinks as the leaf
+    width grows relative to sigma (the condition stated after eq. discBiotS2D)."""
+    w = W.uniform_lamb_oseen(n=4096)
+    o1 = oracle_mod.direct(w.xy, w.gamma, w.sigma)
+    errs = [rel_l2(oracle_mod.split_direct(w.xy, w.gamma, w.sigma, d, w.root_box), o1) for d in (4, 3, 2)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-9
+
+
+# ---------------------------------------------------------------------------------------
+# Tree: binning, lists, pair counts (section "Complexity Estimates")
+# ---------------------------------------------------------------------------------------
+
+def paper_pair_count(L: int, B: int) -> int:
+    """Pairs per the direct-work formula of section "Complexity Estimates" (without the
+    22-flop factor): corner boxes 4(4B^2 - B), side boxes (2^{L+2} - 8)(6B^2 - B), interior
+    boxes (4^L - 2^{L+2} + 4)(9B^2 - B)."""
+    return 4 * (4 * B * B - B) + (2 ** (L + 2) - 8) * (6 * B * B - B) + (4 ** L - 2 ** (L + 2) + 4) * (9 * B * B - B)
+
+
+@pytest.mark.parametrize("side,depth", [(64, 4), (1024, 8)])
+def test_pair_count_matches_paper_formula(oracle_mod, side, depth):
+    """The jittered lattice puts exactly B = side^2/4^L particles in every leaf, the
+    setting of the paper's direct-work count."""
+    w = W.lattice_lamb_oseen(side=side, depth=depth)
+    c = oracle_mod.leaf_counts(w.xy, depth, w.root_box)
+    B = side * side // 4 ** depth
+    assert np.all(c == B)
+    assert oracle_mod.pair_count(c) == paper_pair_count(depth, B)
+    if side == 1024:
+        assert paper_pair_count(8, 16) == 149_160_960
+
+
+def test_interaction_lists_partition_the_far_field(oracle_mod):
+    """For every target leaf, every source leaf is reached exactly once: in the near field
+    or in the interaction list of exactly one ancestor pair.  The list of a cell has at most
+    27 members (section "Complexity Estimates"), and interior cells reach 27."""
+    L = 4
+    n1 = 1 << L
+    max_il = 0
+    for tx in range(n1):
+        for ty in range(n1):
+            per_level = {}
+            for sx in range(n1):
+                for sy in range(n1):
+                    lvl = oracle_mod.cover_level(L, (tx, ty), (sx, sy))
+                    assert lvl == 0 or 2 <= lvl <= L, (tx, ty, sx, sy, lvl)
+                    if lvl >= 2:
+                        per_level[lvl] = per_level.get(lvl, 0) + 1
+            for lvl, nleaf in per_level.items():
+                ncell = nleaf // 4 ** (L - lvl)
+                assert nleaf % 4 ** (L - lvl) == 0
+                assert ncell <= 27
+                max_il = max(max_il, ncell)
+    assert max_il == 27
+
+
+def test_binning_edges(oracle_mod):
+    """Floor binning: a point on an internal edge goes to the higher cell, the top edge is
+    clamped into the last cell, a point outside the root is an error."""
+    root = (0.0, 0.0, 1.0)
+    xy = np.array([[0.25, 0.5], [1.0, 1.0], [0.0, 0.0], [0.999, 0.001]])
+    ix, iy = oracle_mod.bin_leaves(xy, 2, root)
+    assert ix.tolist() == [1, 3, 0, 3]
+    assert iy.tolist() == [2, 3, 0, 0]
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.bin_leaves(np.array([[1.0 + 1e-12, 0.5]]), 2, root)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.bin_leaves(np.array([[-1e-300, 0.5]]), 2, root)
+
+
+def test_root_box_bounding_square(oracle_mod):
+    xy = np.array([[0.2, -1.0], [0.7, 3.0], [0.3, 0.0]])
+    x0, y0, s = oracle_mod.root_box(xy)
+    assert (x0, y0) == (0.2, -1.0)
+    assert s == 4.0 * (1 + 2 ** -20)
+    ix, iy = oracle_mod.bin_leaves(xy, 3, None)
+    assert iy.max() == 7 and iy.min() == 0
+
+
+# ---------------------------------------------------------------------------------------
+# O4: the adjoint
+# ---------------------------------------------------------------------------------------
+
+def _loss(oracle_mod, xy, g, sigma, depth, p, root, ustar, targets=None):
+    uv = oracle_mod.fmm_velocity(xy, g, sigma, depth, p, root, targets=targets)
+    return 0.5 * ((uv - ustar) ** 2).sum(), uv
+
+
+def test_adjoint_gamma_matches_central_differences(oracle_mod):
+    """u is linear in Gamma, so L = 0.5|u - u*|^2 is quadratic and a central difference in
+    Gamma_k equals dL/dGamma_k up to roundoff."""
+    w = W.uniform_lamb_oseen(n=700, seed=31, depth=3, p=8)
+    ustar = W.smooth_target_field(w.xy, seed=3)
+    uv = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box)
+    dg, _ = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, uv - ustar, w.root_box)
+    for k in rng(9).choice(w.n, 6, replace=False):
+        h = 1e-3 * abs(w.gamma[k]) + 1e-6
+        gp, gm = w.gamma.copy(), w.gamma.copy()
+        gp[k] += h
+        gm[k] -= h
+        lp, _ = _loss(oracle_mod, w.xy, gp, w.sigma, w.depth, w.p, w.root_box, ustar)
+        lm, _ = _loss(oracle_mod, w.xy, gm, w.sigma, w.depth, w.p, w.root_box, ustar)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - dg[k]) <= 1e-7 * abs(dg[k]) + 1e-12, (k, fd, dg[k])
+
+
+def test_adjoint_dot_product(oracle_mod):
+    """Antisymmetry of the discrete FMM operator: sum_i q_i (A c)_i = -sum_j (A q)_j c_j."""
+    r = rng(41)
+    n, depth, p = 900, 4, 9
+    xy = r.random((n, 2))
+    c = r.standard_normal(n) + 1j * r.standard_normal(n)
+    q = r.standard_normal(n) + 1j * r.standard_normal(n)
+    ac = sum(oracle_mod.fmm(xy, c, 0.01, depth, p, (0, 0, 1)))
+    aq = sum(oracle_mod.fmm(xy, q, 0.01, depth, p, (0, 0, 1)))
+    lhs = (q * ac).sum()
+    rhs = -(aq * c).sum()
+    assert abs(lhs - rhs) < 1e-13 * (np.abs(q * ac).sum())
+
+
+def test_adjoint_positions_match_central_differences(oracle_mod):
+    """dL/dx_eval against central differences of the O3 field at a moved evaluation point
+    with the sources held fixed; points within 10h of a leaf edge are skipped because the
+    FMM field jumps there by construction."""
+    w = W.uniform_lamb_oseen(n=800, seed=51, depth=3, p=10)
+    ustar = W.smooth_target_field(w.xy, seed=5)
+    uv = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box)
+    _, dx = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, uv - ustar, w.root_box)
+    h = 1e-6
+    wl = 1.0 / 2 ** w.depth
+    checked = 0
+    for k in rng(13).permutation(w.n):
+        if checked == 8:
+            break
+        frac = (w.xy[k] / wl) % 1.0
+        if np.any(np.minimum(frac, 1 - frac) * wl < 10 * h):
+            continue
+        for comp in (0, 1):
+            tp = w.xy[k:k + 1].copy()
+            tm = w.xy[k:k + 1].copy()
+            tp[0, comp] += h
+            tm[0, comp] -= h
+            up = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box, targets=tp)
+            um = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box, targets=tm)
+            lp = 0.5 * ((up[0] - ustar[k]) ** 2).sum()
+            lm = 0.5 * ((um[0] - ustar[k]) ** 2).sum()
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - dx[k, comp]) <= 1e-6 * np.abs(dx[k]).max() + 1e-12, (k, comp, fd, dx[k, comp])
+        checked += 1
+    assert checked == 8
+
+
+def test_adjoint_positions_tiny_direct(oracle_mod):
+    """Six particles, depth 1 (all near): dL/dx_eval, including the smooth self-kernel slope
+    1/(4 pi sigma^2), against central differences of O1 at a moved evaluation point."""
+    r = rng(61)
+    xy = r.random((6, 2))
+    g = r.standard_normal(6)
+    sigma = 0.3
+    ustar = r.standard_normal((6, 2))
+    uv = oracle_mod.fmm_velocity(xy, g, sigma, 1, 5, (0, 0, 1))
+    _, dx = oracle_mod.fmm_grad(xy, g, sigma, 1, 5, uv - ustar, (0, 0, 1))
+    h = 1e-6
+    for k in range(6):
+        for comp in (0, 1):
+            tp = xy[k:k + 1].copy()
+            tm = xy[k:k + 1].copy()
+            tp[0, comp] += h
+            tm[0, comp] -= h
+            up = oracle_mod.direct(xy, g, sigma, targets=tp)[0]
+            um = oracle_mod.direct(xy, g, sigma, targets=tm)[0]
+            fd = (0.5 * ((up - ustar[k]) ** 2).sum() - 0.5 * ((um - ustar[k]) ** 2).sum()) / (2 * h)
+            assert abs(fd - dx[k, comp]) < 1e-7 * max(1.0, abs(fd)), (k, comp, fd, dx[k, comp])
