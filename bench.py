@@ -1,0 +1,197 @@
+"""Benchmark: FMM velocity evaluation throughput on one MI355X.
+
+Workload: 2^24 particles drawn from 8 signed Gaussian vortex patches, blob core
+sigma = 0.01/64, uniform quadtree depth 10 over the bounding square, p = 16 terms,
+mixed precision (FP32 near field and fine-level far field, FP64 coarse levels and
+final sum), coarse levels overlapped with the near field on a second HIP stream.
+A step is one fmm_velocity call (stages 4-10) with the particles, circulations and
+tree already resident in HBM; the tree build (stages 1-3) is outside the timed
+region.
+
+Prints one JSON line (see the README of the repository root for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+# Published MI355X peaks used for the roofline fractions.
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+P2P_FLOPS_PER_PAIR = 22           # section "Complexity Estimates": 9 complex division, 1 exp
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cpu_baseline_leg(w, sample_frac_log4=1):
+    """The CPU oracle on the machine's host cores: (1) accuracy gate of the GPU result on the
+    4096-particle subsample, (2) throughput of the oracle's full FMM (stages 1-10) on a
+    bounded sample of the workload: the first N/4^k particles of the (shuffled) draw with
+    the tree depth lowered by k, which keeps the particles per leaf of the full problem."""
+    import oracle
+    oracle.build()
+    idx = w.extra["sample"]
+    t0 = time.perf_counter()
+    ref = oracle.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, None, targets=w.xy[idx])
+    t_gate = time.perf_counter() - t0
+    k = sample_frac_log4
+    ns = w.n >> (2 * k)
+    xs, gs = w.xy[:ns], w.gamma[:ns]
+    t0 = time.perf_counter()
+    oracle.fmm_velocity(xs, gs, w.sigma, w.depth - k, w.p, None)
+    t_run = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return ref, t_gate, {
+        "value": ns / t_run / 1e6,
+        "unit": "Mparticles/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"oracle FMM stages 1-10 (FP64 C, OpenMP) on the first {ns} particles of the same draw, "
+                  f"depth {w.depth - k}, p={w.p} (same particles per leaf); {t_run:.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--depth", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1008_2410_amd import _lib, fmm, workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = workloads.gaussian_patches(n=args.n, depth=args.depth)
+    log(f"[bench] workload generated: N={w.n} depth={w.depth} p={w.p} ({time.perf_counter() - t0:.1f} s)")
+    xy = torch.from_numpy(w.xy).to(dev)
+    gamma = torch.from_numpy(w.gamma).to(dev)
+    t0 = time.perf_counter()
+    tree = fmm.Tree(xy, w.depth, None)
+    info = tree.info()
+    log(f"[bench] tree built in {time.perf_counter() - t0:.1f} s: {info}")
+    out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
+
+    def run(k, precision="mixed"):
+        for _ in range(k):
+            tree.velocity(gamma, w.sigma, w.p, precision, out=out)
+
+    def timed(k, precision="mixed", timing=True):
+        tree.set_option(_lib.FMM_OPT_TIMING, 1 if timing else 0)
+        tree.timings()  # reset
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(k, precision)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        st = tree.timings()
+        tree.set_option(_lib.FMM_OPT_TIMING, 0)
+        per = {kk: (v / st["calls"] if st["calls"] else None) for kk, v in st.items() if kk != "calls"}
+        return ms, per
+
+    # warmup
+    run(args.warmup)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    # timed region: overlapped schedule
+    ms, stages = timed(args.steps)
+    log(f"[bench] mixed overlap: {ms:.3f} ms/step, stages {stages}")
+    # serial schedule of the same work, for the overlap fraction
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 1)
+    run(1)
+    ms_serial, stages_serial = timed(args.steps)
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 0)
+    log(f"[bench] mixed serial: {ms_serial:.3f} ms/step, stages {stages_serial}")
+    # overlap fraction: how much of the shorter of P2P / far field is hidden, from the
+    # serial stage times and the overlapped span between the pack and final stages
+    t_p2p, t_far = stages_serial["p2p"], stages_serial["far"]
+    t_both = stages["total"] - stages["pack"] - stages["final"]
+    overlap = (t_p2p + t_far - t_both) / min(t_p2p, t_far) if min(t_p2p, t_far) > 0 else None
+    # accuracy sample of the mixed result
+    run(1)
+    uv_mixed = out.cpu().numpy()
+    # plain FP64 GPU FMM at the same configuration
+    run(1, "fp64")
+    ms_fp64, stages_fp64 = timed(args.fp64_steps, "fp64")
+    uv_fp64 = out.cpu().numpy()
+    log(f"[bench] fp64: {ms_fp64:.3f} ms/step, stages {stages_fp64}")
+
+    idx = w.extra["sample"]
+    cpu = None
+    err_mixed = err_fp64 = None
+    if not args.no_cpu:
+        ref, t_gate, cpu = cpu_baseline_leg(w)
+        err_mixed = rel_l2(uv_mixed[idx], ref)
+        err_fp64 = rel_l2(uv_fp64[idx], ref)
+        log(f"[bench] oracle gate: mixed rel-L2 {err_mixed:.3e}, fp64 {err_fp64:.3e} ({t_gate:.1f} s); cpu {cpu}")
+    err_mixed_vs_fp64 = rel_l2(uv_mixed[idx], uv_fp64[idx])
+
+    pairs = info["p2p_pairs"]
+    p2p_ms = stages["p2p"]
+    achieved = P2P_FLOPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
+    value = w.n / (ms * 1e-3) / 1e6
+    rec = {
+        "metric": "Mparticles/s FMM velocity eval, N=16M, p=16, rel-L2<=1e-5 vs FP64; bwd/fwd",
+        "value": round(value, 3),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "gaussian_patches", "n": w.n, "patches": 8, "sigma": w.sigma, "depth": w.depth,
+                   "p": w.p, "precision": "mixed", "schedule": "overlap", "root": "bounding square"},
+        "roofline": {"bound": "alu", "kernel": "p2p_forward_kernel<float>", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": None, "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                     "avg_launch_ms": round(p2p_ms, 4)},
+        "cpu_baseline": cpu,
+        "accuracy": {"mixed_vs_oracle_rel_l2": err_mixed, "fp64_vs_oracle_rel_l2": err_fp64,
+                     "mixed_vs_gpu_fp64_rel_l2": err_mixed_vs_fp64,
+                     "sample": len(idx), "gate": 1e-5},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "serial_ms_per_step": round(ms_serial, 4),
+        "serial_stages_ms": {k: round(v, 4) for k, v in stages_serial.items()},
+        "overlap_fraction": None if overlap is None else round(overlap, 4),
+        "fp64": {"ms_per_step": round(ms_fp64, 4), "value": round(w.n / (ms_fp64 * 1e-3) / 1e6, 3),
+                 "stages_ms": {k: round(v, 4) for k, v in stages_fp64.items()}},
+        "tree": info,
+    }
+    if err_mixed is not None and err_mixed > 1e-5:
+        rec["value_invalid_reason"] = f"mixed rel-L2 {err_mixed:.3e} exceeds 1e-5"
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

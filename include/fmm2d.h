@@ -1,0 +1,171 @@
+/*
+ * fmm2d.h -- C ABI of the MI355X (gfx950) evaluation phase of the 2D vortex-particle
+ * fast multipole method of M. G. Knepley, "Removing the Barrier to Scalability in
+ * Parallel FMM" (arXiv:1008.2410).
+ *
+ * Problem (section "Test problem"): N vortex particles at z_j = x_j + i y_j carry
+ * circulations Gamma_j and Gaussian blobs of core sigma (eqs. omega, zeta).  The
+ * velocity at each particle is
+ *     u(z_i) = sum_{j != i} Gamma_j K_sigma(z_i - z_j)                 (eq. discBiotS2D)
+ *     K_sigma(z) = (1/(2 pi |z|^2)) (-z_y, z_x) (1 - exp(-|z|^2/(2 sigma^2)))
+ *                                                                      (eq. regB-S2DGau)
+ * evaluated by the FMM on a uniform quadtree: the exact kernel on each leaf's 3x3
+ * leaf neighbourhood (near field, stage 9 of Fig. fmmStages) and p-term expansions
+ * of the singular 1/|z|^2 kernel elsewhere (far field, stages 4-8; the substitution
+ * is stated after eq. discBiotS2D).  Stage 10 sums the two.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers (HIP global memory on the current
+ *    device) owned by the caller, unless a comment says "host".  Positions are
+ *    (n, 2) row-major FP64 (x0, y0, x1, y1, ...); velocities likewise (u, v).
+ *  - Streams are hipStream_t passed as void*; NULL means the null stream.  Work is
+ *    enqueued asynchronously; no call synchronises the host unless stated.
+ *  - Every entry point returns FMM_OK or a negative status and never aborts.  On
+ *    failure fmm_last_error() returns a message (thread-local) and the outputs are
+ *    unspecified but never partly scattered: the user-order outputs are written by
+ *    the last kernel of a call.
+ *  - A tree handle may be used by one host thread at a time; a concurrent call on
+ *    the same handle returns FMM_ESTATE.  Different handles are independent.
+ *  - Inputs are never modified.
+ */
+#ifndef FMM2D_H
+#define FMM2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_tree fmm_tree;
+
+enum {
+    FMM_OK = 0,
+    FMM_EINVAL = -1,  /* bad argument: null pointer, n < 1, depth or p out of range, bad sigma */
+    FMM_ENOMEM = -2,  /* device or host allocation failed */
+    FMM_EDEVICE = -3, /* a HIP runtime call or kernel launch failed */
+    FMM_ERANGE = -4,  /* a particle lies outside the root cell */
+    FMM_ESTATE = -5   /* handle busy in another thread, or invalid handle */
+};
+
+/* Arithmetic of fmm_velocity / fmm_velocity_backward. */
+enum {
+    FMM_FP64 = 0,  /* every stage in FP64 */
+    FMM_MIXED = 1  /* P2P, P2M, fine-level M2M/M2L/L2L and L2P in FP32 on radius-scaled
+                      coefficients; coarse-level M2M/M2L/L2L and the near+far sum in FP64 */
+};
+
+/* Options for fmm_set_option. */
+enum {
+    FMM_OPT_SCHEDULE = 1,     /* 0: far field on a second stream, concurrent with P2P (default);
+                                 1: everything serialised on the main stream */
+    FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in one
+                                 single-workgroup kernel in FP64 (default 4, range 1..depth) */
+    FMM_OPT_TIMING = 3        /* 1: record HIP events around each stage of every call for
+                                 fmm_get_timings (default 0) */
+};
+
+/* Stage indices of fmm_get_timings. */
+enum {
+    FMM_T_PACK = 0,     /* a0: gather circulations into Morton order */
+    FMM_T_FAR = 1,      /* stages 4-7: P2M, M2M, M2L, L2L (side stream) */
+    FMM_T_P2P = 2,      /* stage 9: near-field direct sum (main stream) */
+    FMM_T_FINAL = 3,    /* stages 8 + 10: L2P, near+far sum, scatter to user order */
+    FMM_T_TOTAL = 4,    /* whole call, first to last kernel */
+    FMM_T_COUNT = 5
+};
+
+/*
+ * Stages 1-3 of Fig. fmmStages: tree construction, particle binning, interaction
+ * lists.  Builds a uniform quadtree of depth L (4^L leaves, section "Complexity
+ * Estimates") over n particles and keeps everything later calls need.
+ *   xy        device, (n, 2) FP64 positions in user order; read once.
+ *   n         1 <= n < 2^31.
+ *   depth     1 <= depth <= 12.
+ *   root_box  host, {x0, y0, side} of the root cell, or NULL for the bounding square
+ *             x0 = min x, y0 = min y, side = max(range x, range y) * (1 + 2^-20).
+ *   stream    stream on which xy is valid.
+ *   out       receives the handle; free it with fmm_destroy_tree.
+ * Leaf of a particle: (min(floor((x - x0)/w), 2^L - 1), same for y), w = side/2^L;
+ * a particle outside [x0, x0 + side]^2 gives FMM_ERANGE, a non-finite one FMM_EINVAL.
+ * The build runs on the host (the positions are copied down once) and synchronises
+ * `stream`; the tree owns its device buffers, and workspace for each (p, precision)
+ * is allocated on first use and kept until fmm_destroy_tree.
+ */
+int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                   fmm_tree **out);
+
+/* Host-side facts about a tree (any pointer may be NULL):
+ *   n, depth, root_box[3] (host);
+ *   p2p_pairs       ordered near-field pairs sum_T n_T sum_{S in N(T)} n_S - n, the pair
+ *                   count of the direct-work formula of section "Complexity Estimates";
+ *   m2l_pairs       (target, source) cell pairs of the interaction lists, levels 2..L,
+ *                   with both cells non-empty;
+ *   nonempty_leaves, max_leaf  occupancy of the leaf level. */
+int fmm_tree_info(const fmm_tree *tree, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
+                  int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf);
+
+/* Morton order of the tree.  perm: device, n int64, perm[k] = user index of the k-th
+ * particle in leaf-Morton order (stable inside a leaf).  leaf: device, n int32 or NULL,
+ * leaf[k] = Morton index of that particle's leaf (x in the even bits). */
+int fmm_tree_permutation(const fmm_tree *tree, int64_t *perm, int32_t *leaf, void *stream);
+
+/*
+ * Stages 4-10: velocity of every particle.
+ *   gamma       device, n FP64 circulations (user order).
+ *   sigma       blob core, finite, > 0.
+ *   p           expansion terms, 1 <= p <= 32 (coefficients m = 0..p-1).
+ *   precision   FMM_FP64 or FMM_MIXED.
+ *   main_stream P2P, pack and the final sum run here; the call is ordered after prior
+ *               work on it, and later work on it sees the result.
+ *   side_stream far-field stream (NULL: the tree's own non-blocking stream); the
+ *               library forks it from main_stream and joins it back with events.
+ *   uv          device, (n, 2) FP64 velocities (u, v) in user order.
+ */
+int fmm_velocity(fmm_tree *tree, const double *gamma, double sigma, int p, int precision, void *main_stream,
+                 void *side_stream, double *uv);
+
+/* As fmm_velocity, but the near field (stage 9) and far field (stage 8) velocities are
+ * written separately, each (n, 2) FP64 in user order, so that each stage can be checked. */
+int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
+                       void *main_stream, void *side_stream, double *uv_near, double *uv_far);
+
+/*
+ * Adjoint of fmm_velocity for a loss L(u): given dL/du (device, (n, 2) FP64, user
+ * order) returns
+ *   dl_dgamma  device, n FP64:  dL/dGamma_j = -Im((A q)_j)/(2 pi), q_i = dL/du_i + i dL/dv_i,
+ *              where A is the FMM operator (W = u - iv = A c, c_j = -i Gamma_j/(2 pi)),
+ *              exactly antisymmetric for square truncation, so A^T q = -A q is one
+ *              more FMM pass with complex charges q;
+ *   dl_dxeval  device, (n, 2) FP64: derivative with respect to the evaluation
+ *              positions with the sources held fixed: near part from the derivative of
+ *              eq. regB-S2DGau (the particle's own blob included, slope 1/(4 pi sigma^2)),
+ *              far part from the derivative of the local expansion.
+ * Either output may be NULL to skip it.  Other arguments as fmm_velocity.  The paper
+ * has no backward pass; this is the transpose of the discrete operator defined by
+ * stages 4-10.
+ */
+int fmm_velocity_backward(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
+                          const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
+                          double *dl_dxeval);
+
+/* Set an FMM_OPT_* option on a tree.  FMM_EINVAL for an unknown key or bad value. */
+int fmm_set_option(fmm_tree *tree, int key, int64_t value);
+
+/* Per-stage device time (milliseconds, from HIP events on the stream each stage runs
+ * on) summed over the calls made since the last fmm_get_timings with FMM_OPT_TIMING
+ * on.  ms: host, FMM_T_COUNT doubles; calls: host, receives the number of calls.
+ * Synchronises the recorded events; resets the sums. */
+int fmm_get_timings(fmm_tree *tree, double *ms, int64_t *calls);
+
+/* Free a tree and its device memory (synchronises the device first).  NULL is a no-op. */
+void fmm_destroy_tree(fmm_tree *tree);
+
+/* Message for the last failed call on this host thread ("" if none). */
+const char *fmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM2D_H */

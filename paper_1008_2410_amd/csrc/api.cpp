@@ -1,0 +1,635 @@
+// C ABI of the gfx950 FMM library (include/fmm2d.h): argument checks, the host-side
+// tree build (stages 1-3 of Fig. fmmStages), workspace management and the two-stream
+// schedule of stages 4-10.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm2d.h"
+#include "fmm_internal.h"
+
+using namespace fmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(FMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
+    } while (0)
+
+template <typename T>
+int dev_alloc(T **p, size_t count, const char *what)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(FMM_ENOMEM, std::string("device allocation failed: ") + what);
+    }
+    return FMM_OK;
+}
+
+template <typename T>
+int upload(T **p, const std::vector<T> &h, const char *what)
+{
+    int rc = dev_alloc(p, h.size(), what);
+    if (rc) return rc;
+    if (!h.empty()) HIP_TRY(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FMM_OK;
+}
+
+// RAII guard for "one host thread per handle".
+struct BusyGuard {
+    fmm_tree *t;
+    bool ok;
+    explicit BusyGuard(fmm_tree *tree) : t(tree), ok(tree->busy.exchange(1) == 0) {}
+    ~BusyGuard()
+    {
+        if (ok) t->busy.store(0);
+    }
+};
+
+void free_workspace(Workspace &ws)
+{
+    hipFree(ws.rec);
+    hipFree(ws.near);
+    hipFree(ws.mp_d);
+    hipFree(ws.lo_d);
+    hipFree(ws.mp_f);
+    hipFree(ws.lo_f);
+    hipFree(ws.adj);
+    hipFree(ws.bwd_near);
+    hipFree(ws.bwd_b);
+    hipFree(ws.mp2_d);
+    hipFree(ws.lo2_d);
+    hipFree(ws.mp2_f);
+    hipFree(ws.lo2_f);
+    hipFree(ws.rec2);
+    ws = Workspace{};
+}
+
+void free_tree(fmm_tree *t)
+{
+    hipFree(t->d_perm);
+    hipFree(t->d_leaf_of);
+    hipFree(t->d_xy);
+    hipFree(t->d_leaf_start);
+    hipFree(t->d_counts);
+    hipFree(t->d_lists);
+    hipFree(t->d_units);
+    free_workspace(t->ws);
+    free_tables(t->tabs);
+    if (t->own_side) hipStreamDestroy(t->own_side);
+    if (t->ev_fork) hipEventDestroy(t->ev_fork);
+    if (t->ev_join) hipEventDestroy(t->ev_join);
+    for (auto &evs : t->pending_timing)
+        for (auto e : evs) hipEventDestroy(e);
+    delete t;
+}
+
+int effective_lc(const fmm_tree *t) { return std::min(t->lc, t->depth); }
+
+// Last FP64 level: every level in FP64 precision; in mixed precision the coarse levels.
+int split_level(const fmm_tree *t, int precision) { return precision == FMM_FP64 ? t->depth : effective_lc(t); }
+
+int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
+{
+    Workspace &ws = t->ws;
+    const int split = split_level(t, precision);
+    const int L = t->depth;
+    if (ws.p != p || ws.precision != precision || ws.split != split) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        free_workspace(ws);
+    }
+    const int64_t n = t->n;
+    const int64_t cells_d = level_base(std::min(split, L) + 1);
+    const int64_t cells_f = level_base(L + 1) - cells_d;
+    const size_t rec_bytes = precision == FMM_FP64 ? sizeof(double4) : sizeof(float4);
+    int rc = FMM_OK;
+    if (!ws.rec) {
+        if ((rc = dev_alloc((char **)&ws.rec, n * rec_bytes, "particle records"))) return rc;
+        if ((rc = dev_alloc(&ws.near, n, "near field"))) return rc;
+        if (L >= 2) {
+            if ((rc = dev_alloc(&ws.mp_d, cells_d * p, "multipoles"))) return rc;
+            if ((rc = dev_alloc(&ws.lo_d, cells_d * p, "locals"))) return rc;
+            if (cells_f > 0) {
+                if ((rc = dev_alloc(&ws.mp_f, cells_f * p, "multipoles"))) return rc;
+                if ((rc = dev_alloc(&ws.lo_f, cells_f * p, "locals"))) return rc;
+            }
+        }
+        ws.p = p;
+        ws.precision = precision;
+        ws.split = split;
+    }
+    if (backward && !ws.adj) {
+        if ((rc = dev_alloc(&ws.adj, n, "adjoint charges"))) return rc;
+        if ((rc = dev_alloc(&ws.bwd_near, n, "adjoint near field"))) return rc;
+        if ((rc = dev_alloc(&ws.bwd_b, n, "adjoint near field"))) return rc;
+        if (precision != FMM_FP64 && (rc = dev_alloc((float2 **)&ws.rec2, n, "adjoint charges (FP32)"))) return rc;
+        if (L >= 2) {
+            if ((rc = dev_alloc(&ws.mp2_d, cells_d * p, "adjoint multipoles"))) return rc;
+            if ((rc = dev_alloc(&ws.lo2_d, cells_d * p, "adjoint locals"))) return rc;
+            if (cells_f > 0) {
+                if ((rc = dev_alloc(&ws.mp2_f, cells_f * p, "adjoint multipoles"))) return rc;
+                if ((rc = dev_alloc(&ws.lo2_f, cells_f * p, "adjoint locals"))) return rc;
+            }
+        }
+    }
+    return FMM_OK;
+}
+
+int check_eval_args(fmm_tree *t, const double *gamma, double sigma, int p, int precision)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!gamma) return fail(FMM_EINVAL, "gamma is NULL");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FMM_EINVAL, "sigma must be finite and > 0");
+    if (p < 1 || p > kMaxP) return fail(FMM_EINVAL, "p must be in [1, 32]");
+    if (precision != FMM_FP64 && precision != FMM_MIXED) return fail(FMM_EINVAL, "unknown precision");
+    return FMM_OK;
+}
+
+// Coordinate scale of the near-field records: exponent of the pair kernel is -s (FP64,
+// natural exp) or -s in base 2 (FP32) with s = |alpha dz|^2.
+double record_alpha(double sigma, int precision)
+{
+    const double a = 1.0 / (sigma * std::sqrt(2.0));
+    return precision == FMM_FP64 ? a : a * std::sqrt(1.4426950408889634073599246810019);
+}
+
+FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
+{
+    const Workspace &ws = t->ws;
+    FarArgs a{};
+    a.t = t;
+    a.p = p;
+    a.split = ws.split;
+    a.lc = effective_lc(t);
+    a.mp_d = adjoint ? ws.mp2_d : ws.mp_d;
+    a.lo_d = adjoint ? ws.lo2_d : ws.lo_d;
+    a.mp_f = adjoint ? ws.mp2_f : ws.mp_f;
+    a.lo_f = adjoint ? ws.lo2_f : ws.lo_f;
+    a.rec = ws.rec;
+    a.rec_is_double = precision == FMM_FP64;
+    a.charge_kind = adjoint ? 1 : 0;
+    a.adj = adjoint ? ws.adj : nullptr;
+    return a;
+}
+
+struct Timing {
+    std::array<hipEvent_t, kNumEvents> ev{};
+    bool on = false;
+    int init(fmm_tree *t)
+    {
+        on = t->timing != 0;
+        if (!on) return FMM_OK;
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        return FMM_OK;
+    }
+    void mark(int k, hipStream_t s)
+    {
+        if (on) hipEventRecord(ev[k], s);
+    }
+};
+
+int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int precision, void *main_stream,
+                void *side_stream, double *uv, double *uv_near, double *uv_far)
+{
+    int rc = check_eval_args(t, gamma, sigma, p, precision);
+    if (rc) return rc;
+    if (!uv && !(uv_near && uv_far)) return fail(FMM_EINVAL, "output is NULL");
+    BusyGuard guard(t);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
+    HIP_TRY(hipSetDevice(t->device));
+    std::string err;
+    if ((rc = upload_tables(t->tabs, p, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+    if ((rc = ensure_workspace(t, p, precision, false))) return rc;
+
+    hipStream_t ms = (hipStream_t)main_stream;
+    hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    const bool overlap = t->schedule == 0;
+    if (!overlap) ss = ms;
+    const double alpha = record_alpha(sigma, precision);
+    const int is_double = precision == FMM_FP64;
+    FarArgs a = far_args(t, p, precision, false);
+    Timing tm;
+    if ((rc = tm.init(t))) return rc;
+
+    tm.mark(0, ms);
+    launch_pack(t, gamma, alpha, is_double, t->ws.rec, ms);
+    tm.mark(1, ms);
+    if (overlap) {
+        HIP_TRY(hipEventRecord(t->ev_fork, ms));
+        HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
+    }
+    tm.mark(2, ss);
+    launch_far_chain(a, ss);
+    tm.mark(3, ss);
+    if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
+    tm.mark(4, ms);
+    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, ms);
+    tm.mark(5, ms);
+    if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    tm.mark(6, ms);
+    launch_finalize(t, a, t->ws.near, uv, uv_near, uv_far, ms);
+    tm.mark(7, ms);
+    HIP_TRY(hipGetLastError());
+    if (tm.on) t->pending_timing.push_back(tm.ev);
+    return FMM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Stages 1-3: tree construction, binning, work lists (host)
+// ---------------------------------------------------------------------------------------
+extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                              fmm_tree **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!xy) return fail(FMM_EINVAL, "xy is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(FMM_EINVAL, "n must be in [1, 2^31)");
+    if (depth < 1 || depth > kMaxDepth) return fail(FMM_EINVAL, "depth must be in [1, 12]");
+    fmm_tree *t = nullptr;
+    try {
+        t = new fmm_tree();
+        hipStream_t s = (hipStream_t)stream;
+        int dev = 0;
+        hipError_t de = hipGetDevice(&dev);
+        if (de != hipSuccess) {
+            free_tree(t);
+            return hip_fail(de, "hipGetDevice");
+        }
+        t->device = dev;
+        t->n = n;
+        t->depth = depth;
+
+        std::vector<double> h(2 * (size_t)n);
+        {
+            hipError_t e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                free_tree(t);
+                return hip_fail(e, "copying positions to the host");
+            }
+        }
+        for (double v : h)
+            if (!std::isfinite(v)) {
+                free_tree(t);
+                return fail(FMM_EINVAL, "non-finite particle position");
+            }
+        if (root_box) {
+            t->x0 = root_box[0];
+            t->y0 = root_box[1];
+            t->side = root_box[2];
+            if (!std::isfinite(t->x0) || !std::isfinite(t->y0) || !(t->side > 0.0) || !std::isfinite(t->side)) {
+                free_tree(t);
+                return fail(FMM_EINVAL, "root_box must be finite with side > 0");
+            }
+        } else {
+            double xmin = h[0], xmax = h[0], ymin = h[1], ymax = h[1];
+            for (int64_t i = 1; i < n; ++i) {
+                xmin = std::min(xmin, h[2 * i]);
+                xmax = std::max(xmax, h[2 * i]);
+                ymin = std::min(ymin, h[2 * i + 1]);
+                ymax = std::max(ymax, h[2 * i + 1]);
+            }
+            double side = std::max(xmax - xmin, ymax - ymin);
+            if (side <= 0.0) side = 1.0;
+            t->x0 = xmin;
+            t->y0 = ymin;
+            t->side = side * (1.0 + 1.0 / 1048576.0);
+        }
+        const int L = depth;
+        const int nside = 1 << L;
+        const int64_t nleaf = int64_t(1) << (2 * L);
+        const double w = t->side / (double)nside;
+
+        // Stage 2: leaf of each particle, floor binning clamped at the top edge.
+        std::vector<uint32_t> key((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t c[2];
+            for (int d = 0; d < 2; ++d) {
+                const double v = (h[2 * i + d] - (d ? t->y0 : t->x0)) / w;
+                if (!(v >= 0.0) || v > (double)nside) {
+                    free_tree(t);
+                    char buf[160];
+                    snprintf(buf, sizeof buf, "particle %lld lies outside the root cell", (long long)i);
+                    return fail(FMM_ERANGE, buf);
+                }
+                int64_t k = (int64_t)std::floor(v);
+                c[d] = (uint32_t)std::min<int64_t>(k, nside - 1);
+            }
+            key[i] = morton_encode(c[0], c[1]);
+        }
+        // Stable counting sort by leaf Morton key.
+        std::vector<int> leaf_start((size_t)nleaf + 1, 0);
+        for (int64_t i = 0; i < n; ++i) leaf_start[key[i] + 1]++;
+        for (int64_t c = 0; c < nleaf; ++c) leaf_start[c + 1] += leaf_start[c];
+        std::vector<int> perm((size_t)n), leaf_of((size_t)n);
+        {
+            std::vector<int> fill(leaf_start.begin(), leaf_start.end() - 1);
+            for (int64_t i = 0; i < n; ++i) {
+                const int pos = fill[key[i]]++;
+                perm[pos] = (int)i;
+                leaf_of[pos] = (int)key[i];
+            }
+        }
+        std::vector<double2> xys((size_t)n);
+        for (int64_t k = 0; k < n; ++k) {
+            xys[k].x = h[2 * (size_t)perm[k]];
+            xys[k].y = h[2 * (size_t)perm[k] + 1];
+        }
+        // Occupancy of every cell of every level (global cell index).
+        std::vector<int> counts((size_t)level_base(L + 1), 0);
+        for (int64_t c = 0; c < nleaf; ++c) counts[level_base(L) + c] = leaf_start[c + 1] - leaf_start[c];
+        for (int l = L - 1; l >= 0; --l)
+            for (int64_t c = 0; c < (int64_t(1) << (2 * l)); ++c) {
+                const int *ch = &counts[level_base(l + 1) + 4 * c];
+                counts[level_base(l) + c] = ch[0] + ch[1] + ch[2] + ch[3];
+            }
+        // Non-empty cells of levels 2..L, grouped by parity class (Morton & 3).
+        std::vector<int> lists;
+        t->list_off.assign(L + 1, 0);
+        t->list_len.assign(L + 1, 0);
+        for (int l = 2; l <= L; ++l) {
+            t->list_off[l] = (int64_t)lists.size();
+            const int64_t nc = int64_t(1) << (2 * l);
+            for (int par = 0; par < 4; ++par)
+                for (int64_t c = par; c < nc; c += 4)
+                    if (counts[level_base(l) + c] > 0) lists.push_back((int)c);
+            t->list_len[l] = (int64_t)lists.size() - t->list_off[l];
+        }
+        // Statistics: pairs (section "Complexity Estimates" direct work), M2L pairs.
+        auto leaf_count = [&](int x, int y) -> int64_t {
+            if (x < 0 || y < 0 || x >= nside || y >= nside) return 0;
+            return counts[level_base(L) + morton_encode((uint32_t)x, (uint32_t)y)];
+        };
+        int64_t pairs = 0, nonempty = 0, maxleaf = 0;
+        // Stage 9 work units: target chunks of <= 64 in each non-empty leaf.
+        std::vector<int4> units;
+        std::vector<int64_t> cost;
+        for (int64_t c = 0; c < nleaf; ++c) {
+            const int nt = leaf_start[c + 1] - leaf_start[c];
+            if (nt == 0) continue;
+            ++nonempty;
+            maxleaf = std::max<int64_t>(maxleaf, nt);
+            const int x = (int)morton_x((uint32_t)c), y = (int)morton_y((uint32_t)c);
+            int64_t nsrc = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) nsrc += leaf_count(x + dx, y + dy);
+            pairs += (int64_t)nt * nsrc;
+            for (int c0 = 0; c0 < nt; c0 += 64) {
+                const int cnt = std::min(64, nt - c0);
+                int logtp = 0;
+                while ((1 << logtp) < cnt) ++logtp;
+                const int kstride = 64 >> logtp;
+                int4 u;
+                u.x = (int)c;
+                u.y = leaf_start[c] + c0;
+                u.z = cnt;
+                u.w = logtp;
+                units.push_back(u);
+                cost.push_back((nsrc + kstride - 1) / kstride);
+            }
+        }
+        t->p2p_pairs = pairs - n;
+        t->nonempty_leaves = nonempty;
+        t->max_leaf = maxleaf;
+        int64_t m2l = 0;
+        for (int l = 2; l <= L; ++l) {
+            const int n1 = 1 << l;
+            const int *lst = lists.data() + t->list_off[l];
+            for (int64_t k = 0; k < t->list_len[l]; ++k) {
+                const int tx = (int)morton_x((uint32_t)lst[k]), ty = (int)morton_y((uint32_t)lst[k]);
+                const int qx = tx & 1, qy = ty & 1;
+                for (int dy = -2 - qy; dy <= 3 - qy; ++dy)
+                    for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
+                        if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                        const int sx = tx + dx, sy = ty + dy;
+                        if (sx < 0 || sy < 0 || sx >= n1 || sy >= n1) continue;
+                        if (counts[level_base(l) + morton_encode((uint32_t)sx, (uint32_t)sy)] > 0) ++m2l;
+                    }
+            }
+        }
+        t->m2l_pairs = m2l;
+        // Heaviest units first so the tail of the launch is short.
+        std::vector<int64_t> order(units.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+        std::vector<int4> sorted_units(units.size());
+        for (size_t k = 0; k < order.size(); ++k) sorted_units[k] = units[order[k]];
+        t->nunits = (int64_t)sorted_units.size();
+
+        int rc = FMM_OK;
+        if (!rc) rc = upload(&t->d_perm, perm, "permutation");
+        if (!rc) rc = upload(&t->d_leaf_of, leaf_of, "leaf ids");
+        if (!rc) rc = upload(&t->d_xy, xys, "sorted positions");
+        if (!rc) rc = upload(&t->d_leaf_start, leaf_start, "leaf offsets");
+        if (!rc) rc = upload(&t->d_counts, counts, "cell counts");
+        if (!rc) rc = upload(&t->d_lists, lists, "cell lists");
+        if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
+        if (rc) {
+            free_tree(t);
+            return rc;
+        }
+        hipError_t e = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_tree(t);
+            return hip_fail(e, "creating stream/events");
+        }
+    } catch (const std::bad_alloc &) {
+        if (t) free_tree(t);
+        return fail(FMM_ENOMEM, "host allocation failed while building the tree");
+    }
+    *out = t;
+    return FMM_OK;
+}
+
+extern "C" int fmm_tree_info(const fmm_tree *t, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
+                             int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (n) *n = t->n;
+    if (depth) *depth = t->depth;
+    if (root_box) {
+        root_box[0] = t->x0;
+        root_box[1] = t->y0;
+        root_box[2] = t->side;
+    }
+    if (p2p_pairs) *p2p_pairs = t->p2p_pairs;
+    if (m2l_pairs) *m2l_pairs = t->m2l_pairs;
+    if (nonempty_leaves) *nonempty_leaves = t->nonempty_leaves;
+    if (max_leaf) *max_leaf = t->max_leaf;
+    return FMM_OK;
+}
+
+namespace fmm {
+void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStream_t s);
+}
+
+extern "C" int fmm_tree_permutation(const fmm_tree *t, int64_t *perm, int32_t *leaf, void *stream)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!perm) return fail(FMM_EINVAL, "perm is NULL");
+    HIP_TRY(hipSetDevice(t->device));
+    launch_widen_perm(t, perm, leaf, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FMM_OK;
+}
+
+extern "C" int fmm_velocity(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                            void *main_stream, void *side_stream, double *uv)
+{
+    g_last_error.clear();
+    if (!uv) return fail(FMM_EINVAL, "uv is NULL");
+    return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, uv, nullptr, nullptr);
+}
+
+extern "C" int fmm_velocity_parts(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                  void *main_stream, void *side_stream, double *uv_near, double *uv_far)
+{
+    g_last_error.clear();
+    if (!uv_near || !uv_far) return fail(FMM_EINVAL, "uv_near / uv_far is NULL");
+    return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, nullptr, uv_near, uv_far);
+}
+
+extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                     const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
+                                     double *dl_dxeval)
+{
+    g_last_error.clear();
+    int rc = check_eval_args(t, gamma, sigma, p, precision);
+    if (rc) return rc;
+    if (!dl_duv) return fail(FMM_EINVAL, "dl_duv is NULL");
+    if (!dl_dgamma && !dl_dxeval) return FMM_OK;
+    BusyGuard guard(t);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
+    HIP_TRY(hipSetDevice(t->device));
+    std::string err;
+    if ((rc = upload_tables(t->tabs, p, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+    if ((rc = ensure_workspace(t, p, precision, true))) return rc;
+    Workspace &ws = t->ws;
+
+    hipStream_t ms = (hipStream_t)main_stream;
+    hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    const bool overlap = t->schedule == 0;
+    if (!overlap) ss = ms;
+    const double alpha = record_alpha(sigma, precision);
+    const int is_double = precision == FMM_FP64;
+    const FarArgs fc = far_args(t, p, precision, false);
+    const FarArgs fq = far_args(t, p, precision, true);
+    Timing tm;
+    if ((rc = tm.init(t))) return rc;
+
+    tm.mark(0, ms);
+    launch_pack(t, gamma, alpha, is_double, ws.rec, ms);
+    launch_pack_adjoint(t, dl_duv, ws.adj, ws.rec2, is_double, ms);
+    tm.mark(1, ms);
+    if (overlap) {
+        HIP_TRY(hipEventRecord(t->ev_fork, ms));
+        HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
+    }
+    tm.mark(2, ss);
+    launch_far_chain(fc, ss);  // c-field: derivative of its local expansion
+    launch_far_chain(fq, ss);  // q-field: the transpose pass A^T q = -A q
+    tm.mark(3, ss);
+    if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
+    tm.mark(4, ms);
+    launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
+                        ws.bwd_b, ms);
+    tm.mark(5, ms);
+    if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    tm.mark(6, ms);
+    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, is_double, alpha, dl_dgamma, dl_dxeval, ms);
+    tm.mark(7, ms);
+    HIP_TRY(hipGetLastError());
+    if (tm.on) t->pending_timing.push_back(tm.ev);
+    return FMM_OK;
+}
+
+extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    switch (key) {
+    case FMM_OPT_SCHEDULE:
+        if (value != 0 && value != 1) return fail(FMM_EINVAL, "schedule must be 0 or 1");
+        t->schedule = (int)value;
+        return FMM_OK;
+    case FMM_OPT_COARSE_LEVEL:
+        if (value < 1 || value > t->depth) return fail(FMM_EINVAL, "coarse level must be in [1, depth]");
+        t->lc = (int)value;
+        return FMM_OK;
+    case FMM_OPT_TIMING:
+        if (value != 0 && value != 1) return fail(FMM_EINVAL, "timing must be 0 or 1");
+        t->timing = (int)value;
+        return FMM_OK;
+    default:
+        return fail(FMM_EINVAL, "unknown option");
+    }
+}
+
+extern "C" int fmm_get_timings(fmm_tree *t, double *ms, int64_t *calls)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!ms) return fail(FMM_EINVAL, "ms is NULL");
+    HIP_TRY(hipSetDevice(t->device));
+    double acc[FMM_T_COUNT] = {0, 0, 0, 0, 0};
+    int64_t ncalls = 0;
+    for (auto &ev : t->pending_timing) {
+        HIP_TRY(hipEventSynchronize(ev[7]));
+        HIP_TRY(hipEventSynchronize(ev[3]));
+        float f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[0], ev[1]));
+        acc[FMM_T_PACK] += f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[2], ev[3]));
+        acc[FMM_T_FAR] += f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[4], ev[5]));
+        acc[FMM_T_P2P] += f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[6], ev[7]));
+        acc[FMM_T_FINAL] += f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[0], ev[7]));
+        acc[FMM_T_TOTAL] += f;
+        ++ncalls;
+        for (auto e : ev) hipEventDestroy(e);
+    }
+    t->pending_timing.clear();
+    for (int k = 0; k < FMM_T_COUNT; ++k) ms[k] = acc[k];
+    if (calls) *calls = ncalls;
+    return FMM_OK;
+}
+
+extern "C" void fmm_destroy_tree(fmm_tree *t)
+{
+    if (!t) return;
+    hipSetDevice(t->device);
+    hipDeviceSynchronize();
+    free_tree(t);
+}
+
+extern "C" const char *fmm_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,156 @@
+// Internal declarations of the gfx950 FMM library: tree layout, workspace, and the
+// kernel launchers implemented in kernels.hip.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fmm {
+
+constexpr int kMaxDepth = 12;
+constexpr int kMaxP = 32;
+constexpr int kNumEvents = 8;
+
+// ---------------------------------------------------------------------------------
+// Morton order: x in the even bits, y in the odd bits.  The four children of cell k
+// at level l are 4k + q at level l + 1 with q = (child x bit) | (child y bit) << 1,
+// so siblings are adjacent and a cell's parity class is k & 3.
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline uint32_t spread_bits(uint32_t v)
+{
+    v &= 0x0000ffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__host__ __device__ inline uint32_t gather_bits(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0f0f0f0fu;
+    v = (v | (v >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0x0000ffffu;
+    return v;
+}
+
+__host__ __device__ inline uint32_t morton_encode(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
+__host__ __device__ inline uint32_t morton_x(uint32_t m) { return gather_bits(m); }
+__host__ __device__ inline uint32_t morton_y(uint32_t m) { return gather_bits(m >> 1); }
+
+// First global cell index of level l when all levels are stored back to back:
+// sum_{k<l} 4^k = (4^l - 1)/3.
+__host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+
+// ---------------------------------------------------------------------------------
+// Device-side tables for one expansion order p (radius-scaled operators, level
+// independent).  All complex arrays are interleaved (re, im).
+//   m2m[q][m][k]  = C(m,k) d_q^(m-k) 2^-k                 (k <= m, else 0)
+//   l2l[q][k][l]  = C(l,k) d_q^(l-k) 2^-(k+1)             (l >= k, else 0)
+//   m2l[o][m][l]  = (-1)^l C(l+m,m) delta^-(l+m+1), delta = (dx, dy) of offset o = (dx+3)*7 + (dy+3)
+// with d_q = (c_child - c_parent)/w_parent = ((q&1) - 1/2)/2 + i((q>>1) - 1/2)/2.
+// ---------------------------------------------------------------------------------
+struct Tables {
+    int p = 0;
+    double2 *m2m_d = nullptr, *l2l_d = nullptr, *m2l_d = nullptr;
+    float2 *m2m_f = nullptr, *l2l_f = nullptr, *m2l_f = nullptr;
+};
+
+// Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
+// are FP64, levels split+1..L are FP32; each level holds 4^l cells x p coefficients,
+// multipoles (scaled a_m / w^m) and locals (scaled b_l w^(l+1)) in separate arrays.
+struct Workspace {
+    int p = 0, precision = -1, split = -1;
+    void *rec = nullptr;          // per-particle P2P records (float4 or double4), n
+    double2 *near = nullptr;      // near-field (u, v) per sorted particle, n
+    double2 *mp_d = nullptr, *lo_d = nullptr;  // FP64 levels
+    float2 *mp_f = nullptr, *lo_f = nullptr;   // FP32 levels
+    // backward pass
+    double2 *adj = nullptr;       // per sorted particle: adjoint charge q (sorted order)
+    double4 *bwd_near = nullptr;  // per sorted particle: near sums of Phi (2) and A (2)
+    double *bwd_b = nullptr;      // per sorted particle: near sum of B
+    double2 *mp2_d = nullptr, *lo2_d = nullptr;
+    float2 *mp2_f = nullptr, *lo2_f = nullptr;
+    void *rec2 = nullptr;         // adjoint charges q in FP32 for the mixed near field
+};
+
+}  // namespace fmm
+
+struct fmm_tree {
+    int64_t n = 0;
+    int depth = 0;
+    double x0 = 0, y0 = 0, side = 1;
+    int device = 0;
+    int lc = 4;          // coarse-level cutoff L_c
+    int schedule = 0;    // 0 overlap, 1 serial
+    int timing = 0;
+    std::atomic<int> busy{0};
+
+    // host statistics
+    int64_t p2p_pairs = 0, m2l_pairs = 0, nonempty_leaves = 0, max_leaf = 0;
+    int64_t nunits = 0;
+    std::vector<int64_t> list_off;  // per level l: offset into d_lists; list_len[l] entries
+    std::vector<int64_t> list_len;
+
+    // device tree arrays
+    int *d_perm = nullptr;        // sorted slot -> user index
+    int *d_leaf_of = nullptr;     // sorted slot -> leaf Morton index
+    double2 *d_xy = nullptr;      // sorted positions
+    int *d_leaf_start = nullptr;  // CSR over Morton-ordered leaves, 4^L + 1
+    int *d_counts = nullptr;      // particles per cell, all levels, global cell index
+    int *d_lists = nullptr;       // non-empty cells per level (levels 2..L), parity-grouped
+    int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
+
+    hipStream_t own_side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    fmm::Tables tabs;
+    fmm::Workspace ws;
+    std::vector<std::array<hipEvent_t, fmm::kNumEvents>> pending_timing;
+};
+
+namespace fmm {
+
+// Launch parameters shared by the forward and backward far-field chains.
+struct FarArgs {
+    const fmm_tree *t;
+    int p;
+    int split;                 // last FP64 level
+    int lc;                    // coarse cutoff actually used (<= depth)
+    double2 *mp_d, *lo_d;      // FP64 storage (levels 0..split)
+    float2 *mp_f, *lo_f;       // FP32 storage (levels split+1..L)
+    const void *rec;           // P2P records (charges live in .z / complex in adjoint)
+    int rec_is_double;
+    int charge_kind;           // 0: real Gamma in rec.z -> c = -i Gamma/(2 pi); 1: complex q from adj array
+    const double2 *adj;        // complex charges in sorted order (charge_kind 1)
+};
+
+// Launchers (kernels.hip).  All are asynchronous on `s`.
+void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
+void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
+                        hipStream_t s);
+void launch_far_chain(const FarArgs &a, hipStream_t s);
+void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, double *uv, double *uv_near,
+                     double *uv_far, hipStream_t s);
+
+// Backward
+void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,
+                         hipStream_t s);
+void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
+                         double4 *out_pa, double *out_b, hipStream_t s);
+void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
+                              const double *near_b, const double2 *adj, int is_double, double alpha,
+                              double *dl_dgamma, double *dl_dxeval, hipStream_t s);
+
+// Tables (host generation + upload), kernels.hip
+int upload_tables(Tables &tb, int p, std::string &err);
+void free_tables(Tables &tb);
+
+}  // namespace fmm

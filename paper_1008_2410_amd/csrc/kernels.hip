@@ -1,0 +1,790 @@
+// gfx950 kernels of the FMM evaluation phase (stages 4-10 of Fig. fmmStages of
+// Knepley, arXiv:1008.2410) and their host launchers.
+//
+// Conventions (shared with the host code in api.cpp / tree.cpp):
+//  - Particles are in leaf-Morton order ("sorted"); d_perm maps a sorted slot to the
+//    user index, d_leaf_of to its leaf.
+//  - Complex charge c_j = -i Gamma_j / (2 pi) (the factor of the multipole
+//    coefficients, section "Complexity Estimates"); conjugate velocity W = u - i v.
+//  - Expansions are radius-scaled so every translation operator is level independent:
+//    multipole a_m / w^m, local b_l w^(l+1), with w the cell width of the level.
+//  - Complex numbers are interleaved (re, im) float2 / double2.
+#include "fmm_internal.h"
+
+#include <cmath>
+
+namespace fmm {
+namespace {
+
+constexpr double kInv2Pi = 0.15915494309189533576888376337251;
+
+// ---------------------------------------------------------------------------------
+// Small complex helpers on float2 / double2
+// ---------------------------------------------------------------------------------
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T> using c2 = typename Vec2<T>::type;
+
+template <typename T> __device__ __forceinline__ c2<T> mk(T x, T y)
+{
+    c2<T> r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+
+// acc + a * b
+template <typename T> __device__ __forceinline__ c2<T> cmac(c2<T> acc, c2<T> a, c2<T> b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+
+template <typename T> __device__ __forceinline__ c2<T> cmul(c2<T> a, c2<T> b)
+{
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename TO, typename TI> __device__ __forceinline__ c2<TO> cvt(c2<TI> a)
+{
+    return mk<TO>((TO)a.x, (TO)a.y);
+}
+
+// ---------------------------------------------------------------------------------
+// Per-particle records for the near field: {X, Y, Gamma, 0} with (X, Y) = alpha (z - c_leaf),
+// alpha chosen per call so that the pair exponent needs no extra multiply:
+//   FP64: alpha^2 = 1/(2 sigma^2)          -> g = 1 - exp(-s)
+//   FP32: alpha^2 = log2(e)/(2 sigma^2)    -> g = 1 - exp2(-s)
+// with s = |X_i - X_j|^2 (leaf offset added per neighbour leaf).  Leaf-local origins
+// keep FP32 differences accurate at the blob scale.
+// ---------------------------------------------------------------------------------
+template <typename T> struct Rec;
+template <> struct Rec<float> { using type = float4; };
+template <> struct Rec<double> { using type = double4; };
+template <typename T> using rec_t = typename Rec<T>::type;
+
+template <typename T>
+__global__ __launch_bounds__(256) void pack_kernel(int n, const int *__restrict__ perm, const int *__restrict__ leaf_of,
+                                                    const double2 *__restrict__ xy, const double *__restrict__ gamma,
+                                                    double x0, double y0, double w, double alpha,
+                                                    rec_t<T> *__restrict__ rec)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t leaf = (uint32_t)leaf_of[i];
+    double cx = x0 + (morton_x(leaf) + 0.5) * w;
+    double cy = y0 + (morton_y(leaf) + 0.5) * w;
+    double2 z = xy[i];
+    rec_t<T> r;
+    r.x = (T)(alpha * (z.x - cx));
+    r.y = (T)(alpha * (z.y - cy));
+    r.z = (T)gamma[perm[i]];
+    r.w = (T)0;
+    rec[i] = r;
+}
+
+// g(s) = 1 - exp(-|dz|^2/(2 sigma^2)) in the scaled variable s, and 1/s.
+__device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builtin_amdgcn_exp2f(-s); }
+__device__ __forceinline__ double one_minus_exp(double s) { return -expm1(-s); }
+__device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
+__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+// Added to every s: a pair at distance 0 (the particle itself) then gives g = 0 and
+// a finite 1/s, hence exactly zero, while any s above ~1e-23 (FP32) is unchanged.
+template <typename T> __device__ __forceinline__ T tiny();
+template <> __device__ __forceinline__ float tiny<float>() { return 1e-30f; }
+template <> __device__ __forceinline__ double tiny<double>() { return 1e-300; }
+
+// ---------------------------------------------------------------------------------
+// Stage 9, P2P (near field), target-centric: every pair is evaluated from the target's
+// end, so no output is shared between work-items (the paper computes each pair from
+// both ends to avoid memory contention).  One wavefront per work unit
+// {leaf T, first target, count nt <= 64, log2 TP}: lane = k*TP + t handles target t
+// and sources j = k, k+K, ... (K = 64/TP) of each leaf S in the 3x3 neighbourhood, so
+// sparse leaves still fill the wavefront.  Per-source-leaf partial sums are kept in T
+// and folded into FP64; the K partial sums of a target are combined by lane shuffles.
+//   velocity u = -(alpha/2pi) sum Gamma g dY/s,  v = (alpha/2pi) sum Gamma g dX/s
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void p2p_forward_kernel(const int4 *__restrict__ units,
+                                                          const rec_t<T> *__restrict__ rec,
+                                                          const int *__restrict__ leaf_start, int nside, T step,
+                                                          double scale, double2 *__restrict__ near)
+{
+    const int4 u = units[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int logtp = u.w;
+    const int tp = 1 << logtp;
+    const int kstride = 64 >> logtp;
+    const int t = lane & (tp - 1);
+    const int k = lane >> logtp;
+    const int i = u.y + min(t, u.z - 1);
+    const rec_t<T> ri = rec[i];
+    const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
+    double au = 0.0, av = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int ny = iy + dy;
+        if (ny < 0 || ny >= nside) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int nx = ix + dx;
+            if (nx < 0 || nx >= nside) continue;
+            const uint32_t S = morton_encode((uint32_t)nx, (uint32_t)ny);
+            const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
+            // target relative to the centre of leaf S: z_i - c_S = (z_i - c_T) + (c_T - c_S)
+            const T tx = ri.x - (T)dx * step;
+            const T ty = ri.y - (T)dy * step;
+            T fu = 0, fv = 0;
+#pragma unroll 4
+            for (int j = s0 + k; j < s1; j += kstride) {
+                const rec_t<T> rj = rec[j];
+                const T ddx = tx - rj.x;
+                const T ddy = ty - rj.y;
+                const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+                const T f = (one_minus_exp(s) * recip(s)) * rj.z;
+                fu = fma(f, ddy, fu);
+                fv = fma(f, ddx, fv);
+            }
+            au += (double)fu;
+            av += (double)fv;
+        }
+    }
+    for (int o = tp; o < 64; o <<= 1) {
+        au += __shfl_xor(au, o);
+        av += __shfl_xor(av, o);
+    }
+    if (k == 0 && t < u.z) near[i] = make_double2(-scale * au, scale * av);
+}
+
+// ---------------------------------------------------------------------------------
+// Stage 4, P2M: one wavefront per non-empty leaf,
+//   a_m = sum_{j in leaf} c_j xi_j^m,  xi_j = (z_j - c_leaf)/w_L,  m = 0..p-1.
+// Lanes stride over the leaf's particles; the per-lane sums are combined by shuffles.
+// Charges: c_j = -i Gamma_j/(2 pi) from the records, or complex adjoint charges.
+// ---------------------------------------------------------------------------------
+template <typename TR, typename TC, int PMAX>
+__global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, const int *__restrict__ leaf_start,
+                                                  const double2 *__restrict__ xy, const TR *__restrict__ rec,
+                                                  const double2 *__restrict__ adj, double x0, double y0, double w,
+                                                  int p, c2<TC> *__restrict__ out)
+{
+    const uint32_t leaf = (uint32_t)leaves[blockIdx.x];
+    const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
+    const double cx = x0 + (morton_x(leaf) + 0.5) * w;
+    const double cy = y0 + (morton_y(leaf) + 0.5) * w;
+    c2<TC> acc[PMAX];
+#pragma unroll
+    for (int m = 0; m < PMAX; ++m) acc[m] = mk<TC>(0, 0);
+    for (int j = s0 + (int)threadIdx.x; j < s1; j += 64) {
+        const double2 z = xy[j];
+        const c2<TC> xi = mk<TC>((TC)((z.x - cx) / w), (TC)((z.y - cy) / w));
+        c2<TC> pw;
+        if (adj) {
+            const double2 q = adj[j];
+            pw = mk<TC>((TC)q.x, (TC)q.y);
+        } else {
+            pw = mk<TC>(0, (TC)(-(double)rec[j].z * kInv2Pi));
+        }
+#pragma unroll
+        for (int m = 0; m < PMAX; ++m) {
+            if (m < p) {
+                acc[m].x += pw.x;
+                acc[m].y += pw.y;
+                pw = cmul<TC>(pw, xi);
+            }
+        }
+    }
+    c2<TC> mine = mk<TC>(0, 0);
+#pragma unroll
+    for (int m = 0; m < PMAX; ++m) {
+        if (m < p) {
+            TC re = acc[m].x, im = acc[m].y;
+            for (int o = 32; o >= 1; o >>= 1) {
+                re += __shfl_xor(re, o);
+                im += __shfl_xor(im, o);
+            }
+            if ((int)threadIdx.x == m) mine = mk<TC>(re, im);
+        }
+    }
+    if ((int)threadIdx.x < p) out[(int64_t)leaf * p + threadIdx.x] = mine;
+}
+
+// ---------------------------------------------------------------------------------
+// Stage 5, M2M: coefficient m of parent P from its non-empty children,
+//   A_m = sum_q sum_{k<=m} C(m,k) d_q^(m-k) 2^-k a_k(child q)      (scaled form)
+// ---------------------------------------------------------------------------------
+template <typename TC, typename TP>
+__device__ __forceinline__ void m2m_one(int P, int m, int p, const int *__restrict__ child_count,
+                                        const c2<TC> *__restrict__ child, c2<TP> *__restrict__ parent,
+                                        const c2<TP> *__restrict__ tab)
+{
+    c2<TP> acc = mk<TP>(0, 0);
+    for (int q = 0; q < 4; ++q) {
+        const int ch = 4 * P + q;
+        if (child_count[ch] == 0) continue;
+        const c2<TC> *a = child + (int64_t)ch * p;
+        const c2<TP> *row = tab + (q * p + m) * p;
+        for (int k = 0; k <= m; ++k) acc = cmac<TP>(acc, row[k], cvt<TP, TC>(a[k]));
+    }
+    parent[(int64_t)P * p + m] = acc;
+}
+
+// ---------------------------------------------------------------------------------
+// Stages 6 + 7 fused per cell: local coefficient l of cell T at level `level`,
+//   b_l(T) = sum_{S in IL(T), S non-empty} sum_m (-1)^l C(l+m,m) delta^-(l+m+1) a_m(S)
+//          + sum_{k>=l} C(k,l) d_q^(k-l) 2^-(l+1) b_k(parent(T))   (levels >= 3)
+// IL(T) = children of the parent's neighbours that are not neighbours of T: for the
+// parity class (qx, qy) = (tx & 1, ty & 1) the source offsets are
+// dx in [-2-qx, 3-qx], dy in [-2-qy, 3-qy] minus the 3x3 block (27 cells).
+// ---------------------------------------------------------------------------------
+template <typename T, typename TPar>
+__device__ __forceinline__ void m2l_one(int Tm, int lo, int p, int level, const int *__restrict__ count_l,
+                                        const c2<T> *__restrict__ mp_l, c2<T> *__restrict__ lo_l,
+                                        const c2<T> *__restrict__ m2l_tab, const c2<TPar> *__restrict__ loc_par,
+                                        const c2<TPar> *__restrict__ l2l_tab)
+{
+    const int tx = (int)morton_x((uint32_t)Tm), ty = (int)morton_y((uint32_t)Tm);
+    const int qx = tx & 1, qy = ty & 1;
+    const int nside = 1 << level;
+    c2<T> acc = mk<T>(0, 0);
+    for (int dy = -2 - qy; dy <= 3 - qy; ++dy) {
+        const int sy = ty + dy;
+        if (sy < 0 || sy >= nside) continue;
+        for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+            const int sx = tx + dx;
+            if (sx < 0 || sx >= nside) continue;
+            const uint32_t S = morton_encode((uint32_t)sx, (uint32_t)sy);
+            if (count_l[S] == 0) continue;
+            const c2<T> *a = mp_l + (int64_t)S * p;
+            // delta = (c_T - c_S)/w = (-dx, -dy)
+            const c2<T> *tab = m2l_tab + ((3 - dx) * 7 + (3 - dy)) * p * p + lo;
+            for (int m = 0; m < p; ++m) acc = cmac<T>(acc, tab[m * p], a[m]);
+        }
+    }
+    if (loc_par) {
+        const int P = Tm >> 2, q = Tm & 3;
+        const c2<TPar> *b = loc_par + (int64_t)P * p;
+        const c2<TPar> *row = l2l_tab + (q * p + lo) * p;
+        c2<TPar> acc2 = mk<TPar>(0, 0);
+        for (int k = lo; k < p; ++k) acc2 = cmac<TPar>(acc2, row[k], b[k]);
+        acc.x += (T)acc2.x;
+        acc.y += (T)acc2.y;
+    }
+    lo_l[(int64_t)Tm * p + lo] = acc;
+}
+
+template <typename TC, typename TP>
+__global__ __launch_bounds__(256) void m2m_kernel(const int *__restrict__ parents, int nparents, int p,
+                                                   const int *__restrict__ child_count,
+                                                   const c2<TC> *__restrict__ child, c2<TP> *__restrict__ parent,
+                                                   const c2<TP> *__restrict__ tab)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = g / p;
+    if (cell >= nparents) return;
+    const int m = (int)(g - cell * p);
+    m2m_one<TC, TP>(parents[cell], m, p, child_count, child, parent, tab);
+}
+
+template <typename T, typename TPar>
+__global__ __launch_bounds__(256) void m2l_kernel(const int *__restrict__ targets, int ntargets, int p, int level,
+                                                   const int *__restrict__ count_l, const c2<T> *__restrict__ mp_l,
+                                                   c2<T> *__restrict__ lo_l, const c2<T> *__restrict__ m2l_tab,
+                                                   const c2<TPar> *__restrict__ loc_par,
+                                                   const c2<TPar> *__restrict__ l2l_tab)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = g / p;
+    if (cell >= ntargets) return;
+    const int lo = (int)(g - cell * p);
+    m2l_one<T, TPar>(targets[cell], lo, p, level, count_l, mp_l, lo_l, m2l_tab, loc_par, l2l_tab);
+}
+
+// ---------------------------------------------------------------------------------
+// Coarse levels (<= L_c) in one workgroup: M2M into levels L_c-1..2, then M2L + L2L
+// for levels 2..L_c, in FP64.  These levels hold too few cells to fill the chip; the
+// paper assigns them to a single thread group and covers their latency with the
+// near-field work (section "Concurrency").
+// ---------------------------------------------------------------------------------
+struct CoarseArgs {
+    int p, lc;
+    const int *counts;  // global cell index
+    const int *lists;
+    int64_t list_off[kMaxDepth + 1];
+    int64_t list_len[kMaxDepth + 1];
+    double2 *mp, *lo;   // FP64 storage from level 0
+    const double2 *m2m_tab, *m2l_tab, *l2l_tab;
+};
+
+__global__ __launch_bounds__(1024) void coarse_kernel(CoarseArgs a)
+{
+    const int p = a.p;
+    for (int l = a.lc - 1; l >= 2; --l) {
+        const int n = (int)a.list_len[l];
+        const int *lst = a.lists + a.list_off[l];
+        for (int g = threadIdx.x; g < n * p; g += blockDim.x) {
+            const int c = g / p, m = g - c * p;
+            m2m_one<double, double>(lst[c], m, p, a.counts + level_base(l + 1), a.mp + level_base(l + 1) * p,
+                                    a.mp + level_base(l) * p, a.m2m_tab);
+        }
+        __syncthreads();
+    }
+    for (int l = 2; l <= a.lc; ++l) {
+        const int n = (int)a.list_len[l];
+        const int *lst = a.lists + a.list_off[l];
+        for (int g = threadIdx.x; g < n * p; g += blockDim.x) {
+            const int c = g / p, lo = g - c * p;
+            m2l_one<double, double>(lst[c], lo, p, l, a.counts + level_base(l), a.mp + level_base(l) * p,
+                                    a.lo + level_base(l) * p, a.m2l_tab,
+                                    l >= 3 ? a.lo + level_base(l - 1) * p : nullptr, a.l2l_tab);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Stages 8 + 10: L2P from the leaf's local expansion (Horner in xi = (z - c)/w_L,
+// W_far = (1/w_L) sum_l b_l xi^l), plus the near field, scattered to user order:
+// (u, v) = (u_near + Re W_far, v_near - Im W_far).
+// ---------------------------------------------------------------------------------
+template <typename TL>
+__global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restrict__ perm,
+                                                        const int *__restrict__ leaf_of,
+                                                        const double2 *__restrict__ xy,
+                                                        const double2 *__restrict__ near,
+                                                        const c2<TL> *__restrict__ loc, int p, int has_far, double x0,
+                                                        double y0, double w, double *__restrict__ uv,
+                                                        double *__restrict__ uv_near, double *__restrict__ uv_far)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 nr = near[i];
+    double fu = 0.0, fv = 0.0;
+    if (has_far) {
+        const uint32_t leaf = (uint32_t)leaf_of[i];
+        const double cx = x0 + (morton_x(leaf) + 0.5) * w;
+        const double cy = y0 + (morton_y(leaf) + 0.5) * w;
+        const double2 z = xy[i];
+        const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        const c2<TL> *b = loc + (int64_t)leaf * p;
+        c2<TL> acc = b[p - 1];
+        for (int l = p - 2; l >= 0; --l) {
+            const c2<TL> bl = b[l];
+            acc = cmac<TL>(bl, acc, xi);
+        }
+        fu = (double)acc.x / w;
+        fv = -(double)acc.y / w;
+    }
+    const int64_t o = perm[i];
+    if (uv) {
+        uv[2 * o] = nr.x + fu;
+        uv[2 * o + 1] = nr.y + fv;
+    }
+    if (uv_near) {
+        uv_near[2 * o] = nr.x;
+        uv_near[2 * o + 1] = nr.y;
+    }
+    if (uv_far) {
+        uv_far[2 * o] = fu;
+        uv_far[2 * o + 1] = fv;
+    }
+}
+
+inline unsigned blocks_for(int64_t work, int per_block) { return (unsigned)((work + per_block - 1) / per_block); }
+
+template <typename T> c2<T> *level_ptr(const FarArgs &a, int l, bool local);
+template <> double2 *level_ptr<double>(const FarArgs &a, int l, bool local)
+{
+    return (local ? a.lo_d : a.mp_d) + level_base(l) * a.p;
+}
+template <> float2 *level_ptr<float>(const FarArgs &a, int l, bool local)
+{
+    return (local ? a.lo_f : a.mp_f) + (level_base(l) - level_base(a.split + 1)) * a.p;
+}
+
+const int *level_list(const fmm_tree *t, int l) { return t->d_lists + t->list_off[l]; }
+
+template <typename TR, typename TC>
+void p2m_launch(const FarArgs &a, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int L = t->depth;
+    const int64_t nl = t->list_len[L];
+    if (nl == 0) return;
+    const double w = t->side / (double)(1 << L);
+    c2<TC> *out = level_ptr<TC>(a, L, false);
+    if (a.p <= 16)
+        p2m_kernel<TR, TC, 16><<<(unsigned)nl, 64, 0, s>>>(level_list(t, L), t->d_leaf_start, t->d_xy,
+                                                            (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+    else
+        p2m_kernel<TR, TC, 32><<<(unsigned)nl, 64, 0, s>>>(level_list(t, L), t->d_leaf_start, t->d_xy,
+                                                            (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+}
+
+template <typename TC, typename TP>
+void m2m_launch(const FarArgs &a, int l, const c2<TP> *tab, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int64_t n = t->list_len[l];
+    if (n == 0) return;
+    m2m_kernel<TC, TP><<<blocks_for(n * a.p, 256), 256, 0, s>>>(
+        level_list(t, l), (int)n, a.p, t->d_counts + level_base(l + 1), level_ptr<TC>(a, l + 1, false),
+        level_ptr<TP>(a, l, false), tab);
+}
+
+template <typename T, typename TPar>
+void m2l_launch(const FarArgs &a, int l, const c2<T> *m2l_tab, const c2<TPar> *l2l_tab, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int64_t n = t->list_len[l];
+    if (n == 0) return;
+    const c2<TPar> *par = l >= 3 ? level_ptr<TPar>(a, l - 1, true) : nullptr;
+    m2l_kernel<T, TPar><<<blocks_for(n * a.p, 256), 256, 0, s>>>(
+        level_list(t, l), (int)n, a.p, l, t->d_counts + level_base(l), level_ptr<T>(a, l, false),
+        level_ptr<T>(a, l, true), m2l_tab, par, l2l_tab);
+}
+
+// ---------------------------------------------------------------------------------
+// Backward pass (adjoint of stages 4-10 for a loss L(u)).
+// q_i = dL/du_i + i dL/dv_i.  With W = A c and A antisymmetric (A_ij = -A_ji),
+//   dL/dGamma_j = -Im((A q)_j)/(2 pi)
+// and, with the sources held fixed, dW_i/dx_i = A_i + B_i + W'_far, dW_i/dy_i = i(A_i - B_i + W'_far),
+//   A_i = sum_j c_j conj(dz)^2 f'(s),  B_i = sum_j c_j g'(s),   f = g/s, s = |dz|^2,
+// so dL/dx_i = Re(q_i (A+B+W')), dL/dy_i = -Im(q_i (A-B+W')).  The particle's own blob
+// (dz = 0) contributes B = c_i/(2 sigma^2) and nothing else.
+// In the scaled variable s' = alpha^2 |dz|^2 (alpha as in the forward records) and with
+// lambda = 1 (FP64, base e) or ln 2 (FP32, base 2):
+//   Phi_near = alpha sum_j q_j (g/s') conj(dz'),
+//   A = -i alpha^2/(2 pi) sum_j Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2,
+//   B = -i alpha^2 lambda/(2 pi) sum_j Gamma_j e,        e = exp(-|dz|^2/(2 sigma^2)), g = 1 - e.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void pack_adjoint_kernel(int n, const int *__restrict__ perm,
+                                                            const double *__restrict__ dl_duv,
+                                                            double2 *__restrict__ adj, c2<T> *__restrict__ qt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    const double2 q = make_double2(dl_duv[2 * o], dl_duv[2 * o + 1]);
+    adj[i] = q;
+    if (qt) qt[i] = mk<T>((T)q.x, (T)q.y);
+}
+
+// e = exp(-x) and g = 1 - e in the scaled variable: FP32 base 2 (g by subtraction,
+// small x handled by the series below), FP64 base e with g from expm1.
+__device__ __forceinline__ void exp_pair(float s, float &e, float &g)
+{
+    e = __builtin_amdgcn_exp2f(-s);
+    g = 1.0f - e;
+}
+__device__ __forceinline__ void exp_pair(double s, double &e, double &g)
+{
+    g = -expm1(-s);
+    e = 1.0 - g;
+}
+// Below this natural exponent the 5-term series of g/s' and (lambda e s' - g)/s'^2 is
+// used: its truncation error x^5/720 is under the rounding unit of T there.
+template <typename T> __device__ __forceinline__ T series_cut();
+template <> __device__ __forceinline__ float series_cut<float>() { return 0.125f; }
+template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3; }
+
+template <typename T>
+__global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units,
+                                                           const rec_t<T> *__restrict__ rec,
+                                                           const c2<T> *__restrict__ qv,
+                                                           const int *__restrict__ leaf_start, int nside, T step,
+                                                           T lambda, double4 *__restrict__ out_pa,
+                                                           double *__restrict__ out_b)
+{
+    const int4 u = units[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int logtp = u.w;
+    const int tp = 1 << logtp;
+    const int kstride = 64 >> logtp;
+    const int t = lane & (tp - 1);
+    const int k = lane >> logtp;
+    const int i = u.y + min(t, u.z - 1);
+    const rec_t<T> ri = rec[i];
+    const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
+    double pr = 0, pi = 0, ar = 0, ai = 0, bb = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int ny = iy + dy;
+        if (ny < 0 || ny >= nside) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int nx = ix + dx;
+            if (nx < 0 || nx >= nside) continue;
+            const uint32_t S = morton_encode((uint32_t)nx, (uint32_t)ny);
+            const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
+            const T tx = ri.x - (T)dx * step;
+            const T ty = ri.y - (T)dy * step;
+            T fpr = 0, fpi = 0, far_ = 0, fai = 0, fb = 0;
+#pragma unroll 2
+            for (int j = s0 + k; j < s1; j += kstride) {
+                const rec_t<T> rj = rec[j];
+                const c2<T> qj = qv[j];
+                const T ddx = tx - rj.x;
+                const T ddy = ty - rj.y;
+                const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+                T e, g;
+                exp_pair(s, e, g);
+                const T r = recip(s);
+                // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
+                // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
+                //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
+                //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
+                const T x = lambda * s;
+                const bool small = x < series_cut<T>();
+                const T gser = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
+                const T hser = lambda * lambda *
+                               fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
+                const T gr = small ? gser : g * r;
+                // Phi: q_j * (g/s') * conj(dz')
+                const T cx = gr * ddx, cy = -gr * ddy;
+                fpr = fma(qj.x, cx, fpr);
+                fpr = fma(-qj.y, cy, fpr);
+                fpi = fma(qj.x, cy, fpi);
+                fpi = fma(qj.y, cx, fpi);
+                // A: Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2
+                const T h = (small ? hser : fma(lambda * e, s, -g) * r * r) * rj.z;
+                const T zr = fma(ddx, ddx, -ddy * ddy);
+                const T zi = (T)-2 * ddx * ddy;
+                far_ = fma(h, zr, far_);
+                fai = fma(h, zi, fai);
+                // B: Gamma_j e
+                fb = fma(rj.z, e, fb);
+            }
+            pr += (double)fpr;
+            pi += (double)fpi;
+            ar += (double)far_;
+            ai += (double)fai;
+            bb += (double)fb;
+        }
+    }
+    for (int o = tp; o < 64; o <<= 1) {
+        pr += __shfl_xor(pr, o);
+        pi += __shfl_xor(pi, o);
+        ar += __shfl_xor(ar, o);
+        ai += __shfl_xor(ai, o);
+        bb += __shfl_xor(bb, o);
+    }
+    if (k == 0 && t < u.z) {
+        out_pa[i] = make_double4(pr, pi, ar, ai);
+        out_b[i] = bb;
+    }
+}
+
+// Adjoint finalize: far parts from the q-field locals (Phi_far, by L2P) and the c-field
+// locals (W'_far = (1/w^2) sum_l l b_l xi^(l-1)), combined with the near sums.
+template <typename TL>
+__global__ __launch_bounds__(256) void finalize_backward_kernel(
+    int n, const int *__restrict__ perm, const int *__restrict__ leaf_of, const double2 *__restrict__ xy,
+    const double4 *__restrict__ near_pa, const double *__restrict__ near_b, const double2 *__restrict__ adj,
+    const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, int p, int has_far, double x0, double y0,
+    double w, double alpha, double lambda, double *__restrict__ dl_dgamma, double *__restrict__ dl_dxeval)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 a = near_pa[i];
+    const double sb = near_b[i];
+    double phr = alpha * a.x, phi = alpha * a.y;
+    const double ka = alpha * alpha * kInv2Pi;
+    // A = -i ka (a.z + i a.w) = ka (a.w, -a.z);  B = -i ka lambda sb
+    double Ar = ka * a.w, Ai = -ka * a.z;
+    const double Bi = -ka * lambda * sb;
+    double dwr = 0.0, dwi = 0.0;
+    if (has_far) {
+        const uint32_t leaf = (uint32_t)leaf_of[i];
+        const double cx = x0 + (morton_x(leaf) + 0.5) * w;
+        const double cy = y0 + (morton_y(leaf) + 0.5) * w;
+        const double2 z = xy[i];
+        const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        const c2<TL> *bq = loc_q + (int64_t)leaf * p;
+        const c2<TL> *bc = loc_c + (int64_t)leaf * p;
+        c2<TL> accq = bq[p - 1];
+        for (int l = p - 2; l >= 0; --l) accq = cmac<TL>(bq[l], accq, xi);
+        phr += (double)accq.x / w;
+        phi += (double)accq.y / w;
+        if (p >= 2) {
+            c2<TL> accd = mk<TL>((TL)(p - 1) * bc[p - 1].x, (TL)(p - 1) * bc[p - 1].y);
+            for (int l = p - 2; l >= 1; --l) {
+                const c2<TL> t = mk<TL>((TL)l * bc[l].x, (TL)l * bc[l].y);
+                accd = cmac<TL>(t, accd, xi);
+            }
+            dwr = (double)accd.x / (w * w);
+            dwi = (double)accd.y / (w * w);
+        }
+    }
+    const int64_t o = perm[i];
+    if (dl_dgamma) dl_dgamma[o] = -phi * kInv2Pi;
+    if (dl_dxeval) {
+        const double2 q = adj[i];
+        // D1 = A + B + W', D2 = A - B + W'  (B purely imaginary)
+        const double d1r = Ar + dwr, d1i = Ai + Bi + dwi;
+        const double d2r = Ar + dwr, d2i = Ai - Bi + dwi;
+        dl_dxeval[2 * o] = q.x * d1r - q.y * d1i;
+        dl_dxeval[2 * o + 1] = -(q.x * d2i + q.y * d2r);
+    }
+}
+
+__global__ __launch_bounds__(256) void widen_perm_kernel(int n, const int *__restrict__ perm,
+                                                          const int *__restrict__ leaf_of, int64_t *__restrict__ out,
+                                                          int32_t *__restrict__ leaf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = perm[i];
+    if (leaf) leaf[i] = leaf_of[i];
+}
+
+}  // namespace
+
+void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStream_t s)
+{
+    const int n = (int)t->n;
+    widen_perm_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, perm, leaf);
+}
+
+void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s)
+{
+    const double w = t->side / (double)(1 << t->depth);
+    const int n = (int)t->n;
+    if (is_double)
+        pack_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
+                                                                t->y0, w, alpha, (double4 *)rec);
+    else
+        pack_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
+                                                               t->y0, w, alpha, (float4 *)rec);
+}
+
+void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
+                        hipStream_t s)
+{
+    if (t->nunits == 0) return;
+    const int nside = 1 << t->depth;
+    const double w = t->side / (double)nside;
+    const double scale = alpha * kInv2Pi;
+    if (is_double)
+        p2p_forward_kernel<double><<<(unsigned)t->nunits, 64, 0, s>>>(
+            t->d_units, (const double4 *)rec, t->d_leaf_start, nside, alpha * w, scale, near);
+    else
+        p2p_forward_kernel<float><<<(unsigned)t->nunits, 64, 0, s>>>(
+            t->d_units, (const float4 *)rec, t->d_leaf_start, nside, (float)(alpha * w), scale, near);
+}
+
+void launch_far_chain(const FarArgs &a, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int L = t->depth;
+    if (L < 2) return;
+    const Tables &tb = t->tabs;
+    const bool fine_is_double = a.split >= L;  // FP64 precision: every level double
+    // Stage 4: P2M into the leaf level.
+    if (L <= a.split) {
+        if (a.rec_is_double) p2m_launch<double4, double>(a, s);
+        else p2m_launch<float4, double>(a, s);
+    } else {
+        if (a.rec_is_double) p2m_launch<double4, float>(a, s);
+        else p2m_launch<float4, float>(a, s);
+    }
+    // Stage 5 on the fine levels: parents L-1 .. max(lc, 2).
+    for (int l = L - 1; l >= 2 && l >= a.lc; --l) {
+        const bool child_d = (l + 1) <= a.split, parent_d = l <= a.split;
+        if (child_d && parent_d) m2m_launch<double, double>(a, l, tb.m2m_d, s);
+        else if (parent_d) m2m_launch<float, double>(a, l, tb.m2m_d, s);
+        else m2m_launch<float, float>(a, l, tb.m2m_f, s);
+    }
+    // Coarse levels 2..lc in one workgroup (stages 5, 6, 7 there).
+    if (a.lc >= 2) {
+        CoarseArgs c{};
+        c.p = a.p;
+        c.lc = a.lc;
+        c.counts = t->d_counts;
+        c.lists = t->d_lists;
+        for (int l = 0; l <= kMaxDepth; ++l) {
+            c.list_off[l] = l <= L ? t->list_off[l] : 0;
+            c.list_len[l] = l <= L ? t->list_len[l] : 0;
+        }
+        c.mp = a.mp_d;
+        c.lo = a.lo_d;
+        c.m2m_tab = tb.m2m_d;
+        c.m2l_tab = tb.m2l_d;
+        c.l2l_tab = tb.l2l_d;
+        coarse_kernel<<<1, 1024, 0, s>>>(c);
+    }
+    // Stages 6 + 7 on the fine levels.
+    for (int l = (a.lc + 1 > 2 ? a.lc + 1 : 2); l <= L; ++l) {
+        const bool here_d = l <= a.split, par_d = (l - 1) <= a.split;
+        if (here_d) m2l_launch<double, double>(a, l, tb.m2l_d, tb.l2l_d, s);
+        else if (par_d) m2l_launch<float, double>(a, l, tb.m2l_f, tb.l2l_d, s);
+        else m2l_launch<float, float>(a, l, tb.m2l_f, tb.l2l_f, s);
+    }
+    (void)fine_is_double;
+}
+
+void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, double *uv, double *uv_near,
+                     double *uv_far, hipStream_t s)
+{
+    const int L = t->depth;
+    const int n = (int)t->n;
+    const double w = t->side / (double)(1 << L);
+    const int has_far = L >= 2;
+    if (!has_far || L <= a.split)
+        finalize_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(
+            n, t->d_perm, t->d_leaf_of, t->d_xy, near, has_far ? level_ptr<double>(a, L, true) : nullptr, a.p,
+            has_far, t->x0, t->y0, w, uv, uv_near, uv_far);
+    else
+        finalize_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near,
+                                                                   level_ptr<float>(a, L, true), a.p, has_far,
+                                                                   t->x0, t->y0, w, uv, uv_near, uv_far);
+}
+
+void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double, hipStream_t s)
+{
+    const int n = (int)t->n;
+    if (is_double)
+        pack_adjoint_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, adj, nullptr);
+    else
+        pack_adjoint_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, adj, (float2 *)qt);
+}
+
+void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
+                         double4 *out_pa, double *out_b, hipStream_t s)
+{
+    if (t->nunits == 0) return;
+    const int nside = 1 << t->depth;
+    const double w = t->side / (double)nside;
+    if (is_double)
+        p2p_backward_kernel<double><<<(unsigned)t->nunits, 64, 0, s>>>(
+            t->d_units, (const double4 *)rec, (const double2 *)qv, t->d_leaf_start, nside, alpha * w, 1.0, out_pa,
+            out_b);
+    else
+        p2p_backward_kernel<float><<<(unsigned)t->nunits, 64, 0, s>>>(
+            t->d_units, (const float4 *)rec, (const float2 *)qv, t->d_leaf_start, nside, (float)(alpha * w),
+            (float)0.69314718055994530942, out_pa, out_b);
+}
+
+void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
+                              const double *near_b, const double2 *adj, int is_double, double alpha,
+                              double *dl_dgamma, double *dl_dxeval, hipStream_t s)
+{
+    const int L = t->depth;
+    const int n = (int)t->n;
+    const double w = t->side / (double)(1 << L);
+    const int has_far = L >= 2;
+    const double lambda = is_double ? 1.0 : 0.69314718055994530942;
+    if (!has_far || L <= fc.split)
+        finalize_backward_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(
+            n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj,
+            has_far ? level_ptr<double>(fc, L, true) : nullptr, has_far ? level_ptr<double>(fq, L, true) : nullptr,
+            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval);
+    else
+        finalize_backward_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(
+            n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj, level_ptr<float>(fc, L, true),
+            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval);
+}
+
+}  // namespace fmm

@@ -1,0 +1,113 @@
+// Radius-scaled translation operators for p-term expansions (host generation, FP64,
+// uploaded once per p as FP64 and FP32 copies).
+//
+// With multipoles scaled as a_m / w^m and locals as b_l w^(l+1) (w = cell width of
+// the level), the textbook translations become level independent:
+//   M2M (stage 5): A_m = sum_{k<=m} C(m,k) d^(m-k) 2^-k a_k,           d = (c_child - c_parent)/w_parent
+//   M2L (stage 6): b_l = sum_m (-1)^l C(l+m,m) delta^-(l+m+1) a_m,     delta = (c_T - c_S)/w
+//   L2L (stage 7): b_k = sum_{l>=k} C(l,k) d^(l-k) 2^-(k+1) b_l
+// derived from the multipole coefficients of section "Complexity Estimates" and the
+// expansion 1/(D + u - v) = sum_{l,m} (-1)^l C(l+m,l) u^l v^m / D^(l+m+1).
+#include <complex>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+namespace {
+
+using cd = std::complex<double>;
+
+std::vector<double> binomials(int nmax)
+{
+    std::vector<double> c((size_t)(nmax + 1) * (nmax + 1), 0.0);
+    for (int n = 0; n <= nmax; ++n) {
+        c[(size_t)n * (nmax + 1)] = 1.0;
+        for (int k = 1; k <= n; ++k)
+            c[(size_t)n * (nmax + 1) + k] = c[(size_t)(n - 1) * (nmax + 1) + k - 1] + c[(size_t)(n - 1) * (nmax + 1) + k];
+    }
+    return c;
+}
+
+cd child_offset(int q) { return cd(((q & 1) - 0.5) * 0.5, ((q >> 1) - 0.5) * 0.5); }
+
+template <typename V, typename S>
+int upload(V **dst, const std::vector<cd> &src, std::string &err)
+{
+    std::vector<V> h(src.size());
+    for (size_t i = 0; i < src.size(); ++i) {
+        h[i].x = (S)src[i].real();
+        h[i].y = (S)src[i].imag();
+    }
+    if (hipMalloc((void **)dst, h.size() * sizeof(V)) != hipSuccess) {
+        err = "hipMalloc failed for operator tables";
+        return -2;
+    }
+    if (hipMemcpy(*dst, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "hipMemcpy failed for operator tables";
+        return -3;
+    }
+    return 0;
+}
+
+}  // namespace
+
+void free_tables(Tables &tb)
+{
+    hipFree(tb.m2m_d);
+    hipFree(tb.l2l_d);
+    hipFree(tb.m2l_d);
+    hipFree(tb.m2m_f);
+    hipFree(tb.l2l_f);
+    hipFree(tb.m2l_f);
+    tb = Tables{};
+}
+
+int upload_tables(Tables &tb, int p, std::string &err)
+{
+    if (tb.p == p) return 0;
+    free_tables(tb);
+    const int nb = 2 * p;
+    const std::vector<double> C = binomials(nb);
+    auto binom = [&](int n, int k) { return C[(size_t)n * (nb + 1) + k]; };
+
+    std::vector<cd> m2m((size_t)4 * p * p, 0.0), l2l((size_t)4 * p * p, 0.0), m2l((size_t)49 * p * p, 0.0);
+    for (int q = 0; q < 4; ++q) {
+        const cd d = child_offset(q);
+        for (int m = 0; m < p; ++m)
+            for (int k = 0; k <= m; ++k)
+                m2m[((size_t)q * p + m) * p + k] = binom(m, k) * std::pow(d, m - k) * std::ldexp(1.0, -k);
+        for (int k = 0; k < p; ++k)
+            for (int l = k; l < p; ++l)
+                l2l[((size_t)q * p + k) * p + l] = binom(l, k) * std::pow(d, l - k) * std::ldexp(1.0, -(k + 1));
+    }
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy) {
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+            const int o = (dx + 3) * 7 + (dy + 3);
+            const cd inv = 1.0 / cd(dx, dy);
+            // powers inv^n, n = 1 .. 2p-1, by repeated multiplication
+            std::vector<cd> pw(2 * p + 1);
+            pw[0] = 1.0;
+            for (int n = 1; n <= 2 * p; ++n) pw[n] = pw[n - 1] * inv;
+            for (int m = 0; m < p; ++m)
+                for (int l = 0; l < p; ++l)
+                    m2l[((size_t)o * p + m) * p + l] = ((l & 1) ? -1.0 : 1.0) * binom(l + m, m) * pw[l + m + 1];
+        }
+    int rc = 0;
+    if (!rc) rc = upload<double2, double>(&tb.m2m_d, m2m, err);
+    if (!rc) rc = upload<double2, double>(&tb.l2l_d, l2l, err);
+    if (!rc) rc = upload<double2, double>(&tb.m2l_d, m2l, err);
+    if (!rc) rc = upload<float2, float>(&tb.m2m_f, m2m, err);
+    if (!rc) rc = upload<float2, float>(&tb.l2l_f, l2l, err);
+    if (!rc) rc = upload<float2, float>(&tb.m2l_f, m2l, err);
+    if (rc) {
+        free_tables(tb);
+        return rc;
+    }
+    tb.p = p;
+    return 0;
+}
+
+}  // namespace fmm

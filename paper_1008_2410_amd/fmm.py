@@ -1,0 +1,182 @@
+"""Python binding of the gfx950 FMM library: torch tensors in, torch tensors out.
+
+Every step of the evaluation runs in the HIP kernels of libfmm2d.so; this module
+only checks tensor shapes and devices, allocates outputs with torch and passes
+pointers and the current HIP stream to the C ABI (include/fmm2d.h).  There is no
+CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.FMM_FP64, "mixed": L.FMM_MIXED}
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_device_f64(x: torch.Tensor, name: str, shape: tuple, device) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if tuple(x.shape) != shape:
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(x.shape)}")
+    if device is not None and x.device != device:
+        raise ValueError(f"{name} is on {x.device}, tree on {device}")
+    return x.detach().contiguous()
+
+
+def _precision(precision) -> int:
+    if isinstance(precision, str):
+        return PRECISIONS[precision]
+    return int(precision)
+
+
+class Tree:
+    """Uniform quadtree over n particles (stages 1-3): Morton-sorted particles, leaf
+    offsets, per-level occupancy and near-field work units, resident on the device."""
+
+    def __init__(self, xy: torch.Tensor, depth: int, root_box=None, stream=None):
+        if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be an (n, 2) tensor")
+        self.device = xy.device
+        xy = _as_device_f64(xy, "xy", tuple(xy.shape), None)
+        self.n = int(xy.shape[0])
+        self.depth = int(depth)
+        lib = L.load()
+        handle = ctypes.c_void_p()
+        rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        with torch.cuda.device(self.device):
+            L.check(lib.fmm_build_tree(_ptr(xy), self.n, self.depth, rb, _stream_ptr(stream), ctypes.byref(handle)),
+                    "fmm_build_tree")
+        self._h = handle
+
+    # -- lifetime -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().fmm_destroy_tree(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("tree has been closed")
+        return self._h
+
+    # -- facts --------------------------------------------------------------------
+    def info(self) -> dict:
+        n = ctypes.c_int64()
+        depth = ctypes.c_int()
+        root = (ctypes.c_double * 3)()
+        pairs = ctypes.c_int64()
+        m2l = ctypes.c_int64()
+        ne = ctypes.c_int64()
+        mx = ctypes.c_int64()
+        L.check(L.load().fmm_tree_info(self.handle, ctypes.byref(n), ctypes.byref(depth), root, ctypes.byref(pairs),
+                                       ctypes.byref(m2l), ctypes.byref(ne), ctypes.byref(mx)), "fmm_tree_info")
+        return {"n": n.value, "depth": depth.value, "root_box": tuple(root), "p2p_pairs": pairs.value,
+                "m2l_pairs": m2l.value, "nonempty_leaves": ne.value, "max_leaf": mx.value}
+
+    def permutation(self):
+        """(perm, leaf): perm[k] = user index of the k-th particle in Morton order, leaf[k] its leaf."""
+        perm = torch.empty(self.n, dtype=torch.int64, device=self.device)
+        leaf = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_tree_permutation(self.handle, _ptr(perm), _ptr(leaf), _stream_ptr()),
+                    "fmm_tree_permutation")
+        return perm, leaf
+
+    def set_option(self, key: int, value: int):
+        L.check(L.load().fmm_set_option(self.handle, int(key), int(value)), "fmm_set_option")
+
+    def timings(self) -> dict:
+        """Per-stage device milliseconds summed over calls since the last read (FMM_OPT_TIMING on)."""
+        ms = (ctypes.c_double * L.FMM_T_COUNT)()
+        calls = ctypes.c_int64()
+        L.check(L.load().fmm_get_timings(self.handle, ms, ctypes.byref(calls)), "fmm_get_timings")
+        names = ["pack", "far", "p2p", "final", "total"]
+        return {"calls": calls.value, **{k: ms[i] for i, k in enumerate(names)}}
+
+    # -- evaluation ---------------------------------------------------------------
+    def velocity(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed", out=None,
+                 side_stream=None) -> torch.Tensor:
+        """(n, 2) float64 velocities in user order (stages 4-10)."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        uv = out if out is not None else torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_velocity(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                          _stream_ptr(), _stream_ptr(side_stream) if side_stream else None,
+                                          _ptr(uv)), "fmm_velocity")
+        return uv
+
+    def velocity_parts(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed"):
+        """(near, far) velocities, each (n, 2) float64 in user order."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        near = torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        far = torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_velocity_parts(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                                _stream_ptr(), None, _ptr(near), _ptr(far)), "fmm_velocity_parts")
+        return near, far
+
+    def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
+                          need_gamma: bool = True, need_x: bool = True):
+        """(dL/dGamma (n,) or None, dL/dx_eval (n, 2) or None) for a loss with gradient dl_duv."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
+        dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if need_gamma else None
+        dx = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_x else None
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_velocity_backward(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                                   _ptr(d), _stream_ptr(), None, _ptr(dg), _ptr(dx)),
+                    "fmm_velocity_backward")
+        return dg, dx
+
+
+class VelocityFn(torch.autograd.Function):
+    """u = FMM velocity of the particles of `tree` with circulations gamma.
+
+    Backward returns dL/dGamma and dL/dxy where dL/dxy is the derivative with
+    respect to the evaluation positions (the source positions held fixed)."""
+
+    @staticmethod
+    def forward(ctx, xy, gamma, tree: Tree, sigma: float, p: int, precision="mixed"):
+        uv = tree.velocity(gamma, sigma, p, precision)
+        ctx.save_for_backward(gamma)
+        ctx.tree, ctx.sigma, ctx.p, ctx.precision = tree, sigma, p, precision
+        return uv
+
+    @staticmethod
+    def backward(ctx, grad_uv):
+        (gamma,) = ctx.saved_tensors
+        need_x, need_g = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_x or need_g):
+            return None, None, None, None, None, None
+        dg, dx = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision,
+                                            grad_uv.contiguous(), need_gamma=need_g, need_x=need_x)
+        return dx, dg, None, None, None, None
+
+
+def velocity(xy: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, precision="mixed",
+             root_box=None, tree: Tree | None = None) -> torch.Tensor:
+    """Differentiable velocities of particles at xy; builds the tree unless one is given."""
+    if tree is None:
+        tree = Tree(xy, depth, root_box)
+    return VelocityFn.apply(xy, gamma, tree, sigma, p, precision)

@@ -25,3 +25,22 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def native_lib():
+    """The built HIP library (built once here if nothing is built yet)."""
+    from paper_1008_2410_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1008_2410_amd import build
+        build.build_library()
+    return _lib.load()
+
+
+@pytest.fixture(scope="session")
+def fmm_mod(native_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_1008_2410_amd import fmm
+    return fmm

@@ -1,0 +1,52 @@
+"""The C ABI library loads, exports every entry point the header declares, and rejects
+bad arguments with the documented status codes before touching a device."""
+import ctypes
+import os
+import re
+
+from paper_1008_2410_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fname in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fname.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fname)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(fmm_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fmm_build_tree", "fmm_velocity", "fmm_velocity_backward", "fmm_destroy_tree",
+                     "fmm_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(native_lib):
+    names = declared_functions()
+    assert names
+    for name in names:
+        assert hasattr(native_lib, name), name
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_bad_arguments_rejected_without_device(native_lib):
+    h = ctypes.c_void_p()
+    xy = ctypes.c_void_p(0x1000)  # never dereferenced: the checks come first
+    assert native_lib.fmm_build_tree(None, 10, 4, None, None, ctypes.byref(h)) == _lib.FMM_EINVAL
+    assert b"xy" in native_lib.fmm_last_error()
+    assert native_lib.fmm_build_tree(xy, 0, 4, None, None, ctypes.byref(h)) == _lib.FMM_EINVAL
+    assert native_lib.fmm_build_tree(xy, 10, 0, None, None, ctypes.byref(h)) == _lib.FMM_EINVAL
+    assert native_lib.fmm_build_tree(xy, 10, 13, None, None, ctypes.byref(h)) == _lib.FMM_EINVAL
+    assert native_lib.fmm_build_tree(xy, 1 << 31, 4, None, None, ctypes.byref(h)) == _lib.FMM_EINVAL
+    assert native_lib.fmm_build_tree(xy, 10, 4, None, None, None) == _lib.FMM_EINVAL
+    assert native_lib.fmm_velocity(None, xy, 0.1, 8, 0, None, None, xy) == _lib.FMM_ESTATE
+    assert native_lib.fmm_velocity_parts(None, xy, 0.1, 8, 0, None, None, None, xy) == _lib.FMM_EINVAL
+    assert native_lib.fmm_set_option(None, 1, 0) == _lib.FMM_ESTATE
+    assert native_lib.fmm_tree_info(None, None, None, None, None, None, None, None) == _lib.FMM_ESTATE
+    assert native_lib.fmm_get_timings(None, None, None) == _lib.FMM_ESTATE
+    native_lib.fmm_destroy_tree(None)

@@ -1,0 +1,104 @@
+"""GPU parity of the adjoint (fmm_velocity_backward) against the CPU oracle's O4.
+
+Bars: FP64 form within 1e-9 (vector rel-L2) of the oracle gradient; mixed form
+within 1e-4; both against central finite differences of the FP64 forward where the
+forward API can evaluate them (circulations; the evaluation-position derivative is
+checked against the oracle, whose own position derivative is pinned by finite
+differences in the oracle tests).
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+from paper_1008_2410_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _grads(fmm_mod, w, dl_duv, precision, tree=None):
+    tree = tree or fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    dg, dx = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl_duv))
+    return dg.cpu().numpy(), dx.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-4)])
+@pytest.mark.parametrize("n,depth,p", [(4096, 4, 10), (3000, 5, 12), (700, 1, 6), (5000, 3, 16)])
+def test_backward_matches_oracle(fmm_mod, oracle_mod, precision, tol, n, depth, p):
+    w = W.uniform_lamb_oseen(n=n, seed=n + depth, depth=depth, p=p)
+    ustar = W.smooth_target_field(w.xy, seed=7)
+    uv = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box)
+    dl = uv - ustar
+    dg_ref, dx_ref = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    dg, dx = _grads(fmm_mod, w, dl, precision)
+    assert rel_l2(dg, dg_ref) < tol
+    assert rel_l2(dx, dx_ref) < tol
+
+
+def test_gamma_gradient_central_differences_on_gpu(fmm_mod):
+    """u is linear in Gamma: central differences of L(Gamma) with the GPU FP64 forward equal
+    dL/dGamma to roundoff."""
+    w = W.uniform_lamb_oseen(n=6000, seed=77, depth=5, p=12)
+    ustar = W.smooth_target_field(w.xy, seed=8)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    g = _t(w.gamma)
+    uv = tree.velocity(g, w.sigma, w.p, "fp64").cpu().numpy()
+    dg, _ = _grads(fmm_mod, w, uv - ustar, "fp64", tree=tree)
+    for k in np.random.Generator(np.random.PCG64(3)).choice(w.n, 8, replace=False):
+        h = 1e-2 * abs(w.gamma[k]) + 1e-8
+        vals = []
+        for sgn in (1, -1):
+            gg = w.gamma.copy()
+            gg[k] += sgn * h
+            u = tree.velocity(_t(gg), w.sigma, w.p, "fp64").cpu().numpy()
+            vals.append(0.5 * ((u - ustar) ** 2).sum())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - dg[k]) <= 1e-7 * abs(dg[k]) + 1e-14, (k, fd, dg[k])
+
+
+def test_uniform_target_field_mixed(fmm_mod, oracle_mod):
+    """2^20 uniform particles, depth 8, p = 12, FP32 forward, L = 0.5 sum |u - u*|^2:
+    the mixed gradient within 1e-4 of the FP64 oracle gradient, over all particles and
+    at the 64 seeded coordinates (32 circulations, 32 positions)."""
+    w = W.uniform_target_field()
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    uv = tree.velocity(_t(w.gamma), w.sigma, w.p, "mixed").cpu().numpy()
+    dl = uv - w.extra["u_target"]
+    dg, dx = _grads(fmm_mod, w, dl, "mixed", tree=tree)
+    dg_ref, dx_ref = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    assert rel_l2(dg, dg_ref) < 1e-4
+    assert rel_l2(dx, dx_ref) < 1e-4
+    gi = w.extra["fd_gamma_idx"]
+    xi = w.extra["fd_x_idx"]
+    xc = w.extra["fd_x_comp"]
+    assert rel_l2(dg[gi], dg_ref[gi]) < 1e-4
+    assert rel_l2(dx[xi, xc], dx_ref[xi, xc]) < 1e-4
+
+
+def test_autograd_function(fmm_mod, oracle_mod):
+    import torch
+    w = W.uniform_lamb_oseen(n=3000, seed=5, depth=4, p=10)
+    ustar = _t(W.smooth_target_field(w.xy, seed=2))
+    xy = _t(w.xy).requires_grad_(True)
+    g = _t(w.gamma).requires_grad_(True)
+    uv = fmm_mod.velocity(xy, g, w.sigma, w.depth, w.p, "fp64", root_box=w.root_box)
+    loss = 0.5 * ((uv - ustar) ** 2).sum()
+    loss.backward()
+    dl = (uv - ustar).detach().cpu().numpy()
+    dg_ref, dx_ref = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    assert rel_l2(g.grad.cpu().numpy(), dg_ref) < 1e-9
+    assert rel_l2(xy.grad.cpu().numpy(), dx_ref) < 1e-9
+
+
+def test_backward_deterministic(fmm_mod):
+    w = W.uniform_lamb_oseen(n=20000, seed=6, depth=6, p=12)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    dl = np.random.Generator(np.random.PCG64(0)).standard_normal((w.n, 2))
+    for precision in ("fp64", "mixed"):
+        a = _grads(fmm_mod, w, dl, precision, tree=tree)
+        b = _grads(fmm_mod, w, dl, precision, tree=tree)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
