@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--depth", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--bwd-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -143,6 +144,48 @@ def main():
     uv_fp64 = out.cpu().numpy()
     log(f"[bench] fp64: {ms_fp64:.3f} ms/step, stages {stages_fp64}")
 
+    # backward pass (adjoint) at the same configuration: bwd/fwd time ratio
+    dl = torch.empty((w.n, 2), dtype=torch.float64, device=dev).normal_(generator=torch.Generator(dev).manual_seed(0))
+
+    def run_bwd(k, t=tree, g=gamma, sig=w.sigma, p=w.p, d=dl):
+        for _ in range(k):
+            t.velocity_backward(g, sig, p, "mixed", d)
+
+    run_bwd(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run_bwd(args.bwd_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1) / args.bwd_steps
+    log(f"[bench] mixed backward: {ms_bwd:.3f} ms/step (bwd/fwd {ms_bwd / ms:.3f})")
+    del dl
+    # 2^20 uniform particles, depth 8, p = 12 (the differentiation configuration)
+    wu = workloads.uniform_target_field()
+    xu = torch.from_numpy(wu.xy).to(dev)
+    gu = torch.from_numpy(wu.gamma).to(dev)
+    tu = fmm.Tree(xu, wu.depth, wu.root_box)
+    du = torch.from_numpy(wu.extra["u_target"]).to(dev)
+    ou = torch.empty((wu.n, 2), dtype=torch.float64, device=dev)
+
+    def time_it(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(k):
+            fn()
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / k
+
+    ms_fu = time_it(lambda: tu.velocity(gu, wu.sigma, wu.p, "mixed", out=ou), args.steps)
+    ms_bu = time_it(lambda: tu.velocity_backward(gu, wu.sigma, wu.p, "mixed", du), args.steps)
+    log(f"[bench] uniform 2^20 mixed: fwd {ms_fu:.3f} ms, bwd {ms_bu:.3f} ms (bwd/fwd {ms_bu / ms_fu:.3f})")
+    tu.close()
+    del xu, gu, du, ou
+
     idx = w.extra["sample"]
     cpu = None
     err_mixed = err_fp64 = None
@@ -186,6 +229,9 @@ def main():
         "overlap_fraction": None if overlap is None else round(overlap, 4),
         "fp64": {"ms_per_step": round(ms_fp64, 4), "value": round(w.n / (ms_fp64 * 1e-3) / 1e6, 3),
                  "stages_ms": {k: round(v, 4) for k, v in stages_fp64.items()}},
+        "bwd_fwd": {"gaussian_patches_16M": round(ms_bwd / ms, 4), "bwd_ms": round(ms_bwd, 4),
+                    "uniform_1M_p12": round(ms_bu / ms_fu, 4), "uniform_fwd_ms": round(ms_fu, 4),
+                    "uniform_bwd_ms": round(ms_bu, 4)},
         "tree": info,
     }
     if err_mixed is not None and err_mixed > 1e-5:

@@ -105,9 +105,11 @@ int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_bo
 int fmm_tree_info(const fmm_tree *tree, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
                   int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf);
 
-/* Morton order of the tree.  perm: device, n int64, perm[k] = user index of the k-th
- * particle in leaf-Morton order (stable inside a leaf).  leaf: device, n int32 or NULL,
- * leaf[k] = Morton index of that particle's leaf (x in the even bits). */
+/* Sorted order of the tree.  perm: device, n int64, perm[k] = user index of the k-th
+ * particle; particles are grouped by leaf in leaf-Morton order and, inside a leaf,
+ * ordered by the Morton index of their cell in a 64 x 64 grid over the leaf (ties by
+ * user index).  leaf: device, n int32 or NULL, leaf[k] = Morton index of that
+ * particle's leaf (x in the even bits). */
 int fmm_tree_permutation(const fmm_tree *tree, int64_t *perm, int32_t *leaf, void *stream);
 
 /*

@@ -98,6 +98,8 @@ void free_tree(fmm_tree *t)
     hipFree(t->d_counts);
     hipFree(t->d_lists);
     hipFree(t->d_units);
+    hipFree(t->d_tile_start);
+    hipFree(t->d_tile_box);
     free_workspace(t->ws);
     free_tables(t->tabs);
     if (t->own_side) hipStreamDestroy(t->own_side);
@@ -138,6 +140,9 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
                 if ((rc = dev_alloc(&ws.mp_f, cells_f * p, "multipoles"))) return rc;
                 if ((rc = dev_alloc(&ws.lo_f, cells_f * p, "locals"))) return rc;
             }
+            // Empty cells are never written; the MFMA M2L reads them as zero rows.
+            HIP_TRY(hipMemset(ws.mp_d, 0, cells_d * p * sizeof(double2)));
+            if (cells_f > 0) HIP_TRY(hipMemset(ws.mp_f, 0, cells_f * p * sizeof(float2)));
         }
         ws.p = p;
         ws.precision = precision;
@@ -154,7 +159,9 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
             if (cells_f > 0) {
                 if ((rc = dev_alloc(&ws.mp2_f, cells_f * p, "adjoint multipoles"))) return rc;
                 if ((rc = dev_alloc(&ws.lo2_f, cells_f * p, "adjoint locals"))) return rc;
+                HIP_TRY(hipMemset(ws.mp2_f, 0, cells_f * p * sizeof(float2)));
             }
+            HIP_TRY(hipMemset(ws.mp2_d, 0, cells_d * p * sizeof(double2)));
         }
     }
     return FMM_OK;
@@ -328,10 +335,13 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         const int64_t nleaf = int64_t(1) << (2 * L);
         const double w = t->side / (double)nside;
 
-        // Stage 2: leaf of each particle, floor binning clamped at the top edge.
+        // Stage 2: leaf of each particle, floor binning clamped at the top edge; and a
+        // sub-leaf key (Morton index in a 64 x 64 grid over the leaf) that orders the
+        // particles inside a leaf so that 64-particle tiles are spatially compact.
         std::vector<uint32_t> key((size_t)n);
+        std::vector<uint16_t> sub((size_t)n);
         for (int64_t i = 0; i < n; ++i) {
-            uint32_t c[2];
+            uint32_t c[2], f[2];
             for (int d = 0; d < 2; ++d) {
                 const double v = (h[2 * i + d] - (d ? t->y0 : t->x0)) / w;
                 if (!(v >= 0.0) || v > (double)nside) {
@@ -342,8 +352,10 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
                 }
                 int64_t k = (int64_t)std::floor(v);
                 c[d] = (uint32_t)std::min<int64_t>(k, nside - 1);
+                f[d] = (uint32_t)std::min<int64_t>((int64_t)std::floor((v - c[d]) * 64.0), 63);
             }
             key[i] = morton_encode(c[0], c[1]);
+            sub[i] = (uint16_t)morton_encode(f[0], f[1]);
         }
         // Stable counting sort by leaf Morton key.
         std::vector<int> leaf_start((size_t)nleaf + 1, 0);
@@ -357,11 +369,42 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
                 perm[pos] = (int)i;
                 leaf_of[pos] = (int)key[i];
             }
+            // inside each leaf: by sub-leaf key, ties by user index
+            for (int64_t c = 0; c < nleaf; ++c)
+                if (leaf_start[c + 1] - leaf_start[c] > 1)
+                    std::stable_sort(perm.begin() + leaf_start[c], perm.begin() + leaf_start[c + 1],
+                                     [&](int a, int b) { return sub[a] < sub[b]; });
         }
         std::vector<double2> xys((size_t)n);
         for (int64_t k = 0; k < n; ++k) {
             xys[k].x = h[2 * (size_t)perm[k]];
             xys[k].y = h[2 * (size_t)perm[k] + 1];
+        }
+        // 64-particle tiles of each leaf and their bounding boxes in leaf units about the
+        // leaf centre, rounded outwards to FP32.
+        std::vector<int> tile_start((size_t)nleaf + 1, 0);
+        for (int64_t c = 0; c < nleaf; ++c)
+            tile_start[c + 1] = tile_start[c] + (leaf_start[c + 1] - leaf_start[c] + 63) / 64;
+        std::vector<float4> tile_box((size_t)tile_start[nleaf]);
+        for (int64_t c = 0; c < nleaf; ++c) {
+            const double cx = t->x0 + (morton_x((uint32_t)c) + 0.5) * w;
+            const double cy = t->y0 + (morton_y((uint32_t)c) + 0.5) * w;
+            for (int b = leaf_start[c], tt = tile_start[c]; b < leaf_start[c + 1]; b += 64, ++tt) {
+                double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+                for (int k = b; k < std::min(b + 64, leaf_start[c + 1]); ++k) {
+                    const double xl = (xys[k].x - cx) / w, yl = (xys[k].y - cy) / w;
+                    xmin = std::min(xmin, xl);
+                    xmax = std::max(xmax, xl);
+                    ymin = std::min(ymin, yl);
+                    ymax = std::max(ymax, yl);
+                }
+                float4 bx;
+                bx.x = std::nextafter((float)xmin, -INFINITY);
+                bx.y = std::nextafter((float)ymin, -INFINITY);
+                bx.z = std::nextafter((float)xmax, INFINITY);
+                bx.w = std::nextafter((float)ymax, INFINITY);
+                tile_box[tt] = bx;
+            }
         }
         // Occupancy of every cell of every level (global cell index).
         std::vector<int> counts((size_t)level_base(L + 1), 0);
@@ -375,12 +418,15 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         std::vector<int> lists;
         t->list_off.assign(L + 1, 0);
         t->list_len.assign(L + 1, 0);
+        t->class_off.assign(4 * (L + 1), 0);
         for (int l = 2; l <= L; ++l) {
             t->list_off[l] = (int64_t)lists.size();
             const int64_t nc = int64_t(1) << (2 * l);
-            for (int par = 0; par < 4; ++par)
+            for (int par = 0; par < 4; ++par) {
+                t->class_off[4 * l + par] = (int64_t)lists.size() - t->list_off[l];
                 for (int64_t c = par; c < nc; c += 4)
                     if (counts[level_base(l) + c] > 0) lists.push_back((int)c);
+            }
             t->list_len[l] = (int64_t)lists.size() - t->list_off[l];
         }
         // Statistics: pairs (section "Complexity Estimates" direct work), M2L pairs.
@@ -452,6 +498,8 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         if (!rc) rc = upload(&t->d_counts, counts, "cell counts");
         if (!rc) rc = upload(&t->d_lists, lists, "cell lists");
         if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
+        if (!rc) rc = upload(&t->d_tile_start, tile_start, "tile offsets");
+        if (!rc) rc = upload(&t->d_tile_box, tile_box, "tile boxes");
         if (rc) {
             free_tree(t);
             return rc;

@@ -57,10 +57,15 @@ __host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2
 //   m2l[o][m][l]  = (-1)^l C(l+m,m) delta^-(l+m+1), delta = (dx, dy) of offset o = (dx+3)*7 + (dy+3)
 // with d_q = (c_child - c_parent)/w_parent = ((q&1) - 1/2)/2 + i((q>>1) - 1/2)/2.
 // ---------------------------------------------------------------------------------
+// mfma_f: the M2L and L2L operators as 2p x 2p real matrices (complex entries embedded
+// with interleaved (re, im) rows and columns, zero-padded to 32 x 32) in the operand
+// order of the MFMA M2L kernel: [slot][k / 16][column][k % 16], slots 0..48 the M2L
+// offsets (index (dx+3)*7 + (dy+3)), 49..52 the L2L parities.  Built for p <= 16.
 struct Tables {
     int p = 0;
     double2 *m2m_d = nullptr, *l2l_d = nullptr, *m2l_d = nullptr;
     float2 *m2m_f = nullptr, *l2l_f = nullptr, *m2l_f = nullptr;
+    float *mfma_f = nullptr;
 };
 
 // Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
@@ -98,6 +103,7 @@ struct fmm_tree {
     int64_t nunits = 0;
     std::vector<int64_t> list_off;  // per level l: offset into d_lists; list_len[l] entries
     std::vector<int64_t> list_len;
+    std::vector<int64_t> class_off; // per level l: 4 entries, start of each parity class inside the level list
 
     // device tree arrays
     int *d_perm = nullptr;        // sorted slot -> user index
@@ -107,6 +113,8 @@ struct fmm_tree {
     int *d_counts = nullptr;      // particles per cell, all levels, global cell index
     int *d_lists = nullptr;       // non-empty cells per level (levels 2..L), parity-grouped
     int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
+    int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
+    float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
 
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;

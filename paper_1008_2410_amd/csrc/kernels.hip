@@ -103,27 +103,77 @@ template <> __device__ __forceinline__ double tiny<double>() { return 1e-300; }
 // end, so no output is shared between work-items (the paper computes each pair from
 // both ends to avoid memory contention).  One wavefront per work unit
 // {leaf T, first target, count nt <= 64, log2 TP}: lane = k*TP + t handles target t
-// and sources j = k, k+K, ... (K = 64/TP) of each leaf S in the 3x3 neighbourhood, so
-// sparse leaves still fill the wavefront.  Per-source-leaf partial sums are kept in T
-// and folded into FP64; the K partial sums of a target are combined by lane shuffles.
+// and, of every 64-source tile of the 3x3 leaf neighbourhood, the sources k, k+K, ...
+// (K = 64/TP), so sparse leaves still fill the wavefront.
+//
+// Source tiles are the 64-particle, leaf-aligned chunks of the sorted order (particles
+// inside a leaf are ordered by a finer Morton key, so a tile is spatially compact).
+// Each tile is staged in LDS (one coalesced load, then broadcast reads) and tested
+// against the bounding box of the target chunk: when every pair of the tile has
+// s >= cut, 1 - exp(-s) rounds to exactly 1 in T and the exponential is skipped --
+// the result is bit-identical to evaluating it.
+// Per-leaf partial sums are kept in T and folded into FP64; the K partial sums of a
+// target are combined by lane shuffles.
 //   velocity u = -(alpha/2pi) sum Gamma g dY/s,  v = (alpha/2pi) sum Gamma g dX/s
 // ---------------------------------------------------------------------------------
+template <typename T, bool FAR>
+__device__ __forceinline__ void p2p_pair(const rec_t<T> &rj, T tx, T ty, T &fu, T &fv)
+{
+    const T ddx = tx - rj.x;
+    const T ddy = ty - rj.y;
+    const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+    const T g = FAR ? (T)1 : one_minus_exp(s);
+    const T f = (g * recip(s)) * rj.z;
+    fu = fma(f, ddy, fu);
+    fv = fma(f, ddx, fv);
+}
+
+template <typename T, int K, bool FAR>
+__device__ __forceinline__ void p2p_tile(const rec_t<T> *tile, int len, int k, T tx, T ty, T &fu, T &fv)
+{
+    if (len == 64) {
+#pragma unroll 8
+        for (int it = 0; it < 64 / K; ++it) p2p_pair<T, FAR>(tile[k + it * K], tx, ty, fu, fv);
+    } else {
+        for (int j = k; j < len; j += K) p2p_pair<T, FAR>(tile[j], tx, ty, fu, fv);
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void p2p_tile_any(const rec_t<T> *tile, int len, int k, T tx, T ty, T &fu, T &fv, bool far)
+{
+    if (far) p2p_tile<T, K, true>(tile, len, k, tx, ty, fu, fv);
+    else p2p_tile<T, K, false>(tile, len, k, tx, ty, fu, fv);
+}
+
+// Smallest squared distance between two boxes {xmin, ymin, xmax, ymax}, the first
+// shifted by (ox, oy).
+__device__ __forceinline__ float box_gap2(float4 a, float ox, float oy, float4 b)
+{
+    const float gx = fmaxf(0.0f, fmaxf(b.x - (a.z + ox), (a.x + ox) - b.z));
+    const float gy = fmaxf(0.0f, fmaxf(b.y - (a.w + oy), (a.y + oy) - b.w));
+    return gx * gx + gy * gy;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void p2p_forward_kernel(const int4 *__restrict__ units,
                                                           const rec_t<T> *__restrict__ rec,
-                                                          const int *__restrict__ leaf_start, int nside, T step,
-                                                          double scale, double2 *__restrict__ near)
+                                                          const int *__restrict__ leaf_start,
+                                                          const int *__restrict__ tile_start,
+                                                          const float4 *__restrict__ tile_box, int nside, T step,
+                                                          float cut_leaf2, double scale, double2 *__restrict__ near)
 {
+    __shared__ rec_t<T> tile[64];
     const int4 u = units[blockIdx.x];
     const int lane = threadIdx.x;
     const int logtp = u.w;
     const int tp = 1 << logtp;
-    const int kstride = 64 >> logtp;
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
     const rec_t<T> ri = rec[i];
     const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
+    const float4 tbox = tile_box[tile_start[u.x] + ((u.y - leaf_start[u.x]) >> 6)];
     double au = 0.0, av = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int ny = iy + dy;
@@ -137,15 +187,22 @@ __global__ __launch_bounds__(64) void p2p_forward_kernel(const int4 *__restrict_
             const T tx = ri.x - (T)dx * step;
             const T ty = ri.y - (T)dy * step;
             T fu = 0, fv = 0;
-#pragma unroll 4
-            for (int j = s0 + k; j < s1; j += kstride) {
-                const rec_t<T> rj = rec[j];
-                const T ddx = tx - rj.x;
-                const T ddy = ty - rj.y;
-                const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
-                const T f = (one_minus_exp(s) * recip(s)) * rj.z;
-                fu = fma(f, ddy, fu);
-                fv = fma(f, ddx, fv);
+            int tt = tile_start[S];
+            for (int base = s0; base < s1; base += 64, ++tt) {
+                const int len = min(64, s1 - base);
+                __syncthreads();
+                if (lane < len) tile[lane] = rec[base + lane];
+                const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
+                __syncthreads();
+                switch (logtp) {
+                case 6: p2p_tile_any<T, 1>(tile, len, k, tx, ty, fu, fv, far); break;
+                case 5: p2p_tile_any<T, 2>(tile, len, k, tx, ty, fu, fv, far); break;
+                case 4: p2p_tile_any<T, 4>(tile, len, k, tx, ty, fu, fv, far); break;
+                case 3: p2p_tile_any<T, 8>(tile, len, k, tx, ty, fu, fv, far); break;
+                case 2: p2p_tile_any<T, 16>(tile, len, k, tx, ty, fu, fv, far); break;
+                case 1: p2p_tile_any<T, 32>(tile, len, k, tx, ty, fu, fv, far); break;
+                default: p2p_tile_any<T, 64>(tile, len, k, tx, ty, fu, fv, far); break;
+                }
             }
             au += (double)fu;
             av += (double)fv;
@@ -274,6 +331,157 @@ __device__ __forceinline__ void m2l_one(int Tm, int lo, int p, int level, const 
         acc.y += (T)acc2.y;
     }
     lo_l[(int64_t)Tm * p + lo] = acc;
+}
+
+// ---------------------------------------------------------------------------------
+// Stages 6 + 7 on MFMA (FP32, p <= 16).  For a target cell T of parity class q the
+// local expansion is a sum of 28 dense products of 2p-vectors with 2p x 2p real
+// matrices (the complex operators embedded with interleaved (re, im) rows/columns):
+//   L(T) = sum_{o in IL offsets of q} M(T + o) R_o  +  L(parent(T)) R^{L2L}_q.
+// All targets of one parity class share the 28 matrices, so each wavefront takes 4
+// tiles of 32 same-class targets and accumulates 32 x 32 output tiles with
+// v_mfma_f32_32x32x2f32 (16 instructions per offset and tile, K = 32).  Empty and
+// out-of-domain source cells contribute zero rows (multipoles of empty cells are
+// kept at zero).  Operand layouts of the 32x32x2 instruction:
+//   A: lane l holds A[row l%32][k l/32]     B: lane l holds B[k l/32][col l%32]
+//   D: lane l, register r holds D[8(r/4) + 4(l/32) + r%4][l%32]
+// K is permuted so that step s uses k = 16(l/32) + s: a lane then reads 16
+// contiguous floats of its row, and the table stores B as [slot][l/32][col][s].
+// ---------------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaSlots = 53;  // 49 M2L offsets (7 x 7 grid, centre unused) + 4 L2L parities
+
+// a[s] = row[k0 + s] for k0 + s < two_p, else 0; a null row gives zeros.  Indices are
+// clamped into the row so no lane addresses past it.
+__device__ __forceinline__ void load_half_row(float (&a)[16], const float *row, int k0, int two_p)
+{
+    if (row && two_p == 32) {
+        const float4 *r4 = (const float4 *)(row + k0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float4 t4 = r4[v];
+            a[4 * v] = t4.x;
+            a[4 * v + 1] = t4.y;
+            a[4 * v + 2] = t4.z;
+            a[4 * v + 3] = t4.w;
+        }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k = min(k0 + s, two_p - 1);
+        const float v = row ? row[k] : 0.0f;
+        a[s] = (k0 + s < two_p) ? v : 0.0f;
+    }
+}
+__device__ __forceinline__ void load_half_row(float (&a)[16], const double *row, int k0, int two_p)
+{
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k = min(k0 + s, two_p - 1);
+        const float v = row ? (float)row[k] : 0.0f;
+        a[s] = (k0 + s < two_p) ? v : 0.0f;
+    }
+}
+constexpr int kMfmaTiles = 4;   // 32-target tiles per wavefront
+
+template <typename TPar>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(const int *__restrict__ targets, int4 class_start,
+                                                        int4 class_len, int4 class_wave0, int nwaves, int p,
+                                                        int level, const float *__restrict__ mp_l,
+                                                        float *__restrict__ lo_l, const float *__restrict__ tab,
+                                                        const c2<TPar> *__restrict__ loc_par)
+{
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int q = wave >= class_wave0.w ? 3 : wave >= class_wave0.z ? 2 : wave >= class_wave0.y ? 1 : 0;
+    const int cstart = q == 0 ? class_start.x : q == 1 ? class_start.y : q == 2 ? class_start.z : class_start.w;
+    const int clen = q == 0 ? class_len.x : q == 1 ? class_len.y : q == 2 ? class_len.z : class_len.w;
+    const int cw0 = q == 0 ? class_wave0.x : q == 1 ? class_wave0.y : q == 2 ? class_wave0.z : class_wave0.w;
+    const int base = (wave - cw0) * (32 * kMfmaTiles);
+    const int row = lane & 31, kh = lane >> 5;
+    const int two_p = 2 * p;
+    const int nside = 1 << level;
+    const int qx = q & 1, qy = q >> 1;
+
+    int tcell[kMfmaTiles], tx[kMfmaTiles], ty[kMfmaTiles];
+    bool tvalid[kMfmaTiles];
+#pragma unroll
+    for (int w = 0; w < kMfmaTiles; ++w) {
+        const int li = base + 32 * w + row;
+        tvalid[w] = li < clen;
+        tcell[w] = tvalid[w] ? targets[cstart + li] : 0;
+        tx[w] = (int)morton_x((uint32_t)tcell[w]);
+        ty[w] = (int)morton_y((uint32_t)tcell[w]);
+    }
+    floatx16 acc[kMfmaTiles];
+#pragma unroll
+    for (int w = 0; w < kMfmaTiles; ++w)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[w][r] = 0.0f;
+
+    const int k0 = 16 * kh;  // first k of this lane's half row
+    for (int dy = -2 - qy; dy <= 3 - qy; ++dy) {
+        for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+            // delta = (c_T - c_S)/w = (-dx, -dy)
+            const int slot = (3 - dx) * 7 + (3 - dy);
+            const float4 *bsrc = (const float4 *)(tab + ((size_t)(slot * 2 + kh) * 32 + row) * 16);
+            float b[16];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 t4 = bsrc[v];
+                b[4 * v] = t4.x;
+                b[4 * v + 1] = t4.y;
+                b[4 * v + 2] = t4.z;
+                b[4 * v + 3] = t4.w;
+            }
+#pragma unroll
+            for (int w = 0; w < kMfmaTiles; ++w) {
+                const int sx = tx[w] + dx, sy = ty[w] + dy;
+                const bool ok = tvalid[w] && sx >= 0 && sy >= 0 && sx < nside && sy < nside;
+                float a[16];
+                load_half_row(a, ok ? mp_l + (size_t)morton_encode((uint32_t)sx, (uint32_t)sy) * two_p : nullptr,
+                              k0, two_p);
+#pragma unroll
+                for (int s = 0; s < 16; ++s) acc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc[w], 0, 0, 0);
+            }
+        }
+    }
+    if (loc_par) {
+        const int slot = 49 + q;
+        const float4 *bsrc = (const float4 *)(tab + ((size_t)(slot * 2 + kh) * 32 + row) * 16);
+        float b[16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float4 t4 = bsrc[v];
+            b[4 * v] = t4.x;
+            b[4 * v + 1] = t4.y;
+            b[4 * v + 2] = t4.z;
+            b[4 * v + 3] = t4.w;
+        }
+#pragma unroll
+        for (int w = 0; w < kMfmaTiles; ++w) {
+            float a[16];
+            load_half_row(a, tvalid[w] ? (const TPar *)(loc_par + (size_t)(tcell[w] >> 2) * p) : nullptr, k0, two_p);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) acc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc[w], 0, 0, 0);
+        }
+    }
+    // Store: lane holds column `row` of rows 8(r/4) + 4 kh + r%4.
+    if (row < two_p) {
+#pragma unroll
+        for (int w = 0; w < kMfmaTiles; ++w) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int orow = 8 * (r >> 2) + 4 * kh + (r & 3);
+                const int li = base + 32 * w + orow;
+                if (li < clen) lo_l[(size_t)targets[cstart + li] * two_p + row] = acc[w][r];
+            }
+        }
+    }
 }
 
 template <typename TC, typename TP>
@@ -433,6 +641,29 @@ void m2m_launch(const FarArgs &a, int l, const c2<TP> *tab, hipStream_t s)
     m2m_kernel<TC, TP><<<blocks_for(n * a.p, 256), 256, 0, s>>>(
         level_list(t, l), (int)n, a.p, t->d_counts + level_base(l + 1), level_ptr<TC>(a, l + 1, false),
         level_ptr<TP>(a, l, false), tab);
+}
+
+template <typename TPar>
+void m2l_mfma_launch(const FarArgs &a, int l, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int64_t n = t->list_len[l];
+    if (n == 0) return;
+    const int *lst = level_list(t, l);
+    const int64_t *cs = &t->class_off[4 * l];
+    int cstart[4], clen[4], cw0[4];
+    int waves = 0;
+    for (int q = 0; q < 4; ++q) {
+        cstart[q] = (int)cs[q];
+        clen[q] = (int)((q < 3 ? cs[q + 1] : n) - cs[q]);
+        cw0[q] = waves;
+        waves += (clen[q] + 32 * kMfmaTiles - 1) / (32 * kMfmaTiles);
+    }
+    const c2<TPar> *par = l >= 3 ? level_ptr<TPar>(a, l - 1, true) : nullptr;
+    m2l_mfma_kernel<TPar><<<blocks_for((int64_t)waves * 64, 256), 256, 0, s>>>(
+        lst, make_int4(cstart[0], cstart[1], cstart[2], cstart[3]), make_int4(clen[0], clen[1], clen[2], clen[3]),
+        make_int4(cw0[0], cw0[1], cw0[2], cw0[3]), waves, a.p, l, (const float *)level_ptr<float>(a, l, false),
+        (float *)level_ptr<float>(a, l, true), t->tabs.mfma_f, par);
 }
 
 template <typename T, typename TPar>
@@ -667,12 +898,20 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
     const int nside = 1 << t->depth;
     const double w = t->side / (double)nside;
     const double scale = alpha * kInv2Pi;
+    const double step = alpha * w;
+    // Exponential skipped where every pair has s >= cut: FP32 base 2, 1 - 2^-s rounds to 1
+    // for s >= 26; FP64 base e, 1 - e^-s rounds to 1 for s >= 37.5.  One unit of margin
+    // covers the rounding of the records and of the box test (boxes in leaf units).
+    const double cut = is_double ? 39.0 : 27.0;
+    const float cut_leaf2 = (float)(cut / (step * step));
     if (is_double)
         p2p_forward_kernel<double><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const double4 *)rec, t->d_leaf_start, nside, alpha * w, scale, near);
+            t->d_units, (const double4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step,
+            cut_leaf2, scale, near);
     else
         p2p_forward_kernel<float><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const float4 *)rec, t->d_leaf_start, nside, (float)(alpha * w), scale, near);
+            t->d_units, (const float4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step,
+            cut_leaf2, scale, near);
 }
 
 void launch_far_chain(const FarArgs &a, hipStream_t s)
@@ -719,6 +958,8 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
     for (int l = (a.lc + 1 > 2 ? a.lc + 1 : 2); l <= L; ++l) {
         const bool here_d = l <= a.split, par_d = (l - 1) <= a.split;
         if (here_d) m2l_launch<double, double>(a, l, tb.m2l_d, tb.l2l_d, s);
+        else if (a.p <= 16 && par_d) m2l_mfma_launch<double>(a, l, s);
+        else if (a.p <= 16) m2l_mfma_launch<float>(a, l, s);
         else if (par_d) m2l_launch<float, double>(a, l, tb.m2l_f, tb.l2l_d, s);
         else m2l_launch<float, float>(a, l, tb.m2l_f, tb.l2l_f, s);
     }

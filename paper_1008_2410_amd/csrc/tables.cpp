@@ -61,6 +61,7 @@ void free_tables(Tables &tb)
     hipFree(tb.m2m_f);
     hipFree(tb.l2l_f);
     hipFree(tb.m2l_f);
+    hipFree(tb.mfma_f);
     tb = Tables{};
 }
 
@@ -95,7 +96,37 @@ int upload_tables(Tables &tb, int p, std::string &err)
                 for (int l = 0; l < p; ++l)
                     m2l[((size_t)o * p + m) * p + l] = ((l & 1) ? -1.0 : 1.0) * binom(l + m, m) * pw[l + m + 1];
         }
+    // Real 2p x 2p embedding for the MFMA kernel: y = x R with x, y interleaved (re, im),
+    // R[2m][2l] = Re T_lm, R[2m+1][2l] = -Im T_lm, R[2m][2l+1] = Im T_lm, R[2m+1][2l+1] = Re T_lm.
+    std::vector<float> mf;
+    if (p <= 16) {
+        mf.assign((size_t)53 * 2 * 32 * 16, 0.0f);
+        auto put = [&](int slot, int m, int l, cd v) {
+            const int k_re = 2 * m, k_im = 2 * m + 1, n_re = 2 * l, n_im = 2 * l + 1;
+            auto at = [&](int k, int n) -> float & { return mf[(((size_t)slot * 2 + k / 16) * 32 + n) * 16 + k % 16]; };
+            at(k_re, n_re) = (float)v.real();
+            at(k_im, n_re) = (float)-v.imag();
+            at(k_re, n_im) = (float)v.imag();
+            at(k_im, n_im) = (float)v.real();
+        };
+        for (int o = 0; o < 49; ++o)
+            for (int m = 0; m < p; ++m)
+                for (int l = 0; l < p; ++l) put(o, m, l, m2l[((size_t)o * p + m) * p + l]);
+        // L2L: output coefficient k from parent coefficient l (input)
+        for (int q = 0; q < 4; ++q)
+            for (int k = 0; k < p; ++k)
+                for (int l = 0; l < p; ++l) put(49 + q, l, k, l2l[((size_t)q * p + k) * p + l]);
+    }
     int rc = 0;
+    if (!rc && p <= 16) {
+        if (hipMalloc((void **)&tb.mfma_f, mf.size() * sizeof(float)) != hipSuccess) {
+            err = "hipMalloc failed for operator tables";
+            rc = -2;
+        } else if (hipMemcpy(tb.mfma_f, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            err = "hipMemcpy failed for operator tables";
+            rc = -3;
+        }
+    }
     if (!rc) rc = upload<double2, double>(&tb.m2m_d, m2m, err);
     if (!rc) rc = upload<double2, double>(&tb.l2l_d, l2l, err);
     if (!rc) rc = upload<double2, double>(&tb.m2l_d, m2l, err);

@@ -48,8 +48,18 @@ def test_tree_binning_and_permutation(fmm_mod, oracle_mod):
         ly |= ((leaf >> (2 * b + 1)) & 1) << b
     assert np.array_equal(lx, ix[perm]) and np.array_equal(ly, iy[perm])
     assert np.all(np.diff(leaf) >= 0)
+    # inside a leaf: ordered by the Morton index of the 64 x 64 sub-cell, ties by user index
+    wl = w.root_box[2] / 2 ** w.depth
+    sx = np.minimum(np.floor(((w.xy[perm, 0] - w.root_box[0]) / wl - lx) * 64), 63).astype(np.int64)
+    sy = np.minimum(np.floor(((w.xy[perm, 1] - w.root_box[1]) / wl - ly) * 64), 63).astype(np.int64)
+    sub = np.zeros_like(sx)
+    for b in range(6):
+        sub |= ((sx >> b) & 1) << (2 * b)
+        sub |= ((sy >> b) & 1) << (2 * b + 1)
     same = np.diff(leaf) == 0
-    assert np.all(np.diff(perm)[same] > 0)  # stable inside a leaf
+    assert np.all(np.diff(sub)[same] >= 0)
+    tie = same & (np.diff(sub) == 0)
+    assert np.all(np.diff(perm)[tie] > 0)
     info = tree.info()
     counts = oracle_mod.leaf_counts(w.xy, w.depth, w.root_box)
     assert info["p2p_pairs"] == oracle_mod.pair_count(counts)
