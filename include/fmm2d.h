@@ -61,8 +61,13 @@ enum {
                                  1: everything serialised on the main stream */
     FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in one
                                  single-workgroup kernel in FP64 (default 4, range 1..depth) */
-    FMM_OPT_TIMING = 3        /* 1: record HIP events around each stage of every call for
+    FMM_OPT_TIMING = 3,       /* 1: record HIP events around each stage of every call for
                                  fmm_get_timings (default 0) */
+    FMM_OPT_NEAR_WAVES = 4,   /* near-field grid: 0 = one workgroup per work unit (default);
+                                 N > 0 = a persistent grid of N wavefronts taking units from a
+                                 counter, leaving the rest of the chip to the far field */
+    FMM_OPT_FAR_WAVES = 5     /* cap on the far-field kernels' grids (wavefronts) while they run
+                                 beside the near field; 0 = none (default) */
 };
 
 /* Stage indices of fmm_get_timings. */

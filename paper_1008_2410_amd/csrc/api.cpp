@@ -100,6 +100,7 @@ void free_tree(fmm_tree *t)
     hipFree(t->d_units);
     hipFree(t->d_tile_start);
     hipFree(t->d_tile_box);
+    hipFree(t->d_work);
     free_workspace(t->ws);
     free_tables(t->tabs);
     if (t->own_side) hipStreamDestroy(t->own_side);
@@ -134,15 +135,19 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
         if ((rc = dev_alloc((char **)&ws.rec, n * rec_bytes, "particle records"))) return rc;
         if ((rc = dev_alloc(&ws.near, n, "near field"))) return rc;
         if (L >= 2) {
-            if ((rc = dev_alloc(&ws.mp_d, cells_d * p, "multipoles"))) return rc;
-            if ((rc = dev_alloc(&ws.lo_d, cells_d * p, "locals"))) return rc;
+            if ((rc = dev_alloc(&ws.mp_d, cells_d * p + kCoefPad, "multipoles"))) return rc;
+            if ((rc = dev_alloc(&ws.lo_d, cells_d * p + kCoefPad, "locals"))) return rc;
             if (cells_f > 0) {
-                if ((rc = dev_alloc(&ws.mp_f, cells_f * p, "multipoles"))) return rc;
-                if ((rc = dev_alloc(&ws.lo_f, cells_f * p, "locals"))) return rc;
+                if ((rc = dev_alloc(&ws.mp_f, cells_f * p + kCoefPad, "multipoles"))) return rc;
+                if ((rc = dev_alloc(&ws.lo_f, cells_f * p + kCoefPad, "locals"))) return rc;
             }
             // Empty cells are never written; the MFMA M2L reads them as zero rows.
-            HIP_TRY(hipMemset(ws.mp_d, 0, cells_d * p * sizeof(double2)));
-            if (cells_f > 0) HIP_TRY(hipMemset(ws.mp_f, 0, cells_f * p * sizeof(float2)));
+            HIP_TRY(hipMemset(ws.mp_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
+            HIP_TRY(hipMemset(ws.lo_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
+            if (cells_f > 0) {
+                HIP_TRY(hipMemset(ws.mp_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
+                HIP_TRY(hipMemset(ws.lo_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
+            }
         }
         ws.p = p;
         ws.precision = precision;
@@ -154,14 +159,16 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
         if ((rc = dev_alloc(&ws.bwd_b, n, "adjoint near field"))) return rc;
         if (precision != FMM_FP64 && (rc = dev_alloc((float2 **)&ws.rec2, n, "adjoint charges (FP32)"))) return rc;
         if (L >= 2) {
-            if ((rc = dev_alloc(&ws.mp2_d, cells_d * p, "adjoint multipoles"))) return rc;
-            if ((rc = dev_alloc(&ws.lo2_d, cells_d * p, "adjoint locals"))) return rc;
+            if ((rc = dev_alloc(&ws.mp2_d, cells_d * p + kCoefPad, "adjoint multipoles"))) return rc;
+            if ((rc = dev_alloc(&ws.lo2_d, cells_d * p + kCoefPad, "adjoint locals"))) return rc;
+            HIP_TRY(hipMemset(ws.mp2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
+            HIP_TRY(hipMemset(ws.lo2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
             if (cells_f > 0) {
-                if ((rc = dev_alloc(&ws.mp2_f, cells_f * p, "adjoint multipoles"))) return rc;
-                if ((rc = dev_alloc(&ws.lo2_f, cells_f * p, "adjoint locals"))) return rc;
-                HIP_TRY(hipMemset(ws.mp2_f, 0, cells_f * p * sizeof(float2)));
+                if ((rc = dev_alloc(&ws.mp2_f, cells_f * p + kCoefPad, "adjoint multipoles"))) return rc;
+                if ((rc = dev_alloc(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals"))) return rc;
+                HIP_TRY(hipMemset(ws.mp2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
+                HIP_TRY(hipMemset(ws.lo2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
             }
-            HIP_TRY(hipMemset(ws.mp2_d, 0, cells_d * p * sizeof(double2)));
         }
     }
     return FMM_OK;
@@ -201,8 +208,15 @@ FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
     a.rec_is_double = precision == FMM_FP64;
     a.charge_kind = adjoint ? 1 : 0;
     a.adj = adjoint ? ws.adj : nullptr;
+    // Beside the near field the far-field grids can be capped (FMM_OPT_FAR_WAVES);
+    // serialised they take the whole chip.
+    a.max_waves = t->schedule == 0 ? t->far_waves : 0;
     return a;
 }
+
+// Near-field grid: FMM_OPT_NEAR_WAVES when set (0: one workgroup per unit), else one
+// workgroup per unit.
+int near_waves(const fmm_tree *t) { return t->near_waves; }
 
 struct Timing {
     std::array<hipEvent_t, kNumEvents> ev{};
@@ -255,7 +269,7 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
-    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, ms);
+    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, near_waves(t), ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
@@ -291,6 +305,12 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
             return hip_fail(de, "hipGetDevice");
         }
         t->device = dev;
+        {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            t->num_cus = cus;
+        }
         t->n = n;
         t->depth = depth;
 
@@ -500,6 +520,7 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
         if (!rc) rc = upload(&t->d_tile_start, tile_start, "tile offsets");
         if (!rc) rc = upload(&t->d_tile_box, tile_box, "tile boxes");
+        if (!rc) rc = dev_alloc(&t->d_work, 4, "work counter");
         if (rc) {
             free_tree(t);
             return rc;
@@ -610,7 +631,7 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
     launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
-                        ws.bwd_b, ms);
+                        ws.bwd_b, near_waves(t), ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
@@ -632,6 +653,14 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
     case FMM_OPT_COARSE_LEVEL:
         if (value < 1 || value > t->depth) return fail(FMM_EINVAL, "coarse level must be in [1, depth]");
         t->lc = (int)value;
+        return FMM_OK;
+    case FMM_OPT_NEAR_WAVES:
+        if (value < 0 || value > (int64_t(1) << 30)) return fail(FMM_EINVAL, "near waves must be in [0, 2^30]");
+        t->near_waves = (int)value;
+        return FMM_OK;
+    case FMM_OPT_FAR_WAVES:
+        if (value < 0 || value > (int64_t(1) << 30)) return fail(FMM_EINVAL, "far waves must be in [0, 2^30]");
+        t->far_waves = (int)value;
         return FMM_OK;
     case FMM_OPT_TIMING:
         if (value != 0 && value != 1) return fail(FMM_EINVAL, "timing must be 0 or 1");

@@ -60,13 +60,21 @@ __host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2
 // mfma_f: the M2L and L2L operators as 2p x 2p real matrices (complex entries embedded
 // with interleaved (re, im) rows and columns, zero-padded to 32 x 32) in the operand
 // order of the MFMA M2L kernel: [slot][k / 16][column][k % 16], slots 0..48 the M2L
-// offsets (index (dx+3)*7 + (dy+3)), 49..52 the L2L parities.  Built for p <= 16.
+// offsets (index (dx+3)*7 + (dy+3)), 49..52 the L2L parities, 53..56 the M2M children.
+// Built for p <= 16.
 struct Tables {
     int p = 0;
     double2 *m2m_d = nullptr, *l2l_d = nullptr, *m2l_d = nullptr;
     float2 *m2m_f = nullptr, *l2l_f = nullptr, *m2l_f = nullptr;
     float *mfma_f = nullptr;
+    double *mfma_d = nullptr;      // FP64 MFMA operand order: [slot][k / 8][column][k % 8]
+    int4 *mfma_entries = nullptr;  // {dx, dy, slot, kind}: 4 x 28 M2L/L2L entries, then 4 M2M entries
+    double *zero_row = nullptr;    // 128 zero doubles: the row read for absent source cells
 };
+
+// Coefficient arrays are allocated with this many extra elements at the end, so that
+// fixed-length reads of a row never pass the allocation.
+constexpr int64_t kCoefPad = 64;
 
 // Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
 // are FP64, levels split+1..L are FP32; each level holds 4^l cells x p coefficients,
@@ -93,7 +101,10 @@ struct fmm_tree {
     int depth = 0;
     double x0 = 0, y0 = 0, side = 1;
     int device = 0;
+    int num_cus = 256;   // compute units of the device
     int lc = 4;          // coarse-level cutoff L_c
+    int near_waves = 0;  // persistent near-field grid in wavefronts (0: one workgroup per unit)
+    int far_waves = 0;   // cap of the far-field grids beside the near field (0: none)
     int schedule = 0;    // 0 overlap, 1 serial
     int timing = 0;
     std::atomic<int> busy{0};
@@ -115,6 +126,7 @@ struct fmm_tree {
     int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
     int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
     float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
+    int *d_work = nullptr;        // near-field work counter (reset by each call's first kernel)
 
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -138,12 +150,13 @@ struct FarArgs {
     int rec_is_double;
     int charge_kind;           // 0: real Gamma in rec.z -> c = -i Gamma/(2 pi); 1: complex q from adj array
     const double2 *adj;        // complex charges in sorted order (charge_kind 1)
+    int max_waves;             // grid cap of the far-field kernels (0: none)
 };
 
 // Launchers (kernels.hip).  All are asynchronous on `s`.
 void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        hipStream_t s);
+                        int near_waves, hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, double *uv, double *uv_near,
                      double *uv_far, hipStream_t s);
@@ -152,7 +165,7 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, d
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,
                          hipStream_t s);
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, hipStream_t s);
+                         double4 *out_pa, double *out_b, int near_waves, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, int is_double, double alpha,
                               double *dl_dgamma, double *dl_dxeval, hipStream_t s);

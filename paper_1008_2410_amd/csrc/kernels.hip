@@ -71,9 +71,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void pack_kernel(int n, const int *__restrict__ perm, const int *__restrict__ leaf_of,
                                                     const double2 *__restrict__ xy, const double *__restrict__ gamma,
                                                     double x0, double y0, double w, double alpha,
-                                                    rec_t<T> *__restrict__ rec)
+                                                    rec_t<T> *__restrict__ rec, int *__restrict__ work_ctr)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && work_ctr) work_ctr[0] = 0;  // near-field work counter of this call
     if (i >= n) return;
     uint32_t leaf = (uint32_t)leaf_of[i];
     double cx = x0 + (morton_x(leaf) + 0.5) * w;
@@ -92,10 +93,11 @@ __device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builti
 __device__ __forceinline__ double one_minus_exp(double s) { return -expm1(-s); }
 __device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
 __device__ __forceinline__ double recip(double s) { return 1.0 / s; }
-// Added to every s: a pair at distance 0 (the particle itself) then gives g = 0 and
-// a finite 1/s, hence exactly zero, while any s above ~1e-23 (FP32) is unchanged.
+// Added to every s: a pair at distance 0 (the particle itself) then gives g = 0 and a
+// finite Gamma/s (for |Gamma| < 1e18 in FP32), hence exactly zero, while any s above
+// ~1e-13 (FP32) or ~1e-284 (FP64) is unchanged.
 template <typename T> __device__ __forceinline__ T tiny();
-template <> __device__ __forceinline__ float tiny<float>() { return 1e-30f; }
+template <> __device__ __forceinline__ float tiny<float>() { return 1e-20f; }
 template <> __device__ __forceinline__ double tiny<double>() { return 1e-300; }
 
 // ---------------------------------------------------------------------------------
@@ -116,14 +118,22 @@ template <> __device__ __forceinline__ double tiny<double>() { return 1e-300; }
 // target are combined by lane shuffles.
 //   velocity u = -(alpha/2pi) sum Gamma g dY/s,  v = (alpha/2pi) sum Gamma g dX/s
 // ---------------------------------------------------------------------------------
+// f = Gamma (1 - e)/s evaluated as q - e q with q = Gamma/s (one fused multiply-add);
+// on a far tile e rounds to 0 against 1 and f = q.
+__device__ __forceinline__ float exp_neg_scaled(float s) { return __builtin_amdgcn_exp2f(-s); }
+__device__ __forceinline__ double exp_neg_scaled(double s) { return exp(-s); }
+
 template <typename T, bool FAR>
 __device__ __forceinline__ void p2p_pair(const rec_t<T> &rj, T tx, T ty, T &fu, T &fv)
 {
     const T ddx = tx - rj.x;
     const T ddy = ty - rj.y;
     const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
-    const T g = FAR ? (T)1 : one_minus_exp(s);
-    const T f = (g * recip(s)) * rj.z;
+    const T q = recip(s) * rj.z;
+    T f;
+    if (FAR) f = q;
+    else if (sizeof(T) == 4) f = fma(-exp_neg_scaled(s), q, q);
+    else f = one_minus_exp(s) * q;
     fu = fma(f, ddy, fu);
     fv = fma(f, ddx, fv);
 }
@@ -156,15 +166,12 @@ __device__ __forceinline__ float box_gap2(float4 a, float ox, float oy, float4 b
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void p2p_forward_kernel(const int4 *__restrict__ units,
-                                                          const rec_t<T> *__restrict__ rec,
-                                                          const int *__restrict__ leaf_start,
-                                                          const int *__restrict__ tile_start,
-                                                          const float4 *__restrict__ tile_box, int nside, T step,
-                                                          float cut_leaf2, double scale, double2 *__restrict__ near)
+__device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, const rec_t<T> *__restrict__ rec,
+                                                 const int *__restrict__ leaf_start,
+                                                 const int *__restrict__ tile_start,
+                                                 const float4 *__restrict__ tile_box, int nside, T step,
+                                                 float cut_leaf2, double scale, double2 *__restrict__ near)
 {
-    __shared__ rec_t<T> tile[64];
-    const int4 u = units[blockIdx.x];
     const int lane = threadIdx.x;
     const int logtp = u.w;
     const int tp = 1 << logtp;
@@ -215,26 +222,65 @@ __global__ __launch_bounds__(64) void p2p_forward_kernel(const int4 *__restrict_
     if (k == 0 && t < u.z) near[i] = make_double2(-scale * au, scale * av);
 }
 
-// ---------------------------------------------------------------------------------
-// Stage 4, P2M: one wavefront per non-empty leaf,
-//   a_m = sum_{j in leaf} c_j xi_j^m,  xi_j = (z_j - c_leaf)/w_L,  m = 0..p-1.
-// Lanes stride over the leaf's particles; the per-lane sums are combined by shuffles.
-// Charges: c_j = -i Gamma_j/(2 pi) from the records, or complex adjoint charges.
-// ---------------------------------------------------------------------------------
+// Near-field grid, two forms.  One workgroup per unit (persistent == 0): the hardware
+// dispatcher hands out units in order, heaviest first.  Persistent (persistent != 0):
+// a grid smaller than the chip's capacity, each wavefront taking batches of
+// kNearBatch consecutive units from the call's counter until none is left, which
+// leaves wavefront slots free for far-field kernels running beside it.  Either way
+// each unit writes only its own targets, so the result does not depend on which
+// wavefront takes which unit.  The counter's atomic is issued by one lane (a vector
+// memory atomic) and broadcast to the wavefront.
+constexpr int kNearBatch = 4;
+
+template <typename T>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_forward_kernel(const int4 *__restrict__ units,
+                                                                                 int nunits, int persistent,
+                                                                                 int *__restrict__ work_ctr,
+                                                                                 const rec_t<T> *__restrict__ rec,
+                                                                                 const int *__restrict__ leaf_start,
+                                                                                 const int *__restrict__ tile_start,
+                                                                                 const float4 *__restrict__ tile_box,
+                                                                                 int nside, T step, float cut_leaf2,
+                                                                                 double scale,
+                                                                                 double2 *__restrict__ near)
+{
+    __shared__ rec_t<T> tile[64];
+    if (!persistent) {
+        p2p_forward_unit<T>(units[blockIdx.x], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
+                            scale, near);
+        return;
+    }
+    for (;;) {
+        int v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(work_ctr, kNearBatch);
+        const int first = __builtin_amdgcn_readfirstlane(v);
+        if (first >= nunits) break;
+        const int last = min(first + kNearBatch, nunits);
+        for (int cur = first; cur < last; ++cur)
+            p2p_forward_unit<T>(units[cur], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
+                                scale, near);
+    }
+}
+
 template <typename TR, typename TC, int PMAX>
-__global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, const int *__restrict__ leaf_start,
+__global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, int nleaves,
+                                                  const int *__restrict__ leaf_start,
                                                   const double2 *__restrict__ xy, const TR *__restrict__ rec,
                                                   const double2 *__restrict__ adj, double x0, double y0, double w,
                                                   int p, c2<TC> *__restrict__ out)
 {
-    const uint32_t leaf = (uint32_t)leaves[blockIdx.x];
+    constexpr int NC = 2 * PMAX;             // partial sums per lane (re, im interleaved)
+    __shared__ TC red[64][NC + 1];
+    const int lane = threadIdx.x;
+    for (int li = blockIdx.x; li < nleaves; li += gridDim.x) {
+    const uint32_t leaf = (uint32_t)leaves[li];
     const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
     const double cx = x0 + (morton_x(leaf) + 0.5) * w;
     const double cy = y0 + (morton_y(leaf) + 0.5) * w;
     c2<TC> acc[PMAX];
 #pragma unroll
     for (int m = 0; m < PMAX; ++m) acc[m] = mk<TC>(0, 0);
-    for (int j = s0 + (int)threadIdx.x; j < s1; j += 64) {
+    for (int j = s0 + lane; j < s1; j += 64) {
         const double2 z = xy[j];
         const c2<TC> xi = mk<TC>((TC)((z.x - cx) / w), (TC)((z.y - cy) / w));
         c2<TC> pw;
@@ -253,19 +299,22 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
             }
         }
     }
-    c2<TC> mine = mk<TC>(0, 0);
 #pragma unroll
     for (int m = 0; m < PMAX; ++m) {
-        if (m < p) {
-            TC re = acc[m].x, im = acc[m].y;
-            for (int o = 32; o >= 1; o >>= 1) {
-                re += __shfl_xor(re, o);
-                im += __shfl_xor(im, o);
-            }
-            if ((int)threadIdx.x == m) mine = mk<TC>(re, im);
-        }
+        red[lane][2 * m] = acc[m].x;
+        red[lane][2 * m + 1] = acc[m].y;
     }
-    if ((int)threadIdx.x < p) out[(int64_t)leaf * p + threadIdx.x] = mine;
+    __syncthreads();
+    // lane -> column col of the 2p partial sums, rows r0, r0 + 1, ... (NC lanes per row set)
+    const int col = lane % NC;
+    const int r0 = (lane / NC) * NC;
+    const int nrow = NC < 64 ? NC : 64;
+    TC sum = 0;
+    for (int r = 0; r < nrow; ++r) sum += red[r0 + r][col];
+    if (NC < 64) sum += __shfl_xor(sum, 32);
+    if (lane < 2 * p) ((TC *)out)[(int64_t)leaf * 2 * p + lane] = sum;
+    __syncthreads();  // red is reused by the next leaf
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -350,137 +399,232 @@ __device__ __forceinline__ void m2l_one(int Tm, int lo, int p, int level, const 
 // ---------------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kMfmaSlots = 53;  // 49 M2L offsets (7 x 7 grid, centre unused) + 4 L2L parities
 
-// a[s] = row[k0 + s] for k0 + s < two_p, else 0; a null row gives zeros.  Indices are
-// clamped into the row so no lane addresses past it.
+// a[s] = row[k0 + s] for k0 + s < two_p, else 0.  Every coefficient array carries a
+// tail pad of 64 elements and absent sources read a zero row, so the 16 reads of a
+// half row never leave their allocation.
 __device__ __forceinline__ void load_half_row(float (&a)[16], const float *row, int k0, int two_p)
 {
-    if (row && two_p == 32) {
-        const float4 *r4 = (const float4 *)(row + k0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float4 t4 = r4[v];
-            a[4 * v] = t4.x;
-            a[4 * v + 1] = t4.y;
-            a[4 * v + 2] = t4.z;
-            a[4 * v + 3] = t4.w;
-        }
-        return;
-    }
+    const float *r = row + k0;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        const int k = min(k0 + s, two_p - 1);
-        const float v = row ? row[k] : 0.0f;
+        const float v = r[s];
         a[s] = (k0 + s < two_p) ? v : 0.0f;
     }
 }
 __device__ __forceinline__ void load_half_row(float (&a)[16], const double *row, int k0, int two_p)
 {
+    const double *r = row + k0;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        const int k = min(k0 + s, two_p - 1);
-        const float v = row ? (float)row[k] : 0.0f;
-        a[s] = (k0 + s < two_p) ? v : 0.0f;
+        const double v = r[s];
+        a[s] = (k0 + s < two_p) ? (float)v : 0.0f;
     }
 }
-constexpr int kMfmaTiles = 4;   // 32-target tiles per wavefront
 
+// One 32-target tile per wavefront: the 28 (M2L) or 4 (M2M) products of a tile run as
+// one chain of 16-instruction groups.  Entries {dx, dy, slot, kind} of a class:
+//   kind 0: M2L source cell (tx + dx, ty + dy) of the same level (skipped if outside)
+//   kind 1: L2L from the parent's local expansion
+//   kind 2: M2M from child dx (cell 4 T + dx of the next finer level)
+// Operands of one gather-GEMM entry {dx, dy, slot, kind} for this lane: b = the 16
+// table values of column `row`, half kh; a = 16 values of the source row.
 template <typename TPar>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(const int *__restrict__ targets, int4 class_start,
-                                                        int4 class_len, int4 class_wave0, int nwaves, int p,
-                                                        int level, const float *__restrict__ mp_l,
-                                                        float *__restrict__ lo_l, const float *__restrict__ tab,
-                                                        const c2<TPar> *__restrict__ loc_par)
+__device__ __forceinline__ void gemm_load_entry(int4 en, int kh, int row, int tx, int ty, int tcell, bool tvalid,
+                                                int nside, int k0, int two_p, int p,
+                                                const float *__restrict__ src_same,
+                                                const float *__restrict__ src_child,
+                                                const c2<TPar> *__restrict__ loc_par, const float *__restrict__ tab,
+                                                const double *__restrict__ zero, float (&a)[16], float (&b)[16])
 {
-    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= nwaves) return;
+    const float4 *bsrc = (const float4 *)(tab + ((size_t)(en.z * 2 + kh) * 32 + row) * 16);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float4 t4 = bsrc[v];
+        b[4 * v] = t4.x;
+        b[4 * v + 1] = t4.y;
+        b[4 * v + 2] = t4.z;
+        b[4 * v + 3] = t4.w;
+    }
+    if (en.w == 1) {
+        load_half_row(a, (tvalid && loc_par) ? (const TPar *)(loc_par + (size_t)(tcell >> 2) * p) : (const TPar *)zero,
+                      k0, two_p);
+    } else {
+        const float *src = (const float *)zero;
+        if (en.w == 0) {
+            const int sx = tx + en.x, sy = ty + en.y;
+            if (tvalid && sx >= 0 && sy >= 0 && sx < nside && sy < nside)
+                src = src_same + (size_t)morton_encode((uint32_t)sx, (uint32_t)sy) * two_p;
+        } else if (tvalid) {
+            src = src_child + (size_t)(4 * tcell + en.x) * two_p;
+        }
+        load_half_row(a, src, k0, two_p);
+    }
+}
+
+template <typename TPar, typename TOut>
+__global__ __launch_bounds__(256, 4) void gather_gemm_kernel(
+    const int *__restrict__ targets, int4 class_start, int4 class_len, int4 class_wave0, int4 class_entry,
+    int4 class_nentry, int nwaves, int p, int level, const int4 *__restrict__ entries, const float *__restrict__ src_same,
+    const float *__restrict__ src_child, const c2<TPar> *__restrict__ loc_par, TOut *__restrict__ out,
+    const float *__restrict__ tab, const double *__restrict__ zero)
+{
     const int lane = threadIdx.x & 63;
+    const int wave_step = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); wave < nwaves; wave += wave_step) {
     const int q = wave >= class_wave0.w ? 3 : wave >= class_wave0.z ? 2 : wave >= class_wave0.y ? 1 : 0;
     const int cstart = q == 0 ? class_start.x : q == 1 ? class_start.y : q == 2 ? class_start.z : class_start.w;
     const int clen = q == 0 ? class_len.x : q == 1 ? class_len.y : q == 2 ? class_len.z : class_len.w;
     const int cw0 = q == 0 ? class_wave0.x : q == 1 ? class_wave0.y : q == 2 ? class_wave0.z : class_wave0.w;
-    const int base = (wave - cw0) * (32 * kMfmaTiles);
+    const int e0 = q == 0 ? class_entry.x : q == 1 ? class_entry.y : q == 2 ? class_entry.z : class_entry.w;
+    const int ne = q == 0 ? class_nentry.x : q == 1 ? class_nentry.y : q == 2 ? class_nentry.z : class_nentry.w;
+    const int base = (wave - cw0) * 32;
     const int row = lane & 31, kh = lane >> 5;
     const int two_p = 2 * p;
     const int nside = 1 << level;
-    const int qx = q & 1, qy = q >> 1;
+    const int k0 = 16 * kh;
 
-    int tcell[kMfmaTiles], tx[kMfmaTiles], ty[kMfmaTiles];
-    bool tvalid[kMfmaTiles];
-#pragma unroll
-    for (int w = 0; w < kMfmaTiles; ++w) {
-        const int li = base + 32 * w + row;
-        tvalid[w] = li < clen;
-        tcell[w] = tvalid[w] ? targets[cstart + li] : 0;
-        tx[w] = (int)morton_x((uint32_t)tcell[w]);
-        ty[w] = (int)morton_y((uint32_t)tcell[w]);
-    }
-    floatx16 acc[kMfmaTiles];
-#pragma unroll
-    for (int w = 0; w < kMfmaTiles; ++w)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[w][r] = 0.0f;
+    const int li = base + row;
+    const bool tvalid = li < clen;
+    const int tcell = tvalid ? targets[cstart + li] : 0;
+    const int tx = (int)morton_x((uint32_t)tcell), ty = (int)morton_y((uint32_t)tcell);
 
-    const int k0 = 16 * kh;  // first k of this lane's half row
-    for (int dy = -2 - qy; dy <= 3 - qy; ++dy) {
-        for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-            // delta = (c_T - c_S)/w = (-dx, -dy)
-            const int slot = (3 - dx) * 7 + (3 - dy);
-            const float4 *bsrc = (const float4 *)(tab + ((size_t)(slot * 2 + kh) * 32 + row) * 16);
-            float b[16];
+    floatx16 acc;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float4 t4 = bsrc[v];
-                b[4 * v] = t4.x;
-                b[4 * v + 1] = t4.y;
-                b[4 * v + 2] = t4.z;
-                b[4 * v + 3] = t4.w;
-            }
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int e = 0; e < ne; ++e) {
+        float a[16], b[16];
+        gemm_load_entry<TPar>(entries[e0 + e], kh, row, tx, ty, tcell, tvalid, nside, k0, two_p, p, src_same,
+                              src_child, loc_par, tab, zero, a, b);
 #pragma unroll
-            for (int w = 0; w < kMfmaTiles; ++w) {
-                const int sx = tx[w] + dx, sy = ty[w] + dy;
-                const bool ok = tvalid[w] && sx >= 0 && sy >= 0 && sx < nside && sy < nside;
-                float a[16];
-                load_half_row(a, ok ? mp_l + (size_t)morton_encode((uint32_t)sx, (uint32_t)sy) * two_p : nullptr,
-                              k0, two_p);
-#pragma unroll
-                for (int s = 0; s < 16; ++s) acc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc[w], 0, 0, 0);
-            }
-        }
+        for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc, 0, 0, 0);
     }
-    if (loc_par) {
-        const int slot = 49 + q;
-        const float4 *bsrc = (const float4 *)(tab + ((size_t)(slot * 2 + kh) * 32 + row) * 16);
-        float b[16];
+    // Store: lane holds column `row` of rows 8(r/4) + 4 kh + r%4; the cell of output row
+    // o is the target of lane o.
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int orow = 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int cell = __shfl(tcell, orow);
+        if (row < two_p && base + orow < clen) out[(size_t)cell * two_p + row] = (TOut)acc[r];
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// The same gather-GEMM in FP64 on v_mfma_f64_16x16x4f64 (tiles of 16 targets, two
+// 16-column output blocks).  Operand layouts of the 16x16x4 instruction:
+//   A: lane l holds A[row l%16][k l/16]     B: lane l holds B[k l/16][col l%16]
+//   D: lane l, register r holds D[l/16 + 4r][l%16]
+// K is permuted so that step s uses k = 8(l/16) + s; the table stores B as
+// [slot][l/16][column][s].
+// ---------------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// a[s] = row[k0 + s] for k0 + s < two_p, else 0 (rows padded as for load_half_row).
+__device__ __forceinline__ void load_row8(double (&a)[8], const double *row, int k0, int two_p)
+{
+    const double *r = row + k0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const double v = r[s];
+        a[s] = (k0 + s < two_p) ? v : 0.0;
+    }
+}
+
+// One wavefront: the 16 targets tlist[base .. base + 15] (clen entries valid).
+__device__ __forceinline__ void gemm_tile_f64(const int *__restrict__ tlist, int clen, int base,
+                                              const int4 *__restrict__ ents, int ne, int p, int level,
+                                              const double *__restrict__ src_same,
+                                              const double *__restrict__ src_child,
+                                              const double *__restrict__ loc_par, double *__restrict__ out,
+                                              const double *__restrict__ tab, const double *__restrict__ zero)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const int two_p = 2 * p;
+    const int k0 = 8 * kq;
+    const int nside = 1 << level;
+    const int li = base + row;
+    const bool tvalid = li < clen;
+    const int tcell = tvalid ? tlist[li] : 0;
+    const int tx = (int)morton_x((uint32_t)tcell), ty = (int)morton_y((uint32_t)tcell);
+    doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < ne; ++e) {
+        const int4 en = ents[e];
+        const double *b0p = tab + (((size_t)en.z * 4 + kq) * 32 + row) * 8;
+        const double *b1p = b0p + 16 * 8;
+        double a[8], b0[8], b1[8];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float4 t4 = bsrc[v];
-            b[4 * v] = t4.x;
-            b[4 * v + 1] = t4.y;
-            b[4 * v + 2] = t4.z;
-            b[4 * v + 3] = t4.w;
+            const double2 u0 = ((const double2 *)b0p)[v], u1 = ((const double2 *)b1p)[v];
+            b0[2 * v] = u0.x;
+            b0[2 * v + 1] = u0.y;
+            b1[2 * v] = u1.x;
+            b1[2 * v + 1] = u1.y;
         }
+        const double *src = zero;
+        if (en.w == 0) {
+            const int sx = tx + en.x, sy = ty + en.y;
+            if (tvalid && sx >= 0 && sy >= 0 && sx < nside && sy < nside)
+                src = src_same + (size_t)morton_encode((uint32_t)sx, (uint32_t)sy) * two_p;
+        } else if (en.w == 1) {
+            if (tvalid && loc_par) src = loc_par + (size_t)(tcell >> 2) * two_p;
+        } else {
+            if (tvalid) src = src_child + (size_t)(4 * tcell + en.x) * two_p;
+        }
+        load_row8(a, src, k0, two_p);
 #pragma unroll
-        for (int w = 0; w < kMfmaTiles; ++w) {
-            float a[16];
-            load_half_row(a, tvalid[w] ? (const TPar *)(loc_par + (size_t)(tcell[w] >> 2) * p) : nullptr, k0, two_p);
-#pragma unroll
-            for (int s = 0; s < 16; ++s) acc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc[w], 0, 0, 0);
+        for (int st = 0; st < 8; ++st) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b0[st], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b1[st], acc1, 0, 0, 0);
         }
     }
-    // Store: lane holds column `row` of rows 8(r/4) + 4 kh + r%4.
-    if (row < two_p) {
 #pragma unroll
-        for (int w = 0; w < kMfmaTiles; ++w) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int orow = 8 * (r >> 2) + 4 * kh + (r & 3);
-                const int li = base + 32 * w + orow;
-                if (li < clen) lo_l[(size_t)targets[cstart + li] * two_p + row] = acc[w][r];
-            }
+    for (int r = 0; r < 4; ++r) {
+        const int lo = base + kq + 4 * r;
+        if (lo < clen) {
+            double *o = out + (size_t)tlist[lo] * two_p;
+            if (row < two_p) o[row] = acc0[r];
+            if (16 + row < two_p) o[16 + row] = acc1[r];
         }
+    }
+}
+
+// Out-of-line copy for the coarse kernel, which calls it from two loops.
+__device__ __noinline__ void gemm_tile_f64_call(const int *__restrict__ tlist, int clen, int base,
+                                                const int4 *__restrict__ ents, int ne, int p, int level,
+                                                const double *__restrict__ src_same,
+                                                const double *__restrict__ src_child,
+                                                const double *__restrict__ loc_par, double *__restrict__ out,
+                                                const double *__restrict__ tab, const double *__restrict__ zero)
+{
+    gemm_tile_f64(tlist, clen, base, ents, ne, p, level, src_same, src_child, loc_par, out, tab, zero);
+}
+
+struct LevelClasses {
+    int start[4], len[4], wave0[4];
+    int waves;
+};
+
+// Wide FP64 launch over one level: wavefront w takes tile w of its class.
+__global__ __launch_bounds__(256, 4) void gather_gemm_f64_kernel(const int *__restrict__ targets, LevelClasses lc,
+                                                              int4 class_entry, int ne_l2l, int ne_m2m, int mode,
+                                                              int p, int level, const int4 *__restrict__ entries,
+                                                              const double *__restrict__ src_same,
+                                                              const double *__restrict__ src_child,
+                                                              const double *__restrict__ loc_par,
+                                                              double *__restrict__ out, const double *__restrict__ tab,
+                                                              const double *__restrict__ zero)
+{
+    const int wave_step = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); wave < lc.waves; wave += wave_step) {
+        int q = 0;
+        for (int c = 1; c < 4; ++c)
+            if (wave >= lc.wave0[c]) q = c;
+        const int e0 = q == 0 ? class_entry.x : q == 1 ? class_entry.y : q == 2 ? class_entry.z : class_entry.w;
+        const int ne = mode == 2 ? ne_m2m : ne_l2l;
+        gemm_tile_f64(targets + lc.start[q], lc.len[q], (wave - lc.wave0[q]) * 16, entries + e0, ne, p, level,
+                      src_same, src_child, loc_par, out, tab, zero);
     }
 }
 
@@ -513,11 +657,66 @@ __global__ __launch_bounds__(256) void m2l_kernel(const int *__restrict__ target
 
 // ---------------------------------------------------------------------------------
 // Coarse levels (<= L_c) in one workgroup: M2M into levels L_c-1..2, then M2L + L2L
-// for levels 2..L_c, in FP64.  These levels hold too few cells to fill the chip; the
-// paper assigns them to a single thread group and covers their latency with the
-// near-field work (section "Concurrency").
+// for levels 2..L_c, in FP64 on MFMA (4 wavefronts, one 16-target tile each per
+// pass).  These levels hold too few cells to fill the chip; the paper assigns them to
+// a single thread group and covers their latency with the near-field work (section
+// "Concurrency").
 // ---------------------------------------------------------------------------------
 struct CoarseArgs {
+    int p, lc;
+    const int *lists;
+    int64_t list_off[kMaxDepth + 1];
+    int64_t list_len[kMaxDepth + 1];
+    int64_t class_off[4 * (kMaxDepth + 1)];
+    double2 *mp, *lo;   // FP64 storage from level 0
+    const int4 *entries;
+    const double *tab;
+    const double *zero;
+};
+
+__global__ __launch_bounds__(256, 4) void coarse_kernel(CoarseArgs a)
+{
+    const int p = a.p;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int l = a.lc - 1; l >= 2; --l) {
+        const int n = (int)a.list_len[l];
+        const int *lst = a.lists + a.list_off[l];
+        for (int tile = wave; tile * 16 < n; tile += nw)
+            gemm_tile_f64_call(lst, n, tile * 16, a.entries + 112, 4, p, l, nullptr,
+                          (const double *)(a.mp + level_base(l + 1) * p), nullptr,
+                          (double *)(a.mp + level_base(l) * p), a.tab, a.zero);
+        __syncthreads();
+    }
+    for (int l = 2; l <= a.lc; ++l) {
+        const int n = (int)a.list_len[l];
+        const int *lst = a.lists + a.list_off[l];
+        const int64_t *co = &a.class_off[4 * l];
+        // tiles of the four parity classes, numbered consecutively
+        int ntile[4], tot = 0;
+        for (int q = 0; q < 4; ++q) {
+            const int len = (int)((q < 3 ? co[q + 1] : n) - co[q]);
+            ntile[q] = (len + 15) / 16;
+            tot += ntile[q];
+        }
+        for (int tile = wave; tile < tot; tile += nw) {
+            int q = 0, tq = tile;
+            while (tq >= ntile[q]) {
+                tq -= ntile[q];
+                ++q;
+            }
+            const int len = (int)((q < 3 ? co[q + 1] : n) - co[q]);
+            gemm_tile_f64_call(lst + co[q], len, tq * 16, a.entries + 28 * q, l >= 3 ? 28 : 27, p, l,
+                          (const double *)(a.mp + level_base(l) * p), nullptr,
+                          l >= 3 ? (const double *)(a.lo + level_base(l - 1) * p) : nullptr,
+                          (double *)(a.lo + level_base(l) * p), a.tab, a.zero);
+        }
+        __syncthreads();
+    }
+}
+
+// VALU form of the coarse-level kernel for p > 16 (no MFMA tables).
+struct CoarseValuArgs {
     int p, lc;
     const int *counts;  // global cell index
     const int *lists;
@@ -527,7 +726,7 @@ struct CoarseArgs {
     const double2 *m2m_tab, *m2l_tab, *l2l_tab;
 };
 
-__global__ __launch_bounds__(1024) void coarse_kernel(CoarseArgs a)
+__global__ __launch_bounds__(1024) void coarse_valu_kernel(CoarseValuArgs a)
 {
     const int p = a.p;
     for (int l = a.lc - 1; l >= 2; --l) {
@@ -603,6 +802,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
 
 inline unsigned blocks_for(int64_t work, int per_block) { return (unsigned)((work + per_block - 1) / per_block); }
 
+// Grid of a far-field kernel whose work-items loop with a grid stride: at most
+// `max_waves` wavefronts when the far field runs beside the near field (its waves then
+// stay resident instead of waiting for near-field wavefronts to retire one by one),
+// else one wavefront per work item.
+inline unsigned capped_blocks(int64_t waves, int waves_per_block, int max_waves)
+{
+    int64_t w = waves;
+    if (max_waves > 0 && w > max_waves) w = max_waves;
+    return blocks_for(w, waves_per_block);
+}
+
 template <typename T> c2<T> *level_ptr(const FarArgs &a, int l, bool local);
 template <> double2 *level_ptr<double>(const FarArgs &a, int l, bool local)
 {
@@ -624,12 +834,13 @@ void p2m_launch(const FarArgs &a, hipStream_t s)
     if (nl == 0) return;
     const double w = t->side / (double)(1 << L);
     c2<TC> *out = level_ptr<TC>(a, L, false);
+    const unsigned g = capped_blocks(nl, 1, a.max_waves);
     if (a.p <= 16)
-        p2m_kernel<TR, TC, 16><<<(unsigned)nl, 64, 0, s>>>(level_list(t, L), t->d_leaf_start, t->d_xy,
-                                                            (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+        p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
+                                                (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
     else
-        p2m_kernel<TR, TC, 32><<<(unsigned)nl, 64, 0, s>>>(level_list(t, L), t->d_leaf_start, t->d_xy,
-                                                            (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+        p2m_kernel<TR, TC, 32><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
+                                                (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
 }
 
 template <typename TC, typename TP>
@@ -643,27 +854,93 @@ void m2m_launch(const FarArgs &a, int l, const c2<TP> *tab, hipStream_t s)
         level_ptr<TP>(a, l, false), tab);
 }
 
+// Split a level list into up to four classes of 32-target tiles (one wavefront each).
+struct ClassTiles {
+    int start[4], len[4], wave0[4], waves;
+};
+
+ClassTiles class_tiles(const int64_t *class_off, int64_t n, int nclass)
+{
+    ClassTiles c{};
+    for (int q = 0; q < 4; ++q) {
+        if (q < nclass) {
+            c.start[q] = (int)class_off[q];
+            c.len[q] = (int)((q + 1 < nclass ? class_off[q + 1] : n) - class_off[q]);
+        } else {
+            c.start[q] = (int)n;
+            c.len[q] = 0;
+        }
+        c.wave0[q] = c.waves;
+        c.waves += (c.len[q] + 31) / 32;
+    }
+    return c;
+}
+
+inline int4 i4(const int (&v)[4]) { return make_int4(v[0], v[1], v[2], v[3]); }
+
+// Stages 6 + 7 at level l on MFMA: local expansions of the non-empty cells.
 template <typename TPar>
 void m2l_mfma_launch(const FarArgs &a, int l, hipStream_t s)
 {
     const fmm_tree *t = a.t;
     const int64_t n = t->list_len[l];
     if (n == 0) return;
-    const int *lst = level_list(t, l);
-    const int64_t *cs = &t->class_off[4 * l];
-    int cstart[4], clen[4], cw0[4];
-    int waves = 0;
-    for (int q = 0; q < 4; ++q) {
-        cstart[q] = (int)cs[q];
-        clen[q] = (int)((q < 3 ? cs[q + 1] : n) - cs[q]);
-        cw0[q] = waves;
-        waves += (clen[q] + 32 * kMfmaTiles - 1) / (32 * kMfmaTiles);
-    }
+    const ClassTiles c = class_tiles(&t->class_off[4 * l], n, 4);
     const c2<TPar> *par = l >= 3 ? level_ptr<TPar>(a, l - 1, true) : nullptr;
-    m2l_mfma_kernel<TPar><<<blocks_for((int64_t)waves * 64, 256), 256, 0, s>>>(
-        lst, make_int4(cstart[0], cstart[1], cstart[2], cstart[3]), make_int4(clen[0], clen[1], clen[2], clen[3]),
-        make_int4(cw0[0], cw0[1], cw0[2], cw0[3]), waves, a.p, l, (const float *)level_ptr<float>(a, l, false),
-        (float *)level_ptr<float>(a, l, true), t->tabs.mfma_f, par);
+    const int ne = par ? 28 : 27;  // the L2L entry is last in each class
+    gather_gemm_kernel<TPar, float><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+        level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(0, 28, 56, 84), make_int4(ne, ne, ne, ne),
+        c.waves, a.p, l, t->tabs.mfma_entries, (const float *)level_ptr<float>(a, l, false), nullptr, par,
+        (float *)level_ptr<float>(a, l, true), t->tabs.mfma_f, t->tabs.zero_row);
+}
+
+// Stage 5 into level l on MFMA from the FP32 child level l + 1.
+template <typename TP>
+void m2m_mfma_launch(const FarArgs &a, int l, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int64_t n = t->list_len[l];
+    if (n == 0) return;
+    const int64_t one_class[1] = {0};
+    const ClassTiles c = class_tiles(one_class, n, 1);
+    gather_gemm_kernel<float, TP><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+        level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(112, 112, 112, 112), make_int4(4, 0, 0, 0),
+        c.waves, a.p, l, t->tabs.mfma_entries, nullptr, (const float *)level_ptr<float>(a, l + 1, false), nullptr,
+        (TP *)level_ptr<TP>(a, l, false), t->tabs.mfma_f, t->tabs.zero_row);
+}
+
+LevelClasses level_classes(const int64_t *class_off, int64_t n, int nclass)
+{
+    LevelClasses c{};
+    for (int q = 0; q < 4; ++q) {
+        if (q < nclass) {
+            c.start[q] = (int)class_off[q];
+            c.len[q] = (int)((q + 1 < nclass ? class_off[q + 1] : n) - class_off[q]);
+        } else {
+            c.start[q] = (int)n;
+            c.len[q] = 0;
+        }
+        c.wave0[q] = c.waves;
+        c.waves += (c.len[q] + 15) / 16;
+    }
+    return c;
+}
+
+// FP64 stages 6 + 7 (mode 0) or stage 5 (mode 2) at level l on MFMA.
+void gemm_f64_launch(const FarArgs &a, int l, int mode, hipStream_t s)
+{
+    const fmm_tree *t = a.t;
+    const int64_t n = t->list_len[l];
+    if (n == 0) return;
+    const int64_t one_class[1] = {0};
+    const LevelClasses c = mode == 2 ? level_classes(one_class, n, 1) : level_classes(&t->class_off[4 * l], n, 4);
+    const int p = a.p;
+    gather_gemm_f64_kernel<<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+        level_list(t, l), c, mode == 2 ? make_int4(112, 112, 112, 112) : make_int4(0, 28, 56, 84), l >= 3 ? 28 : 27, 4,
+        mode, p, l, t->tabs.mfma_entries, mode == 0 ? (const double *)(a.mp_d + level_base(l) * p) : nullptr,
+        mode == 2 ? (const double *)(a.mp_d + level_base(l + 1) * p) : nullptr,
+        (mode == 0 && l >= 3) ? (const double *)(a.lo_d + level_base(l - 1) * p) : nullptr,
+        (double *)((mode == 0 ? a.lo_d : a.mp_d) + level_base(l) * p), t->tabs.mfma_d, t->tabs.zero_row);
 }
 
 template <typename T, typename TPar>
@@ -723,25 +1000,94 @@ template <typename T> __device__ __forceinline__ T series_cut();
 template <> __device__ __forceinline__ float series_cut<float>() { return 0.125f; }
 template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3; }
 
-template <typename T>
-__global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units,
-                                                           const rec_t<T> *__restrict__ rec,
-                                                           const c2<T> *__restrict__ qv,
-                                                           const int *__restrict__ leaf_start, int nside, T step,
-                                                           T lambda, double4 *__restrict__ out_pa,
-                                                           double *__restrict__ out_b)
+template <typename T, bool FAR>
+__device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda, T &fpr, T &fpi,
+                                             T &far_r, T &far_i, T &fb)
 {
-    const int4 u = units[blockIdx.x];
+    const T ddx = tx - rj.x;
+    const T ddy = ty - rj.y;
+    const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+    const T r = recip(s);
+    T gr, h;
+    if (FAR) {
+        // e rounds to 0 against 1 (g = 1): g/s' = 1/s', (lambda e s' - g)/s'^2 = -1/s'^2
+        gr = r;
+        h = -r * r;
+    } else {
+        T e, g;
+        exp_pair(s, e, g);
+        gr = g * r;
+        h = fma(lambda * e, s, -g) * r * r;
+        // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
+        // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
+        //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
+        //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
+        const T x = lambda * s;
+        if (x < series_cut<T>()) {
+            gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
+            h = lambda * lambda *
+                fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
+        }
+        fb = fma(rj.z, e, fb);  // B: Gamma_j e
+    }
+    // Phi: q_j (g/s') conj(dz')
+    const T cx = gr * ddx, cy = -gr * ddy;
+    fpr = fma(qj.x, cx, fpr);
+    fpr = fma(-qj.y, cy, fpr);
+    fpi = fma(qj.x, cy, fpi);
+    fpi = fma(qj.y, cx, fpi);
+    // A: Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2
+    const T hg = h * rj.z;
+    const T zr = fma(ddx, ddx, -ddy * ddy);
+    const T zi = (T)-2 * ddx * ddy;
+    far_r = fma(hg, zr, far_r);
+    far_i = fma(hg, zi, far_i);
+}
+
+template <typename T, int K, bool FAR>
+__device__ __forceinline__ void p2p_bwd_tile(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
+                                             T lambda, T (&acc)[5])
+{
+    if (len == 64) {
+#pragma unroll 4
+        for (int it = 0; it < 64 / K; ++it)
+            p2p_bwd_pair<T, FAR>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc[0], acc[1], acc[2], acc[3],
+                                 acc[4]);
+    } else {
+        for (int j = k; j < len; j += K)
+            p2p_bwd_pair<T, FAR>(tile[j], qtile[j], tx, ty, lambda, acc[0], acc[1], acc[2], acc[3], acc[4]);
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
+                                                 T lambda, T (&acc)[5], bool far)
+{
+    if (far) p2p_bwd_tile<T, K, true>(tile, qtile, len, k, tx, ty, lambda, acc);
+    else p2p_bwd_tile<T, K, false>(tile, qtile, len, k, tx, ty, lambda, acc);
+}
+
+// Adjoint near field of one work unit, organised as the forward P2P (LDS tiles,
+// exponential skipped on far tiles).
+template <typename T>
+__device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, c2<T> *qtile,
+                                                  const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qv,
+                                                  const int *__restrict__ leaf_start,
+                                                  const int *__restrict__ tile_start,
+                                                  const float4 *__restrict__ tile_box, int nside, T step,
+                                                  float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
+                                                  double *__restrict__ out_b)
+{
     const int lane = threadIdx.x;
     const int logtp = u.w;
     const int tp = 1 << logtp;
-    const int kstride = 64 >> logtp;
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
     const rec_t<T> ri = rec[i];
     const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
-    double pr = 0, pi = 0, ar = 0, ai = 0, bb = 0;
+    const float4 tbox = tile_box[tile_start[u.x] + ((u.y - leaf_start[u.x]) >> 6)];
+    double sum[5] = {0, 0, 0, 0, 0};
     for (int dy = -1; dy <= 1; ++dy) {
         const int ny = iy + dy;
         if (ny < 0 || ny >= nside) continue;
@@ -752,59 +1098,67 @@ __global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict
             const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
             const T tx = ri.x - (T)dx * step;
             const T ty = ri.y - (T)dy * step;
-            T fpr = 0, fpi = 0, far_ = 0, fai = 0, fb = 0;
-#pragma unroll 2
-            for (int j = s0 + k; j < s1; j += kstride) {
-                const rec_t<T> rj = rec[j];
-                const c2<T> qj = qv[j];
-                const T ddx = tx - rj.x;
-                const T ddy = ty - rj.y;
-                const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
-                T e, g;
-                exp_pair(s, e, g);
-                const T r = recip(s);
-                // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
-                // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
-                //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
-                //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
-                const T x = lambda * s;
-                const bool small = x < series_cut<T>();
-                const T gser = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
-                const T hser = lambda * lambda *
-                               fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
-                const T gr = small ? gser : g * r;
-                // Phi: q_j * (g/s') * conj(dz')
-                const T cx = gr * ddx, cy = -gr * ddy;
-                fpr = fma(qj.x, cx, fpr);
-                fpr = fma(-qj.y, cy, fpr);
-                fpi = fma(qj.x, cy, fpi);
-                fpi = fma(qj.y, cx, fpi);
-                // A: Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2
-                const T h = (small ? hser : fma(lambda * e, s, -g) * r * r) * rj.z;
-                const T zr = fma(ddx, ddx, -ddy * ddy);
-                const T zi = (T)-2 * ddx * ddy;
-                far_ = fma(h, zr, far_);
-                fai = fma(h, zi, fai);
-                // B: Gamma_j e
-                fb = fma(rj.z, e, fb);
+            T acc[5] = {0, 0, 0, 0, 0};
+            int tt = tile_start[S];
+            for (int base = s0; base < s1; base += 64, ++tt) {
+                const int len = min(64, s1 - base);
+                __syncthreads();
+                if (lane < len) {
+                    tile[lane] = rec[base + lane];
+                    qtile[lane] = qv[base + lane];
+                }
+                const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
+                __syncthreads();
+                switch (logtp) {
+                case 6: p2p_bwd_tile_any<T, 1>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 5: p2p_bwd_tile_any<T, 2>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 4: p2p_bwd_tile_any<T, 4>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 3: p2p_bwd_tile_any<T, 8>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 2: p2p_bwd_tile_any<T, 16>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 1: p2p_bwd_tile_any<T, 32>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                default: p2p_bwd_tile_any<T, 64>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                }
             }
-            pr += (double)fpr;
-            pi += (double)fpi;
-            ar += (double)far_;
-            ai += (double)fai;
-            bb += (double)fb;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sum[c] += (double)acc[c];
         }
     }
-    for (int o = tp; o < 64; o <<= 1) {
-        pr += __shfl_xor(pr, o);
-        pi += __shfl_xor(pi, o);
-        ar += __shfl_xor(ar, o);
-        ai += __shfl_xor(ai, o);
-        bb += __shfl_xor(bb, o);
-    }
+    for (int o = tp; o < 64; o <<= 1)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sum[c] += __shfl_xor(sum[c], o);
     if (k == 0 && t < u.z) {
-        out_pa[i] = make_double4(pr, pi, ar, ai);
-        out_b[i] = bb;
+        out_pa[i] = make_double4(sum[0], sum[1], sum[2], sum[3]);
+        out_b[i] = sum[4];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
+                                                           int *__restrict__ work_ctr,
+                                                           const rec_t<T> *__restrict__ rec,
+                                                           const c2<T> *__restrict__ qv,
+                                                           const int *__restrict__ leaf_start,
+                                                           const int *__restrict__ tile_start,
+                                                           const float4 *__restrict__ tile_box, int nside, T step,
+                                                           float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
+                                                           double *__restrict__ out_b)
+{
+    __shared__ rec_t<T> tile[64];
+    __shared__ c2<T> qtile[64];
+    if (!persistent) {
+        p2p_backward_unit<T>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
+                             cut_leaf2, lambda, out_pa, out_b);
+        return;
+    }
+    for (;;) {
+        int v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(work_ctr, kNearBatch);
+        const int first = __builtin_amdgcn_readfirstlane(v);
+        if (first >= nunits) break;
+        const int last = min(first + kNearBatch, nunits);
+        for (int cur = first; cur < last; ++cur)
+            p2p_backward_unit<T>(units[cur], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
+                                 cut_leaf2, lambda, out_pa, out_b);
     }
 }
 
@@ -821,7 +1175,7 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
     if (i >= n) return;
     const double4 a = near_pa[i];
     const double sb = near_b[i];
-    double phr = alpha * a.x, phi = alpha * a.y;
+    double phi = alpha * a.y;  // only Im(Phi) enters dL/dGamma
     const double ka = alpha * alpha * kInv2Pi;
     // A = -i ka (a.z + i a.w) = ka (a.w, -a.z);  B = -i ka lambda sb
     double Ar = ka * a.w, Ai = -ka * a.z;
@@ -837,7 +1191,6 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
         const c2<TL> *bc = loc_c + (int64_t)leaf * p;
         c2<TL> accq = bq[p - 1];
         for (int l = p - 2; l >= 0; --l) accq = cmac<TL>(bq[l], accq, xi);
-        phr += (double)accq.x / w;
         phi += (double)accq.y / w;
         if (p >= 2) {
             c2<TL> accd = mk<TL>((TL)(p - 1) * bc[p - 1].x, (TL)(p - 1) * bc[p - 1].y);
@@ -885,14 +1238,14 @@ void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_do
     const int n = (int)t->n;
     if (is_double)
         pack_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
-                                                                t->y0, w, alpha, (double4 *)rec);
+                                                                t->y0, w, alpha, (double4 *)rec, t->d_work);
     else
         pack_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
-                                                               t->y0, w, alpha, (float4 *)rec);
+                                                               t->y0, w, alpha, (float4 *)rec, t->d_work);
 }
 
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        hipStream_t s)
+                        int near_waves, hipStream_t s)
 {
     if (t->nunits == 0) return;
     const int nside = 1 << t->depth;
@@ -904,14 +1257,16 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
     // covers the rounding of the records and of the box test (boxes in leaf units).
     const double cut = is_double ? 39.0 : 27.0;
     const float cut_leaf2 = (float)(cut / (step * step));
+    const int persistent = near_waves > 0 && near_waves < t->nunits;
+    const unsigned grid = (unsigned)(persistent ? near_waves : t->nunits);
     if (is_double)
-        p2p_forward_kernel<double><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const double4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step,
-            cut_leaf2, scale, near);
+        p2p_forward_kernel<double><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+                                                        (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
+                                                        t->d_tile_box, nside, step, cut_leaf2, scale, near);
     else
-        p2p_forward_kernel<float><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const float4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step,
-            cut_leaf2, scale, near);
+        p2p_forward_kernel<float><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+                                                       (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
+                                                       t->d_tile_box, nside, (float)step, cut_leaf2, scale, near);
 }
 
 void launch_far_chain(const FarArgs &a, hipStream_t s)
@@ -932,13 +1287,16 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
     // Stage 5 on the fine levels: parents L-1 .. max(lc, 2).
     for (int l = L - 1; l >= 2 && l >= a.lc; --l) {
         const bool child_d = (l + 1) <= a.split, parent_d = l <= a.split;
-        if (child_d && parent_d) m2m_launch<double, double>(a, l, tb.m2m_d, s);
+        if (child_d && parent_d && a.p <= 16) gemm_f64_launch(a, l, 2, s);
+        else if (child_d && parent_d) m2m_launch<double, double>(a, l, tb.m2m_d, s);
+        else if (a.p <= 16 && parent_d) m2m_mfma_launch<double>(a, l, s);
+        else if (a.p <= 16) m2m_mfma_launch<float>(a, l, s);
         else if (parent_d) m2m_launch<float, double>(a, l, tb.m2m_d, s);
         else m2m_launch<float, float>(a, l, tb.m2m_f, s);
     }
     // Coarse levels 2..lc in one workgroup (stages 5, 6, 7 there).
-    if (a.lc >= 2) {
-        CoarseArgs c{};
+    if (a.lc >= 2 && a.p > 16) {
+        CoarseValuArgs c{};
         c.p = a.p;
         c.lc = a.lc;
         c.counts = t->d_counts;
@@ -952,12 +1310,29 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
         c.m2m_tab = tb.m2m_d;
         c.m2l_tab = tb.m2l_d;
         c.l2l_tab = tb.l2l_d;
-        coarse_kernel<<<1, 1024, 0, s>>>(c);
+        coarse_valu_kernel<<<1, 1024, 0, s>>>(c);
+    } else if (a.lc >= 2) {
+        CoarseArgs c{};
+        c.p = a.p;
+        c.lc = a.lc;
+        c.lists = t->d_lists;
+        for (int l = 0; l <= kMaxDepth; ++l) {
+            c.list_off[l] = l <= L ? t->list_off[l] : 0;
+            c.list_len[l] = l <= L ? t->list_len[l] : 0;
+            for (int q = 0; q < 4; ++q) c.class_off[4 * l + q] = l <= L ? t->class_off[4 * l + q] : 0;
+        }
+        c.mp = a.mp_d;
+        c.lo = a.lo_d;
+        c.entries = tb.mfma_entries;
+        c.tab = tb.mfma_d;
+        c.zero = tb.zero_row;
+        coarse_kernel<<<1, 256, 0, s>>>(c);
     }
     // Stages 6 + 7 on the fine levels.
     for (int l = (a.lc + 1 > 2 ? a.lc + 1 : 2); l <= L; ++l) {
         const bool here_d = l <= a.split, par_d = (l - 1) <= a.split;
-        if (here_d) m2l_launch<double, double>(a, l, tb.m2l_d, tb.l2l_d, s);
+        if (here_d && a.p <= 16) gemm_f64_launch(a, l, 0, s);
+        else if (here_d) m2l_launch<double, double>(a, l, tb.m2l_d, tb.l2l_d, s);
         else if (a.p <= 16 && par_d) m2l_mfma_launch<double>(a, l, s);
         else if (a.p <= 16) m2l_mfma_launch<float>(a, l, s);
         else if (par_d) m2l_launch<float, double>(a, l, tb.m2l_f, tb.l2l_d, s);
@@ -993,19 +1368,26 @@ void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, 
 }
 
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, hipStream_t s)
+                         double4 *out_pa, double *out_b, int near_waves, hipStream_t s)
 {
     if (t->nunits == 0) return;
     const int nside = 1 << t->depth;
     const double w = t->side / (double)nside;
+    const double step = alpha * w;
+    const double cut = is_double ? 39.0 : 27.0;
+    const float cut_leaf2 = (float)(cut / (step * step));
+    const int persistent = near_waves > 0 && near_waves < t->nunits;
+    const unsigned grid = (unsigned)(persistent ? near_waves : t->nunits);
     if (is_double)
-        p2p_backward_kernel<double><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const double4 *)rec, (const double2 *)qv, t->d_leaf_start, nside, alpha * w, 1.0, out_pa,
-            out_b);
+        p2p_backward_kernel<double><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+                                                         (const double4 *)rec, (const double2 *)qv, t->d_leaf_start,
+                                                         t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0,
+                                                         out_pa, out_b);
     else
-        p2p_backward_kernel<float><<<(unsigned)t->nunits, 64, 0, s>>>(
-            t->d_units, (const float4 *)rec, (const float2 *)qv, t->d_leaf_start, nside, (float)(alpha * w),
-            (float)0.69314718055994530942, out_pa, out_b);
+        p2p_backward_kernel<float><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+                                                        (const float4 *)rec, (const float2 *)qv, t->d_leaf_start,
+                                                        t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2,
+                                                        (float)0.69314718055994530942, out_pa, out_b);
 }
 
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,

@@ -62,6 +62,9 @@ void free_tables(Tables &tb)
     hipFree(tb.l2l_f);
     hipFree(tb.m2l_f);
     hipFree(tb.mfma_f);
+    hipFree(tb.mfma_d);
+    hipFree(tb.mfma_entries);
+    hipFree(tb.zero_row);
     tb = Tables{};
 }
 
@@ -99,15 +102,22 @@ int upload_tables(Tables &tb, int p, std::string &err)
     // Real 2p x 2p embedding for the MFMA kernel: y = x R with x, y interleaved (re, im),
     // R[2m][2l] = Re T_lm, R[2m+1][2l] = -Im T_lm, R[2m][2l+1] = Im T_lm, R[2m+1][2l+1] = Re T_lm.
     std::vector<float> mf;
+    std::vector<double> md;
     if (p <= 16) {
-        mf.assign((size_t)53 * 2 * 32 * 16, 0.0f);
+        mf.assign((size_t)57 * 2 * 32 * 16, 0.0f);
+        md.assign((size_t)57 * 4 * 32 * 8, 0.0);
         auto put = [&](int slot, int m, int l, cd v) {
             const int k_re = 2 * m, k_im = 2 * m + 1, n_re = 2 * l, n_im = 2 * l + 1;
             auto at = [&](int k, int n) -> float & { return mf[(((size_t)slot * 2 + k / 16) * 32 + n) * 16 + k % 16]; };
+            auto atd = [&](int k, int n) -> double & { return md[(((size_t)slot * 4 + k / 8) * 32 + n) * 8 + k % 8]; };
             at(k_re, n_re) = (float)v.real();
             at(k_im, n_re) = (float)-v.imag();
             at(k_re, n_im) = (float)v.imag();
             at(k_im, n_im) = (float)v.real();
+            atd(k_re, n_re) = v.real();
+            atd(k_im, n_re) = -v.imag();
+            atd(k_re, n_im) = v.imag();
+            atd(k_im, n_im) = v.real();
         };
         for (int o = 0; o < 49; ++o)
             for (int m = 0; m < p; ++m)
@@ -116,15 +126,52 @@ int upload_tables(Tables &tb, int p, std::string &err)
         for (int q = 0; q < 4; ++q)
             for (int k = 0; k < p; ++k)
                 for (int l = 0; l < p; ++l) put(49 + q, l, k, l2l[((size_t)q * p + k) * p + l]);
+        // M2M: parent coefficient m (output) from child q's coefficient k (input)
+        for (int q = 0; q < 4; ++q)
+            for (int m = 0; m < p; ++m)
+                for (int k = 0; k < p; ++k) put(53 + q, k, m, m2m[((size_t)q * p + m) * p + k]);
     }
+    // Entry lists of the MFMA kernel: per parity class (qx, qy) the 27 interaction-list
+    // source offsets (dx in [-2-qx, 3-qx], dy in [-2-qy, 3-qy] outside the 3x3 block) and
+    // the L2L entry; then the four M2M children.  delta = (c_T - c_S)/w = (-dx, -dy).
+    std::vector<int4> ent;
+    for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        for (int dy = -2 - qy; dy <= 3 - qy; ++dy)
+            for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
+                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+                ent.push_back(make_int4(dx, dy, (3 - dx) * 7 + (3 - dy), 0));
+            }
+        ent.push_back(make_int4(0, 0, 49 + q, 1));
+    }
+    for (int q = 0; q < 4; ++q) ent.push_back(make_int4(q, 0, 53 + q, 2));
     int rc = 0;
     if (!rc && p <= 16) {
-        if (hipMalloc((void **)&tb.mfma_f, mf.size() * sizeof(float)) != hipSuccess) {
+        if (hipMalloc((void **)&tb.mfma_f, mf.size() * sizeof(float)) != hipSuccess ||
+            hipMalloc((void **)&tb.mfma_d, md.size() * sizeof(double)) != hipSuccess) {
             err = "hipMalloc failed for operator tables";
             rc = -2;
-        } else if (hipMemcpy(tb.mfma_f, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        } else if (hipMemcpy(tb.mfma_f, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+                   hipMemcpy(tb.mfma_d, md.data(), md.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
             err = "hipMemcpy failed for operator tables";
             rc = -3;
+        }
+    }
+    if (!rc) {
+        if (hipMalloc((void **)&tb.mfma_entries, ent.size() * sizeof(int4)) != hipSuccess) {
+            err = "hipMalloc failed for operator tables";
+            rc = -2;
+        } else if (hipMemcpy(tb.mfma_entries, ent.data(), ent.size() * sizeof(int4), hipMemcpyHostToDevice) !=
+                   hipSuccess) {
+            err = "hipMemcpy failed for operator tables";
+            rc = -3;
+        }
+    }
+    if (!rc) {
+        if (hipMalloc((void **)&tb.zero_row, 128 * sizeof(double)) != hipSuccess ||
+            hipMemset(tb.zero_row, 0, 128 * sizeof(double)) != hipSuccess) {
+            err = "allocation of the zero row failed";
+            rc = -2;
         }
     }
     if (!rc) rc = upload<double2, double>(&tb.m2m_d, m2m, err);
