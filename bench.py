@@ -28,6 +28,11 @@ sys.path.insert(0, HERE)
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 P2P_FLOPS_PER_PAIR = 22           # section "Complexity Estimates": 9 complex division, 1 exp
+# HBM bytes per launch of p2p_forward_kernel<float> on this workload, from rocprofv3 --pmc
+# FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors of a 256 MiB copy kernel measured the
+# same way (profiles/p2p_forward_gaussian_patches_16M.md).  None when the kernel has changed
+# since the counters were taken.
+P2P_TRAFFIC_BYTES = 6.443e9
 
 
 def log(msg):
@@ -76,6 +81,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--bwd-steps", type=int, default=3)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed headline region (for kernel profiling of exactly that work)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run only a device-to-device copy of MIB MiB ten times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -86,6 +95,15 @@ def main():
     from paper_1008_2410_amd import _lib, fmm, workloads
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 10}), flush=True)
+        return
     t0 = time.perf_counter()
     w = workloads.gaussian_patches(n=args.n, depth=args.depth)
     log(f"[bench] workload generated: N={w.n} depth={w.depth} p={w.p} ({time.perf_counter() - t0:.1f} s)")
@@ -124,6 +142,13 @@ def main():
     # timed region: overlapped schedule
     ms, stages = timed(args.steps)
     log(f"[bench] mixed overlap: {ms:.3f} ms/step, stages {stages}")
+    if args.headline_only:
+        pairs = info["p2p_pairs"]
+        print(json.dumps({"ms_per_step": round(ms, 4), "value": round(w.n / (ms * 1e-3) / 1e6, 3),
+                          "p2p_avg_ms": round(stages["p2p"], 4),
+                          "p2p_tflops": round(P2P_FLOPS_PER_PAIR * pairs / (stages["p2p"] * 1e-3) / 1e12, 3),
+                          "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
     # serial schedule of the same work, for the overlap fraction
     tree.set_option(_lib.FMM_OPT_SCHEDULE, 1)
     run(1)
@@ -217,7 +242,7 @@ def main():
                    "p": w.p, "precision": "mixed", "schedule": "overlap", "root": "bounding square"},
         "roofline": {"bound": "alu", "kernel": "p2p_forward_kernel<float>", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "traffic": None, "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                     "traffic": P2P_TRAFFIC_BYTES, "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs,
                      "avg_launch_ms": round(p2p_ms, 4)},
         "cpu_baseline": cpu,
         "accuracy": {"mixed_vs_oracle_rel_l2": err_mixed, "fp64_vs_oracle_rel_l2": err_fp64,
