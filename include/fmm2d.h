@@ -26,6 +26,8 @@
  *    the last kernel of a call.
  *  - A tree handle may be used by one host thread at a time; a concurrent call on
  *    the same handle returns FMM_ESTATE.  Different handles are independent.
+ *  - Calls on one tree share its device workspace: consecutive calls must be ordered
+ *    on the device (the same main stream, or synchronised in between).
  *  - Inputs are never modified.
  */
 #ifndef FMM2D_H
@@ -60,7 +62,7 @@ enum {
     FMM_OPT_SCHEDULE = 1,     /* 0: far field on a second stream, concurrent with P2P (default);
                                  1: everything serialised on the main stream */
     FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in one
-                                 single-workgroup kernel in FP64 (default 4, range 1..depth) */
+                                 single-workgroup kernel in FP64 (default 3, range 1..depth) */
     FMM_OPT_TIMING = 3,       /* 1: record HIP events around each stage of every call for
                                  fmm_get_timings (default 0) */
     FMM_OPT_NEAR_WAVES = 4,   /* near-field grid: 0 = one workgroup per work unit (default);

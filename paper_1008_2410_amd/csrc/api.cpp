@@ -92,6 +92,9 @@ void free_workspace(Workspace &ws)
 void free_tree(fmm_tree *t)
 {
     hipFree(t->d_perm);
+    hipFree(t->d_gpos1);
+    hipFree(t->d_gpos2);
+    hipFree(t->d_st1);
     hipFree(t->d_leaf_of);
     hipFree(t->d_xy);
     hipFree(t->d_leaf_start);
@@ -395,6 +398,21 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
                     std::stable_sort(perm.begin() + leaf_start[c], perm.begin() + leaf_start[c + 1],
                                      [&](int a, int b) { return sub[a] < sub[b]; });
         }
+        // Staging slots of the two-pass permutation into sorted order: bucket = sorted slot
+        // >> shift, ordered by user index inside a bucket; a bucket's segment of the
+        // staging array is the slot range of the bucket itself.
+        int shift = kStageShiftMin;
+        while ((((n - 1) >> shift) + 1) > 256) ++shift;
+        t->stage_shift = shift;
+        std::vector<int> gpos1((size_t)n), gpos2((size_t)n);
+        {
+            std::vector<int> inv((size_t)n);
+            for (int64_t k = 0; k < n; ++k) inv[perm[k]] = (int)k;
+            std::vector<int64_t> fill(256);
+            for (int64_t b = 0; b < 256; ++b) fill[b] = b << shift;
+            for (int64_t u = 0; u < n; ++u) gpos1[u] = (int)fill[inv[u] >> shift]++;
+            for (int64_t k = 0; k < n; ++k) gpos2[k] = gpos1[perm[k]];
+        }
         std::vector<double2> xys((size_t)n);
         for (int64_t k = 0; k < n; ++k) {
             xys[k].x = h[2 * (size_t)perm[k]];
@@ -512,6 +530,9 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
 
         int rc = FMM_OK;
         if (!rc) rc = upload(&t->d_perm, perm, "permutation");
+        if (!rc) rc = upload(&t->d_gpos1, gpos1, "staging slots");
+        if (!rc) rc = upload(&t->d_gpos2, gpos2, "staging slots");
+        if (!rc) rc = dev_alloc(&t->d_st1, n, "staging array");
         if (!rc) rc = upload(&t->d_leaf_of, leaf_of, "leaf ids");
         if (!rc) rc = upload(&t->d_xy, xys, "sorted positions");
         if (!rc) rc = upload(&t->d_leaf_start, leaf_start, "leaf offsets");

@@ -75,6 +75,11 @@ struct Tables {
 // Coefficient arrays are allocated with this many extra elements at the end, so that
 // fixed-length reads of a row never pass the allocation.
 constexpr int64_t kCoefPad = 64;
+// Permutation staging: buckets of at least 2^kStageShiftMin sorted slots (a 1 MiB gather
+// window of FP64) and at most 256 of them; the number of XCDs that workgroups are dealt
+// to round-robin.
+constexpr int kStageShiftMin = 17;
+constexpr int kXcds = 8;
 
 // Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
 // are FP64, levels split+1..L are FP32; each level holds 4^l cells x p coefficients,
@@ -102,7 +107,7 @@ struct fmm_tree {
     double x0 = 0, y0 = 0, side = 1;
     int device = 0;
     int num_cus = 256;   // compute units of the device
-    int lc = 4;          // coarse-level cutoff L_c
+    int lc = 3;          // coarse-level cutoff L_c
     int near_waves = 0;  // persistent near-field grid in wavefronts (0: one workgroup per unit)
     int far_waves = 0;   // cap of the far-field grids beside the near field (0: none)
     int schedule = 0;    // 0 overlap, 1 serial
@@ -118,6 +123,12 @@ struct fmm_tree {
 
     // device tree arrays
     int *d_perm = nullptr;        // sorted slot -> user index
+    // Two-pass permutation of the circulations into sorted order through a staging array
+    // cut into buckets of 2^stage_shift consecutive sorted slots (at most 256 buckets):
+    int stage_shift = 0;
+    int *d_gpos1 = nullptr;       // user index -> staging slot (inside a bucket: by user index)
+    int *d_gpos2 = nullptr;       // sorted slot -> staging slot of its user index
+    double *d_st1 = nullptr;      // staging array, n FP64
     int *d_leaf_of = nullptr;     // sorted slot -> leaf Morton index
     double2 *d_xy = nullptr;      // sorted positions
     int *d_leaf_start = nullptr;  // CSR over Morton-ordered leaves, 4^L + 1

@@ -11,6 +11,7 @@
 //  - Complex numbers are interleaved (re, im) float2 / double2.
 #include "fmm_internal.h"
 
+#include <climits>
 #include <cmath>
 
 namespace fmm {
@@ -67,13 +68,95 @@ template <> struct Rec<float> { using type = float4; };
 template <> struct Rec<double> { using type = double4; };
 template <typename T> using rec_t = typename Rec<T>::type;
 
+// ---------------------------------------------------------------------------------
+// Circulations from user order into tree order in two passes.  The user order is
+// arbitrary (a random shuffle in the benchmark), so a direct gather makes one random
+// memory access per element.  Instead, with buckets of 2^S consecutive sorted slots:
+//   pass 1 (stage_in_kernel) reads a contiguous chunk of user indices, sorts it in LDS
+//          by bucket and writes each bucket's elements as one run into that bucket's
+//          segment of a staging array (inside a bucket, slots follow user index, so a
+//          chunk's elements of one bucket are one contiguous run);
+//   pass 2 (in pack_kernel) walks the sorted slots and gathers from the current
+//          bucket's segment, a window small enough to stay in one XCD's L2.
+// gpos1[user index] = staging slot; gpos2[sorted slot] = staging slot of its user index.
+// S is chosen with the tree so that there are at most 256 buckets.  Blocks are remapped
+// so that each XCD (workgroups are dealt to XCDs round-robin) walks one contiguous index
+// range, which keeps its live windows few.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_block(int nxcd)
+{
+    const int per = gridDim.x / nxcd;  // grids are launched as a multiple of nxcd
+    return (blockIdx.x % nxcd) * per + blockIdx.x / nxcd;
+}
+
+constexpr int kStageE = 4;  // elements per thread in pass 1 (chunk of 1024)
+
+__global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxcd, const int *__restrict__ gpos1,
+                                                        const double *__restrict__ src, double *__restrict__ st)
+{
+    constexpr int C = 256 * kStageE;
+    __shared__ int cnt[256], lo[256], off[256];
+    __shared__ double val[C];
+    __shared__ int dst[C];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    lo[t] = INT_MAX;
+    __syncthreads();
+    const int64_t k0 = (int64_t)xcd_block(nxcd) * C;
+    int q[kStageE];
+    double v[kStageE];
+#pragma unroll
+    for (int e = 0; e < kStageE; ++e) {
+        const int64_t k = k0 + e * 256 + t;
+        q[e] = -1;
+        v[e] = 0.0;
+        if (k < n) {
+            q[e] = gpos1[k];
+            v[e] = src[k];
+            const int bk = q[e] >> shift;  // < 256 by the choice of shift
+            atomicAdd(&cnt[bk], 1);
+            atomicMin(&lo[bk], q[e]);
+        }
+    }
+    __syncthreads();
+    if (t < 64) {  // exclusive scan of the 256 bucket counts by one wavefront
+        const int c0 = cnt[4 * t], c1 = cnt[4 * t + 1], c2 = cnt[4 * t + 2], c3 = cnt[4 * t + 3];
+        const int sum = c0 + c1 + c2 + c3;
+        int incl = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d);
+            if (t >= d) incl += o;
+        }
+        const int ex = incl - sum;
+        off[4 * t] = ex;
+        off[4 * t + 1] = ex + c0;
+        off[4 * t + 2] = ex + c0 + c1;
+        off[4 * t + 3] = ex + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kStageE; ++e)
+        if (q[e] >= 0) {
+            const int bk = q[e] >> shift;
+            const int slot = off[bk] + (q[e] - lo[bk]);  // < C: the bucket's run is contiguous
+            val[slot] = v[e];
+            dst[slot] = q[e];
+        }
+    __syncthreads();
+    const int m = (int)min((int64_t)C, (int64_t)n - k0);
+    for (int j = t; j < m; j += 256) st[dst[j]] = val[j];
+}
+
+// gamma_st: circulations in the staging array, read at gpos2[i] (pass 2 of the
+// user-to-tree permutation).
 template <typename T>
-__global__ __launch_bounds__(256) void pack_kernel(int n, const int *__restrict__ perm, const int *__restrict__ leaf_of,
-                                                    const double2 *__restrict__ xy, const double *__restrict__ gamma,
+__global__ __launch_bounds__(256) void pack_kernel(int n, int nxcd, const int *__restrict__ gpos2,
+                                                    const int *__restrict__ leaf_of,
+                                                    const double2 *__restrict__ xy, const double *__restrict__ gamma_st,
                                                     double x0, double y0, double w, double alpha,
                                                     rec_t<T> *__restrict__ rec, int *__restrict__ work_ctr)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i == 0 && work_ctr) work_ctr[0] = 0;  // near-field work counter of this call
     if (i >= n) return;
     uint32_t leaf = (uint32_t)leaf_of[i];
@@ -83,7 +166,7 @@ __global__ __launch_bounds__(256) void pack_kernel(int n, const int *__restrict_
     rec_t<T> r;
     r.x = (T)(alpha * (z.x - cx));
     r.y = (T)(alpha * (z.y - cy));
-    r.z = (T)gamma[perm[i]];
+    r.z = (T)gamma_st[gpos2[i]];
     r.w = (T)0;
     rec[i] = r;
 }
@@ -755,7 +838,8 @@ __global__ __launch_bounds__(1024) void coarse_valu_kernel(CoarseValuArgs a)
 // ---------------------------------------------------------------------------------
 // Stages 8 + 10: L2P from the leaf's local expansion (Horner in xi = (z - c)/w_L,
 // W_far = (1/w_L) sum_l b_l xi^l), plus the near field, scattered to user order:
-// (u, v) = (u_near + Re W_far, v_near - Im W_far).
+// (u, v) = (u_near + Re W_far, v_near - Im W_far).  (A two-pass scatter through a
+// staging array, as for the circulations, measured no faster for (u, v) pairs.)
 // ---------------------------------------------------------------------------------
 template <typename TL>
 __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restrict__ perm,
@@ -1232,16 +1316,24 @@ void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStrea
     widen_perm_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, perm, leaf);
 }
 
+// Grids of the permutation kernels: a multiple of the XCD count (see xcd_block).
+inline unsigned xcd_grid(int64_t work, int per_block)
+{
+    return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
+}
+
 void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s)
 {
+    stage_in_kernel<<<xcd_grid(t->n, 256 * kStageE), 256, 0, s>>>((int)t->n, t->stage_shift, kXcds, t->d_gpos1,
+                                                                   gamma, t->d_st1);
     const double w = t->side / (double)(1 << t->depth);
     const int n = (int)t->n;
     if (is_double)
-        pack_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
-                                                                t->y0, w, alpha, (double4 *)rec, t->d_work);
+        pack_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
+                                                              t->x0, t->y0, w, alpha, (double4 *)rec, t->d_work);
     else
-        pack_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, gamma, t->x0,
-                                                               t->y0, w, alpha, (float4 *)rec, t->d_work);
+        pack_kernel<float><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
+                                                             t->x0, t->y0, w, alpha, (float4 *)rec, t->d_work);
 }
 
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,

@@ -160,6 +160,26 @@ def test_deterministic_and_schedule_independent(fmm_mod):
         assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+def test_persistent_near_grid_and_far_cap(fmm_mod):
+    """FMM_OPT_NEAR_WAVES (persistent near-field grid fed by a work counter) and
+    FMM_OPT_FAR_WAVES (capped far-field grids) change only which wavefront does which
+    work: every output bit matches the default launch, forward and adjoint."""
+    w = W.uniform_lamb_oseen(n=70000, seed=21, depth=6, p=12)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    dl = np.random.Generator(np.random.PCG64(2)).standard_normal((w.n, 2))
+    for precision in ("fp64", "mixed"):
+        ref = _run(fmm_mod, w, precision, tree=tree)
+        gref = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl))
+        for near, far in ((64, 0), (1024, 96), (1, 8), (0, 32)):
+            tree.set_option(4, near)
+            tree.set_option(5, far)
+            assert np.array_equal(_run(fmm_mod, w, precision, tree=tree), ref), (precision, near, far)
+            g = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl))
+            assert all(np.array_equal(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(g, gref))
+        tree.set_option(4, 0)
+        tree.set_option(5, 0)
+
+
 @pytest.mark.parametrize("lc", [1, 2, 3, 6])
 def test_coarse_cutoff_variants(fmm_mod, oracle_mod, lc):
     w = W.uniform_lamb_oseen(n=8000, seed=9, depth=6, p=9)
