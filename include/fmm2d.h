@@ -68,8 +68,12 @@ enum {
     FMM_OPT_NEAR_WAVES = 4,   /* near-field grid: 0 = one workgroup per work unit (default);
                                  N > 0 = a persistent grid of N wavefronts taking units from a
                                  counter, leaving the rest of the chip to the far field */
-    FMM_OPT_FAR_WAVES = 5     /* cap on the far-field kernels' grids (wavefronts) while they run
+    FMM_OPT_FAR_WAVES = 5,    /* cap on the far-field kernels' grids (wavefronts) while they run
                                  beside the near field; 0 = none (default) */
+    FMM_OPT_NEAR_MUTUAL = 6,  /* 1 (default): pairs of neighbouring dense leaves are evaluated once
+                                 for both particles (the kernel is odd), the rest from the target
+                                 end; 0: every pair from the target end.  Results agree to rounding. */
+    FMM_OPT_DENSE_LEAF = 7    /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
 };
 
 /* Stage indices of fmm_get_timings. */

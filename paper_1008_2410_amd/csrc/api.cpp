@@ -86,6 +86,7 @@ void free_workspace(Workspace &ws)
     hipFree(ws.mp2_f);
     hipFree(ws.lo2_f);
     hipFree(ws.rec2);
+    hipFree(ws.slots);
     ws = Workspace{};
 }
 
@@ -101,6 +102,9 @@ void free_tree(fmm_tree *t)
     hipFree(t->d_counts);
     hipFree(t->d_lists);
     hipFree(t->d_units);
+    hipFree(t->d_units_tc);
+    hipFree(t->d_mut_items);
+    hipFree(t->d_leaf_mask);
     hipFree(t->d_tile_start);
     hipFree(t->d_tile_box);
     hipFree(t->d_work);
@@ -113,6 +117,100 @@ void free_tree(fmm_tree *t)
         for (auto e : evs) hipEventDestroy(e);
     delete t;
 }
+
+// Near-field plan of the mutual form (stage 9).  A leaf is dense when it holds at least
+// dense_leaf particles.  Every unordered pair of neighbouring dense leaves, and every
+// dense leaf with itself, is one mutual item; every other ordered (target leaf, source
+// leaf) pair is evaluated by the target-centric units, whose flag makes dense target
+// leaves skip their dense neighbours.  leaf_mask[leaf]: bit d (direction d = 3(dy+1) +
+// (dx+1) of a neighbour) when the particles' slot d is written, bit 9 when a
+// target-centric unit writes their near-field sum.  With the mutual form off the plan
+// is empty and the target-centric units cover every pair.
+int build_near_plan(fmm_tree *t)
+{
+    hipFree(t->d_units_tc);
+    hipFree(t->d_mut_items);
+    hipFree(t->d_leaf_mask);
+    t->d_units_tc = nullptr;
+    t->d_mut_items = nullptr;
+    t->d_leaf_mask = nullptr;
+    t->nunits_tc = t->nmut = 0;
+    if (!t->near_mutual) return FMM_OK;
+    const int L = t->depth;
+    const int nside = 1 << L;
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const std::vector<int> &ls = t->h_leaf_start;
+    const int D = t->dense_leaf;
+    auto count = [&](int x, int y) -> int {
+        if (x < 0 || y < 0 || x >= nside || y >= nside) return 0;
+        const uint32_t c = morton_encode((uint32_t)x, (uint32_t)y);
+        return ls[c + 1] - ls[c];
+    };
+    std::vector<int4> units, items;
+    std::vector<int64_t> ucost, icost;
+    std::vector<uint16_t> mask((size_t)nleaf, 0);
+    static const int up[4][2] = {{1, 0}, {-1, 1}, {0, 1}, {1, 1}};
+    for (int64_t c = 0; c < nleaf; ++c) {
+        const int nt = ls[c + 1] - ls[c];
+        if (nt == 0) continue;
+        const int x = (int)morton_x((uint32_t)c), y = (int)morton_y((uint32_t)c);
+        const bool dense = nt >= D;
+        int64_t nsrc = 0;
+        uint16_t m = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ns = count(x + dx, y + dy);
+                if (ns == 0) continue;
+                if (dense && ns >= D) m |= (uint16_t)(1u << (3 * (dy + 1) + (dx + 1)));
+                else nsrc += ns;
+            }
+        if (nsrc > 0) {
+            m |= 1u << 9;
+            for (int c0 = 0; c0 < nt; c0 += 64) {
+                const int cnt = std::min(64, nt - c0);
+                int logtp = 0;
+                while ((1 << logtp) < cnt) ++logtp;
+                const int kstride = 64 >> logtp;
+                units.push_back(make_int4((int)c, ls[c] + c0, cnt, logtp | (dense ? 16 : 0)));
+                ucost.push_back((nsrc + kstride - 1) / kstride);
+            }
+        }
+        mask[c] = m;
+        if (!dense) continue;
+        const int64_t tiles = (nt + 63) / 64;
+        items.push_back(make_int4((int)c, (int)c, 4 | (4 << 4), 0));
+        icost.push_back(tiles * (tiles + 1) / 2 * 64);
+        for (const auto &o : up) {
+            const int nr = count(x + o[0], y + o[1]);
+            if (nr < D) continue;
+            const int ds = 3 * (o[1] + 1) + (o[0] + 1);
+            items.push_back(make_int4((int)c, (int)morton_encode((uint32_t)(x + o[0]), (uint32_t)(y + o[1])),
+                                      ds | ((8 - ds) << 4), 0));
+            icost.push_back(tiles * nr);
+        }
+    }
+    auto by_cost = [](std::vector<int4> &v, const std::vector<int64_t> &cost) {
+        std::vector<int64_t> order(v.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+        std::vector<int4> out(v.size());
+        for (size_t k = 0; k < order.size(); ++k) out[k] = v[order[k]];
+        v.swap(out);
+    };
+    by_cost(units, ucost);
+    by_cost(items, icost);
+    int rc = FMM_OK;
+    if (!units.empty()) rc = upload(&t->d_units_tc, units, "near-field units");
+    if (!rc && !items.empty()) rc = upload(&t->d_mut_items, items, "mutual near-field items");
+    if (!rc) rc = upload(&t->d_leaf_mask, mask, "near-field leaf masks");
+    if (rc) return rc;
+    t->nunits_tc = (int64_t)units.size();
+    t->nmut = (int64_t)items.size();
+    return FMM_OK;
+}
+
+// The mutual form is used when its plan has items; else the target-centric units alone.
+bool use_mutual(const fmm_tree *t) { return t->near_mutual && t->nmut > 0; }
 
 int effective_lc(const fmm_tree *t) { return std::min(t->lc, t->depth); }
 
@@ -249,6 +347,10 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     std::string err;
     if ((rc = upload_tables(t->tabs, p, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
     if ((rc = ensure_workspace(t, p, precision, false))) return rc;
+    if (use_mutual(t) && !t->ws.slots &&
+        (rc = dev_alloc((char **)&t->ws.slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
+                        "mutual near-field slots")))
+        return rc;
 
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
@@ -271,12 +373,13 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     launch_far_chain(a, ss);
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
+    void *slots = use_mutual(t) ? t->ws.slots : nullptr;
     tm.mark(4, ms);
-    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, near_waves(t), ms);
+    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, slots, near_waves(t), ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    launch_finalize(t, a, t->ws.near, uv, uv_near, uv_far, ms);
+    launch_finalize(t, a, t->ws.near, slots, is_double, alpha, uv, uv_near, uv_far, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);
@@ -539,6 +642,8 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         if (!rc) rc = upload(&t->d_counts, counts, "cell counts");
         if (!rc) rc = upload(&t->d_lists, lists, "cell lists");
         if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
+        t->h_leaf_start = leaf_start;
+        if (!rc) rc = build_near_plan(t);
         if (!rc) rc = upload(&t->d_tile_start, tile_start, "tile offsets");
         if (!rc) rc = upload(&t->d_tile_box, tile_box, "tile boxes");
         if (!rc) rc = dev_alloc(&t->d_work, 4, "work counter");
@@ -683,6 +788,18 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         if (value < 0 || value > (int64_t(1) << 30)) return fail(FMM_EINVAL, "far waves must be in [0, 2^30]");
         t->far_waves = (int)value;
         return FMM_OK;
+    case FMM_OPT_NEAR_MUTUAL:
+    case FMM_OPT_DENSE_LEAF: {
+        if (key == FMM_OPT_NEAR_MUTUAL && value != 0 && value != 1)
+            return fail(FMM_EINVAL, "near mutual must be 0 or 1");
+        if (key == FMM_OPT_DENSE_LEAF && (value < 1 || value > (int64_t(1) << 30)))
+            return fail(FMM_EINVAL, "dense leaf must be in [1, 2^30]");
+        HIP_TRY(hipSetDevice(t->device));
+        HIP_TRY(hipDeviceSynchronize());  // the plan's arrays may be in use
+        if (key == FMM_OPT_NEAR_MUTUAL) t->near_mutual = (int)value;
+        else t->dense_leaf = (int)value;
+        return build_near_plan(t);
+    }
     case FMM_OPT_TIMING:
         if (value != 0 && value != 1) return fail(FMM_EINVAL, "timing must be 0 or 1");
         t->timing = (int)value;

@@ -97,6 +97,7 @@ struct Workspace {
     double2 *mp2_d = nullptr, *lo2_d = nullptr;
     float2 *mp2_f = nullptr, *lo2_f = nullptr;
     void *rec2 = nullptr;         // adjoint charges q in FP32 for the mixed near field
+    void *slots = nullptr;        // mutual near field: 9 x n sums (float2 or double2)
 };
 
 }  // namespace fmm
@@ -111,6 +112,8 @@ struct fmm_tree {
     int near_waves = 0;  // persistent near-field grid in wavefronts (0: one workgroup per unit)
     int far_waves = 0;   // cap of the far-field grids beside the near field (0: none)
     int schedule = 0;    // 0 overlap, 1 serial
+    int near_mutual = 1; // pairs of dense leaves evaluated once for both particles
+    int dense_leaf = 32; // a leaf with at least this many particles is dense
     int timing = 0;
     std::atomic<int> busy{0};
 
@@ -135,6 +138,12 @@ struct fmm_tree {
     int *d_counts = nullptr;      // particles per cell, all levels, global cell index
     int *d_lists = nullptr;       // non-empty cells per level (levels 2..L), parity-grouped
     int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
+    std::vector<int> h_leaf_start;  // host copy of d_leaf_start
+    // near-field plan of the mutual form (see build_near_plan)
+    int64_t nunits_tc = 0, nmut = 0;
+    int4 *d_units_tc = nullptr;   // target-centric units; w bit 4: skip dense neighbours
+    int4 *d_mut_items = nullptr;  // mutual items {S, R, d_S | d_R << 4, 0}
+    uint16_t *d_leaf_mask = nullptr; // per leaf: bit d slot d written, bit 9 target-centric part
     int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
     float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
     int *d_work = nullptr;        // near-field work counter (reset by each call's first kernel)
@@ -167,10 +176,10 @@ struct FarArgs {
 // Launchers (kernels.hip).  All are asynchronous on `s`.
 void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        int near_waves, hipStream_t s);
+                        void *slots, int near_waves, hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
-void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, double *uv, double *uv_near,
-                     double *uv_far, hipStream_t s);
+void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
+                     double alpha, double *uv, double *uv_near, double *uv_far, hipStream_t s);
 
 // Backward
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,

@@ -253,10 +253,12 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
                                                  const int *__restrict__ leaf_start,
                                                  const int *__restrict__ tile_start,
                                                  const float4 *__restrict__ tile_box, int nside, T step,
-                                                 float cut_leaf2, double scale, double2 *__restrict__ near)
+                                                 float cut_leaf2, double scale, int dense,
+                                                 double2 *__restrict__ near)
 {
     const int lane = threadIdx.x;
-    const int logtp = u.w;
+    const int logtp = u.w & 15;
+    const bool skip_dense = (u.w >> 4) != 0;  // pairs with dense leaves go to the mutual form
     const int tp = 1 << logtp;
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
@@ -273,6 +275,7 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
             if (nx < 0 || nx >= nside) continue;
             const uint32_t S = morton_encode((uint32_t)nx, (uint32_t)ny);
             const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
+            if (skip_dense && s1 - s0 >= dense) continue;
             // target relative to the centre of leaf S: z_i - c_S = (z_i - c_T) + (c_T - c_S)
             const T tx = ri.x - (T)dx * step;
             const T ty = ri.y - (T)dy * step;
@@ -324,13 +327,13 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_forward_kernel
                                                                                  const int *__restrict__ tile_start,
                                                                                  const float4 *__restrict__ tile_box,
                                                                                  int nside, T step, float cut_leaf2,
-                                                                                 double scale,
+                                                                                 double scale, int dense,
                                                                                  double2 *__restrict__ near)
 {
     __shared__ rec_t<T> tile[64];
     if (!persistent) {
         p2p_forward_unit<T>(units[blockIdx.x], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
-                            scale, near);
+                            scale, dense, near);
         return;
     }
     for (;;) {
@@ -341,8 +344,224 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_forward_kernel
         const int last = min(first + kNearBatch, nunits);
         for (int cur = first; cur < last; ++cur)
             p2p_forward_unit<T>(units[cur], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
-                                scale, near);
+                                scale, dense, near);
     }
+}
+
+// ---------------------------------------------------------------------------------
+// Stage 9, mutual form for pairs of dense leaves.  The kernel of eq. regB-S2DGau is
+// odd, K(-z) = -K(z), so one evaluation of g(s)/s serves both particles of a pair.
+// One wavefront per item {S, R}: R is S itself or one of its neighbours (+1,0),
+// (-1,+1), (0,+1), (+1,+1), so every unordered pair of neighbouring dense leaves is
+// one item.  For each pair of 64-particle tiles (b of S, a of R), one tile is held one
+// particle per lane ("resident") and the other is staged in LDS and streamed in chunks
+// of 16 sources.  Within a chunk, lane l of a 16-lane row meets source (l + j) mod 16
+// at step j; the resident sums stay in the lane and each source's sum travels with its
+// source: a one-lane rotation within the row per step, fused into the add (a DPP
+// operand).  After 16 steps every row holds its partial sums of the chunk's sources;
+// two butterfly steps across rows complete them.  Sums for tile b stay in registers
+// over the tiles of R; sums for tile a accumulate in its particles' slot in memory.
+// Slots: nine per particle, one per neighbour direction d = 3(dy+1) + (dx+1), written
+// by exactly one item (the item of S = R writes its own particles' slot 4 from both
+// ends, tile b folding in what the earlier tiles wrote).  The near field is the fixed
+// order sum of the slots plus the target-centric part for sparse neighbours, so the
+// result does not depend on scheduling.
+// ---------------------------------------------------------------------------------
+
+// Lane l receives the value of lane 16 (l / 16) + ((l + 1) mod 16): DPP row_ror:15.
+__device__ __forceinline__ float row_rot(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF,
+                                                                 false));
+}
+__device__ __forceinline__ double row_rot(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x12F, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x12F, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// 16 steps of one chunk: src points at this lane's start in the chunk's doubled copy
+// (src[j] = source (l + j) mod 16).  rgn = -Gamma of the resident particle (zero for an
+// idle lane).  On return (cu, cv)[l] = this row's sum for source l mod 16 of the chunk.
+template <typename T, bool FAR>
+__device__ __forceinline__ void mutual_chunk(const rec_t<T> *src, T rx, T ry, T rgn, T &fu, T &fv, T &cu, T &cv)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const rec_t<T> sj = src[j];
+        const T ddx = rx - sj.x;
+        const T ddy = ry - sj.y;
+        const T ss = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+        const T r = recip(ss);
+        T h;  // g(s)/s
+        if (FAR) h = r;
+        else if (sizeof(T) == 4) h = fma(-exp_neg_scaled(ss), r, r);
+        else h = one_minus_exp(ss) * r;
+        const T wt = h * sj.z;
+        fu = fma(wt, ddy, fu);
+        fv = fma(wt, ddx, fv);
+        const T ws = h * rgn;
+        if (j == 0) {
+            cu = ws * ddy;
+            cv = ws * ddx;
+        } else {
+            // Not contracted: a multiply and an add that takes the rotation as its DPP
+            // operand are two instructions; an FMA needs the rotation as a separate move.
+#pragma clang fp contract(off)
+            cu = row_rot(cu) + ws * ddy;
+            cv = row_rot(cv) + ws * ddx;
+        }
+    }
+    cu = row_rot(cu);
+    cv = row_rot(cv);
+}
+
+// Records of one tile into LDS, each chunk of 16 stored twice in a row (so that the
+// sources of step j are at a constant offset), zero records past the tile's end.
+template <typename T>
+__device__ __forceinline__ rec_t<T> stage_doubled(rec_t<T> *dst, const rec_t<T> *__restrict__ rec, int first,
+                                                  int len)
+{
+    const int lane = threadIdx.x;
+    rec_t<T> r;
+    r.x = r.y = r.z = r.w = (T)0;
+    if (lane < len) r = rec[first + lane];
+    dst[(lane >> 4) * 32 + (lane & 15)] = r;
+    dst[(lane >> 4) * 32 + (lane & 15) + 16] = r;
+    return r;
+}
+
+// One tile b of S against every tile a of R (a >= b when S = R).  Per block (b, a) the
+// tile with more chunks of 16 sits in the lanes and the other is streamed from LDS, so
+// that fewer steps are spent; either way both sums come out lane-indexed by particle.
+template <typename T>
+__device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b, int b,
+                                                     int tb, const rec_t<T> *__restrict__ rec,
+                                                     const int *__restrict__ leaf_start,
+                                                     const int *__restrict__ tile_start,
+                                                     const float4 *__restrict__ tile_box, T step, float cut_leaf2,
+                                                     c2<T> *__restrict__ slot_s, c2<T> *__restrict__ slot_r)
+{
+    const int lane = threadIdx.x;
+    const uint32_t S = (uint32_t)it.x, R = (uint32_t)it.y;
+    const bool self = S == R;
+    const int ds = it.z & 15;
+    const int dx = ds % 3 - 1, dy = ds / 3 - 1;  // R - S in leaves
+    const T ox = (T)dx * step, oy = (T)dy * step;
+    const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
+    const int r1 = leaf_start[R + 1];
+    const int lenb = min(64, s1 - b);
+    const int nchb = (lenb + 15) >> 4;
+    __syncthreads();
+    const rec_t<T> rb = stage_doubled<T>(tile_b, rec, b, lenb);
+    // tile b in the frame of leaf R (resident form); in the streamed form it stays in
+    // the frame of S and tile a is moved there
+    const T bx = rb.x - ox, by = rb.y - oy;
+    const T bgn = lane < lenb ? -rb.z : (T)0;
+    const float4 bbox = tile_box[tb];
+    T fu = 0, fv = 0;
+    if (self && b > s0 && lane < lenb) {  // what the earlier tiles of S wrote for this tile
+        const c2<T> o = slot_s[b + lane];
+        fu = o.x;
+        fv = o.y;
+    }
+    const bool first_touch = b == s0;  // the first resident tile creates the streamed slots
+    int ta = self ? tb : tile_start[R];
+    for (int a = self ? b : leaf_start[R]; a < r1; a += 64, ++ta) {
+        const int lena = min(64, r1 - a);
+        const int ncha = (lena + 15) >> 4;
+        const bool diag = self && a == b;
+        const bool far = box_gap2(bbox, (float)-dx, (float)-dy, tile_box[ta]) >= cut_leaf2;
+        if (diag) {
+            // the tile with itself: every ordered pair from the resident end
+            __syncthreads();
+            for (int c = 0; c < nchb; ++c)
+                if (far) {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) p2p_pair<T, true>(tile_b[c * 32 + j], bx, by, fu, fv);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) p2p_pair<T, false>(tile_b[c * 32 + j], bx, by, fu, fv);
+                }
+            continue;
+        }
+        c2<T> old;
+        old.x = old.y = (T)0;
+        if (!first_touch && lane < lena) old = slot_r[a + lane];
+        const bool swap = ncha > nchb;  // tile a in the lanes, tile b streamed
+        __syncthreads();
+        const rec_t<T> ra = stage_doubled<T>(tile_a, rec, a, lena);
+        __syncthreads();
+        T px, py, pgn;
+        const rec_t<T> *src;
+        int nch;
+        if (swap) {
+            px = ra.x + ox;
+            py = ra.y + oy;
+            pgn = lane < lena ? -ra.z : (T)0;
+            src = tile_b;
+            nch = nchb;
+        } else {
+            px = bx;
+            py = by;
+            pgn = bgn;
+            src = tile_a;
+            nch = ncha;
+        }
+        T ru = 0, rv = 0, colu = 0, colv = 0;
+        for (int c = 0; c < nch; ++c) {
+            T cu, cv;
+            const rec_t<T> *sp = src + c * 32 + (lane & 15);
+            if (far) mutual_chunk<T, true>(sp, px, py, pgn, ru, rv, cu, cv);
+            else mutual_chunk<T, false>(sp, px, py, pgn, ru, rv, cu, cv);
+            cu += __shfl_xor(cu, 16);
+            cv += __shfl_xor(cv, 16);
+            cu += __shfl_xor(cu, 32);
+            cv += __shfl_xor(cv, 32);
+            if ((lane >> 4) == c) {
+                colu = cu;
+                colv = cv;
+            }
+        }
+        // sums of tile b and of tile a, lane-indexed
+        const T bu = swap ? colu : ru, bv = swap ? colv : rv;
+        const T au = swap ? ru : colu, av = swap ? rv : colv;
+        fu += bu;
+        fv += bv;
+        if (lane < lena) {
+            c2<T> nw;
+            nw.x = old.x + au;
+            nw.y = old.y + av;
+            slot_r[a + lane] = nw;
+        }
+    }
+    if (lane < lenb) {
+        c2<T> nw;
+        nw.x = fu;
+        nw.y = fv;
+        slot_s[b + lane] = nw;
+    }
+}
+
+// items: {S, R, d_S | d_R << 4, -}, d_S = direction of R seen from S, d_R = 8 - d_S.
+// slots: 9 x n sums (dY, dX) in the records' precision, unscaled.
+template <typename T>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_mutual_kernel(
+    const int4 *__restrict__ items, const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+    const int *__restrict__ tile_start, const float4 *__restrict__ tile_box, T step, float cut_leaf2, int64_t n,
+    c2<T> *__restrict__ slots)
+{
+    __shared__ rec_t<T> tile_a[128], tile_b[128];
+    const int4 it = items[blockIdx.x];
+    const uint32_t S = (uint32_t)it.x;
+    c2<T> *slot_s = slots + (int64_t)(it.z & 15) * n;
+    c2<T> *slot_r = slots + (int64_t)(it.z >> 4) * n;
+    const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
+    for (int b = s0, tb = tile_start[S]; b < s1; b += 64, ++tb)
+        mutual_resident_tile<T>(it, tile_a, tile_b, b, tb, rec, leaf_start, tile_start, tile_box, step, cut_leaf2,
+                                slot_s, slot_r);
 }
 
 template <typename TR, typename TC, int PMAX>
@@ -841,21 +1060,46 @@ __global__ __launch_bounds__(1024) void coarse_valu_kernel(CoarseValuArgs a)
 // (u, v) = (u_near + Re W_far, v_near - Im W_far).  (A two-pass scatter through a
 // staging array, as for the circulations, measured no faster for (u, v) pairs.)
 // ---------------------------------------------------------------------------------
-template <typename TL>
+// Near field of a particle: with the mutual form (mask != NULL), the target-centric
+// part (if mask bit 9 of its leaf) plus the slots d with mask bit d, in order d = 0..8.
+template <typename TS>
+__device__ __forceinline__ double2 near_total(int64_t i, int64_t n, uint32_t leaf, const double2 *__restrict__ near,
+                                              const uint16_t *__restrict__ mask, const c2<TS> *__restrict__ slots,
+                                              double scale)
+{
+    if (!mask) return near[i];
+    const int m = mask[leaf];
+    double2 r = (m >> 9) & 1 ? near[i] : make_double2(0.0, 0.0);
+    double su = 0.0, sv = 0.0;
+#pragma unroll
+    for (int d = 0; d < 9; ++d)
+        if ((m >> d) & 1) {
+            const c2<TS> v = slots[d * n + i];
+            su += (double)v.x;
+            sv += (double)v.y;
+        }
+    r.x -= scale * su;
+    r.y += scale * sv;
+    return r;
+}
+
+template <typename TL, typename TS>
 __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restrict__ perm,
                                                         const int *__restrict__ leaf_of,
                                                         const double2 *__restrict__ xy,
                                                         const double2 *__restrict__ near,
+                                                        const uint16_t *__restrict__ mask,
+                                                        const c2<TS> *__restrict__ slots, double scale,
                                                         const c2<TL> *__restrict__ loc, int p, int has_far, double x0,
                                                         double y0, double w, double *__restrict__ uv,
                                                         double *__restrict__ uv_near, double *__restrict__ uv_far)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double2 nr = near[i];
+    const uint32_t leaf = (uint32_t)leaf_of[i];
+    const double2 nr = near_total<TS>(i, n, leaf, near, mask, slots, scale);
     double fu = 0.0, fv = 0.0;
     if (has_far) {
-        const uint32_t leaf = (uint32_t)leaf_of[i];
         const double cx = x0 + (morton_x(leaf) + 0.5) * w;
         const double cy = y0 + (morton_y(leaf) + 0.5) * w;
         const double2 z = xy[i];
@@ -1337,9 +1581,11 @@ void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_do
 }
 
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        int near_waves, hipStream_t s)
+                        void *slots, int near_waves, hipStream_t s)
 {
-    if (t->nunits == 0) return;
+    const bool mutual = slots != nullptr;
+    const int64_t nunits = mutual ? t->nunits_tc : t->nunits;
+    const int4 *units = mutual ? t->d_units_tc : t->d_units;
     const int nside = 1 << t->depth;
     const double w = t->side / (double)nside;
     const double scale = alpha * kInv2Pi;
@@ -1349,16 +1595,29 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
     // covers the rounding of the records and of the box test (boxes in leaf units).
     const double cut = is_double ? 39.0 : 27.0;
     const float cut_leaf2 = (float)(cut / (step * step));
-    const int persistent = near_waves > 0 && near_waves < t->nunits;
-    const unsigned grid = (unsigned)(persistent ? near_waves : t->nunits);
+    if (mutual && t->nmut > 0) {
+        if (is_double)
+            p2p_mutual_kernel<double><<<(unsigned)t->nmut, 64, 0, s>>>(
+                t->d_mut_items, (const double4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, step,
+                cut_leaf2, t->n, (double2 *)slots);
+        else
+            p2p_mutual_kernel<float><<<(unsigned)t->nmut, 64, 0, s>>>(
+                t->d_mut_items, (const float4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, (float)step,
+                cut_leaf2, t->n, (float2 *)slots);
+    }
+    if (nunits == 0) return;
+    const int persistent = near_waves > 0 && near_waves < nunits;
+    const unsigned grid = (unsigned)(persistent ? near_waves : nunits);
     if (is_double)
-        p2p_forward_kernel<double><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+        p2p_forward_kernel<double><<<grid, 64, 0, s>>>(units, (int)nunits, persistent, t->d_work,
                                                         (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
-                                                        t->d_tile_box, nside, step, cut_leaf2, scale, near);
+                                                        t->d_tile_box, nside, step, cut_leaf2, scale, t->dense_leaf,
+                                                        near);
     else
-        p2p_forward_kernel<float><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
+        p2p_forward_kernel<float><<<grid, 64, 0, s>>>(units, (int)nunits, persistent, t->d_work,
                                                        (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
-                                                       t->d_tile_box, nside, (float)step, cut_leaf2, scale, near);
+                                                       t->d_tile_box, nside, (float)step, cut_leaf2, scale,
+                                                       t->dense_leaf, near);
 }
 
 void launch_far_chain(const FarArgs &a, hipStream_t s)
@@ -1433,21 +1692,37 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
     (void)fine_is_double;
 }
 
-void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, double *uv, double *uv_near,
-                     double *uv_far, hipStream_t s)
+void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
+                     double alpha, double *uv, double *uv_near, double *uv_far, hipStream_t s)
 {
     const int L = t->depth;
     const int n = (int)t->n;
     const double w = t->side / (double)(1 << L);
     const int has_far = L >= 2;
-    if (!has_far || L <= a.split)
-        finalize_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(
-            n, t->d_perm, t->d_leaf_of, t->d_xy, near, has_far ? level_ptr<double>(a, L, true) : nullptr, a.p,
-            has_far, t->x0, t->y0, w, uv, uv_near, uv_far);
-    else
-        finalize_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near,
-                                                                   level_ptr<float>(a, L, true), a.p, has_far,
-                                                                   t->x0, t->y0, w, uv, uv_near, uv_far);
+    const uint16_t *mask = slots ? t->d_leaf_mask : nullptr;
+    const double scale = alpha * kInv2Pi;
+    const dim3 g(blocks_for(n, 256));
+    if (!has_far || L <= a.split) {
+        const double2 *loc = has_far ? level_ptr<double>(a, L, true) : nullptr;
+        if (slots_double)
+            finalize_kernel<double, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
+                                                              (const double2 *)slots, scale, loc, a.p, has_far,
+                                                              t->x0, t->y0, w, uv, uv_near, uv_far);
+        else
+            finalize_kernel<double, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
+                                                             (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
+                                                             t->y0, w, uv, uv_near, uv_far);
+    } else {
+        const float2 *loc = level_ptr<float>(a, L, true);
+        if (slots_double)
+            finalize_kernel<float, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
+                                                             (const double2 *)slots, scale, loc, a.p, has_far,
+                                                             t->x0, t->y0, w, uv, uv_near, uv_far);
+        else
+            finalize_kernel<float, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
+                                                            (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
+                                                            t->y0, w, uv, uv_near, uv_far);
+    }
 }
 
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double, hipStream_t s)
