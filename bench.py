@@ -27,12 +27,15 @@ sys.path.insert(0, HERE)
 # Published MI355X peaks used for the roofline fractions.
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
-P2P_FLOPS_PER_PAIR = 22           # section "Complexity Estimates": 9 complex division, 1 exp
-# HBM bytes per launch of p2p_forward_kernel<float> on this workload, from rocprofv3 --pmc
+# Algorithmic flops per ordered (target, source) pair of the near-field sum, section
+# "Complexity Estimates" (a complex division and an exponential).  The mutual form evaluates
+# each unordered pair once for both particles, so its achieved rate counts that evaluation
+# as the two ordered pairs it completes.
+P2P_FLOPS_PER_PAIR = 22
+# HBM bytes per launch of p2p_near_kernel<float> on this workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors of a 256 MiB copy kernel measured the
-# same way (profiles/p2p_forward_gaussian_patches_16M.md).  None when the kernel has changed
-# since the counters were taken.
-P2P_TRAFFIC_BYTES = 6.443e9
+# same way (profiles/).  None when the kernel has changed since the counters were taken.
+P2P_TRAFFIC_BYTES = None
 
 
 def log(msg):
@@ -112,7 +115,8 @@ def main():
     t0 = time.perf_counter()
     tree = fmm.Tree(xy, w.depth, None)
     info = tree.info()
-    log(f"[bench] tree built in {time.perf_counter() - t0:.1f} s: {info}")
+    plan = tree.near_plan()
+    log(f"[bench] tree built in {time.perf_counter() - t0:.1f} s: {info}; near-field plan {plan}")
     out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
 
     def run(k, precision="mixed"):
@@ -143,10 +147,9 @@ def main():
     ms, stages = timed(args.steps)
     log(f"[bench] mixed overlap: {ms:.3f} ms/step, stages {stages}")
     if args.headline_only:
-        pairs = info["p2p_pairs"]
         print(json.dumps({"ms_per_step": round(ms, 4), "value": round(w.n / (ms * 1e-3) / 1e6, 3),
                           "p2p_avg_ms": round(stages["p2p"], 4),
-                          "p2p_tflops": round(P2P_FLOPS_PER_PAIR * pairs / (stages["p2p"] * 1e-3) / 1e12, 3),
+                          "p2p_tflops": round(P2P_FLOPS_PER_PAIR * info["p2p_pairs"] / (stages["p2p"] * 1e-3) / 1e12, 3),
                           "steps": args.steps, "warmup": args.warmup}), flush=True)
         return
     # serial schedule of the same work, for the overlap fraction
@@ -240,7 +243,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gaussian_patches", "n": w.n, "patches": 8, "sigma": w.sigma, "depth": w.depth,
                    "p": w.p, "precision": "mixed", "schedule": "overlap", "root": "bounding square"},
-        "roofline": {"bound": "alu", "kernel": "p2p_forward_kernel<float>", "achieved": round(achieved, 3),
+        "roofline": {"bound": "alu", "kernel": "p2p_near_kernel<float>", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "traffic": P2P_TRAFFIC_BYTES, "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs,
                      "avg_launch_ms": round(p2p_ms, 4)},
@@ -249,6 +252,8 @@ def main():
                      "mixed_vs_gpu_fp64_rel_l2": err_mixed_vs_fp64,
                      "sample": len(idx), "gate": 1e-5},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "near_field": {"mutual_items": plan["mutual_items"], "mutual_pairs": plan["mutual_pairs"],
+                       "target_units": plan["target_units"], "all_pairs": info["p2p_pairs"]},
         "serial_ms_per_step": round(ms_serial, 4),
         "serial_stages_ms": {k: round(v, 4) for k, v in stages_serial.items()},
         "overlap_fraction": None if overlap is None else round(overlap, 4),

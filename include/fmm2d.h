@@ -73,7 +73,10 @@ enum {
     FMM_OPT_NEAR_MUTUAL = 6,  /* 1 (default): pairs of neighbouring dense leaves are evaluated once
                                  for both particles (the kernel is odd), the rest from the target
                                  end; 0: every pair from the target end.  Results agree to rounding. */
-    FMM_OPT_DENSE_LEAF = 7    /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
+    FMM_OPT_DENSE_LEAF = 7,   /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
+    FMM_OPT_NEAR_OCCUPANCY = 8 /* 1..8: with FMM_OPT_SCHEDULE 0 the forward near-field kernel keeps at
+                                  most this many wavefronts per SIMD resident (by reserving LDS),
+                                  leaving room for the far field beside it; 0 = no cap; default 5 */
 };
 
 /* Stage indices of fmm_get_timings. */
@@ -161,6 +164,14 @@ int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p,
 int fmm_velocity_backward(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
                           const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
                           double *dl_dxeval);
+
+/* The near-field plan (stage 9) in force (any pointer may be NULL):
+ *   mutual_items  wavefront items of the mutual form (0 when it is off or finds no
+ *                 pair of dense leaves);
+ *   mutual_pairs  ordered pairs (i != j) those items evaluate, each unordered pair once
+ *                 for both particles;
+ *   target_units  work units of the target-centric form, which covers the other pairs. */
+int fmm_near_plan_info(const fmm_tree *tree, int64_t *mutual_items, int64_t *mutual_pairs, int64_t *target_units);
 
 /* Set an FMM_OPT_* option on a tree.  FMM_EINVAL for an unknown key or bad value. */
 int fmm_set_option(fmm_tree *tree, int key, int64_t value);

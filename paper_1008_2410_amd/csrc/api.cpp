@@ -102,8 +102,7 @@ void free_tree(fmm_tree *t)
     hipFree(t->d_counts);
     hipFree(t->d_lists);
     hipFree(t->d_units);
-    hipFree(t->d_units_tc);
-    hipFree(t->d_mut_items);
+    hipFree(t->d_near_work);
     hipFree(t->d_leaf_mask);
     hipFree(t->d_tile_start);
     hipFree(t->d_tile_box);
@@ -128,13 +127,11 @@ void free_tree(fmm_tree *t)
 // is empty and the target-centric units cover every pair.
 int build_near_plan(fmm_tree *t)
 {
-    hipFree(t->d_units_tc);
-    hipFree(t->d_mut_items);
+    hipFree(t->d_near_work);
     hipFree(t->d_leaf_mask);
-    t->d_units_tc = nullptr;
-    t->d_mut_items = nullptr;
+    t->d_near_work = nullptr;
     t->d_leaf_mask = nullptr;
-    t->nunits_tc = t->nmut = 0;
+    t->nunits_tc = t->nmut = t->nnear_work = t->mutual_pairs = 0;
     if (!t->near_mutual) return FMM_OK;
     const int L = t->depth;
     const int nside = 1 << L;
@@ -146,9 +143,26 @@ int build_near_plan(fmm_tree *t)
         const uint32_t c = morton_encode((uint32_t)x, (uint32_t)y);
         return ls[c + 1] - ls[c];
     };
-    std::vector<int4> units, items;
-    std::vector<int64_t> ucost, icost;
+    // Estimated cost in wavefront steps weighted by their cycles (a mutual step of 64
+    // pairs x 2 ends ~ 3, a target-centric step ~ 2).  Tiles of a leaf: f full ones of 64
+    // and a last one of r < 64; a block of tiles costs 16 steps per chunk of 16 of the
+    // smaller tile (the larger one sits in the lanes).
+    auto nch = [](int len) -> int64_t { return (len + 15) >> 4; };
+    auto block_steps = [&](int cs, int cr) -> int64_t {
+        const int64_t fs = cs / 64, fr = cr / 64;
+        const int rs = cs % 64, rr = cr % 64;
+        return 16 * (fs * fr * 4 + fs * nch(rr) + fr * nch(rs) + std::min(nch(rs), nch(rr)));
+    };
+    auto self_steps = [&](int c, int64_t &diag) -> int64_t {
+        const int64_t f = c / 64;
+        const int r = c % 64;
+        diag = 16 * (f * 4 + nch(r));
+        return 16 * (f * (f - 1) / 2 * 4 + f * nch(r));
+    };
+    std::vector<int4> work;
+    std::vector<int64_t> cost;
     std::vector<uint16_t> mask((size_t)nleaf, 0);
+    int64_t mpairs = 0, nunits = 0, nitems = 0;
     static const int up[4][2] = {{1, 0}, {-1, 1}, {0, 1}, {1, 1}};
     for (int64_t c = 0; c < nleaf; ++c) {
         const int nt = ls[c + 1] - ls[c];
@@ -171,41 +185,43 @@ int build_near_plan(fmm_tree *t)
                 int logtp = 0;
                 while ((1 << logtp) < cnt) ++logtp;
                 const int kstride = 64 >> logtp;
-                units.push_back(make_int4((int)c, ls[c] + c0, cnt, logtp | (dense ? 16 : 0)));
-                ucost.push_back((nsrc + kstride - 1) / kstride);
+                work.push_back(make_int4((int)c, ls[c] + c0, cnt, logtp | (dense ? 16 : 0)));
+                cost.push_back(2 * ((nsrc + kstride - 1) / kstride));
+                ++nunits;
             }
         }
         mask[c] = m;
         if (!dense) continue;
-        const int64_t tiles = (nt + 63) / 64;
-        items.push_back(make_int4((int)c, (int)c, 4 | (4 << 4), 0));
-        icost.push_back(tiles * (tiles + 1) / 2 * 64);
+        int64_t diag = 0;
+        const int64_t st = self_steps(nt, diag);
+        work.push_back(make_int4((int)c, (int)c, 4 | (4 << 4), kMutualItem));
+        cost.push_back(3 * st + 2 * diag);
+        mpairs += (int64_t)nt * (nt - 1);
+        ++nitems;
         for (const auto &o : up) {
             const int nr = count(x + o[0], y + o[1]);
             if (nr < D) continue;
             const int ds = 3 * (o[1] + 1) + (o[0] + 1);
-            items.push_back(make_int4((int)c, (int)morton_encode((uint32_t)(x + o[0]), (uint32_t)(y + o[1])),
-                                      ds | ((8 - ds) << 4), 0));
-            icost.push_back(tiles * nr);
+            work.push_back(make_int4((int)c, (int)morton_encode((uint32_t)(x + o[0]), (uint32_t)(y + o[1])),
+                                     ds | ((8 - ds) << 4), kMutualItem));
+            cost.push_back(3 * block_steps(nt, nr));
+            mpairs += 2 * (int64_t)nt * nr;
+            ++nitems;
         }
     }
-    auto by_cost = [](std::vector<int4> &v, const std::vector<int64_t> &cost) {
-        std::vector<int64_t> order(v.size());
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-        std::vector<int4> out(v.size());
-        for (size_t k = 0; k < order.size(); ++k) out[k] = v[order[k]];
-        v.swap(out);
-    };
-    by_cost(units, ucost);
-    by_cost(items, icost);
+    std::vector<int64_t> order(work.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    std::vector<int4> sorted(work.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = work[order[k]];
     int rc = FMM_OK;
-    if (!units.empty()) rc = upload(&t->d_units_tc, units, "near-field units");
-    if (!rc && !items.empty()) rc = upload(&t->d_mut_items, items, "mutual near-field items");
+    if (!sorted.empty()) rc = upload(&t->d_near_work, sorted, "near-field work list");
     if (!rc) rc = upload(&t->d_leaf_mask, mask, "near-field leaf masks");
     if (rc) return rc;
-    t->nunits_tc = (int64_t)units.size();
-    t->nmut = (int64_t)items.size();
+    t->nunits_tc = nunits;
+    t->nmut = nitems;
+    t->nnear_work = (int64_t)sorted.size();
+    t->mutual_pairs = mpairs;
     return FMM_OK;
 }
 
@@ -800,6 +816,10 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         else t->dense_leaf = (int)value;
         return build_near_plan(t);
     }
+    case FMM_OPT_NEAR_OCCUPANCY:
+        if (value < 0 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [0, 8]");
+        t->near_occupancy = (int)value;
+        return FMM_OK;
     case FMM_OPT_TIMING:
         if (value != 0 && value != 1) return fail(FMM_EINVAL, "timing must be 0 or 1");
         t->timing = (int)value;
@@ -809,12 +829,23 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
     }
 }
 
+extern "C" int fmm_near_plan_info(const fmm_tree *t, int64_t *mutual_items, int64_t *mutual_pairs,
+                                  int64_t *target_units)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    const bool m = use_mutual(t);
+    if (mutual_items) *mutual_items = m ? t->nmut : 0;
+    if (mutual_pairs) *mutual_pairs = m ? t->mutual_pairs : 0;
+    if (target_units) *target_units = m ? t->nunits_tc : t->nunits;
+    return FMM_OK;
+}
+
 extern "C" int fmm_get_timings(fmm_tree *t, double *ms, int64_t *calls)
 {
     if (!t) return fail(FMM_ESTATE, "null tree handle");
     if (!ms) return fail(FMM_EINVAL, "ms is NULL");
     HIP_TRY(hipSetDevice(t->device));
-    double acc[FMM_T_COUNT] = {0, 0, 0, 0, 0};
+    double acc[FMM_T_COUNT] = {};
     int64_t ncalls = 0;
     for (auto &ev : t->pending_timing) {
         HIP_TRY(hipEventSynchronize(ev[7]));

@@ -80,6 +80,8 @@ constexpr int64_t kCoefPad = 64;
 // to round-robin.
 constexpr int kStageShiftMin = 17;
 constexpr int kXcds = 8;
+// Flag (in w) of a mutual item in the near-field work list.
+constexpr int kMutualItem = 256;
 
 // Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
 // are FP64, levels split+1..L are FP32; each level holds 4^l cells x p coefficients,
@@ -114,6 +116,7 @@ struct fmm_tree {
     int schedule = 0;    // 0 overlap, 1 serial
     int near_mutual = 1; // pairs of dense leaves evaluated once for both particles
     int dense_leaf = 32; // a leaf with at least this many particles is dense
+    int near_occupancy = 5; // cap on forward near-field wavefronts per SIMD beside the far field (0: none)
     int timing = 0;
     std::atomic<int> busy{0};
 
@@ -140,9 +143,9 @@ struct fmm_tree {
     int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
     std::vector<int> h_leaf_start;  // host copy of d_leaf_start
     // near-field plan of the mutual form (see build_near_plan)
-    int64_t nunits_tc = 0, nmut = 0;
-    int4 *d_units_tc = nullptr;   // target-centric units; w bit 4: skip dense neighbours
-    int4 *d_mut_items = nullptr;  // mutual items {S, R, d_S | d_R << 4, 0}
+    int64_t nunits_tc = 0, nmut = 0, nnear_work = 0;
+    int64_t mutual_pairs = 0;     // ordered pairs (i != j) evaluated by the mutual items
+    int4 *d_near_work = nullptr;  // mutual items and target-centric units, heaviest first
     uint16_t *d_leaf_mask = nullptr; // per leaf: bit d slot d written, bit 9 target-centric part
     int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
     float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
@@ -175,8 +178,8 @@ struct FarArgs {
 
 // Launchers (kernels.hip).  All are asynchronous on `s`.
 void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
-void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        void *slots, int near_waves, hipStream_t s);
+void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
+                        int near_waves, hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
                      double alpha, double *uv, double *uv_near, double *uv_far, hipStream_t s);

@@ -308,46 +308,6 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
     if (k == 0 && t < u.z) near[i] = make_double2(-scale * au, scale * av);
 }
 
-// Near-field grid, two forms.  One workgroup per unit (persistent == 0): the hardware
-// dispatcher hands out units in order, heaviest first.  Persistent (persistent != 0):
-// a grid smaller than the chip's capacity, each wavefront taking batches of
-// kNearBatch consecutive units from the call's counter until none is left, which
-// leaves wavefront slots free for far-field kernels running beside it.  Either way
-// each unit writes only its own targets, so the result does not depend on which
-// wavefront takes which unit.  The counter's atomic is issued by one lane (a vector
-// memory atomic) and broadcast to the wavefront.
-constexpr int kNearBatch = 4;
-
-template <typename T>
-__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_forward_kernel(const int4 *__restrict__ units,
-                                                                                 int nunits, int persistent,
-                                                                                 int *__restrict__ work_ctr,
-                                                                                 const rec_t<T> *__restrict__ rec,
-                                                                                 const int *__restrict__ leaf_start,
-                                                                                 const int *__restrict__ tile_start,
-                                                                                 const float4 *__restrict__ tile_box,
-                                                                                 int nside, T step, float cut_leaf2,
-                                                                                 double scale, int dense,
-                                                                                 double2 *__restrict__ near)
-{
-    __shared__ rec_t<T> tile[64];
-    if (!persistent) {
-        p2p_forward_unit<T>(units[blockIdx.x], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
-                            scale, dense, near);
-        return;
-    }
-    for (;;) {
-        int v = 0;
-        if (threadIdx.x == 0) v = atomicAdd(work_ctr, kNearBatch);
-        const int first = __builtin_amdgcn_readfirstlane(v);
-        if (first >= nunits) break;
-        const int last = min(first + kNearBatch, nunits);
-        for (int cur = first; cur < last; ++cur)
-            p2p_forward_unit<T>(units[cur], tile, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
-                                scale, dense, near);
-    }
-}
-
 // ---------------------------------------------------------------------------------
 // Stage 9, mutual form for pairs of dense leaves.  The kernel of eq. regB-S2DGau is
 // odd, K(-z) = -K(z), so one evaluation of g(s)/s serves both particles of a pair.
@@ -545,16 +505,27 @@ __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *ti
     }
 }
 
-// items: {S, R, d_S | d_R << 4, -}, d_S = direction of R seen from S, d_R = 8 - d_S.
-// slots: 9 x n sums (dY, dX) in the records' precision, unscaled.
+// Near-field grid (stage 9): one list of work entries, each one wavefront's work:
+//   mutual items {S, R, d_S | d_R << 4, kMutualItem}, d_S = direction of R seen from S
+//   and d_R = 8 - d_S, writing the slots (9 x n sums (dY, dX) in the records'
+//   precision, unscaled);
+//   target-centric units {leaf, first, count, log2 TP | 16 if dense neighbours are
+//   skipped}, writing near.
+// The list is sorted by estimated cost, heaviest first.  One workgroup per entry
+// (persistent == 0): the hardware dispatcher hands them out in order.  Persistent
+// (persistent != 0): a grid smaller than the chip's capacity, each wavefront taking the
+// next entry from the call's counter until none is left, which leaves wavefront slots
+// free for far-field kernels running beside it.  Either way each entry writes only its
+// own outputs, so the result does not depend on which wavefront takes which entry.
+// The counter's atomic is issued by one lane (a vector memory atomic) and broadcast to
+// the wavefront.
+
 template <typename T>
-__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_mutual_kernel(
-    const int4 *__restrict__ items, const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
-    const int *__restrict__ tile_start, const float4 *__restrict__ tile_box, T step, float cut_leaf2, int64_t n,
-    c2<T> *__restrict__ slots)
+__device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b,
+                                            const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
+                                            T step, float cut_leaf2, int64_t n, c2<T> *__restrict__ slots)
 {
-    __shared__ rec_t<T> tile_a[128], tile_b[128];
-    const int4 it = items[blockIdx.x];
     const uint32_t S = (uint32_t)it.x;
     c2<T> *slot_s = slots + (int64_t)(it.z & 15) * n;
     c2<T> *slot_r = slots + (int64_t)(it.z >> 4) * n;
@@ -562,6 +533,44 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_mutual_kernel(
     for (int b = s0, tb = tile_start[S]; b < s1; b += 64, ++tb)
         mutual_resident_tile<T>(it, tile_a, tile_b, b, tb, rec, leaf_start, tile_start, tile_box, step, cut_leaf2,
                                 slot_s, slot_r);
+}
+
+template <typename T>
+__device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t<T> *tile_b,
+                                           const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+                                           const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
+                                           int nside, T step, float cut_leaf2, double scale, int dense, int64_t n,
+                                           double2 *__restrict__ near, c2<T> *__restrict__ slots)
+{
+    if (u.w & kMutualItem)
+        mutual_item<T>(u, tile_a, tile_b, rec, leaf_start, tile_start, tile_box, step, cut_leaf2, n, slots);
+    else
+        p2p_forward_unit<T>(u, tile_a, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2, scale, dense,
+                            near);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
+    const int4 *__restrict__ work, int nwork, int persistent, int *__restrict__ work_ctr,
+    const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start, const int *__restrict__ tile_start,
+    const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2, double scale, int dense, int64_t n,
+    double2 *__restrict__ near, c2<T> *__restrict__ slots)
+{
+    __shared__ rec_t<T> tile_a[128], tile_b[128];
+    if (!persistent) {
+        near_entry<T>(work[blockIdx.x], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step,
+                      cut_leaf2, scale, dense, n, near, slots);
+        return;
+    }
+    for (;;) {
+        int v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(work_ctr, 1);
+        const int cur = __builtin_amdgcn_readfirstlane(v);
+        if (cur >= nwork) break;
+        __syncthreads();  // the previous entry's LDS reads are done
+        near_entry<T>(work[cur], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
+                      scale, dense, n, near, slots);
+    }
 }
 
 template <typename TR, typename TC, int PMAX>
@@ -1460,6 +1469,11 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
     }
 }
 
+// Adjoint near-field grid: one workgroup per target-centric unit, or persistent as in
+// the forward grid with kNearBatch consecutive units per counter increment (the units
+// are small, so the batch hides the atomic's latency).
+constexpr int kNearBatch = 4;
+
 template <typename T>
 __global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
                                                            int *__restrict__ work_ctr,
@@ -1580,44 +1594,48 @@ void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_do
                                                              t->x0, t->y0, w, alpha, (float4 *)rec, t->d_work);
 }
 
-void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near,
-                        void *slots, int near_waves, hipStream_t s)
+// Exponential skipped where every pair has s >= cut: FP32 base 2, 1 - 2^-s rounds to 1
+// for s >= 26; FP64 base e, 1 - e^-s rounds to 1 for s >= 37.5.  One unit of margin
+// covers the rounding of the records and of the box test (boxes in leaf units).
+inline float near_cut_leaf2(const fmm_tree *t, int is_double, double alpha)
+{
+    const double step = alpha * t->side / (double)(1 << t->depth);
+    const double cut = is_double ? 39.0 : 27.0;
+    return (float)(cut / (step * step));
+}
+
+// Dynamic LDS reserved by each near-field workgroup (one wavefront) so that at most
+// near_occupancy wavefronts per SIMD are resident (160 KiB of LDS per CU, 4 SIMDs),
+// leaving room for the far-field kernels on the other stream.  Serial schedule: no cap.
+inline size_t near_lds_reserve(const fmm_tree *t, size_t static_bytes)
+{
+    if (t->near_occupancy <= 0 || t->schedule != 0 || t->depth < 2) return 0;
+    const size_t per_wave = (size_t)160 * 1024 / (4 * (size_t)t->near_occupancy);
+    return per_wave > static_bytes ? per_wave - static_bytes : 0;
+}
+
+void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
+                        int near_waves, hipStream_t s)
 {
     const bool mutual = slots != nullptr;
-    const int64_t nunits = mutual ? t->nunits_tc : t->nunits;
-    const int4 *units = mutual ? t->d_units_tc : t->d_units;
+    const int64_t nwork = mutual ? t->nnear_work : t->nunits;
+    const int4 *work = mutual ? t->d_near_work : t->d_units;
+    if (nwork == 0) return;
     const int nside = 1 << t->depth;
     const double w = t->side / (double)nside;
     const double scale = alpha * kInv2Pi;
     const double step = alpha * w;
-    // Exponential skipped where every pair has s >= cut: FP32 base 2, 1 - 2^-s rounds to 1
-    // for s >= 26; FP64 base e, 1 - e^-s rounds to 1 for s >= 37.5.  One unit of margin
-    // covers the rounding of the records and of the box test (boxes in leaf units).
-    const double cut = is_double ? 39.0 : 27.0;
-    const float cut_leaf2 = (float)(cut / (step * step));
-    if (mutual && t->nmut > 0) {
-        if (is_double)
-            p2p_mutual_kernel<double><<<(unsigned)t->nmut, 64, 0, s>>>(
-                t->d_mut_items, (const double4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, step,
-                cut_leaf2, t->n, (double2 *)slots);
-        else
-            p2p_mutual_kernel<float><<<(unsigned)t->nmut, 64, 0, s>>>(
-                t->d_mut_items, (const float4 *)rec, t->d_leaf_start, t->d_tile_start, t->d_tile_box, (float)step,
-                cut_leaf2, t->n, (float2 *)slots);
-    }
-    if (nunits == 0) return;
-    const int persistent = near_waves > 0 && near_waves < nunits;
-    const unsigned grid = (unsigned)(persistent ? near_waves : nunits);
+    const float cut_leaf2 = near_cut_leaf2(t, is_double, alpha);
+    const int persistent = near_waves > 0 && near_waves < nwork;
+    const unsigned grid = (unsigned)(persistent ? near_waves : nwork);
     if (is_double)
-        p2p_forward_kernel<double><<<grid, 64, 0, s>>>(units, (int)nunits, persistent, t->d_work,
-                                                        (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
-                                                        t->d_tile_box, nside, step, cut_leaf2, scale, t->dense_leaf,
-                                                        near);
+        p2p_near_kernel<double><<<grid, 64, near_lds_reserve(t, 256 * sizeof(double4)), s>>>(
+            work, (int)nwork, persistent, t->d_work, (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
+            t->d_tile_box, nside, step, cut_leaf2, scale, t->dense_leaf, t->n, near, (double2 *)slots);
     else
-        p2p_forward_kernel<float><<<grid, 64, 0, s>>>(units, (int)nunits, persistent, t->d_work,
-                                                       (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
-                                                       t->d_tile_box, nside, (float)step, cut_leaf2, scale,
-                                                       t->dense_leaf, near);
+        p2p_near_kernel<float><<<grid, 64, near_lds_reserve(t, 256 * sizeof(float4)), s>>>(
+            work, (int)nwork, persistent, t->d_work, (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
+            t->d_tile_box, nside, (float)step, cut_leaf2, scale, t->dense_leaf, t->n, near, (float2 *)slots);
 }
 
 void launch_far_chain(const FarArgs &a, hipStream_t s)

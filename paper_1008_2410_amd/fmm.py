@@ -103,6 +103,12 @@ class Tree:
                     "fmm_tree_permutation")
         return perm, leaf
 
+    def near_plan(self) -> dict:
+        """Near-field plan: mutual items, ordered pairs they evaluate, target-centric units."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        L.check(L.load().fmm_near_plan_info(self.handle, *[ctypes.byref(x) for x in v]), "fmm_near_plan_info")
+        return {"mutual_items": v[0].value, "mutual_pairs": v[1].value, "target_units": v[2].value}
+
     def set_option(self, key: int, value: int):
         L.check(L.load().fmm_set_option(self.handle, int(key), int(value)), "fmm_set_option")
 

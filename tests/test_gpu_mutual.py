@@ -70,6 +70,11 @@ def test_mutual_ragged_tiles(fmm_mod, oracle_mod):
     tree = fmm_mod.Tree(_t(xy), w.depth, w.root_box)
     for dense in (1, 16, 17, 64, 65, 1 << 30):
         tree.set_option(OPT_DENSE_LEAF, dense)
+        plan = tree.near_plan()
+        if dense == 1:  # every pair of occupied neighbouring leaves is a mutual pair
+            assert plan["mutual_pairs"] == tree.info()["p2p_pairs"]
+        if dense == 1 << 30:
+            assert plan["mutual_items"] == 0 and plan["mutual_pairs"] == 0
         for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
             near, _ = _parts(tree, w, precision)
             assert rel_l2(near, on) < tol, (dense, precision)
