@@ -34,8 +34,9 @@ PEAK_HBM_GBS = 8000.0
 P2P_FLOPS_PER_PAIR = 22
 # HBM bytes per launch of p2p_near_kernel<float> on this workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors of a 256 MiB copy kernel measured the
-# same way (profiles/).  None when the kernel has changed since the counters were taken.
-P2P_TRAFFIC_BYTES = None
+# same way (profiles/p2p_near_gaussian_patches_16M.md).  None when the kernel has changed since
+# the counters were taken.
+P2P_TRAFFIC_BYTES = 7.402e9
 
 
 def log(msg):
