@@ -16,6 +16,9 @@ Levels (see the C file's header for the readings of points the paper leaves open
                     elsewhere (the far-field substitution after eq. discBiotS2D)
   fmm           O3  FMM stages 1-10 (Fig. fmmStages), unscaled textbook operators
   fmm_grad      O4  gradient of L(u) through O3: dL/dGamma and dL/dx_eval
+  fmm_src_grad  O5  gradient of L(u) through O3 with respect to the source positions
+  direct_grad       gradient of L(u) through O1, every particle moving as source and
+                    evaluation point
 """
 from __future__ import annotations
 
@@ -65,6 +68,9 @@ def _load():
         lib.orc_split_direct.restype = None
         lib.orc_fmm.argtypes = [I64, P, P, I64, P, D, Ci, P, Ci, P, P]
         lib.orc_fmm_jacobian.argtypes = [I64, P, P, I64, P, D, Ci, P, Ci, P, P]
+        lib.orc_fmm_src_grad.argtypes = [I64, P, P, P, D, Ci, P, Ci, P, P]
+        lib.orc_direct_grad.argtypes = [I64, P, P, D, P, P, P]
+        lib.orc_direct_grad.restype = None
         lib.orc_leaf_counts.argtypes = [I64, P, Ci, P, P]
         lib.orc_cover_level.argtypes = [Ci, Ci, Ci, Ci, Ci]
         _lib = lib
@@ -212,6 +218,45 @@ def fmm_grad(xy, gamma, sigma: float, depth: int, p: int, dl_duv, root=None):
     jac = jn + jf
     dx = np.einsum("nij,ni->nj", jac, g)
     return dgamma, dx
+
+
+def fmm_src_grad(xy, gamma, sigma: float, depth: int, p: int, dl_duv, root=None):
+    """O5: gradient of L(u) through the O3 velocities at the particles with respect to
+    the source positions, evaluation points held fixed, as (near part, far part), each
+    (N, 2).  Near: minus the pair Jacobians summed over the particles whose
+    neighbourhood holds the source.  Far: -Re(c_j Phi'_j), Im(c_j Phi'_j) with Phi' the
+    derivative of the local expansion of the FMM run with charges q = dL/du + i dL/dv
+    (the far operator is antisymmetric)."""
+    xy = _f64(xy, (-1, 2))
+    gm = _f64(gamma, (-1,))
+    g = _f64(dl_duv, (-1, 2))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    dn = np.zeros_like(xy)
+    df = np.zeros_like(xy)
+    _check(_load().orc_fmm_src_grad(xy.shape[0], _ptr(xy), _ptr(gm), _ptr(g), float(sigma), depth, _ptr(r), p,
+                                    _ptr(dn), _ptr(df)), "orc_fmm_src_grad")
+    return dn, df
+
+
+def fmm_grad_full(xy, gamma, sigma: float, depth: int, p: int, dl_duv, root=None):
+    """O4 + O5: (dL/dGamma (N,), dL/dx_eval (N, 2), dL/dx_src (N, 2)).  The gradient
+    with respect to the particle positions, each particle moving as evaluation point and
+    as source (the tree's cells held fixed), is dL/dx_eval + dL/dx_src."""
+    dgamma, dx_eval = fmm_grad(xy, gamma, sigma, depth, p, dl_duv, root)
+    dn, df = fmm_src_grad(xy, gamma, sigma, depth, p, dl_duv, root)
+    return dgamma, dx_eval, dn + df
+
+
+def direct_grad(xy, gamma, sigma: float, dl_duv):
+    """Gradient of L(u) through the O1 velocities: (dL/dGamma (N,), dL/dx (N, 2)), each
+    particle moving both as evaluation point and as source."""
+    xy = _f64(xy, (-1, 2))
+    gm = _f64(gamma, (-1,))
+    g = _f64(dl_duv, (-1, 2))
+    dg = np.zeros(xy.shape[0])
+    dx = np.zeros_like(xy)
+    _load().orc_direct_grad(xy.shape[0], _ptr(xy), _ptr(gm), float(sigma), _ptr(g), _ptr(dg), _ptr(dx))
+    return dg, dx
 
 
 def pair_count(counts: np.ndarray) -> int:

@@ -31,6 +31,10 @@
  *   orc_fmm           O3: FMM stages 1-10 with unscaled textbook operators
  *   orc_fmm_jacobian  O4 helper: d(u,v)/d(x,y) of the O3 field at evaluation points
  *                     (sources held fixed)
+ *   orc_fmm_src_grad  O5 helper: gradient of a loss through the O3 velocities with
+ *                     respect to the source positions (evaluation points held fixed)
+ *   orc_direct_grad   O1 gradient: dL/dGamma and dL/dx of a loss through the O1
+ *                     velocities, every particle moving as source and target
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  *   - p is the number of terms, m = 0..p-1, for multipole and local expansions.
@@ -588,6 +592,129 @@ int orc_fmm_jacobian(int64_t ns, const double *sxy, const double *gamma, int64_t
     free(tix);
     free(tiy);
     return ORC_OK;
+}
+
+/* Real-form derivatives of one pair's velocity contribution, (u, v) = G (-dy, dx) f(s),
+ * s = dx^2 + dy^2, (dx, dy) = target - source, with respect to the target position:
+ * J = [du/dx, du/dy, dv/dx, dv/dy].  f(0) and f'(0) are the kernel's limits. */
+static void pair_jacobian(double dx, double dy, double G, double sigma, double *J)
+{
+    double kappa = 1.0 / (2.0 * sigma * sigma);
+    double s = dx * dx + dy * dy;
+    double f = (s == 0.0) ? kappa : reg_f(s, sigma);
+    double fp = kappa * kappa * reg_h(kappa * s);
+    J[0] = G * (-dy) * fp * 2.0 * dx;
+    J[1] = G * (-f - dy * fp * 2.0 * dy);
+    J[2] = G * (f + dx * fp * 2.0 * dx);
+    J[3] = G * dx * fp * 2.0 * dy;
+}
+
+/* O5 helper.  Gradient of L through the O3 velocities at the particles with respect to
+ * the SOURCE positions, the evaluation points held fixed; g = (dL/du_i, dL/dv_i).
+ * Near part: the pair (i, j) term of u_i depends on z_j through z_i - z_j, so its
+ * derivative with respect to z_j is minus the pair's Jacobian, summed over the
+ * particles i whose 3 x 3 neighbourhood holds j (the pair i = j included: moving the
+ * source alone changes it).
+ * Far part: the O3 far operator is antisymmetric as a function of both positions,
+ * F_ij(z_i, z_j) = -F_ji(z_j, z_i) (symmetric lists, square truncation, exact M2M and
+ * L2L), so sum_i q_i dF_ij/dz_j = -Phi'_j, the derivative at z_j of the local expansion
+ * of the same FMM run with charges q_i = g_i,u + i g_i,v.  With dL = Re(sum_i q_i dW_i),
+ * W = u - iv and c_j = -i Gamma_j/(2 pi):  dL/dx_j = -Re(c_j Phi'_j),
+ * dL/dy_j = Im(c_j Phi'_j). */
+int orc_fmm_src_grad(int64_t n, const double *xy, const double *gamma, const double *g, double sigma, int depth,
+                     const double *root, int p, double *d_near, double *d_far)
+{
+    if (!(sigma > 0.0)) return ORC_EINVAL;
+    cplx *q = malloc(sizeof(cplx) * (n ? n : 1));
+    int32_t *tix = malloc(sizeof(int32_t) * (n ? n : 1));
+    int32_t *tiy = malloc(sizeof(int32_t) * (n ? n : 1));
+    if (!q || !tix || !tiy) {
+        free(q);
+        free(tix);
+        free(tiy);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) q[i] = g[2 * i] + I * g[2 * i + 1];
+    otree t;
+    int rc = fmm_setup(&t, n, xy, q, n, xy, tix, tiy, depth, root, p);
+    if (rc) {
+        otree_free(&t);
+        free(q);
+        free(tix);
+        free(tiy);
+        return rc;
+    }
+    int L = depth, nside = 1 << L;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < n; ++j) {
+        double x = xy[2 * j], y = xy[2 * j + 1];
+        int cx = tix[j], cy = tiy[j];
+        cplx dphi = 0.0;
+        if (L >= 2) {
+            cplx d = (x + I * y) - cell_centre(&t, L, cx, cy);
+            const cplx *B = &t.local[L][((int64_t)cy * nside + cx) * p];
+            cplx pw = 1.0;
+            for (int lo = 1; lo < p; ++lo) {
+                dphi += lo * B[lo] * pw;
+                pw *= d;
+            }
+        }
+        cplx c = -I * gamma[j] / TWO_PI;
+        d_far[2 * j] = -creal(c * dphi);
+        d_far[2 * j + 1] = cimag(c * dphi);
+        double gx = 0.0, gy = 0.0, G = gamma[j] / TWO_PI, J[4];
+        for (int ny = cy - 1; ny <= cy + 1; ++ny)
+            for (int nx = cx - 1; nx <= cx + 1; ++nx) {
+                if (nx < 0 || ny < 0 || nx >= nside || ny >= nside) continue;
+                int64_t cell = (int64_t)ny * nside + nx;
+                for (int64_t k = t.leaf_start[cell]; k < t.leaf_start[cell + 1]; ++k) {
+                    int64_t i = t.leaf_src[k];
+                    pair_jacobian(xy[2 * i] - x, xy[2 * i + 1] - y, G, sigma, J);
+                    gx -= g[2 * i] * J[0] + g[2 * i + 1] * J[2];
+                    gy -= g[2 * i] * J[1] + g[2 * i + 1] * J[3];
+                }
+            }
+        d_near[2 * j] = gx;
+        d_near[2 * j + 1] = gy;
+    }
+    otree_free(&t);
+    free(q);
+    free(tix);
+    free(tiy);
+    return ORC_OK;
+}
+
+/* O1 gradient.  L through u_i = sum_{j != i, s_ij > 0} Gamma_j K_sigma(x_i - x_j) with
+ * every particle moving both as evaluation point and as source; g = (dL/du_i, dL/dv_i).
+ * dL/dGamma_j = sum_i g_i . K_sigma(x_i - x_j); each pair (i, j) adds g_i . J_ij to
+ * dL/dx_i and subtracts it from dL/dx_j. */
+void orc_direct_grad(int64_t n, const double *xy, const double *gamma, double sigma, const double *g,
+                     double *dgamma, double *dxy)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t a = 0; a < n; ++a) {
+        double dga = 0.0, ex = 0.0, ey = 0.0, J[4];
+        for (int64_t b = 0; b < n; ++b) {
+            if (b == a) continue;
+            /* pair (target a, source b): eval derivative of a */
+            double dx = xy[2 * a] - xy[2 * b], dy = xy[2 * a + 1] - xy[2 * b + 1];
+            double s = dx * dx + dy * dy;
+            if (s > 0.0) {
+                pair_jacobian(dx, dy, gamma[b] / TWO_PI, sigma, J);
+                ex += g[2 * a] * J[0] + g[2 * a + 1] * J[2];
+                ey += g[2 * a] * J[1] + g[2 * a + 1] * J[3];
+                /* pair (target b, source a): source derivative of a, and dL/dGamma_a */
+                pair_jacobian(-dx, -dy, gamma[a] / TWO_PI, sigma, J);
+                ex -= g[2 * b] * J[0] + g[2 * b + 1] * J[2];
+                ey -= g[2 * b] * J[1] + g[2 * b + 1] * J[3];
+                double k = reg_f(s, sigma) / TWO_PI;
+                dga += g[2 * b] * (dy * k) + g[2 * b + 1] * (-dx * k);
+            }
+        }
+        dgamma[a] = dga;
+        dxy[2 * a] = ex;
+        dxy[2 * a + 1] = ey;
+    }
 }
 
 /* Per-leaf particle counts (row-major leaves) for the pair-count check. */

@@ -296,3 +296,105 @@ def test_adjoint_positions_tiny_direct(oracle_mod):
             um = oracle_mod.direct(xy, g, sigma, targets=tm)[0]
             fd = (0.5 * ((up - ustar[k]) ** 2).sum() - 0.5 * ((um - ustar[k]) ** 2).sum()) / (2 * h)
             assert abs(fd - dx[k, comp]) < 1e-7 * max(1.0, abs(fd)), (k, comp, fd, dx[k, comp])
+
+
+# --- O5: source positions, and the gradient with every particle moving -------------------
+
+def test_direct_gradient_matches_central_differences(oracle_mod):
+    """O1 gradient (every particle moving as source and evaluation point) against central
+    differences of L(O1), on circulations and positions."""
+    r = rng(71)
+    n = 80
+    xy = r.random((n, 2))
+    g = r.standard_normal(n)
+    ustar = r.standard_normal((n, 2))
+    sigma = 0.05
+
+    def loss(x, gm):
+        u = oracle_mod.direct(x, gm, sigma)
+        return 0.5 * ((u - ustar) ** 2).sum()
+
+    dg, dx = oracle_mod.direct_grad(xy, g, sigma, oracle_mod.direct(xy, g, sigma) - ustar)
+    h = 1e-6
+    for k in range(6):
+        for comp in (0, 1):
+            a, b = xy.copy(), xy.copy()
+            a[k, comp] += h
+            b[k, comp] -= h
+            fd = (loss(a, g) - loss(b, g)) / (2 * h)
+            assert abs(fd - dx[k, comp]) <= 1e-7 * abs(fd) + 1e-9, (k, comp, fd, dx[k, comp])
+        a, b = g.copy(), g.copy()
+        a[k] += h
+        b[k] -= h
+        fd = (loss(xy, a) - loss(xy, b)) / (2 * h)
+        assert abs(fd - dg[k]) <= 1e-7 * abs(fd) + 1e-9, (k, fd, dg[k])
+
+
+def test_direct_gradient_translation_invariance(oracle_mod):
+    """u(x + t) = u(x) for a common shift t of all particles, so the position gradient of
+    any L(u) sums to zero over the particles."""
+    r = rng(72)
+    xy = r.random((120, 2))
+    g = r.standard_normal(120)
+    _, dx = oracle_mod.direct_grad(xy, g, 0.04, r.standard_normal((120, 2)))
+    assert np.abs(dx.sum(axis=0)).max() < 1e-12 * np.abs(dx).sum()
+
+
+def test_fmm_total_position_gradient_matches_central_differences(oracle_mod):
+    """O4 + O5: dL/dx_eval + dL/dx_src against central differences of L(O3) when one
+    particle moves (as evaluation point and source; its leaf unchanged), depth 3, p = 12."""
+    r = rng(73)
+    n = 80
+    xy = r.random((n, 2))
+    g = r.standard_normal(n)
+    ustar = r.standard_normal((n, 2))
+    sigma, depth, p, root = 0.05, 3, 12, (0.0, 0.0, 1.0)
+
+    def loss(x):
+        u = oracle_mod.fmm_velocity(x, g, sigma, depth, p, root)
+        return 0.5 * ((u - ustar) ** 2).sum()
+
+    u = oracle_mod.fmm_velocity(xy, g, sigma, depth, p, root)
+    _, de, ds = oracle_mod.fmm_grad_full(xy, g, sigma, depth, p, u - ustar, root)
+    tot = de + ds
+    h = 1e-6
+    checked = 0
+    for k in range(n):
+        frac = (xy[k] * 8) % 1.0
+        if np.any(frac < 0.01) or np.any(frac > 0.99):
+            continue  # a step must not move the particle to another leaf
+        for comp in (0, 1):
+            a, b = xy.copy(), xy.copy()
+            a[k, comp] += h
+            b[k, comp] -= h
+            fd = (loss(a) - loss(b)) / (2 * h)
+            assert abs(fd - tot[k, comp]) <= 1e-5 * abs(fd) + 1e-8, (k, comp, fd, tot[k, comp])
+        checked += 1
+        if checked == 12:
+            break
+    assert checked == 12
+
+
+def test_fmm_total_gradient_tends_to_direct(oracle_mod):
+    """With sigma small against the leaf (the far field's kernel substitution then changes
+    nothing) and p = 30, the O3 gradients equal the O1 ones to truncation error."""
+    r = rng(74)
+    n = 80
+    xy = r.random((n, 2))
+    g = r.standard_normal(n)
+    ustar = r.standard_normal((n, 2))
+    sigma = 0.125 / 25
+    u = oracle_mod.direct(xy, g, sigma)
+    dg1, dx1 = oracle_mod.direct_grad(xy, g, sigma, u - ustar)
+    dg3, de, ds = oracle_mod.fmm_grad_full(xy, g, sigma, 3, 30, u - ustar, (0.0, 0.0, 1.0))
+    assert np.linalg.norm(de + ds - dx1) < 1e-10 * np.linalg.norm(dx1)
+    assert np.linalg.norm(dg3 - dg1) < 1e-10 * np.linalg.norm(dg1)
+
+
+def test_self_term_cancels_for_a_moving_particle(oracle_mod):
+    """A lone particle: its blob's slope at its own centre enters dL/dx_eval and, with the
+    opposite sign, dL/dx_src; a particle moving as a whole feels no self-velocity."""
+    xy = np.array([[0.3, 0.4]])
+    _, de, ds = oracle_mod.fmm_grad_full(xy, np.array([1.3]), 0.05, 3, 10, np.array([[0.7, -0.2]]), (0, 0, 1))
+    assert np.abs(de).max() > 1.0
+    assert np.array_equal(de, -ds)
