@@ -156,14 +156,19 @@ int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p,
  *   dl_dxeval  device, (n, 2) FP64: derivative with respect to the evaluation
  *              positions with the sources held fixed: near part from the derivative of
  *              eq. regB-S2DGau (the particle's own blob included, slope 1/(4 pi sigma^2)),
- *              far part from the derivative of the local expansion.
- * Either output may be NULL to skip it.  Other arguments as fmm_velocity.  The paper
- * has no backward pass; this is the transpose of the discrete operator defined by
- * stages 4-10.
+ *              far part from the derivative of the local expansion;
+ *   dl_dxsrc   device, (n, 2) FP64: derivative with respect to the source positions with
+ *              the evaluation points held fixed: near part minus the pair derivatives
+ *              seen from the sources (own blob included, with the opposite sign), far part
+ *              -Re(c_j Phi'_j), Im(c_j Phi'_j), Phi' the derivative of the q-field's local
+ *              expansion.  A particle moving as a whole (source and evaluation point, its
+ *              leaf unchanged) has dL/dx = dl_dxeval + dl_dxsrc.
+ * Any output may be NULL to skip it.  Other arguments as fmm_velocity.  The paper has no
+ * backward pass; this is the transpose of the discrete operator defined by stages 4-10.
  */
 int fmm_velocity_backward(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
                           const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
-                          double *dl_dxeval);
+                          double *dl_dxeval, double *dl_dxsrc);
 
 /* The near-field plan (stage 9) in force (any pointer may be NULL):
  *   mutual_items  wavefront items of the mutual form (0 when it is off or finds no

@@ -26,7 +26,7 @@ SIGNATURES = {
     "fmm_tree_permutation": (_I, [_P, _P, _P, _P]),
     "fmm_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
-    "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P]),
+    "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fmm_set_option": (_I, [_P, _I, _I64]),
     "fmm_get_timings": (_I, [_P, _P, _P]),
     "fmm_near_plan_info": (_I, [_P, _P, _P, _P]),

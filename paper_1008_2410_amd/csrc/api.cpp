@@ -87,6 +87,7 @@ void free_workspace(Workspace &ws)
     hipFree(ws.lo2_f);
     hipFree(ws.rec2);
     hipFree(ws.slots);
+    hipFree(ws.bwd_src);
     ws = Workspace{};
 }
 
@@ -270,6 +271,7 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
         ws.precision = precision;
         ws.split = split;
     }
+    if (backward && !ws.bwd_src && (rc = dev_alloc(&ws.bwd_src, n, "adjoint source-position sums"))) return rc;
     if (backward && !ws.adj) {
         if ((rc = dev_alloc(&ws.adj, n, "adjoint charges"))) return rc;
         if ((rc = dev_alloc(&ws.bwd_near, n, "adjoint near field"))) return rc;
@@ -732,13 +734,13 @@ extern "C" int fmm_velocity_parts(fmm_tree *t, const double *gamma, double sigma
 
 extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
                                      const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
-                                     double *dl_dxeval)
+                                     double *dl_dxeval, double *dl_dxsrc)
 {
     g_last_error.clear();
     int rc = check_eval_args(t, gamma, sigma, p, precision);
     if (rc) return rc;
     if (!dl_duv) return fail(FMM_EINVAL, "dl_duv is NULL");
-    if (!dl_dgamma && !dl_dxeval) return FMM_OK;
+    if (!dl_dgamma && !dl_dxeval && !dl_dxsrc) return FMM_OK;
     BusyGuard guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
@@ -773,11 +775,12 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
     launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
-                        ws.bwd_b, near_waves(t), ms);
+                        ws.bwd_b, dl_dxsrc ? ws.bwd_src : nullptr, near_waves(t), ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, is_double, alpha, dl_dgamma, dl_dxeval, ms);
+    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, dl_dgamma,
+                             dl_dxeval, dl_dxsrc, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);

@@ -100,6 +100,7 @@ struct Workspace {
     float2 *mp2_f = nullptr, *lo2_f = nullptr;
     void *rec2 = nullptr;         // adjoint charges q in FP32 for the mixed near field
     void *slots = nullptr;        // mutual near field: 9 x n sums (float2 or double2)
+    double4 *bwd_src = nullptr;   // per sorted particle: near sums of the source-position terms
 };
 
 }  // namespace fmm
@@ -188,10 +189,10 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,
                          hipStream_t s);
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, int near_waves, hipStream_t s);
+                         double4 *out_pa, double *out_b, double4 *out_src, int near_waves, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
-                              const double *near_b, const double2 *adj, int is_double, double alpha,
-                              double *dl_dgamma, double *dl_dxeval, hipStream_t s);
+                              const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
+                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, hipStream_t s);
 
 // Tables (host generation + upload), kernels.hip
 int upload_tables(Tables &tb, int p, std::string &err);

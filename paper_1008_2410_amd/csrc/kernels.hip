@@ -1337,10 +1337,13 @@ template <typename T> __device__ __forceinline__ T series_cut();
 template <> __device__ __forceinline__ float series_cut<float>() { return 0.125f; }
 template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3; }
 
-template <typename T, bool FAR>
-__device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda, T &fpr, T &fpi,
-                                             T &far_r, T &far_i, T &fb)
+// acc: Phi (2), A (2), B; with SRC also the source-position sums with the adjoint
+// charges, At = sum q_j conj(dz')^2 (lambda e s' - g)/s'^2 (2) and Bt = sum q_j e (2).
+template <typename T, bool FAR, bool SRC>
+__device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda,
+                                             T (&acc)[SRC ? 9 : 5])
 {
+    T &fpr = acc[0], &fpi = acc[1], &far_r = acc[2], &far_i = acc[3], &fb = acc[4];
     const T ddx = tx - rj.x;
     const T ddy = ty - rj.y;
     const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
@@ -1366,6 +1369,10 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
                 fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
         }
         fb = fma(rj.z, e, fb);  // B: Gamma_j e
+        if constexpr (SRC) {
+            acc[7] = fma(qj.x, e, acc[7]);
+            acc[8] = fma(qj.y, e, acc[8]);
+        }
     }
     // Phi: q_j (g/s') conj(dz')
     const T cx = gr * ddx, cy = -gr * ddy;
@@ -1379,42 +1386,49 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
     const T zi = (T)-2 * ddx * ddy;
     far_r = fma(hg, zr, far_r);
     far_i = fma(hg, zi, far_i);
+    if constexpr (SRC) {
+        const T wr = h * zr, wi = h * zi;
+        acc[5] = fma(qj.x, wr, acc[5]);
+        acc[5] = fma(-qj.y, wi, acc[5]);
+        acc[6] = fma(qj.x, wi, acc[6]);
+        acc[6] = fma(qj.y, wr, acc[6]);
+    }
 }
 
-template <typename T, int K, bool FAR>
+template <typename T, int K, bool FAR, bool SRC>
 __device__ __forceinline__ void p2p_bwd_tile(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
-                                             T lambda, T (&acc)[5])
+                                             T lambda, T (&acc)[SRC ? 9 : 5])
 {
     if (len == 64) {
 #pragma unroll 4
         for (int it = 0; it < 64 / K; ++it)
-            p2p_bwd_pair<T, FAR>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc[0], acc[1], acc[2], acc[3],
-                                 acc[4]);
+            p2p_bwd_pair<T, FAR, SRC>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc);
     } else {
-        for (int j = k; j < len; j += K)
-            p2p_bwd_pair<T, FAR>(tile[j], qtile[j], tx, ty, lambda, acc[0], acc[1], acc[2], acc[3], acc[4]);
+        for (int j = k; j < len; j += K) p2p_bwd_pair<T, FAR, SRC>(tile[j], qtile[j], tx, ty, lambda, acc);
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, bool SRC>
 __device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
-                                                 T lambda, T (&acc)[5], bool far)
+                                                 T lambda, T (&acc)[SRC ? 9 : 5], bool far)
 {
-    if (far) p2p_bwd_tile<T, K, true>(tile, qtile, len, k, tx, ty, lambda, acc);
-    else p2p_bwd_tile<T, K, false>(tile, qtile, len, k, tx, ty, lambda, acc);
+    if (far) p2p_bwd_tile<T, K, true, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
+    else p2p_bwd_tile<T, K, false, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
 }
 
 // Adjoint near field of one work unit, organised as the forward P2P (LDS tiles,
-// exponential skipped on far tiles).
-template <typename T>
+// exponential skipped on far tiles).  With SRC the source-position sums (At, Bt) go to
+// out_src.
+template <typename T, bool SRC>
 __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, c2<T> *qtile,
                                                   const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qv,
                                                   const int *__restrict__ leaf_start,
                                                   const int *__restrict__ tile_start,
                                                   const float4 *__restrict__ tile_box, int nside, T step,
                                                   float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
-                                                  double *__restrict__ out_b)
+                                                  double *__restrict__ out_b, double4 *__restrict__ out_src)
 {
+    constexpr int NA = SRC ? 9 : 5;
     const int lane = threadIdx.x;
     const int logtp = u.w;
     const int tp = 1 << logtp;
@@ -1424,7 +1438,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
     const rec_t<T> ri = rec[i];
     const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
     const float4 tbox = tile_box[tile_start[u.x] + ((u.y - leaf_start[u.x]) >> 6)];
-    double sum[5] = {0, 0, 0, 0, 0};
+    double sum[NA] = {};
     for (int dy = -1; dy <= 1; ++dy) {
         const int ny = iy + dy;
         if (ny < 0 || ny >= nside) continue;
@@ -1435,7 +1449,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
             const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
             const T tx = ri.x - (T)dx * step;
             const T ty = ri.y - (T)dy * step;
-            T acc[5] = {0, 0, 0, 0, 0};
+            T acc[NA] = {};
             int tt = tile_start[S];
             for (int base = s0; base < s1; base += 64, ++tt) {
                 const int len = min(64, s1 - base);
@@ -1447,25 +1461,26 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
                 const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
                 __syncthreads();
                 switch (logtp) {
-                case 6: p2p_bwd_tile_any<T, 1>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 5: p2p_bwd_tile_any<T, 2>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 4: p2p_bwd_tile_any<T, 4>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 3: p2p_bwd_tile_any<T, 8>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 2: p2p_bwd_tile_any<T, 16>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 1: p2p_bwd_tile_any<T, 32>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                default: p2p_bwd_tile_any<T, 64>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
                 }
             }
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sum[c] += (double)acc[c];
+            for (int c = 0; c < NA; ++c) sum[c] += (double)acc[c];
         }
     }
     for (int o = tp; o < 64; o <<= 1)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sum[c] += __shfl_xor(sum[c], o);
+        for (int c = 0; c < NA; ++c) sum[c] += __shfl_xor(sum[c], o);
     if (k == 0 && t < u.z) {
         out_pa[i] = make_double4(sum[0], sum[1], sum[2], sum[3]);
         out_b[i] = sum[4];
+        if constexpr (SRC) out_src[i] = make_double4(sum[5], sum[6], sum[7], sum[8]);
     }
 }
 
@@ -1474,7 +1489,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
 // are small, so the batch hides the atomic's latency).
 constexpr int kNearBatch = 4;
 
-template <typename T>
+template <typename T, bool SRC>
 __global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
                                                            int *__restrict__ work_ctr,
                                                            const rec_t<T> *__restrict__ rec,
@@ -1483,13 +1498,13 @@ __global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict
                                                            const int *__restrict__ tile_start,
                                                            const float4 *__restrict__ tile_box, int nside, T step,
                                                            float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
-                                                           double *__restrict__ out_b)
+                                                           double *__restrict__ out_b, double4 *__restrict__ out_src)
 {
     __shared__ rec_t<T> tile[64];
     __shared__ c2<T> qtile[64];
     if (!persistent) {
-        p2p_backward_unit<T>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
-                             cut_leaf2, lambda, out_pa, out_b);
+        p2p_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside,
+                                  step, cut_leaf2, lambda, out_pa, out_b, out_src);
         return;
     }
     for (;;) {
@@ -1499,19 +1514,27 @@ __global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict
         if (first >= nunits) break;
         const int last = min(first + kNearBatch, nunits);
         for (int cur = first; cur < last; ++cur)
-            p2p_backward_unit<T>(units[cur], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
-                                 cut_leaf2, lambda, out_pa, out_b);
+            p2p_backward_unit<T, SRC>(units[cur], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside,
+                                      step, cut_leaf2, lambda, out_pa, out_b, out_src);
     }
 }
 
 // Adjoint finalize: far parts from the q-field locals (Phi_far, by L2P) and the c-field
 // locals (W'_far = (1/w^2) sum_l l b_l xi^(l-1)), combined with the near sums.
+// Source positions (near_src != NULL): with c = -i Gamma/(2 pi),
+//   At = alpha^2 (near sum) + Phi'_far,  Bt = alpha^2 lambda (near sum),
+//   dL/dx_src = -Re(c (At + Bt)),  dL/dy_src = Im(c (At - Bt)),
+// Phi'_far = (1/w^2) sum_l l b_l(q) xi^(l-1) the derivative of the q-field's local
+// expansion (the far operator is antisymmetric).  gamma_st[gpos2[i]] is Gamma of
+// sorted particle i (the staged circulations).
 template <typename TL>
 __global__ __launch_bounds__(256) void finalize_backward_kernel(
     int n, const int *__restrict__ perm, const int *__restrict__ leaf_of, const double2 *__restrict__ xy,
     const double4 *__restrict__ near_pa, const double *__restrict__ near_b, const double2 *__restrict__ adj,
     const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, int p, int has_far, double x0, double y0,
-    double w, double alpha, double lambda, double *__restrict__ dl_dgamma, double *__restrict__ dl_dxeval)
+    double w, double alpha, double lambda, double *__restrict__ dl_dgamma, double *__restrict__ dl_dxeval,
+    const double4 *__restrict__ near_src, const int *__restrict__ gpos2, const double *__restrict__ gamma_st,
+    double *__restrict__ dl_dxsrc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1522,7 +1545,7 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
     // A = -i ka (a.z + i a.w) = ka (a.w, -a.z);  B = -i ka lambda sb
     double Ar = ka * a.w, Ai = -ka * a.z;
     const double Bi = -ka * lambda * sb;
-    double dwr = 0.0, dwi = 0.0;
+    double dwr = 0.0, dwi = 0.0, dpr = 0.0, dpi = 0.0;
     if (has_far) {
         const uint32_t leaf = (uint32_t)leaf_of[i];
         const double cx = x0 + (morton_x(leaf) + 0.5) * w;
@@ -1542,6 +1565,15 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
             }
             dwr = (double)accd.x / (w * w);
             dwi = (double)accd.y / (w * w);
+            if (near_src) {
+                c2<TL> accp = mk<TL>((TL)(p - 1) * bq[p - 1].x, (TL)(p - 1) * bq[p - 1].y);
+                for (int l = p - 2; l >= 1; --l) {
+                    const c2<TL> t = mk<TL>((TL)l * bq[l].x, (TL)l * bq[l].y);
+                    accp = cmac<TL>(t, accp, xi);
+                }
+                dpr = (double)accp.x / (w * w);
+                dpi = (double)accp.y / (w * w);
+            }
         }
     }
     const int64_t o = perm[i];
@@ -1553,6 +1585,15 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
         const double d2r = Ar + dwr, d2i = Ai - Bi + dwi;
         dl_dxeval[2 * o] = q.x * d1r - q.y * d1i;
         dl_dxeval[2 * o + 1] = -(q.x * d2i + q.y * d2r);
+    }
+    if (near_src) {
+        const double4 ns = near_src[i];
+        const double a2 = alpha * alpha;
+        const double atr = a2 * ns.x + dpr, ati = a2 * ns.y + dpi;
+        const double btr = a2 * lambda * ns.z, bti = a2 * lambda * ns.w;
+        const double G = gamma_st[gpos2[i]] * kInv2Pi;  // c = -i G: Re(c w) = G Im w, Im(c w) = -G Re w
+        dl_dxsrc[2 * o] = -G * (ati + bti);
+        dl_dxsrc[2 * o + 1] = -G * (atr - btr);
     }
 }
 
@@ -1753,7 +1794,7 @@ void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, 
 }
 
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, int near_waves, hipStream_t s)
+                         double4 *out_pa, double *out_b, double4 *out_src, int near_waves, hipStream_t s)
 {
     if (t->nunits == 0) return;
     const int nside = 1 << t->depth;
@@ -1763,21 +1804,33 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
     const float cut_leaf2 = (float)(cut / (step * step));
     const int persistent = near_waves > 0 && near_waves < t->nunits;
     const unsigned grid = (unsigned)(persistent ? near_waves : t->nunits);
-    if (is_double)
-        p2p_backward_kernel<double><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
-                                                         (const double4 *)rec, (const double2 *)qv, t->d_leaf_start,
-                                                         t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0,
-                                                         out_pa, out_b);
-    else
-        p2p_backward_kernel<float><<<grid, 64, 0, s>>>(t->d_units, (int)t->nunits, persistent, t->d_work,
-                                                        (const float4 *)rec, (const float2 *)qv, t->d_leaf_start,
-                                                        t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2,
-                                                        (float)0.69314718055994530942, out_pa, out_b);
+    const float ln2 = (float)0.69314718055994530942;
+    if (is_double) {
+        if (out_src)
+            p2p_backward_kernel<double, true><<<grid, 64, 0, s>>>(
+                t->d_units, (int)t->nunits, persistent, t->d_work, (const double4 *)rec, (const double2 *)qv,
+                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, out_src);
+        else
+            p2p_backward_kernel<double, false><<<grid, 64, 0, s>>>(
+                t->d_units, (int)t->nunits, persistent, t->d_work, (const double4 *)rec, (const double2 *)qv,
+                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, nullptr);
+    } else {
+        if (out_src)
+            p2p_backward_kernel<float, true><<<grid, 64, 0, s>>>(
+                t->d_units, (int)t->nunits, persistent, t->d_work, (const float4 *)rec, (const float2 *)qv,
+                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
+                out_src);
+        else
+            p2p_backward_kernel<float, false><<<grid, 64, 0, s>>>(
+                t->d_units, (int)t->nunits, persistent, t->d_work, (const float4 *)rec, (const float2 *)qv,
+                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
+                nullptr);
+    }
 }
 
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
-                              const double *near_b, const double2 *adj, int is_double, double alpha,
-                              double *dl_dgamma, double *dl_dxeval, hipStream_t s)
+                              const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
+                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, hipStream_t s)
 {
     const int L = t->depth;
     const int n = (int)t->n;
@@ -1788,11 +1841,13 @@ void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArg
         finalize_backward_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj,
             has_far ? level_ptr<double>(fc, L, true) : nullptr, has_far ? level_ptr<double>(fq, L, true) : nullptr,
-            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval);
+            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval, dl_dxsrc ? near_src : nullptr,
+            t->d_gpos2, t->d_st1, dl_dxsrc);
     else
         finalize_backward_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj, level_ptr<float>(fc, L, true),
-            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval);
+            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval,
+            dl_dxsrc ? near_src : nullptr, t->d_gpos2, t->d_st1, dl_dxsrc);
 }
 
 }  // namespace fmm

@@ -143,24 +143,28 @@ class Tree:
         return near, far
 
     def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
-                          need_gamma: bool = True, need_x: bool = True):
-        """(dL/dGamma (n,) or None, dL/dx_eval (n, 2) or None) for a loss with gradient dl_duv."""
+                          need_gamma: bool = True, need_x: bool = True, need_src: bool = False):
+        """(dL/dGamma (n,) or None, dL/dx_eval (n, 2) or None) for a loss with gradient dl_duv;
+        with need_src a third entry, dL/dx_src (n, 2), the derivative with respect to the source
+        positions.  A particle moving as a whole has dL/dx = dL/dx_eval + dL/dx_src."""
         g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
         d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
         dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if need_gamma else None
         dx = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_x else None
+        ds = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_src else None
         with torch.cuda.device(self.device):
             L.check(L.load().fmm_velocity_backward(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
-                                                   _ptr(d), _stream_ptr(), None, _ptr(dg), _ptr(dx)),
+                                                   _ptr(d), _stream_ptr(), None, _ptr(dg), _ptr(dx), _ptr(ds)),
                     "fmm_velocity_backward")
-        return dg, dx
+        return (dg, dx, ds) if need_src else (dg, dx)
 
 
 class VelocityFn(torch.autograd.Function):
     """u = FMM velocity of the particles of `tree` with circulations gamma.
 
-    Backward returns dL/dGamma and dL/dxy where dL/dxy is the derivative with
-    respect to the evaluation positions (the source positions held fixed)."""
+    Backward returns dL/dGamma and dL/dxy, the derivative with respect to the particle
+    positions, each particle moving both as evaluation point and as source
+    (dL/dx_eval + dL/dx_src); the tree's cells are held fixed."""
 
     @staticmethod
     def forward(ctx, xy, gamma, tree: Tree, sigma: float, p: int, precision="mixed"):
@@ -175,9 +179,10 @@ class VelocityFn(torch.autograd.Function):
         need_x, need_g = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_x or need_g):
             return None, None, None, None, None, None
-        dg, dx = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision,
-                                            grad_uv.contiguous(), need_gamma=need_g, need_x=need_x)
-        return dx, dg, None, None, None, None
+        dg, dx, ds = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision,
+                                                grad_uv.contiguous(), need_gamma=need_g, need_x=need_x,
+                                                need_src=need_x)
+        return (dx + ds if need_x else None), dg, None, None, None, None
 
 
 def velocity(xy: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, precision="mixed",

@@ -1,10 +1,11 @@
-"""GPU parity of the adjoint (fmm_velocity_backward) against the CPU oracle's O4.
+"""GPU parity of the adjoint (fmm_velocity_backward) against the CPU oracle's O4 and O5.
 
 Bars: FP64 form within 1e-9 (vector rel-L2) of the oracle gradient; mixed form
 within 1e-4; both against central finite differences of the FP64 forward where the
-forward API can evaluate them (circulations; the evaluation-position derivative is
-checked against the oracle, whose own position derivative is pinned by finite
-differences in the oracle tests).
+forward API can evaluate them (circulations, and positions with every particle
+moving as source and evaluation point; the split into evaluation-position and
+source-position parts is checked against the oracle, whose parts are pinned by
+finite differences in the oracle tests).
 """
 import numpy as np
 import pytest
@@ -33,10 +34,62 @@ def test_backward_matches_oracle(fmm_mod, oracle_mod, precision, tol, n, depth, 
     ustar = W.smooth_target_field(w.xy, seed=7)
     uv = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box)
     dl = uv - ustar
-    dg_ref, dx_ref = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
-    dg, dx = _grads(fmm_mod, w, dl, precision)
+    dg_ref, dx_ref, ds_ref = oracle_mod.fmm_grad_full(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    dg, dx, ds = (a.cpu().numpy() for a in tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl),
+                                                                  need_src=True))
     assert rel_l2(dg, dg_ref) < tol
     assert rel_l2(dx, dx_ref) < tol
+    assert rel_l2(ds, ds_ref) < tol
+    # the default call (no source-position output) gives the same bits for the rest
+    dg2, dx2 = _grads(fmm_mod, w, dl, precision, tree=tree)
+    assert np.array_equal(dg, dg2) and np.array_equal(dx, dx2)
+
+
+def test_position_gradient_central_differences_on_gpu(fmm_mod):
+    """Every particle moving as source and evaluation point: dL/dx_eval + dL/dx_src against
+    central differences of L through the GPU FP64 forward (tree rebuilt at each point, the
+    moved particle's leaf unchanged)."""
+    w = W.uniform_lamb_oseen(n=3000, seed=78, depth=4, p=14)
+    ustar = W.smooth_target_field(w.xy, seed=9)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    uv = tree.velocity(_t(w.gamma), w.sigma, w.p, "fp64").cpu().numpy()
+    _, dx, ds = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, "fp64", _t(uv - ustar), need_src=True)
+    tot = (dx + ds).cpu().numpy()
+
+    def loss(xy):
+        t = fmm_mod.Tree(_t(xy), w.depth, w.root_box)
+        u = t.velocity(_t(w.gamma), w.sigma, w.p, "fp64").cpu().numpy()
+        return 0.5 * ((u - ustar) ** 2).sum()
+
+    h = 1e-6
+    checked = 0
+    for k in np.random.Generator(np.random.PCG64(4)).permutation(w.n):
+        frac = (w.xy[k] * 16) % 1.0
+        if np.any(frac < 0.01) or np.any(frac > 0.99):
+            continue
+        for comp in (0, 1):
+            a, b = w.xy.copy(), w.xy.copy()
+            a[k, comp] += h
+            b[k, comp] -= h
+            fd = (loss(a) - loss(b)) / (2 * h)
+            assert abs(fd - tot[k, comp]) <= 1e-5 * abs(fd) + 1e-9, (k, comp, fd, tot[k, comp])
+        checked += 1
+        if checked == 4:
+            break
+    assert checked == 4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lone_particle_has_no_net_position_gradient(fmm_mod, precision):
+    """The blob's own slope enters dL/dx_eval and, with the opposite sign, dL/dx_src."""
+    w = W.Workload("one", np.array([[0.3, 0.4]]), np.array([1.3]), 0.05, 3, 10, (0, 0, 1), "fp64")
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    _, dx, ds = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(np.array([[0.7, -0.2]])),
+                                       need_src=True)
+    dx, ds = dx.cpu().numpy(), ds.cpu().numpy()
+    assert np.abs(dx).max() > 1.0
+    assert np.abs(dx + ds).max() <= (1e-12 if precision == "fp64" else 1e-6) * np.abs(dx).max()
 
 
 def test_gamma_gradient_central_differences_on_gpu(fmm_mod):
@@ -89,9 +142,9 @@ def test_autograd_function(fmm_mod, oracle_mod):
     loss = 0.5 * ((uv - ustar) ** 2).sum()
     loss.backward()
     dl = (uv - ustar).detach().cpu().numpy()
-    dg_ref, dx_ref = oracle_mod.fmm_grad(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    dg_ref, dx_ref, ds_ref = oracle_mod.fmm_grad_full(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
     assert rel_l2(g.grad.cpu().numpy(), dg_ref) < 1e-9
-    assert rel_l2(xy.grad.cpu().numpy(), dx_ref) < 1e-9
+    assert rel_l2(xy.grad.cpu().numpy(), dx_ref + ds_ref) < 1e-9
 
 
 def test_backward_deterministic(fmm_mod):
