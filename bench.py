@@ -75,6 +75,58 @@ def cpu_baseline_leg(w, sample_frac_log4=1):
     }
 
 
+def rk2_leg(torch, dev, workloads):
+    """Time-stepped workload: forward transport and its discrete adjoint (per-step
+    checkpoints), with tree builds, velocity evaluations and adjoint calls timed
+    separately, and the peak of device memory in use (hipMemGetInfo, all allocations)."""
+    from paper_1008_2410_amd import fmm, rk2
+    t0 = time.perf_counter()
+    w = workloads.transport_patches()
+    dt, steps = w.extra["dt"], w.extra["steps"]
+    target = workloads.smooth_target_field(w.xy, seed=55)
+    log(f"[bench] transport workload: N={w.n} depth={w.depth} p={w.p} dt={dt} steps={steps} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    xy = torch.from_numpy(w.xy).to(dev)
+    gamma = torch.from_numpy(w.gamma).to(dev)
+    tgt = torch.from_numpy(target).to(dev)
+    # warm-up: one evaluation (library load, tables, first-use allocations)
+    tree = fmm.Tree(xy, w.depth, None)
+    tree.velocity(gamma, w.sigma, w.p, "mixed")
+    tree.close()
+    del tree
+    torch.cuda.synchronize()
+    sf = rk2.RK2Stats()
+    t0 = time.perf_counter()
+    xN, ck = rk2.rk2_forward(xy, gamma, w.sigma, w.depth, w.p, dt, steps, "mixed", None, sf)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"[bench] rk2 forward {t_fwd:.2f} s: tree builds {sf.tree_build:.2f} s, velocities {sf.velocity:.3f} s "
+        f"({sf.evals} evaluations)")
+    sb = rk2.RK2Stats()
+    t0 = time.perf_counter()
+    dx0, dg = rk2.rk2_backward(ck, gamma, w.sigma, w.depth, w.p, dt, xN - tgt, "mixed", None, sb)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    log(f"[bench] rk2 adjoint {t_bwd:.2f} s: tree builds {sb.tree_build:.2f} s, velocities {sb.velocity:.3f} s, "
+        f"adjoint calls {sb.backward:.3f} s ({sb.vjps})")
+    peak = max(sf.peak_bytes, sb.peak_bytes)
+    evals = sf.evals
+    print(json.dumps({
+        "workload": "transport_patches", "n": w.n, "depth": w.depth, "p": w.p, "dt": dt, "steps": steps,
+        "precision": "mixed", "fwd_s": round(t_fwd, 3), "bwd_s": round(t_bwd, 3),
+        "fwd_tree_build_s": round(sf.tree_build, 3), "fwd_velocity_s": round(sf.velocity, 4),
+        "velocity_ms_per_eval": round(sf.velocity / evals * 1e3, 3),
+        "velocity_mparticles_per_s": round(w.n * evals / sf.velocity / 1e6, 1),
+        "tree_build_ms_per_eval": round(sf.tree_build / evals * 1e3, 2),
+        "bwd_tree_build_s": round(sb.tree_build, 3), "bwd_recompute_velocity_s": round(sb.velocity, 4),
+        "bwd_adjoint_s": round(sb.backward, 4),
+        "adjoint_ms_per_vjp": round(sb.backward / sb.vjps * 1e3, 3),
+        "bwd_fwd_device": round(sb.backward / sf.velocity, 3),
+        "peak_hbm_gb": round(peak / 1e9, 2),
+        "grad_norms": {"x0": float(torch.linalg.norm(dx0)), "gamma": float(torch.linalg.norm(dg))},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +141,9 @@ def main():
                     help="only the timed headline region (for kernel profiling of exactly that work)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a device-to-device copy of MIB MiB ten times (HBM counter calibration)")
+    ap.add_argument("--rk2", action="store_true",
+                    help="only the time-stepped workload (2^25 particles, 16 patches, 5 midpoint-RK2 steps, trees "
+                         "rebuilt per evaluation): forward and adjoint, one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -107,6 +162,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 10}), flush=True)
+        return
+    if args.rk2:
+        rk2_leg(torch, dev, workloads)
         return
     t0 = time.perf_counter()
     w = workloads.gaussian_patches(n=args.n, depth=args.depth)

@@ -137,6 +137,19 @@ def gaussian_patches(n: int = 1 << 24, n_patches: int = 8, seed: int = 3, depth:
                      "peaks": peaks})
 
 
+def transport_patches(n: int = 1 << 25, n_patches: int = 16, seed: int = 5, depth: int = 11, p: int = 16,
+                      sigma: float = 0.01 / 64, dt: float = 1e-3, steps: int = 5,
+                      precision: str = "mixed") -> Workload:
+    """The time-stepped workload: Gaussian patches (as gaussian_patches) advected by
+    `steps` midpoint-RK2 steps of size dt, every velocity an FMM evaluation over a tree
+    rebuilt for the current positions (bounding square).  extra["dt"], extra["steps"];
+    extra["target"] is a seeded target field for a loss L = 0.5 |x_N - target|^2."""
+    w = gaussian_patches(n=n, n_patches=n_patches, seed=seed, depth=depth, p=p, sigma=sigma, precision=precision)
+    w.name = "transport_patches"
+    w.extra.update(dt=dt, steps=steps)
+    return w
+
+
 def smooth_target_field(xy: np.ndarray, seed: int = 44, n_modes: int = 16) -> np.ndarray:
     """u* = (d psi/dy, -d psi/dx) of the random stream function
     psi = sum_m A_m cos(2 pi k_m . x + phi_m), k_m in Z^2 with 1 <= |k_m|_inf <= 3,
