@@ -101,13 +101,21 @@ enum {
  *   stream    stream on which xy is valid.
  *   out       receives the handle; free it with fmm_destroy_tree.
  * Leaf of a particle: (min(floor((x - x0)/w), 2^L - 1), same for y), w = side/2^L;
- * a particle outside [x0, x0 + side]^2 gives FMM_ERANGE, a non-finite one FMM_EINVAL.
- * The build runs on the host (the positions are copied down once) and synchronises
- * `stream`; the tree owns its device buffers, and workspace for each (p, precision)
- * is allocated on first use and kept until fmm_destroy_tree.
+ * a particle outside [x0, x0 + side]^2 gives FMM_ERANGE, a non-finite one FMM_EINVAL
+ * (the message names the lowest offending index).
+ * The build runs on the device (binning, a stable radix sort by leaf and sub-leaf
+ * Morton key, leaf offsets, cell lists, work lists) and synchronises `stream`; the tree
+ * owns its device buffers, and workspace for each (p, precision) is allocated on first
+ * use and kept until fmm_destroy_tree.
  */
 int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
                    fmm_tree **out);
+
+/* The same tree built on the host (positions copied down once, the arrays uploaded):
+ * the reference that the device build is checked against.  Arguments and results as
+ * fmm_build_tree; the two trees are identical array for array. */
+int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                        fmm_tree **out);
 
 /* Host-side facts about a tree (any pointer may be NULL):
  *   n, depth, root_box[3] (host);

@@ -22,6 +22,7 @@ _I64 = ctypes.c_int64
 _D = ctypes.c_double
 SIGNATURES = {
     "fmm_build_tree": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fmm_build_tree_host": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_tree_info": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "fmm_tree_permutation": (_I, [_P, _P, _P, _P]),
     "fmm_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),

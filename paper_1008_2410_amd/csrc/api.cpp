@@ -118,114 +118,6 @@ void free_tree(fmm_tree *t)
     delete t;
 }
 
-// Near-field plan of the mutual form (stage 9).  A leaf is dense when it holds at least
-// dense_leaf particles.  Every unordered pair of neighbouring dense leaves, and every
-// dense leaf with itself, is one mutual item; every other ordered (target leaf, source
-// leaf) pair is evaluated by the target-centric units, whose flag makes dense target
-// leaves skip their dense neighbours.  leaf_mask[leaf]: bit d (direction d = 3(dy+1) +
-// (dx+1) of a neighbour) when the particles' slot d is written, bit 9 when a
-// target-centric unit writes their near-field sum.  With the mutual form off the plan
-// is empty and the target-centric units cover every pair.
-int build_near_plan(fmm_tree *t)
-{
-    hipFree(t->d_near_work);
-    hipFree(t->d_leaf_mask);
-    t->d_near_work = nullptr;
-    t->d_leaf_mask = nullptr;
-    t->nunits_tc = t->nmut = t->nnear_work = t->mutual_pairs = 0;
-    if (!t->near_mutual) return FMM_OK;
-    const int L = t->depth;
-    const int nside = 1 << L;
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    const std::vector<int> &ls = t->h_leaf_start;
-    const int D = t->dense_leaf;
-    auto count = [&](int x, int y) -> int {
-        if (x < 0 || y < 0 || x >= nside || y >= nside) return 0;
-        const uint32_t c = morton_encode((uint32_t)x, (uint32_t)y);
-        return ls[c + 1] - ls[c];
-    };
-    // Estimated cost in wavefront steps weighted by their cycles (a mutual step of 64
-    // pairs x 2 ends ~ 3, a target-centric step ~ 2).  Tiles of a leaf: f full ones of 64
-    // and a last one of r < 64; a block of tiles costs 16 steps per chunk of 16 of the
-    // smaller tile (the larger one sits in the lanes).
-    auto nch = [](int len) -> int64_t { return (len + 15) >> 4; };
-    auto block_steps = [&](int cs, int cr) -> int64_t {
-        const int64_t fs = cs / 64, fr = cr / 64;
-        const int rs = cs % 64, rr = cr % 64;
-        return 16 * (fs * fr * 4 + fs * nch(rr) + fr * nch(rs) + std::min(nch(rs), nch(rr)));
-    };
-    auto self_steps = [&](int c, int64_t &diag) -> int64_t {
-        const int64_t f = c / 64;
-        const int r = c % 64;
-        diag = 16 * (f * 4 + nch(r));
-        return 16 * (f * (f - 1) / 2 * 4 + f * nch(r));
-    };
-    std::vector<int4> work;
-    std::vector<int64_t> cost;
-    std::vector<uint16_t> mask((size_t)nleaf, 0);
-    int64_t mpairs = 0, nunits = 0, nitems = 0;
-    static const int up[4][2] = {{1, 0}, {-1, 1}, {0, 1}, {1, 1}};
-    for (int64_t c = 0; c < nleaf; ++c) {
-        const int nt = ls[c + 1] - ls[c];
-        if (nt == 0) continue;
-        const int x = (int)morton_x((uint32_t)c), y = (int)morton_y((uint32_t)c);
-        const bool dense = nt >= D;
-        int64_t nsrc = 0;
-        uint16_t m = 0;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int ns = count(x + dx, y + dy);
-                if (ns == 0) continue;
-                if (dense && ns >= D) m |= (uint16_t)(1u << (3 * (dy + 1) + (dx + 1)));
-                else nsrc += ns;
-            }
-        if (nsrc > 0) {
-            m |= 1u << 9;
-            for (int c0 = 0; c0 < nt; c0 += 64) {
-                const int cnt = std::min(64, nt - c0);
-                int logtp = 0;
-                while ((1 << logtp) < cnt) ++logtp;
-                const int kstride = 64 >> logtp;
-                work.push_back(make_int4((int)c, ls[c] + c0, cnt, logtp | (dense ? 16 : 0)));
-                cost.push_back(2 * ((nsrc + kstride - 1) / kstride));
-                ++nunits;
-            }
-        }
-        mask[c] = m;
-        if (!dense) continue;
-        int64_t diag = 0;
-        const int64_t st = self_steps(nt, diag);
-        work.push_back(make_int4((int)c, (int)c, 4 | (4 << 4), kMutualItem));
-        cost.push_back(3 * st + 2 * diag);
-        mpairs += (int64_t)nt * (nt - 1);
-        ++nitems;
-        for (const auto &o : up) {
-            const int nr = count(x + o[0], y + o[1]);
-            if (nr < D) continue;
-            const int ds = 3 * (o[1] + 1) + (o[0] + 1);
-            work.push_back(make_int4((int)c, (int)morton_encode((uint32_t)(x + o[0]), (uint32_t)(y + o[1])),
-                                     ds | ((8 - ds) << 4), kMutualItem));
-            cost.push_back(3 * block_steps(nt, nr));
-            mpairs += 2 * (int64_t)nt * nr;
-            ++nitems;
-        }
-    }
-    std::vector<int64_t> order(work.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-    std::vector<int4> sorted(work.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = work[order[k]];
-    int rc = FMM_OK;
-    if (!sorted.empty()) rc = upload(&t->d_near_work, sorted, "near-field work list");
-    if (!rc) rc = upload(&t->d_leaf_mask, mask, "near-field leaf masks");
-    if (rc) return rc;
-    t->nunits_tc = nunits;
-    t->nmut = nitems;
-    t->nnear_work = (int64_t)sorted.size();
-    t->mutual_pairs = mpairs;
-    return FMM_OK;
-}
-
 // The mutual form is used when its plan has items; else the target-centric units alone.
 bool use_mutual(const fmm_tree *t) { return t->near_mutual && t->nmut > 0; }
 
@@ -406,37 +298,85 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
 
 }  // namespace
 
-// ---------------------------------------------------------------------------------------
-// Stages 1-3: tree construction, binning, work lists (host)
-// ---------------------------------------------------------------------------------------
-extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
-                              fmm_tree **out)
+namespace {
+
+// Argument checks shared by both builds; a new tree with device facts filled in.
+int new_tree(const double *xy, int64_t n, int depth, const double *root_box, fmm_tree **out, fmm_tree *&t)
 {
     g_last_error.clear();
+    t = nullptr;
     if (!out) return fail(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!xy) return fail(FMM_EINVAL, "xy is NULL");
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(FMM_EINVAL, "n must be in [1, 2^31)");
     if (depth < 1 || depth > kMaxDepth) return fail(FMM_EINVAL, "depth must be in [1, 12]");
+    if (root_box && (!std::isfinite(root_box[0]) || !std::isfinite(root_box[1]) || !(root_box[2] > 0.0) ||
+                     !std::isfinite(root_box[2])))
+        return fail(FMM_EINVAL, "root_box must be finite with side > 0");
+    int dev = 0;
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
+    t = new fmm_tree();
+    t->device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    t->num_cus = cus;
+    t->n = n;
+    t->depth = depth;
+    return FMM_OK;
+}
+
+// Common end of both builds: the tree's side stream and events, the near-field plan
+// (device) and the near-field work counter.
+int finish_tree(fmm_tree *t, hipStream_t s)
+{
+    hipError_t e = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "creating stream/events");
+    std::string err;
+    const int rc = build_near_plan_device(t, s, err);
+    if (rc) return fail(rc, err);
+    return dev_alloc(&t->d_work, 4, "work counter");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Stages 1-3: tree construction, binning, work lists -- on the device (default) or on
+// the host (reference build; both give identical trees)
+// ---------------------------------------------------------------------------------------
+extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                              fmm_tree **out)
+{
     fmm_tree *t = nullptr;
+    int rc = new_tree(xy, n, depth, root_box, out, t);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    std::string err;
+    int64_t bad = -1;
+    rc = build_tree_device(t, xy, root_box, s, err, bad);
+    if (!rc) rc = finish_tree(t, s);
+    else {
+        if (bad >= 0) err += " (particle " + std::to_string(bad) + ")";
+        fail(rc, err);
+    }
+    if (rc) {
+        free_tree(t);
+        return rc;
+    }
+    *out = t;
+    return FMM_OK;
+}
+
+extern "C" int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                                   fmm_tree **out)
+{
+    fmm_tree *t = nullptr;
+    int rc0 = new_tree(xy, n, depth, root_box, out, t);
+    if (rc0) return rc0;
     try {
-        t = new fmm_tree();
         hipStream_t s = (hipStream_t)stream;
-        int dev = 0;
-        hipError_t de = hipGetDevice(&dev);
-        if (de != hipSuccess) {
-            free_tree(t);
-            return hip_fail(de, "hipGetDevice");
-        }
-        t->device = dev;
-        {
-            int cus = 0;
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-                cus = 256;
-            t->num_cus = cus;
-        }
-        t->n = n;
-        t->depth = depth;
 
         std::vector<double> h(2 * (size_t)n);
         {
@@ -456,10 +396,6 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
             t->x0 = root_box[0];
             t->y0 = root_box[1];
             t->side = root_box[2];
-            if (!std::isfinite(t->x0) || !std::isfinite(t->y0) || !(t->side > 0.0) || !std::isfinite(t->side)) {
-                free_tree(t);
-                return fail(FMM_EINVAL, "root_box must be finite with side > 0");
-            }
         } else {
             double xmin = h[0], xmax = h[0], ymin = h[1], ymax = h[1];
             for (int64_t i = 1; i < n; ++i) {
@@ -660,21 +596,12 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         if (!rc) rc = upload(&t->d_counts, counts, "cell counts");
         if (!rc) rc = upload(&t->d_lists, lists, "cell lists");
         if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
-        t->h_leaf_start = leaf_start;
-        if (!rc) rc = build_near_plan(t);
         if (!rc) rc = upload(&t->d_tile_start, tile_start, "tile offsets");
         if (!rc) rc = upload(&t->d_tile_box, tile_box, "tile boxes");
-        if (!rc) rc = dev_alloc(&t->d_work, 4, "work counter");
+        if (!rc) rc = finish_tree(t, s);
         if (rc) {
             free_tree(t);
             return rc;
-        }
-        hipError_t e = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            free_tree(t);
-            return hip_fail(e, "creating stream/events");
         }
     } catch (const std::bad_alloc &) {
         if (t) free_tree(t);
@@ -817,7 +744,9 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         HIP_TRY(hipDeviceSynchronize());  // the plan's arrays may be in use
         if (key == FMM_OPT_NEAR_MUTUAL) t->near_mutual = (int)value;
         else t->dense_leaf = (int)value;
-        return build_near_plan(t);
+        std::string err;
+        const int rc = build_near_plan_device(t, t->own_side, err);
+        return rc ? fail(rc, err) : FMM_OK;
     }
     case FMM_OPT_NEAR_OCCUPANCY:
         if (value < 0 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [0, 8]");

@@ -142,7 +142,6 @@ struct fmm_tree {
     int *d_counts = nullptr;      // particles per cell, all levels, global cell index
     int *d_lists = nullptr;       // non-empty cells per level (levels 2..L), parity-grouped
     int4 *d_units = nullptr;      // P2P work units {leaf, first, count, log2 lanes per target}
-    std::vector<int> h_leaf_start;  // host copy of d_leaf_start
     // near-field plan of the mutual form (see build_near_plan)
     int64_t nunits_tc = 0, nmut = 0, nnear_work = 0;
     int64_t mutual_pairs = 0;     // ordered pairs (i != j) evaluated by the mutual items
@@ -178,6 +177,12 @@ struct FarArgs {
 };
 
 // Launchers (kernels.hip).  All are asynchronous on `s`.
+// Stages 1-3 on the device (tree_build.hip); the near-field plan from the device leaf
+// offsets (used by both builds).  FMM_* status; err / bad_index describe a failure.
+int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
+                      int64_t &bad_index);
+int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err);
+
 void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
                         int near_waves, hipStream_t s);

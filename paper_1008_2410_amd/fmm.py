@@ -45,9 +45,10 @@ def _precision(precision) -> int:
 
 class Tree:
     """Uniform quadtree over n particles (stages 1-3): Morton-sorted particles, leaf
-    offsets, per-level occupancy and near-field work units, resident on the device."""
+    offsets, per-level occupancy and near-field work units, resident on the device.
+    builder: "device" (the GPU build) or "host" (the reference build; same tree)."""
 
-    def __init__(self, xy: torch.Tensor, depth: int, root_box=None, stream=None):
+    def __init__(self, xy: torch.Tensor, depth: int, root_box=None, stream=None, builder: str = "device"):
         if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must be an (n, 2) tensor")
         self.device = xy.device
@@ -57,9 +58,12 @@ class Tree:
         lib = L.load()
         handle = ctypes.c_void_p()
         rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        if builder not in ("device", "host"):
+            raise ValueError("builder must be 'device' or 'host'")
+        fn = lib.fmm_build_tree if builder == "device" else lib.fmm_build_tree_host
         with torch.cuda.device(self.device):
-            L.check(lib.fmm_build_tree(_ptr(xy), self.n, self.depth, rb, _stream_ptr(stream), ctypes.byref(handle)),
-                    "fmm_build_tree")
+            L.check(fn(_ptr(xy), self.n, self.depth, rb, _stream_ptr(stream), ctypes.byref(handle)),
+                    "fmm_build_tree" if builder == "device" else "fmm_build_tree_host")
         self._h = handle
 
     # -- lifetime -----------------------------------------------------------------

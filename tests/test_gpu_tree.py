@@ -1,0 +1,102 @@
+"""The device tree build (stages 1-3 on the GPU) against the host reference build.
+
+Both builds must give the same tree array for array, so the checks are bit-exact: the
+permutation and leaf of every particle, the statistics of fmm_tree_info, the
+near-field plan, and every output of the evaluation (forward, parts, adjoint), which
+reads every other array of the tree.  The host build itself is checked against the
+oracle's binning and pair counts in test_gpu_forward.py.
+"""
+import numpy as np
+import pytest
+
+from paper_1008_2410_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _cases():
+    r = np.random.Generator(np.random.PCG64(12))
+    yield "uniform", W.uniform_lamb_oseen()
+    yield "patches", W.gaussian_patches(n=60000, depth=5, p=12, sigma=0.004, seed=11, precision="fp64")
+    yield "clump", W.Workload("clump", 0.5 + 0.01 * r.random((300, 2)), r.standard_normal(300), 0.003, 5, 8,
+                              (0, 0, 1), "fp64")
+    yield "sparse12", W.Workload("sparse12", r.random((1000, 2)), r.standard_normal(1000), 0.001, 12, 6, None,
+                                 "fp64")
+    yield "one", W.Workload("one", np.array([[0.3, 0.7]]), np.array([1.0]), 0.1, 3, 5, (0, 0, 1), "fp64")
+    yield "edges", W.Workload("edges", np.array([[1.0, 1.0], [0.5, 0.5], [0.25, 0.75], [0.0, 1.0], [0.5, 0.5],
+                                                 [0.1, 0.9]]), np.array([1.0, -2.0, 0.5, 0.25, 1.5, -1.0]), 0.05,
+                              3, 6, (0, 0, 1), "fp64")
+    yield "depth1", W.Workload("depth1", r.random((400, 2)), r.standard_normal(400), 0.05, 1, 4, None, "fp64")
+
+
+CASES = list(_cases())
+
+
+@pytest.mark.parametrize("name,w", CASES, ids=[c[0] for c in CASES])
+def test_device_build_equals_host_build(fmm_mod, name, w):
+    xy = _t(w.xy)
+    td = fmm_mod.Tree(xy, w.depth, w.root_box, builder="device")
+    th = fmm_mod.Tree(xy, w.depth, w.root_box, builder="host")
+    assert td.info() == th.info()
+    assert td.near_plan() == th.near_plan()
+    pd, ld = td.permutation()
+    ph, lh = th.permutation()
+    assert np.array_equal(pd.cpu().numpy(), ph.cpu().numpy())
+    assert np.array_equal(ld.cpu().numpy(), lh.cpu().numpy())
+    g = _t(w.gamma)
+    dl = _t(np.random.Generator(np.random.PCG64(3)).standard_normal((w.n, 2)))
+    for precision in ("fp64", "mixed"):
+        assert np.array_equal(td.velocity(g, w.sigma, w.p, precision).cpu().numpy(),
+                              th.velocity(g, w.sigma, w.p, precision).cpu().numpy()), precision
+        a = td.velocity_parts(g, w.sigma, w.p, precision)
+        b = th.velocity_parts(g, w.sigma, w.p, precision)
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b)), precision
+        a = td.velocity_backward(g, w.sigma, w.p, precision, dl, need_src=True)
+        b = th.velocity_backward(g, w.sigma, w.p, precision, dl, need_src=True)
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b)), precision
+
+
+def test_device_build_large_lattice(fmm_mod):
+    """2^20 particles, depth 8: the multi-tile radix sort and scans at size."""
+    w = W.lattice_lamb_oseen()
+    xy = _t(w.xy)
+    td = fmm_mod.Tree(xy, w.depth, w.root_box, builder="device")
+    th = fmm_mod.Tree(xy, w.depth, w.root_box, builder="host")
+    assert td.info() == th.info()
+    assert np.array_equal(td.permutation()[0].cpu().numpy(), th.permutation()[0].cpu().numpy())
+    g = _t(w.gamma)
+    assert np.array_equal(td.velocity(g, w.sigma, w.p, "mixed").cpu().numpy(),
+                          th.velocity(g, w.sigma, w.p, "mixed").cpu().numpy())
+
+
+def test_device_build_option_rebuilds_plan(fmm_mod):
+    """Changing the dense threshold rebuilds the plan on the device: same as the host tree's."""
+    w = CASES[1][1]
+    xy = _t(w.xy)
+    td = fmm_mod.Tree(xy, w.depth, w.root_box, builder="device")
+    th = fmm_mod.Tree(xy, w.depth, w.root_box, builder="host")
+    g = _t(w.gamma)
+    for dense in (1, 100):
+        td.set_option(7, dense)
+        th.set_option(7, dense)
+        assert td.near_plan() == th.near_plan()
+        assert np.array_equal(td.velocity(g, w.sigma, w.p, "mixed").cpu().numpy(),
+                              th.velocity(g, w.sigma, w.p, "mixed").cpu().numpy())
+
+
+def test_device_build_errors(fmm_mod):
+    from paper_1008_2410_amd import _lib
+    xy = np.array([[0.5, 0.5], [0.2, 0.3], [1.5, 0.2], [0.1, 0.1]])
+    with pytest.raises(_lib.FmmError) as e:
+        fmm_mod.Tree(_t(xy), 3, (0.0, 0.0, 1.0))
+    assert e.value.status == _lib.FMM_ERANGE
+    assert "particle 2" in str(e.value)
+    xy[1, 0] = np.nan
+    with pytest.raises(_lib.FmmError) as e:
+        fmm_mod.Tree(_t(xy), 3, None)
+    assert e.value.status == _lib.FMM_EINVAL
