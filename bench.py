@@ -75,6 +75,82 @@ def cpu_baseline_leg(w, sample_frac_log4=1):
     }
 
 
+def cost_model_leg(torch, dev, workloads):
+    """Sweep of depth L and coarse cutoff L_c over uniform particles (p = 16, mixed):
+    each point timed with the stages serialised (per-stage times) and with the two-stream
+    schedule; the paper's four terms are fitted to the stage times and used to choose the
+    depth and check the cover condition against the measured overlap."""
+    from paper_1008_2410_amd import _lib, costmodel, fmm
+    samples, points = [], []
+    for n, depths in ((1 << 20, range(5, 10)), (1 << 22, range(6, 11))):
+        w = workloads.uniform_lamb_oseen(n=n, seed=4, depth=8, p=16)
+        xy = torch.from_numpy(w.xy).to(dev)
+        g = torch.from_numpy(w.gamma).to(dev)
+        for L in depths:
+            tree = fmm.Tree(xy, L, w.root_box)
+            info, levels = tree.info(), tree.levels()
+            out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+            for lc in (2, 3, 4, 5):
+                if lc > L:
+                    continue
+                tree.set_option(_lib.FMM_OPT_COARSE_LEVEL, lc)
+                res = {}
+                for sched in (1, 0):
+                    tree.set_option(_lib.FMM_OPT_SCHEDULE, sched)
+                    for _ in range(2):
+                        tree.velocity(g, w.sigma, w.p, "mixed", out=out)
+                    tree.set_option(_lib.FMM_OPT_TIMING, 1)
+                    tree.timings()
+                    k = 5
+                    for _ in range(k):
+                        tree.velocity(g, w.sigma, w.p, "mixed", out=out)
+                    torch.cuda.synchronize()
+                    st = tree.timings()
+                    tree.set_option(_lib.FMM_OPT_TIMING, 0)
+                    res[sched] = {a: v / st["calls"] for a, v in st.items() if a != "calls"}
+                ser, ovl = res[1], res[0]
+                s = costmodel.Sample(n=n, depth=L, lc=lc, pairs=info["p2p_pairs"],
+                                     fine_cells=costmodel.fine_cells(levels, lc),
+                                     t_part=ser["pack"] + ser["final"], t_far=ser["far"], t_near=ser["p2p"],
+                                     t_overlap=ovl["total"], coarse_cells=costmodel.coarse_cells(levels, lc),
+                                     leaves=info["nonempty_leaves"])
+                samples.append(s)
+                both = ovl["total"] - ovl["pack"] - ovl["final"]
+                overlap = (ser["p2p"] + ser["far"] - both) / min(ser["p2p"], ser["far"])
+                points.append({"n": n, "depth": L, "lc": lc, "B": round(n / 4 ** L, 2), "serial_ms": round(ser["total"], 4),
+                               "overlap_ms": round(ovl["total"], 4), "near_ms": round(ser["p2p"], 4),
+                               "far_ms": round(ser["far"], 4), "part_ms": round(ser["pack"] + ser["final"], 4),
+                               "overlap_fraction": round(overlap, 3)})
+                log(f"[bench] cost model n={n} L={L} lc={lc}: {points[-1]}")
+            tree.close()
+    f = costmodel.fit(samples)
+    errs = []
+    for s, pt in zip(samples, points):
+        pr = f.predict(s)
+        pt["predicted_serial_ms"] = round(pr["serial"], 4)
+        pt["coarse_ms_model"] = round(f.coarse_ms(s), 4)
+        pt["covered"] = f.covered(s)
+        errs.append(abs(pr["serial"] - pt["serial_ms"]) / pt["serial_ms"])
+    best = {}
+    for n in (1 << 20, 1 << 22):
+        pts = [p for p in points if p["n"] == n]
+        meas = min(pts, key=lambda p: p["serial_ms"])
+        sel = min(zip(samples, points), key=lambda sp: f.predict(sp[0])["serial"] if sp[1]["n"] == n else 1e30)[1]
+        best[str(n)] = {"measured_serial": {"depth": meas["depth"], "lc": meas["lc"], "ms": meas["serial_ms"]},
+                        "predicted_serial": {"depth": sel["depth"], "lc": sel["lc"], "ms_measured": sel["serial_ms"]},
+                        "uniform_model_depth": f.best_depth(n, meas["lc"], sorted({p["depth"] for p in pts})),
+                        "measured_overlap_best": min(pts, key=lambda p: p["overlap_ms"])["overlap_ms"]}
+    print(json.dumps({
+        "cost_model": {"a_ns_per_particle": f.a * 1e6, "b_ns_per_coarse_cell": f.b * 1e6,
+                       "c_ns_per_fine_cell": f.c * 1e6, "d_ps_per_pair": f.d * 1e9,
+                       "g_ns_per_leaf_visit": f.g * 1e6, "h_us_per_fine_level": f.h * 1e3,
+                       "intercepts_ms": {"part": f.part0, "far": f.far0, "near": f.near0},
+                       "B_opt_uniform": round(f.b_opt_uniform(), 2),
+                       "paper_B_opt_t15": round(costmodel.paper_b_opt(15), 2),
+                       "max_rel_err_serial": round(max(errs), 4)},
+        "best": best, "points": points}), flush=True)
+
+
 def rk2_leg(torch, dev, workloads):
     """Time-stepped workload: forward transport and its discrete adjoint (per-step
     checkpoints), with tree builds, velocity evaluations and adjoint calls timed
@@ -141,6 +217,9 @@ def main():
                     help="only the timed headline region (for kernel profiling of exactly that work)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a device-to-device copy of MIB MiB ten times (HBM counter calibration)")
+    ap.add_argument("--cost-model", action="store_true",
+                    help="only the cost-model sweep (uniform particles, depth and coarse-level sweep, fit of the "
+                         "paper's complexity terms to the measured stages): one JSON line of its own")
     ap.add_argument("--rk2", action="store_true",
                     help="only the time-stepped workload (2^25 particles, 16 patches, 5 midpoint-RK2 steps, trees "
                          "rebuilt per evaluation): forward and adjoint, one JSON line of its own")
@@ -165,6 +244,9 @@ def main():
         return
     if args.rk2:
         rk2_leg(torch, dev, workloads)
+        return
+    if args.cost_model:
+        cost_model_leg(torch, dev, workloads)
         return
     t0 = time.perf_counter()
     w = workloads.gaussian_patches(n=args.n, depth=args.depth)

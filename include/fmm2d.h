@@ -76,7 +76,8 @@ enum {
     FMM_OPT_DENSE_LEAF = 7,   /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
     FMM_OPT_NEAR_OCCUPANCY = 8 /* 1..8: with FMM_OPT_SCHEDULE 0 the forward near-field kernel keeps at
                                   most this many wavefronts per SIMD resident (by reserving LDS),
-                                  leaving room for the far field beside it; 0 = no cap; default 5 */
+                                  leaving room for the far field beside it; 0 = no cap; -1 (default)
+                                  = 5 or none per call, from the predicted far/near time ratio */
 };
 
 /* Stage indices of fmm_get_timings. */
@@ -126,6 +127,10 @@ int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *ro
  *   nonempty_leaves, max_leaf  occupancy of the leaf level. */
 int fmm_tree_info(const fmm_tree *tree, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
                   int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf);
+
+/* Non-empty cells per level: nonempty[l] for l = 0 .. min(depth, max_levels - 1)
+ * (host array of max_levels entries; entries past depth are set to 0). */
+int fmm_tree_levels(const fmm_tree *tree, int64_t *nonempty, int max_levels);
 
 /* Sorted order of the tree.  perm: device, n int64, perm[k] = user index of the k-th
  * particle; particles are grouped by leaf in leaf-Morton order and, inside a leaf,

@@ -25,6 +25,7 @@ SIGNATURES = {
     "fmm_build_tree_host": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_tree_info": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "fmm_tree_permutation": (_I, [_P, _P, _P, _P]),
+    "fmm_tree_levels": (_I, [_P, _P, _I]),
     "fmm_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
     "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),

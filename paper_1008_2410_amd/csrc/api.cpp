@@ -229,6 +229,32 @@ FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
 // workgroup per unit.
 int near_waves(const fmm_tree *t) { return t->near_waves; }
 
+// Stage costs of the mixed form (p = 16) on one MI355X, in ms, fitted by the cost-model
+// sweep of uniform particles (the complexity terms of section "Complexity Estimates"
+// with the counts a launch pays for):
+//   T_near = kNear0 + kNearPair pairs + kNearVisit 9 N_leaves,
+//   T_far  = kFar0 + kFarCell C_fine + kFarCoarse C_coarse + kFarLevel (L - L_c).
+constexpr double kNear0 = 0.072, kNearPair = 1.95e-10, kNearVisit = 1.72e-7;
+constexpr double kFar0 = 0.124, kFarCell = 1.16e-6, kFarCoarse = 5.35e-4, kFarLevel = 0.0238;
+
+// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic: capping the
+// near field at 5 wavefronts per SIMD slows it by ~12-18% and lets the far chain run
+// beside it; measured on uniform and clustered workloads that pays when the predicted far
+// field takes between 0.12 and 1 times the near field (below, the far field is too short
+// to hide anything; above, the far kernels need more of the chip than the cap leaves).
+int choose_occupancy(const fmm_tree *t, int precision)
+{
+    if (t->near_occupancy >= 0) return t->near_occupancy;
+    if (precision != FMM_MIXED || t->schedule != 0 || t->depth < 2) return 0;
+    const int lc = std::min(t->lc, t->depth);
+    double fine = 0, coarse = 0;
+    for (int l = 2; l <= t->depth; ++l) (l <= lc ? coarse : fine) += (double)t->list_len[l];
+    const double near = kNear0 + kNearPair * (double)t->p2p_pairs + kNearVisit * 9.0 * (double)t->nonempty_leaves;
+    const double far = kFar0 + kFarCell * fine + kFarCoarse * coarse + kFarLevel * (t->depth - lc);
+    const double ratio = far / near;
+    return (ratio >= 0.12 && ratio <= 1.0) ? 5 : 0;
+}
+
 struct Timing {
     std::array<hipEvent_t, kNumEvents> ev{};
     bool on = false;
@@ -284,6 +310,7 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     void *slots = use_mutual(t) ? t->ws.slots : nullptr;
+    t->occupancy_in_use = choose_occupancy(t, precision);
     tm.mark(4, ms);
     launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, slots, near_waves(t), ms);
     tm.mark(5, ms);
@@ -633,6 +660,22 @@ namespace fmm {
 void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStream_t s);
 }
 
+extern "C" int fmm_tree_levels(const fmm_tree *t, int64_t *nonempty, int max_levels)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!nonempty || max_levels < 1) return fail(FMM_EINVAL, "nonempty is NULL or max_levels < 1");
+    std::vector<int> h((size_t)level_base(std::min(t->depth, 1) + 1));
+    for (int l = 0; l < max_levels; ++l) nonempty[l] = 0;
+    // levels 0 and 1 from the cell counts (they hold no expansions and have no list)
+    const int top = std::min(t->depth, 1);
+    if (hipMemcpy(h.data(), t->d_counts, h.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(FMM_EDEVICE, "reading cell counts");
+    for (int l = 0; l <= top && l < max_levels; ++l)
+        for (int64_t c = level_base(l); c < level_base(l + 1); ++c) nonempty[l] += h[c] > 0;
+    for (int l = 2; l <= t->depth && l < max_levels; ++l) nonempty[l] = t->list_len[l];
+    return FMM_OK;
+}
+
 extern "C" int fmm_tree_permutation(const fmm_tree *t, int64_t *perm, int32_t *leaf, void *stream)
 {
     if (!t) return fail(FMM_ESTATE, "null tree handle");
@@ -749,7 +792,7 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         return rc ? fail(rc, err) : FMM_OK;
     }
     case FMM_OPT_NEAR_OCCUPANCY:
-        if (value < 0 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [0, 8]");
+        if (value < -1 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [-1, 8]");
         t->near_occupancy = (int)value;
         return FMM_OK;
     case FMM_OPT_TIMING:

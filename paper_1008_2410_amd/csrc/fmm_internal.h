@@ -117,7 +117,9 @@ struct fmm_tree {
     int schedule = 0;    // 0 overlap, 1 serial
     int near_mutual = 1; // pairs of dense leaves evaluated once for both particles
     int dense_leaf = 32; // a leaf with at least this many particles is dense
-    int near_occupancy = 5; // cap on forward near-field wavefronts per SIMD beside the far field (0: none)
+    int near_occupancy = -1; // cap on forward near-field wavefronts per SIMD beside the far field
+                             // (0: none, -1: chosen per call from the cost model)
+    int occupancy_in_use = 0; // the cap of the current call
     int timing = 0;
     std::atomic<int> busy{0};
 

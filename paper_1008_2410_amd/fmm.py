@@ -98,6 +98,12 @@ class Tree:
         return {"n": n.value, "depth": depth.value, "root_box": tuple(root), "p2p_pairs": pairs.value,
                 "m2l_pairs": m2l.value, "nonempty_leaves": ne.value, "max_leaf": mx.value}
 
+    def levels(self) -> list:
+        """Non-empty cells per level, levels 0 .. depth."""
+        buf = (ctypes.c_int64 * (self.depth + 1))()
+        L.check(L.load().fmm_tree_levels(self.handle, buf, self.depth + 1), "fmm_tree_levels")
+        return list(buf)
+
     def permutation(self):
         """(perm, leaf): perm[k] = user index of the k-th particle in Morton order, leaf[k] its leaf."""
         perm = torch.empty(self.n, dtype=torch.int64, device=self.device)
