@@ -234,8 +234,8 @@ int near_waves(const fmm_tree *t) { return t->near_waves; }
 // with the counts a launch pays for):
 //   T_near = kNear0 + kNearPair pairs + kNearVisit 9 N_leaves,
 //   T_far  = kFar0 + kFarCell C_fine + kFarCoarse C_coarse + kFarLevel (L - L_c).
-constexpr double kNear0 = 0.072, kNearPair = 1.95e-10, kNearVisit = 1.72e-7;
-constexpr double kFar0 = 0.124, kFarCell = 1.16e-6, kFarCoarse = 5.35e-4, kFarLevel = 0.0238;
+constexpr double kNear0 = 0.075, kNearPair = 2.12e-10, kNearVisit = 1.76e-7;
+constexpr double kFar0 = 0.128, kFarCell = 1.18e-6, kFarCoarse = 5.32e-4, kFarLevel = 0.0238;
 
 // Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic: capping the
 // near field at 5 wavefronts per SIMD slows it by ~12-18% and lets the far chain run

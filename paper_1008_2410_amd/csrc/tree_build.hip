@@ -340,15 +340,21 @@ __global__ __launch_bounds__(256) void k_sorted(const uint64_t *__restrict__ key
     xys[i] = xy[u];
 }
 
-// leaf_start[c] = first sorted slot with leaf >= c, c = 0..nleaf.
+// leaf_start[c] = first sorted slot with leaf >= c, c = 0..nleaf: a binary search per
+// leaf (a fill between consecutive occupied leaves would leave one thread to write each
+// run of empty leaves, long for clustered particles).
 __global__ __launch_bounds__(256) void k_leaf_start(const int *__restrict__ leaf_of, int64_t n, int64_t nleaf,
                                                      int *__restrict__ ls)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    const int64_t prev = i == 0 ? -1 : leaf_of[i - 1];
-    const int64_t cur = i == n ? nleaf : leaf_of[i];
-    for (int64_t c = prev + 1; c <= cur; ++c) ls[c] = (int)i;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nleaf) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (leaf_of[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    ls[c] = (int)lo;
 }
 
 // Occupancy of every cell of every level (global cell index (4^l - 1)/3 + Morton).
@@ -820,7 +826,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         !st.check(hipMalloc((void **)&t->d_leaf_start, (nleaf + 1) * sizeof(int)), "leaf offsets"))
         return failed();
     k_sorted<<<grid_for(n, 256), 256, 0, s>>>(key.p, val.p, xy2, n, t->d_perm, t->d_leaf_of, t->d_xy);
-    k_leaf_start<<<grid_for(n + 1, 256), 256, 0, s>>>(t->d_leaf_of, n, nleaf, t->d_leaf_start);
+    k_leaf_start<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(t->d_leaf_of, n, nleaf, t->d_leaf_start);
     // Occupancy of all levels.
     const int64_t ncells = level_base(L + 1);
     if (!st.check(hipMalloc((void **)&t->d_counts, ncells * sizeof(int)), "cell counts")) return failed();
