@@ -19,6 +19,9 @@ Levels (see the C file's header for the readings of points the paper leaves open
   fmm_src_grad  O5  gradient of L(u) through O3 with respect to the source positions
   direct_grad       gradient of L(u) through O1, every particle moving as source and
                     evaluation point
+  afmm          O6  O3 on an adaptive quadtree (cells split above s_max particles, down
+                    to l_max) with the U, V, W, X lists of the adaptive FMM
+                    (``adaptive_oracle.c``)
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = os.path.join(_HERE, "fmm_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("fmm_oracle.c", "adaptive_oracle.c")]
 _lib = None
 
 ORC_OK, ORC_EINVAL, ORC_ENOMEM, ORC_ERANGE = 0, -1, -2, -4
@@ -42,9 +45,9 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile fmm_oracle.c with gcc into liboracle.so (in place)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", _SO + ".tmp", "-lm"]
+    """Compile the oracle's C sources with gcc into liboracle.so (in place)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", *_SRCS, "-o", _SO + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
     return _SO
@@ -73,6 +76,14 @@ def _load():
         lib.orc_direct_grad.restype = None
         lib.orc_leaf_counts.argtypes = [I64, P, Ci, P, P]
         lib.orc_cover_level.argtypes = [Ci, Ci, Ci, Ci, Ci]
+        lib.orc_atree_build.argtypes = [I64, P, P, Ci, Ci, ctypes.POINTER(ctypes.c_void_p)]
+        lib.orc_atree_free.argtypes = [P]
+        lib.orc_atree_free.restype = None
+        lib.orc_atree_sizes.argtypes = [P, P]
+        lib.orc_atree_sizes.restype = None
+        lib.orc_atree_export.argtypes = [P] * 11
+        lib.orc_atree_export.restype = None
+        lib.orc_afmm.argtypes = [I64, P, P, D, P, Ci, Ci, Ci, P, P]
         _lib = lib
     return _lib
 
@@ -266,3 +277,57 @@ def pair_count(counts: np.ndarray) -> int:
     n1 = c.shape[0]
     nb = sum(pad[1 + a:1 + a + n1, 1 + b:1 + b + n1] for a in (-1, 0, 1) for b in (-1, 0, 1))
     return int((c * nb).sum() - c.sum())
+
+
+# --- O6: the adaptive tree -------------------------------------------------------------
+
+ATREE_SIZE_KEYS = ("cells", "leaves", "u", "v", "w", "x", "deepest", "p2p_pairs")
+
+
+def adaptive_tree(xy, smax: int, lmax: int, root=None) -> dict:
+    """The adaptive tree of O6 and its lists: ``cells`` (K, 6) int64 rows (level, ix, iy,
+    leaf, count, parent), ``leaf_of`` (N,), the lists ``U``, ``V``, ``W``, ``X`` as
+    (offsets (K+1,), indices), and the sizes of ``ATREE_SIZE_KEYS``."""
+    xy = _f64(xy, (-1, 2))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    lib = _load()
+    h = ctypes.c_void_p()
+    _check(lib.orc_atree_build(xy.shape[0], _ptr(xy), _ptr(r), int(smax), int(lmax), ctypes.byref(h)),
+           "orc_atree_build")
+    try:
+        s = np.zeros(8, dtype=np.int64)
+        lib.orc_atree_sizes(h, _ptr(s))
+        k = int(s[0])
+        cells = np.zeros((k, 6), dtype=np.int64)
+        leaf_of = np.zeros(xy.shape[0], dtype=np.int64)
+        offs = [np.zeros(k + 1, dtype=np.int64) for _ in range(4)]
+        idxs = [np.zeros(max(int(s[2 + i]), 1), dtype=np.int64) for i in range(4)]
+        lib.orc_atree_export(h, _ptr(cells), _ptr(leaf_of), _ptr(offs[0]), _ptr(idxs[0]), _ptr(offs[1]),
+                             _ptr(idxs[1]), _ptr(offs[2]), _ptr(idxs[2]), _ptr(offs[3]), _ptr(idxs[3]))
+    finally:
+        lib.orc_atree_free(h)
+    out = {"cells": cells, "leaf_of": leaf_of, "root": tuple(float(v) for v in r),
+           "sizes": {key: int(v) for key, v in zip(ATREE_SIZE_KEYS, s)}}
+    for name, o, ix in zip("UVWX", offs, idxs):
+        out[name] = (o, ix[:int(o[-1])])
+    return out
+
+
+def afmm(xy, q, sigma: float, smax: int, lmax: int, p: int, root=None):
+    """O6 with complex charges q at the particles: (W_near, W_far), complex."""
+    xy = _f64(xy, (-1, 2))
+    qc = np.ascontiguousarray(q, dtype=np.complex128)
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    wn = np.zeros(xy.shape[0], dtype=np.complex128)
+    wf = np.zeros(xy.shape[0], dtype=np.complex128)
+    _check(_load().orc_afmm(xy.shape[0], _ptr(xy), _ptr(qc), float(sigma), _ptr(r), int(smax), int(lmax), int(p),
+                            _ptr(wn), _ptr(wf)), "orc_afmm")
+    return wn, wf
+
+
+def afmm_velocity(xy, gamma, sigma: float, smax: int, lmax: int, p: int, root=None, parts: bool = False):
+    """O6 velocities (N, 2) at the particles (near + far, or both parts)."""
+    wn, wf = afmm(xy, charges(gamma), sigma, smax, lmax, p, root)
+    if parts:
+        return w_to_uv(wn), w_to_uv(wf)
+    return w_to_uv(wn + wf)

@@ -1,0 +1,153 @@
+"""Pins of the adaptive-tree oracle (O6) to things other than itself.
+
+* The four lists against a brute-force restatement of their definitions (every cell
+  against every cell, in Python, from the cells' levels and coordinates alone).
+* Exactly-once coverage: for every ordered pair of leaves (T, S), S reaches T by
+  exactly one route: S in U(T); an ancestor-or-self of S in V of an ancestor-or-self
+  of T; an ancestor-or-self of S in W(T); or S in X of an ancestor-or-self of T.
+* Special cases: one leaf (s_max >= N) is the direct sum O1; a lattice with equal
+  leaf counts splits into the uniform tree, where O6 equals O3 and W, X are empty.
+* Accuracy: with sigma small enough that the far kernel is exact, O6 matches O1
+  within the truncation error of p terms on clustered points with non-empty W, X.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import rel_l2
+
+
+def _clustered(seed=1):
+    r = np.random.Generator(np.random.PCG64(seed))
+    xy = np.concatenate([r.random((500, 2)), 0.3 + 0.02 * r.random((900, 2)),
+                         0.71 + 0.005 * r.standard_normal((300, 2)), [[0.999, 0.001], [0.0, 0.0]]])
+    return xy, r.standard_normal(len(xy))
+
+
+def _box(c, lmax):
+    level, ix, iy = int(c[0]), int(c[1]), int(c[2])
+    s = 1 << (lmax - level)
+    return ix * s, (ix + 1) * s, iy * s, (iy + 1) * s
+
+
+def _adj(a, b, lmax):
+    ax0, ax1, ay0, ay1 = _box(a, lmax)
+    bx0, bx1, by0, by1 = _box(b, lmax)
+    return ax0 <= bx1 and bx0 <= ax1 and ay0 <= by1 and by0 <= ay1
+
+
+def _sets(t, name):
+    off, idx = t[name]
+    return [set(idx[off[k]:off[k + 1]].tolist()) for k in range(len(off) - 1)]
+
+
+def _ancestors(cells, k):
+    out = []
+    while k >= 0:
+        out.append(k)
+        k = int(cells[k, 5])
+    return out
+
+
+@pytest.mark.parametrize("smax,lmax", [(20, 9), (5, 7), (60, 12), (1, 5)])
+def test_lists_match_definitions(smax, lmax):
+    xy, _ = _clustered()
+    t = O.adaptive_tree(xy, smax, lmax)
+    cells = t["cells"]
+    K = len(cells)
+    leaf = cells[:, 3].astype(bool)
+    level = cells[:, 0]
+    # the split rule
+    for k in range(K):
+        assert (not leaf[k]) == (cells[k, 4] > smax and level[k] < lmax)
+        if cells[k, 5] >= 0:
+            assert level[cells[k, 5]] == level[k] - 1
+    counts = np.bincount(t["leaf_of"], minlength=K)
+    assert np.array_equal(counts[leaf], cells[leaf, 4]) and counts[~leaf].sum() == 0
+    adj = np.array([[_adj(cells[a], cells[b], lmax) for b in range(K)] for a in range(K)])
+    desc = [set() for _ in range(K)]  # proper descendants
+    for k in range(K):
+        for a in _ancestors(cells, int(cells[k, 5])):
+            desc[a].add(k)
+    coll = [{b for b in range(K) if b != a and level[b] == level[a] and adj[a, b]} for a in range(K)]
+    U, V, W, X = (_sets(t, n) for n in "UVWX")
+    for a in range(K):
+        par = int(cells[a, 5])
+        v_ref = set()
+        if par >= 0:
+            v_ref = {d for c in coll[par] for d in range(K) if cells[d, 5] == c and not adj[a, d]}
+        assert V[a] == v_ref
+        if leaf[a]:
+            assert U[a] == {b for b in range(K) if leaf[b] and adj[a, b]}
+            w_ref = {d for c in coll[a] for d in desc[c]
+                     if not adj[a, d] and adj[a, int(cells[d, 5])]}
+            assert W[a] == w_ref
+        else:
+            assert not U[a] and not W[a]
+        assert X[a] == {b for b in range(K) if leaf[b] and a in W[b]}
+
+
+@pytest.mark.parametrize("smax,lmax", [(20, 9), (5, 7), (1, 5), (300, 8)])
+def test_every_pair_of_leaves_covered_once(smax, lmax):
+    xy, _ = _clustered(3)
+    t = O.adaptive_tree(xy, smax, lmax)
+    cells = t["cells"]
+    K = len(cells)
+    U, V, W, X = (_sets(t, n) for n in "UVWX")
+    leaves = [k for k in range(K) if cells[k, 3]]
+    anc = {k: _ancestors(cells, k) for k in range(K)}
+    assert t["sizes"]["w"] > 0 or smax >= 300  # the adaptive routes are exercised
+    for T, S in itertools.product(leaves, leaves):
+        routes = int(S in U[T])
+        routes += sum(1 for a in anc[T] for b in anc[S] if b in V[a])
+        routes += sum(1 for b in anc[S] if b in W[T])
+        routes += sum(1 for a in anc[T] if S in X[a])
+        assert routes == 1, (T, S, routes)
+
+
+def test_single_leaf_is_the_direct_sum():
+    xy, g = _clustered(5)
+    t = O.adaptive_tree(xy, len(xy), 6)
+    assert t["sizes"]["cells"] == 1 and t["sizes"]["p2p_pairs"] == len(xy) * (len(xy) - 1)
+    un, uf = O.afmm_velocity(xy, g, 0.003, len(xy), 6, 8, parts=True)
+    assert np.all(uf == 0.0)
+    assert rel_l2(un, O.direct(xy, g, 0.003)) < 1e-13
+
+
+def test_equal_leaf_counts_give_the_uniform_tree():
+    r = np.random.Generator(np.random.PCG64(8))
+    L, m = 4, 16  # a jittered 64 x 64 lattice: 16 particles in every depth-4 leaf
+    h = 1.0 / 64
+    g1 = (np.arange(64) + 0.5) * h
+    xy = np.stack(np.meshgrid(g1, g1, indexing="xy"), -1).reshape(-1, 2) + (r.random((4096, 2)) - 0.5) * 0.3 * h
+    g = r.standard_normal(4096)
+    root = (0.0, 0.0, 1.0)
+    t = O.adaptive_tree(xy, m - 1, L, root)
+    s = t["sizes"]
+    assert s["leaves"] == 4 ** L and s["w"] == 0 and s["x"] == 0 and s["deepest"] == L
+    assert s["p2p_pairs"] == _uniform_pairs(xy, L, root)
+    an, af = O.afmm_velocity(xy, g, 0.01, m - 1, L, 12, root, parts=True)
+    un, uf = O.fmm_velocity(xy, g, 0.01, L, 12, root, parts=True)
+    assert rel_l2(an, un) < 1e-14
+    assert rel_l2(af, uf) < 1e-13
+
+
+def _uniform_pairs(xy, L, root):
+    c = O.leaf_counts(xy, L, root)
+    pad = np.pad(c, 1)
+    nb = sum(pad[1 + dy:1 + dy + c.shape[0], 1 + dx:1 + dx + c.shape[1]] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    return int(np.sum(c * nb) - c.sum())
+
+
+@pytest.mark.parametrize("smax,lmax,p,tol", [(20, 9, 20, 1e-8), (8, 8, 12, 1e-5), (40, 10, 30, 1e-11)])
+def test_matches_direct_sum_within_truncation(smax, lmax, p, tol):
+    xy, g = _clustered(2)
+    t = O.adaptive_tree(xy, smax, lmax)
+    assert t["sizes"]["w"] > 0 and t["sizes"]["x"] > 0
+    # the far kernel differs from the regularised one by exp(-d^2/(2 sigma^2)), d >= the
+    # narrowest leaf: below 1e-300 here
+    sigma = 1e-6
+    u = O.afmm_velocity(xy, g, sigma, smax, lmax, p)
+    assert rel_l2(u, O.direct(xy, g, sigma)) < tol
