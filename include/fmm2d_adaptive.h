@@ -1,0 +1,104 @@
+/*
+ * fmm2d_adaptive.h -- C ABI of the adaptive-tree variant of the velocity evaluation
+ * (libfmm2d.so, gfx950), for uneven particle distributions.
+ *
+ * The paper's conclusions note that an uneven distribution puts more work in the
+ * direct (near-field) sum for the same N, and that with the particles per box held
+ * roughly constant the complexity estimates of section "Complexity Estimates" carry
+ * over unchanged.  The paper fixes no adaptive scheme; this variant caps the particles
+ * per leaf with an adaptive quadtree and evaluates it with the four interaction lists
+ * of the adaptive FMM of Carrier, Greengard and Rokhlin (SIAM J. Sci. Stat. Comput. 9,
+ * 1988):
+ *   tree   the root cell (the bounding square of the particles, or root_box) is split
+ *          into its four quadrants while it holds more than max_leaf particles and its
+ *          level is below max_depth, recursively; empty cells are dropped.  Particles
+ *          are binned as by fmm_build_tree at depth max_depth.
+ *   U(A)   leaves adjacent to leaf A (closed squares intersect), A included: the exact
+ *          regularised kernel of eq. regB-S2DGau, pair by pair (near field)
+ *   V(B)   children of the colleagues (same-level adjacent cells) of B's parent that are
+ *          not adjacent to B: multipole-to-local translation (M2L)
+ *   W(A)   cells D below a colleague of leaf A, not adjacent to A, whose parent is:
+ *          D's multipole expansion evaluated at A's particles (M2P)
+ *   X(B)   leaves A with B in W(A): A's particles into B's local expansion (P2L)
+ * with P2M at the leaves, M2M and L2L along the tree, and L2P at the leaves, all on
+ * cells of level >= 2 and with the singular kernel (the far-field substitution after
+ * eq. discBiotS2D), as in fmm2d.h.  With every leaf on level max_depth the lists are
+ * those of the uniform tree of depth max_depth and the result equals fmm_velocity's up
+ * to rounding.
+ *
+ * Accuracy: far-field pairs are at least one leaf width apart, so the leaves must stay
+ * wider than the blob core (width >= ~8 sigma for FP64 accuracy, ~6 sigma for the
+ * mixed form): max_depth plays the role of the uniform tree's depth.
+ *
+ * The conventions of fmm2d.h apply (device pointers unless "host", (n, 2) row-major
+ * FP64 positions and velocities, void* streams, FMM_* status codes with
+ * fmm_last_error(), one host thread per handle, inputs never modified).
+ */
+#ifndef FMM2D_ADAPTIVE_H
+#define FMM2D_ADAPTIVE_H
+
+#include <stdint.h>
+
+#include "fmm2d.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_atree fmm_atree;
+
+/* Sizes reported by fmm_atree_info, in this order. */
+enum {
+    FMM_AT_CELLS = 0,     /* non-empty cells of the tree, the root included */
+    FMM_AT_LEAVES = 1,    /* leaves */
+    FMM_AT_U = 2,         /* sum over leaves of |U| */
+    FMM_AT_V = 3,         /* sum over cells of |V| */
+    FMM_AT_W = 4,         /* sum over leaves of |W| */
+    FMM_AT_X = 5,         /* sum over cells of |X| (= |W|) */
+    FMM_AT_DEEPEST = 6,   /* deepest level of a leaf */
+    FMM_AT_PAIRS = 7,     /* ordered near-field pairs: sum over leaves A of n_A sum_{S in U(A)} n_S, minus N */
+    FMM_AT_COUNT = 8
+};
+
+/* Builds the adaptive tree of n particles xy (device, (n, 2)): binning, sorting and
+ * the lists on the host, then everything the evaluation reads uploaded to the current
+ * device; synchronises `stream` to read xy.  max_leaf >= 1, 0 <= max_depth <= 15,
+ * 1 <= n < 2^31.  root_box (host, {x0, y0, side}) or NULL for the bounding square with
+ * side (1 + 2^-20) max(range x, range y).  Returns FMM_EINVAL for bad arguments or a
+ * non-finite position, FMM_ERANGE (naming the particle) for a particle outside root_box,
+ * FMM_ENOMEM / FMM_EDEVICE on allocation or runtime failures.  *out owns its device
+ * memory until fmm_atree_destroy. */
+int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box, void *stream,
+                    fmm_atree **out);
+
+/* Host: sizes[FMM_AT_COUNT] (see the enum), root_box[3] (may be NULL). */
+int fmm_atree_info(const fmm_atree *tree, int64_t *sizes, double *root_box);
+
+/* Host arrays of n entries, user order: level, ix and iy of each particle's leaf
+ * (cell coordinates on the leaf's level).  Any of the three may be NULL. */
+int fmm_atree_leaves(const fmm_atree *tree, int32_t *level, int32_t *ix, int32_t *iy);
+
+/* Velocities (u, v) of every particle (device, (n, 2), user order) from circulations
+ * gamma (device, n, user order), blob core sigma > 0, p terms (1..32) and precision
+ * FMM_FP64 or FMM_MIXED (near-field pairs in FP32 on leaf-relative records, every
+ * expansion in FP64).  The far field (P2M, M2M, M2L, P2L, L2L) runs on side_stream (NULL:
+ * a stream owned by the tree) concurrently with the near field on main_stream; the call
+ * is ordered after prior work on main_stream and its results are complete in stream
+ * order on main_stream. */
+int fmm_atree_velocity(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
+                       void *main_stream, void *side_stream, double *uv);
+
+/* As fmm_atree_velocity, with the near-field (U) and far-field (V, W, X and the tree
+ * translations) parts in separate outputs. */
+int fmm_atree_velocity_parts(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
+                             void *main_stream, void *side_stream, double *uv_near, double *uv_far);
+
+/* Frees the tree and its device memory (after the device work using it is done);
+ * NULL is ignored. */
+void fmm_atree_destroy(fmm_atree *tree);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

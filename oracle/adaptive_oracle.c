@@ -327,7 +327,7 @@ static int build_lists(atree *t)
 int orc_atree_build(int64_t n, const double *xy, const double *root, int smax, int lmax, atree **out)
 {
     *out = NULL;
-    if (n < 1 || smax < 1 || lmax < 0 || lmax > 20 || !(root[2] > 0.0)) return ORC_EINVAL;
+    if (n < 1 || smax < 1 || lmax < 0 || lmax > 15 || !(root[2] > 0.0)) return ORC_EINVAL;
     atree *t = calloc(1, sizeof(atree));
     int32_t *ix = malloc(sizeof(int32_t) * n), *iy = malloc(sizeof(int32_t) * n);
     if (!t || !ix || !iy) {

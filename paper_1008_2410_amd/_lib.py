@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/fmm2d.h (argument marshalling only)."""
+"""ctypes declarations of the C ABI in include/fmm2d.h and include/fmm2d_adaptive.h
+(argument marshalling only)."""
 from __future__ import annotations
 
 import ctypes
@@ -34,7 +35,15 @@ SIGNATURES = {
     "fmm_near_plan_info": (_I, [_P, _P, _P, _P]),
     "fmm_destroy_tree": (None, [_P]),
     "fmm_last_error": (ctypes.c_char_p, []),
+    # include/fmm2d_adaptive.h
+    "fmm_atree_build": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fmm_atree_info": (_I, [_P, _P, _P]),
+    "fmm_atree_leaves": (_I, [_P, _P, _P, _P]),
+    "fmm_atree_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
+    "fmm_atree_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
+    "fmm_atree_destroy": (None, [_P]),
 }
+FMM_AT_KEYS = ("cells", "leaves", "u", "v", "w", "x", "deepest", "p2p_pairs")
 
 _lib = None
 

@@ -1,0 +1,537 @@
+// C ABI of the adaptive-tree variant (include/fmm2d_adaptive.h): the tree, its lists
+// and work units built on the host, the evaluation enqueued on the device
+// (adaptive.hip).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fmm2d_adaptive.h"
+#include "adaptive_internal.h"
+#include "api_common.h"
+#include "fmm_internal.h"
+
+using namespace fmm;
+
+namespace {
+
+void free_ws(AtreeWs &w)
+{
+    hipFree(w.rec);
+    hipFree(w.gamma);
+    hipFree(w.near);
+    hipFree(w.mp);
+    hipFree(w.lo);
+    hipFree(w.binom);
+    w = AtreeWs{};
+}
+
+void free_atree(fmm_atree *t)
+{
+    if (!t) return;
+    AtreeDev &d = t->d;
+    for (void *p : {(void *)d.perm, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
+                    (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
+                    (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
+                    (void *)d.p2m_cells, (void *)d.inner, (void *)d.tile_start, (void *)d.tile_box,
+                    (void *)d.units})
+        hipFree(p);
+    free_ws(t->ws);
+    if (t->ev_fork) hipEventDestroy(t->ev_fork);
+    if (t->ev_join) hipEventDestroy(t->ev_join);
+    if (t->own_side) hipStreamDestroy(t->own_side);
+    delete t;
+}
+
+struct HostCell {
+    int level;
+    uint64_t code;   // Morton index on its level
+    int ix, iy;
+    int first, count;
+    int parent;
+    int child[4];
+    bool leaf;
+};
+
+// The tree and its lists, from the particles' Morton keys at depth L sorted ascending.
+struct HostTree {
+    int L = 0, smax = 1;
+    std::vector<HostCell> cells;
+    std::unordered_map<uint64_t, int> at;  // (level, ix, iy) -> cell
+    std::vector<std::vector<int>> U, V, W, X;
+
+    static uint64_t pos_key(int level, int ix, int iy)
+    {
+        return ((uint64_t)level << 40) | ((uint64_t)(uint32_t)ix << 20) | (uint64_t)(uint32_t)iy;
+    }
+    int find(int level, int ix, int iy) const
+    {
+        if (ix < 0 || iy < 0 || ix >= (1 << level) || iy >= (1 << level)) return -1;
+        auto it = at.find(pos_key(level, ix, iy));
+        return it == at.end() ? -1 : it->second;
+    }
+    // closed squares intersect, compared in units of the depth-L cell
+    bool touch(int a, int b) const
+    {
+        const HostCell &A = cells[a], &B = cells[b];
+        const int64_t sa = int64_t(1) << (L - A.level), sb = int64_t(1) << (L - B.level);
+        return A.ix * sa <= (B.ix + 1) * sb && B.ix * sb <= (A.ix + 1) * sa && A.iy * sa <= (B.iy + 1) * sb &&
+               B.iy * sb <= (A.iy + 1) * sa;
+    }
+    // same-level cells adjacent to cell k
+    void neighbours(int k, std::vector<int> &out) const
+    {
+        out.clear();
+        const HostCell &c = cells[k];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                const int j = find(c.level, c.ix + dx, c.iy + dy);
+                if (j >= 0) out.push_back(j);
+            }
+    }
+
+    void build(const std::vector<uint32_t> &keys, int n)
+    {
+        cells.clear();
+        cells.push_back({0, 0, 0, 0, 0, n, -1, {-1, -1, -1, -1}, true});
+        for (size_t k = 0; k < cells.size(); ++k) {
+            const HostCell c = cells[k];
+            if (c.count <= smax || c.level >= L) continue;
+            cells[k].leaf = false;
+            const int shift = 2 * (L - c.level - 1);
+            int lo = c.first;
+            const int end = c.first + c.count;
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t next = c.code * 4 + q + 1;  // first key code of the next quadrant
+                const int hi = (int)(std::partition_point(keys.begin() + lo, keys.begin() + end,
+                                                          [&](uint32_t key) { return ((uint64_t)key >> shift) < next; }) -
+                                     keys.begin());
+                if (hi > lo) {
+                    HostCell ch{c.level + 1, c.code * 4 + q, 2 * c.ix + (q & 1), 2 * c.iy + (q >> 1), lo, hi - lo,
+                                (int)k, {-1, -1, -1, -1}, true};
+                    cells[k].child[q] = (int)cells.size();
+                    cells.push_back(ch);
+                }
+                lo = hi;
+            }
+        }
+        at.reserve(cells.size() * 2);
+        for (size_t k = 0; k < cells.size(); ++k) at[pos_key(cells[k].level, cells[k].ix, cells[k].iy)] = (int)k;
+    }
+
+    void lists()
+    {
+        const int K = (int)cells.size();
+        U.assign(K, {});
+        V.assign(K, {});
+        W.assign(K, {});
+        X.assign(K, {});
+        std::vector<int> nb, nbp, stack;
+        for (int k = 0; k < K; ++k) {
+            const HostCell &c = cells[k];
+            neighbours(k, nb);
+            if (c.parent >= 0) {  // V: children of the parent's neighbours, not touching
+                neighbours(c.parent, nbp);
+                for (int P : nbp)
+                    for (int ch : cells[P].child)
+                        if (ch >= 0 && !touch(ch, k)) V[k].push_back(ch);
+            }
+            if (!c.leaf) continue;
+            U[k].push_back(k);
+            for (int C : nb) {  // leaves at or below the neighbours that touch; W
+                stack.assign(1, C);
+                while (!stack.empty()) {
+                    const int d = stack.back();
+                    stack.pop_back();
+                    if (!touch(d, k)) {
+                        W[k].push_back(d);  // its parent touches (C itself always does)
+                        continue;
+                    }
+                    if (cells[d].leaf) {
+                        U[k].push_back(d);
+                        continue;
+                    }
+                    for (int q = 3; q >= 0; --q)
+                        if (cells[d].child[q] >= 0) stack.push_back(cells[d].child[q]);
+                }
+            }
+            for (int a = c.parent; a >= 0; a = cells[a].parent) {  // coarser leaves touching k
+                neighbours(a, nbp);
+                for (int C : nbp)
+                    if (cells[C].leaf && touch(C, k)) U[k].push_back(C);
+            }
+        }
+        for (int a = 0; a < K; ++a)
+            for (int d : W[a]) X[d].push_back(a);
+    }
+};
+
+template <typename T>
+void flatten(const std::vector<std::vector<T>> &lists, std::vector<int> &off, std::vector<T> &idx)
+{
+    off.assign(lists.size() + 1, 0);
+    for (size_t k = 0; k < lists.size(); ++k) off[k + 1] = off[k] + (int)lists[k].size();
+    idx.clear();
+    idx.reserve(off.back());
+    for (const auto &l : lists) idx.insert(idx.end(), l.begin(), l.end());
+}
+
+struct Busy {
+    fmm_atree *t;
+    bool ok;
+    explicit Busy(fmm_atree *tree) : t(tree), ok(tree->busy.exchange(1) == 0) {}
+    ~Busy()
+    {
+        if (ok) t->busy.store(0);
+    }
+};
+
+int ensure_ws(fmm_atree *t, int p, int precision)
+{
+    AtreeWs &w = t->ws;
+    if (w.rec && w.p == p && w.precision == precision) return FMM_OK;
+    if (w.rec) {
+        HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the old workspace
+        free_ws(w);
+    }
+    const size_t n = (size_t)t->n;
+    const size_t coef = (size_t)t->ncells * p + kCoefPad;
+    int rc;
+    if ((rc = dev_alloc((char **)&w.rec, n * (precision == FMM_FP64 ? sizeof(double4) : sizeof(float4)), "records")) ||
+        (rc = dev_alloc(&w.gamma, n, "circulations")) || (rc = dev_alloc(&w.near, n, "near field")) ||
+        (rc = dev_alloc(&w.mp, coef, "multipoles")) || (rc = dev_alloc(&w.lo, coef, "locals"))) {
+        free_ws(w);
+        return rc;
+    }
+    const int nb = 2 * p + 1;
+    std::vector<double> binom((size_t)nb * nb, 0.0);
+    for (int a = 0; a < nb; ++a) {
+        binom[(size_t)a * nb] = 1.0;
+        for (int k = 1; k <= a; ++k)
+            binom[(size_t)a * nb + k] = binom[(size_t)(a - 1) * nb + k - 1] + (k < a ? binom[(size_t)(a - 1) * nb + k] : 0.0);
+    }
+    if ((rc = upload(&w.binom, binom, "binomial table"))) {
+        free_ws(w);
+        return rc;
+    }
+    w.p = p;
+    w.precision = precision;
+    return FMM_OK;
+}
+
+int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, void *main_stream, void *side_stream,
+        double *uv, double *uv_near, double *uv_far)
+{
+    clear_last_error();
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!gamma) return fail(FMM_EINVAL, "gamma is NULL");
+    if (!uv && !(uv_near && uv_far)) return fail(FMM_EINVAL, "output is NULL");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FMM_EINVAL, "sigma must be finite and > 0");
+    if (p < 1 || p > kMaxP) return fail(FMM_EINVAL, "p must be in [1, 32]");
+    if (precision != FMM_FP64 && precision != FMM_MIXED) return fail(FMM_EINVAL, "unknown precision");
+    Busy guard(t);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
+    HIP_TRY(hipSetDevice(t->device));
+    int rc = ensure_ws(t, p, precision);
+    if (rc) return rc;
+    hipStream_t ms = (hipStream_t)main_stream;
+    hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision)};
+    launch_atree_pack(c, gamma, ms);
+    HIP_TRY(hipEventRecord(t->ev_fork, ms));
+    HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
+    launch_atree_far(c, ss);  // P2M, M2M, M2L + P2L + L2L
+    HIP_TRY(hipEventRecord(t->ev_join, ss));
+    launch_atree_near(c, ms);  // P2P over U, beside the far field
+    HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    launch_atree_finalize(c, uv, uv_near, uv_far, ms);  // L2P + M2P + sum
+    HIP_TRY(hipGetLastError());
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
+                               void *stream, fmm_atree **out)
+{
+    clear_last_error();
+    if (!out) return fail(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!xy) return fail(FMM_EINVAL, "xy is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(FMM_EINVAL, "n must be in [1, 2^31)");
+    if (max_leaf < 1) return fail(FMM_EINVAL, "max_leaf must be >= 1");
+    if (max_depth < 0 || max_depth > 15) return fail(FMM_EINVAL, "max_depth must be in [0, 15]");
+    if (root_box && (!std::isfinite(root_box[0]) || !std::isfinite(root_box[1]) || !(root_box[2] > 0.0) ||
+                     !std::isfinite(root_box[2])))
+        return fail(FMM_EINVAL, "root_box must be finite with side > 0");
+    fmm_atree *t = new (std::nothrow) fmm_atree;
+    if (!t) return fail(FMM_ENOMEM, "host allocation failed");
+    t->n = n;
+    t->max_leaf = max_leaf;
+    t->max_depth = max_depth;
+    int rc = FMM_OK;
+    try {
+        hipError_t e = hipGetDevice(&t->device);
+        std::vector<double> h(2 * (size_t)n);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) {
+            free_atree(t);
+            return hip_fail(e, "copying positions to the host");
+        }
+        for (double v : h)
+            if (!std::isfinite(v)) {
+                free_atree(t);
+                return fail(FMM_EINVAL, "non-finite particle position");
+            }
+        if (root_box) {
+            t->x0 = root_box[0];
+            t->y0 = root_box[1];
+            t->side = root_box[2];
+        } else {
+            double xmin = h[0], xmax = h[0], ymin = h[1], ymax = h[1];
+            for (int64_t i = 1; i < n; ++i) {
+                xmin = std::min(xmin, h[2 * i]);
+                xmax = std::max(xmax, h[2 * i]);
+                ymin = std::min(ymin, h[2 * i + 1]);
+                ymax = std::max(ymax, h[2 * i + 1]);
+            }
+            double side = std::max(xmax - xmin, ymax - ymin);
+            if (side <= 0.0) side = 1.0;
+            t->x0 = xmin;
+            t->y0 = ymin;
+            t->side = side * (1.0 + 1.0 / 1048576.0);
+        }
+        // binning at max_depth (as fmm_build_tree at that depth), Morton keys
+        const int L = max_depth;
+        const int64_t nside = int64_t(1) << L;
+        const double w = t->side / (double)nside;
+        std::vector<uint32_t> key((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t c[2];
+            for (int d = 0; d < 2; ++d) {
+                const double v = (h[2 * i + d] - (d ? t->y0 : t->x0)) / w;
+                if (!(v >= 0.0) || v > (double)nside) {
+                    free_atree(t);
+                    char buf[160];
+                    snprintf(buf, sizeof buf, "particle %lld lies outside the root cell", (long long)i);
+                    return fail(FMM_ERANGE, buf);
+                }
+                c[d] = (uint32_t)std::min<int64_t>((int64_t)std::floor(v), nside - 1);
+            }
+            key[i] = morton_encode(c[0], c[1]);
+        }
+        // stable LSD radix sort of the particles by key (two 16-bit digits)
+        std::vector<int> order((size_t)n), tmp((size_t)n);
+        for (int64_t i = 0; i < n; ++i) order[i] = (int)i;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<int64_t> cnt(65537, 0);
+            const int sh = 16 * pass;
+            for (int64_t i = 0; i < n; ++i) cnt[((key[order[i]] >> sh) & 0xffff) + 1]++;
+            for (int b = 0; b < 65536; ++b) cnt[b + 1] += cnt[b];
+            for (int64_t i = 0; i < n; ++i) tmp[cnt[(key[order[i]] >> sh) & 0xffff]++] = order[i];
+            order.swap(tmp);
+        }
+        std::vector<uint32_t> skey((size_t)n);
+        for (int64_t j = 0; j < n; ++j) skey[j] = key[order[j]];
+
+        HostTree ht;
+        ht.L = L;
+        ht.smax = max_leaf;
+        ht.build(skey, (int)n);
+        ht.lists();
+        const int K = (int)ht.cells.size();
+        t->ncells = K;
+
+        // levels, leaves, sizes
+        t->level_off.assign(L + 2, 0);
+        t->inner_off.assign(L + 2, 0);
+        std::vector<int> p2m, inner;
+        std::vector<int4> cell(K);
+        std::vector<int2> range(K);
+        std::vector<int> parent(K), tile_start(K, 0), leaf_sorted((size_t)n);
+        std::vector<int4> child(K);
+        int64_t leaves = 0, deepest = 0, pairs = 0;
+        for (int k = 0; k < K; ++k) {
+            const HostCell &c = ht.cells[k];
+            t->level_off[c.level + 1]++;
+            cell[k] = make_int4(c.level, c.ix, c.iy, c.leaf ? 1 : 0);
+            range[k] = make_int2(c.first, c.count);
+            parent[k] = c.parent;
+            child[k] = make_int4(c.child[0], c.child[1], c.child[2], c.child[3]);
+            if (c.leaf) {
+                leaves++;
+                deepest = std::max<int64_t>(deepest, c.level);
+                int64_t s = 0;
+                for (int S : ht.U[k]) s += ht.cells[S].count;
+                pairs += (int64_t)c.count * s - c.count;
+                for (int j = c.first; j < c.first + c.count; ++j) leaf_sorted[j] = k;
+                if (c.level >= 2) p2m.push_back(k);
+            }
+        }
+        for (int l = 0; l <= L; ++l) t->level_off[l + 1] += t->level_off[l];
+        for (int l = 0; l <= L; ++l) {
+            t->inner_off[l] = (int)inner.size();
+            for (int k = t->level_off[l]; k < t->level_off[l + 1]; ++k)
+                if (!ht.cells[k].leaf && l >= 2) inner.push_back(k);
+        }
+        t->inner_off[L + 1] = (int)inner.size();
+        int64_t lsum[4] = {0, 0, 0, 0};
+        for (int k = 0; k < K; ++k) {
+            lsum[0] += (int64_t)ht.U[k].size();
+            lsum[1] += (int64_t)ht.V[k].size();
+            lsum[2] += (int64_t)ht.W[k].size();
+            lsum[3] += (int64_t)ht.X[k].size();
+        }
+        const int64_t sz[8] = {K, leaves, lsum[0], lsum[1], lsum[2], lsum[3], deepest, pairs};
+        std::copy(sz, sz + 8, t->sizes);
+        t->np2m = (int64_t)p2m.size();
+
+        // per-particle leaf in user order (host copy for fmm_atree_leaves)
+        t->leaf_level.resize((size_t)n);
+        t->leaf_ix.resize((size_t)n);
+        t->leaf_iy.resize((size_t)n);
+        for (int64_t j = 0; j < n; ++j) {
+            const HostCell &c = ht.cells[leaf_sorted[j]];
+            t->leaf_level[order[j]] = c.level;
+            t->leaf_ix[order[j]] = c.ix;
+            t->leaf_iy[order[j]] = c.iy;
+        }
+
+        // 64-particle tiles of each leaf with their boxes; near-field units, heaviest first
+        std::vector<double2> xs((size_t)n);
+        for (int64_t j = 0; j < n; ++j) xs[j] = make_double2(h[2 * order[j]], h[2 * order[j] + 1]);
+        std::vector<double4> boxes;
+        std::vector<int4> units;
+        std::vector<int64_t> cost;
+        for (int k = 0; k < K; ++k) {
+            const HostCell &c = ht.cells[k];
+            if (!c.leaf) continue;
+            tile_start[k] = (int)boxes.size();
+            int64_t src = 0;
+            for (int S : ht.U[k]) src += ht.cells[S].count;
+            for (int b = c.first; b < c.first + c.count; b += 64) {
+                const int len = std::min(64, c.first + c.count - b);
+                double4 bx = make_double4(1e300, 1e300, -1e300, -1e300);
+                for (int j = b; j < b + len; ++j) {
+                    const double x = xs[j].x - t->x0, y = xs[j].y - t->y0;
+                    bx.x = std::min(bx.x, x);
+                    bx.y = std::min(bx.y, y);
+                    bx.z = std::max(bx.z, x);
+                    bx.w = std::max(bx.w, y);
+                }
+                boxes.push_back(bx);
+                int logtp = 0;
+                while ((1 << logtp) < len) ++logtp;
+                units.push_back(make_int4(k, b, len, logtp));
+                cost.push_back((int64_t)len * src);
+            }
+        }
+        std::vector<int> uorder(units.size());
+        for (size_t u = 0; u < units.size(); ++u) uorder[u] = (int)u;
+        std::stable_sort(uorder.begin(), uorder.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<int4> sunits(units.size());
+        for (size_t u = 0; u < units.size(); ++u) sunits[u] = units[uorder[u]];
+        t->ntiles = (int64_t)boxes.size();
+        t->nunits = (int64_t)sunits.size();
+
+        std::vector<int> uo, ui, vo, vi, wo, wi, xo, xi;
+        flatten(ht.U, uo, ui);
+        flatten(ht.V, vo, vi);
+        flatten(ht.W, wo, wi);
+        flatten(ht.X, xo, xi);
+
+        AtreeDev &d = t->d;
+        hipError_t es = hipSetDevice(t->device);
+        rc = es != hipSuccess ? hip_fail(es, "hipSetDevice") : upload(&d.perm, order, "permutation");
+        if (!rc) rc = upload(&d.leaf_of, leaf_sorted, "leaf of each particle");
+        if (!rc) rc = upload(&d.xy, xs, "sorted positions");
+        if (!rc) rc = upload(&d.cell, cell, "cells");
+        if (!rc) rc = upload(&d.range, range, "cell ranges");
+        if (!rc) rc = upload(&d.parent, parent, "parents");
+        if (!rc) rc = upload(&d.child, child, "children");
+        if (!rc) rc = upload(&d.u_off, uo, "U list");
+        if (!rc) rc = upload(&d.u_idx, ui, "U list");
+        if (!rc) rc = upload(&d.v_off, vo, "V list");
+        if (!rc) rc = upload(&d.v_idx, vi, "V list");
+        if (!rc) rc = upload(&d.w_off, wo, "W list");
+        if (!rc) rc = upload(&d.w_idx, wi, "W list");
+        if (!rc) rc = upload(&d.x_off, xo, "X list");
+        if (!rc) rc = upload(&d.x_idx, xi, "X list");
+        if (!rc) rc = upload(&d.p2m_cells, p2m, "leaves with expansions");
+        if (!rc) rc = upload(&d.inner, inner, "split cells");
+        if (!rc) rc = upload(&d.tile_start, tile_start, "tiles");
+        if (!rc) rc = upload(&d.tile_box, boxes, "tile boxes");
+        if (!rc) rc = upload(&d.units, sunits, "near-field units");
+        if (!rc) {
+            hipError_t e2 = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
+            if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
+            if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
+            if (e2 != hipSuccess) rc = hip_fail(e2, "creating the side stream");
+        }
+    } catch (const std::bad_alloc &) {
+        rc = fail(FMM_ENOMEM, "host allocation failed while building the adaptive tree");
+    }
+    if (rc) {
+        free_atree(t);
+        return rc;
+    }
+    *out = t;
+    return FMM_OK;
+}
+
+extern "C" int fmm_atree_info(const fmm_atree *t, int64_t *sizes, double *root_box)
+{
+    clear_last_error();
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!sizes) return fail(FMM_EINVAL, "sizes is NULL");
+    std::copy(t->sizes, t->sizes + FMM_AT_COUNT, sizes);
+    if (root_box) {
+        root_box[0] = t->x0;
+        root_box[1] = t->y0;
+        root_box[2] = t->side;
+    }
+    return FMM_OK;
+}
+
+extern "C" int fmm_atree_leaves(const fmm_atree *t, int32_t *level, int32_t *ix, int32_t *iy)
+{
+    clear_last_error();
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (level) std::copy(t->leaf_level.begin(), t->leaf_level.end(), level);
+    if (ix) std::copy(t->leaf_ix.begin(), t->leaf_ix.end(), ix);
+    if (iy) std::copy(t->leaf_iy.begin(), t->leaf_iy.end(), iy);
+    return FMM_OK;
+}
+
+extern "C" int fmm_atree_velocity(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
+                                  void *main_stream, void *side_stream, double *uv)
+{
+    if (!uv) {
+        clear_last_error();
+        return fail(FMM_EINVAL, "uv is NULL");
+    }
+    return run(t, gamma, sigma, p, precision, main_stream, side_stream, uv, nullptr, nullptr);
+}
+
+extern "C" int fmm_atree_velocity_parts(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
+                                        void *main_stream, void *side_stream, double *uv_near, double *uv_far)
+{
+    if (!uv_near || !uv_far) {
+        clear_last_error();
+        return fail(FMM_EINVAL, "uv_near / uv_far is NULL");
+    }
+    return run(t, gamma, sigma, p, precision, main_stream, side_stream, nullptr, uv_near, uv_far);
+}
+
+extern "C" void fmm_atree_destroy(fmm_atree *t)
+{
+    if (!t) return;
+    hipSetDevice(t->device);
+    free_atree(t);
+}

@@ -1,0 +1,79 @@
+// Internal layout of the adaptive tree (fmm2d_adaptive.h) and the launchers of its
+// kernels (adaptive.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <vector>
+
+namespace fmm {
+
+// Device arrays of one adaptive tree.  Cells are numbered level by level (the cells
+// of level l are [level_off[l], level_off[l+1])), in Morton order inside a level;
+// particles are sorted by their Morton key at max_depth, so every cell's particles
+// are one contiguous range.  Lists are CSR over cells (int offsets, int cell ids).
+struct AtreeDev {
+    int *perm = nullptr;        // sorted slot -> user index
+    int *leaf_of = nullptr;     // sorted slot -> leaf cell
+    double2 *xy = nullptr;      // positions, sorted
+    int4 *cell = nullptr;       // {level, ix, iy, is_leaf}
+    int2 *range = nullptr;      // {first sorted slot, count}
+    int *parent = nullptr;      // -1 for the root
+    int4 *child = nullptr;      // four quadrants (q = x bit | y bit << 1), -1 when empty
+    int *u_off = nullptr, *u_idx = nullptr;
+    int *v_off = nullptr, *v_idx = nullptr;
+    int *w_off = nullptr, *w_idx = nullptr;
+    int *x_off = nullptr, *x_idx = nullptr;
+    int *p2m_cells = nullptr;   // leaves of level >= 2
+    int *inner = nullptr;       // split cells of level >= 2, grouped by level (inner_off)
+    int *tile_start = nullptr;  // per cell: first 64-particle tile of a leaf
+    double4 *tile_box = nullptr;  // per tile: {xmin, ymin, xmax, ymax} relative to (x0, y0)
+    int4 *units = nullptr;      // near-field work units {leaf, first, count, log2 TP}, heaviest first
+};
+
+struct AtreeWs {
+    int p = 0, precision = -1;
+    void *rec = nullptr;        // float4 or double4 records {alpha (z - c_leaf), Gamma, 0}
+    double *gamma = nullptr;    // circulations, sorted
+    double2 *near = nullptr;    // near-field (u, v), sorted
+    double2 *mp = nullptr;      // multipoles a_m / w^m, cells x p
+    double2 *lo = nullptr;      // locals b_l w^(l+1), cells x p
+    double *binom = nullptr;    // C(a, k), a, k <= 2p, row-major (2p + 1)^2
+};
+
+}  // namespace fmm
+
+struct fmm_atree {
+    int device = 0;
+    int64_t n = 0;
+    int max_leaf = 0, max_depth = 0;
+    double x0 = 0, y0 = 0, side = 1;
+    int64_t sizes[8] = {};
+    int64_t ncells = 0, ntiles = 0, nunits = 0, np2m = 0;
+    std::vector<int> level_off;   // max_depth + 2 entries
+    std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
+    std::vector<int> leaf_level, leaf_ix, leaf_iy;  // per particle, user order (host)
+    fmm::AtreeDev d;
+    fmm::AtreeWs ws;
+    hipStream_t own_side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::atomic<int> busy{0};
+};
+
+namespace fmm {
+
+struct AtreeCall {
+    const fmm_atree *t;
+    int p;
+    int is_double;
+    double alpha;   // record scale (as for the uniform tree)
+};
+
+void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
+void launch_atree_far(const AtreeCall &c, hipStream_t s);
+void launch_atree_near(const AtreeCall &c, hipStream_t s);
+void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, hipStream_t s);
+
+}  // namespace fmm

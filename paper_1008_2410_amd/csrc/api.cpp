@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/fmm2d.h"
+#include "api_common.h"
 #include "fmm_internal.h"
 
 using namespace fmm;
@@ -18,46 +19,6 @@ using namespace fmm;
 namespace {
 
 thread_local std::string g_last_error;
-
-int fail(int code, const std::string &msg)
-{
-    g_last_error = msg;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char *what)
-{
-    return fail(FMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define HIP_TRY(expr)                                         \
-    do {                                                      \
-        hipError_t e_ = (expr);                               \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
-    } while (0)
-
-template <typename T>
-int dev_alloc(T **p, size_t count, const char *what)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(FMM_ENOMEM, std::string("device allocation failed: ") + what);
-    }
-    return FMM_OK;
-}
-
-template <typename T>
-int upload(T **p, const std::vector<T> &h, const char *what)
-{
-    int rc = dev_alloc(p, h.size(), what);
-    if (rc) return rc;
-    if (!h.empty()) HIP_TRY(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-    return FMM_OK;
-}
 
 // RAII guard for "one host thread per handle".
 struct BusyGuard {
@@ -195,13 +156,6 @@ int check_eval_args(fmm_tree *t, const double *gamma, double sigma, int p, int p
     return FMM_OK;
 }
 
-// Coordinate scale of the near-field records: exponent of the pair kernel is -s (FP64,
-// natural exp) or -s in base 2 (FP32) with s = |alpha dz|^2.
-double record_alpha(double sigma, int precision)
-{
-    const double a = 1.0 / (sigma * std::sqrt(2.0));
-    return precision == FMM_FP64 ? a : a * std::sqrt(1.4426950408889634073599246810019);
-}
 
 FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
 {
@@ -851,6 +805,20 @@ extern "C" void fmm_destroy_tree(fmm_tree *t)
     hipSetDevice(t->device);
     hipDeviceSynchronize();
     free_tree(t);
+}
+
+int fmm::fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+void fmm::clear_last_error() { g_last_error.clear(); }
+
+double fmm::record_alpha(double sigma, int precision)
+{
+    const double a = 1.0 / (sigma * std::sqrt(2.0));
+    return precision == FMM_FP64 ? a : a * std::sqrt(1.4426950408889634073599246810019);
 }
 
 extern "C" const char *fmm_last_error(void) { return g_last_error.c_str(); }

@@ -169,6 +169,81 @@ class Tree:
         return (dg, dx, ds) if need_src else (dg, dx)
 
 
+class ATree:
+    """Adaptive quadtree over n particles for uneven distributions (include/fmm2d_adaptive.h):
+    cells split while they hold more than max_leaf particles, down to max_depth, and the
+    U, V, W, X lists of the adaptive FMM, resident on the device.  Built on the host."""
+
+    def __init__(self, xy: torch.Tensor, max_leaf: int, max_depth: int, root_box=None, stream=None):
+        if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be an (n, 2) tensor")
+        self.device = xy.device
+        xy = _as_device_f64(xy, "xy", tuple(xy.shape), None)
+        self.n = int(xy.shape[0])
+        self.max_leaf, self.max_depth = int(max_leaf), int(max_depth)
+        handle = ctypes.c_void_p()
+        rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_atree_build(_ptr(xy), self.n, self.max_leaf, self.max_depth, rb, _stream_ptr(stream),
+                                             ctypes.byref(handle)), "fmm_atree_build")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().fmm_atree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("tree is closed")
+        return self._h
+
+    def info(self) -> dict:
+        """Sizes of the tree and its lists (keys of _lib.FMM_AT_KEYS) and the root cell."""
+        sizes = (ctypes.c_int64 * 8)()
+        root = (ctypes.c_double * 3)()
+        L.check(L.load().fmm_atree_info(self.handle, sizes, root), "fmm_atree_info")
+        out = {k: int(v) for k, v in zip(L.FMM_AT_KEYS, sizes)}
+        out["root_box"] = tuple(root)
+        return out
+
+    def leaves(self):
+        """(level, ix, iy) of each particle's leaf, numpy int32 arrays in user order."""
+        import numpy as np
+        lv, ix, iy = (np.zeros(self.n, dtype=np.int32) for _ in range(3))
+        L.check(L.load().fmm_atree_leaves(self.handle, lv.ctypes.data_as(ctypes.c_void_p),
+                                          ix.ctypes.data_as(ctypes.c_void_p), iy.ctypes.data_as(ctypes.c_void_p)),
+                "fmm_atree_leaves")
+        return lv, ix, iy
+
+    def velocity(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed", out=None) -> torch.Tensor:
+        """(n, 2) float64 velocities in user order."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        uv = out if out is not None else torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_atree_velocity(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                                _stream_ptr(), None, _ptr(uv)), "fmm_atree_velocity")
+        return uv
+
+    def velocity_parts(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed"):
+        """(near, far) velocities, each (n, 2) float64 in user order."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        near = torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        far = torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_atree_velocity_parts(self.handle, _ptr(g), float(sigma), int(p),
+                                                      _precision(precision), _stream_ptr(), None, _ptr(near),
+                                                      _ptr(far)), "fmm_atree_velocity_parts")
+        return near, far
+
+
 class VelocityFn(torch.autograd.Function):
     """u = FMM velocity of the particles of `tree` with circulations gamma.
 
