@@ -203,6 +203,72 @@ def rk2_leg(torch, dev, workloads):
     }), flush=True)
 
 
+def adaptive_leg(torch, dev, workloads):
+    """Uneven distributions: the adaptive tree (leaves capped at max_leaf particles) against
+    the uniform tree at several depths, on the 2^24-particle patch workload (depth <= 10,
+    every leaf wider than 8 sigma) and on a clustered workload with a uniform background
+    (density range 1e5).  Per tree: build time (host for the adaptive tree, device for the
+    uniform one), the mixed evaluation's device time, near-field pairs, and the error
+    against the direct sum on sampled particles.  One JSON line of its own."""
+    import oracle
+    from paper_1008_2410_amd import fmm
+    oracle.build()
+
+    def dev_ms(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    result = {"metric": "ms per mixed velocity evaluation, adaptive vs uniform tree", "unit": "ms",
+              "higher_is_better": False, "workloads": []}
+    cases = ((workloads.gaussian_patches(), (9, 10), ((32, 10), (64, 10), (128, 10), (256, 10))),
+             (workloads.clustered_background(), (11, 12), ((32, 15), (64, 15), (128, 15), (256, 15))))
+    for w, depths, cfgs in cases:
+        xy = torch.from_numpy(w.xy).to(dev)
+        g = torch.from_numpy(w.gamma).to(dev)
+        out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
+        idx = w.extra["sample"][:256]
+        t0 = time.perf_counter()
+        ref = oracle.direct(w.xy, w.gamma, w.sigma, targets=w.xy[idx])
+        log(f"[adaptive] {w.name}: direct sum on {len(idx)} particles in {time.perf_counter() - t0:.1f} s")
+        rows = []
+        for kind, a, b in [("uniform", d, None) for d in depths] + [("adaptive", s, l) for s, l in cfgs]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tree = fmm.Tree(xy, a, None) if kind == "uniform" else fmm.ATree(xy, a, b)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - t0
+            info = tree.info()
+            ms = dev_ms(lambda: tree.velocity(g, w.sigma, w.p, "mixed", out=out), 5)
+            err = rel_l2(out.cpu().numpy()[idx], ref)
+            row = {"tree": kind, "build_s": round(t_build, 3), "ms": round(ms, 3), "rel_l2_vs_direct": float(f"{err:.3e}"),
+                   "p2p_pairs": info["p2p_pairs"]}
+            if kind == "uniform":
+                row["depth"] = a
+            else:
+                row.update(max_leaf=a, max_depth=b, cells=info["cells"], leaves=info["leaves"], deepest=info["deepest"],
+                           v=info["v"], w=info["w"])
+            log(f"[adaptive] {w.name}: {row}")
+            rows.append(row)
+            tree.close()
+        ok = [r for r in rows if r["rel_l2_vs_direct"] <= 1e-5]
+        best_u = min((r for r in ok if r["tree"] == "uniform"), key=lambda r: r["ms"], default=None)
+        best_a = min((r for r in ok if r["tree"] == "adaptive"), key=lambda r: r["ms"], default=None)
+        result["workloads"].append({
+            "workload": w.name, "n": w.n, "sigma": w.sigma, "p": w.p, "trees": rows,
+            "best_uniform_ms": best_u and best_u["ms"], "best_adaptive_ms": best_a and best_a["ms"],
+            "speedup_at_1e-5": round(best_u["ms"] / best_a["ms"], 3) if best_u and best_a else None})
+        del xy, g, out
+        torch.cuda.empty_cache()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +289,9 @@ def main():
     ap.add_argument("--rk2", action="store_true",
                     help="only the time-stepped workload (2^25 particles, 16 patches, 5 midpoint-RK2 steps, trees "
                          "rebuilt per evaluation): forward and adjoint, one JSON line of its own")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="only the uneven-distribution comparison (adaptive tree against uniform depths on the "
+                         "patch workload and on a clustered workload): one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -247,6 +316,9 @@ def main():
         return
     if args.cost_model:
         cost_model_leg(torch, dev, workloads)
+        return
+    if args.adaptive:
+        adaptive_leg(torch, dev, workloads)
         return
     t0 = time.perf_counter()
     w = workloads.gaussian_patches(n=args.n, depth=args.depth)

@@ -137,6 +137,33 @@ def gaussian_patches(n: int = 1 << 24, n_patches: int = 8, seed: int = 3, depth:
                      "peaks": peaks})
 
 
+def clustered_background(n: int = 1 << 24, n_clusters: int = 8, background: float = 0.5, seed: int = 7,
+                         p: int = 16, sigma: float = 3.5e-6, radius=(0.002, 0.005), precision: str = "mixed",
+                         n_sample: int = 256, sample_seed: int = 34) -> Workload:
+    """An uneven distribution for the adaptive tree: a fraction `background` of the
+    particles uniform on [0, 1]^2, the rest in n_clusters equal Gaussian clusters with
+    centres ~ U[0.2, 0.8]^2 and standard deviations ~ U(radius).  Circulations
+    Gamma_i ~ N(0, 1)/N.  The particle density spans five orders of magnitude, so no
+    single uniform depth suits both the background and the cluster cores; sigma is small
+    enough that leaves down to depth 15 stay wider than 8 sigma.  Root cell: the bounding
+    square.  extra["sample"]: seeded target indices for accuracy checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = int(round(background * n))
+    centres = rng.uniform(0.2, 0.8, size=(n_clusters, 2))
+    radii = rng.uniform(radius[0], radius[1], size=n_clusters)
+    counts = np.full(n_clusters, (n - nb) // n_clusters, dtype=np.int64)
+    counts[: n - nb - counts.sum()] += 1
+    parts = [rng.random((nb, 2))]
+    for k in range(n_clusters):
+        parts.append(centres[k] + radii[k] * rng.standard_normal((counts[k], 2)))
+    xy = np.concatenate(parts)[rng.permutation(n)]
+    gamma = rng.standard_normal(n) / n
+    srng = np.random.Generator(np.random.PCG64(sample_seed))
+    sample = np.sort(srng.choice(n, size=min(n_sample, n), replace=False))
+    return Workload("clustered_background", xy, gamma, sigma, 15, p, None, precision,
+                    {"sample": sample, "centres": centres, "radii": radii})
+
+
 def transport_patches(n: int = 1 << 25, n_patches: int = 16, seed: int = 5, depth: int = 11, p: int = 16,
                       sigma: float = 0.01 / 64, dt: float = 1e-3, steps: int = 5,
                       precision: str = "mixed") -> Workload:
