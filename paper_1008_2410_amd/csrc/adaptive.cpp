@@ -23,9 +23,12 @@ void free_ws(AtreeWs &w)
     hipFree(w.rec);
     hipFree(w.gamma);
     hipFree(w.near);
+    hipFree(w.slots);
     hipFree(w.mp);
     hipFree(w.lo);
     hipFree(w.binom);
+    hipFree(w.binom16);
+    hipFree(w.binom32);
     w = AtreeWs{};
 }
 
@@ -37,7 +40,8 @@ void free_atree(fmm_atree *t)
                     (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
                     (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
                     (void *)d.p2m_cells, (void *)d.inner, (void *)d.tile_start, (void *)d.tile_box,
-                    (void *)d.units})
+                    (void *)d.work, (void *)d.leaf_start, (void *)d.leaf_tile, (void *)d.tile_box_leaf,
+                    (void *)d.mask})
         hipFree(p);
     free_ws(t->ws);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
@@ -203,18 +207,24 @@ int ensure_ws(fmm_atree *t, int p, int precision)
     int rc;
     if ((rc = dev_alloc((char **)&w.rec, n * (precision == FMM_FP64 ? sizeof(double4) : sizeof(float4)), "records")) ||
         (rc = dev_alloc(&w.gamma, n, "circulations")) || (rc = dev_alloc(&w.near, n, "near field")) ||
+        (rc = dev_alloc((char **)&w.slots, 9 * n * (precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
+                        "mutual near-field slots")) ||
         (rc = dev_alloc(&w.mp, coef, "multipoles")) || (rc = dev_alloc(&w.lo, coef, "locals"))) {
         free_ws(w);
         return rc;
     }
-    const int nb = 2 * p + 1;
-    std::vector<double> binom((size_t)nb * nb, 0.0);
-    for (int a = 0; a < nb; ++a) {
-        binom[(size_t)a * nb] = 1.0;
-        for (int k = 1; k <= a; ++k)
-            binom[(size_t)a * nb + k] = binom[(size_t)(a - 1) * nb + k - 1] + (k < a ? binom[(size_t)(a - 1) * nb + k] : 0.0);
-    }
-    if ((rc = upload(&w.binom, binom, "binomial table"))) {
+    auto pascal = [](int nb) {
+        std::vector<double> b((size_t)nb * nb, 0.0);
+        for (int a = 0; a < nb; ++a) {
+            b[(size_t)a * nb] = 1.0;
+            for (int k = 1; k <= a; ++k)
+                b[(size_t)a * nb + k] = b[(size_t)(a - 1) * nb + k - 1] + (k < a ? b[(size_t)(a - 1) * nb + k] : 0.0);
+        }
+        return b;
+    };
+    if ((rc = upload(&w.binom, pascal(2 * p + 1), "binomial table")) ||
+        (rc = upload(&w.binom16, pascal(33), "binomial table")) ||
+        (rc = upload(&w.binom32, pascal(65), "binomial table"))) {
         free_ws(w);
         return rc;
     }
@@ -403,42 +413,114 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
             t->leaf_iy[order[j]] = c.iy;
         }
 
-        // 64-particle tiles of each leaf with their boxes; near-field units, heaviest first
+        // 64-particle tiles of each leaf (leaves in sorted order) with their boxes: absolute
+        // (relative to x0, y0) for the target-centric units, in leaf widths about the leaf
+        // centre, rounded outwards to FP32, for the mutual items
         std::vector<double2> xs((size_t)n);
         for (int64_t j = 0; j < n; ++j) xs[j] = make_double2(h[2 * order[j]], h[2 * order[j] + 1]);
+        std::vector<int> leaves_sorted;
+        for (int k = 0; k < K; ++k)
+            if (ht.cells[k].leaf) leaves_sorted.push_back(k);
+        std::sort(leaves_sorted.begin(), leaves_sorted.end(),
+                  [&](int a, int b) { return ht.cells[a].first < ht.cells[b].first; });
+        const int NL = (int)leaves_sorted.size();
+        std::vector<int> leaf_index(K, -1), leaf_start(NL + 1), leaf_tile(NL);
         std::vector<double4> boxes;
-        std::vector<int4> units;
-        std::vector<int64_t> cost;
-        for (int k = 0; k < K; ++k) {
+        std::vector<float4> boxes_leaf;
+        for (int li = 0; li < NL; ++li) {
+            const int k = leaves_sorted[li];
             const HostCell &c = ht.cells[k];
-            if (!c.leaf) continue;
-            tile_start[k] = (int)boxes.size();
-            int64_t src = 0;
-            for (int S : ht.U[k]) src += ht.cells[S].count;
+            leaf_index[k] = li;
+            leaf_start[li] = c.first;
+            leaf_tile[li] = tile_start[k] = (int)boxes.size();
+            const double wl = t->side / (double)(int64_t(1) << c.level);
+            const double cx = t->x0 + (c.ix + 0.5) * wl, cy = t->y0 + (c.iy + 0.5) * wl;
             for (int b = c.first; b < c.first + c.count; b += 64) {
                 const int len = std::min(64, c.first + c.count - b);
                 double4 bx = make_double4(1e300, 1e300, -1e300, -1e300);
+                double4 bl = bx;
                 for (int j = b; j < b + len; ++j) {
                     const double x = xs[j].x - t->x0, y = xs[j].y - t->y0;
-                    bx.x = std::min(bx.x, x);
-                    bx.y = std::min(bx.y, y);
-                    bx.z = std::max(bx.z, x);
-                    bx.w = std::max(bx.w, y);
+                    bx.x = std::min(bx.x, x), bx.y = std::min(bx.y, y), bx.z = std::max(bx.z, x), bx.w = std::max(bx.w, y);
+                    const double xl = (xs[j].x - cx) / wl, yl = (xs[j].y - cy) / wl;
+                    bl.x = std::min(bl.x, xl), bl.y = std::min(bl.y, yl), bl.z = std::max(bl.z, xl), bl.w = std::max(bl.w, yl);
                 }
                 boxes.push_back(bx);
-                int logtp = 0;
-                while ((1 << logtp) < len) ++logtp;
-                units.push_back(make_int4(k, b, len, logtp));
-                cost.push_back((int64_t)len * src);
+                boxes_leaf.push_back(make_float4(std::nextafter((float)bl.x, -INFINITY), std::nextafter((float)bl.y, -INFINITY),
+                                                 std::nextafter((float)bl.z, INFINITY), std::nextafter((float)bl.w, INFINITY)));
             }
         }
-        std::vector<int> uorder(units.size());
-        for (size_t u = 0; u < units.size(); ++u) uorder[u] = (int)u;
-        std::stable_sort(uorder.begin(), uorder.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<int4> sunits(units.size());
-        for (size_t u = 0; u < units.size(); ++u) sunits[u] = units[uorder[u]];
+        leaf_start[NL] = (int)n;
+
+        // Near-field plan.  A leaf is dense with at least dense_leaf particles; every
+        // unordered pair of adjacent dense leaves of one level, and every dense leaf with
+        // itself, is one mutual item; the rest of U from the target end.  Costs as for the
+        // uniform tree (mutual steps weight 3, target-centric 2).
+        const int D = t->dense_leaf;
+        std::vector<uint16_t> mask(K, 0);
+        std::vector<int4> work;
+        std::vector<int64_t> cost;
+        auto nch16 = [](int64_t len) { return (len + 15) >> 4; };
+        auto block_steps = [&](int64_t cs, int64_t cr) {
+            const int64_t fs = cs / 64, fr = cr / 64, rs = cs % 64, rr = cr % 64;
+            return 16 * (fs * fr * 4 + fs * nch16(rr) + fr * nch16(rs) + std::min(nch16(rs), nch16(rr)));
+        };
+        const int up[4][2] = {{1, 0}, {-1, 1}, {0, 1}, {1, 1}};
+        int64_t mpairs = 0, nmut = 0, ntc = 0;
+        for (int li = 0; li < NL; ++li) {
+            const int k = leaves_sorted[li];
+            const HostCell &c = ht.cells[k];
+            const bool dense = c.count >= D;
+            uint32_t m = 0;
+            int64_t nsrc = 0;
+            for (int S : ht.U[k]) {
+                const HostCell &cs = ht.cells[S];
+                if (dense && cs.count >= D && cs.level == c.level)
+                    m |= 1u << (3 * (cs.iy - c.iy + 1) + (cs.ix - c.ix + 1));
+                else
+                    nsrc += cs.count;
+            }
+            if (nsrc > 0) {
+                m |= 1u << 9;
+                for (int b = c.first; b < c.first + c.count; b += 64) {
+                    const int len = std::min(64, c.first + c.count - b);
+                    int logtp = 0;
+                    while ((1 << logtp) < len) ++logtp;
+                    const int kstride = 64 >> logtp;
+                    work.push_back(make_int4(k, b, len, logtp | (dense ? 16 : 0)));
+                    cost.push_back(2 * ((nsrc + kstride - 1) / kstride));
+                    ++ntc;
+                }
+            }
+            mask[k] = (uint16_t)m;
+            if (!dense) continue;
+            const int64_t f = c.count / 64, r = c.count % 64;
+            const int64_t diag = 16 * (f * 4 + nch16(r));
+            const int64_t st = 16 * (f * (f - 1) / 2 * 4 + f * nch16(r));
+            work.push_back(make_int4(li, li, 4 | (4 << 4), kMutualItem | (c.level << 9)));
+            cost.push_back(3 * st + 2 * diag);
+            ++nmut;
+            mpairs += (int64_t)c.count * (c.count - 1);
+            for (const auto &o : up) {
+                const int R = ht.find(c.level, c.ix + o[0], c.iy + o[1]);
+                if (R < 0 || !ht.cells[R].leaf || ht.cells[R].count < D) continue;
+                const int ds = 3 * (o[1] + 1) + (o[0] + 1);
+                work.push_back(make_int4(li, leaf_index[R], ds | ((8 - ds) << 4), kMutualItem | (c.level << 9)));
+                cost.push_back(3 * block_steps(c.count, ht.cells[R].count));
+                ++nmut;
+                mpairs += 2 * (int64_t)c.count * ht.cells[R].count;
+            }
+        }
+        std::vector<int> worder(work.size());
+        for (size_t u = 0; u < work.size(); ++u) worder[u] = (int)u;
+        std::stable_sort(worder.begin(), worder.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<int4> swork(work.size());
+        for (size_t u = 0; u < work.size(); ++u) swork[u] = work[worder[u]];
         t->ntiles = (int64_t)boxes.size();
-        t->nunits = (int64_t)sunits.size();
+        t->nwork = (int64_t)swork.size();
+        t->mutual_items = nmut;
+        t->mutual_pairs = mpairs;
+        t->target_units = ntc;
 
         std::vector<int> uo, ui, vo, vi, wo, wi, xo, xi;
         flatten(ht.U, uo, ui);
@@ -467,7 +549,11 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         if (!rc) rc = upload(&d.inner, inner, "split cells");
         if (!rc) rc = upload(&d.tile_start, tile_start, "tiles");
         if (!rc) rc = upload(&d.tile_box, boxes, "tile boxes");
-        if (!rc) rc = upload(&d.units, sunits, "near-field units");
+        if (!rc) rc = upload(&d.work, swork, "near-field work");
+        if (!rc) rc = upload(&d.leaf_start, leaf_start, "leaf offsets");
+        if (!rc) rc = upload(&d.leaf_tile, leaf_tile, "leaf tiles");
+        if (!rc) rc = upload(&d.tile_box_leaf, boxes_leaf, "tile boxes");
+        if (!rc) rc = upload(&d.mask, mask, "near-field mask");
         if (!rc) {
             hipError_t e2 = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
             if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);

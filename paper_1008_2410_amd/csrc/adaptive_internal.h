@@ -30,7 +30,15 @@ struct AtreeDev {
     int *inner = nullptr;       // split cells of level >= 2, grouped by level (inner_off)
     int *tile_start = nullptr;  // per cell: first 64-particle tile of a leaf
     double4 *tile_box = nullptr;  // per tile: {xmin, ymin, xmax, ymax} relative to (x0, y0)
-    int4 *units = nullptr;      // near-field work units {leaf, first, count, log2 TP}, heaviest first
+    // Near-field work, heaviest first: target-centric units {leaf cell, first, count,
+    // log2 TP | 16 when the leaf is dense (its same-level dense neighbours are skipped)}
+    // and mutual items {leaf index S, leaf index R, d_S | d_R << 4, kMutualItem | level << 9}
+    // for same-level adjacent dense leaves (leaf index = position in sorted order).
+    int4 *work = nullptr;
+    int *leaf_start = nullptr;     // per leaf index: first sorted slot (nleaves + 1 entries)
+    int *leaf_tile = nullptr;      // per leaf index: first tile
+    float4 *tile_box_leaf = nullptr;  // per tile: box in leaf widths about the leaf centre
+    uint16_t *mask = nullptr;      // per cell: slots d written by mutual items, bit 9 target-centric part
 };
 
 struct AtreeWs {
@@ -38,9 +46,12 @@ struct AtreeWs {
     void *rec = nullptr;        // float4 or double4 records {alpha (z - c_leaf), Gamma, 0}
     double *gamma = nullptr;    // circulations, sorted
     double2 *near = nullptr;    // near-field (u, v), sorted
+    void *slots = nullptr;      // mutual form: 9 x n sums (dY, dX), float2 or double2
     double2 *mp = nullptr;      // multipoles a_m / w^m, cells x p
     double2 *lo = nullptr;      // locals b_l w^(l+1), cells x p
     double *binom = nullptr;    // C(a, k), a, k <= 2p, row-major (2p + 1)^2
+    double *binom16 = nullptr;  // the same for a, k <= 32 (33 x 33), and for a, k <= 64 (65 x 65):
+    double *binom32 = nullptr;  // the M2L kernel runs 16 or 32 terms whatever p
 };
 
 }  // namespace fmm
@@ -51,7 +62,9 @@ struct fmm_atree {
     int max_leaf = 0, max_depth = 0;
     double x0 = 0, y0 = 0, side = 1;
     int64_t sizes[8] = {};
-    int64_t ncells = 0, ntiles = 0, nunits = 0, np2m = 0;
+    int64_t ncells = 0, ntiles = 0, nwork = 0, np2m = 0;
+    int64_t mutual_items = 0, mutual_pairs = 0, target_units = 0;
+    int dense_leaf = 32;
     std::vector<int> level_off;   // max_depth + 2 entries
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
     std::vector<int> leaf_level, leaf_ix, leaf_iy;  // per particle, user order (host)

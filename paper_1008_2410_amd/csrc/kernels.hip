@@ -141,15 +141,6 @@ __global__ __launch_bounds__(256) void pack_kernel(int n, int nxcd, const int *_
 //   velocity u = -(alpha/2pi) sum Gamma g dY/s,  v = (alpha/2pi) sum Gamma g dX/s
 // ---------------------------------------------------------------------------------
 
-// Smallest squared distance between two boxes {xmin, ymin, xmax, ymax}, the first
-// shifted by (ox, oy).
-__device__ __forceinline__ float box_gap2(float4 a, float ox, float oy, float4 b)
-{
-    const float gx = fmaxf(0.0f, fmaxf(b.x - (a.z + ox), (a.x + ox) - b.z));
-    const float gy = fmaxf(0.0f, fmaxf(b.y - (a.w + oy), (a.y + oy) - b.w));
-    return gx * gx + gy * gy;
-}
-
 template <typename T>
 __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, const rec_t<T> *__restrict__ rec,
                                                  const int *__restrict__ leaf_start,
@@ -210,203 +201,6 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
     if (k == 0 && t < u.z) near[i] = make_double2(-scale * au, scale * av);
 }
 
-// ---------------------------------------------------------------------------------
-// Stage 9, mutual form for pairs of dense leaves.  The kernel of eq. regB-S2DGau is
-// odd, K(-z) = -K(z), so one evaluation of g(s)/s serves both particles of a pair.
-// One wavefront per item {S, R}: R is S itself or one of its neighbours (+1,0),
-// (-1,+1), (0,+1), (+1,+1), so every unordered pair of neighbouring dense leaves is
-// one item.  For each pair of 64-particle tiles (b of S, a of R), one tile is held one
-// particle per lane ("resident") and the other is staged in LDS and streamed in chunks
-// of 16 sources.  Within a chunk, lane l of a 16-lane row meets source (l + j) mod 16
-// at step j; the resident sums stay in the lane and each source's sum travels with its
-// source: a one-lane rotation within the row per step, fused into the add (a DPP
-// operand).  After 16 steps every row holds its partial sums of the chunk's sources;
-// two butterfly steps across rows complete them.  Sums for tile b stay in registers
-// over the tiles of R; sums for tile a accumulate in its particles' slot in memory.
-// Slots: nine per particle, one per neighbour direction d = 3(dy+1) + (dx+1), written
-// by exactly one item (the item of S = R writes its own particles' slot 4 from both
-// ends, tile b folding in what the earlier tiles wrote).  The near field is the fixed
-// order sum of the slots plus the target-centric part for sparse neighbours, so the
-// result does not depend on scheduling.
-// ---------------------------------------------------------------------------------
-
-// Lane l receives the value of lane 16 (l / 16) + ((l + 1) mod 16): DPP row_ror:15.
-__device__ __forceinline__ float row_rot(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF,
-                                                                 false));
-}
-__device__ __forceinline__ double row_rot(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x12F, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x12F, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-// 16 steps of one chunk: src points at this lane's start in the chunk's doubled copy
-// (src[j] = source (l + j) mod 16).  rgn = -Gamma of the resident particle (zero for an
-// idle lane).  On return (cu, cv)[l] = this row's sum for source l mod 16 of the chunk.
-template <typename T, bool FAR>
-__device__ __forceinline__ void mutual_chunk(const rec_t<T> *src, T rx, T ry, T rgn, T &fu, T &fv, T &cu, T &cv)
-{
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const rec_t<T> sj = src[j];
-        const T ddx = rx - sj.x;
-        const T ddy = ry - sj.y;
-        const T ss = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
-        const T r = recip(ss);
-        T h;  // g(s)/s
-        if (FAR) h = r;
-        else if (sizeof(T) == 4) h = fma(-exp_neg_scaled(ss), r, r);
-        else h = one_minus_exp(ss) * r;
-        const T wt = h * sj.z;
-        fu = fma(wt, ddy, fu);
-        fv = fma(wt, ddx, fv);
-        const T ws = h * rgn;
-        if (j == 0) {
-            cu = ws * ddy;
-            cv = ws * ddx;
-        } else {
-            // Not contracted: a multiply and an add that takes the rotation as its DPP
-            // operand are two instructions; an FMA needs the rotation as a separate move.
-#pragma clang fp contract(off)
-            cu = row_rot(cu) + ws * ddy;
-            cv = row_rot(cv) + ws * ddx;
-        }
-    }
-    cu = row_rot(cu);
-    cv = row_rot(cv);
-}
-
-// Records of one tile into LDS, each chunk of 16 stored twice in a row (so that the
-// sources of step j are at a constant offset), zero records past the tile's end.
-template <typename T>
-__device__ __forceinline__ rec_t<T> stage_doubled(rec_t<T> *dst, const rec_t<T> *__restrict__ rec, int first,
-                                                  int len)
-{
-    const int lane = threadIdx.x;
-    rec_t<T> r;
-    r.x = r.y = r.z = r.w = (T)0;
-    if (lane < len) r = rec[first + lane];
-    dst[(lane >> 4) * 32 + (lane & 15)] = r;
-    dst[(lane >> 4) * 32 + (lane & 15) + 16] = r;
-    return r;
-}
-
-// One tile b of S against every tile a of R (a >= b when S = R).  Per block (b, a) the
-// tile with more chunks of 16 sits in the lanes and the other is streamed from LDS, so
-// that fewer steps are spent; either way both sums come out lane-indexed by particle.
-template <typename T>
-__device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b, int b,
-                                                     int tb, const rec_t<T> *__restrict__ rec,
-                                                     const int *__restrict__ leaf_start,
-                                                     const int *__restrict__ tile_start,
-                                                     const float4 *__restrict__ tile_box, T step, float cut_leaf2,
-                                                     c2<T> *__restrict__ slot_s, c2<T> *__restrict__ slot_r)
-{
-    const int lane = threadIdx.x;
-    const uint32_t S = (uint32_t)it.x, R = (uint32_t)it.y;
-    const bool self = S == R;
-    const int ds = it.z & 15;
-    const int dx = ds % 3 - 1, dy = ds / 3 - 1;  // R - S in leaves
-    const T ox = (T)dx * step, oy = (T)dy * step;
-    const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
-    const int r1 = leaf_start[R + 1];
-    const int lenb = min(64, s1 - b);
-    const int nchb = (lenb + 15) >> 4;
-    __syncthreads();
-    const rec_t<T> rb = stage_doubled<T>(tile_b, rec, b, lenb);
-    // tile b in the frame of leaf R (resident form); in the streamed form it stays in
-    // the frame of S and tile a is moved there
-    const T bx = rb.x - ox, by = rb.y - oy;
-    const T bgn = lane < lenb ? -rb.z : (T)0;
-    const float4 bbox = tile_box[tb];
-    T fu = 0, fv = 0;
-    if (self && b > s0 && lane < lenb) {  // what the earlier tiles of S wrote for this tile
-        const c2<T> o = slot_s[b + lane];
-        fu = o.x;
-        fv = o.y;
-    }
-    const bool first_touch = b == s0;  // the first resident tile creates the streamed slots
-    int ta = self ? tb : tile_start[R];
-    for (int a = self ? b : leaf_start[R]; a < r1; a += 64, ++ta) {
-        const int lena = min(64, r1 - a);
-        const int ncha = (lena + 15) >> 4;
-        const bool diag = self && a == b;
-        const bool far = box_gap2(bbox, (float)-dx, (float)-dy, tile_box[ta]) >= cut_leaf2;
-        if (diag) {
-            // the tile with itself: every ordered pair from the resident end
-            __syncthreads();
-            for (int c = 0; c < nchb; ++c)
-                if (far) {
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) p2p_pair<T, true>(tile_b[c * 32 + j], bx, by, fu, fv);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) p2p_pair<T, false>(tile_b[c * 32 + j], bx, by, fu, fv);
-                }
-            continue;
-        }
-        c2<T> old;
-        old.x = old.y = (T)0;
-        if (!first_touch && lane < lena) old = slot_r[a + lane];
-        const bool swap = ncha > nchb;  // tile a in the lanes, tile b streamed
-        __syncthreads();
-        const rec_t<T> ra = stage_doubled<T>(tile_a, rec, a, lena);
-        __syncthreads();
-        T px, py, pgn;
-        const rec_t<T> *src;
-        int nch;
-        if (swap) {
-            px = ra.x + ox;
-            py = ra.y + oy;
-            pgn = lane < lena ? -ra.z : (T)0;
-            src = tile_b;
-            nch = nchb;
-        } else {
-            px = bx;
-            py = by;
-            pgn = bgn;
-            src = tile_a;
-            nch = ncha;
-        }
-        T ru = 0, rv = 0, colu = 0, colv = 0;
-        for (int c = 0; c < nch; ++c) {
-            T cu, cv;
-            const rec_t<T> *sp = src + c * 32 + (lane & 15);
-            if (far) mutual_chunk<T, true>(sp, px, py, pgn, ru, rv, cu, cv);
-            else mutual_chunk<T, false>(sp, px, py, pgn, ru, rv, cu, cv);
-            cu += __shfl_xor(cu, 16);
-            cv += __shfl_xor(cv, 16);
-            cu += __shfl_xor(cu, 32);
-            cv += __shfl_xor(cv, 32);
-            if ((lane >> 4) == c) {
-                colu = cu;
-                colv = cv;
-            }
-        }
-        // sums of tile b and of tile a, lane-indexed
-        const T bu = swap ? colu : ru, bv = swap ? colv : rv;
-        const T au = swap ? ru : colu, av = swap ? rv : colv;
-        fu += bu;
-        fv += bv;
-        if (lane < lena) {
-            c2<T> nw;
-            nw.x = old.x + au;
-            nw.y = old.y + av;
-            slot_r[a + lane] = nw;
-        }
-    }
-    if (lane < lenb) {
-        c2<T> nw;
-        nw.x = fu;
-        nw.y = fv;
-        slot_s[b + lane] = nw;
-    }
-}
-
 // Near-field grid (stage 9): one list of work entries, each one wavefront's work:
 //   mutual items {S, R, d_S | d_R << 4, kMutualItem}, d_S = direction of R seen from S
 //   and d_R = 8 - d_S, writing the slots (9 x n sums (dY, dX) in the records'
@@ -421,21 +215,6 @@ __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *ti
 // own outputs, so the result does not depend on which wavefront takes which entry.
 // The counter's atomic is issued by one lane (a vector memory atomic) and broadcast to
 // the wavefront.
-
-template <typename T>
-__device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b,
-                                            const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
-                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
-                                            T step, float cut_leaf2, int64_t n, c2<T> *__restrict__ slots)
-{
-    const uint32_t S = (uint32_t)it.x;
-    c2<T> *slot_s = slots + (int64_t)(it.z & 15) * n;
-    c2<T> *slot_r = slots + (int64_t)(it.z >> 4) * n;
-    const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
-    for (int b = s0, tb = tile_start[S]; b < s1; b += 64, ++tb)
-        mutual_resident_tile<T>(it, tile_a, tile_b, b, tb, rec, leaf_start, tile_start, tile_box, step, cut_leaf2,
-                                slot_s, slot_r);
-}
 
 template <typename T>
 __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t<T> *tile_b,

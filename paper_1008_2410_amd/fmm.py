@@ -223,13 +223,16 @@ class ATree:
                 "fmm_atree_leaves")
         return lv, ix, iy
 
-    def velocity(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed", out=None) -> torch.Tensor:
-        """(n, 2) float64 velocities in user order."""
+    def velocity(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed", out=None,
+                 serial: bool = False) -> torch.Tensor:
+        """(n, 2) float64 velocities in user order.  serial: the far field on the current
+        stream after the near field instead of beside it (for timing the stages alone)."""
         g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
         uv = out if out is not None else torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
+            s = _stream_ptr()
             L.check(L.load().fmm_atree_velocity(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
-                                                _stream_ptr(), None, _ptr(uv)), "fmm_atree_velocity")
+                                                s, s if serial else None, _ptr(uv)), "fmm_atree_velocity")
         return uv
 
     def velocity_parts(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed"):
