@@ -1018,16 +1018,19 @@ template <typename T> __device__ __forceinline__ T series_cut();
 template <> __device__ __forceinline__ float series_cut<float>() { return 0.125f; }
 template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3; }
 
-// acc: Phi (2), A (2), B; with SRC also the source-position sums with the adjoint
+// acc: Phi (2); A as its real part and its imaginary part divided by -2 (the factor is
+// applied in finalize); B; with SRC also the source-position sums with the adjoint
 // charges, At = sum q_j conj(dz')^2 (lambda e s' - g)/s'^2 (2) and Bt = sum q_j e (2).
+// conj(dz')^2 = (dx'^2 - dy'^2) - 2i dx' dy' reuses dy'^2 from s'.
 template <typename T, bool FAR, bool SRC>
 __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda,
                                              T (&acc)[SRC ? 9 : 5])
 {
-    T &fpr = acc[0], &fpi = acc[1], &far_r = acc[2], &far_i = acc[3], &fb = acc[4];
+    T &fpr = acc[0], &fpi = acc[1], &far_r = acc[2], &far_ih = acc[3], &fb = acc[4];
     const T ddx = tx - rj.x;
     const T ddy = ty - rj.y;
-    const T s = fma(ddx, ddx, fma(ddy, ddy, tiny<T>()));
+    const T dy2 = fma(ddy, ddy, tiny<T>());
+    const T s = fma(ddx, ddx, dy2);
     const T r = recip(s);
     T gr, h;
     if (FAR) {
@@ -1038,13 +1041,14 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
         T e, g;
         exp_pair(s, e, g);
         gr = g * r;
-        h = fma(lambda * e, s, -g) * r * r;
+        h = (lambda * e - gr) * r;  // lambda e/s' - g/s'^2
         // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
         // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
         //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
         //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
-        const T x = lambda * s;
-        if (x < series_cut<T>()) {
+        // (The test is on s' against the cut divided by lambda, a loop invariant.)
+        if (s < series_cut<T>() / lambda) {
+            const T x = lambda * s;
             gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
             h = lambda * lambda *
                 fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
@@ -1063,12 +1067,12 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
     fpi = fma(qj.y, cx, fpi);
     // A: Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2
     const T hg = h * rj.z;
-    const T zr = fma(ddx, ddx, -ddy * ddy);
-    const T zi = (T)-2 * ddx * ddy;
+    const T zr = fma((T)-2, dy2, s);  // dx'^2 - dy'^2
+    const T zh = ddx * ddy;           // Im conj(dz')^2 / -2
     far_r = fma(hg, zr, far_r);
-    far_i = fma(hg, zi, far_i);
+    far_ih = fma(hg, zh, far_ih);
     if constexpr (SRC) {
-        const T wr = h * zr, wi = h * zi;
+        const T wr = h * zr, wi = ((T)-2 * h) * zh;
         acc[5] = fma(qj.x, wr, acc[5]);
         acc[5] = fma(-qj.y, wi, acc[5]);
         acc[6] = fma(qj.x, wi, acc[6]);
@@ -1171,7 +1175,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
 constexpr int kNearBatch = 4;
 
 template <typename T, bool SRC>
-__global__ __launch_bounds__(64) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
                                                            int *__restrict__ work_ctr,
                                                            const rec_t<T> *__restrict__ rec,
                                                            const c2<T> *__restrict__ qv,
@@ -1223,8 +1227,9 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
     const double sb = near_b[i];
     double phi = alpha * a.y;  // only Im(Phi) enters dL/dGamma
     const double ka = alpha * alpha * kInv2Pi;
-    // A = -i ka (a.z + i a.w) = ka (a.w, -a.z);  B = -i ka lambda sb
-    double Ar = ka * a.w, Ai = -ka * a.z;
+    // A = -i ka (a.z + i a.w') with a.w' = -2 a.w (the near sums hold Im A / -2):
+    // A = ka (a.w', -a.z);  B = -i ka lambda sb
+    double Ar = ka * (-2.0 * a.w), Ai = -ka * a.z;
     const double Bi = -ka * lambda * sb;
     double dwr = 0.0, dwi = 0.0, dpr = 0.0, dpi = 0.0;
     if (has_far) {
