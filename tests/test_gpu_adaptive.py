@@ -126,6 +126,16 @@ def test_large_sampled_against_direct_sum(fmm_mod, oracle_mod):
         assert err < tol
 
 
+def test_linear_impulse_fp64(fmm_mod):
+    """sum_i Gamma_i u_i = 0 to roundoff for the FP64 adaptive evaluation (antisymmetric
+    operator: odd near kernel over symmetric U, M2L over symmetric V, M2P/P2L transposes)."""
+    xy, g = _clustered(4)
+    for smax, lmax in ((20, 9), (1, 5), (60, 12)):
+        u = fmm_mod.ATree(_t(xy), smax, lmax).velocity(_t(g), 0.001, 12, "fp64").cpu().numpy()
+        imp = (g[:, None] * u).sum(axis=0)
+        assert np.all(np.abs(imp) < 1e-13 * (np.abs(g)[:, None] * np.abs(u)).sum()), (smax, lmax, imp)
+
+
 def test_errors(fmm_mod):
     from paper_1008_2410_amd import _lib
     xy = np.array([[0.5, 0.5], [0.2, 0.3], [1.5, 0.2], [0.1, 0.1]])

@@ -151,3 +151,15 @@ def test_matches_direct_sum_within_truncation(smax, lmax, p, tol):
     sigma = 1e-6
     u = O.afmm_velocity(xy, g, sigma, smax, lmax, p)
     assert rel_l2(u, O.direct(xy, g, sigma)) < tol
+
+
+@pytest.mark.parametrize("smax,lmax", [(20, 9), (5, 7), (1, 5)])
+def test_linear_impulse(smax, lmax):
+    """sum_i Gamma_i u_i = 0 to roundoff: the near kernel is odd over symmetric U lists, M2L
+    is antisymmetric over symmetric V lists with square truncation, and M2P over W is the
+    exact transpose of P2L over X (same p, exact M2M and L2L chains)."""
+    xy, g = _clustered(4)
+    u = O.afmm_velocity(xy, g, 0.001, smax, lmax, 12)
+    imp = (g[:, None] * u).sum(axis=0)
+    scale = (np.abs(g)[:, None] * np.abs(u)).sum()
+    assert np.all(np.abs(imp) < 1e-13 * scale), (imp, scale)
