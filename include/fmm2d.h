@@ -118,6 +118,19 @@ int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_bo
 int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
                         fmm_tree **out);
 
+/* Stages 1-3 again for particles that have moved (section "Test problem": the particles
+ * are carried by the flow, so every time step needs a tree for the new positions).
+ * Builds a new tree for xy as fmm_build_tree does, with the depth and the FMM_OPT_*
+ * options of `prev`, and hands prev's evaluation workspace to it; prev is then destroyed.
+ * A time-stepping loop that rebuilds this way allocates the workspace once instead of
+ * once per tree.
+ *   prev      tree of the same n on the current device; destroyed on success (after a
+ *             device synchronisation, as fmm_destroy_tree), unchanged on error.
+ *   xy, n, root_box, stream, out   as fmm_build_tree; n must equal prev's (FMM_EINVAL).
+ * FMM_ESTATE for a NULL prev or one in use by another call. */
+int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
+                     fmm_tree **out);
+
 /* Host-side facts about a tree (any pointer may be NULL):
  *   n, depth, root_box[3] (host);
  *   p2p_pairs       ordered near-field pairs sum_T n_T sum_{S in N(T)} n_S - n, the pair

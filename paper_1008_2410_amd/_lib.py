@@ -24,6 +24,7 @@ _D = ctypes.c_double
 SIGNATURES = {
     "fmm_build_tree": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_build_tree_host": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fmm_rebuild_tree": (_I, [_P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     "fmm_tree_info": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "fmm_tree_permutation": (_I, [_P, _P, _P, _P]),
     "fmm_tree_levels": (_I, [_P, _P, _I]),

@@ -25,52 +25,45 @@ struct BusyGuard {
     fmm_tree *t;
     bool ok;
     explicit BusyGuard(fmm_tree *tree) : t(tree), ok(tree->busy.exchange(1) == 0) {}
-    ~BusyGuard()
+    ~BusyGuard() { release(); }
+    void release()
     {
         if (ok) t->busy.store(0);
+        ok = false;
     }
 };
 
-void free_workspace(Workspace &ws)
+// The workspace is allocated from the stream-ordered pool; callers have finished the
+// device work that used it (destroy) or synchronised (reallocation).
+void free_workspace(Workspace &ws, hipStream_t s)
 {
-    hipFree(ws.rec);
-    hipFree(ws.near);
-    hipFree(ws.mp_d);
-    hipFree(ws.lo_d);
-    hipFree(ws.mp_f);
-    hipFree(ws.lo_f);
-    hipFree(ws.adj);
-    hipFree(ws.bwd_near);
-    hipFree(ws.bwd_b);
-    hipFree(ws.mp2_d);
-    hipFree(ws.lo2_d);
-    hipFree(ws.mp2_f);
-    hipFree(ws.lo2_f);
-    hipFree(ws.rec2);
-    hipFree(ws.slots);
-    hipFree(ws.bwd_src);
+    for (void *p : {(void *)ws.rec, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
+                    (void *)ws.lo_f, (void *)ws.adj, (void *)ws.bwd_near, (void *)ws.bwd_b, (void *)ws.mp2_d,
+                    (void *)ws.lo2_d, (void *)ws.mp2_f, (void *)ws.lo2_f, (void *)ws.rec2, (void *)ws.slots,
+                    (void *)ws.bwd_src})
+        if (p) hipFreeAsync(p, s);
     ws = Workspace{};
 }
 
 void free_tree(fmm_tree *t)
 {
-    hipFree(t->d_perm);
-    hipFree(t->d_gpos1);
-    hipFree(t->d_gpos2);
-    hipFree(t->d_st1);
-    hipFree(t->d_leaf_of);
-    hipFree(t->d_xy);
-    hipFree(t->d_leaf_start);
-    hipFree(t->d_counts);
-    hipFree(t->d_lists);
-    hipFree(t->d_units);
-    hipFree(t->d_near_work);
-    hipFree(t->d_leaf_mask);
-    hipFree(t->d_tile_start);
-    hipFree(t->d_tile_box);
+    // arrays of the device build come from the stream-ordered pool (freed without a
+    // device synchronisation), those of the host build from hipMalloc; the near-field
+    // plan is always pooled
+    hipStream_t fs = t->own_side;  // the caller has finished the work on the tree
+    auto release = [fs](void *p, bool pooled) {
+        if (!p) return;
+        if (pooled) hipFreeAsync(p, fs);
+        else hipFree(p);
+    };
+    for (void *p : {(void *)t->d_perm, (void *)t->d_gpos1, (void *)t->d_gpos2, (void *)t->d_st1, (void *)t->d_leaf_of,
+                    (void *)t->d_xy, (void *)t->d_leaf_start, (void *)t->d_counts, (void *)t->d_lists,
+                    (void *)t->d_units, (void *)t->d_tile_start, (void *)t->d_tile_box})
+        release(p, t->pooled);
+    release(t->d_near_work, true);
+    release(t->d_leaf_mask, true);
     hipFree(t->d_work);
-    free_workspace(t->ws);
-    free_tables(t->tabs);
+    free_workspace(t->ws, fs);
     if (t->own_side) hipStreamDestroy(t->own_side);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
@@ -87,7 +80,7 @@ int effective_lc(const fmm_tree *t) { return std::min(t->lc, t->depth); }
 // Last FP64 level: every level in FP64 precision; in mixed precision the coarse levels.
 int split_level(const fmm_tree *t, int precision) { return precision == FMM_FP64 ? t->depth : effective_lc(t); }
 
-int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
+int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream_t s)
 {
     Workspace &ws = t->ws;
     const int split = split_level(t, precision);
@@ -95,7 +88,7 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
     if (ws.p != p || ws.precision != precision || ws.split != split) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        free_workspace(ws);
+        free_workspace(ws, s);
     }
     const int64_t n = t->n;
     const int64_t cells_d = level_base(std::min(split, L) + 1);
@@ -103,43 +96,43 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward)
     const size_t rec_bytes = precision == FMM_FP64 ? sizeof(double4) : sizeof(float4);
     int rc = FMM_OK;
     if (!ws.rec) {
-        if ((rc = dev_alloc((char **)&ws.rec, n * rec_bytes, "particle records"))) return rc;
-        if ((rc = dev_alloc(&ws.near, n, "near field"))) return rc;
+        if ((rc = dev_alloc_async((char **)&ws.rec, n * rec_bytes, "particle records", s))) return rc;
+        if ((rc = dev_alloc_async(&ws.near, n, "near field", s))) return rc;
         if (L >= 2) {
-            if ((rc = dev_alloc(&ws.mp_d, cells_d * p + kCoefPad, "multipoles"))) return rc;
-            if ((rc = dev_alloc(&ws.lo_d, cells_d * p + kCoefPad, "locals"))) return rc;
+            if ((rc = dev_alloc_async(&ws.mp_d, cells_d * p + kCoefPad, "multipoles", s))) return rc;
+            if ((rc = dev_alloc_async(&ws.lo_d, cells_d * p + kCoefPad, "locals", s))) return rc;
             if (cells_f > 0) {
-                if ((rc = dev_alloc(&ws.mp_f, cells_f * p + kCoefPad, "multipoles"))) return rc;
-                if ((rc = dev_alloc(&ws.lo_f, cells_f * p + kCoefPad, "locals"))) return rc;
+                if ((rc = dev_alloc_async(&ws.mp_f, cells_f * p + kCoefPad, "multipoles", s))) return rc;
+                if ((rc = dev_alloc_async(&ws.lo_f, cells_f * p + kCoefPad, "locals", s))) return rc;
             }
             // Empty cells are never written; the MFMA M2L reads them as zero rows.
-            HIP_TRY(hipMemset(ws.mp_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
-            HIP_TRY(hipMemset(ws.lo_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
+            HIP_TRY(hipMemsetAsync(ws.mp_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
+            HIP_TRY(hipMemsetAsync(ws.lo_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
             if (cells_f > 0) {
-                HIP_TRY(hipMemset(ws.mp_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
-                HIP_TRY(hipMemset(ws.lo_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
+                HIP_TRY(hipMemsetAsync(ws.mp_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
+                HIP_TRY(hipMemsetAsync(ws.lo_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
             }
         }
         ws.p = p;
         ws.precision = precision;
         ws.split = split;
     }
-    if (backward && !ws.bwd_src && (rc = dev_alloc(&ws.bwd_src, n, "adjoint source-position sums"))) return rc;
+    if (backward && !ws.bwd_src && (rc = dev_alloc_async(&ws.bwd_src, n, "adjoint source-position sums", s))) return rc;
     if (backward && !ws.adj) {
-        if ((rc = dev_alloc(&ws.adj, n, "adjoint charges"))) return rc;
-        if ((rc = dev_alloc(&ws.bwd_near, n, "adjoint near field"))) return rc;
-        if ((rc = dev_alloc(&ws.bwd_b, n, "adjoint near field"))) return rc;
-        if (precision != FMM_FP64 && (rc = dev_alloc((float2 **)&ws.rec2, n, "adjoint charges (FP32)"))) return rc;
+        if ((rc = dev_alloc_async(&ws.adj, n, "adjoint charges", s))) return rc;
+        if ((rc = dev_alloc_async(&ws.bwd_near, n, "adjoint near field", s))) return rc;
+        if ((rc = dev_alloc_async(&ws.bwd_b, n, "adjoint near field", s))) return rc;
+        if (precision != FMM_FP64 && (rc = dev_alloc_async((float2 **)&ws.rec2, n, "adjoint charges (FP32)", s))) return rc;
         if (L >= 2) {
-            if ((rc = dev_alloc(&ws.mp2_d, cells_d * p + kCoefPad, "adjoint multipoles"))) return rc;
-            if ((rc = dev_alloc(&ws.lo2_d, cells_d * p + kCoefPad, "adjoint locals"))) return rc;
-            HIP_TRY(hipMemset(ws.mp2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
-            HIP_TRY(hipMemset(ws.lo2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2)));
+            if ((rc = dev_alloc_async(&ws.mp2_d, cells_d * p + kCoefPad, "adjoint multipoles", s))) return rc;
+            if ((rc = dev_alloc_async(&ws.lo2_d, cells_d * p + kCoefPad, "adjoint locals", s))) return rc;
+            HIP_TRY(hipMemsetAsync(ws.mp2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
+            HIP_TRY(hipMemsetAsync(ws.lo2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
             if (cells_f > 0) {
-                if ((rc = dev_alloc(&ws.mp2_f, cells_f * p + kCoefPad, "adjoint multipoles"))) return rc;
-                if ((rc = dev_alloc(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals"))) return rc;
-                HIP_TRY(hipMemset(ws.mp2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
-                HIP_TRY(hipMemset(ws.lo2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2)));
+                if ((rc = dev_alloc_async(&ws.mp2_f, cells_f * p + kCoefPad, "adjoint multipoles", s))) return rc;
+                if ((rc = dev_alloc_async(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals", s))) return rc;
+                HIP_TRY(hipMemsetAsync(ws.mp2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
+                HIP_TRY(hipMemsetAsync(ws.lo2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
             }
         }
     }
@@ -235,11 +228,11 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
     std::string err;
-    if ((rc = upload_tables(t->tabs, p, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
-    if ((rc = ensure_workspace(t, p, precision, false))) return rc;
+    if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+    if ((rc = ensure_workspace(t, p, precision, false, (hipStream_t)main_stream))) return rc;
     if (use_mutual(t) && !t->ws.slots &&
-        (rc = dev_alloc((char **)&t->ws.slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
-                        "mutual near-field slots")))
+        (rc = dev_alloc_async((char **)&t->ws.slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
+                              "mutual near-field slots", (hipStream_t)main_stream)))
         return rc;
 
     hipStream_t ms = (hipStream_t)main_stream;
@@ -297,6 +290,7 @@ int new_tree(const double *xy, int64_t n, int depth, const double *root_box, fmm
     int dev = 0;
     const hipError_t de = hipGetDevice(&dev);
     if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
+    retain_pool(dev);
     t = new fmm_tree();
     t->device = dev;
     int cus = 0;
@@ -327,12 +321,26 @@ int finish_tree(fmm_tree *t, hipStream_t s)
 // Stages 1-3: tree construction, binning, work lists -- on the device (default) or on
 // the host (reference build; both give identical trees)
 // ---------------------------------------------------------------------------------------
-extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
-                              fmm_tree **out)
+namespace {
+
+// The device build; the options of `opts` (a tree being replaced) are taken over before
+// the near-field plan is made, since that plan depends on them.
+int build_device(const double *xy, int64_t n, int depth, const double *root_box, void *stream, const fmm_tree *opts,
+                 fmm_tree **out)
 {
     fmm_tree *t = nullptr;
     int rc = new_tree(xy, n, depth, root_box, out, t);
     if (rc) return rc;
+    if (opts) {
+        t->lc = opts->lc;
+        t->near_waves = opts->near_waves;
+        t->far_waves = opts->far_waves;
+        t->schedule = opts->schedule;
+        t->near_mutual = opts->near_mutual;
+        t->dense_leaf = opts->dense_leaf;
+        t->near_occupancy = opts->near_occupancy;
+        t->timing = opts->timing;
+    }
     hipStream_t s = (hipStream_t)stream;
     std::string err;
     int64_t bad = -1;
@@ -346,6 +354,64 @@ extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const doub
         free_tree(t);
         return rc;
     }
+    *out = t;
+    return FMM_OK;
+}
+
+// A workspace handed to a tree over other particles: multipoles of cells that are empty
+// in the new tree must read as zero (the M2L kernels read them unconditionally), so the
+// multipole arrays are cleared.  Locals and per-particle arrays are written in full by
+// every call before they are read.
+int clear_multipoles(const fmm_tree *t, hipStream_t s)
+{
+    const Workspace &ws = t->ws;
+    if (!ws.rec || t->depth < 2) return FMM_OK;
+    const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
+    const int64_t cells_f = level_base(t->depth + 1) - cells_d;
+    const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
+    for (double2 *m : {ws.mp_d, ws.mp2_d})
+        if (m) HIP_TRY(hipMemsetAsync(m, 0, bd, s));
+    for (float2 *m : {ws.mp_f, ws.mp2_f})
+        if (m && cells_f > 0) HIP_TRY(hipMemsetAsync(m, 0, bf, s));
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
+                              fmm_tree **out)
+{
+    return build_device(xy, n, depth, root_box, stream, nullptr, out);
+}
+
+extern "C" int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
+                                fmm_tree **out)
+{
+    g_last_error.clear();
+    if (out) *out = nullptr;
+    if (!prev) return fail(FMM_ESTATE, "null tree handle");
+    if (n != prev->n) return fail(FMM_EINVAL, "n must equal the particle count of the tree being rebuilt");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != prev->device) return fail(FMM_EINVAL, "the current device is not the tree's");
+    BusyGuard guard(prev);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    fmm_tree *t = nullptr;
+    int rc = build_device(xy, n, prev->depth, root_box, stream, prev, &t);
+    if (rc) return rc;
+    hipError_t e = hipDeviceSynchronize();  // work of earlier calls on prev may still use its workspace
+    if (e != hipSuccess) {
+        free_tree(t);
+        return hip_fail(e, "hipDeviceSynchronize");
+    }
+    std::swap(t->ws, prev->ws);
+    if ((rc = clear_multipoles(t, (hipStream_t)stream))) {
+        std::swap(t->ws, prev->ws);
+        free_tree(t);
+        return rc;
+    }
+    guard.release();
+    free_tree(prev);
     *out = t;
     return FMM_OK;
 }
@@ -669,8 +735,8 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
     std::string err;
-    if ((rc = upload_tables(t->tabs, p, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
-    if ((rc = ensure_workspace(t, p, precision, true))) return rc;
+    if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+    if ((rc = ensure_workspace(t, p, precision, true, (hipStream_t)main_stream))) return rc;
     Workspace &ws = t->ws;
 
     hipStream_t ms = (hipStream_t)main_stream;
@@ -814,6 +880,19 @@ int fmm::fail(int code, const std::string &msg)
 }
 
 void fmm::clear_last_error() { g_last_error.clear(); }
+
+void fmm::retain_pool(int device)
+{
+    static std::atomic<uint64_t> done{0};
+    if (device < 0 || device >= 64 || ((done.load() >> device) & 1)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t threshold = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+    (void)hipGetLastError();
+    done.fetch_or(uint64_t(1) << device);
+}
 
 double fmm::record_alpha(double sigma, int precision)
 {

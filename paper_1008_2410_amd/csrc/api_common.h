@@ -38,6 +38,26 @@ int dev_alloc(T **p, size_t count, const char *what)
     return FMM_OK;
 }
 
+// Stream-ordered allocation from the device's default pool (see retain_pool).
+template <typename T>
+int dev_alloc_async(T **p, size_t count, const char *what, hipStream_t s)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMallocAsync((void **)p, count * sizeof(T), s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(FMM_ENOMEM, std::string("device allocation failed: ") + what);
+    }
+    return FMM_OK;
+}
+
+// Keep freed blocks of the device's default memory pool for reuse instead of returning
+// them at every synchronisation, so that trees built and destroyed in a loop (time
+// stepping) allocate from the pool.  Once per device.
+void retain_pool(int device);
+
 template <typename T>
 int upload(T **p, const std::vector<T> &h, const char *what)
 {

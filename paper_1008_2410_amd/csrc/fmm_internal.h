@@ -107,6 +107,7 @@ struct Workspace {
 
 struct fmm_tree {
     int64_t n = 0;
+    bool pooled = false;  // tree arrays from the stream-ordered pool (the device build)
     int depth = 0;
     double x0 = 0, y0 = 0, side = 1;
     int device = 0;
@@ -156,7 +157,7 @@ struct fmm_tree {
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-    fmm::Tables tabs;
+    const fmm::Tables *tabs = nullptr;  // shared, never freed by the tree
     fmm::Workspace ws;
     std::vector<std::array<hipEvent_t, fmm::kNumEvents>> pending_timing;
 };
@@ -204,5 +205,8 @@ void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArg
 // Tables (host generation + upload), kernels.hip
 int upload_tables(Tables &tb, int p, std::string &err);
 void free_tables(Tables &tb);
+// The tables of p-term expansions on a device (the current one): built on first use, shared
+// by every tree of the process and kept until it ends.  Returns 0, -2 (no memory) or -3.
+int shared_tables(int device, int p, const Tables **out, std::string &err);
 
 }  // namespace fmm

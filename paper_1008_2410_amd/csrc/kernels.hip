@@ -908,8 +908,8 @@ void m2l_mfma_launch(const FarArgs &a, int l, hipStream_t s)
     const int ne = par ? 28 : 27;  // the L2L entry is last in each class
     gather_gemm_kernel<TPar, float><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
         level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(0, 28, 56, 84), make_int4(ne, ne, ne, ne),
-        c.waves, a.p, l, t->tabs.mfma_entries, (const float *)level_ptr<float>(a, l, false), nullptr, par,
-        (float *)level_ptr<float>(a, l, true), t->tabs.mfma_f, t->tabs.zero_row);
+        c.waves, a.p, l, t->tabs->mfma_entries, (const float *)level_ptr<float>(a, l, false), nullptr, par,
+        (float *)level_ptr<float>(a, l, true), t->tabs->mfma_f, t->tabs->zero_row);
 }
 
 // Stage 5 into level l on MFMA from the FP32 child level l + 1.
@@ -923,8 +923,8 @@ void m2m_mfma_launch(const FarArgs &a, int l, hipStream_t s)
     const ClassTiles c = class_tiles(one_class, n, 1);
     gather_gemm_kernel<float, TP><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
         level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(112, 112, 112, 112), make_int4(4, 0, 0, 0),
-        c.waves, a.p, l, t->tabs.mfma_entries, nullptr, (const float *)level_ptr<float>(a, l + 1, false), nullptr,
-        (TP *)level_ptr<TP>(a, l, false), t->tabs.mfma_f, t->tabs.zero_row);
+        c.waves, a.p, l, t->tabs->mfma_entries, nullptr, (const float *)level_ptr<float>(a, l + 1, false), nullptr,
+        (TP *)level_ptr<TP>(a, l, false), t->tabs->mfma_f, t->tabs->zero_row);
 }
 
 LevelClasses level_classes(const int64_t *class_off, int64_t n, int nclass)
@@ -955,10 +955,10 @@ void gemm_f64_launch(const FarArgs &a, int l, int mode, hipStream_t s)
     const int p = a.p;
     gather_gemm_f64_kernel<<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
         level_list(t, l), c, mode == 2 ? make_int4(112, 112, 112, 112) : make_int4(0, 28, 56, 84), l >= 3 ? 28 : 27, 4,
-        mode, p, l, t->tabs.mfma_entries, mode == 0 ? (const double *)(a.mp_d + level_base(l) * p) : nullptr,
+        mode, p, l, t->tabs->mfma_entries, mode == 0 ? (const double *)(a.mp_d + level_base(l) * p) : nullptr,
         mode == 2 ? (const double *)(a.mp_d + level_base(l + 1) * p) : nullptr,
         (mode == 0 && l >= 3) ? (const double *)(a.lo_d + level_base(l - 1) * p) : nullptr,
-        (double *)((mode == 0 ? a.lo_d : a.mp_d) + level_base(l) * p), t->tabs.mfma_d, t->tabs.zero_row);
+        (double *)((mode == 0 ? a.lo_d : a.mp_d) + level_base(l) * p), t->tabs->mfma_d, t->tabs->zero_row);
 }
 
 template <typename T, typename TPar>
@@ -1370,7 +1370,7 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
     const fmm_tree *t = a.t;
     const int L = t->depth;
     if (L < 2) return;
-    const Tables &tb = t->tabs;
+    const Tables &tb = *t->tabs;
     const bool fine_is_double = a.split >= L;  // FP64 precision: every level double
     // Stage 4: P2M into the leaf level.
     if (L <= a.split) {

@@ -9,6 +9,8 @@
 // derived from the multipole coefficients of section "Complexity Estimates" and the
 // expansion 1/(D + u - v) = sum_{l,m} (-1)^l C(l+m,l) u^l v^m / D^(l+m+1).
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "fmm_internal.h"
@@ -185,6 +187,21 @@ int upload_tables(Tables &tb, int p, std::string &err)
         return rc;
     }
     tb.p = p;
+    return 0;
+}
+
+int shared_tables(int device, int p, const Tables **out, std::string &err)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, Tables> cache;  // node addresses stay valid
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({device, p});
+    if (it == cache.end()) {
+        Tables tb;
+        if (int rc = upload_tables(tb, p, err)) return rc;
+        it = cache.emplace(std::make_pair(device, p), tb).first;
+    }
+    *out = &it->second;
     return 0;
 }
 

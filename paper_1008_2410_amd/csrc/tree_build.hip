@@ -179,9 +179,19 @@ inline unsigned grid_for(int64_t n, int per) { return (unsigned)std::max<int64_t
 // Device buffer owned for the duration of a build step.
 template <typename T>
 struct Buf {
+    // stream-ordered: allocated and freed in the order of the build's stream, so a
+    // temporary can be released while kernels that use it are still queued
     T *p = nullptr;
-    ~Buf() { hipFree(p); }
-    hipError_t alloc(int64_t count) { return hipMalloc((void **)&p, (size_t)std::max<int64_t>(count, 1) * sizeof(T)); }
+    hipStream_t s = nullptr;
+    ~Buf()
+    {
+        if (p) hipFreeAsync(p, s);
+    }
+    hipError_t alloc(int64_t count, hipStream_t stream)
+    {
+        s = stream;
+        return hipMallocAsync((void **)&p, (size_t)std::max<int64_t>(count, 1) * sizeof(T), stream);
+    }
     T *release()
     {
         T *q = p;
@@ -209,7 +219,7 @@ bool scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tota
 {
     const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
     Buf<uint32_t> sums, total;
-    if (!st.check(sums.alloc(nb), "scan workspace") || !st.check(total.alloc(1), "scan workspace")) return false;
+    if (!st.check(sums.alloc(nb, s), "scan workspace") || !st.check(total.alloc(1, s), "scan workspace")) return false;
     scan_tile_sums<<<(unsigned)nb, 256, 0, s>>>(in, n, sums.p);
     scan_sums<<<1, 256, 0, s>>>(sums.p, nb, total.p);
     scan_tiles<<<(unsigned)nb, 256, 0, s>>>(in, out, n, sums.p);
@@ -218,8 +228,6 @@ bool scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tota
         if (!st.check(hipMemcpyAsync(total_host, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "scan total") ||
             !st.check(hipStreamSynchronize(s), "scan total"))
             return false;
-    } else if (!st.check(hipStreamSynchronize(s), "scan")) {
-        return false;  // the workspace is freed on return
     }
     return true;
 }
@@ -231,8 +239,8 @@ bool radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t
     const int nb = (int)((n + kRsTile - 1) / kRsTile);
     Buf<uint64_t> k2;
     Buf<uint32_t> v2, counts;
-    if (!st.check(k2.alloc(n), "sort workspace") || !st.check(v2.alloc(n), "sort workspace") ||
-        !st.check(counts.alloc((int64_t)256 * nb), "sort workspace"))
+    if (!st.check(k2.alloc(n, s), "sort workspace") || !st.check(v2.alloc(n, s), "sort workspace") ||
+        !st.check(counts.alloc((int64_t)256 * nb, s), "sort workspace"))
         return false;
     uint64_t *ka = keys, *kb = k2.p;
     uint32_t *va = vals, *vb = v2.p;
@@ -249,7 +257,7 @@ bool radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t
             !st.check(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "sort copy"))
             return false;
     }
-    return st.check(hipStreamSynchronize(s), "sort");
+    return true;
 }
 
 // ---------------------------------------------------------------------------------
@@ -685,8 +693,15 @@ __global__ __launch_bounds__(256) void k_plan_fill(const int *__restrict__ ls, i
 // ---------------------------------------------------------------------------------
 int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
 {
-    hipFree(t->d_near_work);
-    hipFree(t->d_leaf_mask);
+    if (t->d_near_work || t->d_leaf_mask) {  // a rebuild (option change): the old plan may be in use
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            err = std::string("near-field plan: ") + hipGetErrorString(e);
+            return FMM_EDEVICE;
+        }
+        if (t->d_near_work) hipFreeAsync(t->d_near_work, s);
+        if (t->d_leaf_mask) hipFreeAsync(t->d_leaf_mask, s);
+    }
     t->d_near_work = nullptr;
     t->d_leaf_mask = nullptr;
     t->nunits_tc = t->nmut = t->nnear_work = t->mutual_pairs = 0;
@@ -697,8 +712,8 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
     Buf<uint32_t> nent;
     Buf<uint16_t> mask;
     Buf<unsigned long long> stats;
-    if (!st.check(nent.alloc(nleaf + 1), "near-field plan") || !st.check(mask.alloc(nleaf), "near-field plan") ||
-        !st.check(stats.alloc(4), "near-field plan") ||
+    if (!st.check(nent.alloc(nleaf + 1, s), "near-field plan") || !st.check(mask.alloc(nleaf, s), "near-field plan") ||
+        !st.check(stats.alloc(4, s), "near-field plan") ||
         !st.check(hipMemsetAsync(stats.p, 0, 4 * sizeof(unsigned long long), s), "near-field plan")) {
         err = st.msg;
         return st.code;
@@ -718,8 +733,8 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
     Buf<int4> work, sorted;
     Buf<uint64_t> key;
     Buf<uint32_t> val;
-    if (!st.check(work.alloc(total), "near-field plan") || !st.check(sorted.alloc(total), "near-field plan") ||
-        !st.check(key.alloc(total), "near-field plan") || !st.check(val.alloc(total), "near-field plan")) {
+    if (!st.check(work.alloc(total, s), "near-field plan") || !st.check(sorted.alloc(total, s), "near-field plan") ||
+        !st.check(key.alloc(total, s), "near-field plan") || !st.check(val.alloc(total, s), "near-field plan")) {
         err = st.msg;
         return st.code;
     }
@@ -750,6 +765,7 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
 int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
                       int64_t &bad_index)
 {
+    t->pooled = true;
     Status st;
     auto failed = [&]() {
         err = st.msg;
@@ -763,7 +779,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     bad_index = -1;
     Buf<int> flags;
     Buf<unsigned long long> first_bad;
-    if (!st.check(flags.alloc(1), "tree build") || !st.check(first_bad.alloc(1), "tree build") ||
+    if (!st.check(flags.alloc(1, s), "tree build") || !st.check(first_bad.alloc(1, s), "tree build") ||
         !st.check(hipMemsetAsync(flags.p, 0, sizeof(int), s), "tree build") ||
         !st.check(hipMemsetAsync(first_bad.p, 0xff, sizeof(unsigned long long), s), "tree build"))
         return failed();
@@ -777,7 +793,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         Buf<double4> part;
         std::vector<double4> h(nb);
         int hf = 0;
-        if (!st.check(part.alloc(nb), "tree build")) return failed();
+        if (!st.check(part.alloc(nb, s), "tree build")) return failed();
         k_minmax<<<nb, 256, 0, s>>>(xy2, n, part.p, flags.p);
         if (!st.check(hipMemcpyAsync(h.data(), part.p, nb * sizeof(double4), hipMemcpyDeviceToHost, s), "tree build") ||
             !st.check(hipMemcpyAsync(&hf, flags.p, sizeof(int), hipMemcpyDeviceToHost, s), "tree build") ||
@@ -804,7 +820,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     // Stage 2: keys, then the stable sort by (leaf, sub-leaf key), ties by user index.
     Buf<uint64_t> key;
     Buf<uint32_t> val;
-    if (!st.check(key.alloc(n), "tree build") || !st.check(val.alloc(n), "tree build")) return failed();
+    if (!st.check(key.alloc(n, s), "tree build") || !st.check(val.alloc(n, s), "tree build")) return failed();
     k_keys<<<grid_for(n, 256), 256, 0, s>>>(xy2, n, t->x0, t->y0, w, nside, key.p, val.p, flags.p, first_bad.p);
     {
         int hf = 0;
@@ -820,26 +836,26 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         }
     }
     if (!radix_sort(key.p, val.p, n, 2 * L + 12, s, st)) return failed();
-    if (!st.check(hipMalloc((void **)&t->d_perm, n * sizeof(int)), "permutation") ||
-        !st.check(hipMalloc((void **)&t->d_leaf_of, n * sizeof(int)), "leaf ids") ||
-        !st.check(hipMalloc((void **)&t->d_xy, n * sizeof(double2)), "sorted positions") ||
-        !st.check(hipMalloc((void **)&t->d_leaf_start, (nleaf + 1) * sizeof(int)), "leaf offsets"))
+    if (!st.check(hipMallocAsync((void **)&t->d_perm, n * sizeof(int), s), "permutation") ||
+        !st.check(hipMallocAsync((void **)&t->d_leaf_of, n * sizeof(int), s), "leaf ids") ||
+        !st.check(hipMallocAsync((void **)&t->d_xy, n * sizeof(double2), s), "sorted positions") ||
+        !st.check(hipMallocAsync((void **)&t->d_leaf_start, (nleaf + 1) * sizeof(int), s), "leaf offsets"))
         return failed();
     k_sorted<<<grid_for(n, 256), 256, 0, s>>>(key.p, val.p, xy2, n, t->d_perm, t->d_leaf_of, t->d_xy);
     k_leaf_start<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(t->d_leaf_of, n, nleaf, t->d_leaf_start);
     // Occupancy of all levels.
     const int64_t ncells = level_base(L + 1);
-    if (!st.check(hipMalloc((void **)&t->d_counts, ncells * sizeof(int)), "cell counts")) return failed();
+    if (!st.check(hipMallocAsync((void **)&t->d_counts, ncells * sizeof(int), s), "cell counts")) return failed();
     k_counts<<<grid_for(ncells, 256), 256, 0, s>>>(t->d_leaf_start, L, ncells, t->d_counts);
     // Tiles and their boxes.
     uint32_t ntiles = 0;
     Buf<uint32_t> tstart;
-    if (!st.check(tstart.alloc(nleaf + 1), "tile offsets")) return failed();
+    if (!st.check(tstart.alloc(nleaf + 1, s), "tile offsets")) return failed();
     k_leaf_tiles<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(t->d_leaf_start, nleaf, tstart.p);
     if (!scan_exclusive(tstart.p, tstart.p, nleaf + 1, &ntiles, s, st)) return failed();
     Buf<int> tile_leaf;
-    if (!st.check(tile_leaf.alloc(ntiles), "tile leaves") ||
-        !st.check(hipMalloc((void **)&t->d_tile_box, std::max<size_t>(ntiles, 1) * sizeof(float4)), "tile boxes"))
+    if (!st.check(tile_leaf.alloc(ntiles, s), "tile leaves") ||
+        !st.check(hipMallocAsync((void **)&t->d_tile_box, std::max<size_t>(ntiles, 1) * sizeof(float4), s), "tile boxes"))
         return failed();
     k_tile_leaf<<<grid_for(nleaf, 256), 256, 0, s>>>(tstart.p, nleaf, tile_leaf.p);
     k_tile_box<<<grid_for(ntiles, 256), 256, 0, s>>>(tile_leaf.p, tstart.p, t->d_leaf_start, t->d_xy, ntiles, t->x0,
@@ -854,10 +870,10 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     uint32_t nlist = 0;
     if (nflags > 0) {
         Buf<uint32_t> pos;
-        if (!st.check(pos.alloc(nflags + 1), "cell lists")) return failed();
+        if (!st.check(pos.alloc(nflags + 1, s), "cell lists")) return failed();
         k_list_flags<<<grid_for(nflags, 256), 256, 0, s>>>(t->d_counts, nflags, pos.p);
         if (!scan_exclusive(pos.p, pos.p, nflags, &nlist, s, st)) return failed();
-        if (!st.check(hipMalloc((void **)&t->d_lists, std::max<size_t>(nlist, 1) * sizeof(int)), "cell lists"))
+        if (!st.check(hipMallocAsync((void **)&t->d_lists, std::max<size_t>(nlist, 1) * sizeof(int), s), "cell lists"))
             return failed();
         k_list_scatter<<<grid_for(nflags, 256), 256, 0, s>>>(t->d_counts, nflags, pos.p, t->d_lists);
         // list offsets at the level and class boundaries
@@ -872,7 +888,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         Buf<uint32_t> dval;
         std::vector<uint32_t> hv(idx.size());
         const int m = (int)idx.size();
-        if (!st.check(didx.alloc(m), "cell lists") || !st.check(dval.alloc(m), "cell lists") ||
+        if (!st.check(didx.alloc(m, s), "cell lists") || !st.check(dval.alloc(m, s), "cell lists") ||
             !st.check(hipMemcpyAsync(didx.p, idx.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s), "cell lists"))
             return failed();
         k_gather_u32<<<1, 256, 0, s>>>(pos.p, didx.p, m, dval.p);
@@ -885,7 +901,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
             for (int q = 0; q < 4; ++q) t->class_off[4 * l + q] = (int64_t)hv[4 * (l - 2) + q] - off;
             t->list_len[l] = (l < L ? (int64_t)hv[4 * (l - 1)] : (int64_t)nlist) - off;
         }
-    } else if (!st.check(hipMalloc((void **)&t->d_lists, sizeof(int)), "cell lists")) {
+    } else if (!st.check(hipMallocAsync((void **)&t->d_lists, sizeof(int), s), "cell lists")) {
         return failed();
     }
     // Statistics and the target-centric units, heaviest first.
@@ -893,10 +909,10 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     Buf<int4> units;
     Buf<uint64_t> ukey;
     Buf<uint32_t> uval;
-    if (!st.check(stats.alloc(4), "statistics") ||
+    if (!st.check(stats.alloc(4, s), "statistics") ||
         !st.check(hipMemsetAsync(stats.p, 0, 4 * sizeof(unsigned long long), s), "statistics") ||
-        !st.check(units.alloc(ntiles), "work units") || !st.check(ukey.alloc(ntiles), "work units") ||
-        !st.check(uval.alloc(ntiles), "work units"))
+        !st.check(units.alloc(ntiles, s), "work units") || !st.check(ukey.alloc(ntiles, s), "work units") ||
+        !st.check(uval.alloc(ntiles, s), "work units"))
         return failed();
     k_leaf_stats<<<grid_for(nleaf, 256), 256, 0, s>>>(t->d_leaf_start, L, (const uint32_t *)t->d_tile_start, stats.p,
                                                        units.p, ukey.p, uval.p);
@@ -905,7 +921,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
             k_m2l_count<<<grid_for(t->list_len[l], 256), 256, 0, s>>>(t->d_lists + t->list_off[l], t->list_len[l], l,
                                                                        t->d_counts, stats.p);
     if (!radix_sort(ukey.p, uval.p, ntiles, 32, s, st)) return failed();
-    if (!st.check(hipMalloc((void **)&t->d_units, std::max<size_t>(ntiles, 1) * sizeof(int4)), "work units"))
+    if (!st.check(hipMallocAsync((void **)&t->d_units, std::max<size_t>(ntiles, 1) * sizeof(int4), s), "work units"))
         return failed();
     k_gather<int4><<<grid_for(ntiles, 256), 256, 0, s>>>(units.p, uval.p, ntiles, t->d_units);
     {
@@ -923,9 +939,9 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     int shift = kStageShiftMin;
     while ((((n - 1) >> shift) + 1) > 256) ++shift;
     t->stage_shift = shift;
-    if (!st.check(hipMalloc((void **)&t->d_gpos1, n * sizeof(int)), "staging slots") ||
-        !st.check(hipMalloc((void **)&t->d_gpos2, n * sizeof(int)), "staging slots") ||
-        !st.check(hipMalloc((void **)&t->d_st1, n * sizeof(double)), "staging array"))
+    if (!st.check(hipMallocAsync((void **)&t->d_gpos1, n * sizeof(int), s), "staging slots") ||
+        !st.check(hipMallocAsync((void **)&t->d_gpos2, n * sizeof(int), s), "staging slots") ||
+        !st.check(hipMallocAsync((void **)&t->d_st1, n * sizeof(double), s), "staging array"))
         return failed();
     k_stage_keys<<<grid_for(n, 256), 256, 0, s>>>(t->d_perm, n, shift, key.p, val.p);
     if (!radix_sort(key.p, val.p, n, 8, s, st)) return failed();

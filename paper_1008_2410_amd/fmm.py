@@ -66,6 +66,22 @@ class Tree:
                     "fmm_build_tree" if builder == "device" else "fmm_build_tree_host")
         self._h = handle
 
+    def rebuild(self, xy: torch.Tensor, root_box=None, stream=None) -> "Tree":
+        """Rebuild in place for new positions of the same n particles (fmm_rebuild_tree):
+        same depth and options, the evaluation workspace kept.  Returns self."""
+        if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be an (n, 2) tensor")
+        if xy.device != self.device:
+            raise ValueError("xy must be on the tree's device")
+        xy = _as_device_f64(xy, "xy", (self.n, 2), None)
+        rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_rebuild_tree(self.handle, _ptr(xy), self.n, rb, _stream_ptr(stream),
+                                              ctypes.byref(handle)), "fmm_rebuild_tree")
+        self._h = handle
+        return self
+
     # -- lifetime -----------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

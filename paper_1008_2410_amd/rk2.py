@@ -7,7 +7,8 @@ fix a time integrator; this module uses the explicit midpoint rule (RK2),
     x_{n+1/2} = x_n + (dt/2) u(x_n),     x_{n+1} = x_n + dt u(x_{n+1/2}),
 
 with every velocity an FMM evaluation (stages 4-10) over a tree rebuilt for the
-current positions (stages 1-3), as the positions change.
+current positions (stages 1-3), as the positions change (Tree.rebuild: the evaluation
+workspace of the tree is kept from one rebuild to the next).
 
 The gradient of a loss L(x_N) with respect to x_0 and Gamma is the discrete adjoint of
 those steps, run backwards with per-step checkpoints (only x_n is kept per step; the
@@ -52,9 +53,10 @@ def _sample_memory(device, stats: RK2Stats):
     stats.peak_bytes = max(stats.peak_bytes, total - free)
 
 
-def _velocity(xy, gamma, sigma, depth, p, precision, root_box, stats: RK2Stats):
+def _velocity(tree, xy, gamma, sigma, depth, p, precision, root_box, stats: RK2Stats):
+    """u(xy) over `tree` rebuilt for xy (a new tree when it is None); returns (tree, u)."""
     t0 = time.perf_counter()
-    tree = Tree(xy, depth, root_box)
+    tree = Tree(xy, depth, root_box) if tree is None else tree.rebuild(xy, root_box)
     torch.cuda.synchronize(xy.device)
     t1 = time.perf_counter()
     uv = tree.velocity(gamma, sigma, p, precision)
@@ -75,14 +77,17 @@ def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int
     x = xy0.detach().contiguous()
     g = gamma.detach().contiguous()
     checkpoints = []
-    for _ in range(steps):
-        checkpoints.append(x)
-        tree, u0 = _velocity(x, g, sigma, depth, p, precision, root_box, stats)
-        tree.close()
-        xm = x + (0.5 * dt) * u0
-        tree, um = _velocity(xm, g, sigma, depth, p, precision, root_box, stats)
-        tree.close()
-        x = x + dt * um
+    tree = None
+    try:
+        for _ in range(steps):
+            checkpoints.append(x)
+            tree, u0 = _velocity(tree, x, g, sigma, depth, p, precision, root_box, stats)
+            xm = x + (0.5 * dt) * u0
+            tree, um = _velocity(tree, xm, g, sigma, depth, p, precision, root_box, stats)
+            x = x + dt * um
+    finally:
+        if tree is not None:
+            tree.close()
     return x, checkpoints
 
 
@@ -93,27 +98,31 @@ def rk2_backward(checkpoints, gamma: torch.Tensor, sigma: float, depth: int, p: 
     g = gamma.detach().contiguous()
     lam = dl_dxN.detach().contiguous().clone()
     dgamma = torch.zeros_like(g)
-    for x in reversed(checkpoints):
-        t0 = time.perf_counter()
-        tree0, u0 = _velocity(x, g, sigma, depth, p, precision, root_box, stats)
-        xm = x + (0.5 * dt) * u0
-        treem, _ = _velocity(xm, g, sigma, depth, p, precision, root_box, stats)
-        t1 = time.perf_counter()
-        mu = dt * lam
-        dgm, dxm, dsm = treem.velocity_backward(g, sigma, p, precision, mu, need_src=True)
-        torch.cuda.synchronize(x.device)
-        _sample_memory(x.device, stats)
-        treem.close()
-        lam_mid = dxm + dsm
-        nu = (0.5 * dt) * lam_mid
-        dg0, dx0, ds0 = tree0.velocity_backward(g, sigma, p, precision, nu, need_src=True)
-        tree0.close()
-        lam = lam + lam_mid + dx0 + ds0
-        dgamma += dgm + dg0
-        torch.cuda.synchronize(x.device)
-        stats.backward += time.perf_counter() - t1
-        stats.vjps += 2
-        stats.per_step.append(time.perf_counter() - t0)
+    tree0 = treem = None
+    try:
+        for x in reversed(checkpoints):
+            t0 = time.perf_counter()
+            tree0, u0 = _velocity(tree0, x, g, sigma, depth, p, precision, root_box, stats)
+            xm = x + (0.5 * dt) * u0
+            treem, _ = _velocity(treem, xm, g, sigma, depth, p, precision, root_box, stats)
+            t1 = time.perf_counter()
+            mu = dt * lam
+            dgm, dxm, dsm = treem.velocity_backward(g, sigma, p, precision, mu, need_src=True)
+            torch.cuda.synchronize(x.device)
+            _sample_memory(x.device, stats)
+            lam_mid = dxm + dsm
+            nu = (0.5 * dt) * lam_mid
+            dg0, dx0, ds0 = tree0.velocity_backward(g, sigma, p, precision, nu, need_src=True)
+            lam = lam + lam_mid + dx0 + ds0
+            dgamma += dgm + dg0
+            torch.cuda.synchronize(x.device)
+            stats.backward += time.perf_counter() - t1
+            stats.vjps += 2
+            stats.per_step.append(time.perf_counter() - t0)
+    finally:
+        for tr in (tree0, treem):
+            if tr is not None:
+                tr.close()
     return lam, dgamma
 
 

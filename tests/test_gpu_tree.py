@@ -100,3 +100,85 @@ def test_device_build_errors(fmm_mod):
     with pytest.raises(_lib.FmmError) as e:
         fmm_mod.Tree(_t(xy), 3, None)
     assert e.value.status == _lib.FMM_EINVAL
+
+
+def _same_tree_outputs(ta, tb, g, sigma, p, dl):
+    """Bit-exact equality of two trees' facts and of every evaluation they give."""
+    assert ta.info() == tb.info()
+    assert ta.near_plan() == tb.near_plan()
+    assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(ta.permutation(), tb.permutation()))
+    for precision in ("mixed", "fp64"):
+        assert np.array_equal(ta.velocity(g, sigma, p, precision).cpu().numpy(),
+                              tb.velocity(g, sigma, p, precision).cpu().numpy()), precision
+        a = ta.velocity_parts(g, sigma, p, precision)
+        b = tb.velocity_parts(g, sigma, p, precision)
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b)), precision
+        a = ta.velocity_backward(g, sigma, p, precision, dl, need_src=True)
+        b = tb.velocity_backward(g, sigma, p, precision, dl, need_src=True)
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b)), precision
+
+
+def test_rebuild_equals_fresh_tree(fmm_mod):
+    """A rebuilt tree (new positions, the old tree's workspace) gives what a tree built
+    afresh for those positions gives, bit for bit: from a uniform cloud to Gaussian
+    patches in the same root box (most cells fall empty, and their multipoles must not
+    keep the old values), and back; the options of the old tree carry over."""
+    w = W.gaussian_patches(n=60000, depth=5, p=12, sigma=0.004, seed=11, precision="fp64")
+    r = np.random.Generator(np.random.PCG64(21))
+    lo = min(0.0, float(w.xy.min())) - 1e-3
+    box = (lo, lo, max(1.0, float(w.xy.max())) + 1e-3 - lo)  # holds both clouds
+    x_uni = _t(r.random((w.n, 2)))
+    x_pat = _t(w.xy)
+    g = _t(w.gamma)
+    dl = _t(r.standard_normal((w.n, 2)))
+    tree = fmm_mod.Tree(x_uni, w.depth, box)
+    tree.set_option(7, 48)  # dense leaf threshold
+    tree.set_option(2, 2)   # coarse level
+    # fill the workspace (both precisions, the adjoint's arrays too) with this tree's values
+    for precision in ("fp64", "mixed"):
+        tree.velocity(g, w.sigma, w.p, precision)
+        tree.velocity_backward(g, w.sigma, w.p, precision, dl, need_src=True)
+    for x in (x_pat, x_uni):
+        tree.rebuild(x, box)
+        fresh = fmm_mod.Tree(x, w.depth, box)
+        fresh.set_option(7, 48)
+        fresh.set_option(2, 2)
+        _same_tree_outputs(tree, fresh, g, w.sigma, w.p, dl)
+        fresh.close()
+    # bounding-square rebuild (root box from the new positions)
+    tree.rebuild(x_pat)
+    fresh = fmm_mod.Tree(x_pat, w.depth)
+    fresh.set_option(7, 48)
+    fresh.set_option(2, 2)
+    _same_tree_outputs(tree, fresh, g, w.sigma, w.p, dl)
+    tree.close()
+
+
+def test_rebuild_errors_leave_the_tree(fmm_mod):
+    """A rebuild that fails (other n, a particle outside the root box, a closed tree)
+    leaves the old tree as it was."""
+    import ctypes
+
+    from paper_1008_2410_amd import _lib
+    r = np.random.Generator(np.random.PCG64(22))
+    n = 2000
+    xy = _t(r.random((n, 2)))
+    g = _t(r.standard_normal(n))
+    tree = fmm_mod.Tree(xy, 4, (0.0, 0.0, 1.0))
+    before = tree.velocity(g, 0.01, 8, "fp64").cpu().numpy()
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    other = _t(r.random((n + 1, 2)))
+    rc = lib.fmm_rebuild_tree(tree.handle, ctypes.c_void_p(other.data_ptr()), n + 1, None, None, ctypes.byref(out))
+    assert rc == _lib.FMM_EINVAL and not out.value
+    with pytest.raises(ValueError):
+        tree.rebuild(other)
+    bad = r.random((n, 2))
+    bad[7] = (1.5, 0.5)
+    with pytest.raises(_lib.FmmError) as e:
+        tree.rebuild(_t(bad), (0.0, 0.0, 1.0))
+    assert e.value.status == _lib.FMM_ERANGE and "particle 7" in str(e.value)
+    assert np.array_equal(tree.velocity(g, 0.01, 8, "fp64").cpu().numpy(), before)
+    rc = lib.fmm_rebuild_tree(None, ctypes.c_void_p(xy.data_ptr()), n, None, None, ctypes.byref(out))
+    assert rc == _lib.FMM_ESTATE
+    tree.close()
