@@ -207,9 +207,9 @@ def adaptive_leg(torch, dev, workloads):
     """Uneven distributions: the adaptive tree (leaves capped at max_leaf particles) against
     the uniform tree at several depths, on the 2^24-particle patch workload (depth <= 10,
     every leaf wider than 8 sigma) and on a clustered workload with a uniform background
-    (density range 1e5).  Per tree: build time (host for the adaptive tree, device for the
-    uniform one), the mixed evaluation's device time, near-field pairs, and the error
-    against the direct sum on sampled particles.  One JSON line of its own."""
+    (density range 1e5).  Per tree: build time (both trees built on the device; host clock
+    around the synchronised build), the mixed evaluation's device time, near-field pairs,
+    and the error against the direct sum on sampled particles.  One JSON line of its own."""
     import oracle
     from paper_1008_2410_amd import fmm
     oracle.build()
@@ -247,7 +247,7 @@ def adaptive_leg(torch, dev, workloads):
             info = tree.info()
             ms = dev_ms(lambda: tree.velocity(g, w.sigma, w.p, "mixed", out=out), 5)
             err = rel_l2(out.cpu().numpy()[idx], ref)
-            row = {"tree": kind, "build_s": round(t_build, 3), "ms": round(ms, 3), "rel_l2_vs_direct": float(f"{err:.3e}"),
+            row = {"tree": kind, "build_ms": round(1e3 * t_build, 2), "ms": round(ms, 3), "rel_l2_vs_direct": float(f"{err:.3e}"),
                    "p2p_pairs": info["p2p_pairs"]}
             if kind == "uniform":
                 row["depth"] = a

@@ -60,9 +60,10 @@ enum {
     FMM_AT_COUNT = 8
 };
 
-/* Builds the adaptive tree of n particles xy (device, (n, 2)): binning, sorting and
- * the lists on the host, then everything the evaluation reads uploaded to the current
- * device; synchronises `stream` to read xy.  max_leaf >= 1, 0 <= max_depth <= 15,
+/* Builds the adaptive tree of n particles xy (device, (n, 2)) on the current device:
+ * keys on the finest grid, a stable sort, the cells level by level, the U, V, W, X
+ * lists and the near-field plan, all in device kernels on `stream` (which is
+ * synchronised to read back sizes).  max_leaf >= 1, 0 <= max_depth <= 15,
  * 1 <= n < 2^31.  root_box (host, {x0, y0, side}) or NULL for the bounding square with
  * side (1 + 2^-20) max(range x, range y).  Returns FMM_EINVAL for bad arguments or a
  * non-finite position, FMM_ERANGE (naming the particle) for a particle outside root_box,
@@ -70,6 +71,12 @@ enum {
  * memory until fmm_atree_destroy. */
 int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box, void *stream,
                     fmm_atree **out);
+
+/* The same tree built on the host (positions copied down once, the arrays uploaded):
+ * the reference that the device build is checked against.  Arguments and results as
+ * fmm_atree_build; the two trees are identical array for array. */
+int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
+                         void *stream, fmm_atree **out);
 
 /* Host: sizes[FMM_AT_COUNT] (see the enum), root_box[3] (may be NULL). */
 int fmm_atree_info(const fmm_atree *tree, int64_t *sizes, double *root_box);

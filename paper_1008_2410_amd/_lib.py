@@ -38,6 +38,7 @@ SIGNATURES = {
     "fmm_last_error": (ctypes.c_char_p, []),
     # include/fmm2d_adaptive.h
     "fmm_atree_build": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fmm_atree_build_host": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_atree_info": (_I, [_P, _P, _P]),
     "fmm_atree_leaves": (_I, [_P, _P, _P, _P]),
     "fmm_atree_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),

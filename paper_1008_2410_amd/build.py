@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm2d.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "tree_build.hip", "adaptive.hip", "tables.cpp", "api.cpp", "adaptive.cpp"]
+SOURCES = ["kernels.hip", "tree_build.hip", "adaptive.hip", "adaptive_build.hip", "tables.cpp", "api.cpp",
+           "adaptive.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 arithmetic is switched off for the device code (the compiler would

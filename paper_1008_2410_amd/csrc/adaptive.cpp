@@ -1,6 +1,6 @@
 // C ABI of the adaptive-tree variant (include/fmm2d_adaptive.h): the tree, its lists
-// and work units built on the host, the evaluation enqueued on the device
-// (adaptive.hip).
+// and work units built on the device (adaptive_build.hip) or, as the reference, on the
+// host (here); the evaluation enqueued on the device (adaptive.hip).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -36,13 +36,20 @@ void free_atree(fmm_atree *t)
 {
     if (!t) return;
     AtreeDev &d = t->d;
+    // the device build's arrays come from the stream-ordered pool
+    if (t->pooled) hipDeviceSynchronize();
     for (void *p : {(void *)d.perm, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
                     (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
                     (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
                     (void *)d.p2m_cells, (void *)d.inner, (void *)d.tile_start, (void *)d.tile_box,
                     (void *)d.work, (void *)d.leaf_start, (void *)d.leaf_tile, (void *)d.tile_box_leaf,
-                    (void *)d.mask})
-        hipFree(p);
+                    (void *)d.mask}) {
+        if (!p) continue;
+        if (t->pooled)
+            hipFreeAsync(p, nullptr);
+        else
+            hipFree(p);
+    }
     free_ws(t->ws);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
@@ -263,12 +270,12 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     return FMM_OK;
 }
 
-}  // namespace
-
-extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
-                               void *stream, fmm_atree **out)
+// Argument checks shared by both builds; a new tree with the caller's parameters.
+int new_atree(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box, fmm_atree **out,
+              fmm_atree *&t)
 {
     clear_last_error();
+    t = nullptr;
     if (!out) return fail(FMM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!xy) return fail(FMM_EINVAL, "xy is NULL");
@@ -278,17 +285,63 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
     if (root_box && (!std::isfinite(root_box[0]) || !std::isfinite(root_box[1]) || !(root_box[2] > 0.0) ||
                      !std::isfinite(root_box[2])))
         return fail(FMM_EINVAL, "root_box must be finite with side > 0");
-    fmm_atree *t = new (std::nothrow) fmm_atree;
+    t = new (std::nothrow) fmm_atree;
     if (!t) return fail(FMM_ENOMEM, "host allocation failed");
     t->n = n;
     t->max_leaf = max_leaf;
     t->max_depth = max_depth;
-    int rc = FMM_OK;
+    const hipError_t e = hipGetDevice(&t->device);
+    if (e != hipSuccess) {
+        free_atree(t);
+        t = nullptr;
+        return hip_fail(e, "hipGetDevice");
+    }
+    return FMM_OK;
+}
+
+int finish_atree(fmm_atree *t)
+{
+    hipError_t e = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
+    return e != hipSuccess ? hip_fail(e, "creating the side stream") : FMM_OK;
+}
+
+}  // namespace
+
+extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
+                               void *stream, fmm_atree **out)
+{
+    fmm_atree *t = nullptr;
+    int rc = new_atree(xy, n, max_leaf, max_depth, root_box, out, t);
+    if (rc) return rc;
+    retain_pool(t->device);
+    std::string err;
+    int64_t bad = -1;
+    rc = build_atree_device(t, xy, root_box, (hipStream_t)stream, err, bad);
+    if (rc) {
+        if (bad >= 0) err += " (particle " + std::to_string(bad) + ")";
+        fail(rc, err);
+    } else {
+        rc = finish_atree(t);
+    }
+    if (rc) {
+        free_atree(t);
+        return rc;
+    }
+    *out = t;
+    return FMM_OK;
+}
+
+extern "C" int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
+                                    void *stream, fmm_atree **out)
+{
+    fmm_atree *t = nullptr;
+    int rc = new_atree(xy, n, max_leaf, max_depth, root_box, out, t);
+    if (rc) return rc;
     try {
-        hipError_t e = hipGetDevice(&t->device);
         std::vector<double> h(2 * (size_t)n);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream);
+        hipError_t e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream);
         if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
         if (e != hipSuccess) {
             free_atree(t);
@@ -402,17 +455,6 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         std::copy(sz, sz + 8, t->sizes);
         t->np2m = (int64_t)p2m.size();
 
-        // per-particle leaf in user order (host copy for fmm_atree_leaves)
-        t->leaf_level.resize((size_t)n);
-        t->leaf_ix.resize((size_t)n);
-        t->leaf_iy.resize((size_t)n);
-        for (int64_t j = 0; j < n; ++j) {
-            const HostCell &c = ht.cells[leaf_sorted[j]];
-            t->leaf_level[order[j]] = c.level;
-            t->leaf_ix[order[j]] = c.ix;
-            t->leaf_iy[order[j]] = c.iy;
-        }
-
         // 64-particle tiles of each leaf (leaves in sorted order) with their boxes: absolute
         // (relative to x0, y0) for the target-centric units, in leaf widths about the leaf
         // centre, rounded outwards to FP32, for the mutual items
@@ -460,11 +502,6 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         std::vector<uint16_t> mask(K, 0);
         std::vector<int4> work;
         std::vector<int64_t> cost;
-        auto nch16 = [](int64_t len) { return (len + 15) >> 4; };
-        auto block_steps = [&](int64_t cs, int64_t cr) {
-            const int64_t fs = cs / 64, fr = cr / 64, rs = cs % 64, rr = cr % 64;
-            return 16 * (fs * fr * 4 + fs * nch16(rr) + fr * nch16(rs) + std::min(nch16(rs), nch16(rr)));
-        };
         const int up[4][2] = {{1, 0}, {-1, 1}, {0, 1}, {1, 1}};
         int64_t mpairs = 0, nmut = 0, ntc = 0;
         for (int li = 0; li < NL; ++li) {
@@ -484,21 +521,15 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
                 m |= 1u << 9;
                 for (int b = c.first; b < c.first + c.count; b += 64) {
                     const int len = std::min(64, c.first + c.count - b);
-                    int logtp = 0;
-                    while ((1 << logtp) < len) ++logtp;
-                    const int kstride = 64 >> logtp;
-                    work.push_back(make_int4(k, b, len, logtp | (dense ? 16 : 0)));
-                    cost.push_back(2 * ((nsrc + kstride - 1) / kstride));
+                    work.push_back(make_int4(k, b, len, at_log2_lanes(len) | (dense ? 16 : 0)));
+                    cost.push_back(at_unit_cost(nsrc, len));
                     ++ntc;
                 }
             }
             mask[k] = (uint16_t)m;
             if (!dense) continue;
-            const int64_t f = c.count / 64, r = c.count % 64;
-            const int64_t diag = 16 * (f * 4 + nch16(r));
-            const int64_t st = 16 * (f * (f - 1) / 2 * 4 + f * nch16(r));
             work.push_back(make_int4(li, li, 4 | (4 << 4), kMutualItem | (c.level << 9)));
-            cost.push_back(3 * st + 2 * diag);
+            cost.push_back(at_self_cost(c.count));
             ++nmut;
             mpairs += (int64_t)c.count * (c.count - 1);
             for (const auto &o : up) {
@@ -506,7 +537,7 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
                 if (R < 0 || !ht.cells[R].leaf || ht.cells[R].count < D) continue;
                 const int ds = 3 * (o[1] + 1) + (o[0] + 1);
                 work.push_back(make_int4(li, leaf_index[R], ds | ((8 - ds) << 4), kMutualItem | (c.level << 9)));
-                cost.push_back(3 * block_steps(c.count, ht.cells[R].count));
+                cost.push_back(3 * at_pair_steps(c.count, ht.cells[R].count));
                 ++nmut;
                 mpairs += 2 * (int64_t)c.count * ht.cells[R].count;
             }
@@ -554,12 +585,7 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         if (!rc) rc = upload(&d.leaf_tile, leaf_tile, "leaf tiles");
         if (!rc) rc = upload(&d.tile_box_leaf, boxes_leaf, "tile boxes");
         if (!rc) rc = upload(&d.mask, mask, "near-field mask");
-        if (!rc) {
-            hipError_t e2 = hipStreamCreateWithFlags(&t->own_side, hipStreamNonBlocking);
-            if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming);
-            if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming);
-            if (e2 != hipSuccess) rc = hip_fail(e2, "creating the side stream");
-        }
+        if (!rc) rc = finish_atree(t);
     } catch (const std::bad_alloc &) {
         rc = fail(FMM_ENOMEM, "host allocation failed while building the adaptive tree");
     }
@@ -589,9 +615,23 @@ extern "C" int fmm_atree_leaves(const fmm_atree *t, int32_t *level, int32_t *ix,
 {
     clear_last_error();
     if (!t) return fail(FMM_ESTATE, "null tree handle");
-    if (level) std::copy(t->leaf_level.begin(), t->leaf_level.end(), level);
-    if (ix) std::copy(t->leaf_ix.begin(), t->leaf_ix.end(), ix);
-    if (iy) std::copy(t->leaf_iy.begin(), t->leaf_iy.end(), iy);
+    try {
+        std::vector<int> perm((size_t)t->n), leaf((size_t)t->n);
+        std::vector<int4> cell((size_t)t->ncells);
+        HIP_TRY(hipSetDevice(t->device));
+        HIP_TRY(hipMemcpy(perm.data(), t->d.perm, perm.size() * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(leaf.data(), t->d.leaf_of, leaf.size() * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(cell.data(), t->d.cell, cell.size() * sizeof(int4), hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < t->n; ++j) {
+            const int4 c = cell[leaf[j]];
+            const int u = perm[j];
+            if (level) level[u] = c.x;
+            if (ix) ix[u] = c.y;
+            if (iy) iy[u] = c.z;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(FMM_ENOMEM, "host allocation failed");
+    }
     return FMM_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 namespace fmm {
@@ -41,6 +42,38 @@ struct AtreeDev {
     uint16_t *mask = nullptr;      // per cell: slots d written by mutual items, bit 9 target-centric part
 };
 
+// Costs of near-field work (steps of the near kernel), for the heaviest-first order of
+// the plan; the same functions serve the host and the device build.
+__host__ __device__ inline int64_t at_chunks16(int64_t len) { return (len + 15) >> 4; }
+// a mutual item between two leaves of cs and cr particles
+__host__ __device__ inline int64_t at_pair_steps(int64_t cs, int64_t cr)
+{
+    const int64_t fs = cs / 64, fr = cr / 64, rs = cs % 64, rr = cr % 64;
+    const int64_t a = at_chunks16(rs), b = at_chunks16(rr);
+    return 16 * (fs * fr * 4 + fs * b + fr * a + (a < b ? a : b));
+}
+// the mutual item of a dense leaf with itself
+__host__ __device__ inline int64_t at_self_cost(int64_t c)
+{
+    const int64_t f = c / 64, r = c % 64;
+    const int64_t diag = 16 * (f * 4 + at_chunks16(r));
+    const int64_t st = 16 * (f * (f - 1) / 2 * 4 + f * at_chunks16(r));
+    return 3 * st + 2 * diag;
+}
+// log2 of the lanes per target of a target-centric unit of len targets (the smallest
+// power of two >= len), and its cost over nsrc sources
+__host__ __device__ inline int at_log2_lanes(int len)
+{
+    int l = 0;
+    while ((1 << l) < len) ++l;
+    return l;
+}
+__host__ __device__ inline int64_t at_unit_cost(int64_t nsrc, int len)
+{
+    const int64_t stride = 64 >> at_log2_lanes(len);
+    return 2 * ((nsrc + stride - 1) / stride);
+}
+
 struct AtreeWs {
     int p = 0, precision = -1;
     void *rec = nullptr;        // float4 or double4 records {alpha (z - c_leaf), Gamma, 0}
@@ -67,7 +100,7 @@ struct fmm_atree {
     int dense_leaf = 32;
     std::vector<int> level_off;   // max_depth + 2 entries
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
-    std::vector<int> leaf_level, leaf_ix, leaf_iy;  // per particle, user order (host)
+    bool pooled = false;  // device arrays from the stream-ordered pool (the device build)
     fmm::AtreeDev d;
     fmm::AtreeWs ws;
     hipStream_t own_side = nullptr;
@@ -83,6 +116,13 @@ struct AtreeCall {
     int is_double;
     double alpha;   // record scale (as for the uniform tree)
 };
+
+// Stages 1-3 on the device (adaptive_build.hip): fills t->d and the host facts of t
+// (n, max_leaf, max_depth and dense_leaf set by the caller) with the arrays the host build
+// makes.  Returns FMM_OK or a status with err; bad_index names a particle outside the root
+// cell or non-finite (else -1).
+int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
+                       int64_t &bad_index);
 
 void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
 void launch_atree_far(const AtreeCall &c, hipStream_t s);

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/fmm2d.h"
+#include "build_prims.h"
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -172,92 +173,6 @@ __global__ __launch_bounds__(256) void rs_scatter(const uint64_t *__restrict__ k
         __syncthreads();
         start[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
     }
-}
-
-inline unsigned grid_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
-
-// Device buffer owned for the duration of a build step.
-template <typename T>
-struct Buf {
-    // stream-ordered: allocated and freed in the order of the build's stream, so a
-    // temporary can be released while kernels that use it are still queued
-    T *p = nullptr;
-    hipStream_t s = nullptr;
-    ~Buf()
-    {
-        if (p) hipFreeAsync(p, s);
-    }
-    hipError_t alloc(int64_t count, hipStream_t stream)
-    {
-        s = stream;
-        return hipMallocAsync((void **)&p, (size_t)std::max<int64_t>(count, 1) * sizeof(T), stream);
-    }
-    T *release()
-    {
-        T *q = p;
-        p = nullptr;
-        return q;
-    }
-};
-
-struct Status {
-    int code = FMM_OK;
-    std::string msg;
-    bool check(hipError_t e, const char *what)
-    {
-        if (e == hipSuccess) return true;
-        if (code == FMM_OK) {
-            code = e == hipErrorOutOfMemory ? FMM_ENOMEM : FMM_EDEVICE;
-            msg = std::string(what) + ": " + hipGetErrorString(e);
-        }
-        return false;
-    }
-};
-
-// Exclusive scan of n uint32 (in place allowed); *total_host receives the sum if non-null.
-bool scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_host, hipStream_t s, Status &st)
-{
-    const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
-    Buf<uint32_t> sums, total;
-    if (!st.check(sums.alloc(nb, s), "scan workspace") || !st.check(total.alloc(1, s), "scan workspace")) return false;
-    scan_tile_sums<<<(unsigned)nb, 256, 0, s>>>(in, n, sums.p);
-    scan_sums<<<1, 256, 0, s>>>(sums.p, nb, total.p);
-    scan_tiles<<<(unsigned)nb, 256, 0, s>>>(in, out, n, sums.p);
-    if (!st.check(hipGetLastError(), "scan launch")) return false;
-    if (total_host) {
-        if (!st.check(hipMemcpyAsync(total_host, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "scan total") ||
-            !st.check(hipStreamSynchronize(s), "scan total"))
-            return false;
-    }
-    return true;
-}
-
-// Sort (keys, vals) in place by the low `bits` bits of the keys (stable).
-bool radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t s, Status &st)
-{
-    if (n <= 1 || bits <= 0) return true;
-    const int nb = (int)((n + kRsTile - 1) / kRsTile);
-    Buf<uint64_t> k2;
-    Buf<uint32_t> v2, counts;
-    if (!st.check(k2.alloc(n, s), "sort workspace") || !st.check(v2.alloc(n, s), "sort workspace") ||
-        !st.check(counts.alloc((int64_t)256 * nb, s), "sort workspace"))
-        return false;
-    uint64_t *ka = keys, *kb = k2.p;
-    uint32_t *va = vals, *vb = v2.p;
-    for (int shift = 0; shift < bits; shift += 8) {
-        rs_hist<<<nb, 256, 0, s>>>(ka, n, shift, counts.p, nb);
-        if (!scan_exclusive(counts.p, counts.p, (int64_t)256 * nb, nullptr, s, st)) return false;
-        rs_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, n, shift, counts.p, nb);
-        if (!st.check(hipGetLastError(), "sort launch")) return false;
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    if (ka != keys) {
-        if (!st.check(hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s), "sort copy") ||
-            !st.check(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "sort copy"))
-            return false;
-    }
-    return true;
 }
 
 // ---------------------------------------------------------------------------------
@@ -680,6 +595,85 @@ __global__ __launch_bounds__(256) void k_plan_fill(const int *__restrict__ ls, i
 
 }  // namespace
 
+// Exclusive scan of n uint32 (in place allowed); *total_host receives the sum if non-null.
+bool scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_host, hipStream_t s, Status &st)
+{
+    const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+    Buf<uint32_t> sums, total;
+    if (!st.check(sums.alloc(nb, s), "scan workspace") || !st.check(total.alloc(1, s), "scan workspace")) return false;
+    scan_tile_sums<<<(unsigned)nb, 256, 0, s>>>(in, n, sums.p);
+    scan_sums<<<1, 256, 0, s>>>(sums.p, nb, total.p);
+    scan_tiles<<<(unsigned)nb, 256, 0, s>>>(in, out, n, sums.p);
+    if (!st.check(hipGetLastError(), "scan launch")) return false;
+    if (total_host) {
+        if (!st.check(hipMemcpyAsync(total_host, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "scan total") ||
+            !st.check(hipStreamSynchronize(s), "scan total"))
+            return false;
+    }
+    return true;
+}
+
+// Sort (keys, vals) in place by the low `bits` bits of the keys (stable).
+bool radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t s, Status &st)
+{
+    if (n <= 1 || bits <= 0) return true;
+    const int nb = (int)((n + kRsTile - 1) / kRsTile);
+    Buf<uint64_t> k2;
+    Buf<uint32_t> v2, counts;
+    if (!st.check(k2.alloc(n, s), "sort workspace") || !st.check(v2.alloc(n, s), "sort workspace") ||
+        !st.check(counts.alloc((int64_t)256 * nb, s), "sort workspace"))
+        return false;
+    uint64_t *ka = keys, *kb = k2.p;
+    uint32_t *va = vals, *vb = v2.p;
+    for (int shift = 0; shift < bits; shift += 8) {
+        rs_hist<<<nb, 256, 0, s>>>(ka, n, shift, counts.p, nb);
+        if (!scan_exclusive(counts.p, counts.p, (int64_t)256 * nb, nullptr, s, st)) return false;
+        rs_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, n, shift, counts.p, nb);
+        if (!st.check(hipGetLastError(), "sort launch")) return false;
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        if (!st.check(hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s), "sort copy") ||
+            !st.check(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "sort copy"))
+            return false;
+    }
+    return true;
+}
+
+
+bool bounding_square(const double2 *xy, int64_t n, hipStream_t s, Status &st, double box[3], bool &nonfinite)
+{
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    Buf<double4> part;
+    Buf<int> flags;
+    std::vector<double4> h(nb);
+    int hf = 0;
+    if (!st.check(part.alloc(nb, s), "bounding square") || !st.check(flags.alloc(1, s), "bounding square") ||
+        !st.check(hipMemsetAsync(flags.p, 0, sizeof(int), s), "bounding square"))
+        return false;
+    k_minmax<<<nb, 256, 0, s>>>(xy, n, part.p, flags.p);
+    if (!st.check(hipMemcpyAsync(h.data(), part.p, nb * sizeof(double4), hipMemcpyDeviceToHost, s), "bounding square") ||
+        !st.check(hipMemcpyAsync(&hf, flags.p, sizeof(int), hipMemcpyDeviceToHost, s), "bounding square") ||
+        !st.check(hipStreamSynchronize(s), "bounding square"))
+        return false;
+    nonfinite = (hf & 2) != 0;
+    double xmin = h[0].x, xmax = h[0].y, ymin = h[0].z, ymax = h[0].w;
+    for (int b = 1; b < nb; ++b) {
+        xmin = std::min(xmin, h[b].x);
+        xmax = std::max(xmax, h[b].y);
+        ymin = std::min(ymin, h[b].z);
+        ymax = std::max(ymax, h[b].w);
+    }
+    double side = std::max(xmax - xmin, ymax - ymin);
+    if (side <= 0.0) side = 1.0;
+    box[0] = xmin;
+    box[1] = ymin;
+    box[2] = side * (1.0 + 1.0 / 1048576.0);
+    return true;
+}
+
+
 // ---------------------------------------------------------------------------------
 // Near-field plan of the mutual form (stage 9), from the device leaf offsets (both
 // builds use it).  A leaf is dense when it holds at least dense_leaf particles.  Every
@@ -789,32 +783,16 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         t->y0 = root_box[1];
         t->side = root_box[2];
     } else {
-        const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
-        Buf<double4> part;
-        std::vector<double4> h(nb);
-        int hf = 0;
-        if (!st.check(part.alloc(nb, s), "tree build")) return failed();
-        k_minmax<<<nb, 256, 0, s>>>(xy2, n, part.p, flags.p);
-        if (!st.check(hipMemcpyAsync(h.data(), part.p, nb * sizeof(double4), hipMemcpyDeviceToHost, s), "tree build") ||
-            !st.check(hipMemcpyAsync(&hf, flags.p, sizeof(int), hipMemcpyDeviceToHost, s), "tree build") ||
-            !st.check(hipStreamSynchronize(s), "tree build"))
-            return failed();
-        if (hf & 2) {
+        double box[3];
+        bool nonfinite = false;
+        if (!bounding_square(xy2, n, s, st, box, nonfinite)) return failed();
+        if (nonfinite) {
             err = "non-finite particle position";
             return FMM_EINVAL;
         }
-        double xmin = h[0].x, xmax = h[0].y, ymin = h[0].z, ymax = h[0].w;
-        for (int b = 1; b < nb; ++b) {
-            xmin = std::min(xmin, h[b].x);
-            xmax = std::max(xmax, h[b].y);
-            ymin = std::min(ymin, h[b].z);
-            ymax = std::max(ymax, h[b].w);
-        }
-        double side = std::max(xmax - xmin, ymax - ymin);
-        if (side <= 0.0) side = 1.0;
-        t->x0 = xmin;
-        t->y0 = ymin;
-        t->side = side * (1.0 + 1.0 / 1048576.0);
+        t->x0 = box[0];
+        t->y0 = box[1];
+        t->side = box[2];
     }
     const double w = t->side / (double)nside;
     // Stage 2: keys, then the stable sort by (leaf, sub-leaf key), ties by user index.

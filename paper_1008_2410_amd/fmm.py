@@ -188,9 +188,11 @@ class Tree:
 class ATree:
     """Adaptive quadtree over n particles for uneven distributions (include/fmm2d_adaptive.h):
     cells split while they hold more than max_leaf particles, down to max_depth, and the
-    U, V, W, X lists of the adaptive FMM, resident on the device.  Built on the host."""
+    U, V, W, X lists of the adaptive FMM, resident on the device.
+    builder: "device" (the GPU build) or "host" (the reference build; same tree)."""
 
-    def __init__(self, xy: torch.Tensor, max_leaf: int, max_depth: int, root_box=None, stream=None):
+    def __init__(self, xy: torch.Tensor, max_leaf: int, max_depth: int, root_box=None, stream=None,
+                 builder: str = "device"):
         if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must be an (n, 2) tensor")
         self.device = xy.device
@@ -199,9 +201,12 @@ class ATree:
         self.max_leaf, self.max_depth = int(max_leaf), int(max_depth)
         handle = ctypes.c_void_p()
         rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        if builder not in ("device", "host"):
+            raise ValueError("builder must be 'device' or 'host'")
+        name = "fmm_atree_build" if builder == "device" else "fmm_atree_build_host"
         with torch.cuda.device(self.device):
-            L.check(L.load().fmm_atree_build(_ptr(xy), self.n, self.max_leaf, self.max_depth, rb, _stream_ptr(stream),
-                                             ctypes.byref(handle)), "fmm_atree_build")
+            L.check(getattr(L.load(), name)(_ptr(xy), self.n, self.max_leaf, self.max_depth, rb, _stream_ptr(stream),
+                                            ctypes.byref(handle)), name)
         self._h = handle
 
     def close(self):

@@ -3,7 +3,9 @@ oracle O6.
 
 Structure (integers, bit-exact): the eight sizes of fmm_atree_info (cells, leaves, list
 lengths, deepest level, near-field pairs) and the leaf (level, ix, iy) of every
-particle equal the oracle's.  Values: FP64 within 1e-12 (rel-L2) of O6 and mixed within
+particle equal the oracle's.  The device build equals the host reference build: same
+sizes and leaves, and every evaluation (forward and parts, both precisions) bit for bit,
+which reads every array of the tree.  Values: FP64 within 1e-12 (rel-L2) of O6 and mixed within
 1e-5 (FP32 records relative to the leaf centre lose accuracy in wide leaves: 2.4e-6 with
 the whole set in one leaf), the near and far parts separately (the two sides use
 different operator forms: scaled tables and Horner on the GPU, unscaled powers in the
@@ -80,6 +82,41 @@ def test_velocity_matches_oracle(fmm_mod, oracle_mod, name, xy, g, smax, lmax, s
         assert np.array_equal(full, again)
 
 
+def _same_atree(td, th, g, sigma, p):
+    assert td.info() == th.info()
+    for a, b in zip(td.leaves(), th.leaves()):
+        assert np.array_equal(a, b)
+    for precision in ("fp64", "mixed"):
+        assert np.array_equal(td.velocity(g, sigma, p, precision).cpu().numpy(),
+                              th.velocity(g, sigma, p, precision).cpu().numpy()), precision
+        a = td.velocity_parts(g, sigma, p, precision)
+        b = th.velocity_parts(g, sigma, p, precision)
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b)), precision
+
+
+@pytest.mark.parametrize("name,xy,g,smax,lmax,sigma", CASES, ids=[c[0] for c in CASES])
+def test_device_build_equals_host_build(fmm_mod, name, xy, g, smax, lmax, sigma):
+    x = _t(xy)
+    td = fmm_mod.ATree(x, smax, lmax, builder="device")
+    th = fmm_mod.ATree(x, smax, lmax, builder="host")
+    _same_atree(td, th, _t(g), sigma, 12)
+
+
+def test_device_build_equals_host_build_clustered_large(fmm_mod):
+    """2^18 particles of the clustered workload (background and Gaussian clusters), leaves
+    capped at 32 and 128 down to depth 15: deep, uneven trees with many W/X entries."""
+    w = W.clustered_background(n=1 << 18)
+    x = _t(w.xy)
+    for smax in (32, 128):
+        td = fmm_mod.ATree(x, smax, 15, builder="device")
+        th = fmm_mod.ATree(x, smax, 15, builder="host")
+        info = td.info()
+        assert info["deepest"] >= 12 and info["w"] > 0
+        _same_atree(td, th, _t(w.gamma), w.sigma, 16)
+        td.close()
+        th.close()
+
+
 def test_equal_leaf_counts_match_the_uniform_tree(fmm_mod, oracle_mod):
     r = np.random.Generator(np.random.PCG64(8))
     h = 1.0 / 64
@@ -136,17 +173,19 @@ def test_linear_impulse_fp64(fmm_mod):
         assert np.all(np.abs(imp) < 1e-13 * (np.abs(g)[:, None] * np.abs(u)).sum()), (smax, lmax, imp)
 
 
-def test_errors(fmm_mod):
+@pytest.mark.parametrize("builder", ["device", "host"])
+def test_errors(fmm_mod, builder):
     from paper_1008_2410_amd import _lib
-    xy = np.array([[0.5, 0.5], [0.2, 0.3], [1.5, 0.2], [0.1, 0.1]])
+    xy = np.array([[0.5, 0.5], [0.2, 0.3], [1.5, 0.2], [0.1, 0.1], [1.2, 0.1]])
     with pytest.raises(_lib.FmmError) as e:
-        fmm_mod.ATree(_t(xy), 4, 3, (0.0, 0.0, 1.0))
+        fmm_mod.ATree(_t(xy), 4, 3, (0.0, 0.0, 1.0), builder=builder)
     assert e.value.status == _lib.FMM_ERANGE and "particle 2" in str(e.value)
     xy[1, 0] = np.nan
-    with pytest.raises(_lib.FmmError) as e:
-        fmm_mod.ATree(_t(xy), 4, 3)
-    assert e.value.status == _lib.FMM_EINVAL
-    tree = fmm_mod.ATree(_t(np.array([[0.1, 0.2], [0.3, 0.4]])), 1, 3)
+    for root in (None, (0.0, 0.0, 1.0)):
+        with pytest.raises(_lib.FmmError) as e:
+            fmm_mod.ATree(_t(xy), 4, 3, root, builder=builder)
+        assert e.value.status == _lib.FMM_EINVAL
+    tree = fmm_mod.ATree(_t(np.array([[0.1, 0.2], [0.3, 0.4]])), 1, 3, builder=builder)
     for bad in ((0.0, 8, "fp64"), (0.1, 0, "fp64"), (0.1, 33, "fp64"), (0.1, 8, 7)):
         with pytest.raises(_lib.FmmError) as e:
             tree.velocity(_t(np.ones(2)), *bad)
