@@ -84,6 +84,7 @@ def _load():
         lib.orc_atree_export.argtypes = [P] * 11
         lib.orc_atree_export.restype = None
         lib.orc_afmm.argtypes = [I64, P, P, D, P, Ci, Ci, Ci, P, P]
+        lib.orc_afmm_grad.argtypes = [I64, P, P, P, D, P, Ci, Ci, Ci, P, P, P]
         _lib = lib
     return _lib
 
@@ -331,3 +332,20 @@ def afmm_velocity(xy, gamma, sigma: float, smax: int, lmax: int, p: int, root=No
     if parts:
         return w_to_uv(wn), w_to_uv(wf)
     return w_to_uv(wn + wf)
+
+
+def afmm_grad(xy, gamma, sigma: float, smax: int, lmax: int, p: int, dl_duv, root=None):
+    """O7: gradient of a loss L(u) through the O6 velocities at the particles, as O4 + O5
+    for the uniform tree: (dL/dGamma (N,), dL/dx_eval (N, 2), dL/dx_src (N, 2)); the
+    particles moving as evaluation points and as sources (tree held fixed) have gradient
+    dL/dx_eval + dL/dx_src."""
+    xy = _f64(xy, (-1, 2))
+    gm = _f64(gamma, (-1,))
+    g = _f64(dl_duv, (-1, 2))
+    r = np.asarray(resolve_root(xy, root), dtype=np.float64)
+    dg = np.zeros(xy.shape[0])
+    dxe = np.zeros_like(xy)
+    dxs = np.zeros_like(xy)
+    _check(_load().orc_afmm_grad(xy.shape[0], _ptr(xy), _ptr(gm), _ptr(g), float(sigma), _ptr(r), int(smax),
+                                 int(lmax), int(p), _ptr(dg), _ptr(dxe), _ptr(dxs)), "orc_afmm_grad")
+    return dg, dxe, dxs

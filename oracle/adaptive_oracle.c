@@ -26,6 +26,10 @@
  * Expansions live on cells of level >= 2 (V is empty above); the far field uses the
  * singular kernel, the near field (U) the regularised one, as in O3.  With every leaf
  * on level l_max the lists are O3's and W, X are empty.
+ *
+ * O7 (orc_afmm_grad) is the adjoint of O6 in the manner of O4 and O5: circulations by the
+ * same evaluation with complex charges, positions by pair Jacobians over U and the
+ * derivatives of the far expansions (differentiated L2P and M2P).
  */
 #include <complex.h>
 #include <math.h>
@@ -39,7 +43,11 @@
 
 typedef double complex cplx;
 
+static const double TWO_PI = 6.283185307179586476925286766559;
+
 int orc_bin(int64_t n, const double *xy, int depth, const double *root, int32_t *ix, int32_t *iy);
+double orc_reg_f(double s, double sigma);
+double orc_reg_h(double x);
 
 typedef struct {
     int level, ix, iy, leaf;
@@ -418,21 +426,17 @@ void orc_atree_export(const atree *t, int64_t *cells, int64_t *leaf_of, int64_t 
  *   M2P   W_far  += sum_m a_m(D) / (z - z_D)^(m+1)                      (D in W(A))
  *   P2P   W_near += sum_{j in U(A), j != i} q_j g(|z - z_j|^2) / (z - z_j)
  * with g(s) = 1 - exp(-s / (2 sigma^2)). */
-int orc_afmm(int64_t n, const double *xy, const double *q_ri, double sigma, const double *root, int smax,
-             int lmax, int p, double *w_near, double *w_far)
+/* Multipole and local expansions of every cell of level >= 2 for charges q: the
+ * upward pass (P2M, M2M) and the downward pass (L2L, M2L over V, P2L over X) of the
+ * evaluation below.  *mp_out, *lo_out: nnodes x p, freed by the caller. */
+static int afmm_expansions(const atree *t, const double *xy, const cplx *q, int p, cplx **mp_out, cplx **lo_out)
 {
-    if (!(sigma > 0.0) || p < 1 || p > 40) return ORC_EINVAL;
-    atree *t;
-    int rc = orc_atree_build(n, xy, root, smax, lmax, &t);
-    if (rc) return rc;
-    const cplx *q = (const cplx *)q_ri;
     int64_t nn = t->nnodes;
     cplx *mp = calloc((size_t)nn * p, sizeof(cplx)), *lo = calloc((size_t)nn * p, sizeof(cplx));
     int nb = 2 * p + 1;
     double *binom = calloc((size_t)nb * nb, sizeof(double));
     if (!mp || !lo || !binom) {
         free(mp), free(lo), free(binom);
-        orc_atree_free(t);
         return ORC_ENOMEM;
     }
     for (int a = 0; a < nb; ++a) {
@@ -502,6 +506,26 @@ int orc_afmm(int64_t n, const double *xy, const double *q_ri, double sigma, cons
             }
         }
     }
+#undef BIN
+    free(binom);
+    *mp_out = mp;
+    *lo_out = lo;
+    return ORC_OK;
+}
+
+int orc_afmm(int64_t n, const double *xy, const double *q_ri, double sigma, const double *root, int smax,
+             int lmax, int p, double *w_near, double *w_far)
+{
+    if (!(sigma > 0.0) || p < 1 || p > 40) return ORC_EINVAL;
+    atree *t;
+    int rc = orc_atree_build(n, xy, root, smax, lmax, &t);
+    if (rc) return rc;
+    const cplx *q = (const cplx *)q_ri;
+    cplx *mp, *lo;
+    if ((rc = afmm_expansions(t, xy, q, p, &mp, &lo))) {
+        orc_atree_free(t);
+        return rc;
+    }
     /* evaluation at the particles */
     double k2 = 1.0 / (2.0 * sigma * sigma);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -539,10 +563,137 @@ int orc_afmm(int64_t n, const double *xy, const double *q_ri, double sigma, cons
         w_far[2 * i] = creal(wf);
         w_far[2 * i + 1] = cimag(wf);
     }
-#undef BIN
     free(mp);
     free(lo);
-    free(binom);
+    orc_atree_free(t);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* O7: the adjoint of O6                                                            */
+/* ------------------------------------------------------------------------------ */
+
+/* Far field of the expansions (lo, mp) at z in leaf A, and its derivative d/dz:
+ *   L2P   sum_l b_l (z - z_A)^l,           derivative sum_{l>=1} l b_l (z - z_A)^(l-1)
+ *   M2P   sum_m a_m / (z - z_D)^(m+1),     derivative -sum_m (m+1) a_m / (z - z_D)^(m+2)  (D in W(A)) */
+static void far_at(const atree *t, int64_t A, cplx z, const cplx *lo, const cplx *mp, int p, cplx *w, cplx *dw)
+{
+    const anode *a = &t->nodes[A];
+    cplx f = 0.0, df = 0.0;
+    if (a->level >= 2) {
+        cplx d = z - centre(t, a), pw = 1.0;
+        const cplx *B = lo + A * p;
+        for (int l = 0; l < p; ++l) {
+            f += B[l] * pw;
+            if (l + 1 < p) df += (l + 1) * B[l + 1] * pw;
+            pw *= d;
+        }
+    }
+    for (int64_t e = t->W.off[A]; e < t->W.off[A + 1]; ++e) {
+        int64_t D = t->W.idx[e];
+        cplx d = z - centre(t, &t->nodes[D]);
+        const cplx *M = mp + D * p;
+        for (int m = 0; m < p; ++m) {
+            f += M[m] / cpow(d, m + 1);
+            df -= (m + 1) * M[m] / cpow(d, m + 2);
+        }
+    }
+    *w = f;
+    *dw = df;
+}
+
+/* Real-form derivatives of one pair's velocity contribution, (u, v) = G (-dy, dx) f(s),
+ * s = dx^2 + dy^2, (dx, dy) = target - source, with respect to the target position:
+ * J = [du/dx, du/dy, dv/dx, dv/dy]; at s = 0 (a particle with itself) the smooth limit
+ * f(0) = 1/(2 sigma^2). */
+static void pair_jac(double dx, double dy, double G, double sigma, double *J)
+{
+    double kappa = 1.0 / (2.0 * sigma * sigma);
+    double s = dx * dx + dy * dy;
+    double f = (s == 0.0) ? kappa : orc_reg_f(s, sigma);
+    double fp = kappa * kappa * orc_reg_h(kappa * s);
+    J[0] = G * (-dy) * fp * 2.0 * dx;
+    J[1] = G * (-f - dy * fp * 2.0 * dy);
+    J[2] = G * (f + dx * fp * 2.0 * dx);
+    J[3] = G * dx * fp * 2.0 * dy;
+}
+
+/* Gradient of a loss L(u) through the O6 velocities at the particles, g = (dL/du_i,
+ * dL/dv_i), q_i = g_i,u + i g_i,v, c_j = -i Gamma_j / (2 pi):
+ *   dgamma  dL/dGamma_j = -Im(Phi_j) / (2 pi), Phi = the same adaptive FMM with charges
+ *           q (its operator is antisymmetric: the near kernel is odd over symmetric U
+ *           lists, M2L runs over symmetric V lists and M2P over W is the transpose of P2L
+ *           over X at equal truncation);
+ *   dx_eval the evaluation points moving, the sources fixed: J_i^T g_i with J the
+ *           Jacobian of (u, v): the pair Jacobians over U (the particle with itself
+ *           included) plus the derivative W' of the far field of the charges c;
+ *   dx_src  the sources moving, the evaluation points fixed: minus the pair Jacobians
+ *           against the particles whose U holds the source (U is symmetric), and, the far
+ *           operator being antisymmetric in both positions, -Re(c_j Phi'_j), Im(c_j Phi'_j)
+ *           with Phi' the derivative of the far field of the charges q.
+ * Each particle moving both as evaluation point and as source, with the tree held fixed,
+ * has gradient dx_eval + dx_src. */
+int orc_afmm_grad(int64_t n, const double *xy, const double *gamma, const double *g, double sigma,
+                  const double *root, int smax, int lmax, int p, double *dgamma, double *dx_eval, double *dx_src)
+{
+    if (!(sigma > 0.0) || p < 1 || p > 40) return ORC_EINVAL;
+    atree *t;
+    int rc = orc_atree_build(n, xy, root, smax, lmax, &t);
+    if (rc) return rc;
+    cplx *c = malloc(sizeof(cplx) * (n ? n : 1)), *q = malloc(sizeof(cplx) * (n ? n : 1));
+    cplx *mpc = NULL, *loc = NULL, *mpq = NULL, *loq = NULL;
+    if (!c || !q) rc = ORC_ENOMEM;
+    if (!rc) {
+        for (int64_t j = 0; j < n; ++j) {
+            c[j] = -I * gamma[j] / TWO_PI;
+            q[j] = g[2 * j] + I * g[2 * j + 1];
+        }
+        rc = afmm_expansions(t, xy, c, p, &mpc, &loc);
+    }
+    if (!rc) rc = afmm_expansions(t, xy, q, p, &mpq, &loq);
+    if (rc) {
+        free(c), free(q), free(mpc), free(loc), free(mpq), free(loq);
+        orc_atree_free(t);
+        return rc;
+    }
+    double k2 = 1.0 / (2.0 * sigma * sigma);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t A = t->leaf_of[i];
+        double x = xy[2 * i], y = xy[2 * i + 1];
+        cplx z = x + I * y, wc, dwc, phi, dphi;
+        far_at(t, A, z, loc, mpc, p, &wc, &dwc);
+        far_at(t, A, z, loq, mpq, p, &phi, &dphi);
+        cplx phin = 0.0;
+        double J[4] = {0, 0, 0, 0}, Jp[4], sx = 0.0, sy = 0.0;
+        for (int64_t e = t->U.off[A]; e < t->U.off[A + 1]; ++e) {
+            const anode *s = &t->nodes[t->U.idx[e]];
+            for (int64_t f = s->first; f < s->first + s->count; ++f) {
+                int64_t j = t->src[f];
+                double dx = x - xy[2 * j], dy = y - xy[2 * j + 1], ss = dx * dx + dy * dy;
+                if (ss > 0.0) phin += q[j] * (-expm1(-ss * k2)) / (dx + I * dy);
+                /* i as evaluation point, j as source */
+                pair_jac(dx, dy, gamma[j] / TWO_PI, sigma, Jp);
+                for (int k = 0; k < 4; ++k) J[k] += Jp[k];
+                /* i as source, j as evaluation point */
+                pair_jac(-dx, -dy, gamma[i] / TWO_PI, sigma, Jp);
+                sx -= g[2 * j] * Jp[0] + g[2 * j + 1] * Jp[2];
+                sy -= g[2 * j] * Jp[1] + g[2 * j + 1] * Jp[3];
+            }
+        }
+        /* far part of the Jacobian: W = u - iv analytic, du/dx = Re W', du/dy = -Im W',
+         * dv/dx = -Im W', dv/dy = -Re W' */
+        J[0] += creal(dwc);
+        J[1] += -cimag(dwc);
+        J[2] += -cimag(dwc);
+        J[3] += -creal(dwc);
+        dgamma[i] = -cimag(phin + phi) / TWO_PI;
+        dx_eval[2 * i] = J[0] * g[2 * i] + J[2] * g[2 * i + 1];
+        dx_eval[2 * i + 1] = J[1] * g[2 * i] + J[3] * g[2 * i + 1];
+        dx_src[2 * i] = sx - creal(c[i] * dphi);
+        dx_src[2 * i + 1] = sy + cimag(c[i] * dphi);
+    }
+    free(c), free(q), free(mpc), free(loc), free(mpq), free(loq);
     orc_atree_free(t);
     return ORC_OK;
 }

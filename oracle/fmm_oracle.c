@@ -513,6 +513,10 @@ static double reg_h(double x)
     return ((1.0 + x) * exp(-x) - 1.0) / (x * x);
 }
 
+/* The two kernel functions above, for the adaptive oracle (adaptive_oracle.c). */
+double orc_reg_f(double s, double sigma) { return reg_f(s, sigma); }
+double orc_reg_h(double x) { return reg_h(x); }
+
 /* O4 helper.  Jacobian of the O3 velocity at evaluation points z_i with respect to
  * z_i, sources held fixed, for real circulations gamma.  Per point, J = [du/dx,
  * du/dy, dv/dx, dv/dy], split into the near part (derivative of the real form of

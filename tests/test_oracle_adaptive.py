@@ -9,6 +9,14 @@
   leaf counts splits into the uniform tree, where O6 equals O3 and W, X are empty.
 * Accuracy: with sigma small enough that the far kernel is exact, O6 matches O1
   within the truncation error of p terms on clustered points with non-empty W, X.
+
+The adjoint O7 against differences of O6 itself and against independent gradients:
+* circulations: the loss sum_i g_i . u_i is linear in Gamma, so a central difference with
+  step 1 is exact to rounding;
+* positions: central differences of O6 with one particle moved (the tree unchanged),
+  where a particle with Gamma = 0 isolates the evaluation-point part, one with g = 0 the
+  source part;
+* one leaf: the O1 gradient (direct sum); equal leaf counts: O4 + O5 of the uniform tree.
 """
 import itertools
 
@@ -163,3 +171,86 @@ def test_linear_impulse(smax, lmax):
     imp = (g[:, None] * u).sum(axis=0)
     scale = (np.abs(g)[:, None] * np.abs(u)).sum()
     assert np.all(np.abs(imp) < 1e-13 * scale), (imp, scale)
+
+
+def _adjoint_case(seed):
+    xy, gamma = _clustered(seed)
+    r = np.random.Generator(np.random.PCG64(seed + 100))
+    dl = r.standard_normal((len(xy), 2))
+    return xy, gamma, dl
+
+
+@pytest.mark.parametrize("smax,lmax", [(8, 7), (30, 10)])
+def test_adjoint_circulation_exact_difference(smax, lmax):
+    xy, gamma, dl = _adjoint_case(5)
+    sigma, p = 0.002, 12
+    root = O.root_box(xy)
+    dg, _, _ = O.afmm_grad(xy, gamma, sigma, smax, lmax, p, dl, root)
+
+    def loss(gm):
+        return float(np.sum(dl * O.afmm_velocity(xy, gm, sigma, smax, lmax, p, root)))
+
+    scale = np.abs(dg).max()
+    for j in np.random.Generator(np.random.PCG64(7)).choice(len(xy), 12, replace=False):
+        e = np.zeros(len(xy))
+        e[j] = 1.0
+        fd = 0.5 * (loss(gamma + e) - loss(gamma - e))
+        assert abs(dg[j] - fd) <= 1e-11 * scale, (j, dg[j], fd)
+
+
+def test_adjoint_positions_central_differences():
+    xy, gamma, dl = _adjoint_case(6)
+    n = len(xy)
+    sigma, p, smax, lmax = 0.002, 14, 10, 8
+    zero_g = np.arange(0, n, 5)        # no source role: the evaluation part alone
+    zero_dl = np.arange(2, n, 7)       # no evaluation role: the source part alone
+    gamma = gamma.copy()
+    dl = dl.copy()
+    gamma[zero_g] = 0.0
+    dl[zero_dl] = 0.0
+    root = O.root_box(xy)
+    dg, dxe, dxs = O.afmm_grad(xy, gamma, sigma, smax, lmax, p, dl, root)
+    assert np.all(dxs[zero_g] == 0.0) and np.all(dxe[zero_dl] == 0.0)
+    # particles away from the lines of the finest grid keep their cells when moved by h
+    w = root[2] / 2 ** lmax
+    frac = np.stack([(xy[:, 0] - root[0]) / w, (xy[:, 1] - root[1]) / w], 1) % 1.0
+    inside = np.all((frac > 1e-3) & (frac < 1 - 1e-3), axis=1)
+    h = 1e-7
+
+    def loss(x):
+        return float(np.sum(dl * O.afmm_velocity(x, gamma, sigma, smax, lmax, p, root)))
+
+    picks = [k for k in list(zero_g[:6]) + list(zero_dl[:6]) + list(range(1, n, 97))[:10] if inside[k]]
+    assert len(picks) >= 15
+    got, want = [], []
+    for k in picks:
+        for d in range(2):
+            xp, xm = xy.copy(), xy.copy()
+            xp[k, d] += h
+            xm[k, d] -= h
+            got.append((loss(xp) - loss(xm)) / (2 * h))
+            want.append(dxe[k, d] + dxs[k, d])
+    assert rel_l2(np.array(got), np.array(want)) < 1e-6
+
+
+def test_adjoint_single_leaf_is_the_direct_gradient():
+    xy, gamma, dl = _adjoint_case(7)
+    dg, dxe, dxs = O.afmm_grad(xy, gamma, 0.01, len(xy), 6, 10, dl)
+    rg, rx = O.direct_grad(xy, gamma, 0.01, dl)
+    assert rel_l2(dg, rg) < 1e-13
+    assert rel_l2(dxe + dxs, rx) < 1e-13
+
+
+def test_adjoint_equal_leaf_counts_give_the_uniform_adjoint():
+    r = np.random.Generator(np.random.PCG64(8))
+    h = 1.0 / 64
+    g1 = (np.arange(64) + 0.5) * h
+    xy = np.stack(np.meshgrid(g1, g1, indexing="xy"), -1).reshape(-1, 2) + (r.random((4096, 2)) - 0.5) * 0.3 * h
+    g = r.standard_normal(4096)
+    dl = r.standard_normal((4096, 2))
+    root = (0.0, 0.0, 1.0)
+    dg, dxe, dxs = O.afmm_grad(xy, g, 0.01, 15, 4, 12, dl, root)
+    ug, uxe, uxs = O.fmm_grad_full(xy, g, 0.01, 4, 12, dl, root)
+    assert rel_l2(dg, ug) < 1e-12
+    assert rel_l2(dxe, uxe) < 1e-12
+    assert rel_l2(dxs, uxs) < 1e-12
