@@ -209,7 +209,9 @@ def adaptive_leg(torch, dev, workloads):
     every leaf wider than 8 sigma) and on a clustered workload with a uniform background
     (density range 1e5).  Per tree: build time (both trees built on the device; host clock
     around the synchronised build), the mixed evaluation's device time, near-field pairs,
-    and the error against the direct sum on sampled particles.  One JSON line of its own."""
+    and the error against the direct sum on sampled particles; for the adaptive tree also
+    the adjoint's device time (all three outputs, the source positions included).  One JSON
+    line of its own."""
     import oracle
     from paper_1008_2410_amd import fmm
     oracle.build()
@@ -246,6 +248,10 @@ def adaptive_leg(torch, dev, workloads):
             t_build = time.perf_counter() - t0
             info = tree.info()
             ms = dev_ms(lambda: tree.velocity(g, w.sigma, w.p, "mixed", out=out), 5)
+            bwd_ms = None
+            if kind == "adaptive":
+                dl = torch.ones((w.n, 2), dtype=torch.float64, device=dev)
+                bwd_ms = dev_ms(lambda: tree.velocity_backward(g, w.sigma, w.p, "mixed", dl, need_src=True), 3)
             err = rel_l2(out.cpu().numpy()[idx], ref)
             row = {"tree": kind, "build_ms": round(1e3 * t_build, 2), "ms": round(ms, 3), "rel_l2_vs_direct": float(f"{err:.3e}"),
                    "p2p_pairs": info["p2p_pairs"]}
@@ -253,7 +259,7 @@ def adaptive_leg(torch, dev, workloads):
                 row["depth"] = a
             else:
                 row.update(max_leaf=a, max_depth=b, cells=info["cells"], leaves=info["leaves"], deepest=info["deepest"],
-                           v=info["v"], w=info["w"])
+                           v=info["v"], w=info["w"], bwd_ms=round(bwd_ms, 3), bwd_fwd=round(bwd_ms / ms, 2))
             log(f"[adaptive] {w.name}: {row}")
             rows.append(row)
             tree.close()

@@ -100,6 +100,24 @@ int fmm_atree_velocity(fmm_atree *tree, const double *gamma, double sigma, int p
 int fmm_atree_velocity_parts(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
                              void *main_stream, void *side_stream, double *uv_near, double *uv_far);
 
+/* Adjoint of fmm_atree_velocity for a loss L(u): given dl_duv = dL/du (device, (n, 2)
+ * FP64, user order) returns, each optional (NULL skips it; all NULL is a no-op):
+ *   dl_dgamma  device, n:      dL/dGamma;
+ *   dl_dxeval  device, (n, 2): dL/dx with the particles moving as evaluation points only;
+ *   dl_dxsrc   device, (n, 2): dL/dx with the particles moving as sources only.
+ * A particle moving as a whole has gradient dl_dxeval + dl_dxsrc (the tree held fixed:
+ * the derivative of the discrete method away from cell boundaries).  As for the uniform
+ * tree (fmm_velocity_backward), the adaptive operator is antisymmetric (odd near kernel
+ * over symmetric U lists, M2L over symmetric V lists, M2P over W the transpose of P2L over
+ * X), so the circulation gradient is one more evaluation with the complex charges
+ * q = dL/du + i dL/dv, and the position gradients combine the near-field sums over U
+ * with the derivatives of the far fields of the charges c and q.  Arguments, precision
+ * and streams as fmm_atree_velocity; the first call on a tree also makes its adjoint
+ * work list (synchronising main_stream). */
+int fmm_atree_velocity_backward(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
+                                const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
+                                double *dl_dxeval, double *dl_dxsrc);
+
 /* Frees the tree and its device memory (after the device work using it is done);
  * NULL is ignored. */
 void fmm_atree_destroy(fmm_atree *tree);

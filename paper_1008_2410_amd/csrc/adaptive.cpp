@@ -29,6 +29,13 @@ void free_ws(AtreeWs &w)
     hipFree(w.binom);
     hipFree(w.binom16);
     hipFree(w.binom32);
+    hipFree(w.mp2);
+    hipFree(w.lo2);
+    hipFree(w.adj);
+    hipFree(w.qt);
+    hipFree(w.pa);
+    hipFree(w.pb);
+    hipFree(w.psrc);
     w = AtreeWs{};
 }
 
@@ -36,8 +43,9 @@ void free_atree(fmm_atree *t)
 {
     if (!t) return;
     AtreeDev &d = t->d;
-    // the device build's arrays come from the stream-ordered pool
-    if (t->pooled) hipDeviceSynchronize();
+    // the device build's arrays and the adjoint units come from the stream-ordered pool
+    if (t->pooled || d.bwd_units) hipDeviceSynchronize();
+    if (d.bwd_units) hipFreeAsync(d.bwd_units, nullptr);
     for (void *p : {(void *)d.perm, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
                     (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
                     (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
@@ -240,16 +248,41 @@ int ensure_ws(fmm_atree *t, int p, int precision)
     return FMM_OK;
 }
 
+// The adjoint's workspace beside the forward one (same p and precision); the
+// source-position sums only when asked for.
+int ensure_ws_backward(fmm_atree *t, bool src)
+{
+    AtreeWs &w = t->ws;
+    const size_t n = (size_t)t->n;
+    const size_t coef = (size_t)t->ncells * w.p + kCoefPad;
+    int rc = FMM_OK;
+    if (!w.mp2 && ((rc = dev_alloc(&w.mp2, coef, "adjoint multipoles")) ||
+                   (rc = dev_alloc(&w.lo2, coef, "adjoint locals")) || (rc = dev_alloc(&w.adj, n, "adjoint charges")) ||
+                   (rc = dev_alloc((char **)&w.qt, n * (w.precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
+                                   "adjoint charges")) ||
+                   (rc = dev_alloc(&w.pa, n, "adjoint near sums")) || (rc = dev_alloc(&w.pb, n, "adjoint near sums"))))
+        return rc;
+    if (src && !w.psrc && (rc = dev_alloc(&w.psrc, n, "adjoint source-position sums"))) return rc;
+    return FMM_OK;
+}
+
+int check_eval(const fmm_atree *t, const double *gamma, double sigma, int p, int precision)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!gamma) return fail(FMM_EINVAL, "gamma is NULL");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FMM_EINVAL, "sigma must be finite and > 0");
+    if (p < 1 || p > kMaxP) return fail(FMM_EINVAL, "p must be in [1, 32]");
+    if (precision != FMM_FP64 && precision != FMM_MIXED) return fail(FMM_EINVAL, "unknown precision");
+    return FMM_OK;
+}
+
 int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, void *main_stream, void *side_stream,
         double *uv, double *uv_near, double *uv_far)
 {
     clear_last_error();
-    if (!t) return fail(FMM_ESTATE, "null tree handle");
-    if (!gamma) return fail(FMM_EINVAL, "gamma is NULL");
-    if (!uv && !(uv_near && uv_far)) return fail(FMM_EINVAL, "output is NULL");
-    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FMM_EINVAL, "sigma must be finite and > 0");
-    if (p < 1 || p > kMaxP) return fail(FMM_EINVAL, "p must be in [1, 32]");
-    if (precision != FMM_FP64 && precision != FMM_MIXED) return fail(FMM_EINVAL, "unknown precision");
+    if (t && !uv && !(uv_near && uv_far)) return fail(FMM_EINVAL, "output is NULL");
+    int rc0 = check_eval(t, gamma, sigma, p, precision);
+    if (rc0) return rc0;
     Busy guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
@@ -266,6 +299,39 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     launch_atree_near(c, ms);  // P2P over U, beside the far field
     HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     launch_atree_finalize(c, uv, uv_near, uv_far, ms);  // L2P + M2P + sum
+    HIP_TRY(hipGetLastError());
+    return FMM_OK;
+}
+
+int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int precision, const double *dl_duv,
+                 void *main_stream, void *side_stream, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc)
+{
+    clear_last_error();
+    int rc = check_eval(t, gamma, sigma, p, precision);
+    if (rc) return rc;
+    if (!dl_duv) return fail(FMM_EINVAL, "dl_duv is NULL");
+    if (!dl_dgamma && !dl_dxeval && !dl_dxsrc) return FMM_OK;
+    Busy guard(t);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
+    HIP_TRY(hipSetDevice(t->device));
+    hipStream_t ms = (hipStream_t)main_stream;
+    hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    if (t->nbwd_units < 0) {
+        std::string err;
+        if ((rc = build_atree_adjoint_units(t, ms, err))) return fail(rc, err);
+    }
+    if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, dl_dxsrc != nullptr))) return rc;
+    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision)};
+    launch_atree_pack(c, gamma, ms);
+    launch_atree_pack_adjoint(c, dl_duv, ms);
+    HIP_TRY(hipEventRecord(t->ev_fork, ms));
+    HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
+    launch_atree_far(c, ss, false);  // the charges c: derivative W' at the particles
+    launch_atree_far(c, ss, true);   // the charges q: the transpose pass
+    HIP_TRY(hipEventRecord(t->ev_join, ss));
+    launch_atree_backward_near(c, dl_dxsrc != nullptr, ms);
+    HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    launch_atree_finalize_backward(c, dl_dgamma, dl_dxeval, dl_dxsrc, ms);
     HIP_TRY(hipGetLastError());
     return FMM_OK;
 }
@@ -653,6 +719,14 @@ extern "C" int fmm_atree_velocity_parts(fmm_atree *t, const double *gamma, doubl
         return fail(FMM_EINVAL, "uv_near / uv_far is NULL");
     }
     return run(t, gamma, sigma, p, precision, main_stream, side_stream, nullptr, uv_near, uv_far);
+}
+
+extern "C" int fmm_atree_velocity_backward(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
+                                           const double *dl_duv, void *main_stream, void *side_stream,
+                                           double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc)
+{
+    return run_backward(t, gamma, sigma, p, precision, dl_duv, main_stream, side_stream, dl_dgamma, dl_dxeval,
+                        dl_dxsrc);
 }
 
 extern "C" void fmm_atree_destroy(fmm_atree *t)

@@ -66,14 +66,24 @@ __device__ __forceinline__ void butterfly_step(double2 (&acc)[N], int o)
     }
 }
 
+// Charge of sorted particle j: c_j = -i Gamma_j / (2 pi), or (CPLX) the complex charge
+// q_j of the adjoint pass.
+template <bool CPLX>
+__device__ __forceinline__ double2 charge(const double *__restrict__ gamma, const double2 *__restrict__ q, int j)
+{
+    if constexpr (CPLX) return q[j];
+    else return make_double2(0.0, -gamma[j] * kInv2Pi);
+}
+
 // P2M (stage 4) at the leaves of level >= 2, one wavefront per leaf:
 //   a_m / w^m = sum_j c_j xi_j^m,  xi_j = (z_j - c)/w,
 // lanes over the leaf's particles, then a butterfly over the wavefront per coefficient.
-template <int PMAX>
+template <int PMAX, bool CPLX>
 __global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cells, const int4 *__restrict__ cell,
                                                      const int2 *__restrict__ range, const double2 *__restrict__ xy,
-                                                     const double *__restrict__ gamma, double x0, double y0,
-                                                     double side, int p, double2 *__restrict__ mp)
+                                                     const double *__restrict__ gamma, const double2 *__restrict__ q,
+                                                     double x0, double y0, double side, int p,
+                                                     double2 *__restrict__ mp)
 {
     const int lane = threadIdx.x;
     const int k = cells[blockIdx.x];
@@ -90,7 +100,7 @@ __global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cell
     for (int j = r.x + lane; j < r.x + r.y; j += 64) {
         const double2 z = xy[j];
         const double2 xi = make_double2((z.x - ctr.x) * rw, (z.y - ctr.y) * rw);
-        double2 pw = make_double2(0.0, -gamma[j] * kInv2Pi);
+        double2 pw = charge<CPLX>(gamma, q, j);
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) {
             acc[m].x += pw.x;
@@ -147,13 +157,14 @@ __global__ __launch_bounds__(256) void at_m2m_kernel(const int *__restrict__ cel
 // M2L from V, with u = 1/delta, delta = (c - c_S)/w and a~_m = u^m a_m(S),
 //   b_l = sum_S (-1)^l u^(l+1) sum_m C(l+m,m) a~_m;
 // P2L from X,  b_l += -sum_{j in A} c_j u_j^(l+1),  u_j = w/(z_j - c).
-template <int PMAX>
+template <int PMAX, bool CPLX>
 __global__ __launch_bounds__(64) void at_m2l_kernel(int first, int ncells, const int4 *__restrict__ cell,
                                                      const int *__restrict__ v_off, const int *__restrict__ v_idx,
                                                      const int *__restrict__ x_off, const int *__restrict__ x_idx,
                                                      const int2 *__restrict__ range, const double2 *__restrict__ xy,
-                                                     const double *__restrict__ gamma, double x0, double y0,
-                                                     double side, const double *__restrict__ binom, int p,
+                                                     const double *__restrict__ gamma, const double2 *__restrict__ q,
+                                                     double x0, double y0, double side,
+                                                     const double *__restrict__ binom, int p,
                                                      const double2 *__restrict__ mp, double2 *__restrict__ lo)
 {
     constexpr int NB = 2 * PMAX + 1;
@@ -202,13 +213,12 @@ __global__ __launch_bounds__(64) void at_m2l_kernel(int first, int ncells, const
             for (int j = r.x; j < r.x + r.y; ++j) {
                 const double2 z = xy[j];
                 const double2 u = cinv(make_double2((z.x - ctr.x) * rw, (z.y - ctr.y) * rw));
-                // -c_j u^(l+1) with c_j = -i Gamma_j/(2 pi):  i (Gamma_j/(2 pi)) u^(l+1)
-                const double g = gamma[j] * kInv2Pi;
-                double2 ul = u;
+                const double2 cj = charge<CPLX>(gamma, q, j);
+                double2 ul = cmul<double>(cj, u);  // c_j u^(l+1)
 #pragma unroll
                 for (int l = 0; l < PMAX; ++l) {
-                    b[l].x -= g * ul.y;
-                    b[l].y += g * ul.x;
+                    b[l].x -= ul.x;
+                    b[l].y -= ul.y;
                     ul = cmul<double>(ul, u);
                 }
             }
@@ -414,6 +424,216 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Adjoint (fmm_atree_velocity_backward).  q_i = dL/du_i + i dL/dv_i.  The adaptive
+// operator is antisymmetric (odd near kernel over symmetric U lists, M2L over symmetric V
+// lists, M2P over W the transpose of P2L over X at equal truncation), so, as for the
+// uniform tree, dL/dGamma = -Im(Phi)/(2 pi) with Phi the same evaluation with charges q,
+// the evaluation-position derivative comes from the near sums A, B and the derivative W'
+// of the far field of the charges c, and the source-position derivative from the near
+// sums with the charges q and the derivative Phi' of the far field of the charges q.
+// ---------------------------------------------------------------------------------
+
+// Adjoint charges in sorted order, FP64 and in the records' precision.
+template <typename T>
+__global__ __launch_bounds__(256) void at_pack_adjoint_kernel(int n, const int *__restrict__ perm,
+                                                               const double *__restrict__ dl_duv,
+                                                               double2 *__restrict__ adj, c2<T> *__restrict__ qt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    const double2 q = make_double2(dl_duv[2 * o], dl_duv[2 * o + 1]);
+    adj[i] = q;
+    qt[i] = mk<T>((T)q.x, (T)q.y);
+}
+
+// Adjoint near field of one unit {leaf A, first, count <= 64, log2 TP}: every source leaf
+// of U(A) in 64-particle tiles (records and adjoint charges staged in LDS), the target
+// moved into the source leaf's frame, the exponential skipped on far tiles; the sums of
+// the uniform tree's adjoint pair kernel, FP64 per source leaf.
+template <typename T, bool SRC>
+__device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c2<T> *qtile,
+                                                 const int4 *__restrict__ cell, const int2 *__restrict__ range,
+                                                 const int *__restrict__ u_off, const int *__restrict__ u_idx,
+                                                 const int *__restrict__ tile_start,
+                                                 const double4 *__restrict__ tile_box,
+                                                 const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qt,
+                                                 double x0, double y0, double side, double alpha, double cut,
+                                                 T lambda, double4 *__restrict__ out_pa, double *__restrict__ out_b,
+                                                 double4 *__restrict__ out_src)
+{
+    constexpr int NA = SRC ? 9 : 5;
+    const int lane = threadIdx.x;
+    const int logtp = u.w & 15;
+    const int tp = 1 << logtp;
+    const int t = lane & (tp - 1);
+    const int k = lane >> logtp;
+    const int i = u.y + min(t, u.z - 1);
+    const rec_t<T> ri = rec[i];
+    const int A = u.x;
+    const int4 cla = cell[A];
+    const double2 ca = cell_centre(x0, y0, side, cla);
+    const double4 tb = tile_box[tile_start[A] + ((u.y - range[A].x) >> 6)];
+    const double a2 = alpha * alpha;
+    double sum[NA] = {};
+    for (int e = u_off[A]; e < u_off[A + 1]; ++e) {
+        const int S = u_idx[e];
+        const int2 r = range[S];
+        const double2 cs = cell_centre(x0, y0, side, cell[S]);
+        const T tx = ri.x + (T)(alpha * (ca.x - cs.x));
+        const T ty = ri.y + (T)(alpha * (ca.y - cs.y));
+        T acc[NA] = {};
+        int tt = tile_start[S];
+        for (int base = r.x; base < r.x + r.y; base += 64, ++tt) {
+            const int len = min(64, r.x + r.y - base);
+            __syncthreads();
+            if (lane < len) {
+                tile[lane] = rec[base + lane];
+                qtile[lane] = qt[base + lane];
+            }
+            const double4 sb = tile_box[tt];
+            const double gx = fmax(0.0, fmax(sb.x - tb.z, tb.x - sb.z));
+            const double gy = fmax(0.0, fmax(sb.y - tb.w, tb.y - sb.w));
+            const bool far = (gx * gx + gy * gy) * a2 >= cut;
+            __syncthreads();
+            switch (logtp) {
+            case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NA; ++c) sum[c] += (double)acc[c];
+    }
+    for (int o = tp; o < 64; o <<= 1)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) sum[c] += __shfl_xor(sum[c], o);
+    if (k == 0 && t < u.z) {
+        out_pa[i] = make_double4(sum[0], sum[1], sum[2], sum[3]);
+        out_b[i] = sum[4];
+        if constexpr (SRC) out_src[i] = make_double4(sum[5], sum[6], sum[7], sum[8]);
+    }
+}
+
+template <typename T, bool SRC>
+__global__ __launch_bounds__(64) void at_backward_kernel(
+    const int4 *__restrict__ units, const int4 *__restrict__ cell, const int2 *__restrict__ range,
+    const int *__restrict__ u_off, const int *__restrict__ u_idx, const int *__restrict__ tile_start,
+    const double4 *__restrict__ tile_box, const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qt, double x0,
+    double y0, double side, double alpha, double cut, T lambda, double4 *__restrict__ out_pa,
+    double *__restrict__ out_b, double4 *__restrict__ out_src)
+{
+    __shared__ rec_t<T> tile[64];
+    __shared__ c2<T> qtile[64];
+    at_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, cell, range, u_off, u_idx, tile_start, tile_box, rec, qt,
+                             x0, y0, side, alpha, cut, lambda, out_pa, out_b, out_src);
+}
+
+// Far field of scaled expansions at z in leaf A and its derivative (FP64):
+//   L2P  (1/w) sum_l b_l xi^l,             derivative (1/w^2) sum_{l>=1} l b_l xi^(l-1);
+//   M2P  (1/w_D) sum_m a_m zeta^-(m+1),     derivative -(1/w_D^2) sum_m (m+1) a_m zeta^-(m+2),
+// over D in W(A), xi = (z - c_A)/w, zeta = (z - c_D)/w_D.  DERIV false: the value only.
+template <bool VALUE, bool DERIV>
+__device__ __forceinline__ void far_value_deriv(int A, int4 c, double2 z, const int *__restrict__ w_off,
+                                                const int *__restrict__ w_idx, const int4 *__restrict__ cell,
+                                                const double2 *__restrict__ mp, const double2 *__restrict__ lo, int p,
+                                                double x0, double y0, double side, double2 &val, double2 &der)
+{
+    val = make_double2(0.0, 0.0);
+    der = make_double2(0.0, 0.0);
+    if (c.x >= 2) {
+        const double w = ldexp(side, -c.x);
+        const double2 ctr = cell_centre(x0, y0, side, c);
+        const double2 xi = make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w);
+        const double2 *b = lo + (int64_t)A * p;
+        if (VALUE) {
+            double2 acc = b[p - 1];
+            for (int l = p - 2; l >= 0; --l) acc = cmac<double>(b[l], acc, xi);
+            val = make_double2(acc.x / w, acc.y / w);
+        }
+        if (DERIV && p >= 2) {
+            double2 acc = make_double2((p - 1) * b[p - 1].x, (p - 1) * b[p - 1].y);
+            for (int l = p - 2; l >= 1; --l) acc = cmac<double>(make_double2(l * b[l].x, l * b[l].y), acc, xi);
+            der = make_double2(acc.x / (w * w), acc.y / (w * w));
+        }
+    }
+    for (int e = w_off[A]; e < w_off[A + 1]; ++e) {
+        const int D = w_idx[e];
+        const int4 cd = cell[D];
+        const double w = ldexp(side, -cd.x);
+        const double2 ctr = cell_centre(x0, y0, side, cd);
+        const double2 inv = cinv(make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w));
+        const double2 *a = mp + (int64_t)D * p;
+        if (VALUE) {
+            double2 acc = a[p - 1];
+            for (int m = p - 2; m >= 0; --m) acc = cmac<double>(a[m], acc, inv);
+            acc = cmul<double>(acc, inv);
+            val.x += acc.x / w;
+            val.y += acc.y / w;
+        }
+        if (DERIV) {
+            double2 acc = make_double2(p * a[p - 1].x, p * a[p - 1].y);
+            for (int m = p - 2; m >= 0; --m) acc = cmac<double>(make_double2((m + 1) * a[m].x, (m + 1) * a[m].y), acc, inv);
+            acc = cmul<double>(acc, cmul<double>(inv, inv));
+            der.x -= acc.x / (w * w);
+            der.y -= acc.y / (w * w);
+        }
+    }
+}
+
+// Adjoint finalize: the near sums (record units: Phi scaled by alpha, A and B by
+// alpha^2 / (2 pi), as for the uniform tree) combined with the far parts:
+//   dL/dGamma = -Im(Phi_near + Phi_far)/(2 pi),
+//   dL/dx_eval = Re(q (A + B + W')), dL/dy_eval = -Im(q (A - B + W'))   (B imaginary),
+//   dL/dx_src = -Re(c (At + Bt)),     dL/dy_src = Im(c (At - Bt)),  At = near + Phi'.
+template <bool SRC>
+__global__ __launch_bounds__(256) void at_finalize_backward_kernel(
+    int n, const int *__restrict__ perm, const int *__restrict__ leaf_of, const int4 *__restrict__ cell,
+    const double2 *__restrict__ xy, const int *__restrict__ w_off, const int *__restrict__ w_idx,
+    const double2 *__restrict__ mp, const double2 *__restrict__ lo, const double2 *__restrict__ mp2,
+    const double2 *__restrict__ lo2, int p, double x0, double y0, double side, const double4 *__restrict__ near_pa,
+    const double *__restrict__ near_b, const double4 *__restrict__ near_src, const double2 *__restrict__ adj,
+    const double *__restrict__ gamma, double alpha, double lambda, double *__restrict__ dl_dgamma,
+    double *__restrict__ dl_dxeval, double *__restrict__ dl_dxsrc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int A = leaf_of[i];
+    const int4 c = cell[A];
+    const double2 z = xy[i];
+    double2 wv, dw, phi, dphi;
+    far_value_deriv<false, true>(A, c, z, w_off, w_idx, cell, mp, lo, p, x0, y0, side, wv, dw);
+    far_value_deriv<true, SRC>(A, c, z, w_off, w_idx, cell, mp2, lo2, p, x0, y0, side, phi, dphi);
+    const double4 a = near_pa[i];
+    const double sb = near_b[i];
+    const double ka = alpha * alpha * kInv2Pi;
+    const double Ar = ka * (-2.0 * a.w), Ai = -ka * a.z;
+    const double Bi = -ka * lambda * sb;
+    const int64_t o = perm[i];
+    if (dl_dgamma) dl_dgamma[o] = -(alpha * a.y + phi.y) * kInv2Pi;
+    if (dl_dxeval) {
+        const double2 q = adj[i];
+        const double d1r = Ar + dw.x, d1i = Ai + Bi + dw.y;
+        const double d2r = Ar + dw.x, d2i = Ai - Bi + dw.y;
+        dl_dxeval[2 * o] = q.x * d1r - q.y * d1i;
+        dl_dxeval[2 * o + 1] = -(q.x * d2i + q.y * d2r);
+    }
+    if constexpr (SRC) {
+        const double4 ns = near_src[i];
+        const double a2 = alpha * alpha;
+        const double atr = a2 * ns.x + dphi.x, ati = a2 * ns.y + dphi.y;
+        const double btr = a2 * lambda * ns.z, bti = a2 * lambda * ns.w;
+        const double G = gamma[i] * kInv2Pi;  // c = -i G: Re(c w) = G Im w, Im(c w) = -G Re w
+        dl_dxsrc[2 * o] = -G * (ati + bti);
+        dl_dxsrc[2 * o + 1] = -G * (atr - btr);
+    }
+}
+
 inline unsigned blocks(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
 
 }  // namespace
@@ -432,46 +652,56 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s)
                                                              t->ws.gamma);
 }
 
-void launch_atree_far(const AtreeCall &c, hipStream_t s)
+template <bool CPLX>
+void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int deepest = (int)t->sizes[6];
     if (deepest < 2) return;
     const int p = c.p, nb = 2 * p + 1;
+    const double2 *q = t->ws.adj;
     if (t->np2m > 0) {
         if (p <= 16)
-            at_p2m_kernel<16><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
-                                                               t->ws.gamma, t->x0, t->y0, t->side, p, t->ws.mp);
+            at_p2m_kernel<16, CPLX><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
+                                                                     t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
         else
-            at_p2m_kernel<32><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
-                                                               t->ws.gamma, t->x0, t->y0, t->side, p, t->ws.mp);
+            at_p2m_kernel<32, CPLX><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
+                                                                     t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
     }
     for (int l = deepest - 1; l >= 2; --l) {
         const int cnt = t->inner_off[l + 1] - t->inner_off[l];
         if (cnt == 0) continue;
         at_m2m_kernel<<<blocks((int64_t)cnt * p, 256), 256, 0, s>>>(t->d.inner + t->inner_off[l], cnt, t->d.child,
-                                                                    t->ws.binom, nb, p, t->ws.mp);
+                                                                    t->ws.binom, nb, p, mp);
     }
     // M2L + P2L for every cell of level >= 2 at once, then L2L level by level
     const int first = t->level_off[2], cnt = t->level_off[deepest + 1] - first;
     if (cnt > 0) {
         if (p <= 16)
-            at_m2l_kernel<16><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
-                                                             t->d.x_off, t->d.x_idx, t->d.range, t->d.xy, t->ws.gamma,
-                                                             t->x0, t->y0, t->side, t->ws.binom16, p, t->ws.mp,
-                                                             t->ws.lo);
+            at_m2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
+                                                                   t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,
+                                                                   t->ws.gamma, q, t->x0, t->y0, t->side,
+                                                                   t->ws.binom16, p, mp, lo);
         else
-            at_m2l_kernel<32><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
-                                                             t->d.x_off, t->d.x_idx, t->d.range, t->d.xy, t->ws.gamma,
-                                                             t->x0, t->y0, t->side, t->ws.binom32, p, t->ws.mp,
-                                                             t->ws.lo);
+            at_m2l_kernel<32, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
+                                                                   t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,
+                                                                   t->ws.gamma, q, t->x0, t->y0, t->side,
+                                                                   t->ws.binom32, p, mp, lo);
     }
     for (int l = 3; l <= deepest; ++l) {
         const int f = t->level_off[l], nc = t->level_off[l + 1] - f;
         if (nc == 0) continue;
         at_l2l_kernel<<<blocks((int64_t)nc * p, 256), 256, 0, s>>>(f, nc, t->d.cell, t->d.parent, t->ws.binom, nb, p,
-                                                                   t->ws.lo);
+                                                                   lo);
     }
+}
+
+void launch_atree_far(const AtreeCall &c, hipStream_t s, bool adjoint)
+{
+    if (adjoint)
+        far_chain<true>(c, c.t->ws.mp2, c.t->ws.lo2, s);
+    else
+        far_chain<false>(c, c.t->ws.mp, c.t->ws.lo, s);
 }
 
 void launch_atree_near(const AtreeCall &c, hipStream_t s)
@@ -507,6 +737,53 @@ void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, doub
         at_finalize_kernel<float><<<blocks(n, 256), 256, 0, s>>>(
             n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->ws.mp, t->ws.lo, c.p, t->x0,
             t->y0, t->side, t->ws.near, t->d.mask, (const float2 *)t->ws.slots, scale, uv, uv_near, uv_far);
+}
+
+void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, hipStream_t s)
+{
+    const fmm_atree *t = c.t;
+    const int n = (int)t->n;
+    if (c.is_double)
+        at_pack_adjoint_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, t->ws.adj,
+                                                                      (double2 *)t->ws.qt);
+    else
+        at_pack_adjoint_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, t->ws.adj,
+                                                                     (float2 *)t->ws.qt);
+}
+
+void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)
+{
+    const fmm_atree *t = c.t;
+    if (t->nbwd_units <= 0) return;
+    const double cut = c.is_double ? 39.0 : 27.0;  // as for the forward near field
+    const unsigned g = (unsigned)t->nbwd_units;
+    const AtreeDev &d = t->d;
+    const AtreeWs &w = t->ws;
+    if (c.is_double) {
+        auto k = src ? at_backward_kernel<double, true> : at_backward_kernel<double, false>;
+        k<<<g, 64, 0, s>>>(d.bwd_units, d.cell, d.range, d.u_off, d.u_idx, d.tile_start, d.tile_box,
+                           (const double4 *)w.rec, (const double2 *)w.qt, t->x0, t->y0, t->side, c.alpha, cut, 1.0,
+                           w.pa, w.pb, src ? w.psrc : nullptr);
+    } else {
+        auto k = src ? at_backward_kernel<float, true> : at_backward_kernel<float, false>;
+        k<<<g, 64, 0, s>>>(d.bwd_units, d.cell, d.range, d.u_off, d.u_idx, d.tile_start, d.tile_box,
+                           (const float4 *)w.rec, (const float2 *)w.qt, t->x0, t->y0, t->side, c.alpha, cut,
+                           0.69314718055994530942f, w.pa, w.pb, src ? w.psrc : nullptr);
+    }
+}
+
+void launch_atree_finalize_backward(const AtreeCall &c, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc,
+                                    hipStream_t s)
+{
+    const fmm_atree *t = c.t;
+    const int n = (int)t->n;
+    const double lambda = c.is_double ? 1.0 : 0.69314718055994530942;
+    const AtreeDev &d = t->d;
+    const AtreeWs &w = t->ws;
+    auto k = dl_dxsrc ? at_finalize_backward_kernel<true> : at_finalize_backward_kernel<false>;
+    k<<<blocks(n, 256), 256, 0, s>>>(n, d.perm, d.leaf_of, d.cell, d.xy, d.w_off, d.w_idx, w.mp, w.lo, w.mp2, w.lo2,
+                                     c.p, t->x0, t->y0, t->side, w.pa, w.pb, w.psrc, w.adj, w.gamma, c.alpha, lambda,
+                                     dl_dgamma, dl_dxeval, dl_dxsrc);
 }
 
 }  // namespace fmm

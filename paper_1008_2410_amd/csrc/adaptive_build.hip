@@ -562,6 +562,41 @@ __global__ __launch_bounds__(256) void ak_compact(const uint32_t *__restrict__ f
     if (k < K && flag[k]) out[pos[k]] = k;
 }
 
+// Adjoint near-field units, one per 64-particle tile of every leaf (leaf index li in
+// sorted order; tile t = leaf_tile[li] + tile within the leaf): {leaf cell, first, count,
+// log2 TP}, cost over all of U(leaf) as for the forward target-centric units.
+__global__ __launch_bounds__(256) void ak_adj_units(const int *__restrict__ leaf_start, const int *__restrict__ leaf_of,
+                                                     const int *__restrict__ leaf_tile, int NL,
+                                                     const int2 *__restrict__ range, const int *__restrict__ u_off,
+                                                     const int *__restrict__ u_idx, int4 *__restrict__ units,
+                                                     uint64_t *__restrict__ cost, uint32_t *__restrict__ order,
+                                                     unsigned long long *__restrict__ cmax)
+{
+    const int li = blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= NL) return;
+    const int k = leaf_of[leaf_start[li]];
+    const int2 r = range[k];
+    int64_t usum = 0;
+    for (int e = u_off[k]; e < u_off[k + 1]; ++e) usum += range[u_idx[e]].y;
+    uint64_t m = 0;
+    int t = leaf_tile[li];
+    for (int b = r.x; b < r.x + r.y; b += 64, ++t) {
+        const int len = min(64, r.x + r.y - b);
+        units[t] = make_int4(k, b, len, at_log2_lanes(len));
+        const uint64_t c = (uint64_t)at_unit_cost(usum, len);
+        cost[t] = c;
+        order[t] = (uint32_t)t;
+        m = m > c ? m : c;
+    }
+    atomicMax(cmax, (unsigned long long)m);
+}
+
+__global__ __launch_bounds__(256) void ak_desc_keys(uint64_t *__restrict__ key, int64_t n, uint64_t cmax)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) key[u] = cmax - key[u];
+}
+
 // The per-cell arrays while the levels are made: grown by doubling, first `used`
 // entries kept.  Released to the tree (cell, range, parent, child) or freed.
 struct CellStore {
@@ -901,6 +936,46 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
     t->mutual_items = (int64_t)hs[kStMutualItems];
     t->mutual_pairs = (int64_t)hs[kStMutualPairs];
     t->target_units = (int64_t)hs[kStUnits];
+    return FMM_OK;
+}
+
+int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err)
+{
+    Status st;
+    const int64_t nt = t->ntiles;
+    const int NL = (int)t->sizes[FMM_AT_LEAVES];
+    Buf<int4> units;
+    Buf<uint64_t> cost;
+    Buf<uint32_t> order;
+    Buf<unsigned long long> cmax;
+    int4 *out = nullptr;
+    if (!st.check(units.alloc(nt, s), "adjoint units") || !st.check(cost.alloc(nt, s), "adjoint units") ||
+        !st.check(order.alloc(nt, s), "adjoint units") || !st.check(cmax.alloc(1, s), "adjoint units") ||
+        !st.check(hipMemsetAsync(cmax.p, 0, sizeof(unsigned long long), s), "adjoint units")) {
+        err = st.msg;
+        return st.code;
+    }
+    ak_adj_units<<<grid_for(NL, 256), 256, 0, s>>>(t->d.leaf_start, t->d.leaf_of, t->d.leaf_tile, NL, t->d.range,
+                                                   t->d.u_off, t->d.u_idx, units.p, cost.p, order.p, cmax.p);
+    unsigned long long hm = 0;
+    if (!read_back(&hm, cmax.p, sizeof hm, s, st)) {
+        err = st.msg;
+        return st.code;
+    }
+    ak_desc_keys<<<grid_for(nt, 256), 256, 0, s>>>(cost.p, nt, hm);
+    if (!radix_sort(cost.p, order.p, nt, bits_for(hm), s, st) ||
+        !st.check(hipMallocAsync((void **)&out, (size_t)std::max<int64_t>(nt, 1) * sizeof(int4), s), "adjoint units")) {
+        err = st.msg;
+        return st.code;
+    }
+    ak_gather_work<<<grid_for(nt, 256), 256, 0, s>>>(units.p, order.p, nt, out);
+    if (!st.check(hipGetLastError(), "adjoint units") || !st.check(hipStreamSynchronize(s), "adjoint units")) {
+        (void)hipFreeAsync(out, s);
+        err = st.msg;
+        return st.code;
+    }
+    t->d.bwd_units = out;
+    t->nbwd_units = nt;
     return FMM_OK;
 }
 

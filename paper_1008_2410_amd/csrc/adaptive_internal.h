@@ -40,6 +40,9 @@ struct AtreeDev {
     int *leaf_tile = nullptr;      // per leaf index: first tile
     float4 *tile_box_leaf = nullptr;  // per tile: box in leaf widths about the leaf centre
     uint16_t *mask = nullptr;      // per cell: slots d written by mutual items, bit 9 target-centric part
+    // Adjoint near field: target-centric units over all of U, one per 64-particle tile
+    // {leaf cell, first, count, log2 TP}, heaviest first (made on the first adjoint call).
+    int4 *bwd_units = nullptr;
 };
 
 // Costs of near-field work (steps of the near kernel), for the heaviest-first order of
@@ -82,6 +85,12 @@ struct AtreeWs {
     void *slots = nullptr;      // mutual form: 9 x n sums (dY, dX), float2 or double2
     double2 *mp = nullptr;      // multipoles a_m / w^m, cells x p
     double2 *lo = nullptr;      // locals b_l w^(l+1), cells x p
+    // adjoint: expansions of the adjoint charges q, the charges (sorted, FP64, and in the
+    // records' precision), the near sums {Phi, A (Re, Im / -2)}, B, and the source sums
+    double2 *mp2 = nullptr, *lo2 = nullptr, *adj = nullptr;
+    void *qt = nullptr;
+    double4 *pa = nullptr, *psrc = nullptr;
+    double *pb = nullptr;
     double *binom = nullptr;    // C(a, k), a, k <= 2p, row-major (2p + 1)^2
     double *binom16 = nullptr;  // the same for a, k <= 32 (33 x 33), and for a, k <= 64 (65 x 65):
     double *binom32 = nullptr;  // the M2L kernel runs 16 or 32 terms whatever p
@@ -97,6 +106,7 @@ struct fmm_atree {
     int64_t sizes[8] = {};
     int64_t ncells = 0, ntiles = 0, nwork = 0, np2m = 0;
     int64_t mutual_items = 0, mutual_pairs = 0, target_units = 0;
+    int64_t nbwd_units = -1;  // -1 until the adjoint units are made
     int dense_leaf = 32;
     std::vector<int> level_off;   // max_depth + 2 entries
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
@@ -124,8 +134,18 @@ struct AtreeCall {
 int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
                        int64_t &bad_index);
 
+// The adjoint near-field units (d.bwd_units, nbwd_units) from the tree's arrays; either
+// build.  Synchronises s.
+int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err);
+
 void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
-void launch_atree_far(const AtreeCall &c, hipStream_t s);
+// adjoint false: the far field of the charges c (mp, lo); true: of the adjoint charges
+// q (mp2, lo2)
+void launch_atree_far(const AtreeCall &c, hipStream_t s, bool adjoint = false);
+void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, hipStream_t s);
+void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s);
+void launch_atree_finalize_backward(const AtreeCall &c, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc,
+                                    hipStream_t s);
 void launch_atree_near(const AtreeCall &c, hipStream_t s);
 void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, hipStream_t s);
 

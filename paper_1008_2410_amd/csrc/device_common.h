@@ -334,4 +334,108 @@ __device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec
                                 slot_s, slot_r);
 }
 
+// ---------------------------------------------------------------------------------
+// Adjoint near field (shared by the uniform and the adaptive tree)
+// ---------------------------------------------------------------------------------
+// e = exp(-x) and g = 1 - e in the scaled variable: FP32 base 2 (g by subtraction,
+// small x handled by the series below), FP64 base e with g from expm1.
+__device__ __forceinline__ void exp_pair(float s, float &e, float &g)
+{
+    e = __builtin_amdgcn_exp2f(-s);
+    g = 1.0f - e;
+}
+__device__ __forceinline__ void exp_pair(double s, double &e, double &g)
+{
+    g = -expm1(-s);
+    e = 1.0 - g;
+}
+// Below this natural exponent the 5-term series of g/s' and (lambda e s' - g)/s'^2 is
+// used: its truncation error x^5/720 is under the rounding unit of T there.
+template <typename T> __device__ __forceinline__ T series_cut();
+template <> __device__ __forceinline__ float series_cut<float>() { return 0.125f; }
+template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3; }
+
+// acc: Phi (2); A as its real part and its imaginary part divided by -2 (the factor is
+// applied in finalize); B; with SRC also the source-position sums with the adjoint
+// charges, At = sum q_j conj(dz')^2 (lambda e s' - g)/s'^2 (2) and Bt = sum q_j e (2).
+// conj(dz')^2 = (dx'^2 - dy'^2) - 2i dx' dy' reuses dy'^2 from s'.
+template <typename T, bool FAR, bool SRC>
+__device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda,
+                                             T (&acc)[SRC ? 9 : 5])
+{
+    T &fpr = acc[0], &fpi = acc[1], &far_r = acc[2], &far_ih = acc[3], &fb = acc[4];
+    const T ddx = tx - rj.x;
+    const T ddy = ty - rj.y;
+    const T dy2 = fma(ddy, ddy, tiny<T>());
+    const T s = fma(ddx, ddx, dy2);
+    const T r = recip(s);
+    T gr, h;
+    if (FAR) {
+        // e rounds to 0 against 1 (g = 1): g/s' = 1/s', (lambda e s' - g)/s'^2 = -1/s'^2
+        gr = r;
+        h = -r * r;
+    } else {
+        T e, g;
+        exp_pair(s, e, g);
+        gr = g * r;
+        h = (lambda * e - gr) * r;  // lambda e/s' - g/s'^2
+        // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
+        // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
+        //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
+        //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
+        // (The test is on s' against the cut divided by lambda, a loop invariant.)
+        if (s < series_cut<T>() / lambda) {
+            const T x = lambda * s;
+            gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
+            h = lambda * lambda *
+                fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
+        }
+        fb = fma(rj.z, e, fb);  // B: Gamma_j e
+        if constexpr (SRC) {
+            acc[7] = fma(qj.x, e, acc[7]);
+            acc[8] = fma(qj.y, e, acc[8]);
+        }
+    }
+    // Phi: q_j (g/s') conj(dz')
+    const T cx = gr * ddx, cy = -gr * ddy;
+    fpr = fma(qj.x, cx, fpr);
+    fpr = fma(-qj.y, cy, fpr);
+    fpi = fma(qj.x, cy, fpi);
+    fpi = fma(qj.y, cx, fpi);
+    // A: Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2
+    const T hg = h * rj.z;
+    const T zr = fma((T)-2, dy2, s);  // dx'^2 - dy'^2
+    const T zh = ddx * ddy;           // Im conj(dz')^2 / -2
+    far_r = fma(hg, zr, far_r);
+    far_ih = fma(hg, zh, far_ih);
+    if constexpr (SRC) {
+        const T wr = h * zr, wi = ((T)-2 * h) * zh;
+        acc[5] = fma(qj.x, wr, acc[5]);
+        acc[5] = fma(-qj.y, wi, acc[5]);
+        acc[6] = fma(qj.x, wi, acc[6]);
+        acc[6] = fma(qj.y, wr, acc[6]);
+    }
+}
+
+template <typename T, int K, bool FAR, bool SRC>
+__device__ __forceinline__ void p2p_bwd_tile(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
+                                             T lambda, T (&acc)[SRC ? 9 : 5])
+{
+    if (len == 64) {
+#pragma unroll 4
+        for (int it = 0; it < 64 / K; ++it)
+            p2p_bwd_pair<T, FAR, SRC>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc);
+    } else {
+        for (int j = k; j < len; j += K) p2p_bwd_pair<T, FAR, SRC>(tile[j], qtile[j], tx, ty, lambda, acc);
+    }
+}
+
+template <typename T, int K, bool SRC>
+__device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
+                                                 T lambda, T (&acc)[SRC ? 9 : 5], bool far)
+{
+    if (far) p2p_bwd_tile<T, K, true, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
+    else p2p_bwd_tile<T, K, false, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
+}
+
 }  // namespace fmm

@@ -267,6 +267,21 @@ class ATree:
                                                       _ptr(far)), "fmm_atree_velocity_parts")
         return near, far
 
+    def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
+                          need_gamma: bool = True, need_x: bool = True, need_src: bool = False):
+        """As Tree.velocity_backward, for the adaptive tree (fmm_atree_velocity_backward):
+        (dL/dGamma, dL/dx_eval) and with need_src dL/dx_src."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
+        dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if need_gamma else None
+        dx = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_x else None
+        ds = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_src else None
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_atree_velocity_backward(self.handle, _ptr(g), float(sigma), int(p),
+                                                         _precision(precision), _ptr(d), _stream_ptr(), None,
+                                                         _ptr(dg), _ptr(dx), _ptr(ds)), "fmm_atree_velocity_backward")
+        return (dg, dx, ds) if need_src else (dg, dx)
+
 
 class VelocityFn(torch.autograd.Function):
     """u = FMM velocity of the particles of `tree` with circulations gamma.

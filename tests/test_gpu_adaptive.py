@@ -5,7 +5,9 @@ Structure (integers, bit-exact): the eight sizes of fmm_atree_info (cells, leave
 lengths, deepest level, near-field pairs) and the leaf (level, ix, iy) of every
 particle equal the oracle's.  The device build equals the host reference build: same
 sizes and leaves, and every evaluation (forward and parts, both precisions) bit for bit,
-which reads every array of the tree.  Values: FP64 within 1e-12 (rel-L2) of O6 and mixed within
+which reads every array of the tree.  The adjoint (fmm_atree_velocity_backward) against
+the oracle's O7: FP64 within 1e-9 and mixed within 1e-4 (vector rel-L2), the bars of the
+uniform tree's adjoint.  Values: FP64 within 1e-12 (rel-L2) of O6 and mixed within
 1e-5 (FP32 records relative to the leaf centre lose accuracy in wide leaves: 2.4e-6 with
 the whole set in one leaf), the near and far parts separately (the two sides use
 different operator forms: scaled tables and Horner on the GPU, unscaled powers in the
@@ -115,6 +117,26 @@ def test_device_build_equals_host_build_clustered_large(fmm_mod):
         _same_atree(td, th, _t(w.gamma), w.sigma, 16)
         td.close()
         th.close()
+
+
+@pytest.mark.parametrize("name,xy,g,smax,lmax,sigma", CASES, ids=[c[0] for c in CASES])
+def test_backward_matches_oracle(fmm_mod, oracle_mod, name, xy, g, smax, lmax, sigma):
+    p = 12
+    dl = np.random.Generator(np.random.PCG64(9)).standard_normal((len(xy), 2))
+    ref = oracle_mod.afmm_grad(xy, g, sigma, smax, lmax, p, dl)
+    for builder in ("device", "host"):
+        tree = fmm_mod.ATree(_t(xy), smax, lmax, builder=builder)
+        for precision, tol in (("fp64", 1e-9), ("mixed", 1e-4)):
+            got = [a.cpu().numpy() for a in tree.velocity_backward(_t(g), sigma, p, precision, _t(dl), need_src=True)]
+            errs = [rel_l2(a, b) for a, b in zip(got, ref)]
+            print(f"[adaptive adjoint {name} {builder} {precision}] rel-L2 vs O7: dgamma {errs[0]:.2e} "
+                  f"dx_eval {errs[1]:.2e} dx_src {errs[2]:.2e}", flush=True)
+            for what, err in zip(("dgamma", "dx_eval", "dx_src"), errs):
+                assert err < tol, (builder, precision, what, err)
+            # the same call without the source output gives the same other two
+            dg, dx = tree.velocity_backward(_t(g), sigma, p, precision, _t(dl))
+            assert np.array_equal(dg.cpu().numpy(), got[0]) and np.array_equal(dx.cpu().numpy(), got[1])
+        tree.close()
 
 
 def test_equal_leaf_counts_match_the_uniform_tree(fmm_mod, oracle_mod):
