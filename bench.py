@@ -151,36 +151,43 @@ def cost_model_leg(torch, dev, workloads):
         "best": best, "points": points}), flush=True)
 
 
-def rk2_leg(torch, dev, workloads):
+def rk2_leg(torch, dev, workloads, adaptive=False):
     """Time-stepped workload: forward transport and its discrete adjoint (per-step
     checkpoints), with tree builds, velocity evaluations and adjoint calls timed
-    separately, and the peak of device memory in use (hipMemGetInfo, all allocations)."""
+    separately, and the peak of device memory in use (hipMemGetInfo, all allocations).
+    adaptive: the clustered workload (2^24 particles) with an adaptive tree (leaves of at
+    most 64 particles, depth <= 15) built for every evaluation, instead of the 2^25-particle
+    patches with the uniform depth-11 tree."""
     from paper_1008_2410_amd import fmm, rk2
     t0 = time.perf_counter()
-    w = workloads.transport_patches()
-    dt, steps = w.extra["dt"], w.extra["steps"]
+    if adaptive:
+        w = workloads.clustered_background()
+        dt, steps, atree = 1e-3, 5, (64, 15)
+    else:
+        w = workloads.transport_patches()
+        dt, steps, atree = w.extra["dt"], w.extra["steps"], None
     target = workloads.smooth_target_field(w.xy, seed=55)
-    log(f"[bench] transport workload: N={w.n} depth={w.depth} p={w.p} dt={dt} steps={steps} "
-        f"({time.perf_counter() - t0:.1f} s)")
+    log(f"[bench] transport workload {w.name}: N={w.n} depth={w.depth} adaptive={atree} p={w.p} dt={dt} "
+        f"steps={steps} ({time.perf_counter() - t0:.1f} s)")
     xy = torch.from_numpy(w.xy).to(dev)
     gamma = torch.from_numpy(w.gamma).to(dev)
     tgt = torch.from_numpy(target).to(dev)
     # warm-up: one evaluation (library load, tables, first-use allocations)
-    tree = fmm.Tree(xy, w.depth, None)
+    tree = fmm.ATree(xy, *atree) if adaptive else fmm.Tree(xy, w.depth, None)
     tree.velocity(gamma, w.sigma, w.p, "mixed")
     tree.close()
     del tree
     torch.cuda.synchronize()
     sf = rk2.RK2Stats()
     t0 = time.perf_counter()
-    xN, ck = rk2.rk2_forward(xy, gamma, w.sigma, w.depth, w.p, dt, steps, "mixed", None, sf)
+    xN, ck = rk2.rk2_forward(xy, gamma, w.sigma, w.depth, w.p, dt, steps, "mixed", None, sf, adaptive=atree)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     log(f"[bench] rk2 forward {t_fwd:.2f} s: tree builds {sf.tree_build:.2f} s, velocities {sf.velocity:.3f} s "
         f"({sf.evals} evaluations)")
     sb = rk2.RK2Stats()
     t0 = time.perf_counter()
-    dx0, dg = rk2.rk2_backward(ck, gamma, w.sigma, w.depth, w.p, dt, xN - tgt, "mixed", None, sb)
+    dx0, dg = rk2.rk2_backward(ck, gamma, w.sigma, w.depth, w.p, dt, xN - tgt, "mixed", None, sb, adaptive=atree)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     log(f"[bench] rk2 adjoint {t_bwd:.2f} s: tree builds {sb.tree_build:.2f} s, velocities {sb.velocity:.3f} s, "
@@ -188,7 +195,9 @@ def rk2_leg(torch, dev, workloads):
     peak = max(sf.peak_bytes, sb.peak_bytes)
     evals = sf.evals
     print(json.dumps({
-        "workload": "transport_patches", "n": w.n, "depth": w.depth, "p": w.p, "dt": dt, "steps": steps,
+        "workload": w.name, "n": w.n, "tree": ({"adaptive": {"max_leaf": atree[0], "max_depth": atree[1]}}
+                                              if adaptive else {"uniform_depth": w.depth}),
+        "p": w.p, "dt": dt, "steps": steps,
         "precision": "mixed", "fwd_s": round(t_fwd, 3), "bwd_s": round(t_bwd, 3),
         "fwd_tree_build_s": round(sf.tree_build, 3), "fwd_velocity_s": round(sf.velocity, 4),
         "velocity_ms_per_eval": round(sf.velocity / evals * 1e3, 3),
@@ -295,6 +304,9 @@ def main():
     ap.add_argument("--rk2", action="store_true",
                     help="only the time-stepped workload (2^25 particles, 16 patches, 5 midpoint-RK2 steps, trees "
                          "rebuilt per evaluation): forward and adjoint, one JSON line of its own")
+    ap.add_argument("--rk2-adaptive", action="store_true",
+                    help="only the time-stepped workload on the clustered distribution (2^24 particles) with an "
+                         "adaptive tree built per evaluation: forward and adjoint, one JSON line of its own")
     ap.add_argument("--adaptive", action="store_true",
                     help="only the uneven-distribution comparison (adaptive tree against uniform depths on the "
                          "patch workload and on a clustered workload): one JSON line of its own")
@@ -317,8 +329,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 10}), flush=True)
         return
-    if args.rk2:
-        rk2_leg(torch, dev, workloads)
+    if args.rk2 or args.rk2_adaptive:
+        rk2_leg(torch, dev, workloads, adaptive=args.rk2_adaptive)
         return
     if args.cost_model:
         cost_model_leg(torch, dev, workloads)

@@ -78,6 +78,17 @@ int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, co
 int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box,
                          void *stream, fmm_atree **out);
 
+/* Stages 1-3 again for particles that have moved (the time-stepped form): a new tree
+ * for xy built as fmm_atree_build with the max_leaf and max_depth of `prev`, which takes
+ * over prev's evaluation workspace (the per-particle arrays as they are, the expansion
+ * arrays grown when the new tree has more cells); prev is then destroyed.
+ *   prev   tree of the same n on the current device; destroyed on success (after a device
+ *          synchronisation), unchanged on error.
+ *   xy, n, root_box, stream, out   as fmm_atree_build; n must equal prev's (FMM_EINVAL).
+ * FMM_ESTATE for a NULL prev or one in use by another call. */
+int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
+                      fmm_atree **out);
+
 /* Host: sizes[FMM_AT_COUNT] (see the enum), root_box[3] (may be NULL). */
 int fmm_atree_info(const fmm_atree *tree, int64_t *sizes, double *root_box);
 

@@ -39,6 +39,7 @@ SIGNATURES = {
     # include/fmm2d_adaptive.h
     "fmm_atree_build": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_atree_build_host": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fmm_atree_rebuild": (_I, [_P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     "fmm_atree_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fmm_atree_info": (_I, [_P, _P, _P]),
     "fmm_atree_leaves": (_I, [_P, _P, _P, _P]),

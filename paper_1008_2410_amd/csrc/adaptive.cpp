@@ -203,23 +203,39 @@ struct Busy {
     fmm_atree *t;
     bool ok;
     explicit Busy(fmm_atree *tree) : t(tree), ok(tree->busy.exchange(1) == 0) {}
-    ~Busy()
+    ~Busy() { release(); }
+    void release()
     {
         if (ok) t->busy.store(0);
+        ok = false;
     }
 };
 
 int ensure_ws(fmm_atree *t, int p, int precision)
 {
     AtreeWs &w = t->ws;
-    if (w.rec && w.p == p && w.precision == precision) return FMM_OK;
+    const size_t n = (size_t)t->n;
+    const size_t coef = (size_t)t->ncells * p + kCoefPad;
+    int rc;
+    if (w.rec && w.p == p && w.precision == precision) {
+        if (coef <= w.coef_cap) return FMM_OK;
+        // a workspace handed over by fmm_atree_rebuild from a tree with fewer cells
+        HIP_TRY(hipDeviceSynchronize());
+        for (double2 **a : {&w.mp, &w.lo, &w.mp2, &w.lo2}) {
+            hipFree(*a);
+            *a = nullptr;
+        }
+        if ((rc = dev_alloc(&w.mp, coef, "multipoles")) || (rc = dev_alloc(&w.lo, coef, "locals"))) {
+            free_ws(w);
+            return rc;
+        }
+        w.coef_cap = coef;
+        return FMM_OK;
+    }
     if (w.rec) {
         HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the old workspace
         free_ws(w);
     }
-    const size_t n = (size_t)t->n;
-    const size_t coef = (size_t)t->ncells * p + kCoefPad;
-    int rc;
     if ((rc = dev_alloc((char **)&w.rec, n * (precision == FMM_FP64 ? sizeof(double4) : sizeof(float4)), "records")) ||
         (rc = dev_alloc(&w.gamma, n, "circulations")) || (rc = dev_alloc(&w.near, n, "near field")) ||
         (rc = dev_alloc((char **)&w.slots, 9 * n * (precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
@@ -228,6 +244,7 @@ int ensure_ws(fmm_atree *t, int p, int precision)
         free_ws(w);
         return rc;
     }
+    w.coef_cap = coef;
     auto pascal = [](int nb) {
         std::vector<double> b((size_t)nb * nb, 0.0);
         for (int a = 0; a < nb; ++a) {
@@ -254,14 +271,29 @@ int ensure_ws_backward(fmm_atree *t, bool src)
 {
     AtreeWs &w = t->ws;
     const size_t n = (size_t)t->n;
-    const size_t coef = (size_t)t->ncells * w.p + kCoefPad;
     int rc = FMM_OK;
-    if (!w.mp2 && ((rc = dev_alloc(&w.mp2, coef, "adjoint multipoles")) ||
-                   (rc = dev_alloc(&w.lo2, coef, "adjoint locals")) || (rc = dev_alloc(&w.adj, n, "adjoint charges")) ||
-                   (rc = dev_alloc((char **)&w.qt, n * (w.precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
-                                   "adjoint charges")) ||
-                   (rc = dev_alloc(&w.pa, n, "adjoint near sums")) || (rc = dev_alloc(&w.pb, n, "adjoint near sums"))))
-        return rc;
+    // each group is allocated whole or not at all (a failed call leaves none of it)
+    if (!w.mp2) {
+        if ((rc = dev_alloc(&w.mp2, w.coef_cap, "adjoint multipoles")) ||
+            (rc = dev_alloc(&w.lo2, w.coef_cap, "adjoint locals"))) {
+            hipFree(w.mp2);
+            w.mp2 = nullptr;
+            return rc;
+        }
+    }
+    if (!w.adj) {
+        if ((rc = dev_alloc(&w.adj, n, "adjoint charges")) ||
+            (rc = dev_alloc((char **)&w.qt, n * (w.precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
+                            "adjoint charges")) ||
+            (rc = dev_alloc(&w.pa, n, "adjoint near sums")) || (rc = dev_alloc(&w.pb, n, "adjoint near sums"))) {
+            for (void *q : {(void *)w.adj, w.qt, (void *)w.pa, (void *)w.pb}) hipFree(q);
+            w.adj = nullptr;
+            w.qt = nullptr;
+            w.pa = nullptr;
+            w.pb = nullptr;
+            return rc;
+        }
+    }
     if (src && !w.psrc && (rc = dev_alloc(&w.psrc, n, "adjoint source-position sums"))) return rc;
     return FMM_OK;
 }
@@ -395,6 +427,34 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         free_atree(t);
         return rc;
     }
+    *out = t;
+    return FMM_OK;
+}
+
+extern "C" int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
+                                 fmm_atree **out)
+{
+    clear_last_error();
+    if (out) *out = nullptr;
+    if (!prev) return fail(FMM_ESTATE, "null tree handle");
+    if (n != prev->n) return fail(FMM_EINVAL, "n must equal the particle count of the tree being rebuilt");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != prev->device) return fail(FMM_EINVAL, "the current device is not the tree's");
+    Busy guard(prev);
+    if (!guard.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    fmm_atree *t = nullptr;
+    int rc = fmm_atree_build(xy, n, prev->max_leaf, prev->max_depth, root_box, stream, &t);
+    if (rc) return rc;
+    t->dense_leaf = prev->dense_leaf;
+    const hipError_t e = hipDeviceSynchronize();  // work of earlier calls on prev may still use its workspace
+    if (e != hipSuccess) {
+        free_atree(t);
+        return hip_fail(e, "hipDeviceSynchronize");
+    }
+    std::swap(t->ws, prev->ws);
+    guard.release();
+    free_atree(prev);
     *out = t;
     return FMM_OK;
 }

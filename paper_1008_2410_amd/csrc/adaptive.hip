@@ -520,8 +520,9 @@ __device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c
     }
 }
 
+// FP32: 6 wavefronts per SIMD (5 with the source sums), as the uniform tree's adjoint.
 template <typename T, bool SRC>
-__global__ __launch_bounds__(64) void at_backward_kernel(
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void at_backward_kernel(
     const int4 *__restrict__ units, const int4 *__restrict__ cell, const int2 *__restrict__ range,
     const int *__restrict__ u_off, const int *__restrict__ u_idx, const int *__restrict__ tile_start,
     const double4 *__restrict__ tile_box, const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qt, double x0,

@@ -79,6 +79,7 @@ __host__ __device__ inline int64_t at_unit_cost(int64_t nsrc, int len)
 
 struct AtreeWs {
     int p = 0, precision = -1;
+    size_t coef_cap = 0;        // elements of each expansion array (mp, lo, mp2, lo2)
     void *rec = nullptr;        // float4 or double4 records {alpha (z - c_leaf), Gamma, 0}
     double *gamma = nullptr;    // circulations, sorted
     double2 *near = nullptr;    // near-field (u, v), sorted

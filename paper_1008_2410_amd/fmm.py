@@ -209,6 +209,22 @@ class ATree:
                                             ctypes.byref(handle)), name)
         self._h = handle
 
+    def rebuild(self, xy: torch.Tensor, root_box=None, stream=None) -> "ATree":
+        """Rebuild on the device for new positions of the same n particles (fmm_atree_rebuild):
+        same max_leaf and max_depth, the evaluation workspace kept.  Returns self."""
+        if not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be an (n, 2) tensor")
+        if xy.device != self.device:
+            raise ValueError("xy must be on the tree's device")
+        xy = _as_device_f64(xy, "xy", (self.n, 2), None)
+        rb = (ctypes.c_double * 3)(*[float(v) for v in root_box]) if root_box is not None else None
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.load().fmm_atree_rebuild(self.handle, _ptr(xy), self.n, rb, _stream_ptr(stream),
+                                               ctypes.byref(handle)), "fmm_atree_rebuild")
+        self._h = handle
+        return self
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             L.load().fmm_atree_destroy(self._h)

@@ -8,7 +8,9 @@ fix a time integrator; this module uses the explicit midpoint rule (RK2),
 
 with every velocity an FMM evaluation (stages 4-10) over a tree rebuilt for the
 current positions (stages 1-3), as the positions change (Tree.rebuild: the evaluation
-workspace of the tree is kept from one rebuild to the next).
+workspace of the tree is kept from one rebuild to the next).  With adaptive=(max_leaf,
+max_depth) every evaluation uses the adaptive tree (ATree, rebuilt on the device for the
+current positions the same way) instead of the uniform tree of the given depth.
 
 The gradient of a loss L(x_N) with respect to x_0 and Gamma is the discrete adjoint of
 those steps, run backwards with per-step checkpoints (only x_n is kept per step; the
@@ -32,7 +34,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from .fmm import Tree
+from .fmm import ATree, Tree
 
 
 @dataclass
@@ -53,10 +55,18 @@ def _sample_memory(device, stats: RK2Stats):
     stats.peak_bytes = max(stats.peak_bytes, total - free)
 
 
-def _velocity(tree, xy, gamma, sigma, depth, p, precision, root_box, stats: RK2Stats):
+def _tree_for(tree, xy, depth, root_box, adaptive):
+    """A tree for the positions xy: `tree` rebuilt in place (its workspace kept), or a new
+    uniform or adaptive tree when it is None."""
+    if tree is not None:
+        return tree.rebuild(xy, root_box)
+    return ATree(xy, adaptive[0], adaptive[1], root_box) if adaptive is not None else Tree(xy, depth, root_box)
+
+
+def _velocity(tree, xy, gamma, sigma, depth, p, precision, root_box, stats: RK2Stats, adaptive=None):
     """u(xy) over `tree` rebuilt for xy (a new tree when it is None); returns (tree, u)."""
     t0 = time.perf_counter()
-    tree = Tree(xy, depth, root_box) if tree is None else tree.rebuild(xy, root_box)
+    tree = _tree_for(tree, xy, depth, root_box, adaptive)
     torch.cuda.synchronize(xy.device)
     t1 = time.perf_counter()
     uv = tree.velocity(gamma, sigma, p, precision)
@@ -70,7 +80,7 @@ def _velocity(tree, xy, gamma, sigma, depth, p, precision, root_box, stats: RK2S
 
 
 def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, dt: float, steps: int,
-                precision="mixed", root_box=None, stats: RK2Stats | None = None):
+                precision="mixed", root_box=None, stats: RK2Stats | None = None, adaptive=None):
     """Advance the particles `steps` midpoint-RK2 steps.  Returns (x_N, checkpoints) with
     checkpoints[n] = x_n, n = 0..steps-1 (device tensors)."""
     stats = stats if stats is not None else RK2Stats()
@@ -81,9 +91,9 @@ def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int
     try:
         for _ in range(steps):
             checkpoints.append(x)
-            tree, u0 = _velocity(tree, x, g, sigma, depth, p, precision, root_box, stats)
+            tree, u0 = _velocity(tree, x, g, sigma, depth, p, precision, root_box, stats, adaptive)
             xm = x + (0.5 * dt) * u0
-            tree, um = _velocity(tree, xm, g, sigma, depth, p, precision, root_box, stats)
+            tree, um = _velocity(tree, xm, g, sigma, depth, p, precision, root_box, stats, adaptive)
             x = x + dt * um
     finally:
         if tree is not None:
@@ -92,7 +102,8 @@ def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int
 
 
 def rk2_backward(checkpoints, gamma: torch.Tensor, sigma: float, depth: int, p: int, dt: float,
-                 dl_dxN: torch.Tensor, precision="mixed", root_box=None, stats: RK2Stats | None = None):
+                 dl_dxN: torch.Tensor, precision="mixed", root_box=None, stats: RK2Stats | None = None,
+                 adaptive=None):
     """Discrete adjoint of rk2_forward: (dL/dx_0, dL/dGamma) from dL/dx_N."""
     stats = stats if stats is not None else RK2Stats()
     g = gamma.detach().contiguous()
@@ -102,9 +113,9 @@ def rk2_backward(checkpoints, gamma: torch.Tensor, sigma: float, depth: int, p: 
     try:
         for x in reversed(checkpoints):
             t0 = time.perf_counter()
-            tree0, u0 = _velocity(tree0, x, g, sigma, depth, p, precision, root_box, stats)
+            tree0, u0 = _velocity(tree0, x, g, sigma, depth, p, precision, root_box, stats, adaptive)
             xm = x + (0.5 * dt) * u0
-            treem, _ = _velocity(treem, xm, g, sigma, depth, p, precision, root_box, stats)
+            treem, _ = _velocity(treem, xm, g, sigma, depth, p, precision, root_box, stats, adaptive)
             t1 = time.perf_counter()
             mu = dt * lam
             dgm, dxm, dsm = treem.velocity_backward(g, sigma, p, precision, mu, need_src=True)
@@ -131,21 +142,22 @@ class RK2Transport(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, xy0, gamma, sigma: float, depth: int, p: int, dt: float, steps: int, precision="mixed",
-                root_box=None):
-        xN, checkpoints = rk2_forward(xy0, gamma, sigma, depth, p, dt, steps, precision, root_box)
+                root_box=None, adaptive=None):
+        xN, checkpoints = rk2_forward(xy0, gamma, sigma, depth, p, dt, steps, precision, root_box, adaptive=adaptive)
         ctx.save_for_backward(gamma, *checkpoints)
-        ctx.args = (sigma, depth, p, dt, precision, root_box)
+        ctx.args = (sigma, depth, p, dt, precision, root_box, adaptive)
         return xN
 
     @staticmethod
     def backward(ctx, grad_xN):
         gamma, *checkpoints = ctx.saved_tensors
-        sigma, depth, p, dt, precision, root_box = ctx.args
-        dx0, dg = rk2_backward(checkpoints, gamma, sigma, depth, p, dt, grad_xN, precision, root_box)
-        return dx0, dg, None, None, None, None, None, None, None
+        sigma, depth, p, dt, precision, root_box, adaptive = ctx.args
+        dx0, dg = rk2_backward(checkpoints, gamma, sigma, depth, p, dt, grad_xN, precision, root_box,
+                               adaptive=adaptive)
+        return dx0, dg, None, None, None, None, None, None, None, None
 
 
 def transport(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, dt: float, steps: int,
-              precision="mixed", root_box=None) -> torch.Tensor:
+              precision="mixed", root_box=None, adaptive=None) -> torch.Tensor:
     """Differentiable midpoint-RK2 transport of the particles (see the module docstring)."""
-    return RK2Transport.apply(xy0, gamma, sigma, depth, p, dt, steps, precision, root_box)
+    return RK2Transport.apply(xy0, gamma, sigma, depth, p, dt, steps, precision, root_box, adaptive)

@@ -139,6 +139,56 @@ def test_backward_matches_oracle(fmm_mod, oracle_mod, name, xy, g, smax, lmax, s
         tree.close()
 
 
+def test_rebuild_equals_fresh_tree(fmm_mod):
+    """A rebuilt tree (new positions, the old tree's workspace) gives what a tree built
+    afresh gives, bit for bit, forward and adjoint: to a uniform cloud (fewer cells), to a
+    tight cluster (more cells: the expansion arrays grow) and back."""
+    xy, g = _clustered(3)
+    n = len(xy)
+    r = np.random.Generator(np.random.PCG64(41))
+    x_uni = r.random((n, 2))
+    x_tight = 0.5 + 0.004 * r.standard_normal((n, 2))
+    dl = _t(r.standard_normal((n, 2)))
+    gt = _t(g)
+    sigma, p = 0.0005, 12
+    tree = fmm_mod.ATree(_t(xy), 8, 12)
+    for precision in ("fp64", "mixed"):  # fill the workspace, the adjoint's arrays included
+        tree.velocity(gt, sigma, p, precision)
+        tree.velocity_backward(gt, sigma, p, precision, dl, need_src=True)
+    for x in (x_uni, x_tight, xy):
+        tree.rebuild(_t(x))
+        fresh = fmm_mod.ATree(_t(x), 8, 12)
+        _same_atree(tree, fresh, gt, sigma, p)
+        for precision in ("fp64", "mixed"):
+            a = tree.velocity_backward(gt, sigma, p, precision, dl, need_src=True)
+            b = fresh.velocity_backward(gt, sigma, p, precision, dl, need_src=True)
+            assert all(np.array_equal(u.cpu().numpy(), v.cpu().numpy()) for u, v in zip(a, b)), precision
+        fresh.close()
+    tree.close()
+
+
+def test_rebuild_errors_leave_the_tree(fmm_mod):
+    import ctypes
+
+    from paper_1008_2410_amd import _lib
+    xy, g = _clustered(5)
+    n = len(xy)
+    tree = fmm_mod.ATree(_t(xy), 16, 8, (0.0, 0.0, 1.0))
+    before = tree.velocity(_t(g), 0.002, 10, "fp64").cpu().numpy()
+    out = ctypes.c_void_p()
+    other = _t(np.random.Generator(np.random.PCG64(6)).random((n + 1, 2)))
+    rc = _lib.load().fmm_atree_rebuild(tree.handle, ctypes.c_void_p(other.data_ptr()), n + 1, None, None,
+                                       ctypes.byref(out))
+    assert rc == _lib.FMM_EINVAL and not out.value
+    bad = xy.copy()
+    bad[11] = (1.5, 0.5)
+    with pytest.raises(_lib.FmmError) as e:
+        tree.rebuild(_t(bad), (0.0, 0.0, 1.0))
+    assert e.value.status == _lib.FMM_ERANGE and "particle 11" in str(e.value)
+    assert np.array_equal(tree.velocity(_t(g), 0.002, 10, "fp64").cpu().numpy(), before)
+    tree.close()
+
+
 def test_equal_leaf_counts_match_the_uniform_tree(fmm_mod, oracle_mod):
     r = np.random.Generator(np.random.PCG64(8))
     h = 1.0 / 64

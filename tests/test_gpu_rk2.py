@@ -112,3 +112,50 @@ def test_rk2_gradient_central_differences(fmm_mod, patches):
             break
     assert checked == 4
     torch.cuda.synchronize()
+
+
+def _oracle_rk2_adaptive(oracle_mod, xy, g, sigma, smax, lmax, p):
+    xs = [xy]
+    x = xy
+    for _ in range(STEPS):
+        u0 = oracle_mod.afmm_velocity(x, g, sigma, smax, lmax, p)
+        xm = x + 0.5 * DT * u0
+        um = oracle_mod.afmm_velocity(xm, g, sigma, smax, lmax, p)
+        x = x + DT * um
+        xs.append(x)
+    return xs
+
+
+def _oracle_rk2_adaptive_grad(oracle_mod, xs, g, sigma, smax, lmax, p, dl_dxN):
+    lam = dl_dxN.copy()
+    dg = np.zeros_like(g)
+    for x in reversed(xs[:-1]):
+        u0 = oracle_mod.afmm_velocity(x, g, sigma, smax, lmax, p)
+        xm = x + 0.5 * DT * u0
+        dgm, dxm, dsm = oracle_mod.afmm_grad(xm, g, sigma, smax, lmax, p, DT * lam)
+        lam_mid = dxm + dsm
+        dg0, dx0, ds0 = oracle_mod.afmm_grad(x, g, sigma, smax, lmax, p, 0.5 * DT * lam_mid)
+        lam = lam + lam_mid + dx0 + ds0
+        dg += dgm + dg0
+    return lam, dg
+
+
+@pytest.mark.parametrize("precision,tol_x,tol_g", [("fp64", 1e-12, 1e-9), ("mixed", 1e-6, 1e-4)])
+def test_rk2_adaptive_matches_oracle(fmm_mod, oracle_mod, precision, tol_x, tol_g):
+    """The transport and its adjoint with an adaptive tree (leaves of at most 20 particles,
+    depth <= 9) built for every evaluation, against the same steps over O6 and O7."""
+    from paper_1008_2410_amd import rk2
+    r = np.random.Generator(np.random.PCG64(31))
+    xy = np.concatenate([r.random((400, 2)), 0.3 + 0.02 * r.random((600, 2)),
+                         0.7 + 0.005 * r.standard_normal((300, 2))])
+    g = r.standard_normal(len(xy)) / len(xy)
+    sigma, smax, lmax, p = 0.002, 20, 9, 12
+    xs = _oracle_rk2_adaptive(oracle_mod, xy, g, sigma, smax, lmax, p)
+    target = W.smooth_target_field(xy, seed=5)
+    dl = xs[-1] - target
+    lam_ref, dg_ref = _oracle_rk2_adaptive_grad(oracle_mod, xs, g, sigma, smax, lmax, p, dl)
+    xN, ck = rk2.rk2_forward(_t(xy), _t(g), sigma, 0, p, DT, STEPS, precision, adaptive=(smax, lmax))
+    assert rel_l2(xN.cpu().numpy() - xy, xs[-1] - xy) < tol_x
+    lam, dg = rk2.rk2_backward(ck, _t(g), sigma, 0, p, DT, _t(dl), precision, adaptive=(smax, lmax))
+    assert rel_l2(lam.cpu().numpy(), lam_ref) < tol_g
+    assert rel_l2(dg.cpu().numpy(), dg_ref) < tol_g
