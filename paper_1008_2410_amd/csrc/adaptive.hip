@@ -75,20 +75,24 @@ __device__ __forceinline__ double2 charge(const double *__restrict__ gamma, cons
     else return make_double2(0.0, -gamma[j] * kInv2Pi);
 }
 
-// P2M (stage 4) at the leaves of level >= 2, one wavefront per leaf:
+// P2M (stage 4) at the leaves of level >= 2, G lanes per leaf (64/G leaves per
+// wavefront):
 //   a_m / w^m = sum_j c_j xi_j^m,  xi_j = (z_j - c)/w,
-// lanes over the leaf's particles, then a butterfly over the wavefront per coefficient.
-template <int PMAX, bool CPLX>
-__global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cells, const int4 *__restrict__ cell,
-                                                     const int2 *__restrict__ range, const double2 *__restrict__ xy,
-                                                     const double *__restrict__ gamma, const double2 *__restrict__ q,
-                                                     double x0, double y0, double side, int p,
-                                                     double2 *__restrict__ mp)
+// the G lanes over the leaf's particles, then a butterfly over the G lanes per
+// coefficient (log2 G steps of independent shuffles).
+template <int PMAX, bool CPLX, int G>
+__global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cells, int ncells,
+                                                     const int4 *__restrict__ cell, const int2 *__restrict__ range,
+                                                     const double2 *__restrict__ xy, const double *__restrict__ gamma,
+                                                     const double2 *__restrict__ q, double x0, double y0, double side,
+                                                     int p, double2 *__restrict__ mp)
 {
-    const int lane = threadIdx.x;
-    const int k = cells[blockIdx.x];
+    const int lane = threadIdx.x, g = lane % G;
+    const int idx = blockIdx.x * (64 / G) + lane / G;
+    const bool valid = idx < ncells;  // a group past the end idles (its shuffles stay inside it)
+    const int k = valid ? cells[idx] : 0;
     const int4 c = cell[k];
-    const int2 r = range[k];
+    const int2 r = valid ? range[k] : make_int2(0, 0);
     const double w = ldexp(side, -c.x);
     const double rw = 1.0 / w;
     const double2 ctr = cell_centre(x0, y0, side, c);
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cell
     double2 acc[PMAX];
 #pragma unroll
     for (int m = 0; m < PMAX; ++m) acc[m] = make_double2(0.0, 0.0);
-    for (int j = r.x + lane; j < r.x + r.y; j += 64) {
+    for (int j = r.x + g; j < r.x + r.y; j += G) {
         const double2 z = xy[j];
         const double2 xi = make_double2((z.x - ctr.x) * rw, (z.y - ctr.y) * rw);
         double2 pw = charge<CPLX>(gamma, q, j);
@@ -108,15 +112,12 @@ __global__ __launch_bounds__(64) void at_p2m_kernel(const int *__restrict__ cell
             pw = cmul<double>(pw, xi);
         }
     }
-    butterfly_step<PMAX>(acc, 32);
-    butterfly_step<PMAX>(acc, 16);
-    butterfly_step<PMAX>(acc, 8);
-    butterfly_step<PMAX>(acc, 4);
-    butterfly_step<PMAX>(acc, 2);
-    butterfly_step<PMAX>(acc, 1);
-    // every lane holds the sums; lane 0 stores them (constant indices: a lane-dependent
-    // pick would make the compiler address the array in scratch memory)
-    if (lane == 0)
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) butterfly_step<PMAX>(acc, o);
+    // every lane of the group holds the sums; its first lane stores them (constant
+    // indices: a lane-dependent pick would make the compiler address the array in
+    // scratch memory)
+    if (valid && g == 0)
 #pragma unroll
         for (int m = 0; m < PMAX; ++m)
             if (m < p) mp[(int64_t)k * p + m] = acc[m];
@@ -662,12 +663,15 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
     const int p = c.p, nb = 2 * p + 1;
     const double2 *q = t->ws.adj;
     if (t->np2m > 0) {
+        // 16 lanes per leaf, four leaves per wavefront
+        const int np = (int)t->np2m;
+        const unsigned g = (unsigned)((np + 3) / 4);
         if (p <= 16)
-            at_p2m_kernel<16, CPLX><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
-                                                                     t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
+            at_p2m_kernel<16, CPLX, 16><<<g, 64, 0, s>>>(t->d.p2m_cells, np, t->d.cell, t->d.range, t->d.xy,
+                                                         t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
         else
-            at_p2m_kernel<32, CPLX><<<(unsigned)t->np2m, 64, 0, s>>>(t->d.p2m_cells, t->d.cell, t->d.range, t->d.xy,
-                                                                     t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
+            at_p2m_kernel<32, CPLX, 16><<<g, 64, 0, s>>>(t->d.p2m_cells, np, t->d.cell, t->d.range, t->d.xy,
+                                                         t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
     }
     for (int l = deepest - 1; l >= 2; --l) {
         const int cnt = t->inner_off[l + 1] - t->inner_off[l];
