@@ -65,10 +65,18 @@ def cpu_baseline_leg(w, sample_frac_log4=1):
     oracle.fmm_velocity(xs, gs, w.sigma, w.depth - k, w.p, None)
     t_run = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return ref, t_gate, {
         "value": ns / t_run / 1e6,
         "unit": "Mparticles/s",
         "cores": threads,
+        "host_cpus": os.cpu_count(),
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"oracle FMM stages 1-10 (FP64 C, OpenMP) on the first {ns} particles of the same draw, "
                   f"depth {w.depth - k}, p={w.p} (same particles per leaf); {t_run:.2f} s",
