@@ -300,14 +300,14 @@ class ATree:
 
 
 class VelocityFn(torch.autograd.Function):
-    """u = FMM velocity of the particles of `tree` with circulations gamma.
+    """u = FMM velocity of the particles of `tree` (a Tree or an ATree) with circulations gamma.
 
     Backward returns dL/dGamma and dL/dxy, the derivative with respect to the particle
     positions, each particle moving both as evaluation point and as source
     (dL/dx_eval + dL/dx_src); the tree's cells are held fixed."""
 
     @staticmethod
-    def forward(ctx, xy, gamma, tree: Tree, sigma: float, p: int, precision="mixed"):
+    def forward(ctx, xy, gamma, tree, sigma: float, p: int, precision="mixed"):
         uv = tree.velocity(gamma, sigma, p, precision)
         ctx.save_for_backward(gamma)
         ctx.tree, ctx.sigma, ctx.p, ctx.precision = tree, sigma, p, precision
@@ -326,8 +326,9 @@ class VelocityFn(torch.autograd.Function):
 
 
 def velocity(xy: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, precision="mixed",
-             root_box=None, tree: Tree | None = None) -> torch.Tensor:
-    """Differentiable velocities of particles at xy; builds the tree unless one is given."""
+             root_box=None, tree=None) -> torch.Tensor:
+    """Differentiable velocities of particles at xy over `tree` (a Tree or an ATree built for
+    xy); builds a uniform tree of the given depth unless one is given."""
     if tree is None:
         tree = Tree(xy, depth, root_box)
     return VelocityFn.apply(xy, gamma, tree, sigma, p, precision)

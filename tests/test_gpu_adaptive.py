@@ -139,6 +139,22 @@ def test_backward_matches_oracle(fmm_mod, oracle_mod, name, xy, g, smax, lmax, s
         tree.close()
 
 
+def test_autograd_through_the_adaptive_tree(fmm_mod, oracle_mod):
+    """fmm.velocity over an ATree: torch autograd gives dL/dGamma and dL/dxy (every particle
+    moving as evaluation point and as source) equal to O7's."""
+    xy, g = _clustered(2)
+    dl = np.random.Generator(np.random.PCG64(12)).standard_normal((len(xy), 2))
+    sigma, p = 0.002, 12
+    dg_ref, dxe_ref, dxs_ref = oracle_mod.afmm_grad(xy, g, sigma, 20, 9, p, dl)
+    x = _t(xy).requires_grad_(True)
+    gg = _t(g).requires_grad_(True)
+    tree = fmm_mod.ATree(_t(xy), 20, 9)
+    uv = fmm_mod.velocity(x, gg, sigma, 0, p, "fp64", tree=tree)
+    (uv * _t(dl)).sum().backward()
+    assert rel_l2(gg.grad.cpu().numpy(), dg_ref) < 1e-9
+    assert rel_l2(x.grad.cpu().numpy(), dxe_ref + dxs_ref) < 1e-9
+
+
 def test_rebuild_equals_fresh_tree(fmm_mod):
     """A rebuilt tree (new positions, the old tree's workspace) gives what a tree built
     afresh gives, bit for bit, forward and adjoint: to a uniform cloud (fewer cells), to a
