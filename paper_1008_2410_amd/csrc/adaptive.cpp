@@ -446,7 +446,6 @@ extern "C" int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, c
     fmm_atree *t = nullptr;
     int rc = fmm_atree_build(xy, n, prev->max_leaf, prev->max_depth, root_box, stream, &t);
     if (rc) return rc;
-    t->dense_leaf = prev->dense_leaf;
     const hipError_t e = hipDeviceSynchronize();  // work of earlier calls on prev may still use its workspace
     if (e != hipSuccess) {
         free_atree(t);
