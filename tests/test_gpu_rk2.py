@@ -159,3 +159,44 @@ def test_rk2_adaptive_matches_oracle(fmm_mod, oracle_mod, precision, tol_x, tol_
     lam, dg = rk2.rk2_backward(ck, _t(g), sigma, 0, p, DT, _t(dl), precision, adaptive=(smax, lmax))
     assert rel_l2(lam.cpu().numpy(), lam_ref) < tol_g
     assert rel_l2(dg.cpu().numpy(), dg_ref) < tol_g
+
+
+def test_transport_full_size(fmm_mod, oracle_mod):
+    """The time-stepped configuration at full size (2^25 particles in 16 patches, depth 11,
+    p = 16, dt = 1e-3, 5 steps): the first velocity (mixed) within 1e-5 of O3 on a
+    4096-particle sample; the linear impulse sum_i Gamma_i x_i kept by the FP64 steps to
+    rounding (each velocity has sum_i Gamma_i u_i = 0: the operator is antisymmetric); the
+    FP64 gradient in Gamma along Gamma itself against a central difference of the FP64
+    transport."""
+    import torch
+    from paper_1008_2410_amd import rk2
+    w = W.transport_patches()
+    dt, steps = w.extra["dt"], w.extra["steps"]
+    idx = w.extra["sample"]
+    xy, g = _t(w.xy), _t(w.gamma)
+    tree = fmm_mod.Tree(xy, w.depth, None)
+    u0 = tree.velocity(g, w.sigma, w.p, "mixed").cpu().numpy()[idx]
+    tree.close()
+    ref = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, None, targets=w.xy[idx])
+    err = rel_l2(u0, ref)
+    print(f"[transport 2^25] first velocity mixed rel-L2 vs O3 on 4096: {err:.3e}", flush=True)
+    assert err < 1e-5
+    target = _t(W.smooth_target_field(w.xy, seed=55))
+
+    def run(gm):
+        xN, ck = rk2.rk2_forward(xy, gm, w.sigma, w.depth, w.p, dt, steps, "fp64")
+        return xN, ck, 0.5 * float(((xN - target) ** 2).sum())
+
+    xN, ck, _ = run(g)
+    dx = xN - xy
+    drift = float((g[:, None] * dx).sum(0).abs().max())  # change of sum_i Gamma_i x_i
+    scale = float((g.abs()[:, None] * dx.abs()).sum())
+    print(f"[transport 2^25] linear impulse drift {drift:.3e} (scale {scale:.3e})", flush=True)
+    assert drift < 1e-10 * scale
+    _, dg = rk2.rk2_backward(ck, g, w.sigma, w.depth, w.p, dt, xN - target, "fp64")
+    eps = 1e-5
+    fd = (run(g * (1 + eps))[2] - run(g * (1 - eps))[2]) / (2 * eps)
+    ad = float((dg * g).sum())
+    print(f"[transport 2^25] dL/deps along Gamma: adjoint {ad:.10e}, central difference {fd:.10e}", flush=True)
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    torch.cuda.synchronize()
