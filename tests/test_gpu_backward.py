@@ -155,3 +155,71 @@ def test_backward_deterministic(fmm_mod):
         a = _grads(fmm_mod, w, dl, precision, tree=tree)
         b = _grads(fmm_mod, w, dl, precision, tree=tree)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_uniform_target_field_central_differences_fp64(fmm_mod):
+    """The differentiation configuration at full size (2^20 uniform particles, depth 8,
+    p = 12, L = 0.5 sum |u - u*|^2): the FP64 gradient at the 64 seeded coordinates against
+    central differences of the FP64 forward, the difference of the losses summed per
+    particle, 0.5 (u+ - u-).(u+ + u- - 2 u*), so that unchanged particles add no rounding.
+    32 circulations with step 1e-6 (L is quadratic in Gamma: exact up to rounding).  32
+    positions, each particle moving as evaluation point and as source (tree rebuilt for the
+    moved particle; coordinates within 0.03 leaf widths of a leaf edge, where the method
+    is discontinuous, skipped), with steps 1e-4 and 5e-5 combined by Richardson extrapolation
+    ((4 D(h/2) - D(h))/3 cancels the h^2 term, up to 1e-5 of the derivative at 1e-4 where two
+    particles are much closer than the blob core): a moved source changes the far field of all
+    2^20 particles, and below ~1e-5 the rounding of those changes, summed over the field,
+    exceeds 1e-6 of the derivative (a step of 1e-6 gives errors up to 8e-6)."""
+    import torch
+    w = W.uniform_target_field()
+    xy, g = _t(w.xy), _t(w.gamma)
+    ustar = _t(w.extra["u_target"])
+    tree = fmm_mod.Tree(xy, w.depth, w.root_box)
+    uv = tree.velocity(g, w.sigma, w.p, "fp64")
+    dg, dx, ds = (a.cpu().numpy() for a in tree.velocity_backward(g, w.sigma, w.p, "fp64", uv - ustar,
+                                                                    need_src=True))
+    dxt = dx + ds
+
+    def central(up, um, h):
+        return float((0.5 * (up - um) * (up + um - 2 * ustar)).sum()) / (2 * h)
+
+    h = 1e-6
+    worst_g = 0.0
+    for k in w.extra["fd_gamma_idx"]:
+        gp, gm = g.clone(), g.clone()
+        gp[k] += h
+        gm[k] -= h
+        fd = central(tree.velocity(gp, w.sigma, w.p, "fp64"), tree.velocity(gm, w.sigma, w.p, "fp64"), h)
+        worst_g = max(worst_g, abs(fd - dg[k]) / abs(dg[k]))
+    hx = 1e-4
+    root = w.root_box
+    lw = root[2] / 2 ** w.depth
+    fds, ads = [], []
+    moved = fmm_mod.Tree(xy, w.depth, root)
+    for k, c in zip(w.extra["fd_x_idx"], w.extra["fd_x_comp"]):
+        frac = ((w.xy[k, c] - root[c]) / lw) % 1.0
+        if frac < 0.03 or frac > 0.97:
+            continue
+        d = []
+        for step in (hx, hx / 2):
+            us = []
+            for sgn in (1, -1):
+                x2 = xy.clone()
+                x2[k, c] += sgn * step
+                us.append(moved.rebuild(x2, root).velocity(g, w.sigma, w.p, "fp64"))
+            d.append(central(us[0], us[1], step))
+        fds.append((4 * d[1] - d[0]) / 3)
+        ads.append(dxt[k, c])
+    fds, ads = np.array(fds), np.array(ads)
+    scale = np.median(np.abs(ads))
+    worst_x = np.max(np.abs(fds - ads) / (np.abs(ads) + 0.1 * scale))
+    print(f"[2^20 target field] FD vs FP64 adjoint: worst relative difference Gamma {worst_g:.2e}; positions "
+          f"rel-L2 {rel_l2(fds, ads):.2e}, worst {worst_x:.2e} against |dL/dx| + 0.1 median ({len(fds)} coordinates)",
+          flush=True)
+    assert worst_g < 1e-7
+    assert rel_l2(fds, ads) < 1e-6
+    assert worst_x < 1e-5
+    assert len(fds) >= 26
+    moved.close()
+    tree.close()
+    torch.cuda.synchronize()
