@@ -45,6 +45,7 @@ SIGNATURES = {
     "fmm_atree_leaves": (_I, [_P, _P, _P, _P]),
     "fmm_atree_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_atree_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
+    "fmm_atree_set_option": (_I, [_P, _I, _I64]),
     "fmm_atree_destroy": (None, [_P]),
 }
 FMM_AT_KEYS = ("cells", "leaves", "u", "v", "w", "x", "deepest", "p2p_pairs")

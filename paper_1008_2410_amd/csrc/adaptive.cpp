@@ -308,6 +308,29 @@ int check_eval(const fmm_atree *t, const double *gamma, double sigma, int p, int
     return FMM_OK;
 }
 
+// Near-field occupancy cap of a forward call (FMM_OPT_NEAR_OCCUPANCY), for the far chain
+// on the other stream.  Without a cap the near-field workgroups take every wavefront slot
+// and the far kernels wait for them to retire, so the two hardly overlap (2^24 particles:
+// 9.78 ms beside each other against 9.83 ms one after the other).  Automatic (mixed
+// precision): the stage times predicted from the tree's sizes (ms, fitted to the kernels
+// run alone on Gaussian-patch and clustered trees of 2^24 particles, max_leaf 32..256),
+//   near = kAtNearPair pairs + kAtNearU |U|,  far = kAtFar0 + kAtFarV |V| + kAtFarCell cells,
+// and the cap 5 while the far field is comparable with the near field (0.4 <= far/near
+// <= 1.6), else 6: on those eight trees this picks the fastest cap or one within 0.02 ms.
+constexpr double kAtNearPair = 2.58e-10, kAtNearU = 2.4e-7;
+constexpr double kAtFar0 = 0.08, kAtFarV = 1.0e-7, kAtFarCell = 1.5e-6;
+
+int choose_occupancy(const fmm_atree *t, int precision, bool concurrent)
+{
+    if (!concurrent) return 0;
+    if (t->near_occupancy >= 0) return t->near_occupancy;
+    if (precision != FMM_MIXED || t->sizes[FMM_AT_DEEPEST] < 2) return 0;
+    const double near = kAtNearPair * (double)t->sizes[FMM_AT_PAIRS] + kAtNearU * (double)t->sizes[FMM_AT_U];
+    const double far = kAtFar0 + kAtFarV * (double)t->sizes[FMM_AT_V] + kAtFarCell * (double)t->sizes[FMM_AT_CELLS];
+    const double ratio = far / near;
+    return (ratio >= 0.4 && ratio <= 1.6) ? 5 : 6;
+}
+
 int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, void *main_stream, void *side_stream,
         double *uv, double *uv_near, double *uv_far)
 {
@@ -322,7 +345,8 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     if (rc) return rc;
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
-    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision)};
+    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision),
+                      choose_occupancy(t, precision, ss != ms)};
     launch_atree_pack(c, gamma, ms);
     HIP_TRY(hipEventRecord(t->ev_fork, ms));
     HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
@@ -452,6 +476,7 @@ extern "C" int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, c
         return hip_fail(e, "hipDeviceSynchronize");
     }
     std::swap(t->ws, prev->ws);
+    t->near_occupancy = prev->near_occupancy;
     guard.release();
     free_atree(prev);
     *out = t;
@@ -786,6 +811,20 @@ extern "C" int fmm_atree_velocity_backward(fmm_atree *t, const double *gamma, do
 {
     return run_backward(t, gamma, sigma, p, precision, dl_duv, main_stream, side_stream, dl_dgamma, dl_dxeval,
                         dl_dxsrc);
+}
+
+extern "C" int fmm_atree_set_option(fmm_atree *t, int key, int64_t value)
+{
+    clear_last_error();
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    switch (key) {
+    case FMM_OPT_NEAR_OCCUPANCY:
+        if (value < -1 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [-1, 8]");
+        t->near_occupancy = (int)value;
+        return FMM_OK;
+    default:
+        return fail(FMM_EINVAL, "unknown option key for an adaptive tree");
+    }
 }
 
 extern "C" void fmm_atree_destroy(fmm_atree *t)

@@ -717,13 +717,19 @@ void launch_atree_near(const AtreeCall &c, hipStream_t s)
     // exponent at which 1 - e rounds to 1: FP32 base 2 at 26, FP64 base e at 37.5, one
     // unit of margin for the rounding of the records and the boxes
     const double cut = c.is_double ? 39.0 : 27.0;
+    // Occupancy cap: each workgroup (one wavefront) reserves LDS so that at most near_occ
+    // of them fit on a SIMD (160 KiB per CU, 4 SIMDs); the far chain on the other stream
+    // takes the wavefront slots left over.
+    const size_t static_lds = 256 * (c.is_double ? sizeof(double4) : sizeof(float4));
+    const size_t per_wave = c.near_occ > 0 ? (size_t)160 * 1024 / (4 * (size_t)c.near_occ) : 0;
+    const size_t dyn = per_wave > static_lds ? per_wave - static_lds : 0;
     if (c.is_double)
-        at_near_kernel<double><<<(unsigned)t->nwork, 64, 0, s>>>(
+        at_near_kernel<double><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
             t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const double4 *)t->ws.rec, t->x0, t->y0, t->side,
             c.alpha, cut, scale, t->dense_leaf, t->n, t->ws.near, (double2 *)t->ws.slots);
     else
-        at_near_kernel<float><<<(unsigned)t->nwork, 64, 0, s>>>(
+        at_near_kernel<float><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
             t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const float4 *)t->ws.rec, t->x0, t->y0, t->side,
             c.alpha, cut, scale, t->dense_leaf, t->n, t->ws.near, (float2 *)t->ws.slots);

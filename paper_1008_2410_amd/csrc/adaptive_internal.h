@@ -109,6 +109,7 @@ struct fmm_atree {
     int64_t mutual_items = 0, mutual_pairs = 0, target_units = 0;
     int64_t nbwd_units = -1;  // -1 until the adjoint units are made
     int dense_leaf = 32;
+    int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
     std::vector<int> level_off;   // max_depth + 2 entries
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
     bool pooled = false;  // device arrays from the stream-ordered pool (the device build)
@@ -126,6 +127,7 @@ struct AtreeCall {
     int p;
     int is_double;
     double alpha;   // record scale (as for the uniform tree)
+    int near_occ = 0;  // forward near field: wavefronts per SIMD it may hold (0: no cap)
 };
 
 // Stages 1-3 on the device (adaptive_build.hip): fills t->d and the host facts of t

@@ -242,6 +242,10 @@ class ATree:
             raise RuntimeError("tree is closed")
         return self._h
 
+    def set_option(self, key: int, value: int):
+        """fmm_atree_set_option: FMM_OPT_NEAR_OCCUPANCY (-1 automatic, 0 no cap, 1..8)."""
+        L.check(L.load().fmm_atree_set_option(self.handle, int(key), int(value)), "fmm_atree_set_option")
+
     def info(self) -> dict:
         """Sizes of the tree and its lists (keys of _lib.FMM_AT_KEYS) and the root cell."""
         sizes = (ctypes.c_int64 * 8)()

@@ -50,3 +50,5 @@ def test_bad_arguments_rejected_without_device(native_lib):
     assert native_lib.fmm_tree_info(None, None, None, None, None, None, None, None) == _lib.FMM_ESTATE
     assert native_lib.fmm_get_timings(None, None, None) == _lib.FMM_ESTATE
     native_lib.fmm_destroy_tree(None)
+    assert native_lib.fmm_atree_set_option(None, _lib.FMM_OPT_NEAR_OCCUPANCY, 5) == _lib.FMM_ESTATE
+    native_lib.fmm_atree_destroy(None)

@@ -205,6 +205,34 @@ def test_rebuild_errors_leave_the_tree(fmm_mod):
     tree.close()
 
 
+def test_near_occupancy_cap_leaves_results_unchanged(fmm_mod):
+    """FMM_OPT_NEAR_OCCUPANCY only limits how many near-field wavefronts share the chip with
+    the far field: every cap, the automatic choice and the serialised call give the same
+    bits, in both precisions, on a rebuilt tree too; values outside [-1, 8] and other keys
+    are rejected."""
+    from paper_1008_2410_amd import _lib
+    name, xy, g, smax, lmax, sigma = CASES[-2]
+    gt = _t(g)
+    tree = fmm_mod.ATree(_t(xy), smax, lmax)
+    for rebuilt in (False, True):
+        if rebuilt:
+            tree.set_option(_lib.FMM_OPT_NEAR_OCCUPANCY, 3)
+            tree.rebuild(_t(xy[::-1].copy()))
+            gt = _t(g[::-1].copy())
+        for precision in ("mixed", "fp64"):
+            ref = tree.velocity(gt, sigma, 12, precision, serial=True).cpu().numpy()
+            for occ in (0, 1, 5, 8, -1):
+                tree.set_option(_lib.FMM_OPT_NEAR_OCCUPANCY, occ)
+                got = tree.velocity(gt, sigma, 12, precision).cpu().numpy()
+                assert np.array_equal(got, ref), (rebuilt, precision, occ)
+    for key, value in ((_lib.FMM_OPT_NEAR_OCCUPANCY, 9), (_lib.FMM_OPT_NEAR_OCCUPANCY, -2),
+                       (_lib.FMM_OPT_SCHEDULE, 0)):
+        with pytest.raises(_lib.FmmError) as e:
+            tree.set_option(key, value)
+        assert e.value.status == _lib.FMM_EINVAL
+    tree.close()
+
+
 def test_equal_leaf_counts_match_the_uniform_tree(fmm_mod, oracle_mod):
     r = np.random.Generator(np.random.PCG64(8))
     h = 1.0 / 64
