@@ -366,11 +366,15 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
                                                            const uint16_t *__restrict__ mask,
                                                            const c2<TS> *__restrict__ slots, double scale,
                                                            double *__restrict__ uv, double *__restrict__ uv_near,
-                                                           double *__restrict__ uv_far)
+                                                           double *__restrict__ uv_far, double2 *__restrict__ staged)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t o = staged ? 0 : perm[i];  // issued with the first loads
     const int A = leaf_of[i];
+    // near field: the target-centric part (mask bit 9) plus the slots of the mutual
+    // items (bits d), in order d = 0..8 (first, so that its loads overlap the far part's)
+    const double2 nr = near_from_slots<TS>(i, n, mask[A], near, slots, scale);
     const int4 c = cell[A];
     const double2 z = xy[i];
     double2 W = make_double2(0.0, 0.0);
@@ -378,9 +382,7 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
         const double w = ldexp(side, -c.x);
         const double2 ctr = cell_centre(x0, y0, side, c);
         const double2 xi = make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w);
-        const double2 *b = lo + (int64_t)A * p;
-        double2 acc = b[p - 1];
-        for (int l = p - 2; l >= 0; --l) acc = cmac<double>(b[l], acc, xi);
+        const double2 acc = horner_prefetch<double>(lo + (int64_t)A * p, p, xi);
         W = make_double2(acc.x / w, acc.y / w);
     }
     for (int e = w_off[A]; e < w_off[A + 1]; ++e) {
@@ -389,28 +391,14 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
         const double w = ldexp(side, -cd.x);
         const double2 ctr = cell_centre(x0, y0, side, cd);
         const double2 inv = cinv(make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w));
-        const double2 *a = mp + (int64_t)D * p;
-        double2 acc = a[p - 1];
-        for (int m = p - 2; m >= 0; --m) acc = cmac<double>(a[m], acc, inv);
-        acc = cmul<double>(acc, inv);
+        const double2 acc = cmul<double>(horner_prefetch<double>(mp + (int64_t)D * p, p, inv), inv);
         W.x += acc.x / w;
         W.y += acc.y / w;
     }
-    // near field: the target-centric part (mask bit 9) plus the slots of the mutual
-    // items (bits d), in order d = 0..8
-    const int m = mask[A];
-    double2 nr = (m >> 9) & 1 ? near[i] : make_double2(0.0, 0.0);
-    double su = 0.0, sv = 0.0;
-#pragma unroll
-    for (int d = 0; d < 9; ++d)
-        if ((m >> d) & 1) {
-            const c2<TS> v = slots[d * (int64_t)n + i];
-            su += (double)v.x;
-            sv += (double)v.y;
-        }
-    nr.x -= scale * su;
-    nr.y += scale * sv;
-    const int64_t o = perm[i];
+    if (staged) {
+        staged[i] = make_double2(nr.x + W.x, nr.y - W.y);
+        return;
+    }
     if (uv) {
         uv[2 * o] = nr.x + W.x;
         uv[2 * o + 1] = nr.y - W.y;
@@ -740,14 +728,21 @@ void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, doub
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
     const double scale = c.alpha * kInv2Pi;
+    // uv alone: the totals go to the records (free once the near field and the far chain
+    // are done; n double2 or more) in sorted order, then to user order
+    double2 *staged = uv && !uv_near && !uv_far ? (double2 *)t->ws.rec : nullptr;
+    double *uv_direct = staged ? nullptr : uv;
     if (c.is_double)
         at_finalize_kernel<double><<<blocks(n, 256), 256, 0, s>>>(
             n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->ws.mp, t->ws.lo, c.p, t->x0,
-            t->y0, t->side, t->ws.near, t->d.mask, (const double2 *)t->ws.slots, scale, uv, uv_near, uv_far);
+            t->y0, t->side, t->ws.near, t->d.mask, (const double2 *)t->ws.slots, scale, uv_direct, uv_near, uv_far,
+            staged);
     else
         at_finalize_kernel<float><<<blocks(n, 256), 256, 0, s>>>(
             n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->ws.mp, t->ws.lo, c.p, t->x0,
-            t->y0, t->side, t->ws.near, t->d.mask, (const float2 *)t->ws.slots, scale, uv, uv_near, uv_far);
+            t->y0, t->side, t->ws.near, t->d.mask, (const float2 *)t->ws.slots, scale, uv_direct, uv_near, uv_far,
+            staged);
+    if (staged) scatter_rows_kernel<<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, staged, uv);
 }
 
 void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, hipStream_t s)

@@ -263,7 +263,8 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    launch_finalize(t, a, t->ws.near, slots, is_double, alpha, uv, uv_near, uv_far, ms);
+    // the records are free once the near field and the far chain are done: staging for uv
+    launch_finalize(t, a, t->ws.near, slots, is_double, alpha, uv, uv_near, uv_far, t->ws.rec, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);

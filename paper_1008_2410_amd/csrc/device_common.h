@@ -438,4 +438,75 @@ __device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<
     else p2p_bwd_tile<T, K, false, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
 }
 
+// ---------------------------------------------------------------------------------
+// Per-particle gathers of the finalize kernels, written so that a wavefront waits for
+// memory a few times rather than once per load.  A load guarded by a lane-dependent
+// branch is followed by a wait inside the branch, so nine guarded slot loads cost nine
+// memory round trips; a loop over coefficients with a run-time bound waits once per
+// coefficient.
+// ---------------------------------------------------------------------------------
+
+// Near-field velocity of sorted particle i of n from the mutual form: the target-centric
+// part near[i] when bit 9 of the leaf mask m is set, minus/plus scale times the slots
+// d = 0..8 whose bits are set, summed in that order.  All ten loads go out together: a
+// slot the leaf's items did not write is read at slot 0's address (always allocated) and
+// its value discarded by a select, as is near[i] without bit 9.  su and sv start at +0
+// and never become -0, so adding 0 for an unset slot gives the bits of skipping it.
+template <typename TS>
+__device__ __forceinline__ double2 near_from_slots(int64_t i, int64_t n, int m, const double2 *__restrict__ near,
+                                                   const c2<TS> *__restrict__ slots, double scale)
+{
+    c2<TS> v[9];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) v[d] = slots[((m >> d) & 1 ? (int64_t)d * n : 0) + i];
+    const double2 t = near[i];
+    double su = 0.0, sv = 0.0;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        const bool on = (m >> d) & 1;
+        su += on ? (double)v[d].x : 0.0;
+        sv += on ? (double)v[d].y : 0.0;
+    }
+    double2 r = (m >> 9) & 1 ? t : make_double2(0.0, 0.0);
+    r.x -= scale * su;
+    r.y += scale * sv;
+    return r;
+}
+
+// Horner's rule b_{p-1} x^{p-1} + ... + b_0 (p >= 1), in the order l = p-2 .. 0, with the
+// coefficients loaded eight at a time ahead of their use (an index below 0 re-reads b_0
+// and is not used).
+template <typename T>
+__device__ __forceinline__ c2<T> horner_prefetch(const c2<T> *__restrict__ b, int p, c2<T> x)
+{
+    c2<T> acc = b[p - 1];
+    for (int l0 = p - 2; l0 >= 0; l0 -= 8) {
+        c2<T> c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = b[l0 - k >= 0 ? l0 - k : 0];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (l0 - k >= 0) acc = cmac<T>(c[k], acc, x);
+    }
+    return acc;
+}
+
+// Second half of a staged finalize: (u, v) of sorted particle i, written in sorted order
+// by the finalize kernel, to row perm[i] of the user-order output.  Reading the slot sums
+// and writing rows in random order in one kernel took longer (840 us for 2^24 particles)
+// than doing each in a kernel of its own (413 + 343 us).
+namespace {
+__global__ __launch_bounds__(256) void scatter_rows_kernel(int n, const int *__restrict__ perm,
+                                                           const double2 *__restrict__ staged,
+                                                           double *__restrict__ uv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    const double2 v = staged[i];
+    uv[2 * o] = v.x;
+    uv[2 * o + 1] = v.y;
+}
+}  // namespace
+
 }  // namespace fmm

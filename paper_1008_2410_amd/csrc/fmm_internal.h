@@ -191,7 +191,7 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
                         int near_waves, hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
-                     double alpha, double *uv, double *uv_near, double *uv_far, hipStream_t s);
+                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, hipStream_t s);
 
 // Backward
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,

@@ -752,27 +752,6 @@ __global__ __launch_bounds__(1024) void coarse_valu_kernel(CoarseValuArgs a)
 // ---------------------------------------------------------------------------------
 // Near field of a particle: with the mutual form (mask != NULL), the target-centric
 // part (if mask bit 9 of its leaf) plus the slots d with mask bit d, in order d = 0..8.
-template <typename TS>
-__device__ __forceinline__ double2 near_total(int64_t i, int64_t n, uint32_t leaf, const double2 *__restrict__ near,
-                                              const uint16_t *__restrict__ mask, const c2<TS> *__restrict__ slots,
-                                              double scale)
-{
-    if (!mask) return near[i];
-    const int m = mask[leaf];
-    double2 r = (m >> 9) & 1 ? near[i] : make_double2(0.0, 0.0);
-    double su = 0.0, sv = 0.0;
-#pragma unroll
-    for (int d = 0; d < 9; ++d)
-        if ((m >> d) & 1) {
-            const c2<TS> v = slots[d * n + i];
-            su += (double)v.x;
-            sv += (double)v.y;
-        }
-    r.x -= scale * su;
-    r.y += scale * sv;
-    return r;
-}
-
 template <typename TL, typename TS>
 __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restrict__ perm,
                                                         const int *__restrict__ leaf_of,
@@ -782,28 +761,28 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
                                                         const c2<TS> *__restrict__ slots, double scale,
                                                         const c2<TL> *__restrict__ loc, int p, int has_far, double x0,
                                                         double y0, double w, double *__restrict__ uv,
-                                                        double *__restrict__ uv_near, double *__restrict__ uv_far)
+                                                        double *__restrict__ uv_near, double *__restrict__ uv_far,
+                                                        double2 *__restrict__ staged)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t o = staged ? 0 : perm[i];  // issued with the first loads
     const uint32_t leaf = (uint32_t)leaf_of[i];
-    const double2 nr = near_total<TS>(i, n, leaf, near, mask, slots, scale);
+    const double2 nr = mask ? near_from_slots<TS>(i, n, mask[leaf], near, slots, scale) : near[i];
     double fu = 0.0, fv = 0.0;
     if (has_far) {
         const double cx = x0 + (morton_x(leaf) + 0.5) * w;
         const double cy = y0 + (morton_y(leaf) + 0.5) * w;
         const double2 z = xy[i];
         const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
-        const c2<TL> *b = loc + (int64_t)leaf * p;
-        c2<TL> acc = b[p - 1];
-        for (int l = p - 2; l >= 0; --l) {
-            const c2<TL> bl = b[l];
-            acc = cmac<TL>(bl, acc, xi);
-        }
+        const c2<TL> acc = horner_prefetch<TL>(loc + (int64_t)leaf * p, p, xi);
         fu = (double)acc.x / w;
         fv = -(double)acc.y / w;
     }
-    const int64_t o = perm[i];
+    if (staged) {
+        staged[i] = make_double2(nr.x + fu, nr.y + fv);
+        return;
+    }
     if (uv) {
         uv[2 * o] = nr.x + fu;
         uv[2 * o + 1] = nr.y + fv;
@@ -1337,8 +1316,11 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
 }
 
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
-                     double alpha, double *uv, double *uv_near, double *uv_far, hipStream_t s)
+                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, hipStream_t s)
 {
+    // uv alone: the totals go to stage (n double2) in sorted order, then to user order
+    double2 *staged = uv && !uv_near && !uv_far ? (double2 *)stage : nullptr;
+    double *uv_direct = staged ? nullptr : uv;
     const int L = t->depth;
     const int n = (int)t->n;
     const double w = t->side / (double)(1 << L);
@@ -1351,24 +1333,24 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
         if (slots_double)
             finalize_kernel<double, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
                                                               (const double2 *)slots, scale, loc, a.p, has_far,
-                                                              t->x0, t->y0, w, uv, uv_near, uv_far);
+                                                              t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged);
         else
             finalize_kernel<double, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
                                                              (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
-                                                             t->y0, w, uv, uv_near, uv_far);
+                                                             t->y0, w, uv_direct, uv_near, uv_far, staged);
     } else {
         const float2 *loc = level_ptr<float>(a, L, true);
         if (slots_double)
             finalize_kernel<float, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
                                                              (const double2 *)slots, scale, loc, a.p, has_far,
-                                                             t->x0, t->y0, w, uv, uv_near, uv_far);
+                                                             t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged);
         else
             finalize_kernel<float, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
                                                             (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
-                                                            t->y0, w, uv, uv_near, uv_far);
+                                                            t->y0, w, uv_direct, uv_near, uv_far, staged);
     }
+    if (staged) scatter_rows_kernel<<<g, 256, 0, s>>>(n, t->d_perm, staged, uv);
 }
-
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double, hipStream_t s)
 {
     const int n = (int)t->n;
