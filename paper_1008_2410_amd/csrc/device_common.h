@@ -448,28 +448,34 @@ __device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<
 
 // Near-field velocity of sorted particle i of n from the mutual form: the target-centric
 // part near[i] when bit 9 of the leaf mask m is set, minus/plus scale times the slots
-// d = 0..8 whose bits are set, summed in that order.  All ten loads go out together: a
-// slot the leaf's items did not write is read at slot 0's address (always allocated) and
-// its value discarded by a select, as is near[i] without bit 9.  su and sv start at +0
-// and never become -0, so adding 0 for an unset slot gives the bits of skipping it.
+// d = 0..8 whose bits are set, summed in that order.  The slot loads go out together,
+// unguarded: a slot the leaf's items did not write is read at the address of the lowest
+// one they did (a line this particle reads anyway) and its value discarded by a select,
+// so the wavefront waits once.  (Guarding each load by its bit made the compiler wait
+// after each.)  su and sv start at +0 and never become -0, so adding +0 for an unset slot
+// gives the bits of skipping it.
 template <typename TS>
 __device__ __forceinline__ double2 near_from_slots(int64_t i, int64_t n, int m, const double2 *__restrict__ near,
                                                    const c2<TS> *__restrict__ slots, double scale)
 {
-    c2<TS> v[9];
+    double2 r = make_double2(0.0, 0.0);
+    if ((m >> 9) & 1) r = near[i];
+    const int set = m & 0x1FF;
+    if (set) {
+        const int64_t lowest = (int64_t)__builtin_ctz(set) * n + i;
+        c2<TS> v[9];
 #pragma unroll
-    for (int d = 0; d < 9; ++d) v[d] = slots[((m >> d) & 1 ? (int64_t)d * n : 0) + i];
-    const double2 t = near[i];
-    double su = 0.0, sv = 0.0;
+        for (int d = 0; d < 9; ++d) v[d] = slots[(set >> d) & 1 ? (int64_t)d * n + i : lowest];
+        double su = 0.0, sv = 0.0;
 #pragma unroll
-    for (int d = 0; d < 9; ++d) {
-        const bool on = (m >> d) & 1;
-        su += on ? (double)v[d].x : 0.0;
-        sv += on ? (double)v[d].y : 0.0;
+        for (int d = 0; d < 9; ++d) {
+            const bool on = (set >> d) & 1;
+            su += on ? (double)v[d].x : 0.0;
+            sv += on ? (double)v[d].y : 0.0;
+        }
+        r.x -= scale * su;
+        r.y += scale * sv;
     }
-    double2 r = (m >> 9) & 1 ? t : make_double2(0.0, 0.0);
-    r.x -= scale * su;
-    r.y += scale * sv;
     return r;
 }
 
