@@ -542,13 +542,11 @@ __device__ __forceinline__ void far_value_deriv(int A, int4 c, double2 z, const 
         const double2 xi = make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w);
         const double2 *b = lo + (int64_t)A * p;
         if (VALUE) {
-            double2 acc = b[p - 1];
-            for (int l = p - 2; l >= 0; --l) acc = cmac<double>(b[l], acc, xi);
+            const double2 acc = horner_prefetch<double>(b, p, xi);
             val = make_double2(acc.x / w, acc.y / w);
         }
         if (DERIV && p >= 2) {
-            double2 acc = make_double2((p - 1) * b[p - 1].x, (p - 1) * b[p - 1].y);
-            for (int l = p - 2; l >= 1; --l) acc = cmac<double>(make_double2(l * b[l].x, l * b[l].y), acc, xi);
+            const double2 acc = horner_weighted_prefetch<double>(b, p, xi, 1, 0);
             der = make_double2(acc.x / (w * w), acc.y / (w * w));
         }
     }
@@ -560,16 +558,12 @@ __device__ __forceinline__ void far_value_deriv(int A, int4 c, double2 z, const 
         const double2 inv = cinv(make_double2((z.x - ctr.x) / w, (z.y - ctr.y) / w));
         const double2 *a = mp + (int64_t)D * p;
         if (VALUE) {
-            double2 acc = a[p - 1];
-            for (int m = p - 2; m >= 0; --m) acc = cmac<double>(a[m], acc, inv);
-            acc = cmul<double>(acc, inv);
+            const double2 acc = cmul<double>(horner_prefetch<double>(a, p, inv), inv);
             val.x += acc.x / w;
             val.y += acc.y / w;
         }
         if (DERIV) {
-            double2 acc = make_double2(p * a[p - 1].x, p * a[p - 1].y);
-            for (int m = p - 2; m >= 0; --m) acc = cmac<double>(make_double2((m + 1) * a[m].x, (m + 1) * a[m].y), acc, inv);
-            acc = cmul<double>(acc, cmul<double>(inv, inv));
+            const double2 acc = cmul<double>(horner_weighted_prefetch<double>(a, p, inv, 0, 1), cmul<double>(inv, inv));
             der.x -= acc.x / (w * w);
             der.y -= acc.y / (w * w);
         }
@@ -593,18 +587,19 @@ __global__ __launch_bounds__(256) void at_finalize_backward_kernel(
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // the per-particle loads first, in flight during the far-field work
+    const int64_t o = perm[i];
+    const double4 a = near_pa[i];
+    const double sb = near_b[i];
     const int A = leaf_of[i];
     const int4 c = cell[A];
     const double2 z = xy[i];
     double2 wv, dw, phi, dphi;
     far_value_deriv<false, true>(A, c, z, w_off, w_idx, cell, mp, lo, p, x0, y0, side, wv, dw);
     far_value_deriv<true, SRC>(A, c, z, w_off, w_idx, cell, mp2, lo2, p, x0, y0, side, phi, dphi);
-    const double4 a = near_pa[i];
-    const double sb = near_b[i];
     const double ka = alpha * alpha * kInv2Pi;
     const double Ar = ka * (-2.0 * a.w), Ai = -ka * a.z;
     const double Bi = -ka * lambda * sb;
-    const int64_t o = perm[i];
     if (dl_dgamma) dl_dgamma[o] = -(alpha * a.y + phi.y) * kInv2Pi;
     if (dl_dxeval) {
         const double2 q = adj[i];

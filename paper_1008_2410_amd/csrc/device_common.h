@@ -497,6 +497,30 @@ __device__ __forceinline__ c2<T> horner_prefetch(const c2<T> *__restrict__ b, in
     return acc;
 }
 
+// Horner's rule with weighted coefficients, sum_{l=lo}^{p-1} (l + add) b_l x^(l-lo)
+// (p > lo), in the order l = p-2 .. lo, the coefficients loaded eight at a time ahead of
+// their use: the derivative of the series above with lo = 1, add = 0.
+template <typename T>
+__device__ __forceinline__ c2<T> horner_weighted_prefetch(const c2<T> *__restrict__ b, int p, c2<T> x, int lo,
+                                                          int add)
+{
+    const c2<T> top = b[p - 1];
+    const T wt = (T)(p - 1 + add);
+    c2<T> acc = mk<T>(wt * top.x, wt * top.y);
+    for (int l0 = p - 2; l0 >= lo; l0 -= 8) {
+        c2<T> c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = b[l0 - k >= lo ? l0 - k : lo];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (l0 - k >= lo) {
+                const T l = (T)(l0 - k + add);
+                acc = cmac<T>(mk<T>(l * c[k].x, l * c[k].y), acc, x);
+            }
+    }
+    return acc;
+}
+
 // Second half of a staged finalize: (u, v) of sorted particle i, written in sorted order
 // by the finalize kernel, to row perm[i] of the user-order output.  Reading the slot sums
 // and writing rows in random order in one kernel took longer (840 us for 2^24 particles)

@@ -1101,6 +1101,7 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t o = perm[i];  // issued with the first loads
     const double4 a = near_pa[i];
     const double sb = near_b[i];
     double phi = alpha * a.y;  // only Im(Phi) enters dL/dGamma
@@ -1118,29 +1119,19 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
         const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
         const c2<TL> *bq = loc_q + (int64_t)leaf * p;
         const c2<TL> *bc = loc_c + (int64_t)leaf * p;
-        c2<TL> accq = bq[p - 1];
-        for (int l = p - 2; l >= 0; --l) accq = cmac<TL>(bq[l], accq, xi);
+        const c2<TL> accq = horner_prefetch<TL>(bq, p, xi);
         phi += (double)accq.y / w;
         if (p >= 2) {
-            c2<TL> accd = mk<TL>((TL)(p - 1) * bc[p - 1].x, (TL)(p - 1) * bc[p - 1].y);
-            for (int l = p - 2; l >= 1; --l) {
-                const c2<TL> t = mk<TL>((TL)l * bc[l].x, (TL)l * bc[l].y);
-                accd = cmac<TL>(t, accd, xi);
-            }
+            const c2<TL> accd = horner_weighted_prefetch<TL>(bc, p, xi, 1, 0);
             dwr = (double)accd.x / (w * w);
             dwi = (double)accd.y / (w * w);
             if (near_src) {
-                c2<TL> accp = mk<TL>((TL)(p - 1) * bq[p - 1].x, (TL)(p - 1) * bq[p - 1].y);
-                for (int l = p - 2; l >= 1; --l) {
-                    const c2<TL> t = mk<TL>((TL)l * bq[l].x, (TL)l * bq[l].y);
-                    accp = cmac<TL>(t, accp, xi);
-                }
+                const c2<TL> accp = horner_weighted_prefetch<TL>(bq, p, xi, 1, 0);
                 dpr = (double)accp.x / (w * w);
                 dpi = (double)accp.y / (w * w);
             }
         }
     }
-    const int64_t o = perm[i];
     if (dl_dgamma) dl_dgamma[o] = -phi * kInv2Pi;
     if (dl_dxeval) {
         const double2 q = adj[i];
