@@ -40,7 +40,7 @@ void free_workspace(Workspace &ws, hipStream_t s)
     for (void *p : {(void *)ws.rec, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
                     (void *)ws.lo_f, (void *)ws.adj, (void *)ws.bwd_near, (void *)ws.bwd_b, (void *)ws.mp2_d,
                     (void *)ws.lo2_d, (void *)ws.mp2_f, (void *)ws.lo2_f, (void *)ws.rec2, (void *)ws.slots,
-                    (void *)ws.bwd_src})
+                    (void *)ws.bwd_src, (void *)ws.bwd_stage})
         if (p) hipFreeAsync(p, s);
     ws = Workspace{};
 }
@@ -118,6 +118,9 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
         ws.split = split;
     }
     if (backward && !ws.bwd_src && (rc = dev_alloc_async(&ws.bwd_src, n, "adjoint source-position sums", s))) return rc;
+    if (backward && !ws.bwd_stage && n * (int64_t)sizeof(double2) > kLastLevelCacheBytes &&
+        (rc = dev_alloc_async(&ws.bwd_stage, 5 * n, "adjoint output staging", s)))
+        return rc;
     if (backward && !ws.adj) {
         if ((rc = dev_alloc_async(&ws.adj, n, "adjoint charges", s))) return rc;
         if ((rc = dev_alloc_async(&ws.bwd_near, n, "adjoint near field", s))) return rc;
@@ -771,7 +774,7 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
     launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, dl_dgamma,
-                             dl_dxeval, dl_dxsrc, ms);
+                             dl_dxeval, dl_dxsrc, ws.bwd_stage, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);

@@ -80,6 +80,7 @@ constexpr int64_t kCoefPad = 64;
 // to round-robin.
 constexpr int kStageShiftMin = 17;
 constexpr int kXcds = 8;
+constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;  // MI355X Infinity Cache
 // Flag (in w) of a mutual item in the near-field work list.
 constexpr int kMutualItem = 256;
 
@@ -101,6 +102,8 @@ struct Workspace {
     void *rec2 = nullptr;         // adjoint charges q in FP32 for the mixed near field
     void *slots = nullptr;        // mutual near field: 9 x n sums (float2 or double2)
     double4 *bwd_src = nullptr;   // per sorted particle: near sums of the source-position terms
+    double *bwd_stage = nullptr;  // n above the last-level cache: the adjoint outputs by staging
+                                  // slot, dL/dGamma (n), dL/dx_eval (2n), dL/dx_src (2n)
 };
 
 }  // namespace fmm
@@ -200,7 +203,7 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
                          double4 *out_pa, double *out_b, double4 *out_src, int near_waves, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
-                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, hipStream_t s);
+                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, double *stage, hipStream_t s);
 
 // Tables (host generation + upload), kernels.hip
 int upload_tables(Tables &tb, int p, std::string &err);

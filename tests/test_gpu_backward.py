@@ -223,3 +223,41 @@ def test_uniform_target_field_central_differences_fp64(fmm_mod):
     moved.close()
     tree.close()
     torch.cuda.synchronize()
+
+
+def test_user_order_above_cache_size(fmm_mod):
+    """Above 2^24 particles the velocities and the three adjoint outputs reach user order
+    through the staging windows.  Renumbering the particles (a random permutation of the
+    user order; the tree, hence every sum, is the same) must permute every output the same
+    way: a wrong staging slot would move values between particles.  Every particle sits in
+    a cell of its own on the 2^15 x 2^15 grid of sub-leaf keys (depth 9, 64 x 64 per leaf),
+    so the tree order does not depend on the numbering and the outputs must agree bit for
+    bit, in both precisions."""
+    import torch
+    n = (1 << 24) + 4097
+    r = np.random.Generator(np.random.PCG64(31))
+    cells = np.unique(r.integers(0, 1 << 30, size=n + n // 8))
+    cells = r.permutation(cells)[:n]
+    assert len(cells) == n
+    ij = np.stack([cells >> 15, cells & 0x7FFF], axis=1).astype(np.float64)
+    xy = (ij + 0.25 + 0.5 * r.random((n, 2))) / 32768.0
+    g = r.standard_normal(n) / n
+    dl = r.standard_normal((n, 2))
+    order = r.permutation(n)
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n)
+    sigma, p = 0.5 / 512, 8
+    out = {}
+    for key, perm in (("a", np.arange(n)), ("b", order)):
+        tree = fmm_mod.Tree(_t(xy[perm]), 9, (0.0, 0.0, 1.0))
+        res = []
+        for precision in ("mixed", "fp64"):
+            gt, dlt = _t(g[perm]), _t(dl[perm])
+            res.append(tree.velocity(gt, sigma, p, precision).cpu().numpy())
+            res += [v.cpu().numpy() for v in tree.velocity_backward(gt, sigma, p, precision, dlt, need_src=True)]
+        out[key] = res
+        del tree
+        torch.cuda.empty_cache()
+    names = ["uv", "dgamma", "dxeval", "dxsrc"] * 2
+    for name, a, b in zip(names, out["a"], out["b"]):
+        assert np.array_equal(a, b[inv]), name

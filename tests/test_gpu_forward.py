@@ -136,6 +136,26 @@ def test_patches_mixed_full_size(fmm_mod, oracle_mod):
     assert e_fp64 < FP64_TOL
 
 
+def test_output_permutation_above_cache_size(fmm_mod):
+    """Above 2^24 rows (256 MiB of output) velocity reaches user order through the staging
+    windows (finalize writes at gpos2, a gather reads at gpos1); velocity_parts still
+    scatters directly.  A ragged n just past the switch: uv must be near + far bit for bit,
+    in both precisions, and every row must be written (the output starts as NaN)."""
+    import torch
+    n = (1 << 24) + 4097
+    r = np.random.Generator(np.random.PCG64(29))
+    xy = r.random((n, 2))
+    g = _t(r.standard_normal(n) / n)
+    tree = fmm_mod.Tree(_t(xy), 9, (0.0, 0.0, 1.0))
+    for precision in ("mixed", "fp64"):
+        uv = torch.full((n, 2), float("nan"), dtype=torch.float64, device="cuda")
+        tree.velocity(g, 0.5 / 512, 8, precision, out=uv)
+        near, far = tree.velocity_parts(g, 0.5 / 512, 8, precision)
+        assert torch.equal(uv, near + far), precision
+    del tree
+    torch.cuda.empty_cache()
+
+
 def test_linear_impulse_fp64(fmm_mod):
     """sum_i Gamma_i u_i = 0 to roundoff: the truncated FMM operator is antisymmetric."""
     w = W.uniform_lamb_oseen(n=20000, seed=17, depth=5, p=11)
