@@ -249,12 +249,13 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     if ((rc = tm.init(t))) return rc;
 
     tm.mark(0, ms);
-    launch_pack(t, gamma, alpha, is_double, t->ws.rec, ms);
-    tm.mark(1, ms);
-    if (overlap) {
+    launch_stage_in(t, gamma, ms);
+    if (overlap) {  // the far chain needs only the staged circulations: it starts beside pack
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
+    launch_pack(t, alpha, is_double, t->ws.rec, ms);
+    tm.mark(1, ms);
     tm.mark(2, ss);
     launch_far_chain(a, ss);
     tm.mark(3, ss);
@@ -755,7 +756,8 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if ((rc = tm.init(t))) return rc;
 
     tm.mark(0, ms);
-    launch_pack(t, gamma, alpha, is_double, ws.rec, ms);
+    launch_stage_in(t, gamma, ms);
+    launch_pack(t, alpha, is_double, ws.rec, ms);
     launch_pack_adjoint(t, dl_duv, ws.adj, ws.rec2, is_double, ms);
     tm.mark(1, ms);
     if (overlap) {

@@ -62,6 +62,9 @@ template <typename T> struct Rec;
 template <> struct Rec<float> { using type = float4; };
 template <> struct Rec<double> { using type = double4; };
 template <typename T> using rec_t = typename Rec<T>::type;
+template <typename R> struct RecScalar;
+template <> struct RecScalar<float4> { using type = float; };
+template <> struct RecScalar<double4> { using type = double; };
 
 // g(s) = 1 - exp(-|dz|^2/(2 sigma^2)) in the scaled variable s, and 1/s.
 __device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builtin_amdgcn_exp2f(-s); }

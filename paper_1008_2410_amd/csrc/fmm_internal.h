@@ -189,7 +189,10 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
                       int64_t &bad_index);
 int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err);
 
-void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s);
+// Pass 1 of the circulations into tree order (the staging array, all P2M needs), then
+// pass 2 with the near-field records.
+void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s);
+void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipStream_t s);
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
                         int near_waves, hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);

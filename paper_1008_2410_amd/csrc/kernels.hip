@@ -257,7 +257,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
 template <typename TR, typename TC, int PMAX>
 __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, int nleaves,
                                                   const int *__restrict__ leaf_start,
-                                                  const double2 *__restrict__ xy, const TR *__restrict__ rec,
+                                                  const double2 *__restrict__ xy, const int *__restrict__ gpos2,
+                                                  const double *__restrict__ gamma_st,
                                                   const double2 *__restrict__ adj, double x0, double y0, double w,
                                                   int p, c2<TC> *__restrict__ out)
 {
@@ -280,7 +281,10 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
             const double2 q = adj[j];
             pw = mk<TC>((TC)q.x, (TC)q.y);
         } else {
-            pw = mk<TC>(0, (TC)(-(double)rec[j].z * kInv2Pi));
+            // the circulation as the records hold it (rounded to their precision), read
+            // from the staging array so that P2M need not wait for the records
+            const double gj = (double)(typename RecScalar<TR>::type)gamma_st[gpos2[j]];
+            pw = mk<TC>(0, (TC)(-gj * kInv2Pi));
         }
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) {
@@ -854,10 +858,10 @@ void p2m_launch(const FarArgs &a, hipStream_t s)
     const unsigned g = capped_blocks(nl, 1, a.max_waves);
     if (a.p <= 16)
         p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out);
     else
         p2m_kernel<TR, TC, 32><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                (const TR *)a.rec, a.adj, t->x0, t->y0, w, a.p, out);
+                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out);
 }
 
 template <typename TC, typename TP>
@@ -1223,10 +1227,14 @@ inline unsigned xcd_grid(int64_t work, int per_block)
     return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
 }
 
-void launch_pack(const fmm_tree *t, const double *gamma, double alpha, int is_double, void *rec, hipStream_t s)
+void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s)
 {
     stage_in_kernel<<<xcd_grid(t->n, 256 * kStageE), 256, 0, s>>>((int)t->n, t->stage_shift, kXcds, t->d_gpos1,
                                                                    gamma, t->d_st1);
+}
+
+void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipStream_t s)
+{
     const double w = t->side / (double)(1 << t->depth);
     const int n = (int)t->n;
     if (is_double)
