@@ -260,12 +260,14 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
                                                   const double2 *__restrict__ xy, const int *__restrict__ gpos2,
                                                   const double *__restrict__ gamma_st,
                                                   const double2 *__restrict__ adj, double x0, double y0, double w,
-                                                  int p, c2<TC> *__restrict__ out)
+                                                  int p, c2<TC> *__restrict__ out, int nxcd)
 {
     constexpr int NC = 2 * PMAX;             // partial sums per lane (re, im interleaved)
     __shared__ TC red[64][NC + 1];
     const int lane = threadIdx.x;
-    for (int li = blockIdx.x; li < nleaves; li += gridDim.x) {
+    // with nxcd > 1 each XCD takes a contiguous run of leaves, so the staging windows its
+    // circulation reads fall in stay in its own L2
+    for (int li = xcd_block(nxcd); li < nleaves; li += gridDim.x) {
     const uint32_t leaf = (uint32_t)leaves[li];
     const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
     const double cx = x0 + (morton_x(leaf) + 0.5) * w;
@@ -823,6 +825,12 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int n, int nxcd, const
 
 inline unsigned blocks_for(int64_t work, int per_block) { return (unsigned)((work + per_block - 1) / per_block); }
 
+// A grid of whole rounds over the XCDs, for kernels that index blocks with xcd_block.
+inline unsigned xcd_grid(int64_t work, int per_block)
+{
+    return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
+}
+
 // Grid of a far-field kernel whose work-items loop with a grid stride: at most
 // `max_waves` wavefronts when the far field runs beside the near field (its waves then
 // stay resident instead of waiting for near-field wavefronts to retire one by one),
@@ -855,13 +863,17 @@ void p2m_launch(const FarArgs &a, hipStream_t s)
     if (nl == 0) return;
     const double w = t->side / (double)(1 << L);
     c2<TC> *out = level_ptr<TC>(a, L, false);
-    const unsigned g = capped_blocks(nl, 1, a.max_waves);
+    // capped beside the near field: a grid-stride loop in launch order; else one leaf per
+    // workgroup, contiguous per XCD
+    const bool capped = a.max_waves > 0 && nl > a.max_waves;
+    const unsigned g = capped ? capped_blocks(nl, 1, a.max_waves) : xcd_grid(nl, 1);
+    const int nxcd = capped ? 1 : kXcds;
     if (a.p <= 16)
         p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out);
+                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
     else
         p2m_kernel<TR, TC, 32><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out);
+                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
 }
 
 template <typename TC, typename TP>
@@ -1222,10 +1234,6 @@ void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStrea
 }
 
 // Grids of the permutation kernels: a multiple of the XCD count (see xcd_block).
-inline unsigned xcd_grid(int64_t work, int per_block)
-{
-    return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
-}
 
 void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s)
 {
