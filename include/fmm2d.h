@@ -65,19 +65,22 @@ enum {
                                  single-workgroup kernel in FP64 (default 3, range 1..depth) */
     FMM_OPT_TIMING = 3,       /* 1: record HIP events around each stage of every call for
                                  fmm_get_timings (default 0) */
-    FMM_OPT_NEAR_WAVES = 4,   /* near-field grid: 0 = one workgroup per work unit (default);
-                                 N > 0 = a persistent grid of N wavefronts taking units from a
-                                 counter, leaving the rest of the chip to the far field */
-    FMM_OPT_FAR_WAVES = 5,    /* cap on the far-field kernels' grids (wavefronts) while they run
-                                 beside the near field; 0 = none (default) */
+                              /* keys 4 and 5 (a persistent near-field grid, a cap on the far-field
+                                 grids) were measured slower than the default and are withdrawn:
+                                 FMM_EINVAL */
     FMM_OPT_NEAR_MUTUAL = 6,  /* 1 (default): pairs of neighbouring dense leaves are evaluated once
                                  for both particles (the kernel is odd), the rest from the target
                                  end; 0: every pair from the target end.  Results agree to rounding. */
     FMM_OPT_DENSE_LEAF = 7,   /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
-    FMM_OPT_NEAR_OCCUPANCY = 8 /* 1..8: with FMM_OPT_SCHEDULE 0 the forward near-field kernel keeps at
+    FMM_OPT_NEAR_OCCUPANCY = 8, /* 1..8: with FMM_OPT_SCHEDULE 0 the forward near-field kernel keeps at
                                   most this many wavefronts per SIMD resident (by reserving LDS),
                                   leaving room for the far field beside it; 0 = no cap; -1 (default)
                                   = 5 or none per call, from the predicted far/near time ratio */
+    FMM_OPT_VALIDATE = 9      /* 1: every evaluation first checks the circulations (and an adjoint
+                                 call its dL/du) for NaN and infinities on the device and returns
+                                 FMM_EINVAL, naming the lowest particle index, before any other
+                                 work; the check synchronises main_stream.  0 (default): no check
+                                 (a non-finite input then gives non-finite outputs) */
 };
 
 /* Stage indices of fmm_get_timings. */
@@ -212,6 +215,17 @@ int fmm_set_option(fmm_tree *tree, int key, int64_t value);
  * on.  ms: host, FMM_T_COUNT doubles; calls: host, receives the number of calls.
  * Synchronises the recorded events; resets the sums. */
 int fmm_get_timings(fmm_tree *tree, double *ms, int64_t *calls);
+
+/* Event times of the most recent call made with FMM_OPT_TIMING on and not yet summed by
+ * fmm_get_timings (that call is kept for it), in milliseconds after the call's first event:
+ *   ms[0] stage-in start (0), ms[1] pack end (main stream), ms[2] far-field chain start and
+ *   ms[3] its end (side stream, or the main stream when serialised), ms[4] P2P start and
+ *   ms[5] its end (main stream), ms[6] final stage start, ms[7] its end.
+ * A far chain running concurrently with P2P (the two-stream schedule of section
+ * "Concurrency", no edge between stages 4-8 and 9 in Fig. fmmStages) shows ms[2] < ms[5]
+ * and ms[4] < ms[3].  ms: host, count doubles (entries past 7 are set to 0).  Synchronises
+ * the recorded events.  FMM_ESTATE when no such call is pending. */
+int fmm_get_timeline(fmm_tree *tree, double *ms, int count);
 
 /* Free a tree and its device memory (synchronises the device first).  NULL is a no-op. */
 void fmm_destroy_tree(fmm_tree *tree);

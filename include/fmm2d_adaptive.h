@@ -89,13 +89,17 @@ int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, int max_dept
 int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
                       fmm_atree **out);
 
-/* Set an option of the tree.  Only FMM_OPT_NEAR_OCCUPANCY (fmm2d.h) applies here: 1..8
- * keeps at most that many forward near-field wavefronts per SIMD resident (by reserving
- * LDS) while the far field runs beside them on side_stream, 0 = no cap, -1 (default) =
- * chosen per call from the tree's predicted far/near time ratio (mixed precision; no cap
- * in FP64).  A call whose side_stream is main_stream runs serialised and uncapped.
- * Results do not depend on it.  fmm_atree_rebuild keeps it.  FMM_EINVAL for another key
- * or a value outside [-1, 8], FMM_ESTATE for a NULL tree. */
+/* Set an option of the tree.  Two keys of fmm2d.h apply here:
+ *  FMM_OPT_NEAR_OCCUPANCY: 1..8 keeps at most that many forward near-field wavefronts per
+ *    SIMD resident (by reserving LDS) while the far field runs beside them on side_stream,
+ *    0 = no cap, -1 (default) = chosen per call from the tree's predicted far/near time
+ *    ratio (mixed precision; no cap in FP64).  A call whose side_stream is main_stream runs
+ *    serialised and uncapped.  Results do not depend on it.
+ *  FMM_OPT_VALIDATE: 1 checks the circulations (and dL/du of an adjoint call) for NaN and
+ *    infinities first, FMM_EINVAL naming the lowest particle index (synchronises
+ *    main_stream); 0 (default) no check.
+ * fmm_atree_rebuild keeps both.  FMM_EINVAL for another key or a value out of range,
+ * FMM_ESTATE for a NULL tree. */
 int fmm_atree_set_option(fmm_atree *tree, int key, int64_t value);
 
 /* Host: sizes[FMM_AT_COUNT] (see the enum), root_box[3] (may be NULL). */

@@ -10,8 +10,8 @@ LIB_PATH = os.path.join(_HERE, "libfmm2d.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ERANGE, FMM_ESTATE = 0, -1, -2, -3, -4, -5
 FMM_FP64, FMM_MIXED = 0, 1
-FMM_OPT_SCHEDULE, FMM_OPT_COARSE_LEVEL, FMM_OPT_TIMING, FMM_OPT_NEAR_WAVES, FMM_OPT_FAR_WAVES = 1, 2, 3, 4, 5
-FMM_OPT_NEAR_MUTUAL, FMM_OPT_DENSE_LEAF, FMM_OPT_NEAR_OCCUPANCY = 6, 7, 8
+FMM_OPT_SCHEDULE, FMM_OPT_COARSE_LEVEL, FMM_OPT_TIMING = 1, 2, 3
+FMM_OPT_NEAR_MUTUAL, FMM_OPT_DENSE_LEAF, FMM_OPT_NEAR_OCCUPANCY, FMM_OPT_VALIDATE = 6, 7, 8, 9
 FMM_T_PACK, FMM_T_FAR, FMM_T_P2P, FMM_T_FINAL, FMM_T_TOTAL, FMM_T_COUNT = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_EINVAL", -2: "FMM_ENOMEM", -3: "FMM_EDEVICE", -4: "FMM_ERANGE",
                 -5: "FMM_ESTATE"}
@@ -33,6 +33,7 @@ SIGNATURES = {
     "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fmm_set_option": (_I, [_P, _I, _I64]),
     "fmm_get_timings": (_I, [_P, _P, _P]),
+    "fmm_get_timeline": (_I, [_P, _P, _I]),
     "fmm_near_plan_info": (_I, [_P, _P, _P, _P]),
     "fmm_destroy_tree": (None, [_P]),
     "fmm_last_error": (ctypes.c_char_p, []),

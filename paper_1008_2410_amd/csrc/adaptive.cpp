@@ -59,6 +59,7 @@ void free_atree(fmm_atree *t)
             hipFree(p);
     }
     free_ws(t->ws);
+    if (t->d_flag) hipFree(t->d_flag);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
     if (t->own_side) hipStreamDestroy(t->own_side);
@@ -298,6 +299,22 @@ int ensure_ws_backward(fmm_atree *t, bool src)
     return FMM_OK;
 }
 
+// FMM_OPT_VALIDATE: circulations (and dL/du) checked for NaN / Inf first (synchronises s).
+int validate_inputs(fmm_atree *t, const double *gamma, const double *dl_duv, hipStream_t s)
+{
+    if (!t->validate) return FMM_OK;
+    int rc = FMM_OK;
+    if (!t->d_flag && (rc = dev_alloc(&t->d_flag, 1, "input check flag"))) return rc;
+    int64_t bad = -1;
+    HIP_TRY(find_nonfinite(gamma, t->n, 1, t->d_flag, s, bad));
+    if (bad >= 0) return fail(FMM_EINVAL, "non-finite circulation (particle " + std::to_string(bad) + ")");
+    if (dl_duv) {
+        HIP_TRY(find_nonfinite(dl_duv, t->n, 2, t->d_flag, s, bad));
+        if (bad >= 0) return fail(FMM_EINVAL, "non-finite dL/du (particle " + std::to_string(bad) + ")");
+    }
+    return FMM_OK;
+}
+
 int check_eval(const fmm_atree *t, const double *gamma, double sigma, int p, int precision)
 {
     if (!t) return fail(FMM_ESTATE, "null tree handle");
@@ -341,8 +358,8 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     Busy guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
-    int rc = ensure_ws(t, p, precision);
-    if (rc) return rc;
+    int rc = validate_inputs(t, gamma, nullptr, (hipStream_t)main_stream);
+    if (rc || (rc = ensure_ws(t, p, precision))) return rc;
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
     const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision),
@@ -372,6 +389,7 @@ int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int pre
     HIP_TRY(hipSetDevice(t->device));
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    if ((rc = validate_inputs(t, gamma, dl_duv, ms))) return rc;
     if (t->nbwd_units < 0) {
         std::string err;
         if ((rc = build_atree_adjoint_units(t, ms, err))) return fail(rc, err);
@@ -477,6 +495,7 @@ extern "C" int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, c
     }
     std::swap(t->ws, prev->ws);
     t->near_occupancy = prev->near_occupancy;
+    t->validate = prev->validate;
     guard.release();
     free_atree(prev);
     *out = t;
@@ -821,6 +840,10 @@ extern "C" int fmm_atree_set_option(fmm_atree *t, int key, int64_t value)
     case FMM_OPT_NEAR_OCCUPANCY:
         if (value < -1 || value > 8) return fail(FMM_EINVAL, "near occupancy must be in [-1, 8]");
         t->near_occupancy = (int)value;
+        return FMM_OK;
+    case FMM_OPT_VALIDATE:
+        if (value != 0 && value != 1) return fail(FMM_EINVAL, "validate must be 0 or 1");
+        t->validate = (int)value;
         return FMM_OK;
     default:
         return fail(FMM_EINVAL, "unknown option key for an adaptive tree");

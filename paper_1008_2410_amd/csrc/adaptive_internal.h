@@ -110,6 +110,8 @@ struct fmm_atree {
     int64_t nbwd_units = -1;  // -1 until the adjoint units are made
     int dense_leaf = 32;
     int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
+    int validate = 0;         // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf
+    int *d_flag = nullptr;    // device result of that check
     std::vector<int> level_off;   // max_depth + 2 entries
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
     bool pooled = false;  // device arrays from the stream-ordered pool (the device build)

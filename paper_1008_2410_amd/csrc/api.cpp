@@ -62,7 +62,7 @@ void free_tree(fmm_tree *t)
         release(p, t->pooled);
     release(t->d_near_work, true);
     release(t->d_leaf_mask, true);
-    hipFree(t->d_work);
+    hipFree(t->d_flag);
     free_workspace(t->ws, fs);
     if (t->own_side) hipStreamDestroy(t->own_side);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
@@ -153,6 +153,22 @@ int check_eval_args(fmm_tree *t, const double *gamma, double sigma, int p, int p
 }
 
 
+// FMM_OPT_VALIDATE: the circulations (and the cotangent of an adjoint call) are checked
+// for NaN and infinities before any other work of the call; a bad value gives FMM_EINVAL
+// naming the lowest particle index.  The check synchronises the main stream.
+int validate_inputs(fmm_tree *t, const double *gamma, const double *dl_duv, hipStream_t s)
+{
+    if (!t->validate) return FMM_OK;
+    int64_t bad = -1;
+    HIP_TRY(find_nonfinite(gamma, t->n, 1, t->d_flag, s, bad));
+    if (bad >= 0) return fail(FMM_EINVAL, "non-finite circulation (particle " + std::to_string(bad) + ")");
+    if (dl_duv) {
+        HIP_TRY(find_nonfinite(dl_duv, t->n, 2, t->d_flag, s, bad));
+        if (bad >= 0) return fail(FMM_EINVAL, "non-finite dL/du (particle " + std::to_string(bad) + ")");
+    }
+    return FMM_OK;
+}
+
 FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
 {
     const Workspace &ws = t->ws;
@@ -169,15 +185,8 @@ FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
     a.rec_is_double = precision == FMM_FP64;
     a.charge_kind = adjoint ? 1 : 0;
     a.adj = adjoint ? ws.adj : nullptr;
-    // Beside the near field the far-field grids can be capped (FMM_OPT_FAR_WAVES);
-    // serialised they take the whole chip.
-    a.max_waves = t->schedule == 0 ? t->far_waves : 0;
     return a;
 }
-
-// Near-field grid: FMM_OPT_NEAR_WAVES when set (0: one workgroup per unit), else one
-// workgroup per unit.
-int near_waves(const fmm_tree *t) { return t->near_waves; }
 
 // Stage costs of the mixed form (p = 16) on one MI355X, in ms, fitted by the cost-model
 // sweep of uniform particles (the complexity terms of section "Complexity Estimates"
@@ -230,6 +239,7 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     BusyGuard guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
+    if ((rc = validate_inputs(t, gamma, nullptr, (hipStream_t)main_stream))) return rc;
     std::string err;
     if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
     if ((rc = ensure_workspace(t, p, precision, false, (hipStream_t)main_stream))) return rc;
@@ -263,7 +273,7 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     void *slots = use_mutual(t) ? t->ws.slots : nullptr;
     t->occupancy_in_use = choose_occupancy(t, precision);
     tm.mark(4, ms);
-    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, slots, near_waves(t), ms);
+    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, slots, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
@@ -317,7 +327,7 @@ int finish_tree(fmm_tree *t, hipStream_t s)
     std::string err;
     const int rc = build_near_plan_device(t, s, err);
     if (rc) return fail(rc, err);
-    return dev_alloc(&t->d_work, 4, "work counter");
+    return dev_alloc(&t->d_flag, 1, "input check flag");
 }
 
 }  // namespace
@@ -338,13 +348,12 @@ int build_device(const double *xy, int64_t n, int depth, const double *root_box,
     if (rc) return rc;
     if (opts) {
         t->lc = opts->lc;
-        t->near_waves = opts->near_waves;
-        t->far_waves = opts->far_waves;
         t->schedule = opts->schedule;
         t->near_mutual = opts->near_mutual;
         t->dense_leaf = opts->dense_leaf;
         t->near_occupancy = opts->near_occupancy;
         t->timing = opts->timing;
+        t->validate = opts->validate;
     }
     hipStream_t s = (hipStream_t)stream;
     std::string err;
@@ -739,6 +748,7 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     BusyGuard guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
+    if ((rc = validate_inputs(t, gamma, dl_duv, (hipStream_t)main_stream))) return rc;
     std::string err;
     if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
     if ((rc = ensure_workspace(t, p, precision, true, (hipStream_t)main_stream))) return rc;
@@ -771,7 +781,7 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
     launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
-                        ws.bwd_b, dl_dxsrc ? ws.bwd_src : nullptr, near_waves(t), ms);
+                        ws.bwd_b, dl_dxsrc ? ws.bwd_src : nullptr, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
@@ -795,14 +805,6 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         if (value < 1 || value > t->depth) return fail(FMM_EINVAL, "coarse level must be in [1, depth]");
         t->lc = (int)value;
         return FMM_OK;
-    case FMM_OPT_NEAR_WAVES:
-        if (value < 0 || value > (int64_t(1) << 30)) return fail(FMM_EINVAL, "near waves must be in [0, 2^30]");
-        t->near_waves = (int)value;
-        return FMM_OK;
-    case FMM_OPT_FAR_WAVES:
-        if (value < 0 || value > (int64_t(1) << 30)) return fail(FMM_EINVAL, "far waves must be in [0, 2^30]");
-        t->far_waves = (int)value;
-        return FMM_OK;
     case FMM_OPT_NEAR_MUTUAL:
     case FMM_OPT_DENSE_LEAF: {
         if (key == FMM_OPT_NEAR_MUTUAL && value != 0 && value != 1)
@@ -825,6 +827,13 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
         if (value != 0 && value != 1) return fail(FMM_EINVAL, "timing must be 0 or 1");
         t->timing = (int)value;
         return FMM_OK;
+    case FMM_OPT_VALIDATE:
+        if (value != 0 && value != 1) return fail(FMM_EINVAL, "validate must be 0 or 1");
+        t->validate = (int)value;
+        return FMM_OK;
+    case 4:
+    case 5:
+        return fail(FMM_EINVAL, "option withdrawn (persistent near-field grid, far-field grid cap)");
     default:
         return fail(FMM_EINVAL, "unknown option");
     }
@@ -868,6 +877,25 @@ extern "C" int fmm_get_timings(fmm_tree *t, double *ms, int64_t *calls)
     t->pending_timing.clear();
     for (int k = 0; k < FMM_T_COUNT; ++k) ms[k] = acc[k];
     if (calls) *calls = ncalls;
+    return FMM_OK;
+}
+
+extern "C" int fmm_get_timeline(fmm_tree *t, double *ms, int count)
+{
+    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (!ms || count < 1) return fail(FMM_EINVAL, "ms is NULL or count < 1");
+    if (t->pending_timing.empty()) return fail(FMM_ESTATE, "no call recorded with FMM_OPT_TIMING since the last read");
+    HIP_TRY(hipSetDevice(t->device));
+    auto &ev = t->pending_timing.back();
+    HIP_TRY(hipEventSynchronize(ev[7]));
+    HIP_TRY(hipEventSynchronize(ev[3]));
+    for (int k = 0; k < count; ++k) {
+        ms[k] = 0.0;
+        if (k >= kNumEvents) continue;
+        float f = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&f, ev[0], ev[k]));
+        ms[k] = f;
+    }
     return FMM_OK;
 }
 

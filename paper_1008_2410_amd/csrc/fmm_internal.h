@@ -116,8 +116,6 @@ struct fmm_tree {
     int device = 0;
     int num_cus = 256;   // compute units of the device
     int lc = 3;          // coarse-level cutoff L_c
-    int near_waves = 0;  // persistent near-field grid in wavefronts (0: one workgroup per unit)
-    int far_waves = 0;   // cap of the far-field grids beside the near field (0: none)
     int schedule = 0;    // 0 overlap, 1 serial
     int near_mutual = 1; // pairs of dense leaves evaluated once for both particles
     int dense_leaf = 32; // a leaf with at least this many particles is dense
@@ -125,6 +123,7 @@ struct fmm_tree {
                              // (0: none, -1: chosen per call from the cost model)
     int occupancy_in_use = 0; // the cap of the current call
     int timing = 0;
+    int validate = 0;    // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf first
     std::atomic<int> busy{0};
 
     // host statistics
@@ -155,7 +154,7 @@ struct fmm_tree {
     uint16_t *d_leaf_mask = nullptr; // per leaf: bit d slot d written, bit 9 target-centric part
     int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
     float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
-    int *d_work = nullptr;        // near-field work counter (reset by each call's first kernel)
+    int *d_flag = nullptr;        // result of the input check (FMM_OPT_VALIDATE)
 
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -179,7 +178,6 @@ struct FarArgs {
     int rec_is_double;
     int charge_kind;           // 0: real Gamma in rec.z -> c = -i Gamma/(2 pi); 1: complex q from adj array
     const double2 *adj;        // complex charges in sorted order (charge_kind 1)
-    int max_waves;             // grid cap of the far-field kernels (0: none)
 };
 
 // Launchers (kernels.hip).  All are asynchronous on `s`.
@@ -194,7 +192,7 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err);
 void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s);
 void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipStream_t s);
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
-                        int near_waves, hipStream_t s);
+                        hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
                      double alpha, double *uv, double *uv_near, double *uv_far, void *stage, hipStream_t s);
@@ -203,10 +201,14 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,
                          hipStream_t s);
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, double4 *out_src, int near_waves, hipStream_t s);
+                         double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
                               double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, double *stage, hipStream_t s);
+
+// Lowest index k of the n groups of `stride` doubles at a (device) that holds a NaN or an
+// infinity, or -1 in bad; flag is a device int of the caller.  Synchronises s.
+hipError_t find_nonfinite(const double *a, int64_t n, int stride, int *flag, hipStream_t s, int64_t &bad);
 
 // Tables (host generation + upload), kernels.hip
 int upload_tables(Tables &tb, int p, std::string &err);

@@ -12,6 +12,7 @@
 #include "fmm_internal.h"
 #include "device_common.h"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -104,10 +105,9 @@ __global__ __launch_bounds__(256) void pack_kernel(int n, int nxcd, const int *_
                                                     const int *__restrict__ leaf_of,
                                                     const double2 *__restrict__ xy, const double *__restrict__ gamma_st,
                                                     double x0, double y0, double w, double alpha,
-                                                    rec_t<T> *__restrict__ rec, int *__restrict__ work_ctr)
+                                                    rec_t<T> *__restrict__ rec)
 {
     int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
-    if (i == 0 && work_ctr) work_ctr[0] = 0;  // near-field work counter of this call
     if (i >= n) return;
     uint32_t leaf = (uint32_t)leaf_of[i];
     double cx = x0 + (morton_x(leaf) + 0.5) * w;
@@ -207,14 +207,9 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
 //   precision, unscaled);
 //   target-centric units {leaf, first, count, log2 TP | 16 if dense neighbours are
 //   skipped}, writing near.
-// The list is sorted by estimated cost, heaviest first.  One workgroup per entry
-// (persistent == 0): the hardware dispatcher hands them out in order.  Persistent
-// (persistent != 0): a grid smaller than the chip's capacity, each wavefront taking the
-// next entry from the call's counter until none is left, which leaves wavefront slots
-// free for far-field kernels running beside it.  Either way each entry writes only its
-// own outputs, so the result does not depend on which wavefront takes which entry.
-// The counter's atomic is issued by one lane (a vector memory atomic) and broadcast to
-// the wavefront.
+// The list is sorted by estimated cost, heaviest first, and launched as one workgroup
+// per entry: the hardware dispatcher hands them out in order.  Each entry writes only
+// its own outputs, so the result does not depend on which wavefront takes which entry.
 
 template <typename T>
 __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t<T> *tile_b,
@@ -232,26 +227,13 @@ __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t
 
 template <typename T>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
-    const int4 *__restrict__ work, int nwork, int persistent, int *__restrict__ work_ctr,
-    const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start, const int *__restrict__ tile_start,
-    const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2, double scale, int dense, int64_t n,
-    double2 *__restrict__ near, c2<T> *__restrict__ slots)
+    const int4 *__restrict__ work, const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+    const int *__restrict__ tile_start, const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2,
+    double scale, int dense, int64_t n, double2 *__restrict__ near, c2<T> *__restrict__ slots)
 {
     __shared__ rec_t<T> tile_a[128], tile_b[128];
-    if (!persistent) {
-        near_entry<T>(work[blockIdx.x], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step,
-                      cut_leaf2, scale, dense, n, near, slots);
-        return;
-    }
-    for (;;) {
-        int v = 0;
-        if (threadIdx.x == 0) v = atomicAdd(work_ctr, 1);
-        const int cur = __builtin_amdgcn_readfirstlane(v);
-        if (cur >= nwork) break;
-        __syncthreads();  // the previous entry's LDS reads are done
-        near_entry<T>(work[cur], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
-                      scale, dense, n, near, slots);
-    }
+    near_entry<T>(work[blockIdx.x], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
+                  scale, dense, n, near, slots);
 }
 
 template <typename TR, typename TC, int PMAX>
@@ -265,8 +247,8 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
     constexpr int NC = 2 * PMAX;             // partial sums per lane (re, im interleaved)
     __shared__ TC red[64][NC + 1];
     const int lane = threadIdx.x;
-    // with nxcd > 1 each XCD takes a contiguous run of leaves, so the staging windows its
-    // circulation reads fall in stay in its own L2
+    // each XCD takes a contiguous run of leaves, so the staging windows its circulation
+    // reads fall in stay in its own L2
     for (int li = xcd_block(nxcd); li < nleaves; li += gridDim.x) {
     const uint32_t leaf = (uint32_t)leaves[li];
     const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
@@ -831,16 +813,6 @@ inline unsigned xcd_grid(int64_t work, int per_block)
     return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
 }
 
-// Grid of a far-field kernel whose work-items loop with a grid stride: at most
-// `max_waves` wavefronts when the far field runs beside the near field (its waves then
-// stay resident instead of waiting for near-field wavefronts to retire one by one),
-// else one wavefront per work item.
-inline unsigned capped_blocks(int64_t waves, int waves_per_block, int max_waves)
-{
-    int64_t w = waves;
-    if (max_waves > 0 && w > max_waves) w = max_waves;
-    return blocks_for(w, waves_per_block);
-}
 
 template <typename T> c2<T> *level_ptr(const FarArgs &a, int l, bool local);
 template <> double2 *level_ptr<double>(const FarArgs &a, int l, bool local)
@@ -863,11 +835,9 @@ void p2m_launch(const FarArgs &a, hipStream_t s)
     if (nl == 0) return;
     const double w = t->side / (double)(1 << L);
     c2<TC> *out = level_ptr<TC>(a, L, false);
-    // capped beside the near field: a grid-stride loop in launch order; else one leaf per
-    // workgroup, contiguous per XCD
-    const bool capped = a.max_waves > 0 && nl > a.max_waves;
-    const unsigned g = capped ? capped_blocks(nl, 1, a.max_waves) : xcd_grid(nl, 1);
-    const int nxcd = capped ? 1 : kXcds;
+    // one leaf per workgroup, contiguous per XCD
+    const unsigned g = xcd_grid(nl, 1);
+    const int nxcd = kXcds;
     if (a.p <= 16)
         p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
                                                 t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
@@ -921,7 +891,7 @@ void m2l_mfma_launch(const FarArgs &a, int l, hipStream_t s)
     const ClassTiles c = class_tiles(&t->class_off[4 * l], n, 4);
     const c2<TPar> *par = l >= 3 ? level_ptr<TPar>(a, l - 1, true) : nullptr;
     const int ne = par ? 28 : 27;  // the L2L entry is last in each class
-    gather_gemm_kernel<TPar, float><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+    gather_gemm_kernel<TPar, float><<<blocks_for(c.waves, 4), 256, 0, s>>>(
         level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(0, 28, 56, 84), make_int4(ne, ne, ne, ne),
         c.waves, a.p, l, t->tabs->mfma_entries, (const float *)level_ptr<float>(a, l, false), nullptr, par,
         (float *)level_ptr<float>(a, l, true), t->tabs->mfma_f, t->tabs->zero_row);
@@ -936,7 +906,7 @@ void m2m_mfma_launch(const FarArgs &a, int l, hipStream_t s)
     if (n == 0) return;
     const int64_t one_class[1] = {0};
     const ClassTiles c = class_tiles(one_class, n, 1);
-    gather_gemm_kernel<float, TP><<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+    gather_gemm_kernel<float, TP><<<blocks_for(c.waves, 4), 256, 0, s>>>(
         level_list(t, l), i4(c.start), i4(c.len), i4(c.wave0), make_int4(112, 112, 112, 112), make_int4(4, 0, 0, 0),
         c.waves, a.p, l, t->tabs->mfma_entries, nullptr, (const float *)level_ptr<float>(a, l + 1, false), nullptr,
         (TP *)level_ptr<TP>(a, l, false), t->tabs->mfma_f, t->tabs->zero_row);
@@ -968,7 +938,7 @@ void gemm_f64_launch(const FarArgs &a, int l, int mode, hipStream_t s)
     const int64_t one_class[1] = {0};
     const LevelClasses c = mode == 2 ? level_classes(one_class, n, 1) : level_classes(&t->class_off[4 * l], n, 4);
     const int p = a.p;
-    gather_gemm_f64_kernel<<<capped_blocks(c.waves, 4, a.max_waves), 256, 0, s>>>(
+    gather_gemm_f64_kernel<<<blocks_for(c.waves, 4), 256, 0, s>>>(
         level_list(t, l), c, mode == 2 ? make_int4(112, 112, 112, 112) : make_int4(0, 28, 56, 84), l >= 3 ? 28 : 27, 4,
         mode, p, l, t->tabs->mfma_entries, mode == 0 ? (const double *)(a.mp_d + level_base(l) * p) : nullptr,
         mode == 2 ? (const double *)(a.mp_d + level_base(l + 1) * p) : nullptr,
@@ -1083,39 +1053,18 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
     }
 }
 
-// Adjoint near-field grid: one workgroup per target-centric unit, or persistent as in
-// the forward grid with kNearBatch consecutive units per counter increment (the units
-// are small, so the batch hides the atomic's latency).
-constexpr int kNearBatch = 4;
-
+// Adjoint near-field grid: one workgroup per target-centric unit.
 template <typename T, bool SRC>
-__global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void p2p_backward_kernel(const int4 *__restrict__ units, int nunits, int persistent,
-                                                           int *__restrict__ work_ctr,
-                                                           const rec_t<T> *__restrict__ rec,
-                                                           const c2<T> *__restrict__ qv,
-                                                           const int *__restrict__ leaf_start,
-                                                           const int *__restrict__ tile_start,
-                                                           const float4 *__restrict__ tile_box, int nside, T step,
-                                                           float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
-                                                           double *__restrict__ out_b, double4 *__restrict__ out_src)
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void p2p_backward_kernel(
+    const int4 *__restrict__ units, const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qv,
+    const int *__restrict__ leaf_start, const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
+    int nside, T step, float cut_leaf2, T lambda, double4 *__restrict__ out_pa, double *__restrict__ out_b,
+    double4 *__restrict__ out_src)
 {
     __shared__ rec_t<T> tile[64];
     __shared__ c2<T> qtile[64];
-    if (!persistent) {
-        p2p_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside,
-                                  step, cut_leaf2, lambda, out_pa, out_b, out_src);
-        return;
-    }
-    for (;;) {
-        int v = 0;
-        if (threadIdx.x == 0) v = atomicAdd(work_ctr, kNearBatch);
-        const int first = __builtin_amdgcn_readfirstlane(v);
-        if (first >= nunits) break;
-        const int last = min(first + kNearBatch, nunits);
-        for (int cur = first; cur < last; ++cur)
-            p2p_backward_unit<T, SRC>(units[cur], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside,
-                                      step, cut_leaf2, lambda, out_pa, out_b, out_src);
-    }
+    p2p_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
+                              cut_leaf2, lambda, out_pa, out_b, out_src);
 }
 
 // Adjoint finalize: far parts from the q-field locals (Phi_far, by L2P) and the c-field
@@ -1215,6 +1164,18 @@ __global__ __launch_bounds__(256) void gather_adjoint_kernel(int n, int nxcd, co
     }
 }
 
+// Input check (FMM_OPT_VALIDATE): the lowest particle index whose `stride` values hold a
+// NaN or an infinity, by atomic minimum into *first (which starts at INT_MAX).
+__global__ void int_fill_kernel(int *p, int v) { *p = v; }
+
+__global__ __launch_bounds__(256) void nonfinite_kernel(int64_t count, int stride, const double *__restrict__ a,
+                                                         int *__restrict__ first)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += step)
+        if (!__builtin_isfinite(a[k])) atomicMin(first, (int)(k / stride));
+}
+
 __global__ __launch_bounds__(256) void widen_perm_kernel(int n, const int *__restrict__ perm,
                                                           const int *__restrict__ leaf_of, int64_t *__restrict__ out,
                                                           int32_t *__restrict__ leaf)
@@ -1226,6 +1187,20 @@ __global__ __launch_bounds__(256) void widen_perm_kernel(int n, const int *__res
 }
 
 }  // namespace
+
+hipError_t find_nonfinite(const double *a, int64_t n, int stride, int *flag, hipStream_t s, int64_t &bad)
+{
+    bad = -1;
+    const int64_t count = n * stride;
+    int_fill_kernel<<<1, 1, 0, s>>>(flag, INT_MAX);
+    const unsigned g = (unsigned)std::min<int64_t>(blocks_for(count, 256), 4096);
+    nonfinite_kernel<<<g, 256, 0, s>>>(count, stride, a, flag);
+    int h = INT_MAX;
+    hipError_t e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && h != INT_MAX) bad = h;
+    return e;
+}
 
 void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStream_t s)
 {
@@ -1247,10 +1222,10 @@ void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipS
     const int n = (int)t->n;
     if (is_double)
         pack_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
-                                                              t->x0, t->y0, w, alpha, (double4 *)rec, t->d_work);
+                                                              t->x0, t->y0, w, alpha, (double4 *)rec);
     else
         pack_kernel<float><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
-                                                             t->x0, t->y0, w, alpha, (float4 *)rec, t->d_work);
+                                                             t->x0, t->y0, w, alpha, (float4 *)rec);
 }
 
 // Exponential skipped where every pair has s >= cut: FP32 base 2, 1 - 2^-s rounds to 1
@@ -1274,7 +1249,7 @@ inline size_t near_lds_reserve(const fmm_tree *t, size_t static_bytes)
 }
 
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
-                        int near_waves, hipStream_t s)
+                        hipStream_t s)
 {
     const bool mutual = slots != nullptr;
     const int64_t nwork = mutual ? t->nnear_work : t->nunits;
@@ -1285,15 +1260,14 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
     const double scale = alpha * kInv2Pi;
     const double step = alpha * w;
     const float cut_leaf2 = near_cut_leaf2(t, is_double, alpha);
-    const int persistent = near_waves > 0 && near_waves < nwork;
-    const unsigned grid = (unsigned)(persistent ? near_waves : nwork);
+    const unsigned grid = (unsigned)nwork;
     if (is_double)
         p2p_near_kernel<double><<<grid, 64, near_lds_reserve(t, 256 * sizeof(double4)), s>>>(
-            work, (int)nwork, persistent, t->d_work, (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
+            work, (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
             t->d_tile_box, nside, step, cut_leaf2, scale, t->dense_leaf, t->n, near, (double2 *)slots);
     else
         p2p_near_kernel<float><<<grid, 64, near_lds_reserve(t, 256 * sizeof(float4)), s>>>(
-            work, (int)nwork, persistent, t->d_work, (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
+            work, (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
             t->d_tile_box, nside, (float)step, cut_leaf2, scale, t->dense_leaf, t->n, near, (float2 *)slots);
 }
 
@@ -1418,7 +1392,7 @@ void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, 
 }
 
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, double4 *out_src, int near_waves, hipStream_t s)
+                         double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s)
 {
     if (t->nunits == 0) return;
     const int nside = 1 << t->depth;
@@ -1426,27 +1400,26 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
     const double step = alpha * w;
     const double cut = is_double ? 39.0 : 27.0;
     const float cut_leaf2 = (float)(cut / (step * step));
-    const int persistent = near_waves > 0 && near_waves < t->nunits;
-    const unsigned grid = (unsigned)(persistent ? near_waves : t->nunits);
+    const unsigned grid = (unsigned)t->nunits;
     const float ln2 = (float)0.69314718055994530942;
     if (is_double) {
         if (out_src)
             p2p_backward_kernel<double, true><<<grid, 64, 0, s>>>(
-                t->d_units, (int)t->nunits, persistent, t->d_work, (const double4 *)rec, (const double2 *)qv,
+                t->d_units, (const double4 *)rec, (const double2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, out_src);
         else
             p2p_backward_kernel<double, false><<<grid, 64, 0, s>>>(
-                t->d_units, (int)t->nunits, persistent, t->d_work, (const double4 *)rec, (const double2 *)qv,
+                t->d_units, (const double4 *)rec, (const double2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, nullptr);
     } else {
         if (out_src)
             p2p_backward_kernel<float, true><<<grid, 64, 0, s>>>(
-                t->d_units, (int)t->nunits, persistent, t->d_work, (const float4 *)rec, (const float2 *)qv,
+                t->d_units, (const float4 *)rec, (const float2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
                 out_src);
         else
             p2p_backward_kernel<float, false><<<grid, 64, 0, s>>>(
-                t->d_units, (int)t->nunits, persistent, t->d_work, (const float4 *)rec, (const float2 *)qv,
+                t->d_units, (const float4 *)rec, (const float2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
                 nullptr);
     }

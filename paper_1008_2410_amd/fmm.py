@@ -37,6 +37,22 @@ def _as_device_f64(x: torch.Tensor, name: str, shape: tuple, device) -> torch.Te
     return x.detach().contiguous()
 
 
+def _check_out(out: torch.Tensor, n: int, device) -> torch.Tensor:
+    """An output tensor the library writes through directly: float64, shape (n, 2),
+    contiguous, on the tree's device (a copy would leave the caller's tensor unwritten)."""
+    if not isinstance(out, torch.Tensor):
+        raise ValueError("out must be a tensor")
+    if out.dtype != torch.float64:
+        raise ValueError(f"out must be float64, got {out.dtype}")
+    if tuple(out.shape) != (n, 2):
+        raise ValueError(f"out must have shape {(n, 2)}, got {tuple(out.shape)}")
+    if out.device != device:
+        raise ValueError(f"out is on {out.device}, tree on {device}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    return out
+
+
 def _precision(precision) -> int:
     if isinstance(precision, str):
         return PRECISIONS[precision]
@@ -146,12 +162,21 @@ class Tree:
         names = ["pack", "far", "p2p", "final", "total"]
         return {"calls": calls.value, **{k: ms[i] for i, k in enumerate(names)}}
 
+    def timeline(self) -> dict:
+        """Event times (ms after the call's first event) of the last call made with
+        FMM_OPT_TIMING on and not yet read by timings()."""
+        ms = (ctypes.c_double * 8)()
+        L.check(L.load().fmm_get_timeline(self.handle, ms, 8), "fmm_get_timeline")
+        names = ["start", "pack_end", "far_start", "far_end", "p2p_start", "p2p_end", "final_start", "final_end"]
+        return {k: ms[i] for i, k in enumerate(names)}
+
     # -- evaluation ---------------------------------------------------------------
     def velocity(self, gamma: torch.Tensor, sigma: float, p: int, precision="mixed", out=None,
                  side_stream=None) -> torch.Tensor:
         """(n, 2) float64 velocities in user order (stages 4-10)."""
         g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
-        uv = out if out is not None else torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        uv = _check_out(out, self.n, self.device) if out is not None else \
+            torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             L.check(L.load().fmm_velocity(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
                                           _stream_ptr(), _stream_ptr(side_stream) if side_stream else None,
@@ -269,7 +294,8 @@ class ATree:
         """(n, 2) float64 velocities in user order.  serial: the far field on the current
         stream after the near field instead of beside it (for timing the stages alone)."""
         g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
-        uv = out if out is not None else torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
+        uv = _check_out(out, self.n, self.device) if out is not None else \
+            torch.empty((self.n, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             s = _stream_ptr()
             L.check(L.load().fmm_atree_velocity(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
@@ -323,10 +349,10 @@ class VelocityFn(torch.autograd.Function):
         need_x, need_g = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_x or need_g):
             return None, None, None, None, None, None
-        dg, dx, ds = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision,
-                                                grad_uv.contiguous(), need_gamma=need_g, need_x=need_x,
-                                                need_src=need_x)
-        return (dx + ds if need_x else None), dg, None, None, None, None
+        res = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision, grad_uv.contiguous(),
+                                         need_gamma=need_g, need_x=need_x, need_src=need_x)
+        dg, dx = res[0], res[1]
+        return (dx + res[2] if need_x else None), dg, None, None, None, None
 
 
 def velocity(xy: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, precision="mixed",

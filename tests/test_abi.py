@@ -49,6 +49,25 @@ def test_bad_arguments_rejected_without_device(native_lib):
     assert native_lib.fmm_set_option(None, 1, 0) == _lib.FMM_ESTATE
     assert native_lib.fmm_tree_info(None, None, None, None, None, None, None, None) == _lib.FMM_ESTATE
     assert native_lib.fmm_get_timings(None, None, None) == _lib.FMM_ESTATE
+    assert native_lib.fmm_get_timeline(None, None, 8) == _lib.FMM_ESTATE
     native_lib.fmm_destroy_tree(None)
     assert native_lib.fmm_atree_set_option(None, _lib.FMM_OPT_NEAR_OCCUPANCY, 5) == _lib.FMM_ESTATE
     native_lib.fmm_atree_destroy(None)
+
+
+def test_output_tensor_check_on_host():
+    """The binding passes out= tensors to the library as they are, so it rejects any tensor
+    the kernels could not write in place (checked here with host tensors and the host device)."""
+    import pytest
+    import torch
+    from paper_1008_2410_amd.fmm import _check_out
+    dev = torch.device("cpu")
+    ok = torch.empty((7, 2), dtype=torch.float64)
+    assert _check_out(ok, 7, dev) is ok
+    for bad in (torch.empty((7, 2), dtype=torch.float32), torch.empty((6, 2), dtype=torch.float64),
+                torch.empty((2, 7), dtype=torch.float64).t(), torch.empty(14, dtype=torch.float64),
+                ok.numpy()):
+        with pytest.raises(ValueError):
+            _check_out(bad, 7, dev)
+    with pytest.raises(ValueError):
+        _check_out(ok, 7, torch.device("meta"))

@@ -1,0 +1,218 @@
+"""GPU parity over the rest of the ABI's range and the schedule of section "Concurrency".
+
+* Expansion orders 17..32 switch the far field to separate kernels (FP32 VALU M2M/M2L on
+  radius-scaled coefficients in the mixed form, the VALU coarse kernel): forward and adjoint
+  against the oracle FMM (O3) and its adjoint (O4 + O5), in both precisions.
+* The 1024^2 jittered lattice as its configuration states it: FP64, depth 8, p = 12, coarse
+  levels <= 5 in the single-workgroup kernel on the second stream.
+* The two-stream schedule: event times of a call show the far chain running while the near
+  field runs (no edge between stages 4-8 and stage 9 in Fig. fmmStages).
+* Input checks (FMM_OPT_VALIDATE), output-tensor checks, and the autograd function with only
+  one of its inputs requiring a gradient.
+
+Bars as elsewhere: FP64 rel-L2 <= 1e-10 (gradients 1e-9), mixed 1e-5 (gradients 1e-4), and
+per element max_i |a_i - b_i| / max_i |b_i| at the same gates.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+from paper_1008_2410_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def max_rel(a, b):
+    """Largest per-particle error against the largest per-particle magnitude."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return float(np.linalg.norm(a - b, axis=1).max() / np.linalg.norm(b, axis=1).max())
+
+
+@pytest.mark.parametrize("p", [17, 20, 24, 32])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_high_order_forward(fmm_mod, oracle_mod, p, precision, tol):
+    """p > 16: forward against O3, near and far parts separately and the sum, on a ragged
+    uniform draw (leaves of 0..40 particles) at depth 5, so that the fine levels 4..5 run in
+    the per-level kernels and levels 2..3 in the coarse kernel."""
+    n = 9001
+    r = np.random.Generator(np.random.PCG64(100 + p))
+    xy = r.random((n, 2))
+    g = r.standard_normal(n) / n
+    sigma, depth = 0.004, 5
+    tree = fmm_mod.Tree(_t(xy), depth, (0.0, 0.0, 1.0))
+    near, far = (v.cpu().numpy() for v in tree.velocity_parts(_t(g), sigma, p, precision))
+    full = tree.velocity(_t(g), sigma, p, precision).cpu().numpy()
+    on, of = oracle_mod.fmm_velocity(xy, g, sigma, depth, p, (0.0, 0.0, 1.0), parts=True)
+    print(f"p={p} {precision}: near {rel_l2(near, on):.2e}, far {rel_l2(far, of):.2e}, "
+          f"total {rel_l2(full, on + of):.2e} (max {max_rel(full, on + of):.2e})", flush=True)
+    assert rel_l2(near, on) < tol
+    assert rel_l2(far, of) < (tol if precision == "fp64" else 10 * tol)
+    assert rel_l2(full, on + of) < tol
+    assert max_rel(full, on + of) < tol
+
+
+@pytest.mark.parametrize("p", [17, 24, 32])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-4)])
+def test_high_order_backward(fmm_mod, oracle_mod, p, precision, tol):
+    """p > 16: the adjoint (circulations, evaluation positions, source positions) against O4
+    and O5 on a uniform draw at depth 4."""
+    w = W.uniform_lamb_oseen(n=5000, seed=200 + p, depth=4, p=p)
+    ustar = W.smooth_target_field(w.xy, seed=11)
+    uv = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box)
+    dl = uv - ustar
+    refs = oracle_mod.fmm_grad_full(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    got = [a.cpu().numpy() for a in tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl),
+                                                            need_src=True)]
+    for name, a, b in zip(("dgamma", "dxeval", "dxsrc"), got, refs):
+        print(f"p={p} {precision} {name}: rel-L2 {rel_l2(a, b):.2e}, max {max_rel(a, b):.2e}", flush=True)
+        assert rel_l2(a, b) < tol, name
+        assert max_rel(a, b) < tol, name
+
+
+def test_lattice_as_configured(fmm_mod, oracle_mod):
+    """1024^2 jittered lattice, depth 8, p = 12, FP64, coarse levels <= 5 in the one-workgroup
+    kernel on the side stream beside the near field: against O3 at 4096 particles, and the
+    same bits as the serial schedule; the event times show the two streams overlapping."""
+    import torch
+    from paper_1008_2410_amd import _lib
+    w = W.lattice_lamb_oseen()
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    tree.set_option(_lib.FMM_OPT_COARSE_LEVEL, 5)
+    g = _t(w.gamma)
+    tree.velocity(g, w.sigma, w.p, "fp64")  # tables and workspace
+    tree.set_option(_lib.FMM_OPT_TIMING, 1)
+    got = tree.velocity(g, w.sigma, w.p, "fp64").cpu().numpy()
+    tl = tree.timeline()
+    tree.timings()
+    tree.set_option(_lib.FMM_OPT_TIMING, 0)
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 1)
+    serial = tree.velocity(g, w.sigma, w.p, "fp64").cpu().numpy()
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 0)
+    idx = np.random.Generator(np.random.PCG64(22)).choice(w.n, 4096, replace=False)
+    ref = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, w.root_box, targets=w.xy[idx])
+    print(f"lattice L_c=5 fp64: rel-L2 {rel_l2(got[idx], ref):.2e}, max {max_rel(got[idx], ref):.2e}; "
+          f"timeline {tl}", flush=True)
+    assert rel_l2(got[idx], ref) < FP64_TOL
+    assert max_rel(got[idx], ref) < FP64_TOL
+    assert np.array_equal(got, serial)
+    # the far chain (side stream) starts before the near field and overlaps it
+    assert tl["far_start"] <= tl["p2p_start"]
+    assert tl["far_start"] < tl["p2p_end"] and tl["p2p_start"] < tl["far_end"]
+    del tree
+    torch.cuda.empty_cache()
+
+
+def test_schedule_timeline(fmm_mod):
+    """Event times of one call: with the two-stream schedule the far chain starts before the
+    near field starts and ends before the near field ends (it never waits for the near
+    field), and the two intervals overlap; serialised, the far chain ends before the near
+    field starts.  2^22 patch particles at depth 9, p = 16, mixed (far field about a tenth of
+    the near field)."""
+    from paper_1008_2410_amd import _lib
+    w = W.gaussian_patches(n=1 << 22, depth=9, n_sample=16)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, None)
+    g = _t(w.gamma)
+    out = tree.velocity(g, w.sigma, w.p, "mixed")
+    tree.set_option(_lib.FMM_OPT_TIMING, 1)
+    lines = {}
+    for sched in (0, 1):
+        tree.set_option(_lib.FMM_OPT_SCHEDULE, sched)
+        tree.velocity(g, w.sigma, w.p, "mixed", out=out)
+        lines[sched] = tree.timeline()
+        tree.timings()
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 0)
+    tree.set_option(_lib.FMM_OPT_TIMING, 0)
+    ov, se = lines[0], lines[1]
+    print(f"overlapped {ov}\nserial {se}", flush=True)
+    assert ov["far_start"] <= ov["p2p_start"]
+    assert ov["far_end"] < ov["p2p_end"]
+    assert ov["p2p_start"] < ov["far_end"]
+    assert se["far_end"] <= se["p2p_start"]
+    tree.close()
+
+
+def test_validate_rejects_non_finite(fmm_mod):
+    """FMM_OPT_VALIDATE: a NaN or infinite circulation or dL/du gives FMM_EINVAL naming the
+    lowest bad particle, for both trees; finite inputs pass and give the unchecked result."""
+    from paper_1008_2410_amd import _lib
+    w = W.uniform_lamb_oseen(n=3000, seed=41, depth=4, p=8)
+    for kind in ("uniform", "adaptive"):
+        tree = (fmm_mod.Tree(_t(w.xy), w.depth, w.root_box) if kind == "uniform"
+                else fmm_mod.ATree(_t(w.xy), 16, 6, w.root_box))
+        ref = tree.velocity(_t(w.gamma), w.sigma, w.p, "fp64").cpu().numpy()
+        tree.set_option(_lib.FMM_OPT_VALIDATE, 1)
+        assert np.array_equal(tree.velocity(_t(w.gamma), w.sigma, w.p, "fp64").cpu().numpy(), ref)
+        for bad, val in ((1234, math.nan), (17, math.inf), (2999, -math.inf)):
+            g = w.gamma.copy()
+            g[bad:] = math.nan  # every later particle bad as well: the lowest index is reported
+            g[bad] = val
+            with pytest.raises(_lib.FmmError) as e:
+                tree.velocity(_t(g), w.sigma, w.p, "mixed")
+            assert e.value.status == _lib.FMM_EINVAL and f"particle {bad}" in str(e.value), (kind, str(e.value))
+        dl = np.ones((w.n, 2))
+        dl[77, 1] = math.nan
+        with pytest.raises(_lib.FmmError) as e:
+            tree.velocity_backward(_t(w.gamma), w.sigma, w.p, "fp64", _t(dl))
+        assert e.value.status == _lib.FMM_EINVAL and "particle 77" in str(e.value), kind
+        tree.set_option(_lib.FMM_OPT_VALIDATE, 0)
+        g = w.gamma.copy()
+        g[5] = math.nan
+        assert np.isnan(tree.velocity(_t(g), w.sigma, w.p, "fp64").cpu().numpy()).any()
+        tree.close()
+
+
+def test_output_tensor_checked(fmm_mod):
+    """out= goes to the library unchanged, so a wrong dtype, shape, layout or device is an
+    error instead of a write past or beside the tensor."""
+    import torch
+    w = W.uniform_lamb_oseen(n=500, seed=3, depth=3, p=6)
+    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
+    g = _t(w.gamma)
+    for bad in (torch.empty((w.n, 2), dtype=torch.float32, device="cuda"),
+                torch.empty((w.n - 1, 2), dtype=torch.float64, device="cuda"),
+                torch.empty((2, w.n), dtype=torch.float64, device="cuda").t(),
+                torch.empty((w.n, 2), dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            tree.velocity(g, w.sigma, w.p, "fp64", out=bad)
+    ok = torch.empty((w.n, 2), dtype=torch.float64, device="cuda")
+    assert tree.velocity(g, w.sigma, w.p, "fp64", out=ok) is ok
+
+
+@pytest.mark.parametrize("which", ["gamma", "xy"])
+@pytest.mark.parametrize("kind", ["uniform", "adaptive"])
+def test_autograd_one_input(fmm_mod, oracle_mod, which, kind):
+    """The autograd function when only the circulations, or only the positions, require a
+    gradient: that gradient matches the oracle (O4 + O5; O7 for the adaptive tree)."""
+    w = W.uniform_lamb_oseen(n=2500, seed=8, depth=4, p=10)
+    ustar = _t(W.smooth_target_field(w.xy, seed=3))
+    xy = _t(w.xy).requires_grad_(which == "xy")
+    g = _t(w.gamma).requires_grad_(which == "gamma")
+    tree = (fmm_mod.Tree(xy, w.depth, w.root_box) if kind == "uniform"
+            else fmm_mod.ATree(xy, 16, 6, w.root_box))
+    uv = fmm_mod.velocity(xy, g, w.sigma, w.depth, w.p, "fp64", tree=tree)
+    loss = 0.5 * ((uv - ustar) ** 2).sum()
+    loss.backward()
+    dl = (uv - ustar).detach().cpu().numpy()
+    if kind == "uniform":
+        dg_ref, dx_ref, ds_ref = oracle_mod.fmm_grad_full(w.xy, w.gamma, w.sigma, w.depth, w.p, dl, w.root_box)
+    else:
+        dg_ref, dx_ref, ds_ref = oracle_mod.afmm_grad(w.xy, w.gamma, w.sigma, 16, 6, w.p, dl, w.root_box)
+    if which == "gamma":
+        assert xy.grad is None
+        assert rel_l2(g.grad.cpu().numpy(), dg_ref) < 1e-9
+    else:
+        assert g.grad is None
+        assert rel_l2(xy.grad.cpu().numpy(), dx_ref + ds_ref) < 1e-9
+    tree.close()

@@ -131,9 +131,13 @@ def test_patches_mixed_full_size(fmm_mod, oracle_mod):
     ref = oracle_mod.fmm_velocity(w.xy, w.gamma, w.sigma, w.depth, w.p, None, targets=w.xy[idx])
     e_mixed = rel_l2(mixed, ref)
     e_fp64 = rel_l2(fp64, ref)
-    print(f"patches 2^24: mixed rel-L2 {e_mixed:.3e}, fp64 rel-L2 {e_fp64:.3e}")
-    assert e_mixed < MIXED_TOL
-    assert e_fp64 < FP64_TOL
+    # per particle: the largest error against the largest velocity of the sample
+    m_mixed = float(np.linalg.norm(mixed - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+    m_fp64 = float(np.linalg.norm(fp64 - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+    print(f"patches 2^24: mixed rel-L2 {e_mixed:.3e} (max {m_mixed:.3e}), fp64 rel-L2 {e_fp64:.3e} "
+          f"(max {m_fp64:.3e})")
+    assert e_mixed < MIXED_TOL and m_mixed < MIXED_TOL
+    assert e_fp64 < FP64_TOL and m_fp64 < FP64_TOL
 
 
 def test_output_permutation_above_cache_size(fmm_mod):
@@ -178,26 +182,6 @@ def test_deterministic_and_schedule_independent(fmm_mod):
         c = _run(fmm_mod, w, precision, tree=tree)
         tree.set_option(1, 0)
         assert np.array_equal(a, b) and np.array_equal(a, c)
-
-
-def test_persistent_near_grid_and_far_cap(fmm_mod):
-    """FMM_OPT_NEAR_WAVES (persistent near-field grid fed by a work counter) and
-    FMM_OPT_FAR_WAVES (capped far-field grids) change only which wavefront does which
-    work: every output bit matches the default launch, forward and adjoint."""
-    w = W.uniform_lamb_oseen(n=70000, seed=21, depth=6, p=12)
-    tree = fmm_mod.Tree(_t(w.xy), w.depth, w.root_box)
-    dl = np.random.Generator(np.random.PCG64(2)).standard_normal((w.n, 2))
-    for precision in ("fp64", "mixed"):
-        ref = _run(fmm_mod, w, precision, tree=tree)
-        gref = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl))
-        for near, far in ((64, 0), (1024, 96), (1, 8), (0, 32)):
-            tree.set_option(4, near)
-            tree.set_option(5, far)
-            assert np.array_equal(_run(fmm_mod, w, precision, tree=tree), ref), (precision, near, far)
-            g = tree.velocity_backward(_t(w.gamma), w.sigma, w.p, precision, _t(dl))
-            assert all(np.array_equal(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(g, gref))
-        tree.set_option(4, 0)
-        tree.set_option(5, 0)
 
 
 @pytest.mark.parametrize("lc", [1, 2, 3, 6])
@@ -249,4 +233,9 @@ def test_errors(fmm_mod):
     for bad in [dict(sigma=0.0, p=4), dict(sigma=0.1, p=0), dict(sigma=0.1, p=33), dict(sigma=math.inf, p=4)]:
         with pytest.raises(_lib.FmmError) as e:
             tree.velocity(g, bad["sigma"], bad["p"], "fp64")
+        assert e.value.status == _lib.FMM_EINVAL
+    # withdrawn option keys (persistent near-field grid, far-field grid cap), unknown keys
+    for key, value in ((4, 64), (5, 32), (99, 0), (_lib.FMM_OPT_VALIDATE, 2)):
+        with pytest.raises(_lib.FmmError) as e:
+            tree.set_option(key, value)
         assert e.value.status == _lib.FMM_EINVAL
