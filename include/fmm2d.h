@@ -134,6 +134,17 @@ int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *ro
 int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, const double *root_box, void *stream,
                      fmm_tree **out);
 
+/* Let `tree` use the evaluation workspace of `from` (its own is freed) until either is
+ * destroyed or rebuilt; the memory is freed with the last tree using it.  For trees that
+ * are evaluated one after the other, such as the two trees of each step of a
+ * time-stepping adjoint (the positions and the midpoint of the step), this halves the
+ * memory of the workspace (the per-particle arrays and the expansions).  A call on either
+ * tree first clears the multipoles when the other tree made the previous call.  Calls on
+ * the two trees must be ordered on the device (the same main stream).  FMM_EINVAL unless
+ * both have the same n, depth and device; FMM_ESTATE for a NULL or busy handle.
+ * Synchronises the device. */
+int fmm_share_workspace(fmm_tree *tree, fmm_tree *from);
+
 /* Host-side facts about a tree (any pointer may be NULL):
  *   n, depth, root_box[3] (host);
  *   p2p_pairs       ordered near-field pairs sum_T n_T sum_{S in N(T)} n_S - n, the pair
@@ -177,7 +188,7 @@ int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p,
 
 /*
  * Adjoint of fmm_velocity for a loss L(u): given dL/du (device, (n, 2) FP64, user
- * order) returns
+ * order) returns (each output device memory in user order, written in full)
  *   dl_dgamma  device, n FP64:  dL/dGamma_j = -Im((A q)_j)/(2 pi), q_i = dL/du_i + i dL/dv_i,
  *              where A is the FMM operator (W = u - iv = A c, c_j = -i Gamma_j/(2 pi)),
  *              exactly antisymmetric for square truncation, so A^T q = -A q is one
@@ -190,14 +201,51 @@ int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p,
  *              the evaluation points held fixed: near part minus the pair derivatives
  *              seen from the sources (own blob included, with the opposite sign), far part
  *              -Re(c_j Phi'_j), Im(c_j Phi'_j), Phi' the derivative of the q-field's local
- *              expansion.  A particle moving as a whole (source and evaluation point, its
- *              leaf unchanged) has dL/dx = dl_dxeval + dl_dxsrc.
+ *              expansion;
+ *   dl_dxy     device, (n, 2) FP64: dl_dxeval + dl_dxsrc, the derivative for particles
+ *              moving as a whole (source and evaluation point, the tree's cells held fixed).
  * Any output may be NULL to skip it.  Other arguments as fmm_velocity.  The paper has no
  * backward pass; this is the transpose of the discrete operator defined by stages 4-10.
  */
 int fmm_velocity_backward(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
                           const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
-                          double *dl_dxeval, double *dl_dxsrc);
+                          double *dl_dxeval, double *dl_dxsrc, double *dl_dxy);
+
+/*
+ * One explicit stage of the particle transport of section "Test problem" (the particles
+ * move with the velocity they induce, dx/dt = u, circulations carried unchanged):
+ *   x_out = x_base + h u,   u = the velocity of every particle of the tree (stages 4-10),
+ * written in user order by the last kernel of the call; x_base (device, (n, 2) FP64, user
+ * order) may be the tree's own positions or any other array, and x_out may equal x_base.
+ * Midpoint RK2 is two calls: x_half = x + (dt/2) u(x) over a tree of x, then
+ * x_next = x + dt u(x_half) over a tree of x_half.  Other arguments as fmm_velocity;
+ * FMM_EINVAL for a NULL array or a non-finite h.
+ */
+int fmm_transport_step(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
+                       void *main_stream, void *side_stream, const double *x_base, double h, double *x_out);
+
+/* Flags of fmm_transport_vjp. */
+enum {
+    FMM_ACC_GAMMA = 1, /* dl_dgamma is added to instead of written */
+    FMM_ACC_X = 2,     /* dl_dx is added to instead of written */
+    FMM_IDENTITY = 4   /* dl_dx includes lam itself: the stage's x_base is the tree's positions */
+};
+
+/*
+ * Adjoint of fmm_transport_step with respect to the tree's particles: given
+ * lam = dL/dx_out (device, (n, 2) FP64, user order),
+ *   dl_dgamma  (n)     h dL/dGamma through u (as fmm_velocity_backward with dL/du = h lam);
+ *   dl_dx      (n, 2)  h (dl_dxeval + dl_dxsrc) for dL/du = h lam, plus lam with
+ *                      FMM_IDENTITY (the derivative through x_base = x);
+ * each written, or added to with FMM_ACC_GAMMA / FMM_ACC_X (a NULL output is skipped).
+ * The backward step of midpoint RK2 from per-step checkpoints is two calls with no other
+ * arithmetic: lam_half = vjp(tree of x_half, lam, h = dt, flags FMM_ACC_GAMMA) and
+ * lam = vjp(tree of x, lam_half, h = dt/2, flags FMM_ACC_GAMMA | FMM_ACC_X | FMM_IDENTITY),
+ * since x_next = x + dt u(x_half) and x_half = x + (dt/2) u(x).  FMM_EINVAL for a NULL lam,
+ * a non-finite h or an unknown flag; other arguments as fmm_velocity.
+ */
+int fmm_transport_vjp(fmm_tree *tree, const double *gamma, double sigma, int p, int precision, const double *lam,
+                      double h, int flags, void *main_stream, void *side_stream, double *dl_dgamma, double *dl_dx);
 
 /* The near-field plan (stage 9) in force (any pointer may be NULL):
  *   mutual_items  wavefront items of the mutual form (0 when it is off or finds no

@@ -103,6 +103,10 @@ int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, const double
 int fmm_atree_set_option(fmm_atree *tree, int key, int64_t value);
 
 /* Host: sizes[FMM_AT_COUNT] (see the enum), root_box[3] (may be NULL). */
+/* As fmm_share_workspace (fmm2d.h) for two adaptive trees of the same n on one device
+ * (their cell counts may differ: the expansion arrays grow to the larger). */
+int fmm_atree_share_workspace(fmm_atree *tree, fmm_atree *from);
+
 int fmm_atree_info(const fmm_atree *tree, int64_t *sizes, double *root_box);
 
 /* Host arrays of n entries, user order: level, ix and iy of each particle's leaf
@@ -128,9 +132,10 @@ int fmm_atree_velocity_parts(fmm_atree *tree, const double *gamma, double sigma,
  * FP64, user order) returns, each optional (NULL skips it; all NULL is a no-op):
  *   dl_dgamma  device, n:      dL/dGamma;
  *   dl_dxeval  device, (n, 2): dL/dx with the particles moving as evaluation points only;
- *   dl_dxsrc   device, (n, 2): dL/dx with the particles moving as sources only.
- * A particle moving as a whole has gradient dl_dxeval + dl_dxsrc (the tree held fixed:
- * the derivative of the discrete method away from cell boundaries).  As for the uniform
+ *   dl_dxsrc   device, (n, 2): dL/dx with the particles moving as sources only;
+ *   dl_dxy     device, (n, 2): dl_dxeval + dl_dxsrc, the gradient of a particle moving as a
+ *              whole (the tree held fixed: the derivative of the discrete method away from
+ *              cell boundaries).  As for the uniform
  * tree (fmm_velocity_backward), the adaptive operator is antisymmetric (odd near kernel
  * over symmetric U lists, M2L over symmetric V lists, M2P over W the transpose of P2L over
  * X), so the circulation gradient is one more evaluation with the complex charges
@@ -140,7 +145,20 @@ int fmm_atree_velocity_parts(fmm_atree *tree, const double *gamma, double sigma,
  * work list (synchronising main_stream). */
 int fmm_atree_velocity_backward(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
                                 const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
-                                double *dl_dxeval, double *dl_dxsrc);
+                                double *dl_dxeval, double *dl_dxsrc, double *dl_dxy);
+
+/* One explicit stage of the particle transport (section "Test problem", dx/dt = u) over
+ * the adaptive tree: x_out = x_base + h u, as fmm_transport_step (fmm2d.h) does for the
+ * uniform tree; arguments and errors as there. */
+int fmm_atree_transport_step(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
+                             void *main_stream, void *side_stream, const double *x_base, double h, double *x_out);
+
+/* Adjoint of fmm_atree_transport_step with respect to the tree's particles, with the
+ * flags FMM_ACC_GAMMA, FMM_ACC_X and FMM_IDENTITY of fmm2d.h, as fmm_transport_vjp does
+ * for the uniform tree. */
+int fmm_atree_transport_vjp(fmm_atree *tree, const double *gamma, double sigma, int p, int precision,
+                            const double *lam, double h, int flags, void *main_stream, void *side_stream,
+                            double *dl_dgamma, double *dl_dx);
 
 /* Frees the tree and its device memory (after the device work using it is done);
  * NULL is ignored. */

@@ -12,6 +12,7 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ERANGE, FMM_ESTATE = 0, -1, -2,
 FMM_FP64, FMM_MIXED = 0, 1
 FMM_OPT_SCHEDULE, FMM_OPT_COARSE_LEVEL, FMM_OPT_TIMING = 1, 2, 3
 FMM_OPT_NEAR_MUTUAL, FMM_OPT_DENSE_LEAF, FMM_OPT_NEAR_OCCUPANCY, FMM_OPT_VALIDATE = 6, 7, 8, 9
+FMM_ACC_GAMMA, FMM_ACC_X, FMM_IDENTITY = 1, 2, 4
 FMM_T_PACK, FMM_T_FAR, FMM_T_P2P, FMM_T_FINAL, FMM_T_TOTAL, FMM_T_COUNT = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_EINVAL", -2: "FMM_ENOMEM", -3: "FMM_EDEVICE", -4: "FMM_ERANGE",
                 -5: "FMM_ESTATE"}
@@ -26,11 +27,14 @@ SIGNATURES = {
     "fmm_build_tree_host": (_I, [_P, _I64, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_rebuild_tree": (_I, [_P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     "fmm_tree_info": (_I, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "fmm_share_workspace": (_I, [_P, _P]),
     "fmm_tree_permutation": (_I, [_P, _P, _P, _P]),
     "fmm_tree_levels": (_I, [_P, _P, _I]),
     "fmm_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
-    "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
+    "fmm_transport_step": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _D, _P]),
+    "fmm_transport_vjp": (_I, [_P, _P, _D, _I, _I, _P, _D, _I, _P, _P, _P, _P]),
     "fmm_set_option": (_I, [_P, _I, _I64]),
     "fmm_get_timings": (_I, [_P, _P, _P]),
     "fmm_get_timeline": (_I, [_P, _P, _I]),
@@ -41,8 +45,11 @@ SIGNATURES = {
     "fmm_atree_build": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_atree_build_host": (_I, [_P, _I64, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fmm_atree_rebuild": (_I, [_P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
-    "fmm_atree_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "fmm_atree_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
+    "fmm_atree_transport_step": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _D, _P]),
+    "fmm_atree_transport_vjp": (_I, [_P, _P, _D, _I, _I, _P, _D, _I, _P, _P, _P, _P]),
     "fmm_atree_info": (_I, [_P, _P, _P]),
+    "fmm_atree_share_workspace": (_I, [_P, _P]),
     "fmm_atree_leaves": (_I, [_P, _P, _P, _P]),
     "fmm_atree_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_atree_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),

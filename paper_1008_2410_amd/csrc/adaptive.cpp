@@ -58,7 +58,7 @@ void free_atree(fmm_atree *t)
         else
             hipFree(p);
     }
-    free_ws(t->ws);
+    if (t->wsp.use_count() == 1) free_ws(*t->wsp);
     if (t->d_flag) hipFree(t->d_flag);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
@@ -214,7 +214,7 @@ struct Busy {
 
 int ensure_ws(fmm_atree *t, int p, int precision)
 {
-    AtreeWs &w = t->ws;
+    AtreeWs &w = *t->wsp;
     const size_t n = (size_t)t->n;
     const size_t coef = (size_t)t->ncells * p + kCoefPad;
     int rc;
@@ -270,7 +270,7 @@ int ensure_ws(fmm_atree *t, int p, int precision)
 // source-position sums only when asked for.
 int ensure_ws_backward(fmm_atree *t, bool src)
 {
-    AtreeWs &w = t->ws;
+    AtreeWs &w = *t->wsp;
     const size_t n = (size_t)t->n;
     int rc = FMM_OK;
     // each group is allocated whole or not at all (a failed call leaves none of it)
@@ -349,7 +349,7 @@ int choose_occupancy(const fmm_atree *t, int precision, bool concurrent)
 }
 
 int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, void *main_stream, void *side_stream,
-        double *uv, double *uv_near, double *uv_far)
+        double *uv, double *uv_near, double *uv_far, const double *base = nullptr, double h = 0.0)
 {
     clear_last_error();
     if (t && !uv && !(uv_near && uv_far)) return fail(FMM_EINVAL, "output is NULL");
@@ -371,19 +371,21 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     HIP_TRY(hipEventRecord(t->ev_join, ss));
     launch_atree_near(c, ms);  // P2P over U, beside the far field
     HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
-    launch_atree_finalize(c, uv, uv_near, uv_far, ms);  // L2P + M2P + sum
+    launch_atree_finalize(c, uv, uv_near, uv_far, base, h, ms);  // L2P + M2P + sum
     HIP_TRY(hipGetLastError());
     return FMM_OK;
 }
 
+// The adjoint for the cotangent scale * dl_duv, written as `out` says (see AdjointOut).
 int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int precision, const double *dl_duv,
-                 void *main_stream, void *side_stream, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc)
+                 double scale, void *main_stream, void *side_stream, const AdjointOut &out)
 {
-    clear_last_error();
     int rc = check_eval(t, gamma, sigma, p, precision);
     if (rc) return rc;
     if (!dl_duv) return fail(FMM_EINVAL, "dl_duv is NULL");
-    if (!dl_dgamma && !dl_dxeval && !dl_dxsrc) return FMM_OK;
+    if (!std::isfinite(scale)) return fail(FMM_EINVAL, "the cotangent scale must be finite");
+    if (!out.dg && !out.dxe && !out.dxs && !out.dxy) return FMM_OK;
+    const bool src = out.dxs || out.dxy;
     Busy guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
@@ -394,18 +396,18 @@ int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int pre
         std::string err;
         if ((rc = build_atree_adjoint_units(t, ms, err))) return fail(rc, err);
     }
-    if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, dl_dxsrc != nullptr))) return rc;
+    if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, src))) return rc;
     const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision)};
     launch_atree_pack(c, gamma, ms);
-    launch_atree_pack_adjoint(c, dl_duv, ms);
+    launch_atree_pack_adjoint(c, dl_duv, scale, ms);
     HIP_TRY(hipEventRecord(t->ev_fork, ms));
     HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     launch_atree_far(c, ss, false);  // the charges c: derivative W' at the particles
     launch_atree_far(c, ss, true);   // the charges q: the transpose pass
     HIP_TRY(hipEventRecord(t->ev_join, ss));
-    launch_atree_backward_near(c, dl_dxsrc != nullptr, ms);
+    launch_atree_backward_near(c, src, ms);
     HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
-    launch_atree_finalize_backward(c, dl_dgamma, dl_dxeval, dl_dxsrc, ms);
+    launch_atree_finalize_backward(c, out, ms);
     HIP_TRY(hipGetLastError());
     return FMM_OK;
 }
@@ -493,7 +495,7 @@ extern "C" int fmm_atree_rebuild(fmm_atree *prev, const double *xy, int64_t n, c
         free_atree(t);
         return hip_fail(e, "hipDeviceSynchronize");
     }
-    std::swap(t->ws, prev->ws);
+    std::swap(t->wsp, prev->wsp);
     t->near_occupancy = prev->near_occupancy;
     t->validate = prev->validate;
     guard.release();
@@ -766,6 +768,25 @@ extern "C" int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, i
     return FMM_OK;
 }
 
+extern "C" int fmm_atree_share_workspace(fmm_atree *t, fmm_atree *from)
+{
+    clear_last_error();
+    if (!t || !from) return fail(FMM_ESTATE, "null tree handle");
+    if (t == from) return FMM_OK;
+    if (t->n != from->n || t->device != from->device)
+        return fail(FMM_EINVAL, "trees sharing a workspace need the same n and device");
+    Busy g1(t);
+    if (!g1.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    Busy g2(from);
+    if (!g2.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    if (t->wsp == from->wsp) return FMM_OK;
+    HIP_TRY(hipSetDevice(t->device));
+    HIP_TRY(hipDeviceSynchronize());  // t's earlier calls may still use its workspace
+    if (t->wsp.use_count() == 1) free_ws(*t->wsp);
+    t->wsp = from->wsp;
+    return FMM_OK;
+}
+
 extern "C" int fmm_atree_info(const fmm_atree *t, int64_t *sizes, double *root_box)
 {
     clear_last_error();
@@ -826,10 +847,41 @@ extern "C" int fmm_atree_velocity_parts(fmm_atree *t, const double *gamma, doubl
 
 extern "C" int fmm_atree_velocity_backward(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
                                            const double *dl_duv, void *main_stream, void *side_stream,
-                                           double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc)
+                                           double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, double *dl_dxy)
 {
-    return run_backward(t, gamma, sigma, p, precision, dl_duv, main_stream, side_stream, dl_dgamma, dl_dxeval,
-                        dl_dxsrc);
+    clear_last_error();
+    AdjointOut out;
+    out.dg = dl_dgamma;
+    out.dxe = dl_dxeval;
+    out.dxs = dl_dxsrc;
+    out.dxy = dl_dxy;
+    return run_backward(t, gamma, sigma, p, precision, dl_duv, 1.0, main_stream, side_stream, out);
+}
+
+extern "C" int fmm_atree_transport_step(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
+                                        void *main_stream, void *side_stream, const double *x_base, double h,
+                                        double *x_out)
+{
+    clear_last_error();
+    if (!x_base || !x_out) return fail(FMM_EINVAL, "x_base / x_out is NULL");
+    if (!std::isfinite(h)) return fail(FMM_EINVAL, "h must be finite");
+    return run(t, gamma, sigma, p, precision, main_stream, side_stream, x_out, nullptr, nullptr, x_base, h);
+}
+
+extern "C" int fmm_atree_transport_vjp(fmm_atree *t, const double *gamma, double sigma, int p, int precision,
+                                       const double *lam, double h, int flags, void *main_stream, void *side_stream,
+                                       double *dl_dgamma, double *dl_dx)
+{
+    clear_last_error();
+    if (flags & ~(FMM_ACC_GAMMA | FMM_ACC_X | FMM_IDENTITY)) return fail(FMM_EINVAL, "unknown flag");
+    if (!lam) return fail(FMM_EINVAL, "lam is NULL");
+    AdjointOut out;
+    out.dg = dl_dgamma;
+    out.dxy = dl_dx;
+    out.lam = (flags & FMM_IDENTITY) ? lam : nullptr;
+    out.acc_g = (flags & FMM_ACC_GAMMA) != 0;
+    out.acc_xy = (flags & FMM_ACC_X) != 0;
+    return run_backward(t, gamma, sigma, p, precision, lam, h, main_stream, side_stream, out);
 }
 
 extern "C" int fmm_atree_set_option(fmm_atree *t, int key, int64_t value)

@@ -429,13 +429,13 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
 // Adjoint charges in sorted order, FP64 and in the records' precision.
 template <typename T>
 __global__ __launch_bounds__(256) void at_pack_adjoint_kernel(int n, const int *__restrict__ perm,
-                                                               const double *__restrict__ dl_duv,
+                                                               const double *__restrict__ dl_duv, double scale,
                                                                double2 *__restrict__ adj, c2<T> *__restrict__ qt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t o = perm[i];
-    const double2 q = make_double2(dl_duv[2 * o], dl_duv[2 * o + 1]);
+    const double2 q = make_double2(scale * dl_duv[2 * o], scale * dl_duv[2 * o + 1]);
     adj[i] = q;
     qt[i] = mk<T>((T)q.x, (T)q.y);
 }
@@ -585,8 +585,7 @@ __global__ __launch_bounds__(256) void at_finalize_backward_kernel(
     const double2 *__restrict__ mp, const double2 *__restrict__ lo, const double2 *__restrict__ mp2,
     const double2 *__restrict__ lo2, int p, double x0, double y0, double side, const double4 *__restrict__ near_pa,
     const double *__restrict__ near_b, const double4 *__restrict__ near_src, const double2 *__restrict__ adj,
-    const double *__restrict__ gamma, double alpha, double lambda, double *__restrict__ dl_dgamma,
-    double *__restrict__ dl_dxeval, double *__restrict__ dl_dxsrc)
+    const double *__restrict__ gamma, double alpha, double lambda, AdjointOut out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -603,13 +602,14 @@ __global__ __launch_bounds__(256) void at_finalize_backward_kernel(
     const double ka = alpha * alpha * kInv2Pi;
     const double Ar = ka * (-2.0 * a.w), Ai = -ka * a.z;
     const double Bi = -ka * lambda * sb;
-    if (dl_dgamma) dl_dgamma[o] = -(alpha * a.y + phi.y) * kInv2Pi;
-    if (dl_dxeval) {
+    const double g = -(alpha * a.y + phi.y) * kInv2Pi;
+    double ex = 0.0, ey = 0.0, sx = 0.0, sy = 0.0;
+    if (out.dxe || out.dxy) {
         const double2 q = adj[i];
         const double d1r = Ar + dw.x, d1i = Ai + Bi + dw.y;
         const double d2r = Ar + dw.x, d2i = Ai - Bi + dw.y;
-        dl_dxeval[2 * o] = q.x * d1r - q.y * d1i;
-        dl_dxeval[2 * o + 1] = -(q.x * d2i + q.y * d2r);
+        ex = q.x * d1r - q.y * d1i;
+        ey = -(q.x * d2i + q.y * d2r);
     }
     if constexpr (SRC) {
         const double4 ns = near_src[i];
@@ -617,9 +617,10 @@ __global__ __launch_bounds__(256) void at_finalize_backward_kernel(
         const double atr = a2 * ns.x + dphi.x, ati = a2 * ns.y + dphi.y;
         const double btr = a2 * lambda * ns.z, bti = a2 * lambda * ns.w;
         const double G = gamma[i] * kInv2Pi;  // c = -i G: Re(c w) = G Im w, Im(c w) = -G Re w
-        dl_dxsrc[2 * o] = -G * (ati + bti);
-        dl_dxsrc[2 * o + 1] = -G * (atr - btr);
+        sx = -G * (ati + bti);
+        sy = -G * (atr - btr);
     }
+    store_adjoint(out, o, g, ex, ey, sx, sy);
 }
 
 inline unsigned blocks(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
@@ -633,11 +634,11 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s)
     if (c.is_double)
         at_pack_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, gamma,
                                                               t->x0, t->y0, t->side, c.alpha,
-                                                              (double4 *)t->ws.rec, t->ws.gamma);
+                                                              (double4 *)t->wsp->rec, t->wsp->gamma);
     else
         at_pack_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, gamma,
-                                                             t->x0, t->y0, t->side, c.alpha, (float4 *)t->ws.rec,
-                                                             t->ws.gamma);
+                                                             t->x0, t->y0, t->side, c.alpha, (float4 *)t->wsp->rec,
+                                                             t->wsp->gamma);
 }
 
 template <bool CPLX>
@@ -647,23 +648,23 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
     const int deepest = (int)t->sizes[6];
     if (deepest < 2) return;
     const int p = c.p, nb = 2 * p + 1;
-    const double2 *q = t->ws.adj;
+    const double2 *q = t->wsp->adj;
     if (t->np2m > 0) {
         // 16 lanes per leaf, four leaves per wavefront
         const int np = (int)t->np2m;
         const unsigned g = (unsigned)((np + 3) / 4);
         if (p <= 16)
             at_p2m_kernel<16, CPLX, 16><<<g, 64, 0, s>>>(t->d.p2m_cells, np, t->d.cell, t->d.range, t->d.xy,
-                                                         t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
+                                                         t->wsp->gamma, q, t->x0, t->y0, t->side, p, mp);
         else
             at_p2m_kernel<32, CPLX, 16><<<g, 64, 0, s>>>(t->d.p2m_cells, np, t->d.cell, t->d.range, t->d.xy,
-                                                         t->ws.gamma, q, t->x0, t->y0, t->side, p, mp);
+                                                         t->wsp->gamma, q, t->x0, t->y0, t->side, p, mp);
     }
     for (int l = deepest - 1; l >= 2; --l) {
         const int cnt = t->inner_off[l + 1] - t->inner_off[l];
         if (cnt == 0) continue;
         at_m2m_kernel<<<blocks((int64_t)cnt * p, 256), 256, 0, s>>>(t->d.inner + t->inner_off[l], cnt, t->d.child,
-                                                                    t->ws.binom, nb, p, mp);
+                                                                    t->wsp->binom, nb, p, mp);
     }
     // M2L + P2L for every cell of level >= 2 at once, then L2L level by level
     const int first = t->level_off[2], cnt = t->level_off[deepest + 1] - first;
@@ -671,18 +672,18 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
         if (p <= 16)
             at_m2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
                                                                    t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,
-                                                                   t->ws.gamma, q, t->x0, t->y0, t->side,
-                                                                   t->ws.binom16, p, mp, lo);
+                                                                   t->wsp->gamma, q, t->x0, t->y0, t->side,
+                                                                   t->wsp->binom16, p, mp, lo);
         else
             at_m2l_kernel<32, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
                                                                    t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,
-                                                                   t->ws.gamma, q, t->x0, t->y0, t->side,
-                                                                   t->ws.binom32, p, mp, lo);
+                                                                   t->wsp->gamma, q, t->x0, t->y0, t->side,
+                                                                   t->wsp->binom32, p, mp, lo);
     }
     for (int l = 3; l <= deepest; ++l) {
         const int f = t->level_off[l], nc = t->level_off[l + 1] - f;
         if (nc == 0) continue;
-        at_l2l_kernel<<<blocks((int64_t)nc * p, 256), 256, 0, s>>>(f, nc, t->d.cell, t->d.parent, t->ws.binom, nb, p,
+        at_l2l_kernel<<<blocks((int64_t)nc * p, 256), 256, 0, s>>>(f, nc, t->d.cell, t->d.parent, t->wsp->binom, nb, p,
                                                                    lo);
     }
 }
@@ -690,9 +691,9 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
 void launch_atree_far(const AtreeCall &c, hipStream_t s, bool adjoint)
 {
     if (adjoint)
-        far_chain<true>(c, c.t->ws.mp2, c.t->ws.lo2, s);
+        far_chain<true>(c, c.t->wsp->mp2, c.t->wsp->lo2, s);
     else
-        far_chain<false>(c, c.t->ws.mp, c.t->ws.lo, s);
+        far_chain<false>(c, c.t->wsp->mp, c.t->wsp->lo, s);
 }
 
 void launch_atree_near(const AtreeCall &c, hipStream_t s)
@@ -712,47 +713,48 @@ void launch_atree_near(const AtreeCall &c, hipStream_t s)
     if (c.is_double)
         at_near_kernel<double><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
-            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const double4 *)t->ws.rec, t->x0, t->y0, t->side,
-            c.alpha, cut, scale, t->dense_leaf, t->n, t->ws.near, (double2 *)t->ws.slots);
+            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const double4 *)t->wsp->rec, t->x0, t->y0, t->side,
+            c.alpha, cut, scale, t->dense_leaf, t->n, t->wsp->near, (double2 *)t->wsp->slots);
     else
         at_near_kernel<float><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
-            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const float4 *)t->ws.rec, t->x0, t->y0, t->side,
-            c.alpha, cut, scale, t->dense_leaf, t->n, t->ws.near, (float2 *)t->ws.slots);
+            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const float4 *)t->wsp->rec, t->x0, t->y0, t->side,
+            c.alpha, cut, scale, t->dense_leaf, t->n, t->wsp->near, (float2 *)t->wsp->slots);
 }
 
-void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, hipStream_t s)
+void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, const double *base,
+                           double h, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
     const double scale = c.alpha * kInv2Pi;
     // uv alone: the totals go to the records (free once the near field and the far chain
     // are done; n double2 or more) in sorted order, then to user order
-    double2 *staged = uv && !uv_near && !uv_far ? (double2 *)t->ws.rec : nullptr;
+    double2 *staged = uv && !uv_near && !uv_far ? (double2 *)t->wsp->rec : nullptr;
     double *uv_direct = staged ? nullptr : uv;
     if (c.is_double)
         at_finalize_kernel<double><<<blocks(n, 256), 256, 0, s>>>(
-            n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->ws.mp, t->ws.lo, c.p, t->x0,
-            t->y0, t->side, t->ws.near, t->d.mask, (const double2 *)t->ws.slots, scale, uv_direct, uv_near, uv_far,
+            n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->wsp->mp, t->wsp->lo, c.p, t->x0,
+            t->y0, t->side, t->wsp->near, t->d.mask, (const double2 *)t->wsp->slots, scale, uv_direct, uv_near, uv_far,
             staged);
     else
         at_finalize_kernel<float><<<blocks(n, 256), 256, 0, s>>>(
-            n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->ws.mp, t->ws.lo, c.p, t->x0,
-            t->y0, t->side, t->ws.near, t->d.mask, (const float2 *)t->ws.slots, scale, uv_direct, uv_near, uv_far,
+            n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->wsp->mp, t->wsp->lo, c.p, t->x0,
+            t->y0, t->side, t->wsp->near, t->d.mask, (const float2 *)t->wsp->slots, scale, uv_direct, uv_near, uv_far,
             staged);
-    if (staged) scatter_rows_kernel<<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, staged, uv);
+    if (staged) scatter_rows_kernel<<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, staged, uv, base, h);
 }
 
-void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, hipStream_t s)
+void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, double scale, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
     if (c.is_double)
-        at_pack_adjoint_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, t->ws.adj,
-                                                                      (double2 *)t->ws.qt);
+        at_pack_adjoint_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, scale, t->wsp->adj,
+                                                                      (double2 *)t->wsp->qt);
     else
-        at_pack_adjoint_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, t->ws.adj,
-                                                                     (float2 *)t->ws.qt);
+        at_pack_adjoint_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, scale, t->wsp->adj,
+                                                                     (float2 *)t->wsp->qt);
 }
 
 void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)
@@ -762,7 +764,7 @@ void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)
     const double cut = c.is_double ? 39.0 : 27.0;  // as for the forward near field
     const unsigned g = (unsigned)t->nbwd_units;
     const AtreeDev &d = t->d;
-    const AtreeWs &w = t->ws;
+    const AtreeWs &w = *t->wsp;
     if (c.is_double) {
         auto k = src ? at_backward_kernel<double, true> : at_backward_kernel<double, false>;
         k<<<g, 64, 0, s>>>(d.bwd_units, d.cell, d.range, d.u_off, d.u_idx, d.tile_start, d.tile_box,
@@ -776,18 +778,17 @@ void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)
     }
 }
 
-void launch_atree_finalize_backward(const AtreeCall &c, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc,
-                                    hipStream_t s)
+void launch_atree_finalize_backward(const AtreeCall &c, const AdjointOut &out, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
     const double lambda = c.is_double ? 1.0 : 0.69314718055994530942;
     const AtreeDev &d = t->d;
-    const AtreeWs &w = t->ws;
-    auto k = dl_dxsrc ? at_finalize_backward_kernel<true> : at_finalize_backward_kernel<false>;
+    const AtreeWs &w = *t->wsp;
+    auto k = (out.dxs || out.dxy) ? at_finalize_backward_kernel<true> : at_finalize_backward_kernel<false>;
     k<<<blocks(n, 256), 256, 0, s>>>(n, d.perm, d.leaf_of, d.cell, d.xy, d.w_off, d.w_idx, w.mp, w.lo, w.mp2, w.lo2,
                                      c.p, t->x0, t->y0, t->side, w.pa, w.pb, w.psrc, w.adj, w.gamma, c.alpha, lambda,
-                                     dl_dgamma, dl_dxeval, dl_dxsrc);
+                                     out);
 }
 
 }  // namespace fmm

@@ -5,9 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <cstdint>
 #include <string>
 #include <vector>
+
+#include "fmm_internal.h"
 
 namespace fmm {
 
@@ -116,7 +119,7 @@ struct fmm_atree {
     std::vector<int> inner_off;   // max_depth + 2 entries, into AtreeDev::inner
     bool pooled = false;  // device arrays from the stream-ordered pool (the device build)
     fmm::AtreeDev d;
-    fmm::AtreeWs ws;
+    std::shared_ptr<fmm::AtreeWs> wsp = std::make_shared<fmm::AtreeWs>();  // shared by fmm_atree_share_workspace
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::atomic<int> busy{0};
@@ -147,11 +150,12 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
 // adjoint false: the far field of the charges c (mp, lo); true: of the adjoint charges
 // q (mp2, lo2)
 void launch_atree_far(const AtreeCall &c, hipStream_t s, bool adjoint = false);
-void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, hipStream_t s);
+void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, double scale, hipStream_t s);
 void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s);
-void launch_atree_finalize_backward(const AtreeCall &c, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc,
-                                    hipStream_t s);
+void launch_atree_finalize_backward(const AtreeCall &c, const AdjointOut &out, hipStream_t s);
 void launch_atree_near(const AtreeCall &c, hipStream_t s);
-void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, hipStream_t s);
+// uv alone goes through the records as staging; with base, uv = base + h u
+void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, double *uv_far, const double *base,
+                           double h, hipStream_t s);
 
 }  // namespace fmm

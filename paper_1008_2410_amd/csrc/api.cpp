@@ -63,7 +63,7 @@ void free_tree(fmm_tree *t)
     release(t->d_near_work, true);
     release(t->d_leaf_mask, true);
     hipFree(t->d_flag);
-    free_workspace(t->ws, fs);
+    if (t->wsp.use_count() == 1) free_workspace(*t->wsp, fs);
     if (t->own_side) hipStreamDestroy(t->own_side);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
@@ -80,9 +80,27 @@ int effective_lc(const fmm_tree *t) { return std::min(t->lc, t->depth); }
 // Last FP64 level: every level in FP64 precision; in mixed precision the coarse levels.
 int split_level(const fmm_tree *t, int precision) { return precision == FMM_FP64 ? t->depth : effective_lc(t); }
 
+// A workspace last used by another tree (a rebuild's hand-over, or a tree sharing it):
+// multipoles of cells that are empty in this tree must read as zero (the M2L kernels
+// read them unconditionally), so the multipole arrays are cleared.  Locals and
+// per-particle arrays are written in full by every call before they are read.
+int clear_multipoles(const fmm_tree *t, hipStream_t s)
+{
+    const Workspace &ws = *t->wsp;
+    if (!ws.rec || t->depth < 2) return FMM_OK;
+    const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
+    const int64_t cells_f = level_base(t->depth + 1) - cells_d;
+    const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
+    for (double2 *m : {ws.mp_d, ws.mp2_d})
+        if (m) HIP_TRY(hipMemsetAsync(m, 0, bd, s));
+    for (float2 *m : {ws.mp_f, ws.mp2_f})
+        if (m && cells_f > 0) HIP_TRY(hipMemsetAsync(m, 0, bf, s));
+    return FMM_OK;
+}
+
 int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream_t s)
 {
-    Workspace &ws = t->ws;
+    Workspace &ws = *t->wsp;
     const int split = split_level(t, precision);
     const int L = t->depth;
     if (ws.p != p || ws.precision != precision || ws.split != split) {
@@ -116,6 +134,7 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
         ws.p = p;
         ws.precision = precision;
         ws.split = split;
+        ws.owner = t->serial;  // zeroed just now
     }
     if (backward && !ws.bwd_src && (rc = dev_alloc_async(&ws.bwd_src, n, "adjoint source-position sums", s))) return rc;
     if (backward && !ws.bwd_stage && n * (int64_t)sizeof(double2) > kLastLevelCacheBytes &&
@@ -138,6 +157,11 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
                 HIP_TRY(hipMemsetAsync(ws.lo2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
             }
         }
+    }
+    if (ws.owner != t->serial) {
+        int rc2 = clear_multipoles(t, s);
+        if (rc2) return rc2;
+        ws.owner = t->serial;
     }
     return FMM_OK;
 }
@@ -171,7 +195,7 @@ int validate_inputs(fmm_tree *t, const double *gamma, const double *dl_duv, hipS
 
 FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
 {
-    const Workspace &ws = t->ws;
+    const Workspace &ws = *t->wsp;
     FarArgs a{};
     a.t = t;
     a.p = p;
@@ -231,7 +255,8 @@ struct Timing {
 };
 
 int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int precision, void *main_stream,
-                void *side_stream, double *uv, double *uv_near, double *uv_far)
+                void *side_stream, double *uv, double *uv_near, double *uv_far, const double *base = nullptr,
+                double h = 0.0)
 {
     int rc = check_eval_args(t, gamma, sigma, p, precision);
     if (rc) return rc;
@@ -243,8 +268,8 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     std::string err;
     if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
     if ((rc = ensure_workspace(t, p, precision, false, (hipStream_t)main_stream))) return rc;
-    if (use_mutual(t) && !t->ws.slots &&
-        (rc = dev_alloc_async((char **)&t->ws.slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
+    if (use_mutual(t) && !t->wsp->slots &&
+        (rc = dev_alloc_async((char **)&t->wsp->slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
                               "mutual near-field slots", (hipStream_t)main_stream)))
         return rc;
 
@@ -264,21 +289,21 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
-    launch_pack(t, alpha, is_double, t->ws.rec, ms);
+    launch_pack(t, alpha, is_double, t->wsp->rec, ms);
     tm.mark(1, ms);
     tm.mark(2, ss);
     launch_far_chain(a, ss);
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
-    void *slots = use_mutual(t) ? t->ws.slots : nullptr;
+    void *slots = use_mutual(t) ? t->wsp->slots : nullptr;
     t->occupancy_in_use = choose_occupancy(t, precision);
     tm.mark(4, ms);
-    launch_p2p_forward(t, t->ws.rec, is_double, alpha, t->ws.near, slots, ms);
+    launch_p2p_forward(t, t->wsp->rec, is_double, alpha, t->wsp->near, slots, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
     // the records are free once the near field and the far chain are done: staging for uv
-    launch_finalize(t, a, t->ws.near, slots, is_double, alpha, uv, uv_near, uv_far, t->ws.rec, ms);
+    launch_finalize(t, a, t->wsp->near, slots, is_double, alpha, uv, uv_near, uv_far, t->wsp->rec, base, h, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);
@@ -307,6 +332,8 @@ int new_tree(const double *xy, int64_t n, int depth, const double *root_box, fmm
     if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
     retain_pool(dev);
     t = new fmm_tree();
+    static std::atomic<uint64_t> next_serial{1};
+    t->serial = next_serial.fetch_add(1);
     t->device = dev;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
@@ -372,24 +399,6 @@ int build_device(const double *xy, int64_t n, int depth, const double *root_box,
     return FMM_OK;
 }
 
-// A workspace handed to a tree over other particles: multipoles of cells that are empty
-// in the new tree must read as zero (the M2L kernels read them unconditionally), so the
-// multipole arrays are cleared.  Locals and per-particle arrays are written in full by
-// every call before they are read.
-int clear_multipoles(const fmm_tree *t, hipStream_t s)
-{
-    const Workspace &ws = t->ws;
-    if (!ws.rec || t->depth < 2) return FMM_OK;
-    const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
-    const int64_t cells_f = level_base(t->depth + 1) - cells_d;
-    const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
-    for (double2 *m : {ws.mp_d, ws.mp2_d})
-        if (m) HIP_TRY(hipMemsetAsync(m, 0, bd, s));
-    for (float2 *m : {ws.mp_f, ws.mp2_f})
-        if (m && cells_f > 0) HIP_TRY(hipMemsetAsync(m, 0, bf, s));
-    return FMM_OK;
-}
-
 }  // namespace
 
 extern "C" int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
@@ -418,12 +427,8 @@ extern "C" int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, con
         free_tree(t);
         return hip_fail(e, "hipDeviceSynchronize");
     }
-    std::swap(t->ws, prev->ws);
-    if ((rc = clear_multipoles(t, (hipStream_t)stream))) {
-        std::swap(t->ws, prev->ws);
-        free_tree(t);
-        return rc;
-    }
+    std::swap(t->wsp, prev->wsp);
+    t->wsp->owner = kForeignOwner;  // cleared by the next call
     guard.release();
     free_tree(prev);
     *out = t;
@@ -672,6 +677,25 @@ extern "C" int fmm_build_tree_host(const double *xy, int64_t n, int depth, const
     return FMM_OK;
 }
 
+extern "C" int fmm_share_workspace(fmm_tree *t, fmm_tree *from)
+{
+    g_last_error.clear();
+    if (!t || !from) return fail(FMM_ESTATE, "null tree handle");
+    if (t == from) return FMM_OK;
+    if (t->n != from->n || t->depth != from->depth || t->device != from->device)
+        return fail(FMM_EINVAL, "trees sharing a workspace need the same n, depth and device");
+    BusyGuard g1(t);
+    if (!g1.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    BusyGuard g2(from);
+    if (!g2.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    if (t->wsp == from->wsp) return FMM_OK;
+    HIP_TRY(hipSetDevice(t->device));
+    HIP_TRY(hipDeviceSynchronize());  // t's earlier calls may still use its workspace
+    if (t->wsp.use_count() == 1) free_workspace(*t->wsp, t->own_side);
+    t->wsp = from->wsp;
+    return FMM_OK;
+}
+
 extern "C" int fmm_tree_info(const fmm_tree *t, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
                              int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf)
 {
@@ -736,23 +760,27 @@ extern "C" int fmm_velocity_parts(fmm_tree *t, const double *gamma, double sigma
     return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, nullptr, uv_near, uv_far);
 }
 
-extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
-                                     const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
-                                     double *dl_dxeval, double *dl_dxsrc)
+namespace {
+
+// The adjoint of stages 4-10 for the cotangent scale * cot (user order), written as `out`
+// says (see AdjointOut).
+int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int precision, const double *cot,
+                 double scale, void *main_stream, void *side_stream, const AdjointOut &out)
 {
-    g_last_error.clear();
     int rc = check_eval_args(t, gamma, sigma, p, precision);
     if (rc) return rc;
-    if (!dl_duv) return fail(FMM_EINVAL, "dl_duv is NULL");
-    if (!dl_dgamma && !dl_dxeval && !dl_dxsrc) return FMM_OK;
+    if (!cot) return fail(FMM_EINVAL, "dl_duv is NULL");
+    if (!std::isfinite(scale)) return fail(FMM_EINVAL, "the cotangent scale must be finite");
+    if (!out.dg && !out.dxe && !out.dxs && !out.dxy) return FMM_OK;
     BusyGuard guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
-    if ((rc = validate_inputs(t, gamma, dl_duv, (hipStream_t)main_stream))) return rc;
+    if ((rc = validate_inputs(t, gamma, cot, (hipStream_t)main_stream))) return rc;
     std::string err;
     if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
     if ((rc = ensure_workspace(t, p, precision, true, (hipStream_t)main_stream))) return rc;
-    Workspace &ws = t->ws;
+    Workspace &ws = *t->wsp;
+    const bool need_src = out.dxs || out.dxy;
 
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
@@ -768,7 +796,7 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     tm.mark(0, ms);
     launch_stage_in(t, gamma, ms);
     launch_pack(t, alpha, is_double, ws.rec, ms);
-    launch_pack_adjoint(t, dl_duv, ws.adj, ws.rec2, is_double, ms);
+    launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ms);
     tm.mark(1, ms);
     if (overlap) {
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
@@ -781,16 +809,56 @@ extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double si
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
     launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
-                        ws.bwd_b, dl_dxsrc ? ws.bwd_src : nullptr, ms);
+                        ws.bwd_b, need_src ? ws.bwd_src : nullptr, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, dl_dgamma,
-                             dl_dxeval, dl_dxsrc, ws.bwd_stage, ms);
+    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, out,
+                             ws.bwd_stage, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);
     return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" int fmm_velocity_backward(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                     const double *dl_duv, void *main_stream, void *side_stream, double *dl_dgamma,
+                                     double *dl_dxeval, double *dl_dxsrc, double *dl_dxy)
+{
+    g_last_error.clear();
+    AdjointOut out;
+    out.dg = dl_dgamma;
+    out.dxe = dl_dxeval;
+    out.dxs = dl_dxsrc;
+    out.dxy = dl_dxy;
+    return run_backward(t, gamma, sigma, p, precision, dl_duv, 1.0, main_stream, side_stream, out);
+}
+
+extern "C" int fmm_transport_step(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                  void *main_stream, void *side_stream, const double *x_base, double h, double *x_out)
+{
+    g_last_error.clear();
+    if (!x_base || !x_out) return fail(FMM_EINVAL, "x_base / x_out is NULL");
+    if (!std::isfinite(h)) return fail(FMM_EINVAL, "h must be finite");
+    return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, x_out, nullptr, nullptr, x_base, h);
+}
+
+extern "C" int fmm_transport_vjp(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                 const double *lam, double h, int flags, void *main_stream, void *side_stream,
+                                 double *dl_dgamma, double *dl_dx)
+{
+    g_last_error.clear();
+    if (flags & ~(FMM_ACC_GAMMA | FMM_ACC_X | FMM_IDENTITY)) return fail(FMM_EINVAL, "unknown flag");
+    if (!lam) return fail(FMM_EINVAL, "lam is NULL");
+    AdjointOut out;
+    out.dg = dl_dgamma;
+    out.dxy = dl_dx;
+    out.lam = (flags & FMM_IDENTITY) ? lam : nullptr;
+    out.acc_g = (flags & FMM_ACC_GAMMA) != 0;
+    out.acc_xy = (flags & FMM_ACC_X) != 0;
+    return run_backward(t, gamma, sigma, p, precision, lam, h, main_stream, side_stream, out);
 }
 
 extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)

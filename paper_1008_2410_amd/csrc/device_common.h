@@ -524,6 +524,19 @@ __device__ __forceinline__ c2<T> horner_weighted_prefetch(const c2<T> *__restric
     return acc;
 }
 
+// A velocity row of user row o: the velocity itself, or with a base (the transport
+// update of section "Test problem", dx/dt = u, one explicit stage) base + h u.
+__device__ __forceinline__ void store_velocity(double *__restrict__ uv, int64_t o, double2 v,
+                                               const double *__restrict__ base, double h)
+{
+    if (base) {
+        v.x = fma(h, v.x, base[2 * o]);
+        v.y = fma(h, v.y, base[2 * o + 1]);
+    }
+    uv[2 * o] = v.x;
+    uv[2 * o + 1] = v.y;
+}
+
 // Second half of a staged finalize: (u, v) of sorted particle i, written in sorted order
 // by the finalize kernel, to row perm[i] of the user-order output.  Reading the slot sums
 // and writing rows in random order in one kernel took longer (840 us for 2^24 particles)
@@ -531,15 +544,40 @@ __device__ __forceinline__ c2<T> horner_weighted_prefetch(const c2<T> *__restric
 namespace {
 __global__ __launch_bounds__(256) void scatter_rows_kernel(int n, const int *__restrict__ perm,
                                                            const double2 *__restrict__ staged,
-                                                           double *__restrict__ uv)
+                                                           double *__restrict__ uv, const double *__restrict__ base,
+                                                           double h)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t o = perm[i];
-    const double2 v = staged[i];
-    uv[2 * o] = v.x;
-    uv[2 * o + 1] = v.y;
+    store_velocity(uv, perm[i], staged[i], base, h);
 }
 }  // namespace
+
+__device__ __forceinline__ void store_adjoint(const AdjointOut &a, int64_t o, double g, double ex, double ey, double sx,
+                                              double sy)
+{
+    if (a.dg) a.dg[o] = a.acc_g ? a.dg[o] + g : g;
+    if (a.dxe) {
+        a.dxe[2 * o] = ex;
+        a.dxe[2 * o + 1] = ey;
+    }
+    if (a.dxs) {
+        a.dxs[2 * o] = sx;
+        a.dxs[2 * o + 1] = sy;
+    }
+    if (a.dxy) {
+        double vx = ex + sx, vy = ey + sy;
+        if (a.lam) {
+            vx += a.lam[2 * o];
+            vy += a.lam[2 * o + 1];
+        }
+        if (a.acc_xy) {
+            vx += a.dxy[2 * o];
+            vy += a.dxy[2 * o + 1];
+        }
+        a.dxy[2 * o] = vx;
+        a.dxy[2 * o + 1] = vy;
+    }
+}
 
 }  // namespace fmm

@@ -6,6 +6,7 @@
 
 #include <array>
 #include <atomic>
+#include <memory>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -84,11 +85,18 @@ constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;  // MI355X Infinity
 // Flag (in w) of a mutual item in the near-field work list.
 constexpr int kMutualItem = 256;
 
+// Owner value of a workspace handed to a tree over other particles (clear before use).
+constexpr uint64_t kForeignOwner = ~uint64_t(0);
+
 // Coefficient storage for one (p, precision, split) configuration.  Levels 0..split
 // are FP64, levels split+1..L are FP32; each level holds 4^l cells x p coefficients,
 // multipoles (scaled a_m / w^m) and locals (scaled b_l w^(l+1)) in separate arrays.
 struct Workspace {
     int p = 0, precision = -1, split = -1;
+    // serial number of the tree whose call last wrote the multipoles (0: none yet, or
+    // unknown after a hand-over): another tree must clear them first, since each call
+    // writes only the cells that are non-empty in its own tree
+    uint64_t owner = 0;
     void *rec = nullptr;          // per-particle P2P records (float4 or double4), n
     double2 *near = nullptr;      // near-field (u, v) per sorted particle, n
     double2 *mp_d = nullptr, *lo_d = nullptr;  // FP64 levels
@@ -160,11 +168,25 @@ struct fmm_tree {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     const fmm::Tables *tabs = nullptr;  // shared, never freed by the tree
-    fmm::Workspace ws;
+    // evaluation workspace, shared by the trees of fmm_share_workspace (freed with the last)
+    std::shared_ptr<fmm::Workspace> wsp = std::make_shared<fmm::Workspace>();
+    uint64_t serial = 0;  // unique per tree of the process
     std::vector<std::array<hipEvent_t, fmm::kNumEvents>> pending_timing;
 };
 
 namespace fmm {
+
+// Outputs of an adjoint call, in user order (device pointers, each may be null):
+//   dg   dL/dGamma, added to the array when acc_g (else written);
+//   dxe  dL/dx at the evaluation points, dxs dL/dx of the sources (written);
+//   dxy  their sum, the derivative for particles moving as both, plus lam (when given: the
+//        identity part of a transport stage x + h u(x)), added to the array when acc_xy.
+// The cotangent is scaled before the sums, so every part but lam carries that scale.
+struct AdjointOut {
+    double *dg = nullptr, *dxe = nullptr, *dxs = nullptr, *dxy = nullptr;
+    const double *lam = nullptr;
+    int acc_g = 0, acc_xy = 0;
+};
 
 // Launch parameters shared by the forward and backward far-field chains.
 struct FarArgs {
@@ -194,17 +216,19 @@ void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipS
 void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
                         hipStream_t s);
 void launch_far_chain(const FarArgs &a, hipStream_t s);
+// uv alone is written through `stage` (a buffer of n double2); with base, uv = base + h u.
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
-                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, hipStream_t s);
+                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, const double *base,
+                     double h, hipStream_t s);
 
 // Backward
-void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double,
+void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, double2 *adj, void *qt, int is_double,
                          hipStream_t s);
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
                          double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
-                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, double *stage, hipStream_t s);
+                              double alpha, const AdjointOut &out, double *stage, hipStream_t s);
 
 // Lowest index k of the n groups of `stride` doubles at a (device) that holds a NaN or an
 // infinity, or -1 in bad; flag is a device int of the caller.  Synchronises s.

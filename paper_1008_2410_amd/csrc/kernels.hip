@@ -796,13 +796,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
 // (537 MB) the scatter alone took 1.12 ms, and the windows save 0.3 ms per evaluation.
 __global__ __launch_bounds__(256) void gather_rows_kernel(int n, int nxcd, const int *__restrict__ gpos1,
                                                           const double2 *__restrict__ staged,
-                                                          double *__restrict__ uv)
+                                                          double *__restrict__ uv, const double *__restrict__ base,
+                                                          double h)
 {
     const int u = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (u >= n) return;
-    const double2 v = staged[gpos1[u]];
-    uv[2 * (int64_t)u] = v.x;
-    uv[2 * (int64_t)u + 1] = v.y;
+    store_velocity(uv, u, staged[gpos1[u]], base, h);
 }
 
 inline unsigned blocks_for(int64_t work, int per_block) { return (unsigned)((work + per_block - 1) / per_block); }
@@ -974,13 +973,13 @@ void m2l_launch(const FarArgs &a, int l, const c2<T> *m2l_tab, const c2<TPar> *l
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void pack_adjoint_kernel(int n, const int *__restrict__ perm,
-                                                            const double *__restrict__ dl_duv,
+                                                            const double *__restrict__ dl_duv, double scale,
                                                             double2 *__restrict__ adj, c2<T> *__restrict__ qt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t o = perm[i];
-    const double2 q = make_double2(dl_duv[2 * o], dl_duv[2 * o + 1]);
+    const double2 q = make_double2(scale * dl_duv[2 * o], scale * dl_duv[2 * o + 1]);
     adj[i] = q;
     if (qt) qt[i] = mk<T>((T)q.x, (T)q.y);
 }
@@ -1080,10 +1079,10 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
     int n, const int *__restrict__ perm, const int *__restrict__ leaf_of, const double2 *__restrict__ xy,
     const double4 *__restrict__ near_pa, const double *__restrict__ near_b, const double2 *__restrict__ adj,
     const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, int p, int has_far, double x0, double y0,
-    double w, double alpha, double lambda, double *__restrict__ dl_dgamma, double *__restrict__ dl_dxeval,
-    const double4 *__restrict__ near_src, const int *__restrict__ gpos2, const double *__restrict__ gamma_st,
-    double *__restrict__ dl_dxsrc, double *__restrict__ stage, int nxcd)
+    double w, double alpha, double lambda, AdjointOut out, const double4 *__restrict__ near_src,
+    const int *__restrict__ gpos2, const double *__restrict__ gamma_st, double *__restrict__ stage, int nxcd)
 {
+    const bool need_x = out.dxe || out.dxy, need_s = out.dxs || out.dxy;
     const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     // the user row, or with stage the staging slot inside the window of the sorted bucket
@@ -1111,57 +1110,61 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
             const c2<TL> accd = horner_weighted_prefetch<TL>(bc, p, xi, 1, 0);
             dwr = (double)accd.x / (w * w);
             dwi = (double)accd.y / (w * w);
-            if (near_src) {
+            if (need_s) {
                 const c2<TL> accp = horner_weighted_prefetch<TL>(bq, p, xi, 1, 0);
                 dpr = (double)accp.x / (w * w);
                 dpi = (double)accp.y / (w * w);
             }
         }
     }
-    double *out_g = stage ? stage : dl_dgamma;
-    double *out_x = stage ? stage + n : dl_dxeval;
-    double *out_s = stage ? stage + 3 * (int64_t)n : dl_dxsrc;
-    if (dl_dgamma) out_g[o] = -phi * kInv2Pi;
-    if (dl_dxeval) {
+    const double g = -phi * kInv2Pi;
+    double ex = 0.0, ey = 0.0, sx = 0.0, sy = 0.0;
+    if (need_x) {
         const double2 q = adj[i];
         // D1 = A + B + W', D2 = A - B + W'  (B purely imaginary)
         const double d1r = Ar + dwr, d1i = Ai + Bi + dwi;
         const double d2r = Ar + dwr, d2i = Ai - Bi + dwi;
-        out_x[2 * o] = q.x * d1r - q.y * d1i;
-        out_x[2 * o + 1] = -(q.x * d2i + q.y * d2r);
+        ex = q.x * d1r - q.y * d1i;
+        ey = -(q.x * d2i + q.y * d2r);
     }
-    if (near_src) {
+    if (need_s) {
         const double4 ns = near_src[i];
         const double a2 = alpha * alpha;
         const double atr = a2 * ns.x + dpr, ati = a2 * ns.y + dpi;
         const double btr = a2 * lambda * ns.z, bti = a2 * lambda * ns.w;
         const double G = gamma_st[gpos2[i]] * kInv2Pi;  // c = -i G: Re(c w) = G Im w, Im(c w) = -G Re w
-        out_s[2 * o] = -G * (ati + bti);
-        out_s[2 * o + 1] = -G * (atr - btr);
+        sx = -G * (ati + bti);
+        sy = -G * (atr - btr);
     }
+    if (stage) {  // by staging slot: dL/dGamma (n), evaluation part (2n), source part (2n)
+        if (out.dg) stage[o] = g;
+        if (need_x) {
+            stage[n + 2 * o] = ex;
+            stage[n + 2 * o + 1] = ey;
+        }
+        if (need_s) {
+            stage[3 * (int64_t)n + 2 * o] = sx;
+            stage[3 * (int64_t)n + 2 * o + 1] = sy;
+        }
+        return;
+    }
+    store_adjoint(out, o, g, ex, ey, sx, sy);
 }
 
 // The adjoint outputs from their staging slots (written by finalize_backward_kernel for n
 // above the last-level cache) to user order, as gather_rows_kernel does for velocities.
 __global__ __launch_bounds__(256) void gather_adjoint_kernel(int n, int nxcd, const int *__restrict__ gpos1,
-                                                             const double *__restrict__ stage,
-                                                             double *__restrict__ dl_dgamma,
-                                                             double *__restrict__ dl_dxeval,
-                                                             double *__restrict__ dl_dxsrc)
+                                                             const double *__restrict__ stage, AdjointOut out)
 {
     const int u = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const int64_t k = gpos1[u];
-    const int64_t o = u;
-    if (dl_dgamma) dl_dgamma[o] = stage[k];
-    if (dl_dxeval) {
-        dl_dxeval[2 * o] = stage[n + 2 * k];
-        dl_dxeval[2 * o + 1] = stage[n + 2 * k + 1];
-    }
-    if (dl_dxsrc) {
-        dl_dxsrc[2 * o] = stage[3 * (int64_t)n + 2 * k];
-        dl_dxsrc[2 * o + 1] = stage[3 * (int64_t)n + 2 * k + 1];
-    }
+    const bool need_x = out.dxe || out.dxy, need_s = out.dxs || out.dxy;
+    const double g = out.dg ? stage[k] : 0.0;
+    const double ex = need_x ? stage[n + 2 * k] : 0.0, ey = need_x ? stage[n + 2 * k + 1] : 0.0;
+    const double sx = need_s ? stage[3 * (int64_t)n + 2 * k] : 0.0;
+    const double sy = need_s ? stage[3 * (int64_t)n + 2 * k + 1] : 0.0;
+    store_adjoint(out, u, g, ex, ey, sx, sy);
 }
 
 // Input check (FMM_OPT_VALIDATE): the lowest particle index whose `stride` values hold a
@@ -1344,7 +1347,8 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
 }
 
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
-                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, hipStream_t s)
+                     double alpha, double *uv, double *uv_near, double *uv_far, void *stage, const double *base,
+                     double h, hipStream_t s)
 {
     // uv alone: the totals go to stage (n double2), then out in user order; through the
     // staging windows once the output outgrows the last-level cache
@@ -1379,16 +1383,18 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
                                                             (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
                                                             t->y0, w, uv_direct, uv_near, uv_far, staged, windowed ? t->d_gpos2 : nullptr, kXcds);
     }
-    if (staged && windowed) gather_rows_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, staged, uv);
-    else if (staged) scatter_rows_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, staged, uv);
+    if (staged && windowed) gather_rows_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, staged, uv, base, h);
+    else if (staged) scatter_rows_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, staged, uv, base, h);
 }
-void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double2 *adj, void *qt, int is_double, hipStream_t s)
+void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, double2 *adj, void *qt, int is_double,
+                         hipStream_t s)
 {
     const int n = (int)t->n;
     if (is_double)
-        pack_adjoint_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, adj, nullptr);
+        pack_adjoint_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, scale, adj, nullptr);
     else
-        pack_adjoint_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, adj, (float2 *)qt);
+        pack_adjoint_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, scale, adj,
+                                                                       (float2 *)qt);
 }
 
 void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
@@ -1427,8 +1433,7 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
 
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
-                              double alpha, double *dl_dgamma, double *dl_dxeval, double *dl_dxsrc, double *stage,
-                              hipStream_t s)
+                              double alpha, const AdjointOut &out, double *stage, hipStream_t s)
 {
     const int L = t->depth;
     const int n = (int)t->n;
@@ -1440,14 +1445,13 @@ void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArg
         finalize_backward_kernel<double><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj,
             has_far ? level_ptr<double>(fc, L, true) : nullptr, has_far ? level_ptr<double>(fq, L, true) : nullptr,
-            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval, dl_dxsrc ? near_src : nullptr,
-            t->d_gpos2, t->d_st1, dl_dxsrc, stage, kXcds);
+            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2, t->d_st1, stage, kXcds);
     else
         finalize_backward_kernel<float><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj, level_ptr<float>(fc, L, true),
-            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, dl_dgamma, dl_dxeval,
-            dl_dxsrc ? near_src : nullptr, t->d_gpos2, t->d_st1, dl_dxsrc, stage, kXcds);
-    if (stage) gather_adjoint_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, stage, dl_dgamma, dl_dxeval, dl_dxsrc);
+            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2,
+            t->d_st1, stage, kXcds);
+    if (stage) gather_adjoint_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, stage, out);
 }
 
 

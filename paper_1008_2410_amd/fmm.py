@@ -59,7 +59,75 @@ def _precision(precision) -> int:
     return int(precision)
 
 
-class Tree:
+class _Adjoint:
+    """Adjoint and transport calls shared by Tree and ATree (the C entry points differ only
+    by the prefix fmm_ / fmm_atree_)."""
+
+    _prefix = "fmm_"
+
+    def _abi(self, name: str):
+        return getattr(L.load(), self._prefix + name)
+
+    def share_workspace(self, other) -> None:
+        """Use the evaluation workspace of `other` (a tree of the same kind, n and depth)
+        from now on; for trees evaluated one after the other."""
+        if type(other) is not type(self):
+            raise ValueError("both trees must be of the same kind")
+        with torch.cuda.device(self.device):
+            L.check(self._abi("share_workspace")(self.handle, other.handle), self._prefix + "share_workspace")
+
+    def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
+                          need_gamma: bool = True, need_x: bool = True, need_src: bool = False,
+                          need_xy: bool = False):
+        """Adjoint of velocity for a loss with gradient dl_duv: (dL/dGamma (n,) or None,
+        dL/dx_eval (n, 2) or None), then dL/dx_src (n, 2) with need_src, then with need_xy
+        dL/dx_eval + dL/dx_src (n, 2), the gradient of particles moving as a whole, summed by
+        the library."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
+
+        def new(flag, shape):
+            return torch.empty(shape, dtype=torch.float64, device=self.device) if flag else None
+
+        dg, dx = new(need_gamma, (self.n,)), new(need_x, (self.n, 2))
+        ds, dxy = new(need_src, (self.n, 2)), new(need_xy, (self.n, 2))
+        with torch.cuda.device(self.device):
+            L.check(self._abi("velocity_backward")(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                                   _ptr(d), _stream_ptr(), None, _ptr(dg), _ptr(dx), _ptr(ds),
+                                                   _ptr(dxy)), self._prefix + "velocity_backward")
+        return (dg, dx) + ((ds,) if need_src else ()) + ((dxy,) if need_xy else ())
+
+    def transport_step(self, gamma: torch.Tensor, sigma: float, p: int, precision, x_base: torch.Tensor, h: float,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """x_base + h u, u the velocity of the tree's particles (one explicit transport stage)."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        xb = _as_device_f64(x_base, "x_base", (self.n, 2), self.device)
+        xo = _check_out(out, self.n, self.device) if out is not None else torch.empty_like(xb)
+        with torch.cuda.device(self.device):
+            L.check(self._abi("transport_step")(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                                _stream_ptr(), None, _ptr(xb), float(h), _ptr(xo)),
+                    self._prefix + "transport_step")
+        return xo
+
+    def transport_vjp(self, gamma: torch.Tensor, sigma: float, p: int, precision, lam: torch.Tensor, h: float,
+                      flags: int, dl_dgamma: torch.Tensor | None, dl_dx: torch.Tensor | None):
+        """Adjoint of transport_step with respect to the tree's particles (fmm_transport_vjp):
+        writes, or with the FMM_ACC_* flags adds to, dl_dgamma (n,) and dl_dx (n, 2) in place."""
+        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
+        lm = _as_device_f64(lam, "lam", (self.n, 2), self.device)
+        if dl_dgamma is not None:
+            if dl_dgamma.dtype != torch.float64 or tuple(dl_dgamma.shape) != (self.n,) or \
+                    dl_dgamma.device != self.device or not dl_dgamma.is_contiguous():
+                raise ValueError("dl_dgamma must be a contiguous float64 (n,) tensor on the tree's device")
+        if dl_dx is not None:
+            _check_out(dl_dx, self.n, self.device)
+        with torch.cuda.device(self.device):
+            L.check(self._abi("transport_vjp")(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
+                                               _ptr(lm), float(h), int(flags), _stream_ptr(), None, _ptr(dl_dgamma),
+                                               _ptr(dl_dx)), self._prefix + "transport_vjp")
+
+
+class Tree(_Adjoint):
     """Uniform quadtree over n particles (stages 1-3): Morton-sorted particles, leaf
     offsets, per-level occupancy and near-field work units, resident on the device.
     builder: "device" (the GPU build) or "host" (the reference build; same tree)."""
@@ -193,28 +261,15 @@ class Tree:
                                                 _stream_ptr(), None, _ptr(near), _ptr(far)), "fmm_velocity_parts")
         return near, far
 
-    def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
-                          need_gamma: bool = True, need_x: bool = True, need_src: bool = False):
-        """(dL/dGamma (n,) or None, dL/dx_eval (n, 2) or None) for a loss with gradient dl_duv;
-        with need_src a third entry, dL/dx_src (n, 2), the derivative with respect to the source
-        positions.  A particle moving as a whole has dL/dx = dL/dx_eval + dL/dx_src."""
-        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
-        d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
-        dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if need_gamma else None
-        dx = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_x else None
-        ds = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_src else None
-        with torch.cuda.device(self.device):
-            L.check(L.load().fmm_velocity_backward(self.handle, _ptr(g), float(sigma), int(p), _precision(precision),
-                                                   _ptr(d), _stream_ptr(), None, _ptr(dg), _ptr(dx), _ptr(ds)),
-                    "fmm_velocity_backward")
-        return (dg, dx, ds) if need_src else (dg, dx)
 
 
-class ATree:
+class ATree(_Adjoint):
     """Adaptive quadtree over n particles for uneven distributions (include/fmm2d_adaptive.h):
     cells split while they hold more than max_leaf particles, down to max_depth, and the
     U, V, W, X lists of the adaptive FMM, resident on the device.
     builder: "device" (the GPU build) or "host" (the reference build; same tree)."""
+
+    _prefix = "fmm_atree_"
 
     def __init__(self, xy: torch.Tensor, max_leaf: int, max_depth: int, root_box=None, stream=None,
                  builder: str = "device"):
@@ -313,20 +368,6 @@ class ATree:
                                                       _ptr(far)), "fmm_atree_velocity_parts")
         return near, far
 
-    def velocity_backward(self, gamma: torch.Tensor, sigma: float, p: int, precision, dl_duv: torch.Tensor,
-                          need_gamma: bool = True, need_x: bool = True, need_src: bool = False):
-        """As Tree.velocity_backward, for the adaptive tree (fmm_atree_velocity_backward):
-        (dL/dGamma, dL/dx_eval) and with need_src dL/dx_src."""
-        g = _as_device_f64(gamma, "gamma", (self.n,), self.device)
-        d = _as_device_f64(dl_duv, "dl_duv", (self.n, 2), self.device)
-        dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if need_gamma else None
-        dx = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_x else None
-        ds = torch.empty((self.n, 2), dtype=torch.float64, device=self.device) if need_src else None
-        with torch.cuda.device(self.device):
-            L.check(L.load().fmm_atree_velocity_backward(self.handle, _ptr(g), float(sigma), int(p),
-                                                         _precision(precision), _ptr(d), _stream_ptr(), None,
-                                                         _ptr(dg), _ptr(dx), _ptr(ds)), "fmm_atree_velocity_backward")
-        return (dg, dx, ds) if need_src else (dg, dx)
 
 
 class VelocityFn(torch.autograd.Function):
@@ -350,9 +391,8 @@ class VelocityFn(torch.autograd.Function):
         if not (need_x or need_g):
             return None, None, None, None, None, None
         res = ctx.tree.velocity_backward(gamma.detach(), ctx.sigma, ctx.p, ctx.precision, grad_uv.contiguous(),
-                                         need_gamma=need_g, need_x=need_x, need_src=need_x)
-        dg, dx = res[0], res[1]
-        return (dx + res[2] if need_x else None), dg, None, None, None, None
+                                         need_gamma=need_g, need_x=False, need_xy=need_x)
+        return (res[2] if need_x else None), res[0], None, None, None, None
 
 
 def velocity(xy: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, precision="mixed",

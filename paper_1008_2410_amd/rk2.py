@@ -12,20 +12,22 @@ workspace of the tree is kept from one rebuild to the next).  With adaptive=(max
 max_depth) every evaluation uses the adaptive tree (ATree, rebuilt on the device for the
 current positions the same way) instead of the uniform tree of the given depth.
 
-The gradient of a loss L(x_N) with respect to x_0 and Gamma is the discrete adjoint of
-those steps, run backwards with per-step checkpoints (only x_n is kept per step; the
-two velocities of step n are recomputed in its backward step):
+Each stage is one fmm_transport_step call (the velocity and the update x_base + h u in
+the library's kernels).  The gradient of a loss L(x_N) with respect to x_0 and Gamma is
+the discrete adjoint of those steps, run backwards with per-step checkpoints (only x_n is
+kept per step; the midpoint of step n is recomputed in its backward step):
 
-    mu      = dt lambda_{n+1}                  (cotangent of u(x_{n+1/2}))
-    lambda' = VJP_x u(x_{n+1/2}) [mu]           (every particle moving as source and target)
-    nu      = (dt/2) lambda'                    (cotangent of u(x_n))
-    lambda_n = lambda_{n+1} + lambda' + VJP_x u(x_n) [nu]
-    dL/dGamma += VJP_Gamma u(x_{n+1/2}) [mu] + VJP_Gamma u(x_n) [nu]
+    lambda_half = dt J_half^T lambda_{n+1}                 (x_{n+1} = x_n + dt u(x_half))
+    lambda_n    = lambda_{n+1} + lambda_half + (dt/2) J_n^T lambda_half
+                                                           (x_half = x_n + (dt/2) u(x_n))
+    dL/dGamma  += the Gamma parts of the same two products
 
-with each VJP one fmm_velocity_backward call (dL/dx_eval + dL/dx_src, dL/dGamma).
-Trees are treated as fixed within each evaluation (the leaf of a particle does not
-change under an infinitesimal move), which is the derivative of the discrete method
-away from leaf boundaries.
+with J the Jacobian of the velocities with respect to the particles moving as sources and
+evaluation points.  Each line is one fmm_transport_vjp call, the accumulation and the
+identity term done by the library (flags FMM_ACC_GAMMA, FMM_ACC_X, FMM_IDENTITY), so no
+arithmetic of the method runs outside it.  Trees are treated as fixed within each
+evaluation (the leaf of a particle does not change under an infinitesimal move), which is
+the derivative of the discrete method away from leaf boundaries.
 """
 from __future__ import annotations
 
@@ -63,20 +65,24 @@ def _tree_for(tree, xy, depth, root_box, adaptive):
     return ATree(xy, adaptive[0], adaptive[1], root_box) if adaptive is not None else Tree(xy, depth, root_box)
 
 
-def _velocity(tree, xy, gamma, sigma, depth, p, precision, root_box, stats: RK2Stats, adaptive=None):
-    """u(xy) over `tree` rebuilt for xy (a new tree when it is None); returns (tree, u)."""
+def _rebuilt(tree, xy, depth, root_box, stats: RK2Stats, adaptive=None):
+    """`tree` rebuilt for xy (a new tree when it is None), timed as a tree build."""
     t0 = time.perf_counter()
     tree = _tree_for(tree, xy, depth, root_box, adaptive)
     torch.cuda.synchronize(xy.device)
-    t1 = time.perf_counter()
-    uv = tree.velocity(gamma, sigma, p, precision)
-    torch.cuda.synchronize(xy.device)
-    t2 = time.perf_counter()
-    stats.tree_build += t1 - t0
-    stats.velocity += t2 - t1
+    stats.tree_build += time.perf_counter() - t0
+    return tree
+
+
+def _stage(tree, x_base, h, gamma, sigma, p, precision, stats: RK2Stats):
+    """x_base + h u over `tree` (one fmm_transport_step), timed as a velocity evaluation."""
+    t0 = time.perf_counter()
+    out = tree.transport_step(gamma, sigma, p, precision, x_base, h)
+    torch.cuda.synchronize(x_base.device)
+    stats.velocity += time.perf_counter() - t0
     stats.evals += 1
-    _sample_memory(xy.device, stats)
-    return tree, uv
+    _sample_memory(x_base.device, stats)
+    return out
 
 
 def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int, p: int, dt: float, steps: int,
@@ -91,10 +97,10 @@ def rk2_forward(xy0: torch.Tensor, gamma: torch.Tensor, sigma: float, depth: int
     try:
         for _ in range(steps):
             checkpoints.append(x)
-            tree, u0 = _velocity(tree, x, g, sigma, depth, p, precision, root_box, stats, adaptive)
-            xm = x + (0.5 * dt) * u0
-            tree, um = _velocity(tree, xm, g, sigma, depth, p, precision, root_box, stats, adaptive)
-            x = x + dt * um
+            tree = _rebuilt(tree, x, depth, root_box, stats, adaptive)
+            xm = _stage(tree, x, 0.5 * dt, g, sigma, p, precision, stats)
+            tree = _rebuilt(tree, xm, depth, root_box, stats, adaptive)
+            x = _stage(tree, x, dt, g, sigma, p, precision, stats)
     finally:
         if tree is not None:
             tree.close()
@@ -105,33 +111,34 @@ def rk2_backward(checkpoints, gamma: torch.Tensor, sigma: float, depth: int, p: 
                  dl_dxN: torch.Tensor, precision="mixed", root_box=None, stats: RK2Stats | None = None,
                  adaptive=None):
     """Discrete adjoint of rk2_forward: (dL/dx_0, dL/dGamma) from dL/dx_N."""
+    from ._lib import FMM_ACC_GAMMA, FMM_ACC_X, FMM_IDENTITY
     stats = stats if stats is not None else RK2Stats()
     g = gamma.detach().contiguous()
-    lam = dl_dxN.detach().contiguous().clone()
-    dgamma = torch.zeros_like(g)
+    lam = dl_dxN.detach().contiguous().clone()   # lambda_n, updated in place by the library
+    lam_half = torch.empty_like(lam)
+    dgamma = torch.empty_like(g)
     tree0 = treem = None
     try:
-        for x in reversed(checkpoints):
+        for k, x in enumerate(reversed(checkpoints)):
             t0 = time.perf_counter()
-            tree0, u0 = _velocity(tree0, x, g, sigma, depth, p, precision, root_box, stats, adaptive)
-            xm = x + (0.5 * dt) * u0
-            treem, _ = _velocity(treem, xm, g, sigma, depth, p, precision, root_box, stats, adaptive)
+            tree0 = _rebuilt(tree0, x, depth, root_box, stats, adaptive)
+            xm = _stage(tree0, x, 0.5 * dt, g, sigma, p, precision, stats)
+            first = treem is None
+            treem = _rebuilt(treem, xm, depth, root_box, stats, adaptive)
+            if first:
+                treem.share_workspace(tree0)  # the two trees are used one after the other
             t1 = time.perf_counter()
-            mu = dt * lam
-            dgm, dxm, dsm = treem.velocity_backward(g, sigma, p, precision, mu, need_src=True)
+            acc_g = FMM_ACC_GAMMA if k > 0 else 0
+            treem.transport_vjp(g, sigma, p, precision, lam, dt, acc_g, dgamma, lam_half)
+            tree0.transport_vjp(g, sigma, p, precision, lam_half, 0.5 * dt, FMM_ACC_GAMMA | FMM_ACC_X | FMM_IDENTITY,
+                                dgamma, lam)
             torch.cuda.synchronize(x.device)
             _sample_memory(x.device, stats)
-            lam_mid = dxm + dsm
-            nu = (0.5 * dt) * lam_mid
-            dg0, dx0, ds0 = tree0.velocity_backward(g, sigma, p, precision, nu, need_src=True)
-            lam = lam + lam_mid + dx0 + ds0
-            dgamma += dgm + dg0
-            torch.cuda.synchronize(x.device)
             stats.backward += time.perf_counter() - t1
             stats.vjps += 2
             stats.per_step.append(time.perf_counter() - t0)
     finally:
-        for tr in (tree0, treem):
+        for tr in (treem, tree0):
             if tr is not None:
                 tr.close()
     return lam, dgamma
