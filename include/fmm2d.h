@@ -181,6 +181,27 @@ int fmm_tree_permutation(const fmm_tree *tree, int64_t *perm, int32_t *leaf, voi
 int fmm_velocity(fmm_tree *tree, const double *gamma, double sigma, int p, int precision, void *main_stream,
                  void *side_stream, double *uv);
 
+/*
+ * fmm_velocity for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same stages and kernels,
+ * the same results bit for bit, with every per-call array (records, near-field sums and
+ * slots, multipoles and locals of all levels) in the library's static device workspace of
+ * 128 MiB, a file-scope array each device holds from the library's first use until the
+ * process ends.  The call allocates nothing and creates no event: FMM_OPT_TIMING is not
+ * applied (FMM_OPT_VALIDATE is, and synchronises main_stream).
+ *   Preconditions: the tree (built by fmm_build_tree) and the expansion tables of p on the
+ *   device, which any earlier allocating evaluation with this p makes (FMM_ESTATE if not).
+ *   Size limit: an evaluation needs about n (104 bytes mixed, 192 bytes FP64 with the mutual
+ *   near field; 32 / 48 without it) + 22 p 4^depth (mixed) or 43 p 4^depth (FP64) bytes;
+ *   beyond 128 MiB the call returns FMM_EINVAL, naming both sizes, before any work.
+ *   Sharing: all calls of the process on one device use the same workspace; calls that
+ *   overlap on one device race and must be ordered (one stream, or synchronised), as
+ *   calls on one tree must be.  The multipoles are cleared by each call.
+ * Arguments as fmm_velocity.
+ */
+int fmm_velocity_noalloc(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,
+                         void *main_stream, void *side_stream, double *uv);
+
 /* As fmm_velocity, but the near field (stage 9) and far field (stage 8) velocities are
  * written separately, each (n, 2) FP64 in user order, so that each stage can be checked. */
 int fmm_velocity_parts(fmm_tree *tree, const double *gamma, double sigma, int p, int precision,

@@ -32,6 +32,7 @@ SIGNATURES = {
     "fmm_tree_levels": (_I, [_P, _P, _I]),
     "fmm_velocity": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_velocity_parts": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P]),
+    "fmm_velocity_noalloc": (_I, [_P, _P, _D, _I, _I, _P, _P, _P]),
     "fmm_velocity_backward": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
     "fmm_transport_step": (_I, [_P, _P, _D, _I, _I, _P, _P, _P, _D, _P]),
     "fmm_transport_vjp": (_I, [_P, _P, _D, _I, _I, _P, _D, _I, _P, _P, _P, _P]),

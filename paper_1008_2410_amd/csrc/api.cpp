@@ -193,9 +193,8 @@ int validate_inputs(fmm_tree *t, const double *gamma, const double *dl_duv, hipS
     return FMM_OK;
 }
 
-FarArgs far_args(const fmm_tree *t, int p, int precision, bool adjoint)
+FarArgs far_args(const fmm_tree *t, const Workspace &ws, int p, int precision, bool adjoint)
 {
-    const Workspace &ws = *t->wsp;
     FarArgs a{};
     a.t = t;
     a.p = p;
@@ -254,9 +253,51 @@ struct Timing {
     }
 };
 
+// The per-call arrays of an evaluation carved from the static workspace (no allocation):
+// records, near field, slots (mutual form), then the multipoles and locals of every level,
+// each 256-byte aligned.  FMM_EINVAL when they do not fit, naming both sizes.
+int static_ws(const fmm_tree *t, int p, int precision, Workspace &ws)
+{
+    char *base = nullptr;
+    const int e = static_workspace(t->device, &base);
+    if (e != 0) return hip_fail((hipError_t)e, "looking up the static workspace");
+    const int split = split_level(t, precision);
+    const int L = t->depth;
+    const int64_t n = t->n;
+    const int64_t cells_d = L >= 2 ? level_base(std::min(split, L) + 1) * p + kCoefPad : 0;
+    const int64_t cells_f = L >= 2 && level_base(L + 1) > level_base(std::min(split, L) + 1)
+                                ? (level_base(L + 1) - level_base(std::min(split, L) + 1)) * p + kCoefPad
+                                : 0;
+    const size_t rec = precision == FMM_FP64 ? sizeof(double4) : sizeof(float4);
+    const size_t slot = precision == FMM_FP64 ? sizeof(double2) : sizeof(float2);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return base + at;
+    };
+    ws = Workspace{};
+    ws.p = p;
+    ws.precision = precision;
+    ws.split = split;
+    ws.rec = take((size_t)n * rec);
+    ws.near = (double2 *)take((size_t)n * sizeof(double2));
+    if (use_mutual(t)) ws.slots = take((size_t)9 * n * slot);
+    ws.mp_d = (double2 *)take((size_t)cells_d * sizeof(double2));
+    ws.lo_d = (double2 *)take((size_t)cells_d * sizeof(double2));
+    ws.mp_f = (float2 *)take((size_t)cells_f * sizeof(float2));
+    ws.lo_f = (float2 *)take((size_t)cells_f * sizeof(float2));
+    if (off > kStaticWorkspaceBytes)
+        return fail(FMM_EINVAL, "this evaluation needs " + std::to_string(off) + " bytes of device workspace, more "
+                                "than the " + std::to_string(kStaticWorkspaceBytes) + " bytes of the static workspace");
+    return FMM_OK;
+}
+
+// Stages 4-10.  noalloc: the per-call arrays in the static workspace (cleared where they
+// must start at zero) and the tables already on the device; no allocation, no events.
 int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int precision, void *main_stream,
                 void *side_stream, double *uv, double *uv_near, double *uv_far, const double *base = nullptr,
-                double h = 0.0)
+                double h = 0.0, bool noalloc = false)
 {
     int rc = check_eval_args(t, gamma, sigma, p, precision);
     if (rc) return rc;
@@ -264,24 +305,36 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     BusyGuard guard(t);
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
-    if ((rc = validate_inputs(t, gamma, nullptr, (hipStream_t)main_stream))) return rc;
-    std::string err;
-    if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
-    if ((rc = ensure_workspace(t, p, precision, false, (hipStream_t)main_stream))) return rc;
-    if (use_mutual(t) && !t->wsp->slots &&
-        (rc = dev_alloc_async((char **)&t->wsp->slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
-                              "mutual near-field slots", (hipStream_t)main_stream)))
-        return rc;
-
     hipStream_t ms = (hipStream_t)main_stream;
+    if ((rc = validate_inputs(t, gamma, nullptr, ms))) return rc;
+    std::string err;
+    Workspace local;
+    if (noalloc) {
+        if ((rc = shared_tables(t->device, p, &t->tabs, err, false)))
+            return fail(FMM_ESTATE, err + " (an allocating evaluation with this p makes them)");
+        if ((rc = static_ws(t, p, precision, local))) return rc;
+        // multipoles of empty cells are read as zero rows by M2L
+        if (local.mp_d) launch_zero(local.mp_d, (size_t)((char *)local.lo_d - (char *)local.mp_d), ms);
+        if (local.mp_f) launch_zero(local.mp_f, (size_t)((char *)local.lo_f - (char *)local.mp_f), ms);
+    } else {
+        if ((rc = shared_tables(t->device, p, &t->tabs, err)))
+            return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+        if ((rc = ensure_workspace(t, p, precision, false, ms))) return rc;
+        if (use_mutual(t) && !t->wsp->slots &&
+            (rc = dev_alloc_async((char **)&t->wsp->slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
+                                  "mutual near-field slots", ms)))
+            return rc;
+    }
+    Workspace &ws = noalloc ? local : *t->wsp;
+
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
     const bool overlap = t->schedule == 0;
     if (!overlap) ss = ms;
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
-    FarArgs a = far_args(t, p, precision, false);
+    FarArgs a = far_args(t, ws, p, precision, false);
     Timing tm;
-    if ((rc = tm.init(t))) return rc;
+    if (!noalloc && (rc = tm.init(t))) return rc;
 
     tm.mark(0, ms);
     launch_stage_in(t, gamma, ms);
@@ -289,21 +342,21 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
-    launch_pack(t, alpha, is_double, t->wsp->rec, ms);
+    launch_pack(t, alpha, is_double, ws.rec, ms);
     tm.mark(1, ms);
     tm.mark(2, ss);
     launch_far_chain(a, ss);
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
-    void *slots = use_mutual(t) ? t->wsp->slots : nullptr;
+    void *slots = use_mutual(t) ? ws.slots : nullptr;
     t->occupancy_in_use = choose_occupancy(t, precision);
     tm.mark(4, ms);
-    launch_p2p_forward(t, t->wsp->rec, is_double, alpha, t->wsp->near, slots, ms);
+    launch_p2p_forward(t, ws.rec, is_double, alpha, ws.near, slots, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
     // the records are free once the near field and the far chain are done: staging for uv
-    launch_finalize(t, a, t->wsp->near, slots, is_double, alpha, uv, uv_near, uv_far, t->wsp->rec, base, h, ms);
+    launch_finalize(t, a, ws.near, slots, is_double, alpha, uv, uv_near, uv_far, ws.rec, base, h, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);
@@ -752,6 +805,15 @@ extern "C" int fmm_velocity(fmm_tree *t, const double *gamma, double sigma, int 
     return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, uv, nullptr, nullptr);
 }
 
+extern "C" int fmm_velocity_noalloc(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
+                                    void *main_stream, void *side_stream, double *uv)
+{
+    g_last_error.clear();
+    if (!uv) return fail(FMM_EINVAL, "uv is NULL");
+    return run_forward(t, gamma, sigma, p, precision, main_stream, side_stream, uv, nullptr, nullptr, nullptr, 0.0,
+                       true);
+}
+
 extern "C" int fmm_velocity_parts(fmm_tree *t, const double *gamma, double sigma, int p, int precision,
                                   void *main_stream, void *side_stream, double *uv_near, double *uv_far)
 {
@@ -788,8 +850,8 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     if (!overlap) ss = ms;
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
-    const FarArgs fc = far_args(t, p, precision, false);
-    const FarArgs fq = far_args(t, p, precision, true);
+    const FarArgs fc = far_args(t, ws, p, precision, false);
+    const FarArgs fq = far_args(t, ws, p, precision, true);
     Timing tm;
     if ((rc = tm.init(t))) return rc;
 

@@ -238,7 +238,15 @@ hipError_t find_nonfinite(const double *a, int64_t n, int stride, int *flag, hip
 int upload_tables(Tables &tb, int p, std::string &err);
 void free_tables(Tables &tb);
 // The tables of p-term expansions on a device (the current one): built on first use, shared
-// by every tree of the process and kept until it ends.  Returns 0, -2 (no memory) or -3.
-int shared_tables(int device, int p, const Tables **out, std::string &err);
+// by every tree of the process and kept until it ends.  Returns 0, -2 (no memory) or -3;
+// with create false, -5 when they do not exist yet (nothing is allocated).
+int shared_tables(int device, int p, const Tables **out, std::string &err, bool create = true);
+
+// The library's static device workspace (fmm_velocity_noalloc): its address on the
+// current device (looked up once per device) and its size in bytes.  hipError_t status.
+constexpr size_t kStaticWorkspaceBytes = size_t(128) << 20;
+int static_workspace(int device, char **base);
+// Zero `bytes` (a multiple of 8) at p with a kernel (no memset node, no allocation).
+void launch_zero(void *p, size_t bytes, hipStream_t s);
 
 }  // namespace fmm

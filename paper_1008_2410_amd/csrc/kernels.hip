@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 namespace fmm {
 namespace {
@@ -1203,6 +1204,46 @@ hipError_t find_nonfinite(const double *a, int64_t n, int stride, int *flag, hip
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && h != INT_MAX) bad = h;
     return e;
+}
+
+// ---------------------------------------------------------------------------------
+// The static workspace of fmm_velocity_noalloc: per-particle arrays, slots and
+// expansions of one call carved from a file-scope device array, for callers that cannot
+// allocate.  Host code never uses the array's name as an address: the device address is
+// looked up once per device and kept.
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+__global__ __launch_bounds__(256) void zero_kernel(uint64_t *__restrict__ p, int64_t count)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += step) p[k] = 0;
+}
+}  // namespace
+
+int static_workspace(int device, char **base)
+{
+    static std::mutex mu;
+    static char *ptr[64] = {};
+    *base = nullptr;
+    if (device < 0 || device >= 64) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+        if (e != hipSuccess) return (int)e;
+        ptr[device] = (char *)p;
+    }
+    *base = ptr[device];
+    return (int)hipSuccess;
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t count = (int64_t)(bytes / 8);
+    if (count == 0) return;
+    zero_kernel<<<(unsigned)std::min<int64_t>(blocks_for(count, 256), 2048), 256, 0, s>>>((uint64_t *)p, count);
 }
 
 void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStream_t s)

@@ -190,13 +190,17 @@ int upload_tables(Tables &tb, int p, std::string &err)
     return 0;
 }
 
-int shared_tables(int device, int p, const Tables **out, std::string &err)
+int shared_tables(int device, int p, const Tables **out, std::string &err, bool create)
 {
     static std::mutex mu;
     static std::map<std::pair<int, int>, Tables> cache;  // node addresses stay valid
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find({device, p});
     if (it == cache.end()) {
+        if (!create) {
+            err = "the expansion tables of p = " + std::to_string(p) + " are not on this device yet";
+            return -5;
+        }
         Tables tb;
         if (int rc = upload_tables(tb, p, err)) return rc;
         it = cache.emplace(std::make_pair(device, p), tb).first;
