@@ -26,17 +26,64 @@ sys.path.insert(0, HERE)
 
 # Published MI355X peaks used for the roofline fractions.
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP64_VECTOR_TFLOPS = 78.6    # the same without the packed dual issue
+# The FP32 rate the kernels can issue: the build switches packed FP32 off, so one FMA per lane
+# per cycle, 256 x 4 x 16 x 2 x 2.4 GHz.
+ISSUABLE_FP32_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # Algorithmic flops per ordered (target, source) pair of the near-field sum, section
-# "Complexity Estimates" (a complex division and an exponential).  The mutual form evaluates
-# each unordered pair once for both particles, so its achieved rate counts that evaluation
-# as the two ordered pairs it completes.
+# "Complexity Estimates" (a complex division and an exponential).
 P2P_FLOPS_PER_PAIR = 22
-# HBM bytes per launch of p2p_near_kernel<float> on this workload, from rocprofv3 --pmc
-# FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors of a 256 MiB copy kernel measured the
-# same way (profiles/p2p_near_gaussian_patches_16M.md).  None when the kernel has changed since
-# the counters were taken.
-P2P_TRAFFIC_BYTES = 7.402e9
+# HBM traffic of the near-field kernel comes from the rocprofv3 --pmc summary under
+# profiles/, which records the hash of the kernel sources it was taken with; the line
+# reports it only while the sources still hash the same.
+PROFILE_WITH_TRAFFIC = os.path.join(HERE, "profiles", "p2p_near_gaussian_patches_16M.md")
+KERNEL_SOURCES = ("paper_1008_2410_amd/csrc/kernels.hip", "paper_1008_2410_amd/csrc/device_common.h")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str):
+    """(bytes per launch, note) of `kernel` from the profile summary's machine-readable
+    traffic lines, or (None, reason) when absent or taken with other kernel sources."""
+    try:
+        with open(PROFILE_WITH_TRAFFIC) as f:
+            lines = [ln for ln in f if ln.startswith("<!-- traffic ")]
+    except OSError:
+        return None, "no profile summary"
+    cur = kernel_sources_hash()
+    for ln in lines:
+        rec = json.loads(ln[len("<!-- traffic "):].rsplit("-->", 1)[0])
+        if rec.get("kernel") != kernel:
+            continue
+        if rec.get("sources") != cur:
+            return None, f"kernel sources changed since the counters were taken ({rec.get('sources')} -> {cur})"
+        return rec["bytes"], f"rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE, sources {cur}"
+    return None, "no counter record for this kernel"
+
+
+def p2p_roofline(kernel: str, pairs: int, plan: dict, ms: float, peak: float, issuable: float):
+    """Roofline of the near-field kernel: the paper's 22 flops per ordered pair against the
+    published vector peak (the algorithmic fraction), and the evaluations the kernel really
+    performs (each unordered pair of the mutual form once, each ordered pair of the
+    target-centric form once) at 22 flops against the rate the build can issue."""
+    evals = plan["mutual_pairs"] // 2 + (pairs - plan["mutual_pairs"])
+    achieved = P2P_FLOPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+    executed = P2P_FLOPS_PER_PAIR * evals / (ms * 1e-3) / 1e12
+    traffic, note = profiled_traffic(kernel)
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic, "traffic_source": note,
+            "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs, "avg_launch_ms": round(ms, 4),
+            "executed": {"evaluations_per_launch": evals, "evaluations_per_s": round(evals / (ms * 1e-3), 1),
+                         "achieved": round(executed, 3), "peak": issuable, "frac": round(executed / issuable, 4),
+                         "note": "mutual form counted once per unordered pair; peak = non-packed issue rate"}}
 
 
 def log(msg):
@@ -47,11 +94,12 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def cpu_baseline_leg(w, sample_frac_log4=1):
+def cpu_baseline_leg(w, sample_frac_log4=0):
     """The CPU oracle on the machine's host cores: (1) accuracy gate of the GPU result on the
-    4096-particle subsample, (2) throughput of the oracle's full FMM (stages 1-10) on a
-    bounded sample of the workload: the first N/4^k particles of the (shuffled) draw with
-    the tree depth lowered by k, which keeps the particles per leaf of the full problem."""
+    4096-particle subsample, (2) throughput of the oracle's full FMM (stages 1-10) on the
+    benchmark workload itself (k = 0: all N particles at depth L, about a minute on 16
+    threads), or with k > 0 on the first N/4^k particles of the (shuffled) draw with the tree
+    depth lowered by k, which keeps the particles per leaf of the full problem."""
     import oracle
     oracle.build()
     idx = w.extra["sample"]
@@ -78,9 +126,52 @@ def cpu_baseline_leg(w, sample_frac_log4=1):
         "host_cpus": os.cpu_count(),
         "cpu_model": model,
         "kind": "oracle",
-        "sample": f"oracle FMM stages 1-10 (FP64 C, OpenMP) on the first {ns} particles of the same draw, "
-                  f"depth {w.depth - k}, p={w.p} (same particles per leaf); {t_run:.2f} s",
+        "sample": (f"oracle FMM stages 1-10 (FP64 C, OpenMP) on the whole workload: N = {ns}, depth {w.depth}, "
+                   f"p={w.p}; {t_run:.2f} s" if k == 0 else
+                   f"oracle FMM stages 1-10 (FP64 C, OpenMP) on the first {ns} particles of the same draw, "
+                   f"depth {w.depth - k}, p={w.p} (same particles per leaf); {t_run:.2f} s"),
     }
+
+
+def lattice_overlap_leg(torch, dev, workloads, steps):
+    """The jittered 1024^2 lattice as configured (FP64, depth 8, p = 12, coarse levels <= 5
+    in the one-workgroup kernel on the second stream): the evaluation overlapped and
+    serialised, and the overlap fraction (T_P2P + T_far - T_both) / min(T_P2P, T_far) from
+    the serialised stage times and the overlapped span between the pack and final stages."""
+    from paper_1008_2410_amd import _lib, fmm
+    w = workloads.lattice_lamb_oseen()
+    xy = torch.from_numpy(w.xy).to(dev)
+    g = torch.from_numpy(w.gamma).to(dev)
+    tree = fmm.Tree(xy, w.depth, w.root_box)
+    tree.set_option(_lib.FMM_OPT_COARSE_LEVEL, 5)
+    out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
+    res = {}
+    for sched in (0, 1):
+        tree.set_option(_lib.FMM_OPT_SCHEDULE, sched)
+        for _ in range(3):
+            tree.velocity(g, w.sigma, w.p, "fp64", out=out)
+        tree.set_option(_lib.FMM_OPT_TIMING, 1)
+        tree.timings()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            tree.velocity(g, w.sigma, w.p, "fp64", out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        st = tree.timings()
+        tree.set_option(_lib.FMM_OPT_TIMING, 0)
+        res[sched] = (e0.elapsed_time(e1) / steps, {k: v / st["calls"] for k, v in st.items() if k != "calls"})
+    tree.close()
+    (ms_o, st_o), (ms_s, st_s) = res[0], res[1]
+    both = st_o["total"] - st_o["pack"] - st_o["final"]
+    frac = (st_s["p2p"] + st_s["far"] - both) / min(st_s["p2p"], st_s["far"])
+    log(f"[bench] lattice fp64 L_c=5: overlap {ms_o:.3f} ms, serial {ms_s:.3f} ms, near {st_s['p2p']:.3f} ms, "
+        f"far {st_s['far']:.3f} ms, overlap fraction {frac:.3f}")
+    return {"workload": "lattice_lamb_oseen", "n": w.n, "depth": w.depth, "p": w.p, "precision": "fp64",
+            "coarse_level": 5, "ms_per_step": round(ms_o, 4), "serial_ms_per_step": round(ms_s, 4),
+            "mparticles_per_s": round(w.n / (ms_o * 1e-3) / 1e6, 1), "near_ms_serial": round(st_s["p2p"], 4),
+            "far_ms_serial": round(st_s["far"], 4), "overlap_fraction": round(frac, 4)}
 
 
 def cost_model_leg(torch, dev, workloads):
@@ -201,6 +292,7 @@ def rk2_leg(torch, dev, workloads, adaptive=False):
     log(f"[bench] rk2 adjoint {t_bwd:.2f} s: tree builds {sb.tree_build:.2f} s, velocities {sb.velocity:.3f} s, "
         f"adjoint calls {sb.backward:.3f} s ({sb.vjps})")
     peak = max(sf.peak_bytes, sb.peak_bytes)
+    torch_at_peak = sf.torch_reserved_bytes if sf.peak_bytes >= sb.peak_bytes else sb.torch_reserved_bytes
     evals = sf.evals
     print(json.dumps({
         "workload": w.name, "n": w.n, "tree": ({"adaptive": {"max_leaf": atree[0], "max_depth": atree[1]}}
@@ -216,6 +308,7 @@ def rk2_leg(torch, dev, workloads, adaptive=False):
         "adjoint_ms_per_vjp": round(sb.backward / sb.vjps * 1e3, 3),
         "bwd_fwd_device": round(sb.backward / sf.velocity, 3),
         "peak_hbm_gb": round(peak / 1e9, 2),
+        "peak_torch_reserved_gb": round(torch_at_peak / 1e9, 2),
         "grad_norms": {"x0": float(torch.linalg.norm(dx0)), "gamma": float(torch.linalg.norm(dg))},
     }), flush=True)
 
@@ -300,6 +393,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--depth", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-sample-log4", type=int, default=0,
+                    help="CPU oracle leg on the first N/4^k particles at depth L-k (default 0: the whole workload)")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--bwd-steps", type=int, default=3)
     ap.add_argument("--headline-only", action="store_true",
@@ -315,6 +410,9 @@ def main():
     ap.add_argument("--rk2-adaptive", action="store_true",
                     help="only the time-stepped workload on the clustered distribution (2^24 particles) with an "
                          "adaptive tree built per evaluation: forward and adjoint, one JSON line of its own")
+    ap.add_argument("--lattice", action="store_true",
+                    help="only the 1024^2 lattice in FP64 with coarse levels <= 5 overlapped and serialised "
+                         "(overlap fraction): one JSON line of its own")
     ap.add_argument("--adaptive", action="store_true",
                     help="only the uneven-distribution comparison (adaptive tree against uniform depths on the "
                          "patch workload and on a clustered workload): one JSON line of its own")
@@ -345,6 +443,9 @@ def main():
         return
     if args.adaptive:
         adaptive_leg(torch, dev, workloads)
+        return
+    if args.lattice:
+        print(json.dumps(lattice_overlap_leg(torch, dev, workloads, args.steps)), flush=True)
         return
     t0 = time.perf_counter()
     w = workloads.gaussian_patches(n=args.n, depth=args.depth)
@@ -389,9 +490,11 @@ def main():
     ms, stages = timed(args.steps)
     log(f"[bench] mixed overlap: {ms:.3f} ms/step, stages {stages}")
     if args.headline_only:
+        rl = p2p_roofline("p2p_near_kernel<float>", info["p2p_pairs"], plan, stages["p2p"], PEAK_FP32_VECTOR_TFLOPS,
+                          ISSUABLE_FP32_VECTOR_TFLOPS)
         print(json.dumps({"ms_per_step": round(ms, 4), "value": round(w.n / (ms * 1e-3) / 1e6, 3),
-                          "p2p_avg_ms": round(stages["p2p"], 4),
-                          "p2p_tflops": round(P2P_FLOPS_PER_PAIR * info["p2p_pairs"] / (stages["p2p"] * 1e-3) / 1e12, 3),
+                          "p2p_avg_ms": round(stages["p2p"], 4), "p2p_tflops": rl["achieved"],
+                          "p2p_executed_tflops": rl["executed"]["achieved"], "kernel_sources": kernel_sources_hash(),
                           "steps": args.steps, "warmup": args.warmup}), flush=True)
         return
     # serial schedule of the same work, for the overlap fraction
@@ -455,20 +558,19 @@ def main():
     log(f"[bench] uniform 2^20 mixed: fwd {ms_fu:.3f} ms, bwd {ms_bu:.3f} ms (bwd/fwd {ms_bu / ms_fu:.3f})")
     tu.close()
     del xu, gu, du, ou
+    lattice = lattice_overlap_leg(torch, dev, workloads, args.steps)
 
     idx = w.extra["sample"]
     cpu = None
     err_mixed = err_fp64 = None
     if not args.no_cpu:
-        ref, t_gate, cpu = cpu_baseline_leg(w)
+        ref, t_gate, cpu = cpu_baseline_leg(w, args.cpu_sample_log4)
         err_mixed = rel_l2(uv_mixed[idx], ref)
         err_fp64 = rel_l2(uv_fp64[idx], ref)
         log(f"[bench] oracle gate: mixed rel-L2 {err_mixed:.3e}, fp64 {err_fp64:.3e} ({t_gate:.1f} s); cpu {cpu}")
     err_mixed_vs_fp64 = rel_l2(uv_mixed[idx], uv_fp64[idx])
 
     pairs = info["p2p_pairs"]
-    p2p_ms = stages["p2p"]
-    achieved = P2P_FLOPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
     value = w.n / (ms * 1e-3) / 1e6
     rec = {
         "metric": "Mparticles/s FMM velocity eval, N=16M, p=16, rel-L2<=1e-5 vs FP64; bwd/fwd",
@@ -485,10 +587,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gaussian_patches", "n": w.n, "patches": 8, "sigma": w.sigma, "depth": w.depth,
                    "p": w.p, "precision": "mixed", "schedule": "overlap", "root": "bounding square"},
-        "roofline": {"bound": "alu", "kernel": "p2p_near_kernel<float>", "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "traffic": P2P_TRAFFIC_BYTES, "flops_per_pair": P2P_FLOPS_PER_PAIR, "pairs_per_launch": pairs,
-                     "avg_launch_ms": round(p2p_ms, 4)},
+        "roofline": p2p_roofline("p2p_near_kernel<float>", pairs, plan, stages["p2p"], PEAK_FP32_VECTOR_TFLOPS,
+                                 ISSUABLE_FP32_VECTOR_TFLOPS),
         "cpu_baseline": cpu,
         "accuracy": {"mixed_vs_oracle_rel_l2": err_mixed, "fp64_vs_oracle_rel_l2": err_fp64,
                      "mixed_vs_gpu_fp64_rel_l2": err_mixed_vs_fp64,
@@ -500,7 +600,10 @@ def main():
         "serial_stages_ms": {k: round(v, 4) for k, v in stages_serial.items()},
         "overlap_fraction": None if overlap is None else round(overlap, 4),
         "fp64": {"ms_per_step": round(ms_fp64, 4), "value": round(w.n / (ms_fp64 * 1e-3) / 1e6, 3),
-                 "stages_ms": {k: round(v, 4) for k, v in stages_fp64.items()}},
+                 "stages_ms": {k: round(v, 4) for k, v in stages_fp64.items()},
+                 "roofline": p2p_roofline("p2p_near_kernel<double>", pairs, plan, stages_fp64["p2p"],
+                                          PEAK_FP64_VECTOR_TFLOPS, PEAK_FP64_VECTOR_TFLOPS)},
+        "lattice_fp64_overlap": lattice,
         "bwd_fwd": {"gaussian_patches_16M": round(ms_bwd / ms, 4), "bwd_ms": round(ms_bwd, 4),
                     "uniform_1M_p12": round(ms_bu / ms_fu, 4), "uniform_fwd_ms": round(ms_fu, 4),
                     "uniform_bwd_ms": round(ms_bu, 4)},

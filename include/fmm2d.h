@@ -61,8 +61,10 @@ enum {
 enum {
     FMM_OPT_SCHEDULE = 1,     /* 0: far field on a second stream, concurrent with P2P (default);
                                  1: everything serialised on the main stream */
-    FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in one
-                                 single-workgroup kernel in FP64 (default 3, range 1..depth) */
+    FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in FP64 on the far-
+                                 field stream (default 3, range 1..depth); those of them with at
+                                 most 256 cells (levels <= 4) in one single-workgroup kernel, the
+                                 others as wide launches */
     FMM_OPT_TIMING = 3,       /* 1: record HIP events around each stage of every call for
                                  fmm_get_timings (default 0) */
                               /* keys 4 and 5 (a persistent near-field grid, a cap on the far-field

@@ -38,9 +38,7 @@ struct BusyGuard {
 void free_workspace(Workspace &ws, hipStream_t s)
 {
     for (void *p : {(void *)ws.rec, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
-                    (void *)ws.lo_f, (void *)ws.adj, (void *)ws.bwd_near, (void *)ws.bwd_b, (void *)ws.mp2_d,
-                    (void *)ws.lo2_d, (void *)ws.mp2_f, (void *)ws.lo2_f, (void *)ws.rec2, (void *)ws.slots,
-                    (void *)ws.bwd_src, (void *)ws.bwd_stage})
+                    (void *)ws.lo_f, (void *)ws.adj, (void *)ws.lo2_d, (void *)ws.lo2_f, (void *)ws.rec2, ws.sums})
         if (p) hipFreeAsync(p, s);
     ws = Workspace{};
 }
@@ -91,10 +89,8 @@ int clear_multipoles(const fmm_tree *t, hipStream_t s)
     const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
     const int64_t cells_f = level_base(t->depth + 1) - cells_d;
     const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
-    for (double2 *m : {ws.mp_d, ws.mp2_d})
-        if (m) HIP_TRY(hipMemsetAsync(m, 0, bd, s));
-    for (float2 *m : {ws.mp_f, ws.mp2_f})
-        if (m && cells_f > 0) HIP_TRY(hipMemsetAsync(m, 0, bf, s));
+    if (ws.mp_d) HIP_TRY(hipMemsetAsync(ws.mp_d, 0, bd, s));  // the adjoint's multipoles are the same arrays
+    if (ws.mp_f && cells_f > 0) HIP_TRY(hipMemsetAsync(ws.mp_f, 0, bf, s));
     return FMM_OK;
 }
 
@@ -136,26 +132,30 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
         ws.split = split;
         ws.owner = t->serial;  // zeroed just now
     }
-    if (backward && !ws.bwd_src && (rc = dev_alloc_async(&ws.bwd_src, n, "adjoint source-position sums", s))) return rc;
-    if (backward && !ws.bwd_stage && n * (int64_t)sizeof(double2) > kLastLevelCacheBytes &&
-        (rc = dev_alloc_async(&ws.bwd_stage, 5 * n, "adjoint output staging", s)))
-        return rc;
+    if (!ws.sums) {
+        // the mutual slots, or the adjoint sums at 256-byte aligned offsets 0, A(32n), A(A(32n) + 8n)
+        auto a256 = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t nn = (size_t)n;
+        const size_t o_b = a256(32 * nn), o_src = a256(o_b + 8 * nn);
+        const size_t bytes = std::max(9 * nn * (precision == FMM_FP64 ? 16 : 8), o_src + 32 * nn);
+        if ((rc = dev_alloc_async((char **)&ws.sums, bytes, "near-field sums", s))) return rc;
+        ws.slots = ws.sums;
+        ws.bwd_near = (double4 *)ws.sums;
+        ws.bwd_b = (double *)((char *)ws.sums + o_b);
+        ws.bwd_src = (double4 *)((char *)ws.sums + o_src);
+    }
     if (backward && !ws.adj) {
         if ((rc = dev_alloc_async(&ws.adj, n, "adjoint charges", s))) return rc;
-        if ((rc = dev_alloc_async(&ws.bwd_near, n, "adjoint near field", s))) return rc;
-        if ((rc = dev_alloc_async(&ws.bwd_b, n, "adjoint near field", s))) return rc;
         if (precision != FMM_FP64 && (rc = dev_alloc_async((float2 **)&ws.rec2, n, "adjoint charges (FP32)", s))) return rc;
         if (L >= 2) {
-            if ((rc = dev_alloc_async(&ws.mp2_d, cells_d * p + kCoefPad, "adjoint multipoles", s))) return rc;
+            // The adjoint's two far chains run one after the other on one stream and the
+            // multipoles of the first are dead once its M2L is done: the second (charges q)
+            // reuses them.  Its locals are kept beside the first's for the finalize.
+            ws.mp2_d = ws.mp_d;
+            ws.mp2_f = ws.mp_f;
             if ((rc = dev_alloc_async(&ws.lo2_d, cells_d * p + kCoefPad, "adjoint locals", s))) return rc;
-            HIP_TRY(hipMemsetAsync(ws.mp2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
-            HIP_TRY(hipMemsetAsync(ws.lo2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
-            if (cells_f > 0) {
-                if ((rc = dev_alloc_async(&ws.mp2_f, cells_f * p + kCoefPad, "adjoint multipoles", s))) return rc;
-                if ((rc = dev_alloc_async(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals", s))) return rc;
-                HIP_TRY(hipMemsetAsync(ws.mp2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
-                HIP_TRY(hipMemsetAsync(ws.lo2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
-            }
+            if (cells_f > 0 && (rc = dev_alloc_async(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals", s)))
+                return rc;
         }
     }
     if (ws.owner != t->serial) {
@@ -219,21 +219,28 @@ FarArgs far_args(const fmm_tree *t, const Workspace &ws, int p, int precision, b
 constexpr double kNear0 = 0.075, kNearPair = 2.12e-10, kNearVisit = 1.76e-7;
 constexpr double kFar0 = 0.128, kFarCell = 1.18e-6, kFarCoarse = 5.32e-4, kFarLevel = 0.0238;
 
-// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic: capping the
-// near field at 5 wavefronts per SIMD slows it by ~12-18% and lets the far chain run
-// beside it; measured on uniform and clustered workloads that pays when the predicted far
-// field takes between 0.12 and 1 times the near field (below, the far field is too short
-// to hide anything; above, the far kernels need more of the chip than the cap leaves).
+// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic, from the
+// predicted far/near time ratio of the mixed form (the model above):
+//  - mixed: capping the near field at 5 wavefronts per SIMD slows it by ~12-18% and lets
+//    the far chain run beside it; measured on uniform and clustered workloads that pays
+//    when the far field takes between 0.12 and 1 times the near field (below, the far
+//    field is too short to hide anything; above, the far kernels need more of the chip
+//    than the cap leaves);
+//  - FP64: the near field (at most 4 wavefronts per SIMD) capped at 2 when the far field
+//    is the longer part (ratio >= 1): the 1024^2 lattice, depth 8, p = 12, coarse levels
+//    <= 5 took 0.78 ms against 0.90 uncapped or serialised (caps 1, 3, 4: 1.04, 1.02,
+//    0.95 ms); with a short far field (2^24 patches) every cap was slower than none.
 int choose_occupancy(const fmm_tree *t, int precision)
 {
     if (t->near_occupancy >= 0) return t->near_occupancy;
-    if (precision != FMM_MIXED || t->schedule != 0 || t->depth < 2) return 0;
+    if (t->schedule != 0 || t->depth < 2) return 0;
     const int lc = std::min(t->lc, t->depth);
     double fine = 0, coarse = 0;
     for (int l = 2; l <= t->depth; ++l) (l <= lc ? coarse : fine) += (double)t->list_len[l];
     const double near = kNear0 + kNearPair * (double)t->p2p_pairs + kNearVisit * 9.0 * (double)t->nonempty_leaves;
     const double far = kFar0 + kFarCell * fine + kFarCoarse * coarse + kFarLevel * (t->depth - lc);
     const double ratio = far / near;
+    if (precision == FMM_FP64) return ratio >= 1.0 ? 2 : 0;
     return (ratio >= 0.12 && ratio <= 1.0) ? 5 : 0;
 }
 
@@ -320,10 +327,6 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
         if ((rc = shared_tables(t->device, p, &t->tabs, err)))
             return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
         if ((rc = ensure_workspace(t, p, precision, false, ms))) return rc;
-        if (use_mutual(t) && !t->wsp->slots &&
-            (rc = dev_alloc_async((char **)&t->wsp->slots, (size_t)9 * t->n * (precision == FMM_FP64 ? 16 : 8),
-                                  "mutual near-field slots", ms)))
-            return rc;
     }
     Workspace &ws = noalloc ? local : *t->wsp;
 
@@ -333,6 +336,9 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
     FarArgs a = far_args(t, ws, p, precision, false);
+    t->occupancy_in_use = choose_occupancy(t, precision);
+    // beside a capped near field the coarse kernel must fit in one wavefront per SIMD
+    if (overlap && t->occupancy_in_use > 0) a.coarse_threads = 256;
     Timing tm;
     if (!noalloc && (rc = tm.init(t))) return rc;
 
@@ -349,7 +355,6 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     void *slots = use_mutual(t) ? ws.slots : nullptr;
-    t->occupancy_in_use = choose_occupancy(t, precision);
     tm.mark(4, ms);
     launch_p2p_forward(t, ws.rec, is_double, alpha, ws.near, slots, ms);
     tm.mark(5, ms);
@@ -875,8 +880,16 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, out,
-                             ws.bwd_stage, ms);
+    // above the last-level cache the outputs reach user order through staging slots, kept in
+    // arrays this call no longer reads: dL/dGamma in the FP32 charges (mixed) or the second
+    // half of the FP64 records, the evaluation part in the records, the source part in the
+    // forward's near-field array
+    const bool staged = t->n * (int64_t)sizeof(double2) > kLastLevelCacheBytes;
+    double *st_g = !staged ? nullptr : is_double ? (double *)((char *)ws.rec + 16 * t->n) : (double *)ws.rec2;
+    double *st_x = staged ? (double *)ws.rec : nullptr;
+    double *st_s = staged ? (double *)ws.near : nullptr;
+    launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, out, st_g, st_x,
+                             st_s, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);

@@ -105,13 +105,15 @@ struct Workspace {
     double2 *adj = nullptr;       // per sorted particle: adjoint charge q (sorted order)
     double4 *bwd_near = nullptr;  // per sorted particle: near sums of Phi (2) and A (2)
     double *bwd_b = nullptr;      // per sorted particle: near sum of B
-    double2 *mp2_d = nullptr, *lo2_d = nullptr;
+    double2 *mp2_d = nullptr, *lo2_d = nullptr;  // mp2_* = mp_* (the charges q reuse the multipoles)
     float2 *mp2_f = nullptr, *lo2_f = nullptr;
     void *rec2 = nullptr;         // adjoint charges q in FP32 for the mixed near field
-    void *slots = nullptr;        // mutual near field: 9 x n sums (float2 or double2)
     double4 *bwd_src = nullptr;   // per sorted particle: near sums of the source-position terms
-    double *bwd_stage = nullptr;  // n above the last-level cache: the adjoint outputs by staging
-                                  // slot, dL/dGamma (n), dL/dx_eval (2n), dL/dx_src (2n)
+    // One region for the per-particle sums of either call: the forward's mutual near-field
+    // slots (9 x n float2 or double2) or the adjoint's near sums (bwd_near, bwd_b, bwd_src),
+    // never live in the same call.
+    void *sums = nullptr;
+    void *slots = nullptr;        // = sums
 };
 
 }  // namespace fmm
@@ -200,6 +202,7 @@ struct FarArgs {
     int rec_is_double;
     int charge_kind;           // 0: real Gamma in rec.z -> c = -i Gamma/(2 pi); 1: complex q from adj array
     const double2 *adj;        // complex charges in sorted order (charge_kind 1)
+    int coarse_threads = 1024; // workgroup size of the coarse-level kernel (256 or 1024)
 };
 
 // Launchers (kernels.hip).  All are asynchronous on `s`.
@@ -228,7 +231,8 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
                          double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
-                              double alpha, const AdjointOut &out, double *stage, hipStream_t s);
+                              double alpha, const AdjointOut &out, double *stage_g, double *stage_x,
+                              double *stage_s, hipStream_t s);
 
 // Lowest index k of the n groups of `stride` doubles at a (device) that holds a NaN or an
 // infinity, or -1 in bad; flag is a device int of the caller.  Synchronises s.

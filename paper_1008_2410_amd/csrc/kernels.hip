@@ -638,11 +638,19 @@ __global__ __launch_bounds__(256) void m2l_kernel(const int *__restrict__ target
 
 // ---------------------------------------------------------------------------------
 // Coarse levels (<= L_c) in one workgroup: M2M into levels L_c-1..2, then M2L + L2L
-// for levels 2..L_c, in FP64 on MFMA (4 wavefronts, one 16-target tile each per
+// for levels 2..L_c, in FP64 on MFMA (16 wavefronts, one 16-target tile each per
 // pass).  These levels hold too few cells to fill the chip; the paper assigns them to
 // a single thread group and covers their latency with the near-field work (section
 // "Concurrency").
 // ---------------------------------------------------------------------------------
+// One workgroup of up to 16 wavefronts (four per SIMD of its CU): each level's tiles are
+// dealt to the wavefronts, so a level of 1024 cells takes four rounds of gathers with 16
+// wavefronts instead of 16 rounds with 4.  Beside a near field capped below the full
+// occupancy only one wavefront per SIMD fits in the registers it leaves, so the kernel is
+// then launched with 4 (FarArgs::coarse_threads).
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseMaxLevel = 4;
+
 struct CoarseArgs {
     int p, lc;
     const int *lists;
@@ -655,7 +663,7 @@ struct CoarseArgs {
     const double *zero;
 };
 
-__global__ __launch_bounds__(256, 4) void coarse_kernel(CoarseArgs a)
+__global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs a)
 {
     const int p = a.p;
     const int wave = threadIdx.x >> 6;
@@ -1081,8 +1089,10 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
     const double4 *__restrict__ near_pa, const double *__restrict__ near_b, const double2 *__restrict__ adj,
     const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, int p, int has_far, double x0, double y0,
     double w, double alpha, double lambda, AdjointOut out, const double4 *__restrict__ near_src,
-    const int *__restrict__ gpos2, const double *__restrict__ gamma_st, double *__restrict__ stage, int nxcd)
+    const int *__restrict__ gpos2, const double *__restrict__ gamma_st, double *__restrict__ stage_g,
+    double *__restrict__ stage_x, double *__restrict__ stage_s, int nxcd)
 {
+    const bool stage = stage_x != nullptr;
     const bool need_x = out.dxe || out.dxy, need_s = out.dxs || out.dxy;
     const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1137,15 +1147,15 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
         sx = -G * (ati + bti);
         sy = -G * (atr - btr);
     }
-    if (stage) {  // by staging slot: dL/dGamma (n), evaluation part (2n), source part (2n)
-        if (out.dg) stage[o] = g;
+    if (stage) {  // by staging slot: dL/dGamma, evaluation part, source part
+        if (out.dg) stage_g[o] = g;
         if (need_x) {
-            stage[n + 2 * o] = ex;
-            stage[n + 2 * o + 1] = ey;
+            stage_x[2 * o] = ex;
+            stage_x[2 * o + 1] = ey;
         }
         if (need_s) {
-            stage[3 * (int64_t)n + 2 * o] = sx;
-            stage[3 * (int64_t)n + 2 * o + 1] = sy;
+            stage_s[2 * o] = sx;
+            stage_s[2 * o + 1] = sy;
         }
         return;
     }
@@ -1155,16 +1165,17 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
 // The adjoint outputs from their staging slots (written by finalize_backward_kernel for n
 // above the last-level cache) to user order, as gather_rows_kernel does for velocities.
 __global__ __launch_bounds__(256) void gather_adjoint_kernel(int n, int nxcd, const int *__restrict__ gpos1,
-                                                             const double *__restrict__ stage, AdjointOut out)
+                                                             const double *__restrict__ stage_g,
+                                                             const double *__restrict__ stage_x,
+                                                             const double *__restrict__ stage_s, AdjointOut out)
 {
     const int u = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const int64_t k = gpos1[u];
     const bool need_x = out.dxe || out.dxy, need_s = out.dxs || out.dxy;
-    const double g = out.dg ? stage[k] : 0.0;
-    const double ex = need_x ? stage[n + 2 * k] : 0.0, ey = need_x ? stage[n + 2 * k + 1] : 0.0;
-    const double sx = need_s ? stage[3 * (int64_t)n + 2 * k] : 0.0;
-    const double sy = need_s ? stage[3 * (int64_t)n + 2 * k + 1] : 0.0;
+    const double g = out.dg ? stage_g[k] : 0.0;
+    const double ex = need_x ? stage_x[2 * k] : 0.0, ey = need_x ? stage_x[2 * k + 1] : 0.0;
+    const double sx = need_s ? stage_s[2 * k] : 0.0, sy = need_s ? stage_s[2 * k + 1] : 0.0;
     store_adjoint(out, u, g, ex, ey, sx, sy);
 }
 
@@ -1330,8 +1341,13 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
         if (a.rec_is_double) p2m_launch<double4, float>(a, s);
         else p2m_launch<float4, float>(a, s);
     }
-    // Stage 5 on the fine levels: parents L-1 .. max(lc, 2).
-    for (int l = L - 1; l >= 2 && l >= a.lc; --l) {
+    // Levels <= lw run in the one-workgroup coarse kernel: the coarse levels up to 256
+    // cells (level 4), one round of gathers for its 16 wavefronts.  Coarse levels above that
+    // (L_c = 5: 1024 cells, 64 tiles) keep FP64 and the side stream but run as wide launches
+    // like the fine levels: on one CU their MFMA work alone takes longer than the near field.
+    const int lw = std::min(a.lc, kCoarseMaxLevel);
+    // Stage 5 on the fine levels: parents L-1 .. max(lw, 2).
+    for (int l = L - 1; l >= 2 && l >= lw; --l) {
         const bool child_d = (l + 1) <= a.split, parent_d = l <= a.split;
         if (child_d && parent_d && a.p <= 16) gemm_f64_launch(a, l, 2, s);
         else if (child_d && parent_d) m2m_launch<double, double>(a, l, tb.m2m_d, s);
@@ -1340,11 +1356,11 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
         else if (parent_d) m2m_launch<float, double>(a, l, tb.m2m_d, s);
         else m2m_launch<float, float>(a, l, tb.m2m_f, s);
     }
-    // Coarse levels 2..lc in one workgroup (stages 5, 6, 7 there).
-    if (a.lc >= 2 && a.p > 16) {
+    // Coarse levels 2..lw in one workgroup (stages 5, 6, 7 there).
+    if (lw >= 2 && a.p > 16) {
         CoarseValuArgs c{};
         c.p = a.p;
-        c.lc = a.lc;
+        c.lc = lw;
         c.counts = t->d_counts;
         c.lists = t->d_lists;
         for (int l = 0; l <= kMaxDepth; ++l) {
@@ -1357,10 +1373,10 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
         c.m2l_tab = tb.m2l_d;
         c.l2l_tab = tb.l2l_d;
         coarse_valu_kernel<<<1, 1024, 0, s>>>(c);
-    } else if (a.lc >= 2) {
+    } else if (lw >= 2) {
         CoarseArgs c{};
         c.p = a.p;
-        c.lc = a.lc;
+        c.lc = lw;
         c.lists = t->d_lists;
         for (int l = 0; l <= kMaxDepth; ++l) {
             c.list_off[l] = l <= L ? t->list_off[l] : 0;
@@ -1372,10 +1388,10 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
         c.entries = tb.mfma_entries;
         c.tab = tb.mfma_d;
         c.zero = tb.zero_row;
-        coarse_kernel<<<1, 256, 0, s>>>(c);
+        coarse_kernel<<<1, a.coarse_threads, 0, s>>>(c);
     }
     // Stages 6 + 7 on the fine levels.
-    for (int l = (a.lc + 1 > 2 ? a.lc + 1 : 2); l <= L; ++l) {
+    for (int l = (lw + 1 > 2 ? lw + 1 : 2); l <= L; ++l) {
         const bool here_d = l <= a.split, par_d = (l - 1) <= a.split;
         if (here_d && a.p <= 16) gemm_f64_launch(a, l, 0, s);
         else if (here_d) m2l_launch<double, double>(a, l, tb.m2l_d, tb.l2l_d, s);
@@ -1474,7 +1490,8 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
 
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
-                              double alpha, const AdjointOut &out, double *stage, hipStream_t s)
+                              double alpha, const AdjointOut &out, double *stage_g, double *stage_x,
+                              double *stage_s, hipStream_t s)
 {
     const int L = t->depth;
     const int n = (int)t->n;
@@ -1486,13 +1503,14 @@ void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArg
         finalize_backward_kernel<double><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj,
             has_far ? level_ptr<double>(fc, L, true) : nullptr, has_far ? level_ptr<double>(fq, L, true) : nullptr,
-            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2, t->d_st1, stage, kXcds);
+            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2, t->d_st1, stage_g, stage_x,
+            stage_s, kXcds);
     else
         finalize_backward_kernel<float><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj, level_ptr<float>(fc, L, true),
             level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2,
-            t->d_st1, stage, kXcds);
-    if (stage) gather_adjoint_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, stage, out);
+            t->d_st1, stage_g, stage_x, stage_s, kXcds);
+    if (stage_x) gather_adjoint_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, stage_g, stage_x, stage_s, out);
 }
 
 

@@ -49,12 +49,15 @@ class RK2Stats:
     evals: int = 0
     vjps: int = 0
     peak_bytes: int = 0
+    torch_reserved_bytes: int = 0   # the part held by torch's caching allocator (inputs, checkpoints)
     per_step: list = field(default_factory=list)
 
 
 def _sample_memory(device, stats: RK2Stats):
     free, total = torch.cuda.mem_get_info(device)
-    stats.peak_bytes = max(stats.peak_bytes, total - free)
+    if total - free > stats.peak_bytes:
+        stats.peak_bytes = total - free
+        stats.torch_reserved_bytes = torch.cuda.memory_reserved(device)
 
 
 def _tree_for(tree, xy, depth, root_box, adaptive):
