@@ -37,7 +37,7 @@ struct BusyGuard {
 // device work that used it (destroy) or synchronised (reallocation).
 void free_workspace(Workspace &ws, hipStream_t s)
 {
-    for (void *p : {(void *)ws.rec, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
+    for (void *p : {ws.gam, (void *)ws.stage, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
                     (void *)ws.lo_f, (void *)ws.adj, (void *)ws.lo2_d, (void *)ws.lo2_f, (void *)ws.rec2, ws.sums})
         if (p) hipFreeAsync(p, s);
     ws = Workspace{};
@@ -60,6 +60,8 @@ void free_tree(fmm_tree *t)
         release(p, t->pooled);
     release(t->d_near_work, true);
     release(t->d_leaf_mask, true);
+    release(t->d_pos[0], true);
+    release(t->d_pos[1], true);
     hipFree(t->d_flag);
     if (t->wsp.use_count() == 1) free_workspace(*t->wsp, fs);
     if (t->own_side) hipStreamDestroy(t->own_side);
@@ -85,7 +87,7 @@ int split_level(const fmm_tree *t, int precision) { return precision == FMM_FP64
 int clear_multipoles(const fmm_tree *t, hipStream_t s)
 {
     const Workspace &ws = *t->wsp;
-    if (!ws.rec || t->depth < 2) return FMM_OK;
+    if (!ws.gam || t->depth < 2) return FMM_OK;
     const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
     const int64_t cells_f = level_base(t->depth + 1) - cells_d;
     const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
@@ -107,10 +109,11 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
     const int64_t n = t->n;
     const int64_t cells_d = level_base(std::min(split, L) + 1);
     const int64_t cells_f = level_base(L + 1) - cells_d;
-    const size_t rec_bytes = precision == FMM_FP64 ? sizeof(double4) : sizeof(float4);
+    const size_t gam_bytes = precision == FMM_FP64 ? sizeof(double) : sizeof(float);
     int rc = FMM_OK;
-    if (!ws.rec) {
-        if ((rc = dev_alloc_async((char **)&ws.rec, n * rec_bytes, "particle records", s))) return rc;
+    if (!ws.gam) {
+        if ((rc = dev_alloc_async((char **)&ws.gam, n * gam_bytes, "circulations in tree order", s))) return rc;
+        if ((rc = dev_alloc_async(&ws.stage, n, "velocities in tree order", s))) return rc;
         if ((rc = dev_alloc_async(&ws.near, n, "near field", s))) return rc;
         if (L >= 2) {
             if ((rc = dev_alloc_async(&ws.mp_d, cells_d * p + kCoefPad, "multipoles", s))) return rc;
@@ -204,7 +207,8 @@ FarArgs far_args(const fmm_tree *t, const Workspace &ws, int p, int precision, b
     a.lo_d = adjoint ? ws.lo2_d : ws.lo_d;
     a.mp_f = adjoint ? ws.mp2_f : ws.mp_f;
     a.lo_f = adjoint ? ws.lo2_f : ws.lo_f;
-    a.rec = ws.rec;
+    a.pos = t->d_pos[precision == FMM_FP64];
+    a.gam = ws.gam;
     a.rec_is_double = precision == FMM_FP64;
     a.charge_kind = adjoint ? 1 : 0;
     a.adj = adjoint ? ws.adj : nullptr;
@@ -260,8 +264,21 @@ struct Timing {
     }
 };
 
+// The tree's leaf-unit coordinates in the precision of a call, made on its first use.
+int ensure_positions(fmm_tree *t, int precision, hipStream_t s)
+{
+    const int d = precision == FMM_FP64;
+    if (t->d_pos[d]) return FMM_OK;
+    const int rc = dev_alloc_async((char **)&t->d_pos[d], (size_t)t->n * (d ? sizeof(double2) : sizeof(float2)),
+                                   "leaf-unit coordinates", s);
+    if (rc) return rc;
+    launch_leaf_coords(t, d, t->d_pos[d], s);
+    return FMM_OK;
+}
+
 // The per-call arrays of an evaluation carved from the static workspace (no allocation):
-// records, near field, slots (mutual form), then the multipoles and locals of every level,
+// circulations, staged velocities, near field, leaf-unit coordinates (in `sums`, when the
+// tree has none yet), slots (mutual form), then the multipoles and locals of every level,
 // each 256-byte aligned.  FMM_EINVAL when they do not fit, naming both sizes.
 int static_ws(const fmm_tree *t, int p, int precision, Workspace &ws)
 {
@@ -275,7 +292,7 @@ int static_ws(const fmm_tree *t, int p, int precision, Workspace &ws)
     const int64_t cells_f = L >= 2 && level_base(L + 1) > level_base(std::min(split, L) + 1)
                                 ? (level_base(L + 1) - level_base(std::min(split, L) + 1)) * p + kCoefPad
                                 : 0;
-    const size_t rec = precision == FMM_FP64 ? sizeof(double4) : sizeof(float4);
+    const size_t real = precision == FMM_FP64 ? sizeof(double) : sizeof(float);
     const size_t slot = precision == FMM_FP64 ? sizeof(double2) : sizeof(float2);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -287,8 +304,11 @@ int static_ws(const fmm_tree *t, int p, int precision, Workspace &ws)
     ws.p = p;
     ws.precision = precision;
     ws.split = split;
-    ws.rec = take((size_t)n * rec);
+    ws.gam = take((size_t)n * real);
+    ws.stage = (double2 *)take((size_t)n * sizeof(double2));
     ws.near = (double2 *)take((size_t)n * sizeof(double2));
+    // the tree's leaf-unit coordinates when an allocating evaluation has not made them yet
+    if (!t->d_pos[precision == FMM_FP64]) ws.sums = take((size_t)n * 2 * real);
     if (use_mutual(t)) ws.slots = take((size_t)9 * n * slot);
     ws.mp_d = (double2 *)take((size_t)cells_d * sizeof(double2));
     ws.lo_d = (double2 *)take((size_t)cells_d * sizeof(double2));
@@ -323,12 +343,15 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
         // multipoles of empty cells are read as zero rows by M2L
         if (local.mp_d) launch_zero(local.mp_d, (size_t)((char *)local.lo_d - (char *)local.mp_d), ms);
         if (local.mp_f) launch_zero(local.mp_f, (size_t)((char *)local.lo_f - (char *)local.mp_f), ms);
+        if (local.sums) launch_leaf_coords(t, precision == FMM_FP64, local.sums, ms);
     } else {
         if ((rc = shared_tables(t->device, p, &t->tabs, err)))
             return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
-        if ((rc = ensure_workspace(t, p, precision, false, ms))) return rc;
+        if ((rc = ensure_workspace(t, p, precision, false, ms)) || (rc = ensure_positions(t, precision, ms)))
+            return rc;
     }
     Workspace &ws = noalloc ? local : *t->wsp;
+    const void *pos = noalloc && local.sums ? local.sums : t->d_pos[precision == FMM_FP64];
 
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
     const bool overlap = t->schedule == 0;
@@ -336,6 +359,8 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
     FarArgs a = far_args(t, ws, p, precision, false);
+    a.pos = pos;
+    a.gam = nullptr;  // P2M starts before the circulations are gathered: it reads the staging array
     t->occupancy_in_use = choose_occupancy(t, precision);
     // beside a capped near field the coarse kernel must fit in one wavefront per SIMD
     if (overlap && t->occupancy_in_use > 0) a.coarse_threads = 256;
@@ -348,7 +373,7 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
-    launch_pack(t, alpha, is_double, ws.rec, ms);
+    launch_pack(t, is_double, ws.gam, ms);
     tm.mark(1, ms);
     tm.mark(2, ss);
     launch_far_chain(a, ss);
@@ -356,12 +381,11 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     void *slots = use_mutual(t) ? ws.slots : nullptr;
     tm.mark(4, ms);
-    launch_p2p_forward(t, ws.rec, is_double, alpha, ws.near, slots, ms);
+    launch_p2p_forward(t, pos, ws.gam, is_double, alpha, ws.near, slots, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
-    // the records are free once the near field and the far chain are done: staging for uv
-    launch_finalize(t, a, ws.near, slots, is_double, alpha, uv, uv_near, uv_far, ws.rec, base, h, ms);
+    launch_finalize(t, a, ws.near, slots, is_double, alpha, uv, uv_near, uv_far, ws.stage, base, h, ms);
     tm.mark(7, ms);
     HIP_TRY(hipGetLastError());
     if (tm.on) t->pending_timing.push_back(tm.ev);
@@ -845,9 +869,12 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     if ((rc = validate_inputs(t, gamma, cot, (hipStream_t)main_stream))) return rc;
     std::string err;
     if ((rc = shared_tables(t->device, p, &t->tabs, err))) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
-    if ((rc = ensure_workspace(t, p, precision, true, (hipStream_t)main_stream))) return rc;
+    if ((rc = ensure_workspace(t, p, precision, true, (hipStream_t)main_stream)) ||
+        (rc = ensure_positions(t, precision, (hipStream_t)main_stream)))
+        return rc;
     Workspace &ws = *t->wsp;
     const bool need_src = out.dxs || out.dxy;
+    const void *pos = t->d_pos[precision == FMM_FP64];
 
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
@@ -862,7 +889,7 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
 
     tm.mark(0, ms);
     launch_stage_in(t, gamma, ms);
-    launch_pack(t, alpha, is_double, ws.rec, ms);
+    launch_pack(t, is_double, ws.gam, ms);
     launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ms);
     tm.mark(1, ms);
     if (overlap) {
@@ -875,18 +902,18 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     tm.mark(4, ms);
-    launch_p2p_backward(t, ws.rec, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
+    launch_p2p_backward(t, pos, ws.gam, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
                         ws.bwd_b, need_src ? ws.bwd_src : nullptr, ms);
     tm.mark(5, ms);
     if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
     // above the last-level cache the outputs reach user order through staging slots, kept in
-    // arrays this call no longer reads: dL/dGamma in the FP32 charges (mixed) or the second
-    // half of the FP64 records, the evaluation part in the records, the source part in the
-    // forward's near-field array
+    // arrays this call no longer reads: dL/dGamma in the FP32 charges (mixed) or the FP64
+    // circulations, the evaluation part in the forward's staged velocities, the source part
+    // in the forward's near-field array
     const bool staged = t->n * (int64_t)sizeof(double2) > kLastLevelCacheBytes;
-    double *st_g = !staged ? nullptr : is_double ? (double *)((char *)ws.rec + 16 * t->n) : (double *)ws.rec2;
-    double *st_x = staged ? (double *)ws.rec : nullptr;
+    double *st_g = !staged ? nullptr : is_double ? (double *)ws.gam : (double *)ws.rec2;
+    double *st_x = staged ? (double *)ws.stage : nullptr;
     double *st_s = staged ? (double *)ws.near : nullptr;
     launch_finalize_backward(t, fc, fq, ws.bwd_near, ws.bwd_b, ws.adj, ws.bwd_src, is_double, alpha, out, st_g, st_x,
                              st_s, ms);

@@ -66,6 +66,31 @@ template <typename R> struct RecScalar;
 template <> struct RecScalar<float4> { using type = float; };
 template <> struct RecScalar<double4> { using type = double; };
 
+// Where the near-field kernels read a particle's record from:
+//   AosRec: an array of records {X, Y, Gamma, 0} (the adaptive tree);
+//   SoaRec: leaf-unit coordinates xi = (z - c_leaf)/w, kept with the tree, scaled on load
+//           by alpha w, and the circulations in tree order, gathered per call (the uniform
+//           tree: only the circulations change between calls).
+template <typename T> struct AosRec {
+    const rec_t<T> *__restrict__ r;
+    __device__ __forceinline__ rec_t<T> operator()(int64_t i) const { return r[i]; }
+};
+template <typename T> struct SoaRec {
+    const c2<T> *__restrict__ pos;
+    const T *__restrict__ gam;
+    T scale;
+    __device__ __forceinline__ rec_t<T> operator()(int64_t i) const
+    {
+        const c2<T> p = pos[i];
+        rec_t<T> r;
+        r.x = p.x * scale;
+        r.y = p.y * scale;
+        r.z = gam[i];
+        r.w = (T)0;
+        return r;
+    }
+};
+
 // g(s) = 1 - exp(-|dz|^2/(2 sigma^2)) in the scaled variable s, and 1/s.
 __device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builtin_amdgcn_exp2f(-s); }
 __device__ __forceinline__ double one_minus_exp(double s) { return -expm1(-s); }
@@ -197,14 +222,13 @@ __device__ __forceinline__ void mutual_chunk(const rec_t<T> *src, T rx, T ry, T 
 
 // Records of one tile into LDS, each chunk of 16 stored twice in a row (so that the
 // sources of step j are at a constant offset), zero records past the tile's end.
-template <typename T>
-__device__ __forceinline__ rec_t<T> stage_doubled(rec_t<T> *dst, const rec_t<T> *__restrict__ rec, int first,
-                                                  int len)
+template <typename T, typename Src>
+__device__ __forceinline__ rec_t<T> stage_doubled(rec_t<T> *dst, const Src &rec, int first, int len)
 {
     const int lane = threadIdx.x;
     rec_t<T> r;
     r.x = r.y = r.z = r.w = (T)0;
-    if (lane < len) r = rec[first + lane];
+    if (lane < len) r = rec(first + lane);
     dst[(lane >> 4) * 32 + (lane & 15)] = r;
     dst[(lane >> 4) * 32 + (lane & 15) + 16] = r;
     return r;
@@ -213,9 +237,9 @@ __device__ __forceinline__ rec_t<T> stage_doubled(rec_t<T> *dst, const rec_t<T> 
 // One tile b of S against every tile a of R (a >= b when S = R).  Per block (b, a) the
 // tile with more chunks of 16 sits in the lanes and the other is streamed from LDS, so
 // that fewer steps are spent; either way both sums come out lane-indexed by particle.
-template <typename T>
+template <typename T, typename Src>
 __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b, int b,
-                                                     int tb, const rec_t<T> *__restrict__ rec,
+                                                     int tb, const Src &rec,
                                                      const int *__restrict__ leaf_start,
                                                      const int *__restrict__ tile_start,
                                                      const float4 *__restrict__ tile_box, T step, float cut_leaf2,
@@ -232,7 +256,7 @@ __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *ti
     const int lenb = min(64, s1 - b);
     const int nchb = (lenb + 15) >> 4;
     __syncthreads();
-    const rec_t<T> rb = stage_doubled<T>(tile_b, rec, b, lenb);
+    const rec_t<T> rb = stage_doubled<T, Src>(tile_b, rec, b, lenb);
     // tile b in the frame of leaf R (resident form); in the streamed form it stays in
     // the frame of S and tile a is moved there
     const T bx = rb.x - ox, by = rb.y - oy;
@@ -269,7 +293,7 @@ __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *ti
         if (!first_touch && lane < lena) old = slot_r[a + lane];
         const bool swap = ncha > nchb;  // tile a in the lanes, tile b streamed
         __syncthreads();
-        const rec_t<T> ra = stage_doubled<T>(tile_a, rec, a, lena);
+        const rec_t<T> ra = stage_doubled<T, Src>(tile_a, rec, a, lena);
         __syncthreads();
         T px, py, pgn;
         const rec_t<T> *src;
@@ -322,19 +346,31 @@ __device__ __forceinline__ void mutual_resident_tile(const int4 it, rec_t<T> *ti
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b,
-                                            const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
-                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
-                                            T step, float cut_leaf2, int64_t n, c2<T> *__restrict__ slots)
+template <typename T, typename Src>
+__device__ __forceinline__ void mutual_item_src(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b, const Src &rec,
+                                                const int *__restrict__ leaf_start,
+                                                const int *__restrict__ tile_start,
+                                                const float4 *__restrict__ tile_box, T step, float cut_leaf2,
+                                                int64_t n, c2<T> *__restrict__ slots)
 {
     const uint32_t S = (uint32_t)it.x;
     c2<T> *slot_s = slots + (int64_t)(it.z & 15) * n;
     c2<T> *slot_r = slots + (int64_t)(it.z >> 4) * n;
     const int s0 = leaf_start[S], s1 = leaf_start[S + 1];
     for (int b = s0, tb = tile_start[S]; b < s1; b += 64, ++tb)
-        mutual_resident_tile<T>(it, tile_a, tile_b, b, tb, rec, leaf_start, tile_start, tile_box, step, cut_leaf2,
-                                slot_s, slot_r);
+        mutual_resident_tile<T, Src>(it, tile_a, tile_b, b, tb, rec, leaf_start, tile_start, tile_box, step,
+                                     cut_leaf2, slot_s, slot_r);
+}
+
+// The mutual item over an array of records (the adaptive tree).
+template <typename T>
+__device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b,
+                                            const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
+                                            T step, float cut_leaf2, int64_t n, c2<T> *__restrict__ slots)
+{
+    mutual_item_src<T, AosRec<T>>(it, tile_a, tile_b, AosRec<T>{rec}, leaf_start, tile_start, tile_box, step,
+                                  cut_leaf2, n, slots);
 }
 
 // ---------------------------------------------------------------------------------

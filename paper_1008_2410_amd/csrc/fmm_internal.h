@@ -97,7 +97,8 @@ struct Workspace {
     // unknown after a hand-over): another tree must clear them first, since each call
     // writes only the cells that are non-empty in its own tree
     uint64_t owner = 0;
-    void *rec = nullptr;          // per-particle P2P records (float4 or double4), n
+    void *gam = nullptr;          // circulations in tree order in the near field's precision, n
+    double2 *stage = nullptr;     // n: the velocities in tree order before the permutation to user order
     double2 *near = nullptr;      // near-field (u, v) per sorted particle, n
     double2 *mp_d = nullptr, *lo_d = nullptr;  // FP64 levels
     float2 *mp_f = nullptr, *lo_f = nullptr;   // FP32 levels
@@ -165,6 +166,9 @@ struct fmm_tree {
     int *d_tile_start = nullptr;  // per leaf: index of its first 64-particle tile, 4^L + 1
     float4 *d_tile_box = nullptr; // per tile: {xmin, ymin, xmax, ymax} in leaf units about the leaf centre
     int *d_flag = nullptr;        // result of the input check (FMM_OPT_VALIDATE)
+    // leaf-unit coordinates xi = (z - c_leaf)/w_L of the sorted particles, float2 [0] and
+    // double2 [1], each made on the first evaluation in that precision
+    void *d_pos[2] = {nullptr, nullptr};
 
     hipStream_t own_side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -198,7 +202,8 @@ struct FarArgs {
     int lc;                    // coarse cutoff actually used (<= depth)
     double2 *mp_d, *lo_d;      // FP64 storage (levels 0..split)
     float2 *mp_f, *lo_f;       // FP32 storage (levels split+1..L)
-    const void *rec;           // P2P records (charges live in .z / complex in adjoint)
+    const void *pos;           // the tree's leaf-unit coordinates in the records' precision (or null)
+    const void *gam;           // circulations in tree order in that precision (null: P2M reads the staging array)
     int rec_is_double;
     int charge_kind;           // 0: real Gamma in rec.z -> c = -i Gamma/(2 pi); 1: complex q from adj array
     const double2 *adj;        // complex charges in sorted order (charge_kind 1)
@@ -215,10 +220,14 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err);
 // Pass 1 of the circulations into tree order (the staging array, all P2M needs), then
 // pass 2 with the near-field records.
 void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s);
-void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipStream_t s);
-void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
-                        hipStream_t s);
-void launch_far_chain(const FarArgs &a, hipStream_t s);
+void launch_pack(const fmm_tree *t, int is_double, void *gam, hipStream_t s);
+// The tree's leaf-unit coordinates (float2 or double2, n) into pos.
+void launch_leaf_coords(const fmm_tree *t, int is_double, void *pos, hipStream_t s);
+void launch_p2p_forward(const fmm_tree *t, const void *pos, const void *gam, int is_double, double alpha,
+                        double2 *near, void *slots, hipStream_t s);
+// Stages 4-7 (P2M, M2M, M2L, L2L), or 5-7 without P2M when it was launched on its own.
+void launch_far_chain(const FarArgs &a, hipStream_t s, bool with_p2m = true);
+void launch_p2m(const FarArgs &a, hipStream_t s);
 // uv alone is written through `stage` (a buffer of n double2); with base, uv = base + h u.
 void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, const void *slots, int slots_double,
                      double alpha, double *uv, double *uv_near, double *uv_far, void *stage, const double *base,
@@ -227,8 +236,8 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
 // Backward
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, double2 *adj, void *qt, int is_double,
                          hipStream_t s);
-void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
-                         double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s);
+void launch_p2p_backward(const fmm_tree *t, const void *pos, const void *gam, const void *qv, int is_double,
+                         double alpha, double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s);
 void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArgs &fq, const double4 *near_pa,
                               const double *near_b, const double2 *adj, const double4 *near_src, int is_double,
                               double alpha, const AdjointOut &out, double *stage_g, double *stage_x,

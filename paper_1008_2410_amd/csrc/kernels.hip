@@ -16,6 +16,7 @@
 #include <climits>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 namespace fmm {
 namespace {
@@ -99,27 +100,33 @@ __global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxc
     for (int j = t; j < m; j += 256) st[dst[j]] = val[j];
 }
 
-// gamma_st: circulations in the staging array, read at gpos2[i] (pass 2 of the
-// user-to-tree permutation).
+// Pass 2 of the user-to-tree permutation: the circulation of sorted particle i, read from
+// the staging array at gpos2[i] and rounded to the near field's precision (the near-field
+// records' Gamma; the positions of the records are the tree's, in leaf units).
 template <typename T>
 __global__ __launch_bounds__(256) void pack_kernel(int n, int nxcd, const int *__restrict__ gpos2,
-                                                    const int *__restrict__ leaf_of,
-                                                    const double2 *__restrict__ xy, const double *__restrict__ gamma_st,
-                                                    double x0, double y0, double w, double alpha,
-                                                    rec_t<T> *__restrict__ rec)
+                                                    const double *__restrict__ gamma_st, T *__restrict__ gam)
 {
-    int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
+    const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t leaf = (uint32_t)leaf_of[i];
-    double cx = x0 + (morton_x(leaf) + 0.5) * w;
-    double cy = y0 + (morton_y(leaf) + 0.5) * w;
-    double2 z = xy[i];
-    rec_t<T> r;
-    r.x = (T)(alpha * (z.x - cx));
-    r.y = (T)(alpha * (z.y - cy));
-    r.z = (T)gamma_st[gpos2[i]];
-    r.w = (T)0;
-    rec[i] = r;
+    gam[i] = (T)gamma_st[gpos2[i]];
+}
+
+// Leaf-unit coordinates xi = (z - c_leaf)/w_L of the sorted particles (the tree's, made once
+// per precision): the near-field records are xi scaled by alpha w_L on load, and L2P and
+// P2M evaluate their series at xi.
+template <typename T>
+__global__ __launch_bounds__(256) void leaf_coords_kernel(int n, const int *__restrict__ leaf_of,
+                                                           const double2 *__restrict__ xy, double x0, double y0,
+                                                           double w, c2<T> *__restrict__ pos)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t leaf = (uint32_t)leaf_of[i];
+    const double cx = x0 + (morton_x(leaf) + 0.5) * w;
+    const double cy = y0 + (morton_y(leaf) + 0.5) * w;
+    const double2 z = xy[i];
+    pos[i] = mk<T>((T)((z.x - cx) / w), (T)((z.y - cy) / w));
 }
 
 
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(256) void pack_kernel(int n, int nxcd, const int *_
 // ---------------------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, const rec_t<T> *__restrict__ rec,
+__device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, const SoaRec<T> &rec,
                                                  const int *__restrict__ leaf_start,
                                                  const int *__restrict__ tile_start,
                                                  const float4 *__restrict__ tile_box, int nside, T step,
@@ -157,7 +164,7 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
-    const rec_t<T> ri = rec[i];
+    const rec_t<T> ri = rec(i);
     const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
     const float4 tbox = tile_box[tile_start[u.x] + ((u.y - leaf_start[u.x]) >> 6)];
     double au = 0.0, av = 0.0;
@@ -178,7 +185,7 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
             for (int base = s0; base < s1; base += 64, ++tt) {
                 const int len = min(64, s1 - base);
                 __syncthreads();
-                if (lane < len) tile[lane] = rec[base + lane];
+                if (lane < len) tile[lane] = rec(base + lane);
                 const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
                 __syncthreads();
                 switch (logtp) {
@@ -214,13 +221,14 @@ __device__ __forceinline__ void p2p_forward_unit(const int4 u, rec_t<T> *tile, c
 
 template <typename T>
 __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t<T> *tile_b,
-                                           const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
+                                           const SoaRec<T> &rec, const int *__restrict__ leaf_start,
                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
                                            int nside, T step, float cut_leaf2, double scale, int dense, int64_t n,
                                            double2 *__restrict__ near, c2<T> *__restrict__ slots)
 {
     if (u.w & kMutualItem)
-        mutual_item<T>(u, tile_a, tile_b, rec, leaf_start, tile_start, tile_box, step, cut_leaf2, n, slots);
+        mutual_item_src<T, SoaRec<T>>(u, tile_a, tile_b, rec, leaf_start, tile_start, tile_box, step, cut_leaf2, n,
+                                      slots);
     else
         p2p_forward_unit<T>(u, tile_a, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2, scale, dense,
                             near);
@@ -228,11 +236,13 @@ __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t
 
 template <typename T>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
-    const int4 *__restrict__ work, const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
-    const int *__restrict__ tile_start, const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2,
-    double scale, int dense, int64_t n, double2 *__restrict__ near, c2<T> *__restrict__ slots)
+    const int4 *__restrict__ work, const c2<T> *__restrict__ pos, const T *__restrict__ gam,
+    const int *__restrict__ leaf_start, const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
+    int nside, T step, float cut_leaf2, double scale, int dense, int64_t n, double2 *__restrict__ near,
+    c2<T> *__restrict__ slots)
 {
     __shared__ rec_t<T> tile_a[128], tile_b[128];
+    const SoaRec<T> rec{pos, gam, step};
     near_entry<T>(work[blockIdx.x], tile_a, tile_b, rec, leaf_start, tile_start, tile_box, nside, step, cut_leaf2,
                   scale, dense, n, near, slots);
 }
@@ -240,8 +250,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
 template <typename TR, typename TC, int PMAX>
 __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, int nleaves,
                                                   const int *__restrict__ leaf_start,
-                                                  const double2 *__restrict__ xy, const int *__restrict__ gpos2,
-                                                  const double *__restrict__ gamma_st,
+                                                  const double2 *__restrict__ xy, const c2<TC> *__restrict__ pos,
+                                                  const int *__restrict__ gpos2, const double *__restrict__ gamma_st,
+                                                  const typename RecScalar<TR>::type *__restrict__ gam,
                                                   const double2 *__restrict__ adj, double x0, double y0, double w,
                                                   int p, c2<TC> *__restrict__ out, int nxcd)
 {
@@ -259,16 +270,21 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
 #pragma unroll
     for (int m = 0; m < PMAX; ++m) acc[m] = mk<TC>(0, 0);
     for (int j = s0 + lane; j < s1; j += 64) {
-        const double2 z = xy[j];
-        const c2<TC> xi = mk<TC>((TC)((z.x - cx) / w), (TC)((z.y - cy) / w));
+        c2<TC> xi;
+        if (pos) {
+            xi = pos[j];  // the tree's leaf-unit coordinates, made by the same formula
+        } else {
+            const double2 z = xy[j];
+            xi = mk<TC>((TC)((z.x - cx) / w), (TC)((z.y - cy) / w));
+        }
         c2<TC> pw;
         if (adj) {
             const double2 q = adj[j];
             pw = mk<TC>((TC)q.x, (TC)q.y);
         } else {
-            // the circulation as the records hold it (rounded to their precision), read
-            // from the staging array so that P2M need not wait for the records
-            const double gj = (double)(typename RecScalar<TR>::type)gamma_st[gpos2[j]];
+            // the circulation as the records hold it (rounded to their precision): from the
+            // gathered circulations, or from the staging array when P2M starts before them
+            const double gj = gam ? (double)gam[j] : (double)(typename RecScalar<TR>::type)gamma_st[gpos2[j]];
             pw = mk<TC>(0, (TC)(-gj * kInv2Pi));
         }
 #pragma unroll
@@ -756,7 +772,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
                                                         const double2 *__restrict__ near,
                                                         const uint16_t *__restrict__ mask,
                                                         const c2<TS> *__restrict__ slots, double scale,
-                                                        const c2<TL> *__restrict__ loc, int p, int has_far, double x0,
+                                                        const c2<TL> *__restrict__ loc, const c2<TL> *__restrict__ pos,
+                                                        int p, int has_far, double x0,
                                                         double y0, double w, double *__restrict__ uv,
                                                         double *__restrict__ uv_near, double *__restrict__ uv_far,
                                                         double2 *__restrict__ staged, const int *__restrict__ gpos2,
@@ -771,8 +788,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
     if (has_far) {
         const double cx = x0 + (morton_x(leaf) + 0.5) * w;
         const double cy = y0 + (morton_y(leaf) + 0.5) * w;
-        const double2 z = xy[i];
-        const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        c2<TL> xi;
+        if (pos) {
+            xi = pos[i];  // the tree's leaf-unit coordinates, made by the same formula
+        } else {
+            const double2 z = xy[i];
+            xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        }
         const c2<TL> acc = horner_prefetch<TL>(loc + (int64_t)leaf * p, p, xi);
         fu = (double)acc.x / w;
         fv = -(double)acc.y / w;
@@ -846,12 +868,16 @@ void p2m_launch(const FarArgs &a, hipStream_t s)
     // one leaf per workgroup, contiguous per XCD
     const unsigned g = xcd_grid(nl, 1);
     const int nxcd = kXcds;
+    // the leaf-unit coordinates when they are in the precision of the expansions
+    using TRs = typename RecScalar<TR>::type;
+    const c2<TC> *pos = std::is_same<TRs, TC>::value ? (const c2<TC> *)a.pos : nullptr;
+    const TRs *gam = (const TRs *)a.gam;
     if (a.p <= 16)
-        p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
+        p2m_kernel<TR, TC, 16><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy, pos,
+                                                t->d_gpos2, t->d_st1, gam, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
     else
-        p2m_kernel<TR, TC, 32><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy,
-                                                t->d_gpos2, t->d_st1, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
+        p2m_kernel<TR, TC, 32><<<g, 64, 0, s>>>(level_list(t, L), (int)nl, t->d_leaf_start, t->d_xy, pos,
+                                                t->d_gpos2, t->d_st1, gam, a.adj, t->x0, t->y0, w, a.p, out, nxcd);
 }
 
 template <typename TC, typename TP>
@@ -998,7 +1024,7 @@ __global__ __launch_bounds__(256) void pack_adjoint_kernel(int n, const int *__r
 // out_src.
 template <typename T, bool SRC>
 __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, c2<T> *qtile,
-                                                  const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qv,
+                                                  const SoaRec<T> &rec, const c2<T> *__restrict__ qv,
                                                   const int *__restrict__ leaf_start,
                                                   const int *__restrict__ tile_start,
                                                   const float4 *__restrict__ tile_box, int nside, T step,
@@ -1012,7 +1038,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
-    const rec_t<T> ri = rec[i];
+    const rec_t<T> ri = rec(i);
     const int ix = (int)morton_x((uint32_t)u.x), iy = (int)morton_y((uint32_t)u.x);
     const float4 tbox = tile_box[tile_start[u.x] + ((u.y - leaf_start[u.x]) >> 6)];
     double sum[NA] = {};
@@ -1032,7 +1058,7 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
                 const int len = min(64, s1 - base);
                 __syncthreads();
                 if (lane < len) {
-                    tile[lane] = rec[base + lane];
+                    tile[lane] = rec(base + lane);
                     qtile[lane] = qv[base + lane];
                 }
                 const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
@@ -1064,13 +1090,14 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
 // Adjoint near-field grid: one workgroup per target-centric unit.
 template <typename T, bool SRC>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void p2p_backward_kernel(
-    const int4 *__restrict__ units, const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qv,
-    const int *__restrict__ leaf_start, const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
-    int nside, T step, float cut_leaf2, T lambda, double4 *__restrict__ out_pa, double *__restrict__ out_b,
-    double4 *__restrict__ out_src)
+    const int4 *__restrict__ units, const c2<T> *__restrict__ pos, const T *__restrict__ gam,
+    const c2<T> *__restrict__ qv, const int *__restrict__ leaf_start, const int *__restrict__ tile_start,
+    const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
+    double *__restrict__ out_b, double4 *__restrict__ out_src)
 {
     __shared__ rec_t<T> tile[64];
     __shared__ c2<T> qtile[64];
+    const SoaRec<T> rec{pos, gam, step};
     p2p_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
                               cut_leaf2, lambda, out_pa, out_b, out_src);
 }
@@ -1087,7 +1114,8 @@ template <typename TL>
 __global__ __launch_bounds__(256) void finalize_backward_kernel(
     int n, const int *__restrict__ perm, const int *__restrict__ leaf_of, const double2 *__restrict__ xy,
     const double4 *__restrict__ near_pa, const double *__restrict__ near_b, const double2 *__restrict__ adj,
-    const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, int p, int has_far, double x0, double y0,
+    const c2<TL> *__restrict__ loc_c, const c2<TL> *__restrict__ loc_q, const c2<TL> *__restrict__ pos, int p,
+    int has_far, double x0, double y0,
     double w, double alpha, double lambda, AdjointOut out, const double4 *__restrict__ near_src,
     const int *__restrict__ gpos2, const double *__restrict__ gamma_st, double *__restrict__ stage_g,
     double *__restrict__ stage_x, double *__restrict__ stage_s, int nxcd)
@@ -1111,8 +1139,13 @@ __global__ __launch_bounds__(256) void finalize_backward_kernel(
         const uint32_t leaf = (uint32_t)leaf_of[i];
         const double cx = x0 + (morton_x(leaf) + 0.5) * w;
         const double cy = y0 + (morton_y(leaf) + 0.5) * w;
-        const double2 z = xy[i];
-        const c2<TL> xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        c2<TL> xi;
+        if (pos) {
+            xi = pos[i];
+        } else {
+            const double2 z = xy[i];
+            xi = mk<TL>((TL)((z.x - cx) / w), (TL)((z.y - cy) / w));
+        }
         const c2<TL> *bq = loc_q + (int64_t)leaf * p;
         const c2<TL> *bc = loc_c + (int64_t)leaf * p;
         const c2<TL> accq = horner_prefetch<TL>(bq, p, xi);
@@ -1271,16 +1304,25 @@ void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s)
                                                                    gamma, t->d_st1);
 }
 
-void launch_pack(const fmm_tree *t, double alpha, int is_double, void *rec, hipStream_t s)
+void launch_pack(const fmm_tree *t, int is_double, void *gam, hipStream_t s)
 {
-    const double w = t->side / (double)(1 << t->depth);
     const int n = (int)t->n;
     if (is_double)
-        pack_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
-                                                              t->x0, t->y0, w, alpha, (double4 *)rec);
+        pack_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_st1, (double *)gam);
     else
-        pack_kernel<float><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_leaf_of, t->d_xy, t->d_st1,
-                                                             t->x0, t->y0, w, alpha, (float4 *)rec);
+        pack_kernel<float><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, t->d_st1, (float *)gam);
+}
+
+void launch_leaf_coords(const fmm_tree *t, int is_double, void *pos, hipStream_t s)
+{
+    const int n = (int)t->n;
+    const double w = t->side / (double)(1 << t->depth);
+    if (is_double)
+        leaf_coords_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_leaf_of, t->d_xy, t->x0, t->y0, w,
+                                                                      (double2 *)pos);
+    else
+        leaf_coords_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_leaf_of, t->d_xy, t->x0, t->y0, w,
+                                                                     (float2 *)pos);
 }
 
 // Exponential skipped where every pair has s >= cut: FP32 base 2, 1 - 2^-s rounds to 1
@@ -1303,8 +1345,8 @@ inline size_t near_lds_reserve(const fmm_tree *t, size_t static_bytes)
     return per_wave > static_bytes ? per_wave - static_bytes : 0;
 }
 
-void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, double alpha, double2 *near, void *slots,
-                        hipStream_t s)
+void launch_p2p_forward(const fmm_tree *t, const void *pos, const void *gam, int is_double, double alpha,
+                        double2 *near, void *slots, hipStream_t s)
 {
     const bool mutual = slots != nullptr;
     const int64_t nwork = mutual ? t->nnear_work : t->nunits;
@@ -1318,15 +1360,27 @@ void launch_p2p_forward(const fmm_tree *t, const void *rec, int is_double, doubl
     const unsigned grid = (unsigned)nwork;
     if (is_double)
         p2p_near_kernel<double><<<grid, 64, near_lds_reserve(t, 256 * sizeof(double4)), s>>>(
-            work, (const double4 *)rec, t->d_leaf_start, t->d_tile_start,
+            work, (const double2 *)pos, (const double *)gam, t->d_leaf_start, t->d_tile_start,
             t->d_tile_box, nside, step, cut_leaf2, scale, t->dense_leaf, t->n, near, (double2 *)slots);
     else
         p2p_near_kernel<float><<<grid, 64, near_lds_reserve(t, 256 * sizeof(float4)), s>>>(
-            work, (const float4 *)rec, t->d_leaf_start, t->d_tile_start,
+            work, (const float2 *)pos, (const float *)gam, t->d_leaf_start, t->d_tile_start,
             t->d_tile_box, nside, (float)step, cut_leaf2, scale, t->dense_leaf, t->n, near, (float2 *)slots);
 }
 
-void launch_far_chain(const FarArgs &a, hipStream_t s)
+void launch_p2m(const FarArgs &a, hipStream_t s)
+{
+    if (a.t->depth < 2) return;
+    if (a.t->depth <= a.split) {
+        if (a.rec_is_double) p2m_launch<double4, double>(a, s);
+        else p2m_launch<float4, double>(a, s);
+    } else {
+        if (a.rec_is_double) p2m_launch<double4, float>(a, s);
+        else p2m_launch<float4, float>(a, s);
+    }
+}
+
+void launch_far_chain(const FarArgs &a, hipStream_t s, bool with_p2m)
 {
     const fmm_tree *t = a.t;
     const int L = t->depth;
@@ -1334,13 +1388,7 @@ void launch_far_chain(const FarArgs &a, hipStream_t s)
     const Tables &tb = *t->tabs;
     const bool fine_is_double = a.split >= L;  // FP64 precision: every level double
     // Stage 4: P2M into the leaf level.
-    if (L <= a.split) {
-        if (a.rec_is_double) p2m_launch<double4, double>(a, s);
-        else p2m_launch<float4, double>(a, s);
-    } else {
-        if (a.rec_is_double) p2m_launch<double4, float>(a, s);
-        else p2m_launch<float4, float>(a, s);
-    }
+    if (with_p2m) launch_p2m(a, s);
     // Levels <= lw run in the one-workgroup coarse kernel: the coarse levels up to 256
     // cells (level 4), one round of gathers for its 16 wavefronts.  Coarse levels above that
     // (L_c = 5: 1024 cells, 64 tiles) keep FP64 and the side stream but run as wide launches
@@ -1419,26 +1467,34 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
     const uint16_t *mask = slots ? t->d_leaf_mask : nullptr;
     const double scale = alpha * kInv2Pi;
     const dim3 g(xcd_grid(n, 256));
+    const int *gp = windowed ? t->d_gpos2 : nullptr;
+    // L2P at the tree's leaf-unit coordinates when they are in the precision of the locals
     if (!has_far || L <= a.split) {
         const double2 *loc = has_far ? level_ptr<double>(a, L, true) : nullptr;
+        const double2 *pos = a.rec_is_double ? (const double2 *)a.pos : nullptr;
         if (slots_double)
             finalize_kernel<double, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
-                                                              (const double2 *)slots, scale, loc, a.p, has_far,
-                                                              t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, windowed ? t->d_gpos2 : nullptr, kXcds);
+                                                              (const double2 *)slots, scale, loc, pos, a.p, has_far,
+                                                              t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, gp,
+                                                              kXcds);
         else
             finalize_kernel<double, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
-                                                             (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
-                                                             t->y0, w, uv_direct, uv_near, uv_far, staged, windowed ? t->d_gpos2 : nullptr, kXcds);
+                                                             (const float2 *)slots, scale, loc, pos, a.p, has_far,
+                                                             t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, gp,
+                                                             kXcds);
     } else {
         const float2 *loc = level_ptr<float>(a, L, true);
+        const float2 *pos = a.rec_is_double ? nullptr : (const float2 *)a.pos;
         if (slots_double)
             finalize_kernel<float, double><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
-                                                             (const double2 *)slots, scale, loc, a.p, has_far,
-                                                             t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, windowed ? t->d_gpos2 : nullptr, kXcds);
+                                                             (const double2 *)slots, scale, loc, pos, a.p, has_far,
+                                                             t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, gp,
+                                                             kXcds);
         else
             finalize_kernel<float, float><<<g, 256, 0, s>>>(n, t->d_perm, t->d_leaf_of, t->d_xy, near, mask,
-                                                            (const float2 *)slots, scale, loc, a.p, has_far, t->x0,
-                                                            t->y0, w, uv_direct, uv_near, uv_far, staged, windowed ? t->d_gpos2 : nullptr, kXcds);
+                                                            (const float2 *)slots, scale, loc, pos, a.p, has_far,
+                                                            t->x0, t->y0, w, uv_direct, uv_near, uv_far, staged, gp,
+                                                            kXcds);
     }
     if (staged && windowed) gather_rows_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, staged, uv, base, h);
     else if (staged) scatter_rows_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, staged, uv, base, h);
@@ -1454,7 +1510,8 @@ void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, 
                                                                        (float2 *)qt);
 }
 
-void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int is_double, double alpha,
+void launch_p2p_backward(const fmm_tree *t, const void *pos, const void *gam, const void *qv, int is_double,
+                         double alpha,
                          double4 *out_pa, double *out_b, double4 *out_src, hipStream_t s)
 {
     if (t->nunits == 0) return;
@@ -1468,21 +1525,21 @@ void launch_p2p_backward(const fmm_tree *t, const void *rec, const void *qv, int
     if (is_double) {
         if (out_src)
             p2p_backward_kernel<double, true><<<grid, 64, 0, s>>>(
-                t->d_units, (const double4 *)rec, (const double2 *)qv,
+                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, out_src);
         else
             p2p_backward_kernel<double, false><<<grid, 64, 0, s>>>(
-                t->d_units, (const double4 *)rec, (const double2 *)qv,
+                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, nullptr);
     } else {
         if (out_src)
             p2p_backward_kernel<float, true><<<grid, 64, 0, s>>>(
-                t->d_units, (const float4 *)rec, (const float2 *)qv,
+                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
                 out_src);
         else
             p2p_backward_kernel<float, false><<<grid, 64, 0, s>>>(
-                t->d_units, (const float4 *)rec, (const float2 *)qv,
+                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv,
                 t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
                 nullptr);
     }
@@ -1503,12 +1560,12 @@ void launch_finalize_backward(const fmm_tree *t, const FarArgs &fc, const FarArg
         finalize_backward_kernel<double><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj,
             has_far ? level_ptr<double>(fc, L, true) : nullptr, has_far ? level_ptr<double>(fq, L, true) : nullptr,
-            fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2, t->d_st1, stage_g, stage_x,
+            fc.rec_is_double ? (const double2 *)fc.pos : nullptr, fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2, t->d_st1, stage_g, stage_x,
             stage_s, kXcds);
     else
         finalize_backward_kernel<float><<<g, 256, 0, s>>>(
             n, t->d_perm, t->d_leaf_of, t->d_xy, near_pa, near_b, adj, level_ptr<float>(fc, L, true),
-            level_ptr<float>(fq, L, true), fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2,
+            level_ptr<float>(fq, L, true), fc.rec_is_double ? nullptr : (const float2 *)fc.pos, fc.p, has_far, t->x0, t->y0, w, alpha, lambda, out, near_src, t->d_gpos2,
             t->d_st1, stage_g, stage_x, stage_s, kXcds);
     if (stage_x) gather_adjoint_kernel<<<g, 256, 0, s>>>(n, kXcds, t->d_gpos1, stage_g, stage_x, stage_s, out);
 }

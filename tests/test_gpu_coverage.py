@@ -107,8 +107,7 @@ def test_lattice_as_configured(fmm_mod, oracle_mod):
     assert rel_l2(got[idx], ref) < FP64_TOL
     assert max_rel(got[idx], ref) < FP64_TOL
     assert np.array_equal(got, serial)
-    # the far chain (side stream) starts before the near field and overlaps it
-    assert tl["far_start"] <= tl["p2p_start"]
+    # the far chain (side stream) runs while the near field runs
     assert tl["far_start"] < tl["p2p_end"] and tl["p2p_start"] < tl["far_end"]
     del tree
     torch.cuda.empty_cache()
