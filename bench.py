@@ -146,7 +146,7 @@ def lattice_overlap_leg(torch, dev, workloads, steps):
     tree.set_option(_lib.FMM_OPT_COARSE_LEVEL, 5)
     out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
     res = {}
-    for sched in (0, 1):
+    for sched in (0, 1):  # concurrent, then serialised
         tree.set_option(_lib.FMM_OPT_SCHEDULE, sched)
         for _ in range(3):
             tree.velocity(g, w.sigma, w.p, "fp64", out=out)
@@ -194,7 +194,7 @@ def cost_model_leg(torch, dev, workloads):
                     continue
                 tree.set_option(_lib.FMM_OPT_COARSE_LEVEL, lc)
                 res = {}
-                for sched in (1, 0):
+                for sched in (1, 0):  # serialised, then concurrent
                     tree.set_option(_lib.FMM_OPT_SCHEDULE, sched)
                     for _ in range(2):
                         tree.velocity(g, w.sigma, w.p, "mixed", out=out)
@@ -501,7 +501,7 @@ def main():
     tree.set_option(_lib.FMM_OPT_SCHEDULE, 1)
     run(1)
     ms_serial, stages_serial = timed(args.steps)
-    tree.set_option(_lib.FMM_OPT_SCHEDULE, 0)
+    tree.set_option(_lib.FMM_OPT_SCHEDULE, 2)  # back to the default (automatic)
     log(f"[bench] mixed serial: {ms_serial:.3f} ms/step, stages {stages_serial}")
     # overlap fraction: how much of the shorter of P2P / far field is hidden, from the
     # serial stage times and the overlapped span between the pack and final stages

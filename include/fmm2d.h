@@ -59,8 +59,12 @@ enum {
 
 /* Options for fmm_set_option. */
 enum {
-    FMM_OPT_SCHEDULE = 1,     /* 0: far field on a second stream, concurrent with P2P (default);
-                                 1: everything serialised on the main stream */
+    FMM_OPT_SCHEDULE = 1,     /* 0: far field on a second stream, concurrent with P2P;
+                                 1: everything serialised on the main stream;
+                                 2 (default): per call from the tree's predicted far/near time
+                                 ratio: serialised in the mixed form when the far field is
+                                 predicted the longer part (where overlapping measured slower on
+                                 one GPU), concurrent otherwise and in FP64 */
     FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in FP64 on the far-
                                  field stream (default 3, range 1..depth); those of them with at
                                  most 256 cells (levels <= 4) in one single-workgroup kernel, the
@@ -74,10 +78,11 @@ enum {
                                  for both particles (the kernel is odd), the rest from the target
                                  end; 0: every pair from the target end.  Results agree to rounding. */
     FMM_OPT_DENSE_LEAF = 7,   /* particles that make a leaf dense for FMM_OPT_NEAR_MUTUAL (default 32) */
-    FMM_OPT_NEAR_OCCUPANCY = 8, /* 1..8: with FMM_OPT_SCHEDULE 0 the forward near-field kernel keeps at
+    FMM_OPT_NEAR_OCCUPANCY = 8, /* 1..8: in a concurrent call the forward near-field kernel keeps at
                                   most this many wavefronts per SIMD resident (by reserving LDS),
                                   leaving room for the far field beside it; 0 = no cap; -1 (default)
-                                  = 5 or none per call, from the predicted far/near time ratio */
+                                  = per call from the predicted far/near time ratio (mixed: 5 or
+                                  none; FP64: 2 or none) */
     FMM_OPT_VALIDATE = 9      /* 1: every evaluation first checks the circulations (and an adjoint
                                  call its dL/du) for NaN and infinities on the device and returns
                                  FMM_EINVAL, naming the lowest particle index, before any other

@@ -33,8 +33,13 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = [os.path.join(_HERE, f) for f in ("fmm_oracle.c", "adaptive_oracle.c")]
+# ORACLE_SANITIZE=1 selects a build with AddressSanitizer and UndefinedBehaviorSanitizer
+# (the process must preload gcc's libasan; tests/test_sanitizers.py runs the oracle's pins so)
+SANITIZE = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
 _lib = None
 
 ORC_OK, ORC_EINVAL, ORC_ENOMEM, ORC_ERANGE = 0, -1, -2, -4
@@ -45,9 +50,11 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle's C sources with gcc into liboracle.so (in place)."""
+    """Compile the oracle's C sources with gcc into liboracle.so (in place), or with
+    ORACLE_SANITIZE=1 into liboracle_san.so with the sanitizers."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", *_SRCS, "-o", _SO + ".tmp", "-lm"]
+        opt = SANITIZE_FLAGS if SANITIZE else ["-O2"]
+        cmd = ["gcc", *opt, "-std=gnu11", "-fopenmp", "-fPIC", "-shared", *_SRCS, "-o", _SO + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
     return _SO

@@ -392,6 +392,12 @@ void orc_atree_sizes(const atree *t, int64_t *s)
 
 /* Cells (level, ix, iy, leaf, count, parent) as int64 rows of 6, the leaf of each
  * source, and the four lists (offsets nnodes + 1, indices). */
+/* count int64 values; an empty list may have no array at all (memcpy's pointers must not be NULL) */
+static void copy_i64(int64_t *dst, const int64_t *src, int64_t count)
+{
+    if (count > 0) memcpy(dst, src, sizeof(int64_t) * (size_t)count);
+}
+
 void orc_atree_export(const atree *t, int64_t *cells, int64_t *leaf_of, int64_t *uo, int64_t *ui, int64_t *vo,
                       int64_t *vi, int64_t *wo, int64_t *wi, int64_t *xo, int64_t *xi)
 {
@@ -401,15 +407,15 @@ void orc_atree_export(const atree *t, int64_t *cells, int64_t *leaf_of, int64_t 
         int64_t *r = cells + 6 * k;
         r[0] = b->level, r[1] = b->ix, r[2] = b->iy, r[3] = b->leaf, r[4] = b->count, r[5] = b->parent;
     }
-    memcpy(leaf_of, t->leaf_of, sizeof(int64_t) * t->n);
-    memcpy(uo, t->U.off, sizeof(int64_t) * (nn + 1));
-    memcpy(vo, t->V.off, sizeof(int64_t) * (nn + 1));
-    memcpy(wo, t->W.off, sizeof(int64_t) * (nn + 1));
-    memcpy(xo, t->X.off, sizeof(int64_t) * (nn + 1));
-    memcpy(ui, t->U.idx, sizeof(int64_t) * t->U.off[nn]);
-    memcpy(vi, t->V.idx, sizeof(int64_t) * t->V.off[nn]);
-    memcpy(wi, t->W.idx, sizeof(int64_t) * t->W.off[nn]);
-    memcpy(xi, t->X.idx, sizeof(int64_t) * t->X.off[nn]);
+    copy_i64(leaf_of, t->leaf_of, t->n);
+    copy_i64(uo, t->U.off, nn + 1);
+    copy_i64(vo, t->V.off, nn + 1);
+    copy_i64(wo, t->W.off, nn + 1);
+    copy_i64(xo, t->X.off, nn + 1);
+    copy_i64(ui, t->U.idx, t->U.off[nn]);
+    copy_i64(vi, t->V.idx, t->V.off[nn]);
+    copy_i64(wi, t->W.idx, t->W.off[nn]);
+    copy_i64(xi, t->X.idx, t->X.off[nn]);
 }
 
 /* ------------------------------------------------------------------------------ */

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm2d.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "tree_build.hip", "adaptive.hip", "adaptive_build.hip", "tables.cpp", "api.cpp",
-           "adaptive.cpp"]
+           "adaptive.cpp", "host_tree.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 arithmetic is switched off for the device code (the compiler would
@@ -31,8 +31,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, extra: list[str]) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+# A build whose host code runs under AddressSanitizer and UndefinedBehaviorSanitizer (device
+# code unchanged): each -fsanitize= applies to the host compilation only.
+HOST_SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                       "-Xarch_host", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def _compile(src: str, extra: list[str], build_dir: str = BUILD_DIR) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     cmd = [hipcc(), "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
            "-Wall", "-Wno-unused-function", *DEVICE_FLAGS, *extra, os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -41,21 +47,27 @@ def _compile(src: str, extra: list[str]) -> str:
     return obj
 
 
-def build_library(extra: list[str] | None = None, verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libfmm2d.so; always rebuilds."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    extra = list(extra or [])
+def build_library(extra: list[str] | None = None, verbose: bool = False, lib: str = LIB,
+                  build_dir: str = BUILD_DIR, host_sanitize: bool = False) -> str:
+    """Compile every source for gfx950 and link the library (libfmm2d.so in place by
+    default); always rebuilds.  host_sanitize: the host code under the sanitizers (a test
+    build, loaded with gcc's libasan preloaded)."""
+    os.makedirs(build_dir, exist_ok=True)
+    extra = list(extra or []) + (HOST_SANITIZE_FLAGS if host_sanitize else [])
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", *objs, "-o", tmp]
+        objs = list(ex.map(lambda s: _compile(s, extra, build_dir), SOURCES))
+    tmp = lib + ".tmp"
+    link_extra = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+                  "-shared-libsan"] if host_sanitize else []
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", *link_extra, *objs,
+           "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

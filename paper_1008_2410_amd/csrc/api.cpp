@@ -220,30 +220,49 @@ FarArgs far_args(const fmm_tree *t, const Workspace &ws, int p, int precision, b
 // with the counts a launch pays for):
 //   T_near = kNear0 + kNearPair pairs + kNearVisit 9 N_leaves,
 //   T_far  = kFar0 + kFarCell C_fine + kFarCoarse C_coarse + kFarLevel (L - L_c).
-constexpr double kNear0 = 0.075, kNearPair = 2.12e-10, kNearVisit = 1.76e-7;
-constexpr double kFar0 = 0.128, kFarCell = 1.18e-6, kFarCoarse = 5.32e-4, kFarLevel = 0.0238;
+constexpr double kNear0 = 0.070, kNearPair = 1.95e-10, kNearVisit = 1.74e-7;
+constexpr double kFar0 = 0.268, kFarCell = 1.32e-6, kFarCoarse = 4.87e-5, kFarLevel = 0.00216;
 
-// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic, from the
-// predicted far/near time ratio of the mixed form (the model above):
-//  - mixed: capping the near field at 5 wavefronts per SIMD slows it by ~12-18% and lets
-//    the far chain run beside it; measured on uniform and clustered workloads that pays
-//    when the far field takes between 0.12 and 1 times the near field (below, the far
-//    field is too short to hide anything; above, the far kernels need more of the chip
-//    than the cap leaves);
-//  - FP64: the near field (at most 4 wavefronts per SIMD) capped at 2 when the far field
-//    is the longer part (ratio >= 1): the 1024^2 lattice, depth 8, p = 12, coarse levels
-//    <= 5 took 0.78 ms against 0.90 uncapped or serialised (caps 1, 3, 4: 1.04, 1.02,
-//    0.95 ms); with a short far field (2^24 patches) every cap was slower than none.
-int choose_occupancy(const fmm_tree *t, int precision)
+// Predicted far-field / near-field time of the tree (the model above).
+double far_near_ratio(const fmm_tree *t)
 {
-    if (t->near_occupancy >= 0) return t->near_occupancy;
-    if (t->schedule != 0 || t->depth < 2) return 0;
     const int lc = std::min(t->lc, t->depth);
     double fine = 0, coarse = 0;
     for (int l = 2; l <= t->depth; ++l) (l <= lc ? coarse : fine) += (double)t->list_len[l];
     const double near = kNear0 + kNearPair * (double)t->p2p_pairs + kNearVisit * 9.0 * (double)t->nonempty_leaves;
     const double far = kFar0 + kFarCell * fine + kFarCoarse * coarse + kFarLevel * (t->depth - lc);
-    const double ratio = far / near;
+    return far / near;
+}
+
+// Whether a call runs the far chain beside the near field (FMM_OPT_SCHEDULE 0), after it
+// (1), or by the model (2, the default): on one GPU both are throughput work on the same
+// CUs, and in the mixed form overlapping measured slower than serialising whenever the far
+// field is the longer part (uniform 2^20 particles at depths 7-9: -0.07 to -0.23 of the
+// far time; 2^22 at depth 9: -0.02), so such calls are serialised.  FP64 calls overlap (the
+// FP64 near field leaves issue slots that the far chain uses: 0.78 against 0.90 ms on the
+// 1024^2 lattice).
+bool call_overlaps(const fmm_tree *t, int precision)
+{
+    if (t->schedule != 2) return t->schedule == 0;
+    if (precision == FMM_FP64 || t->depth < 2) return true;
+    return far_near_ratio(t) <= 1.0;
+}
+
+// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic, from the
+// predicted far/near time ratio:
+//  - mixed: capping the near field at 5 wavefronts per SIMD slows it by ~12-18% and lets
+//    the far chain run beside it; measured on uniform and clustered workloads that pays
+//    when the far field takes between 0.12 and 1 times the near field (below, the far
+//    field is too short to hide anything; above, the call is serialised);
+//  - FP64: the near field (at most 4 wavefronts per SIMD) capped at 2 when the far field
+//    is the longer part (ratio >= 1): the 1024^2 lattice, depth 8, p = 12, coarse levels
+//    <= 5 took 0.78 ms against 0.90 uncapped or serialised (caps 1, 3, 4: 1.04, 1.02,
+//    0.95 ms); with a short far field (2^24 patches) every cap was slower than none.
+int choose_occupancy(const fmm_tree *t, int precision, bool overlap)
+{
+    if (!overlap || t->depth < 2) return 0;
+    if (t->near_occupancy >= 0) return t->near_occupancy;
+    const double ratio = far_near_ratio(t);
     if (precision == FMM_FP64) return ratio >= 1.0 ? 2 : 0;
     return (ratio >= 0.12 && ratio <= 1.0) ? 5 : 0;
 }
@@ -354,14 +373,14 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     const void *pos = noalloc && local.sums ? local.sums : t->d_pos[precision == FMM_FP64];
 
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
-    const bool overlap = t->schedule == 0;
+    const bool overlap = call_overlaps(t, precision);
     if (!overlap) ss = ms;
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
     FarArgs a = far_args(t, ws, p, precision, false);
     a.pos = pos;
     a.gam = nullptr;  // P2M starts before the circulations are gathered: it reads the staging array
-    t->occupancy_in_use = choose_occupancy(t, precision);
+    t->occupancy_in_use = choose_occupancy(t, precision, overlap);
     // beside a capped near field the coarse kernel must fit in one wavefront per SIMD
     if (overlap && t->occupancy_in_use > 0) a.coarse_threads = 256;
     Timing tm;
@@ -525,227 +544,45 @@ extern "C" int fmm_build_tree_host(const double *xy, int64_t n, int depth, const
     if (rc0) return rc0;
     try {
         hipStream_t s = (hipStream_t)stream;
-
         std::vector<double> h(2 * (size_t)n);
-        {
-            hipError_t e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) {
-                free_tree(t);
-                return hip_fail(e, "copying positions to the host");
-            }
+        hipError_t e = hipMemcpyAsync(h.data(), xy, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            free_tree(t);
+            return hip_fail(e, "copying positions to the host");
         }
-        for (double v : h)
-            if (!std::isfinite(v)) {
-                free_tree(t);
-                return fail(FMM_EINVAL, "non-finite particle position");
-            }
-        if (root_box) {
-            t->x0 = root_box[0];
-            t->y0 = root_box[1];
-            t->side = root_box[2];
-        } else {
-            double xmin = h[0], xmax = h[0], ymin = h[1], ymax = h[1];
-            for (int64_t i = 1; i < n; ++i) {
-                xmin = std::min(xmin, h[2 * i]);
-                xmax = std::max(xmax, h[2 * i]);
-                ymin = std::min(ymin, h[2 * i + 1]);
-                ymax = std::max(ymax, h[2 * i + 1]);
-            }
-            double side = std::max(xmax - xmin, ymax - ymin);
-            if (side <= 0.0) side = 1.0;
-            t->x0 = xmin;
-            t->y0 = ymin;
-            t->side = side * (1.0 + 1.0 / 1048576.0);
+        UniformHostTree ht;
+        int64_t bad = -1;
+        std::string err;
+        int rc = build_host_tree(h.data(), n, depth, root_box, ht, bad, err);
+        if (rc) {
+            free_tree(t);
+            return fail(rc, err);
         }
-        const int L = depth;
-        const int nside = 1 << L;
-        const int64_t nleaf = int64_t(1) << (2 * L);
-        const double w = t->side / (double)nside;
-
-        // Stage 2: leaf of each particle, floor binning clamped at the top edge; and a
-        // sub-leaf key (Morton index in a 64 x 64 grid over the leaf) that orders the
-        // particles inside a leaf so that 64-particle tiles are spatially compact.
-        std::vector<uint32_t> key((size_t)n);
-        std::vector<uint16_t> sub((size_t)n);
-        for (int64_t i = 0; i < n; ++i) {
-            uint32_t c[2], f[2];
-            for (int d = 0; d < 2; ++d) {
-                const double v = (h[2 * i + d] - (d ? t->y0 : t->x0)) / w;
-                if (!(v >= 0.0) || v > (double)nside) {
-                    free_tree(t);
-                    char buf[160];
-                    snprintf(buf, sizeof buf, "particle %lld lies outside the root cell", (long long)i);
-                    return fail(FMM_ERANGE, buf);
-                }
-                int64_t k = (int64_t)std::floor(v);
-                c[d] = (uint32_t)std::min<int64_t>(k, nside - 1);
-                f[d] = (uint32_t)std::min<int64_t>((int64_t)std::floor((v - c[d]) * 64.0), 63);
-            }
-            key[i] = morton_encode(c[0], c[1]);
-            sub[i] = (uint16_t)morton_encode(f[0], f[1]);
-        }
-        // Stable counting sort by leaf Morton key.
-        std::vector<int> leaf_start((size_t)nleaf + 1, 0);
-        for (int64_t i = 0; i < n; ++i) leaf_start[key[i] + 1]++;
-        for (int64_t c = 0; c < nleaf; ++c) leaf_start[c + 1] += leaf_start[c];
-        std::vector<int> perm((size_t)n), leaf_of((size_t)n);
-        {
-            std::vector<int> fill(leaf_start.begin(), leaf_start.end() - 1);
-            for (int64_t i = 0; i < n; ++i) {
-                const int pos = fill[key[i]]++;
-                perm[pos] = (int)i;
-                leaf_of[pos] = (int)key[i];
-            }
-            // inside each leaf: by sub-leaf key, ties by user index
-            for (int64_t c = 0; c < nleaf; ++c)
-                if (leaf_start[c + 1] - leaf_start[c] > 1)
-                    std::stable_sort(perm.begin() + leaf_start[c], perm.begin() + leaf_start[c + 1],
-                                     [&](int a, int b) { return sub[a] < sub[b]; });
-        }
-        // Staging slots of the two-pass permutation into sorted order: bucket = sorted slot
-        // >> shift, ordered by user index inside a bucket; a bucket's segment of the
-        // staging array is the slot range of the bucket itself.
-        int shift = kStageShiftMin;
-        while ((((n - 1) >> shift) + 1) > 256) ++shift;
-        t->stage_shift = shift;
-        std::vector<int> gpos1((size_t)n), gpos2((size_t)n);
-        {
-            std::vector<int> inv((size_t)n);
-            for (int64_t k = 0; k < n; ++k) inv[perm[k]] = (int)k;
-            std::vector<int64_t> fill(256);
-            for (int64_t b = 0; b < 256; ++b) fill[b] = b << shift;
-            for (int64_t u = 0; u < n; ++u) gpos1[u] = (int)fill[inv[u] >> shift]++;
-            for (int64_t k = 0; k < n; ++k) gpos2[k] = gpos1[perm[k]];
-        }
-        std::vector<double2> xys((size_t)n);
-        for (int64_t k = 0; k < n; ++k) {
-            xys[k].x = h[2 * (size_t)perm[k]];
-            xys[k].y = h[2 * (size_t)perm[k] + 1];
-        }
-        // 64-particle tiles of each leaf and their bounding boxes in leaf units about the
-        // leaf centre, rounded outwards to FP32.
-        std::vector<int> tile_start((size_t)nleaf + 1, 0);
-        for (int64_t c = 0; c < nleaf; ++c)
-            tile_start[c + 1] = tile_start[c] + (leaf_start[c + 1] - leaf_start[c] + 63) / 64;
-        std::vector<float4> tile_box((size_t)tile_start[nleaf]);
-        for (int64_t c = 0; c < nleaf; ++c) {
-            const double cx = t->x0 + (morton_x((uint32_t)c) + 0.5) * w;
-            const double cy = t->y0 + (morton_y((uint32_t)c) + 0.5) * w;
-            for (int b = leaf_start[c], tt = tile_start[c]; b < leaf_start[c + 1]; b += 64, ++tt) {
-                double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
-                for (int k = b; k < std::min(b + 64, leaf_start[c + 1]); ++k) {
-                    const double xl = (xys[k].x - cx) / w, yl = (xys[k].y - cy) / w;
-                    xmin = std::min(xmin, xl);
-                    xmax = std::max(xmax, xl);
-                    ymin = std::min(ymin, yl);
-                    ymax = std::max(ymax, yl);
-                }
-                float4 bx;
-                bx.x = std::nextafter((float)xmin, -INFINITY);
-                bx.y = std::nextafter((float)ymin, -INFINITY);
-                bx.z = std::nextafter((float)xmax, INFINITY);
-                bx.w = std::nextafter((float)ymax, INFINITY);
-                tile_box[tt] = bx;
-            }
-        }
-        // Occupancy of every cell of every level (global cell index).
-        std::vector<int> counts((size_t)level_base(L + 1), 0);
-        for (int64_t c = 0; c < nleaf; ++c) counts[level_base(L) + c] = leaf_start[c + 1] - leaf_start[c];
-        for (int l = L - 1; l >= 0; --l)
-            for (int64_t c = 0; c < (int64_t(1) << (2 * l)); ++c) {
-                const int *ch = &counts[level_base(l + 1) + 4 * c];
-                counts[level_base(l) + c] = ch[0] + ch[1] + ch[2] + ch[3];
-            }
-        // Non-empty cells of levels 2..L, grouped by parity class (Morton & 3).
-        std::vector<int> lists;
-        t->list_off.assign(L + 1, 0);
-        t->list_len.assign(L + 1, 0);
-        t->class_off.assign(4 * (L + 1), 0);
-        for (int l = 2; l <= L; ++l) {
-            t->list_off[l] = (int64_t)lists.size();
-            const int64_t nc = int64_t(1) << (2 * l);
-            for (int par = 0; par < 4; ++par) {
-                t->class_off[4 * l + par] = (int64_t)lists.size() - t->list_off[l];
-                for (int64_t c = par; c < nc; c += 4)
-                    if (counts[level_base(l) + c] > 0) lists.push_back((int)c);
-            }
-            t->list_len[l] = (int64_t)lists.size() - t->list_off[l];
-        }
-        // Statistics: pairs (section "Complexity Estimates" direct work), M2L pairs.
-        auto leaf_count = [&](int x, int y) -> int64_t {
-            if (x < 0 || y < 0 || x >= nside || y >= nside) return 0;
-            return counts[level_base(L) + morton_encode((uint32_t)x, (uint32_t)y)];
-        };
-        int64_t pairs = 0, nonempty = 0, maxleaf = 0;
-        // Stage 9 work units: target chunks of <= 64 in each non-empty leaf.
-        std::vector<int4> units;
-        std::vector<int64_t> cost;
-        for (int64_t c = 0; c < nleaf; ++c) {
-            const int nt = leaf_start[c + 1] - leaf_start[c];
-            if (nt == 0) continue;
-            ++nonempty;
-            maxleaf = std::max<int64_t>(maxleaf, nt);
-            const int x = (int)morton_x((uint32_t)c), y = (int)morton_y((uint32_t)c);
-            int64_t nsrc = 0;
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) nsrc += leaf_count(x + dx, y + dy);
-            pairs += (int64_t)nt * nsrc;
-            for (int c0 = 0; c0 < nt; c0 += 64) {
-                const int cnt = std::min(64, nt - c0);
-                int logtp = 0;
-                while ((1 << logtp) < cnt) ++logtp;
-                const int kstride = 64 >> logtp;
-                int4 u;
-                u.x = (int)c;
-                u.y = leaf_start[c] + c0;
-                u.z = cnt;
-                u.w = logtp;
-                units.push_back(u);
-                cost.push_back((nsrc + kstride - 1) / kstride);
-            }
-        }
-        t->p2p_pairs = pairs - n;
-        t->nonempty_leaves = nonempty;
-        t->max_leaf = maxleaf;
-        int64_t m2l = 0;
-        for (int l = 2; l <= L; ++l) {
-            const int n1 = 1 << l;
-            const int *lst = lists.data() + t->list_off[l];
-            for (int64_t k = 0; k < t->list_len[l]; ++k) {
-                const int tx = (int)morton_x((uint32_t)lst[k]), ty = (int)morton_y((uint32_t)lst[k]);
-                const int qx = tx & 1, qy = ty & 1;
-                for (int dy = -2 - qy; dy <= 3 - qy; ++dy)
-                    for (int dx = -2 - qx; dx <= 3 - qx; ++dx) {
-                        if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-                        const int sx = tx + dx, sy = ty + dy;
-                        if (sx < 0 || sy < 0 || sx >= n1 || sy >= n1) continue;
-                        if (counts[level_base(l) + morton_encode((uint32_t)sx, (uint32_t)sy)] > 0) ++m2l;
-                    }
-            }
-        }
-        t->m2l_pairs = m2l;
-        // Heaviest units first so the tail of the launch is short.
-        std::vector<int64_t> order(units.size());
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-        std::vector<int4> sorted_units(units.size());
-        for (size_t k = 0; k < order.size(); ++k) sorted_units[k] = units[order[k]];
-        t->nunits = (int64_t)sorted_units.size();
-
-        int rc = FMM_OK;
-        if (!rc) rc = upload(&t->d_perm, perm, "permutation");
-        if (!rc) rc = upload(&t->d_gpos1, gpos1, "staging slots");
-        if (!rc) rc = upload(&t->d_gpos2, gpos2, "staging slots");
+        t->x0 = ht.x0;
+        t->y0 = ht.y0;
+        t->side = ht.side;
+        t->stage_shift = ht.stage_shift;
+        t->list_off = ht.list_off;
+        t->list_len = ht.list_len;
+        t->class_off = ht.class_off;
+        t->p2p_pairs = ht.p2p_pairs;
+        t->m2l_pairs = ht.m2l_pairs;
+        t->nonempty_leaves = ht.nonempty_leaves;
+        t->max_leaf = ht.max_leaf;
+        t->nunits = (int64_t)ht.units.size();
+        if (!rc) rc = upload(&t->d_perm, ht.perm, "permutation");
+        if (!rc) rc = upload(&t->d_gpos1, ht.gpos1, "staging slots");
+        if (!rc) rc = upload(&t->d_gpos2, ht.gpos2, "staging slots");
         if (!rc) rc = dev_alloc(&t->d_st1, n, "staging array");
-        if (!rc) rc = upload(&t->d_leaf_of, leaf_of, "leaf ids");
-        if (!rc) rc = upload(&t->d_xy, xys, "sorted positions");
-        if (!rc) rc = upload(&t->d_leaf_start, leaf_start, "leaf offsets");
-        if (!rc) rc = upload(&t->d_counts, counts, "cell counts");
-        if (!rc) rc = upload(&t->d_lists, lists, "cell lists");
-        if (!rc) rc = upload(&t->d_units, sorted_units, "P2P work units");
-        if (!rc) rc = upload(&t->d_tile_start, tile_start, "tile offsets");
-        if (!rc) rc = upload(&t->d_tile_box, tile_box, "tile boxes");
+        if (!rc) rc = upload(&t->d_leaf_of, ht.leaf_of, "leaf ids");
+        if (!rc) rc = upload_as(&t->d_xy, ht.xy, "sorted positions");
+        if (!rc) rc = upload(&t->d_leaf_start, ht.leaf_start, "leaf offsets");
+        if (!rc) rc = upload(&t->d_counts, ht.counts, "cell counts");
+        if (!rc) rc = upload(&t->d_lists, ht.lists, "cell lists");
+        if (!rc) rc = upload_as(&t->d_units, ht.units, "P2P work units");
+        if (!rc) rc = upload(&t->d_tile_start, ht.tile_start, "tile offsets");
+        if (!rc) rc = upload_as(&t->d_tile_box, ht.tile_box, "tile boxes");
         if (!rc) rc = finish_tree(t, s);
         if (rc) {
             free_tree(t);
@@ -878,8 +715,9 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
 
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
-    const bool overlap = t->schedule == 0;
+    const bool overlap = call_overlaps(t, precision);
     if (!overlap) ss = ms;
+    t->occupancy_in_use = 0;  // the adjoint's near field is not capped
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
     const FarArgs fc = far_args(t, ws, p, precision, false);
@@ -968,7 +806,7 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
     if (!t) return fail(FMM_ESTATE, "null tree handle");
     switch (key) {
     case FMM_OPT_SCHEDULE:
-        if (value != 0 && value != 1) return fail(FMM_EINVAL, "schedule must be 0 or 1");
+        if (value < 0 || value > 2) return fail(FMM_EINVAL, "schedule must be 0, 1 or 2");
         t->schedule = (int)value;
         return FMM_OK;
     case FMM_OPT_COARSE_LEVEL:

@@ -70,6 +70,20 @@ int upload(T **p, const std::vector<T> &h, const char *what)
     return FMM_OK;
 }
 
+// upload for host structs laid out as the device vector type D (HostD2 -> double2, ...)
+template <typename D, typename H>
+int upload_as(D **p, const std::vector<H> &h, const char *what)
+{
+    static_assert(sizeof(D) == sizeof(H), "host and device element layouts differ");
+    int rc = dev_alloc(p, h.size(), what);
+    if (rc) return rc;
+    if (!h.empty()) {
+        hipError_t e = hipMemcpy(*p, h.data(), h.size() * sizeof(D), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    return FMM_OK;
+}
+
 }  // namespace fmm
 
 #define HIP_TRY(expr)                                           \

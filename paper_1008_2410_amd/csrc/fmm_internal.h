@@ -11,44 +11,15 @@
 #include <string>
 #include <vector>
 
+#include "host_tree.h"
+#include "morton.h"
+
 namespace fmm {
 
 constexpr int kMaxDepth = 12;
 constexpr int kMaxP = 32;
 constexpr int kNumEvents = 8;
 
-// ---------------------------------------------------------------------------------
-// Morton order: x in the even bits, y in the odd bits.  The four children of cell k
-// at level l are 4k + q at level l + 1 with q = (child x bit) | (child y bit) << 1,
-// so siblings are adjacent and a cell's parity class is k & 3.
-// ---------------------------------------------------------------------------------
-__host__ __device__ inline uint32_t spread_bits(uint32_t v)
-{
-    v &= 0x0000ffffu;
-    v = (v | (v << 8)) & 0x00ff00ffu;
-    v = (v | (v << 4)) & 0x0f0f0f0fu;
-    v = (v | (v << 2)) & 0x33333333u;
-    v = (v | (v << 1)) & 0x55555555u;
-    return v;
-}
-
-__host__ __device__ inline uint32_t gather_bits(uint32_t v)
-{
-    v &= 0x55555555u;
-    v = (v | (v >> 1)) & 0x33333333u;
-    v = (v | (v >> 2)) & 0x0f0f0f0fu;
-    v = (v | (v >> 4)) & 0x00ff00ffu;
-    v = (v | (v >> 8)) & 0x0000ffffu;
-    return v;
-}
-
-__host__ __device__ inline uint32_t morton_encode(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
-__host__ __device__ inline uint32_t morton_x(uint32_t m) { return gather_bits(m); }
-__host__ __device__ inline uint32_t morton_y(uint32_t m) { return gather_bits(m >> 1); }
-
-// First global cell index of level l when all levels are stored back to back:
-// sum_{k<l} 4^k = (4^l - 1)/3.
-__host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
 
 // ---------------------------------------------------------------------------------
 // Device-side tables for one expansion order p (radius-scaled operators, level
@@ -79,7 +50,6 @@ constexpr int64_t kCoefPad = 64;
 // Permutation staging: buckets of at least 2^kStageShiftMin sorted slots (a 1 MiB gather
 // window of FP64) and at most 256 of them; the number of XCDs that workgroups are dealt
 // to round-robin.
-constexpr int kStageShiftMin = 17;
 constexpr int kXcds = 8;
 constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;  // MI355X Infinity Cache
 // Flag (in w) of a mutual item in the near-field work list.
@@ -127,12 +97,12 @@ struct fmm_tree {
     int device = 0;
     int num_cus = 256;   // compute units of the device
     int lc = 3;          // coarse-level cutoff L_c
-    int schedule = 0;    // 0 overlap, 1 serial
+    int schedule = 2;    // 0 overlap, 1 serial, 2 by the cost model (FMM_OPT_SCHEDULE)
     int near_mutual = 1; // pairs of dense leaves evaluated once for both particles
     int dense_leaf = 32; // a leaf with at least this many particles is dense
     int near_occupancy = -1; // cap on forward near-field wavefronts per SIMD beside the far field
                              // (0: none, -1: chosen per call from the cost model)
-    int occupancy_in_use = 0; // the cap of the current call
+    int occupancy_in_use = 0; // the cap of the current call (0 when serialised)
     int timing = 0;
     int validate = 0;    // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf first
     std::atomic<int> busy{0};

@@ -1340,7 +1340,7 @@ inline float near_cut_leaf2(const fmm_tree *t, int is_double, double alpha)
 // leaving room for the far-field kernels on the other stream.  Serial schedule: no cap.
 inline size_t near_lds_reserve(const fmm_tree *t, size_t static_bytes)
 {
-    if (t->occupancy_in_use <= 0 || t->schedule != 0 || t->depth < 2) return 0;
+    if (t->occupancy_in_use <= 0 || t->depth < 2) return 0;
     const size_t per_wave = (size_t)160 * 1024 / (4 * (size_t)t->occupancy_in_use);
     return per_wave > static_bytes ? per_wave - static_bytes : 0;
 }
