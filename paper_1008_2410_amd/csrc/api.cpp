@@ -38,7 +38,8 @@ struct BusyGuard {
 void free_workspace(Workspace &ws, hipStream_t s)
 {
     for (void *p : {ws.gam, (void *)ws.stage, (void *)ws.near, (void *)ws.mp_d, (void *)ws.lo_d, (void *)ws.mp_f,
-                    (void *)ws.lo_f, (void *)ws.adj, (void *)ws.lo2_d, (void *)ws.lo2_f, (void *)ws.rec2, ws.sums})
+                    (void *)ws.lo_f, (void *)ws.adj, (void *)ws.mp2_d, (void *)ws.lo2_d, (void *)ws.mp2_f,
+                    (void *)ws.lo2_f, (void *)ws.rec2, ws.sums})
         if (p) hipFreeAsync(p, s);
     ws = Workspace{};
 }
@@ -91,8 +92,10 @@ int clear_multipoles(const fmm_tree *t, hipStream_t s)
     const int64_t cells_d = level_base(std::min(ws.split, t->depth) + 1);
     const int64_t cells_f = level_base(t->depth + 1) - cells_d;
     const size_t bd = (cells_d * ws.p + kCoefPad) * sizeof(double2), bf = (cells_f * ws.p + kCoefPad) * sizeof(float2);
-    if (ws.mp_d) HIP_TRY(hipMemsetAsync(ws.mp_d, 0, bd, s));  // the adjoint's multipoles are the same arrays
-    if (ws.mp_f && cells_f > 0) HIP_TRY(hipMemsetAsync(ws.mp_f, 0, bf, s));
+    for (double2 *m : {ws.mp_d, ws.mp2_d})
+        if (m) HIP_TRY(hipMemsetAsync(m, 0, bd, s));
+    for (float2 *m : {ws.mp_f, ws.mp2_f})
+        if (m && cells_f > 0) HIP_TRY(hipMemsetAsync(m, 0, bf, s));
     return FMM_OK;
 }
 
@@ -151,14 +154,15 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
         if ((rc = dev_alloc_async(&ws.adj, n, "adjoint charges", s))) return rc;
         if (precision != FMM_FP64 && (rc = dev_alloc_async((float2 **)&ws.rec2, n, "adjoint charges (FP32)", s))) return rc;
         if (L >= 2) {
-            // The adjoint's two far chains run one after the other on one stream and the
-            // multipoles of the first are dead once its M2L is done: the second (charges q)
-            // reuses them.  Its locals are kept beside the first's for the finalize.
-            ws.mp2_d = ws.mp_d;
-            ws.mp2_f = ws.mp_f;
+            // the far field of the charges q, computed beside that of the charges c
+            if ((rc = dev_alloc_async(&ws.mp2_d, cells_d * p + kCoefPad, "adjoint multipoles", s))) return rc;
             if ((rc = dev_alloc_async(&ws.lo2_d, cells_d * p + kCoefPad, "adjoint locals", s))) return rc;
-            if (cells_f > 0 && (rc = dev_alloc_async(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals", s)))
-                return rc;
+            HIP_TRY(hipMemsetAsync(ws.mp2_d, 0, (cells_d * p + kCoefPad) * sizeof(double2), s));
+            if (cells_f > 0) {
+                if ((rc = dev_alloc_async(&ws.mp2_f, cells_f * p + kCoefPad, "adjoint multipoles", s))) return rc;
+                if ((rc = dev_alloc_async(&ws.lo2_f, cells_f * p + kCoefPad, "adjoint locals", s))) return rc;
+                HIP_TRY(hipMemsetAsync(ws.mp2_f, 0, (cells_f * p + kCoefPad) * sizeof(float2), s));
+            }
         }
     }
     if (ws.owner != t->serial) {
@@ -730,20 +734,27 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     launch_pack(t, is_double, ws.gam, ms);
     launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ms);
     tm.mark(1, ms);
+    // The two far chains (the charges c: the derivative of their local expansion; the
+    // charges q: the transpose pass A^T q = -A q) are independent: with the two streams they
+    // run beside each other, the q chain on the side stream, the c chain on the main stream,
+    // and the near field follows them.  (Beside the adjoint's near field, which holds every
+    // wavefront slot, they would wait for it to drain.)
     if (overlap) {
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
     tm.mark(2, ss);
-    launch_far_chain(fc, ss);  // c-field: derivative of its local expansion
-    launch_far_chain(fq, ss);  // q-field: the transpose pass A^T q = -A q
+    launch_far_chain(fq, ss);
     tm.mark(3, ss);
-    if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
+    launch_far_chain(fc, ms);
+    if (overlap) {
+        HIP_TRY(hipEventRecord(t->ev_join, ss));
+        HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    }
     tm.mark(4, ms);
     launch_p2p_backward(t, pos, ws.gam, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
                         ws.bwd_b, need_src ? ws.bwd_src : nullptr, ms);
     tm.mark(5, ms);
-    if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(6, ms);
     // above the last-level cache the outputs reach user order through staging slots, kept in
     // arrays this call no longer reads: dL/dGamma in the FP32 charges (mixed) or the FP64
