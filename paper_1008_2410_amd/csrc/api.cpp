@@ -732,7 +732,7 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     tm.mark(0, ms);
     launch_stage_in(t, gamma, ms);
     launch_pack(t, is_double, ws.gam, ms);
-    launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ms);
+    launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ws.stage, ms);  // stage: free until finalize
     tm.mark(1, ms);
     // The two far chains (the charges c: the derivative of their local expansion; the
     // charges q: the transpose pass A^T q = -A q) are independent: with the two streams they
@@ -756,11 +756,12 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
                         ws.bwd_b, need_src ? ws.bwd_src : nullptr, ms);
     tm.mark(5, ms);
     tm.mark(6, ms);
-    // above the last-level cache the outputs reach user order through staging slots, kept in
+    // once the outputs fill the last-level cache they reach user order through staging slots, kept in
     // arrays this call no longer reads: dL/dGamma in the FP32 charges (mixed) or the FP64
     // circulations, the evaluation part in the forward's staged velocities, the source part
     // in the forward's near-field array
-    const bool staged = t->n * (int64_t)sizeof(double2) > kLastLevelCacheBytes;
+    const int64_t out_bytes = (out.dg ? 8 : 0) + ((out.dxe || out.dxy) ? 16 : 0) + ((out.dxs || out.dxy) ? 16 : 0);
+    const bool staged = outputs_windowed(t->n, out_bytes);
     double *st_g = !staged ? nullptr : is_double ? (double *)ws.gam : (double *)ws.rec2;
     double *st_x = staged ? (double *)ws.stage : nullptr;
     double *st_s = staged ? (double *)ws.near : nullptr;

@@ -408,32 +408,48 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
     const T dy2 = fma(ddy, ddy, tiny<T>());
     const T s = fma(ddx, ddx, dy2);
     const T r = recip(s);
-    T gr, h;
-    if (FAR) {
-        // e rounds to 0 against 1 (g = 1): g/s' = 1/s', (lambda e s' - g)/s'^2 = -1/s'^2
-        gr = r;
-        h = -r * r;
-    } else {
-        T e, g;
-        exp_pair(s, e, g);
-        gr = g * r;
-        h = (lambda * e - gr) * r;  // lambda e/s' - g/s'^2
-        // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x,
-        // 1 - e cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
-        //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
-        //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
-        // (The test is on s' against the cut divided by lambda, a loop invariant.)
-        if (s < series_cut<T>() / lambda) {
-            const T x = lambda * s;
-            gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
-            h = lambda * lambda *
-                fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
-        }
-        fb = fma(rj.z, e, fb);  // B: Gamma_j e
+    if constexpr (FAR) {
+        // e rounds to 0 against 1 (g = 1): the terms of the point vortex, Phi: q_j w and
+        // A: -Gamma_j w^2 with w = 1/dz' = conj(dz')/s' = cx + i cy.  The A sums take
+        // Re(-w^2) = d = cy^2 - cx^2 and Im(-w^2)/-2 = cx cy; the source-position sum takes
+        // q_j (d - 2i cx cy).  (Three operations fewer than the general form below.)
+        const T cx = r * ddx, cy = -r * ddy;
+        fpr = fma(qj.x, cx, fpr);
+        fpr = fma(-qj.y, cy, fpr);
+        fpi = fma(qj.x, cy, fpi);
+        fpi = fma(qj.y, cx, fpi);
+        const T d = fma(cy, cy, -cx * cx);
+        const T m = cx * cy;
+        far_r = fma(rj.z, d, far_r);
+        far_ih = fma(rj.z, m, far_ih);
         if constexpr (SRC) {
-            acc[7] = fma(qj.x, e, acc[7]);
-            acc[8] = fma(qj.y, e, acc[8]);
+            const T wi = (T)-2 * m;
+            acc[5] = fma(qj.x, d, acc[5]);
+            acc[5] = fma(-qj.y, wi, acc[5]);
+            acc[6] = fma(qj.x, wi, acc[6]);
+            acc[6] = fma(qj.y, d, acc[6]);
         }
+        return;
+    }
+    T e, g;
+    exp_pair(s, e, g);
+    T gr = g * r;
+    T h = (lambda * e - gr) * r;  // lambda e/s' - g/s'^2
+    // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x, 1 - e
+    // cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
+    //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
+    //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
+    // (The test is on s' against the cut divided by lambda, a loop invariant.)
+    if (s < series_cut<T>() / lambda) {
+        const T x = lambda * s;
+        gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
+        h = lambda * lambda *
+            fma(x, fma(x, fma(x, fma(x, (T)(-1.0 / 144), (T)(1.0 / 30)), (T)(-1.0 / 8)), (T)(1.0 / 3)), (T)-0.5);
+    }
+    fb = fma(rj.z, e, fb);  // B: Gamma_j e
+    if constexpr (SRC) {
+        acc[7] = fma(qj.x, e, acc[7]);
+        acc[8] = fma(qj.y, e, acc[8]);
     }
     // Phi: q_j (g/s') conj(dz')
     const T cx = gr * ddx, cy = -gr * ddy;

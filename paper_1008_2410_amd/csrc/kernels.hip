@@ -44,12 +44,13 @@ __device__ __forceinline__ int xcd_block(int nxcd)
 
 constexpr int kStageE = 4;  // elements per thread in pass 1 (chunk of 1024)
 
+template <typename V>
 __global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxcd, const int *__restrict__ gpos1,
-                                                        const double *__restrict__ src, double *__restrict__ st)
+                                                        const V *__restrict__ src, V *__restrict__ st)
 {
     constexpr int C = 256 * kStageE;
     __shared__ int cnt[256], lo[256], off[256];
-    __shared__ double val[C];
+    __shared__ V val[C];
     __shared__ int dst[C];
     const int t = threadIdx.x;
     cnt[t] = 0;
@@ -57,12 +58,12 @@ __global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxc
     __syncthreads();
     const int64_t k0 = (int64_t)xcd_block(nxcd) * C;
     int q[kStageE];
-    double v[kStageE];
+    V v[kStageE];
 #pragma unroll
     for (int e = 0; e < kStageE; ++e) {
         const int64_t k = k0 + e * 256 + t;
         q[e] = -1;
-        v[e] = 0.0;
+        v[e] = V{};
         if (k < n) {
             q[e] = gpos1[k];
             v[e] = src[k];
@@ -1006,15 +1007,17 @@ void m2l_launch(const FarArgs &a, int l, const c2<T> *m2l_tab, const c2<TPar> *l
 //   A = -i alpha^2/(2 pi) sum_j Gamma_j conj(dz')^2 (lambda e s' - g)/s'^2,
 //   B = -i alpha^2 lambda/(2 pi) sum_j Gamma_j e,        e = exp(-|dz|^2/(2 sigma^2)), g = 1 - e.
 // ---------------------------------------------------------------------------------
+// The cotangent reaches tree order as the circulations do: staged by bucket (stage_in_kernel
+// on rows of two doubles), then gathered by sorted slot here.
 template <typename T>
-__global__ __launch_bounds__(256) void pack_adjoint_kernel(int n, const int *__restrict__ perm,
-                                                            const double *__restrict__ dl_duv, double scale,
+__global__ __launch_bounds__(256) void pack_adjoint_kernel(int n, int nxcd, const int *__restrict__ gpos2,
+                                                            const double2 *__restrict__ dl_st, double scale,
                                                             double2 *__restrict__ adj, c2<T> *__restrict__ qt)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t o = perm[i];
-    const double2 q = make_double2(scale * dl_duv[2 * o], scale * dl_duv[2 * o + 1]);
+    const double2 d = dl_st[gpos2[i]];
+    const double2 q = make_double2(scale * d.x, scale * d.y);
     adj[i] = q;
     if (qt) qt[i] = mk<T>((T)q.x, (T)q.y);
 }
@@ -1300,8 +1303,8 @@ void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStrea
 
 void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s)
 {
-    stage_in_kernel<<<xcd_grid(t->n, 256 * kStageE), 256, 0, s>>>((int)t->n, t->stage_shift, kXcds, t->d_gpos1,
-                                                                   gamma, t->d_st1);
+    stage_in_kernel<double><<<xcd_grid(t->n, 256 * kStageE), 256, 0, s>>>((int)t->n, t->stage_shift, kXcds,
+                                                                           t->d_gpos1, gamma, t->d_st1);
 }
 
 void launch_pack(const fmm_tree *t, int is_double, void *gam, hipStream_t s)
@@ -1458,7 +1461,7 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
     // uv alone: the totals go to stage (n double2), then out in user order; through the
     // staging windows once the output outgrows the last-level cache
     double2 *staged = uv && !uv_near && !uv_far ? (double2 *)stage : nullptr;
-    const bool windowed = t->n * (int64_t)sizeof(double2) > kLastLevelCacheBytes;
+    const bool windowed = outputs_windowed(t->n, sizeof(double2));
     double *uv_direct = staged ? nullptr : uv;
     const int L = t->depth;
     const int n = (int)t->n;
@@ -1500,14 +1503,17 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
     else if (staged) scatter_rows_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, staged, uv, base, h);
 }
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, double2 *adj, void *qt, int is_double,
-                         hipStream_t s)
+                         double2 *staging, hipStream_t s)
 {
     const int n = (int)t->n;
+    stage_in_kernel<double2><<<xcd_grid(n, 256 * kStageE), 256, 0, s>>>(n, t->stage_shift, kXcds, t->d_gpos1,
+                                                                         (const double2 *)dl_duv, staging);
     if (is_double)
-        pack_adjoint_kernel<double><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, scale, adj, nullptr);
+        pack_adjoint_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, staging, scale, adj,
+                                                                      nullptr);
     else
-        pack_adjoint_kernel<float><<<blocks_for(n, 256), 256, 0, s>>>(n, t->d_perm, dl_duv, scale, adj,
-                                                                       (float2 *)qt);
+        pack_adjoint_kernel<float><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, staging, scale, adj,
+                                                                     (float2 *)qt);
 }
 
 void launch_p2p_backward(const fmm_tree *t, const void *pos, const void *gam, const void *qv, int is_double,
