@@ -47,9 +47,7 @@ struct Tables {
 // Coefficient arrays are allocated with this many extra elements at the end, so that
 // fixed-length reads of a row never pass the allocation.
 constexpr int64_t kCoefPad = 64;
-// Permutation staging: buckets of at least 2^kStageShiftMin sorted slots (a 1 MiB gather
-// window of FP64) and at most 256 of them; the number of XCDs that workgroups are dealt
-// to round-robin.
+// The number of XCDs that workgroups are dealt to round-robin.
 constexpr int kXcds = 8;
 constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;  // MI355X Infinity Cache
 
@@ -127,7 +125,7 @@ struct fmm_tree {
     // device tree arrays
     int *d_perm = nullptr;        // sorted slot -> user index
     // Two-pass permutation of the circulations into sorted order through a staging array
-    // cut into buckets of 2^stage_shift consecutive sorted slots (at most 256 buckets):
+    // cut into buckets of 2^stage_shift consecutive sorted slots (at most kStageBuckets):
     int stage_shift = 0;
     int *d_gpos1 = nullptr;       // user index -> staging slot (inside a bucket: by user index)
     int *d_gpos2 = nullptr;       // sorted slot -> staging slot of its user index

@@ -91,7 +91,7 @@ int build_host_tree(const double *xy, int64_t n, int depth, const double *root_b
     // >> shift, ordered by user index inside a bucket; a bucket's segment of the
     // staging array is the slot range of the bucket itself.
     int shift = kStageShiftMin;
-    while ((((n - 1) >> shift) + 1) > 256) ++shift;
+    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
     t.stage_shift = shift;
     std::vector<int> &gpos1 = t.gpos1, &gpos2 = t.gpos2;
     gpos1.assign((size_t)n, 0);
@@ -99,8 +99,8 @@ int build_host_tree(const double *xy, int64_t n, int depth, const double *root_b
     {
         std::vector<int> inv((size_t)n);
         for (int64_t k = 0; k < n; ++k) inv[perm[k]] = (int)k;
-        std::vector<int64_t> fill(256);
-        for (int64_t b = 0; b < 256; ++b) fill[b] = b << shift;
+        std::vector<int64_t> fill(kStageBuckets);
+        for (int64_t b = 0; b < kStageBuckets; ++b) fill[b] = b << shift;
         for (int64_t u = 0; u < n; ++u) gpos1[u] = (int)fill[inv[u] >> shift]++;
         for (int64_t k = 0; k < n; ++k) gpos2[k] = gpos1[perm[k]];
     }

@@ -21,9 +21,13 @@ struct HostI4 {
     int x, y, z, w;
 };
 
-// Lowest particles per staging bucket of the circulations' two-pass permutation
-// (2^17 sorted slots, a 1 MiB window of FP64), at most 256 buckets.
-constexpr int kStageShiftMin = 17;
+// Staging buckets of the two-pass permutations between user and sorted order: at least
+// 2^kStageShiftMin sorted slots per bucket and at most kStageBuckets buckets.  Small
+// windows (2^14 slots: 256 KiB of double2 outputs) keep the random writes of a pass inside
+// the L2 of the XCD that makes them until their lines are whole.
+constexpr int kStageShiftMin = 14;
+constexpr int kStageBucketsLog2 = 10;
+constexpr int kStageBuckets = 1 << kStageBucketsLog2;
 
 struct UniformHostTree {
     double x0 = 0, y0 = 0, side = 1;  // root cell

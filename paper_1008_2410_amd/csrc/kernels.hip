@@ -32,7 +32,7 @@ namespace {
 //   pass 2 (in pack_kernel) walks the sorted slots and gathers from the current
 //          bucket's segment, a window small enough to stay in one XCD's L2.
 // gpos1[user index] = staging slot; gpos2[sorted slot] = staging slot of its user index.
-// S is chosen with the tree so that there are at most 256 buckets.  Blocks are remapped
+// S is chosen with the tree so that there are at most kStageBuckets.  Blocks are remapped
 // so that each XCD (workgroups are dealt to XCDs round-robin) walks one contiguous index
 // range, which keeps its live windows few.
 // ---------------------------------------------------------------------------------
@@ -49,12 +49,15 @@ __global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxc
                                                         const V *__restrict__ src, V *__restrict__ st)
 {
     constexpr int C = 256 * kStageE;
-    __shared__ int cnt[256], lo[256], off[256];
+    __shared__ int cnt[kStageBuckets], lo[kStageBuckets], off[kStageBuckets];
     __shared__ V val[C];
     __shared__ int dst[C];
     const int t = threadIdx.x;
-    cnt[t] = 0;
-    lo[t] = INT_MAX;
+    const int nb = ((n - 1) >> shift) + 1;  // buckets in use, <= kStageBuckets by the choice of shift
+    for (int b = t; b < nb; b += 256) {
+        cnt[b] = 0;
+        lo[b] = INT_MAX;
+    }
     __syncthreads();
     const int64_t k0 = (int64_t)xcd_block(nxcd) * C;
     int q[kStageE];
@@ -67,25 +70,27 @@ __global__ __launch_bounds__(256) void stage_in_kernel(int n, int shift, int nxc
         if (k < n) {
             q[e] = gpos1[k];
             v[e] = src[k];
-            const int bk = q[e] >> shift;  // < 256 by the choice of shift
+            const int bk = q[e] >> shift;
             atomicAdd(&cnt[bk], 1);
             atomicMin(&lo[bk], q[e]);
         }
     }
     __syncthreads();
-    if (t < 64) {  // exclusive scan of the 256 bucket counts by one wavefront
-        const int c0 = cnt[4 * t], c1 = cnt[4 * t + 1], c2 = cnt[4 * t + 2], c3 = cnt[4 * t + 3];
-        const int sum = c0 + c1 + c2 + c3;
+    if (t < 64) {  // exclusive scan of the bucket counts by one wavefront, a run of buckets per lane
+        const int per = (nb + 63) / 64;
+        const int b0 = t * per, b1 = min(b0 + per, nb);
+        int sum = 0;
+        for (int b = b0; b < b1; ++b) sum += cnt[b];
         int incl = sum;
         for (int d = 1; d < 64; d <<= 1) {
             const int o = __shfl_up(incl, d);
             if (t >= d) incl += o;
         }
-        const int ex = incl - sum;
-        off[4 * t] = ex;
-        off[4 * t + 1] = ex + c0;
-        off[4 * t + 2] = ex + c0 + c1;
-        off[4 * t + 3] = ex + c0 + c1 + c2;
+        int run = incl - sum;
+        for (int b = b0; b < b1; ++b) {
+            off[b] = run;
+            run += cnt[b];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -823,9 +828,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(int n, const int *__restr
 // bucket, where the random writes merge in L2; here user row u reads its slot gpos1[u]
 // (a chunk of users reads one short run per bucket) and the rows go out in user order.
 // The direct scatter to user order (scatter_rows_kernel) makes one random 16-byte write
-// per row, which is cheaper while the output fits in the chip's 256 MiB last-level cache:
-// for 2^24 rows, 0.38 + 0.34 ms against 0.58 + 0.15 ms through the windows; for 2^25 rows
-// (537 MB) the scatter alone took 1.12 ms, and the windows save 0.3 ms per evaluation.
+// per row, which is cheaper while the output is smaller than the chip's 256 MiB last-level
+// cache; for 2^25 rows (537 MB) the scatter alone took 1.12 ms, and the windows save 0.3 ms
+// per evaluation.  With windows of 2^14 slots (1024 buckets at 2^24 rows) the writes of a
+// window stay in the XCD's L2 until their lines are whole: 2^24 patches, 8.35 -> 8.29 ms
+// per evaluation against windows of 2^17.
 __global__ __launch_bounds__(256) void gather_rows_kernel(int n, int nxcd, const int *__restrict__ gpos1,
                                                           const double2 *__restrict__ staged,
                                                           double *__restrict__ uv, const double *__restrict__ base,

@@ -915,14 +915,14 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     t->nunits = ntiles;
     // Staging slots of the two-pass permutation of the circulations.
     int shift = kStageShiftMin;
-    while ((((n - 1) >> shift) + 1) > 256) ++shift;
+    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
     t->stage_shift = shift;
     if (!st.check(hipMallocAsync((void **)&t->d_gpos1, n * sizeof(int), s), "staging slots") ||
         !st.check(hipMallocAsync((void **)&t->d_gpos2, n * sizeof(int), s), "staging slots") ||
         !st.check(hipMallocAsync((void **)&t->d_st1, n * sizeof(double), s), "staging array"))
         return failed();
     k_stage_keys<<<grid_for(n, 256), 256, 0, s>>>(t->d_perm, n, shift, key.p, val.p);
-    if (!radix_sort(key.p, val.p, n, 8, s, st)) return failed();
+    if (!radix_sort(key.p, val.p, n, kStageBucketsLog2, s, st)) return failed();
     k_gpos<<<grid_for(n, 256), 256, 0, s>>>(val.p, n, t->d_gpos1);
     k_gpos2<<<grid_for(n, 256), 256, 0, s>>>(t->d_gpos1, t->d_perm, n, t->d_gpos2);
     if (!st.check(hipGetLastError(), "tree build") || !st.check(hipStreamSynchronize(s), "tree build"))
