@@ -44,8 +44,9 @@ void free_atree(fmm_atree *t)
     if (!t) return;
     AtreeDev &d = t->d;
     // the device build's arrays and the adjoint units come from the stream-ordered pool
-    if (t->pooled || d.bwd_units) hipDeviceSynchronize();
-    if (d.bwd_units) hipFreeAsync(d.bwd_units, nullptr);
+    if (t->pooled || d.bwd_units || d.vslot) hipDeviceSynchronize();
+    for (void *p : {(void *)d.bwd_units, (void *)d.m2l_targets, (void *)d.vslot})
+        if (p) hipFreeAsync(p, nullptr);
     for (void *p : {(void *)d.perm, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
                     (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
                     (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
@@ -348,6 +349,21 @@ int choose_occupancy(const fmm_atree *t, int precision, bool concurrent)
     return (ratio >= 0.4 && ratio <= 1.6) ? 5 : 6;
 }
 
+// Up to 16 terms the M2L runs on MFMA with the shared operator tables and the tree's M2L
+// plan (made on the first such call, synchronising s); tabs stays NULL otherwise.
+int ensure_m2l_plan(fmm_atree *t, int p, hipStream_t s, const Tables *&tabs)
+{
+    tabs = nullptr;
+    if (p > 16 || t->sizes[FMM_AT_DEEPEST] < 2) return FMM_OK;
+    std::string err;
+    const Tables *tb = nullptr;
+    int rc = shared_tables(t->device, p, &tb, err);
+    if (rc) return fail(rc == -2 ? FMM_ENOMEM : FMM_EDEVICE, err);
+    if (!t->m2l_plan && (rc = build_atree_m2l_plan(t, tb->mfma_entries, s, err))) return fail(rc, err);
+    tabs = tb;
+    return FMM_OK;
+}
+
 int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, void *main_stream, void *side_stream,
         double *uv, double *uv_near, double *uv_far, const double *base = nullptr, double h = 0.0)
 {
@@ -362,8 +378,10 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     if (rc || (rc = ensure_ws(t, p, precision))) return rc;
     hipStream_t ms = (hipStream_t)main_stream;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
+    const Tables *tabs = nullptr;
+    if ((rc = ensure_m2l_plan(t, p, ms, tabs))) return rc;
     const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision),
-                      choose_occupancy(t, precision, ss != ms)};
+                      choose_occupancy(t, precision, ss != ms), tabs};
     launch_atree_pack(c, gamma, ms);
     HIP_TRY(hipEventRecord(t->ev_fork, ms));
     HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
@@ -396,8 +414,11 @@ int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int pre
         std::string err;
         if ((rc = build_atree_adjoint_units(t, ms, err))) return fail(rc, err);
     }
-    if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, src))) return rc;
-    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision)};
+    const Tables *tabs = nullptr;
+    if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, src)) ||
+        (rc = ensure_m2l_plan(t, p, ms, tabs)))
+        return rc;
+    const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision), 0, tabs};
     launch_atree_pack(c, gamma, ms);
     launch_atree_pack_adjoint(c, dl_duv, scale, ms);
     HIP_TRY(hipEventRecord(t->ev_fork, ms));

@@ -233,6 +233,127 @@ __global__ __launch_bounds__(64, PMAX <= 16 ? 3 : 1) void at_m2l_kernel(int firs
         if (l < p) lo[(int64_t)k * p + l] = b[l];
 }
 
+// Stage 6 (M2L from V) on v_mfma_f64_16x16x4f64 for p <= 16.  V holds cells of the
+// target's own level at the offsets of the uniform tree's interaction list, and with
+// radius-scaled coefficients the M2L operator depends only on the offset, so the cells of
+// every level >= 2 run together, grouped by parity class: a wavefront takes 16 targets of
+// one class and, per offset of the class, gathers the 16 source rows (zero where the
+// target's V list has no cell there; an offset no target of the tile has is skipped) and
+// multiplies them by that offset's 2p x 2p real operator.  Operand layouts as for the
+// uniform tree's FP64 gather-GEMM:
+//   A: lane l holds A[row l%16][k l/16]     B: lane l holds B[k l/16][col l%16]
+//   D: lane l, register r holds D[l/16 + 4r][l%16]
+// with K permuted so that step s uses k = 8(l/16) + s.  Writes the locals of every target
+// (P2L from X adds to them afterwards).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 4) void at_m2l_gemm_kernel(const int *__restrict__ targets, int4 cstart,
+                                                             int4 clen, int4 cwave0, int nwaves, int first,
+                                                             const int *__restrict__ vslot,
+                                                             const int4 *__restrict__ entries, int p,
+                                                             const double *__restrict__ mp, double *__restrict__ lo,
+                                                             const double *__restrict__ tab,
+                                                             const double *__restrict__ zero)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const int two_p = 2 * p;
+    const int k0 = 8 * kq;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= nwaves) return;
+    const int q = wave >= cwave0.w ? 3 : wave >= cwave0.z ? 2 : wave >= cwave0.y ? 1 : 0;
+    const int cs = q == 0 ? cstart.x : q == 1 ? cstart.y : q == 2 ? cstart.z : cstart.w;
+    const int cl = q == 0 ? clen.x : q == 1 ? clen.y : q == 2 ? clen.z : clen.w;
+    const int cw = q == 0 ? cwave0.x : q == 1 ? cwave0.y : q == 2 ? cwave0.z : cwave0.w;
+    const int base = (wave - cw) * 16;
+    const int li = base + row;
+    const bool tvalid = li < cl;
+    const int tcell = tvalid ? targets[cs + li] : first;
+    const int *vs = vslot + (int64_t)(tcell - first) * 27;
+    doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < 27; ++e) {
+        const int S = tvalid ? vs[e] : -1;
+        if (!__any(S >= 0)) continue;  // wavefront-uniform
+        const int4 en = entries[28 * q + e];
+        const double *b0p = tab + (((size_t)en.z * 4 + kq) * 32 + row) * 8;
+        const double *b1p = b0p + 16 * 8;
+        double a[8], b0[8], b1[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double2 u0 = ((const double2 *)b0p)[v], u1 = ((const double2 *)b1p)[v];
+            b0[2 * v] = u0.x;
+            b0[2 * v + 1] = u0.y;
+            b1[2 * v] = u1.x;
+            b1[2 * v + 1] = u1.y;
+        }
+        // rows carry a tail pad and absent sources read the zero row: the 8 reads stay inside
+        const double *src = S >= 0 ? mp + (size_t)S * two_p + k0 : zero + k0;
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const double v = src[st];
+            a[st] = (k0 + st < two_p) ? v : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b0[st], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b1[st], acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = base + kq + 4 * r;
+        if (o < cl) {
+            double *out = lo + (size_t)targets[cs + o] * two_p;
+            if (row < two_p) out[row] = acc0[r];
+            if (16 + row < two_p) out[16 + row] = acc1[r];
+        }
+    }
+}
+
+// P2L from X after the MFMA M2L, one thread per cell with a non-empty X list:
+//   b_l += -sum_{j in A} c_j u_j^(l+1),  u_j = w/(z_j - c).
+template <int PMAX, bool CPLX>
+__global__ __launch_bounds__(64) void at_p2l_kernel(int first, int ncells, const int4 *__restrict__ cell,
+                                                     const int *__restrict__ x_off, const int *__restrict__ x_idx,
+                                                     const int2 *__restrict__ range, const double2 *__restrict__ xy,
+                                                     const double *__restrict__ gamma,
+                                                     const double2 *__restrict__ q, double x0, double y0,
+                                                     double side, int p, double2 *__restrict__ lo)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncells) return;
+    const int k = first + t;
+    if (x_off[k] == x_off[k + 1]) return;
+    const int4 c = cell[k];
+    double2 b[PMAX];
+#pragma unroll
+    for (int l = 0; l < PMAX; ++l) b[l] = make_double2(0.0, 0.0);
+    const double rw = 1.0 / ldexp(side, -c.x);
+    const double2 ctr = cell_centre(x0, y0, side, c);
+    for (int e = x_off[k]; e < x_off[k + 1]; ++e) {
+        const int2 r = range[x_idx[e]];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+            const double2 z = xy[j];
+            const double2 u = cinv(make_double2((z.x - ctr.x) * rw, (z.y - ctr.y) * rw));
+            const double2 cj = charge<CPLX>(gamma, q, j);
+            double2 ul = cmul<double>(cj, u);  // c_j u^(l+1)
+#pragma unroll
+            for (int l = 0; l < PMAX; ++l) {
+                b[l].x -= ul.x;
+                b[l].y -= ul.y;
+                ul = cmul<double>(ul, u);
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < PMAX; ++l)
+        if (l < p) {
+            double2 &o = lo[(int64_t)k * p + l];
+            o.x += b[l].x;
+            o.y += b[l].y;
+        }
+}
+
 // Stage 7 into the cells of one level l >= 3 (parents of level >= 2), one thread per
 // (cell, k), by Horner in d = (c - c_parent)/w_parent:
 //   b_k += 2^-(k+1) sum_{j>=k} C(j,k) d^(j-k) b_j(parent).
@@ -668,7 +789,26 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
     }
     // M2L + P2L for every cell of level >= 2 at once, then L2L level by level
     const int first = t->level_off[2], cnt = t->level_off[deepest + 1] - first;
-    if (cnt > 0) {
+    if (cnt > 0 && c.tabs && t->m2l_plan) {
+        // p <= 16: M2L on MFMA over the classes, then P2L adds to the locals
+        const int *co = t->m2l_class_off;
+        int len[4], w0[4];
+        int waves = 0;
+        for (int k = 0; k < 4; ++k) {
+            len[k] = co[k + 1] - co[k];
+            w0[k] = waves;
+            waves += (len[k] + 15) / 16;
+        }
+        if (waves > 0)
+            at_m2l_gemm_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
+                t->d.m2l_targets, make_int4(co[0], co[1], co[2], co[3]), make_int4(len[0], len[1], len[2], len[3]),
+                make_int4(w0[0], w0[1], w0[2], w0[3]), waves, first, t->d.vslot, c.tabs->mfma_entries, p,
+                (const double *)mp, (double *)lo, c.tabs->mfma_d, c.tabs->zero_row);
+        if (t->sizes[5] > 0)  // |X|
+            at_p2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.x_off, t->d.x_idx,
+                                                                   t->d.range, t->d.xy, t->wsp->gamma, q, t->x0,
+                                                                   t->y0, t->side, p, lo);
+    } else if (cnt > 0) {
         if (p <= 16)
             at_m2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
                                                                    t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,

@@ -979,4 +979,95 @@ int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err)
     return FMM_OK;
 }
 
+// M2L plan of the MFMA path: class key and cell of every cell of level >= 2, and the
+// counts per class (count[0..3]).
+__global__ __launch_bounds__(256) void ak_m2l_keys(const int4 *__restrict__ cell, int first, int ncl,
+                                                   uint64_t *__restrict__ key, uint32_t *__restrict__ val,
+                                                   unsigned int *__restrict__ count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const int4 c = cell[first + i];
+    const int q = (c.y & 1) | ((c.z & 1) << 1);
+    key[i] = (uint64_t)q;
+    val[i] = (uint32_t)(first + i);
+    atomicAdd(&count[q], 1u);
+}
+
+// Source cell of each interaction offset {dx, dy} of the cell's class (entries 28 q ..
+// 28 q + 26 of the operator tables) from its V list; a V member of another level or at an
+// offset outside the class's 27 counts into *bad.
+__global__ __launch_bounds__(256) void ak_vslot(const int4 *__restrict__ cell, int first, int ncl,
+                                                const int *__restrict__ v_off, const int *__restrict__ v_idx,
+                                                const int4 *__restrict__ entries, int *__restrict__ vslot,
+                                                unsigned int *__restrict__ bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const int k = first + i;
+    const int4 c = cell[k];
+    const int q = (c.y & 1) | ((c.z & 1) << 1);
+    int *vs = vslot + (int64_t)i * 27;
+    for (int j = 0; j < 27; ++j) vs[j] = -1;
+    for (int e = v_off[k]; e < v_off[k + 1]; ++e) {
+        const int S = v_idx[e];
+        const int4 cs = cell[S];
+        const int dx = cs.y - c.y, dy = cs.z - c.z;
+        int slot = -1;
+        for (int j = 0; j < 27; ++j) {
+            const int4 en = entries[28 * q + j];
+            if (en.x == dx && en.y == dy) slot = j;
+        }
+        if (slot < 0 || cs.x != c.x) atomicAdd(bad, 1u);
+        else vs[slot] = S;
+    }
+}
+
+int build_atree_m2l_plan(fmm_atree *t, const int4 *entries, hipStream_t s, std::string &err)
+{
+    Status st;
+    const int deepest = (int)t->sizes[FMM_AT_DEEPEST];
+    std::fill(t->m2l_class_off, t->m2l_class_off + 5, 0);
+    if (deepest < 2) {
+        t->m2l_plan = true;
+        return FMM_OK;
+    }
+    const int first = t->level_off[2], ncl = t->level_off[deepest + 1] - first;
+    Buf<uint64_t> key;
+    Buf<uint32_t> val;
+    Buf<unsigned int> cnt;
+    int *targets = nullptr, *vslot = nullptr;
+    auto failed = [&]() {
+        if (targets) (void)hipFreeAsync(targets, s);
+        if (vslot) (void)hipFreeAsync(vslot, s);
+        err = st.msg;
+        return st.code;
+    };
+    if (!st.check(key.alloc(ncl, s), "M2L plan") || !st.check(val.alloc(ncl, s), "M2L plan") ||
+        !st.check(cnt.alloc(5, s), "M2L plan") ||
+        !st.check(hipMemsetAsync(cnt.p, 0, 5 * sizeof(unsigned int), s), "M2L plan") ||
+        !st.check(hipMallocAsync((void **)&targets, (size_t)std::max(ncl, 1) * sizeof(int), s), "M2L plan") ||
+        !st.check(hipMallocAsync((void **)&vslot, (size_t)std::max(ncl, 1) * 27 * sizeof(int), s), "M2L plan"))
+        return failed();
+    ak_m2l_keys<<<grid_for(ncl, 256), 256, 0, s>>>(t->d.cell, first, ncl, key.p, val.p, cnt.p);
+    ak_vslot<<<grid_for(ncl, 256), 256, 0, s>>>(t->d.cell, first, ncl, t->d.v_off, t->d.v_idx, entries, vslot,
+                                                cnt.p + 4);
+    // stable by class: Morton order inside a class as inside a level
+    if (!radix_sort(key.p, val.p, ncl, 2, s, st) ||
+        !st.check(hipMemcpyAsync(targets, val.p, (size_t)ncl * sizeof(int), hipMemcpyDeviceToDevice, s), "M2L plan"))
+        return failed();
+    unsigned int hc[5];
+    if (!read_back(hc, cnt.p, sizeof hc, s, st)) return failed();
+    if (hc[4] != 0) {
+        st.code = FMM_EDEVICE;
+        st.msg = "M2L plan: " + std::to_string(hc[4]) + " V-list entries outside the interaction offsets";
+        return failed();
+    }
+    for (int q = 0; q < 4; ++q) t->m2l_class_off[q + 1] = t->m2l_class_off[q] + (int)hc[q];
+    t->d.m2l_targets = targets;
+    t->d.vslot = vslot;
+    t->m2l_plan = true;
+    return FMM_OK;
+}
+
 }  // namespace fmm

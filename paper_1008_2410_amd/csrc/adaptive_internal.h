@@ -46,6 +46,11 @@ struct AtreeDev {
     // Adjoint near field: target-centric units over all of U, one per 64-particle tile
     // {leaf cell, first, count, log2 TP}, heaviest first (made on the first adjoint call).
     int4 *bwd_units = nullptr;
+    // M2L on MFMA (made on the first evaluation with p <= 16): the cells of level >= 2
+    // grouped by parity class (x bit | y bit << 1), and per such cell (index - level_off[2])
+    // the source cell of each of its class's 27 interaction offsets, -1 where V holds none.
+    int *m2l_targets = nullptr;
+    int *vslot = nullptr;
 };
 
 // Costs of near-field work (steps of the near kernel), for the heaviest-first order of
@@ -113,6 +118,8 @@ struct fmm_atree {
     int64_t nbwd_units = -1;  // -1 until the adjoint units are made
     int dense_leaf = 32;
     int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
+    bool m2l_plan = false;    // d.m2l_targets and d.vslot made
+    int m2l_class_off[5] = {};  // class starts in d.m2l_targets
     int validate = 0;         // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf
     int *d_flag = nullptr;    // device result of that check
     std::vector<int> level_off;   // max_depth + 2 entries
@@ -133,6 +140,7 @@ struct AtreeCall {
     int is_double;
     double alpha;   // record scale (as for the uniform tree)
     int near_occ = 0;  // forward near field: wavefronts per SIMD it may hold (0: no cap)
+    const Tables *tabs = nullptr;  // with the M2L plan (p <= 16): the MFMA operators
 };
 
 // Stages 1-3 on the device (adaptive_build.hip): fills t->d and the host facts of t
@@ -145,6 +153,10 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
 // The adjoint near-field units (d.bwd_units, nbwd_units) from the tree's arrays; either
 // build.  Synchronises s.
 int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err);
+
+// The M2L plan of the MFMA path (d.m2l_targets, d.vslot, m2l_class_off) from the V lists
+// and the interaction entries of the operator tables.  Synchronises s.
+int build_atree_m2l_plan(fmm_atree *t, const int4 *entries, hipStream_t s, std::string &err);
 
 void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
 // adjoint false: the far field of the charges c (mp, lo); true: of the adjoint charges
