@@ -47,7 +47,7 @@ void free_atree(fmm_atree *t)
     if (t->pooled || d.bwd_units || d.vslot) hipDeviceSynchronize();
     for (void *p : {(void *)d.bwd_units, (void *)d.m2l_targets, (void *)d.vslot})
         if (p) hipFreeAsync(p, nullptr);
-    for (void *p : {(void *)d.perm, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
+    for (void *p : {(void *)d.perm, (void *)d.gpos1, (void *)d.gpos2, (void *)d.st1, (void *)d.leaf_of, (void *)d.xy, (void *)d.cell, (void *)d.range,
                     (void *)d.parent, (void *)d.child, (void *)d.u_off, (void *)d.u_idx, (void *)d.v_off,
                     (void *)d.v_idx, (void *)d.w_off, (void *)d.w_idx, (void *)d.x_off, (void *)d.x_idx,
                     (void *)d.p2m_cells, (void *)d.inner, (void *)d.tile_start, (void *)d.tile_box,
@@ -421,13 +421,15 @@ int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int pre
     const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision), 0, tabs};
     launch_atree_pack(c, gamma, ms);
     launch_atree_pack_adjoint(c, dl_duv, scale, ms);
+    // The two far chains run beside each other, then the near field (which holds every
+    // wavefront slot, so that far kernels beside it would wait for it to drain).
     HIP_TRY(hipEventRecord(t->ev_fork, ms));
     HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
-    launch_atree_far(c, ss, false);  // the charges c: derivative W' at the particles
     launch_atree_far(c, ss, true);   // the charges q: the transpose pass
+    launch_atree_far(c, ms, false);  // the charges c: derivative W' at the particles
     HIP_TRY(hipEventRecord(t->ev_join, ss));
-    launch_atree_backward_near(c, src, ms);
     HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
+    launch_atree_backward_near(c, src, ms);
     launch_atree_finalize_backward(c, out, ms);
     HIP_TRY(hipGetLastError());
     return FMM_OK;
@@ -754,6 +756,13 @@ extern "C" int fmm_atree_build_host(const double *xy, int64_t n, int max_leaf, i
         AtreeDev &d = t->d;
         hipError_t es = hipSetDevice(t->device);
         rc = es != hipSuccess ? hip_fail(es, "hipSetDevice") : upload(&d.perm, order, "permutation");
+        if (!rc) {
+            std::vector<int> g1, g2;
+            host_staging(order, t->stage_shift, g1, g2);
+            rc = upload(&d.gpos1, g1, "staging slots");
+            if (!rc) rc = upload(&d.gpos2, g2, "staging slots");
+            if (!rc) rc = dev_alloc(&d.st1, (size_t)t->n, "staging array");
+        }
         if (!rc) rc = upload(&d.leaf_of, leaf_sorted, "leaf of each particle");
         if (!rc) rc = upload(&d.xy, xs, "sorted positions");
         if (!rc) rc = upload(&d.cell, cell, "cells");

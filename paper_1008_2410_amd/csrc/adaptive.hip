@@ -28,18 +28,21 @@ __device__ __forceinline__ double2 cinv(double2 a)
 
 // Records {alpha (z - c_leaf), Gamma, 0} for the near field and the circulations in
 // sorted order for the expansions.
+// The circulation of sorted particle i comes from its staging slot gpos2[i] (the
+// circulations staged by bucket beforehand).
 template <typename T>
-__global__ __launch_bounds__(256) void at_pack_kernel(int n, const int *__restrict__ perm,
+__global__ __launch_bounds__(256) void at_pack_kernel(int n, int nxcd, const int *__restrict__ gpos2,
                                                        const int *__restrict__ leaf_of, const int4 *__restrict__ cell,
-                                                       const double2 *__restrict__ xy, const double *__restrict__ gamma,
-                                                       double x0, double y0, double side, double alpha,
-                                                       rec_t<T> *__restrict__ rec, double *__restrict__ gamma_sorted)
+                                                       const double2 *__restrict__ xy,
+                                                       const double *__restrict__ gamma_st, double x0, double y0,
+                                                       double side, double alpha, rec_t<T> *__restrict__ rec,
+                                                       double *__restrict__ gamma_sorted)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double2 c = cell_centre(x0, y0, side, cell[leaf_of[i]]);
     const double2 z = xy[i];
-    const double g = gamma[perm[i]];
+    const double g = gamma_st[gpos2[i]];
     rec_t<T> r;
     r.x = (T)(alpha * (z.x - c.x));
     r.y = (T)(alpha * (z.y - c.y));
@@ -490,11 +493,12 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
                                                            const uint16_t *__restrict__ mask,
                                                            const c2<TS> *__restrict__ slots, double scale,
                                                            double *__restrict__ uv, double *__restrict__ uv_near,
-                                                           double *__restrict__ uv_far, double2 *__restrict__ staged)
+                                                           double *__restrict__ uv_far, double2 *__restrict__ staged,
+                                                           const int *__restrict__ gpos2, int nxcd)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t o = staged ? 0 : perm[i];  // issued with the first loads
+    const int64_t o = staged ? (gpos2 ? gpos2[i] : i) : perm[i];  // issued with the first loads
     const int A = leaf_of[i];
     // near field: the target-centric part (mask bit 9) plus the slots of the mutual
     // items (bits d), in order d = 0..8 (first, so that its loads overlap the far part's)
@@ -519,8 +523,8 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
         W.x += acc.x / w;
         W.y += acc.y / w;
     }
-    if (staged) {
-        staged[i] = make_double2(nr.x + W.x, nr.y - W.y);
+    if (staged) {  // at its staging slot (windows) or in sorted order
+        staged[o] = make_double2(nr.x + W.x, nr.y - W.y);
         return;
     }
     if (uv) {
@@ -549,14 +553,14 @@ __global__ __launch_bounds__(256) void at_finalize_kernel(int n, const int *__re
 
 // Adjoint charges in sorted order, FP64 and in the records' precision.
 template <typename T>
-__global__ __launch_bounds__(256) void at_pack_adjoint_kernel(int n, const int *__restrict__ perm,
-                                                               const double *__restrict__ dl_duv, double scale,
+__global__ __launch_bounds__(256) void at_pack_adjoint_kernel(int n, int nxcd, const int *__restrict__ gpos2,
+                                                               const double2 *__restrict__ dl_st, double scale,
                                                                double2 *__restrict__ adj, c2<T> *__restrict__ qt)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t o = perm[i];
-    const double2 q = make_double2(scale * dl_duv[2 * o], scale * dl_duv[2 * o + 1]);
+    const double2 d = dl_st[gpos2[i]];  // the cotangent staged by bucket
+    const double2 q = make_double2(scale * d.x, scale * d.y);
     adj[i] = q;
     qt[i] = mk<T>((T)q.x, (T)q.y);
 }
@@ -752,14 +756,15 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
+    launch_stage_rows(n, t->stage_shift, t->d.gpos1, gamma, t->d.st1, s);
+    const unsigned g = xcd_grid(n, 256, kXcds);
     if (c.is_double)
-        at_pack_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, gamma,
-                                                              t->x0, t->y0, t->side, c.alpha,
-                                                              (double4 *)t->wsp->rec, t->wsp->gamma);
+        at_pack_kernel<double><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.leaf_of, t->d.cell, t->d.xy, t->d.st1,
+                                                 t->x0, t->y0, t->side, c.alpha, (double4 *)t->wsp->rec,
+                                                 t->wsp->gamma);
     else
-        at_pack_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, gamma,
-                                                             t->x0, t->y0, t->side, c.alpha, (float4 *)t->wsp->rec,
-                                                             t->wsp->gamma);
+        at_pack_kernel<float><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.leaf_of, t->d.cell, t->d.xy, t->d.st1,
+                                                t->x0, t->y0, t->side, c.alpha, (float4 *)t->wsp->rec, t->wsp->gamma);
 }
 
 template <bool CPLX>
@@ -869,32 +874,41 @@ void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, doub
     const int n = (int)t->n;
     const double scale = c.alpha * kInv2Pi;
     // uv alone: the totals go to the records (free once the near field and the far chain
-    // are done; n double2 or more) in sorted order, then to user order
+    // are done; n double2 or more), then to user order: through the staging windows once
+    // the output fills the last-level cache, else in sorted order and scattered
     double2 *staged = uv && !uv_near && !uv_far ? (double2 *)t->wsp->rec : nullptr;
+    const bool windowed = staged && outputs_windowed(n, sizeof(double2));
+    const int *gp = windowed ? t->d.gpos2 : nullptr;
     double *uv_direct = staged ? nullptr : uv;
+    const unsigned g = xcd_grid(n, 256, kXcds);
     if (c.is_double)
-        at_finalize_kernel<double><<<blocks(n, 256), 256, 0, s>>>(
+        at_finalize_kernel<double><<<g, 256, 0, s>>>(
             n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->wsp->mp, t->wsp->lo, c.p, t->x0,
             t->y0, t->side, t->wsp->near, t->d.mask, (const double2 *)t->wsp->slots, scale, uv_direct, uv_near, uv_far,
-            staged);
+            staged, gp, kXcds);
     else
-        at_finalize_kernel<float><<<blocks(n, 256), 256, 0, s>>>(
+        at_finalize_kernel<float><<<g, 256, 0, s>>>(
             n, t->d.perm, t->d.leaf_of, t->d.cell, t->d.xy, t->d.w_off, t->d.w_idx, t->wsp->mp, t->wsp->lo, c.p, t->x0,
             t->y0, t->side, t->wsp->near, t->d.mask, (const float2 *)t->wsp->slots, scale, uv_direct, uv_near, uv_far,
-            staged);
-    if (staged) scatter_rows_kernel<<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, staged, uv, base, h);
+            staged, gp, kXcds);
+    if (windowed) launch_gather_rows(n, t->d.gpos1, staged, uv, base, h, s);
+    else if (staged) scatter_rows_kernel<<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, staged, uv, base, h);
 }
 
 void launch_atree_pack_adjoint(const AtreeCall &c, const double *dl_duv, double scale, hipStream_t s)
 {
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
+    // the forward's near-field array (n double2) is free during the adjoint: the staging
+    double2 *st = t->wsp->near;
+    launch_stage_rows2(n, t->stage_shift, t->d.gpos1, (const double2 *)dl_duv, st, s);
+    const unsigned g = xcd_grid(n, 256, kXcds);
     if (c.is_double)
-        at_pack_adjoint_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, scale, t->wsp->adj,
-                                                                      (double2 *)t->wsp->qt);
+        at_pack_adjoint_kernel<double><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, st, scale, t->wsp->adj,
+                                                         (double2 *)t->wsp->qt);
     else
-        at_pack_adjoint_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.perm, dl_duv, scale, t->wsp->adj,
-                                                                     (float2 *)t->wsp->qt);
+        at_pack_adjoint_kernel<float><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, st, scale, t->wsp->adj,
+                                                        (float2 *)t->wsp->qt);
 }
 
 void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)

@@ -917,6 +917,12 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
         return FMM_EDEVICE;
     }
 
+    // Staging slots of the two-pass permutations between user and sorted order.
+    if (!build_staging(d.perm, n, s, st, t->stage_shift, d.gpos1, d.gpos2, d.st1)) {
+        err = st.msg;
+        return st.code;
+    }
+
     // The cell arrays pass to the tree; the neighbour slots were the build's alone.
     d.cell = cs.cell;
     d.range = cs.range;
@@ -985,13 +991,19 @@ __global__ __launch_bounds__(256) void ak_m2l_keys(const int4 *__restrict__ cell
                                                    uint64_t *__restrict__ key, uint32_t *__restrict__ val,
                                                    unsigned int *__restrict__ count)
 {
+    __shared__ unsigned int bc[4];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const int4 c = cell[first + i];
-    const int q = (c.y & 1) | ((c.z & 1) << 1);
-    key[i] = (uint64_t)q;
-    val[i] = (uint32_t)(first + i);
-    atomicAdd(&count[q], 1u);
+    if (threadIdx.x < 4) bc[threadIdx.x] = 0;
+    __syncthreads();
+    if (i < ncl) {
+        const int4 c = cell[first + i];
+        const int q = (c.y & 1) | ((c.z & 1) << 1);
+        key[i] = (uint64_t)q;
+        val[i] = (uint32_t)(first + i);
+        atomicAdd(&bc[q], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && bc[threadIdx.x]) atomicAdd(&count[threadIdx.x], bc[threadIdx.x]);
 }
 
 // Source cell of each interaction offset {dx, dy} of the cell's class (entries 28 q ..

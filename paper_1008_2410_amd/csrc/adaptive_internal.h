@@ -20,6 +20,11 @@ namespace fmm {
 // are one contiguous range.  Lists are CSR over cells (int offsets, int cell ids).
 struct AtreeDev {
     int *perm = nullptr;        // sorted slot -> user index
+    // two-pass permutations between user and sorted order (buckets of 2^stage_shift sorted
+    // slots): user index -> staging slot, sorted slot -> staging slot of its user index,
+    // and the staging array of the circulations
+    int *gpos1 = nullptr, *gpos2 = nullptr;
+    double *st1 = nullptr;
     int *leaf_of = nullptr;     // sorted slot -> leaf cell
     double2 *xy = nullptr;      // positions, sorted
     int4 *cell = nullptr;       // {level, ix, iy, is_leaf}
@@ -117,6 +122,7 @@ struct fmm_atree {
     int64_t mutual_items = 0, mutual_pairs = 0, target_units = 0;
     int64_t nbwd_units = -1;  // -1 until the adjoint units are made
     int dense_leaf = 32;
+    int stage_shift = 0;
     int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
     bool m2l_plan = false;    // d.m2l_targets and d.vslot made
     int m2l_class_off[5] = {};  // class starts in d.m2l_targets

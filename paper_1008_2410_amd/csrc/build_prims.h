@@ -60,6 +60,14 @@ bool scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tota
 // Stable LSD sort of (keys, vals) in place by the low `bits` bits of the keys, 8-bit digits.
 bool radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t s, Status &st);
 
+// Staging slots of the two-pass permutations for the sorted order perm (sorted slot ->
+// user index, device): bucket shift, gpos1 (user index -> staging slot), gpos2 (sorted
+// slot -> staging slot of its user index) and a staging array st1 of n doubles, the three
+// from the stream-ordered pool.  Buckets of 2^shift sorted slots, ordered by user index
+// inside a bucket.
+bool build_staging(const int *perm, int64_t n, hipStream_t s, Status &st, int &shift, int *&gpos1, int *&gpos2,
+                   double *&st1);
+
 // Root cell when none is given: {x0, y0, side} = (min x, min y, max(range x, range y) (1 + 2^-20)),
 // side 1 for a single point; nonfinite when any coordinate is not finite.  Synchronises s.
 bool bounding_square(const double2 *xy, int64_t n, hipStream_t s, Status &st, double box[3], bool &nonfinite);

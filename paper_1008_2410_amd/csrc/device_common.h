@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fmm_internal.h"
@@ -58,6 +59,20 @@ template <typename TO, typename TI> __device__ __forceinline__ c2<TO> cvt(c2<TI>
 // with s = |X_i - X_j|^2 (leaf offset added per neighbour leaf).  Leaf-local origins
 // keep FP32 differences accurate at the blob scale.
 // ---------------------------------------------------------------------------------
+// Workgroups are dealt to the XCDs round-robin; this remaps block b so that XCD x walks
+// the contiguous range [x per, (x + 1) per) of logical blocks (grids are launched as a
+// multiple of nxcd), which keeps the memory windows each XCD touches few and in its L2.
+__device__ __forceinline__ int xcd_block(int nxcd)
+{
+    const int per = gridDim.x / nxcd;
+    return (blockIdx.x % nxcd) * per + blockIdx.x / nxcd;
+}
+inline unsigned xcd_grid(int64_t work, int per_block, int nxcd)
+{
+    const int64_t b = (work + per_block - 1) / per_block;
+    return (unsigned)((std::max<int64_t>(b, 1) + nxcd - 1) / nxcd * nxcd);
+}
+
 template <typename T> struct Rec;
 template <> struct Rec<float> { using type = float4; };
 template <> struct Rec<double> { using type = double4; };

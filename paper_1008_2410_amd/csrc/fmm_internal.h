@@ -212,6 +212,14 @@ void launch_finalize(const fmm_tree *t, const FarArgs &a, const double2 *near, c
                      double h, hipStream_t s);
 
 // Backward
+// The two passes between user and sorted order through bucket staging windows (gpos1,
+// gpos2 and the shift of a sorted order): rows of one or two doubles from user order into
+// their staging slots, and staged double2 rows out to user order (uv = base + h row with
+// base, else the row).
+void launch_stage_rows(int64_t n, int shift, const int *gpos1, const double *src, double *st, hipStream_t s);
+void launch_stage_rows2(int64_t n, int shift, const int *gpos1, const double2 *src, double2 *st, hipStream_t s);
+void launch_gather_rows(int64_t n, const int *gpos1, const double2 *staged, double *uv, const double *base, double h,
+                        hipStream_t s);
 void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, double2 *adj, void *qt, int is_double,
                          double2 *staging, hipStream_t s);
 void launch_p2p_backward(const fmm_tree *t, const void *pos, const void *gam, const void *qv, int is_double,

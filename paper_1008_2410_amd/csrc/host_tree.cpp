@@ -11,6 +11,23 @@
 
 namespace fmm {
 
+void host_staging(const std::vector<int> &perm, int &shift, std::vector<int> &gpos1, std::vector<int> &gpos2)
+{
+    // bucket = sorted slot >> shift, ordered by user index inside a bucket; a bucket's
+    // segment of the staging array is the slot range of the bucket itself
+    const int64_t n = (int64_t)perm.size();
+    shift = kStageShiftMin;
+    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
+    gpos1.assign((size_t)n, 0);
+    gpos2.assign((size_t)n, 0);
+    std::vector<int> inv((size_t)n);
+    for (int64_t k = 0; k < n; ++k) inv[perm[k]] = (int)k;
+    std::vector<int64_t> fill(kStageBuckets);
+    for (int64_t b = 0; b < kStageBuckets; ++b) fill[b] = b << shift;
+    for (int64_t u = 0; u < n; ++u) gpos1[u] = (int)fill[inv[u] >> shift]++;
+    for (int64_t k = 0; k < n; ++k) gpos2[k] = gpos1[perm[k]];
+}
+
 int build_host_tree(const double *xy, int64_t n, int depth, const double *root_box, UniformHostTree &t, int64_t &bad,
                     std::string &err)
 {
@@ -87,23 +104,7 @@ int build_host_tree(const double *xy, int64_t n, int depth, const double *root_b
                 std::stable_sort(perm.begin() + leaf_start[c], perm.begin() + leaf_start[c + 1],
                                  [&](int a, int b) { return sub[a] < sub[b]; });
     }
-    // Staging slots of the two-pass permutation into sorted order: bucket = sorted slot
-    // >> shift, ordered by user index inside a bucket; a bucket's segment of the
-    // staging array is the slot range of the bucket itself.
-    int shift = kStageShiftMin;
-    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
-    t.stage_shift = shift;
-    std::vector<int> &gpos1 = t.gpos1, &gpos2 = t.gpos2;
-    gpos1.assign((size_t)n, 0);
-    gpos2.assign((size_t)n, 0);
-    {
-        std::vector<int> inv((size_t)n);
-        for (int64_t k = 0; k < n; ++k) inv[perm[k]] = (int)k;
-        std::vector<int64_t> fill(kStageBuckets);
-        for (int64_t b = 0; b < kStageBuckets; ++b) fill[b] = b << shift;
-        for (int64_t u = 0; u < n; ++u) gpos1[u] = (int)fill[inv[u] >> shift]++;
-        for (int64_t k = 0; k < n; ++k) gpos2[k] = gpos1[perm[k]];
-    }
+    host_staging(perm, t.stage_shift, t.gpos1, t.gpos2);
     std::vector<HostD2> &xys = t.xy;
     xys.assign((size_t)n, HostD2{});
     for (int64_t k = 0; k < n; ++k) {

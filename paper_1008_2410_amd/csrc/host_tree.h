@@ -29,6 +29,10 @@ constexpr int kStageShiftMin = 14;
 constexpr int kStageBucketsLog2 = 10;
 constexpr int kStageBuckets = 1 << kStageBucketsLog2;
 
+// Staging slots of a sorted order perm (sorted slot -> user index): the shift, gpos1
+// (user index -> staging slot) and gpos2 (sorted slot -> staging slot of its user index).
+void host_staging(const std::vector<int> &perm, int &shift, std::vector<int> &gpos1, std::vector<int> &gpos2);
+
 struct UniformHostTree {
     double x0 = 0, y0 = 0, side = 1;  // root cell
     int stage_shift = 0;

@@ -36,12 +36,6 @@ namespace {
 // so that each XCD (workgroups are dealt to XCDs round-robin) walks one contiguous index
 // range, which keeps its live windows few.
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_block(int nxcd)
-{
-    const int per = gridDim.x / nxcd;  // grids are launched as a multiple of nxcd
-    return (blockIdx.x % nxcd) * per + blockIdx.x / nxcd;
-}
-
 constexpr int kStageE = 4;  // elements per thread in pass 1 (chunk of 1024)
 
 template <typename V>
@@ -846,10 +840,7 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int n, int nxcd, const
 inline unsigned blocks_for(int64_t work, int per_block) { return (unsigned)((work + per_block - 1) / per_block); }
 
 // A grid of whole rounds over the XCDs, for kernels that index blocks with xcd_block.
-inline unsigned xcd_grid(int64_t work, int per_block)
-{
-    return (blocks_for(work, per_block) + kXcds - 1) / kXcds * kXcds;
-}
+inline unsigned xcd_grid(int64_t work, int per_block) { return fmm::xcd_grid(work, per_block, kXcds); }
 
 
 template <typename T> c2<T> *level_ptr(const FarArgs &a, int l, bool local);
@@ -1308,10 +1299,25 @@ void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStrea
 
 // Grids of the permutation kernels: a multiple of the XCD count (see xcd_block).
 
+void launch_stage_rows(int64_t n, int shift, const int *gpos1, const double *src, double *st, hipStream_t s)
+{
+    stage_in_kernel<double><<<xcd_grid(n, 256 * kStageE), 256, 0, s>>>((int)n, shift, kXcds, gpos1, src, st);
+}
+
+void launch_stage_rows2(int64_t n, int shift, const int *gpos1, const double2 *src, double2 *st, hipStream_t s)
+{
+    stage_in_kernel<double2><<<xcd_grid(n, 256 * kStageE), 256, 0, s>>>((int)n, shift, kXcds, gpos1, src, st);
+}
+
+void launch_gather_rows(int64_t n, const int *gpos1, const double2 *staged, double *uv, const double *base, double h,
+                        hipStream_t s)
+{
+    gather_rows_kernel<<<xcd_grid(n, 256), 256, 0, s>>>((int)n, kXcds, gpos1, staged, uv, base, h);
+}
+
 void launch_stage_in(const fmm_tree *t, const double *gamma, hipStream_t s)
 {
-    stage_in_kernel<double><<<xcd_grid(t->n, 256 * kStageE), 256, 0, s>>>((int)t->n, t->stage_shift, kXcds,
-                                                                           t->d_gpos1, gamma, t->d_st1);
+    launch_stage_rows(t->n, t->stage_shift, t->d_gpos1, gamma, t->d_st1, s);
 }
 
 void launch_pack(const fmm_tree *t, int is_double, void *gam, hipStream_t s)
@@ -1513,8 +1519,7 @@ void launch_pack_adjoint(const fmm_tree *t, const double *dl_duv, double scale, 
                          double2 *staging, hipStream_t s)
 {
     const int n = (int)t->n;
-    stage_in_kernel<double2><<<xcd_grid(n, 256 * kStageE), 256, 0, s>>>(n, t->stage_shift, kXcds, t->d_gpos1,
-                                                                         (const double2 *)dl_duv, staging);
+    launch_stage_rows2(n, t->stage_shift, t->d_gpos1, (const double2 *)dl_duv, staging, s);
     if (is_double)
         pack_adjoint_kernel<double><<<xcd_grid(n, 256), 256, 0, s>>>(n, kXcds, t->d_gpos2, staging, scale, adj,
                                                                       nullptr);

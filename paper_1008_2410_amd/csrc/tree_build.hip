@@ -913,21 +913,30 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
         t->m2l_pairs = (int64_t)hs[3];
     }
     t->nunits = ntiles;
-    // Staging slots of the two-pass permutation of the circulations.
-    int shift = kStageShiftMin;
-    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
-    t->stage_shift = shift;
-    if (!st.check(hipMallocAsync((void **)&t->d_gpos1, n * sizeof(int), s), "staging slots") ||
-        !st.check(hipMallocAsync((void **)&t->d_gpos2, n * sizeof(int), s), "staging slots") ||
-        !st.check(hipMallocAsync((void **)&t->d_st1, n * sizeof(double), s), "staging array"))
-        return failed();
-    k_stage_keys<<<grid_for(n, 256), 256, 0, s>>>(t->d_perm, n, shift, key.p, val.p);
-    if (!radix_sort(key.p, val.p, n, kStageBucketsLog2, s, st)) return failed();
-    k_gpos<<<grid_for(n, 256), 256, 0, s>>>(val.p, n, t->d_gpos1);
-    k_gpos2<<<grid_for(n, 256), 256, 0, s>>>(t->d_gpos1, t->d_perm, n, t->d_gpos2);
+    // Staging slots of the two-pass permutations between user and sorted order.
+    if (!build_staging(t->d_perm, n, s, st, t->stage_shift, t->d_gpos1, t->d_gpos2, t->d_st1)) return failed();
     if (!st.check(hipGetLastError(), "tree build") || !st.check(hipStreamSynchronize(s), "tree build"))
         return failed();
     return FMM_OK;
+}
+
+bool build_staging(const int *perm, int64_t n, hipStream_t s, Status &st, int &shift, int *&gpos1, int *&gpos2,
+                   double *&st1)
+{
+    shift = kStageShiftMin;
+    while ((((n - 1) >> shift) + 1) > kStageBuckets) ++shift;
+    Buf<uint64_t> key;
+    Buf<uint32_t> val;
+    if (!st.check(key.alloc(n, s), "staging slots") || !st.check(val.alloc(n, s), "staging slots") ||
+        !st.check(hipMallocAsync((void **)&gpos1, n * sizeof(int), s), "staging slots") ||
+        !st.check(hipMallocAsync((void **)&gpos2, n * sizeof(int), s), "staging slots") ||
+        !st.check(hipMallocAsync((void **)&st1, n * sizeof(double), s), "staging array"))
+        return false;
+    k_stage_keys<<<grid_for(n, 256), 256, 0, s>>>(perm, n, shift, key.p, val.p);
+    if (!radix_sort(key.p, val.p, n, kStageBucketsLog2, s, st)) return false;
+    k_gpos<<<grid_for(n, 256), 256, 0, s>>>(val.p, n, gpos1);
+    k_gpos2<<<grid_for(n, 256), 256, 0, s>>>(gpos1, perm, n, gpos2);
+    return st.check(hipGetLastError(), "staging slots");
 }
 
 }  // namespace fmm
