@@ -236,51 +236,91 @@ __global__ __launch_bounds__(64, PMAX <= 16 ? 3 : 1) void at_m2l_kernel(int firs
         if (l < p) lo[(int64_t)k * p + l] = b[l];
 }
 
-// Stage 6 (M2L from V) on v_mfma_f64_16x16x4f64 for p <= 16.  V holds cells of the
-// target's own level at the offsets of the uniform tree's interaction list, and with
-// radius-scaled coefficients the M2L operator depends only on the offset, so the cells of
-// every level >= 2 run together, grouped by parity class: a wavefront takes 16 targets of
-// one class and, per offset of the class, gathers the 16 source rows (zero where the
-// target's V list has no cell there; an offset no target of the tile has is skipped) and
-// multiplies them by that offset's 2p x 2p real operator.  Operand layouts as for the
-// uniform tree's FP64 gather-GEMM:
+// Stages 5-7 on v_mfma_f64_16x16x4f64 for p <= 16.  With radius-scaled coefficients
+// every translation is a fixed 2p x 2p real operator per offset, shared with the uniform
+// tree (its tables and interaction entries):
+//  - mode 0 (stages 6 + 7) over the cells of one level, grouped by parity class q: the
+//    M2L from V, whose cells sit at the class's 27 interaction offsets (vslot: the source
+//    cell per offset, -1 where V has none), plus the L2L from the parent's locals (levels
+//    >= 3), added to the P2L sums of the cells with an X list (written before);
+//  - mode 1 (stage 5) over the split cells of one level: the M2M from the four children.
+// A wavefront takes 16 targets; per operator it gathers their 16 source rows (a zero row
+// where a target has no source; an operator no target of the tile uses is skipped).
+// Operand layouts as for the uniform tree's FP64 gather-GEMM:
 //   A: lane l holds A[row l%16][k l/16]     B: lane l holds B[k l/16][col l%16]
 //   D: lane l, register r holds D[l/16 + 4r][l%16]
-// with K permuted so that step s uses k = 8(l/16) + s.  Writes the locals of every target
-// (P2L from X adds to them afterwards).
+// with K permuted so that step s uses k = 8(l/16) + s.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256, 4) void at_m2l_gemm_kernel(const int *__restrict__ targets, int4 cstart,
-                                                             int4 clen, int4 cwave0, int nwaves, int first,
-                                                             const int *__restrict__ vslot,
-                                                             const int4 *__restrict__ entries, int p,
-                                                             const double *__restrict__ mp, double *__restrict__ lo,
-                                                             const double *__restrict__ tab,
-                                                             const double *__restrict__ zero)
+struct AtGemm {
+    const int *targets;          // the launch's targets, by class (mode 0) or one list (mode 1)
+    int cstart[4], clen[4], cwave0[4];
+    int nwaves, mode, first, p;
+    const int *vslot;            // mode 0: 27 source cells per cell of level >= 2 (index - first)
+    const int *x_off;            // mode 0: cells with an X list start from their P2L sums
+    const int *parent;           // mode 0: the L2L source (with par)
+    const int4 *child;           // mode 1: the four children
+    const int4 *entries;         // {dx, dy, slot, kind}: 4 x 28 M2L/L2L, then 4 M2M
+    const double *src;           // multipoles (M2L and M2M sources)
+    const double *par;           // mode 0: locals of the parents' level, NULL at level 2
+    double *out;                 // locals (mode 0) or multipoles (mode 1)
+    const double *tab, *zero;
+};
+
+__global__ __launch_bounds__(256, 4) void at_gemm_kernel(AtGemm a)
 {
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kq = lane >> 4;
-    const int two_p = 2 * p;
+    const int two_p = 2 * a.p;
     const int k0 = 8 * kq;
     const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= nwaves) return;
-    const int q = wave >= cwave0.w ? 3 : wave >= cwave0.z ? 2 : wave >= cwave0.y ? 1 : 0;
-    const int cs = q == 0 ? cstart.x : q == 1 ? cstart.y : q == 2 ? cstart.z : cstart.w;
-    const int cl = q == 0 ? clen.x : q == 1 ? clen.y : q == 2 ? clen.z : clen.w;
-    const int cw = q == 0 ? cwave0.x : q == 1 ? cwave0.y : q == 2 ? cwave0.z : cwave0.w;
-    const int base = (wave - cw) * 16;
+    if (wave >= a.nwaves) return;  // whole wavefronts
+    int q = 0;
+    for (int c = 1; c < 4; ++c)
+        if (wave >= a.cwave0[c]) q = c;
+    const int cs = a.cstart[q], cl = a.clen[q];
+    const int base = (wave - a.cwave0[q]) * 16;
     const int li = base + row;
     const bool tvalid = li < cl;
-    const int tcell = tvalid ? targets[cs + li] : first;
-    const int *vs = vslot + (int64_t)(tcell - first) * 27;
+    const int tcell = tvalid ? a.targets[cs + li] : -1;
     doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int e = 0; e < 27; ++e) {
-        const int S = tvalid ? vs[e] : -1;
+    if (a.mode == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = base + kq + 4 * r;
+            if (o < cl) {
+                const int k = a.targets[cs + o];
+                if (a.x_off[k] < a.x_off[k + 1]) {
+                    const double *b = a.out + (size_t)k * two_p;
+                    if (row < two_p) acc0[r] = b[row];
+                    if (16 + row < two_p) acc1[r] = b[16 + row];
+                }
+            }
+        }
+    }
+    const int ne = a.mode == 0 ? 28 : 4;
+    for (int e = 0; e < ne; ++e) {
+        int S = -1, en_idx;
+        const double *sbase = a.src;
+        if (a.mode == 1) {
+            en_idx = 112 + e;
+            if (tvalid) {
+                const int4 ch = a.child[tcell];
+                S = e == 0 ? ch.x : e == 1 ? ch.y : e == 2 ? ch.z : ch.w;
+            }
+        } else if (e < 27) {
+            en_idx = 28 * q + e;
+            if (tvalid) S = a.vslot[(int64_t)(tcell - a.first) * 27 + e];
+        } else {
+            en_idx = 28 * q + 27;  // L2L from the parent (child quadrant q)
+            sbase = a.par;
+            if (tvalid && a.par) S = a.parent[tcell];
+        }
         if (!__any(S >= 0)) continue;  // wavefront-uniform
-        const int4 en = entries[28 * q + e];
-        const double *b0p = tab + (((size_t)en.z * 4 + kq) * 32 + row) * 8;
+        const int4 en = a.entries[en_idx];
+        const double *b0p = a.tab + (((size_t)en.z * 4 + kq) * 32 + row) * 8;
         const double *b1p = b0p + 16 * 8;
-        double a[8], b0[8], b1[8];
+        double av[8], b0[8], b1[8];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const double2 u0 = ((const double2 *)b0p)[v], u1 = ((const double2 *)b1p)[v];
@@ -290,31 +330,32 @@ __global__ __launch_bounds__(256, 4) void at_m2l_gemm_kernel(const int *__restri
             b1[2 * v + 1] = u1.y;
         }
         // rows carry a tail pad and absent sources read the zero row: the 8 reads stay inside
-        const double *src = S >= 0 ? mp + (size_t)S * two_p + k0 : zero + k0;
+        const double *src = S >= 0 ? sbase + (size_t)S * two_p + k0 : a.zero + k0;
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const double v = src[st];
-            a[st] = (k0 + st < two_p) ? v : 0.0;
+            av[st] = (k0 + st < two_p) ? v : 0.0;
         }
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b0[st], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b1[st], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], b0[st], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], b1[st], acc1, 0, 0, 0);
         }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int o = base + kq + 4 * r;
         if (o < cl) {
-            double *out = lo + (size_t)targets[cs + o] * two_p;
+            double *out = a.out + (size_t)a.targets[cs + o] * two_p;
             if (row < two_p) out[row] = acc0[r];
             if (16 + row < two_p) out[16 + row] = acc1[r];
         }
     }
 }
 
-// P2L from X after the MFMA M2L, one thread per cell with a non-empty X list:
-//   b_l += -sum_{j in A} c_j u_j^(l+1),  u_j = w/(z_j - c).
+// P2L from X before the MFMA translations, one thread per cell with a non-empty X list,
+// written to its locals (the level's gather-GEMM adds M2L and L2L to them):
+//   b_l = -sum_{j in A} c_j u_j^(l+1),  u_j = w/(z_j - c).
 template <int PMAX, bool CPLX>
 __global__ __launch_bounds__(64) void at_p2l_kernel(int first, int ncells, const int4 *__restrict__ cell,
                                                      const int *__restrict__ x_off, const int *__restrict__ x_idx,
@@ -350,11 +391,7 @@ __global__ __launch_bounds__(64) void at_p2l_kernel(int first, int ncells, const
     }
 #pragma unroll
     for (int l = 0; l < PMAX; ++l)
-        if (l < p) {
-            double2 &o = lo[(int64_t)k * p + l];
-            o.x += b[l].x;
-            o.y += b[l].y;
-        }
+        if (l < p) lo[(int64_t)k * p + l] = b[l];
 }
 
 // Stage 7 into the cells of one level l >= 3 (parents of level >= 2), one thread per
@@ -767,6 +804,19 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s)
                                                 t->x0, t->y0, t->side, c.alpha, (float4 *)t->wsp->rec, t->wsp->gamma);
 }
 
+// One gather-GEMM launch over up to four target lists (classes).
+void at_gemm_launch(AtGemm a, const int *seg_off, int nlists, hipStream_t s)
+{
+    a.nwaves = 0;
+    for (int k = 0; k < 4; ++k) {
+        a.cstart[k] = k < nlists ? seg_off[k] : 0;
+        a.clen[k] = k < nlists ? seg_off[k + 1] - seg_off[k] : 0;
+        a.cwave0[k] = a.nwaves;
+        a.nwaves += (a.clen[k] + 15) / 16;
+    }
+    if (a.nwaves > 0) at_gemm_kernel<<<(unsigned)((a.nwaves + 3) / 4), 256, 0, s>>>(a);
+}
+
 template <bool CPLX>
 void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
 {
@@ -775,6 +825,7 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
     if (deepest < 2) return;
     const int p = c.p, nb = 2 * p + 1;
     const double2 *q = t->wsp->adj;
+    const bool gemm = c.tabs && t->m2l_plan;  // p <= 16: stages 5-7 on MFMA
     if (t->np2m > 0) {
         // 16 lanes per leaf, four leaves per wavefront
         const int np = (int)t->np2m;
@@ -786,34 +837,52 @@ void far_chain(const AtreeCall &c, double2 *mp, double2 *lo, hipStream_t s)
             at_p2m_kernel<32, CPLX, 16><<<g, 64, 0, s>>>(t->d.p2m_cells, np, t->d.cell, t->d.range, t->d.xy,
                                                          t->wsp->gamma, q, t->x0, t->y0, t->side, p, mp);
     }
+    AtGemm a{};
+    if (gemm) {
+        a.first = t->level_off[2];
+        a.p = p;
+        a.vslot = t->d.vslot;
+        a.x_off = t->d.x_off;
+        a.parent = t->d.parent;
+        a.child = t->d.child;
+        a.entries = c.tabs->mfma_entries;
+        a.src = (const double *)mp;
+        a.tab = c.tabs->mfma_d;
+        a.zero = c.tabs->zero_row;
+    }
     for (int l = deepest - 1; l >= 2; --l) {
         const int cnt = t->inner_off[l + 1] - t->inner_off[l];
         if (cnt == 0) continue;
-        at_m2m_kernel<<<blocks((int64_t)cnt * p, 256), 256, 0, s>>>(t->d.inner + t->inner_off[l], cnt, t->d.child,
-                                                                    t->wsp->binom, nb, p, mp);
-    }
-    // M2L + P2L for every cell of level >= 2 at once, then L2L level by level
-    const int first = t->level_off[2], cnt = t->level_off[deepest + 1] - first;
-    if (cnt > 0 && c.tabs && t->m2l_plan) {
-        // p <= 16: M2L on MFMA over the classes, then P2L adds to the locals
-        const int *co = t->m2l_class_off;
-        int len[4], w0[4];
-        int waves = 0;
-        for (int k = 0; k < 4; ++k) {
-            len[k] = co[k + 1] - co[k];
-            w0[k] = waves;
-            waves += (len[k] + 15) / 16;
+        if (gemm) {
+            a.mode = 1;
+            a.targets = t->d.inner + t->inner_off[l];
+            a.out = (double *)mp;
+            const int one[2] = {0, cnt};
+            at_gemm_launch(a, one, 1, s);
+        } else {
+            at_m2m_kernel<<<blocks((int64_t)cnt * p, 256), 256, 0, s>>>(t->d.inner + t->inner_off[l], cnt,
+                                                                        t->d.child, t->wsp->binom, nb, p, mp);
         }
-        if (waves > 0)
-            at_m2l_gemm_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
-                t->d.m2l_targets, make_int4(co[0], co[1], co[2], co[3]), make_int4(len[0], len[1], len[2], len[3]),
-                make_int4(w0[0], w0[1], w0[2], w0[3]), waves, first, t->d.vslot, c.tabs->mfma_entries, p,
-                (const double *)mp, (double *)lo, c.tabs->mfma_d, c.tabs->zero_row);
+    }
+    const int first = t->level_off[2], cnt = t->level_off[deepest + 1] - first;
+    if (cnt > 0 && gemm) {
+        // P2L into the locals of the cells with an X list, then level by level the M2L
+        // from V and the L2L from the parent added to them
         if (t->sizes[5] > 0)  // |X|
             at_p2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.x_off, t->d.x_idx,
                                                                    t->d.range, t->d.xy, t->wsp->gamma, q, t->x0,
                                                                    t->y0, t->side, p, lo);
-    } else if (cnt > 0) {
+        a.mode = 0;
+        a.targets = t->d.m2l_targets;
+        a.out = (double *)lo;
+        for (int l = 2; l <= deepest; ++l) {
+            a.par = l >= 3 ? (const double *)lo : nullptr;
+            at_gemm_launch(a, &t->m2l_seg_off[4 * (l - 2)], 4, s);
+        }
+        return;
+    }
+    // M2L + P2L for every cell of level >= 2 at once, then L2L level by level
+    if (cnt > 0) {
         if (p <= 16)
             at_m2l_kernel<16, CPLX><<<blocks(cnt, 64), 64, 0, s>>>(first, cnt, t->d.cell, t->d.v_off, t->d.v_idx,
                                                                    t->d.x_off, t->d.x_idx, t->d.range, t->d.xy,

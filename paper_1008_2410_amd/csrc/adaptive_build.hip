@@ -985,25 +985,25 @@ int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err)
     return FMM_OK;
 }
 
-// M2L plan of the MFMA path: class key and cell of every cell of level >= 2, and the
-// counts per class (count[0..3]).
-__global__ __launch_bounds__(256) void ak_m2l_keys(const int4 *__restrict__ cell, int first, int ncl,
+// M2L plan of the MFMA path: segment key 4 (level - 2) + parity class and cell of every
+// cell of level >= 2, and the counts per segment (count[0 .. 4 nlev - 1]).
+__global__ __launch_bounds__(256) void ak_m2l_keys(const int4 *__restrict__ cell, int first, int ncl, int nseg,
                                                    uint64_t *__restrict__ key, uint32_t *__restrict__ val,
                                                    unsigned int *__restrict__ count)
 {
-    __shared__ unsigned int bc[4];
+    __shared__ unsigned int bc[64];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (threadIdx.x < 4) bc[threadIdx.x] = 0;
+    if (threadIdx.x < nseg) bc[threadIdx.x] = 0;
     __syncthreads();
     if (i < ncl) {
         const int4 c = cell[first + i];
-        const int q = (c.y & 1) | ((c.z & 1) << 1);
-        key[i] = (uint64_t)q;
+        const int sg = 4 * (c.x - 2) + ((c.y & 1) | ((c.z & 1) << 1));
+        key[i] = (uint64_t)sg;
         val[i] = (uint32_t)(first + i);
-        atomicAdd(&bc[q], 1u);
+        atomicAdd(&bc[sg], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 4 && bc[threadIdx.x]) atomicAdd(&count[threadIdx.x], bc[threadIdx.x]);
+    if (threadIdx.x < nseg && bc[threadIdx.x]) atomicAdd(&count[threadIdx.x], bc[threadIdx.x]);
 }
 
 // Source cell of each interaction offset {dx, dy} of the cell's class (entries 28 q ..
@@ -1039,12 +1039,13 @@ int build_atree_m2l_plan(fmm_atree *t, const int4 *entries, hipStream_t s, std::
 {
     Status st;
     const int deepest = (int)t->sizes[FMM_AT_DEEPEST];
-    std::fill(t->m2l_class_off, t->m2l_class_off + 5, 0);
+    t->m2l_seg_off.assign(1, 0);
     if (deepest < 2) {
         t->m2l_plan = true;
         return FMM_OK;
     }
     const int first = t->level_off[2], ncl = t->level_off[deepest + 1] - first;
+    const int nseg = 4 * (deepest - 1);  // <= 56
     Buf<uint64_t> key;
     Buf<uint32_t> val;
     Buf<unsigned int> cnt;
@@ -1056,26 +1057,27 @@ int build_atree_m2l_plan(fmm_atree *t, const int4 *entries, hipStream_t s, std::
         return st.code;
     };
     if (!st.check(key.alloc(ncl, s), "M2L plan") || !st.check(val.alloc(ncl, s), "M2L plan") ||
-        !st.check(cnt.alloc(5, s), "M2L plan") ||
-        !st.check(hipMemsetAsync(cnt.p, 0, 5 * sizeof(unsigned int), s), "M2L plan") ||
+        !st.check(cnt.alloc(nseg + 1, s), "M2L plan") ||
+        !st.check(hipMemsetAsync(cnt.p, 0, (nseg + 1) * sizeof(unsigned int), s), "M2L plan") ||
         !st.check(hipMallocAsync((void **)&targets, (size_t)std::max(ncl, 1) * sizeof(int), s), "M2L plan") ||
         !st.check(hipMallocAsync((void **)&vslot, (size_t)std::max(ncl, 1) * 27 * sizeof(int), s), "M2L plan"))
         return failed();
-    ak_m2l_keys<<<grid_for(ncl, 256), 256, 0, s>>>(t->d.cell, first, ncl, key.p, val.p, cnt.p);
+    ak_m2l_keys<<<grid_for(ncl, 256), 256, 0, s>>>(t->d.cell, first, ncl, nseg, key.p, val.p, cnt.p);
     ak_vslot<<<grid_for(ncl, 256), 256, 0, s>>>(t->d.cell, first, ncl, t->d.v_off, t->d.v_idx, entries, vslot,
-                                                cnt.p + 4);
-    // stable by class: Morton order inside a class as inside a level
-    if (!radix_sort(key.p, val.p, ncl, 2, s, st) ||
+                                                cnt.p + nseg);
+    // stable by segment: Morton order inside a class as inside a level
+    if (!radix_sort(key.p, val.p, ncl, 6, s, st) ||
         !st.check(hipMemcpyAsync(targets, val.p, (size_t)ncl * sizeof(int), hipMemcpyDeviceToDevice, s), "M2L plan"))
         return failed();
-    unsigned int hc[5];
-    if (!read_back(hc, cnt.p, sizeof hc, s, st)) return failed();
-    if (hc[4] != 0) {
+    std::vector<unsigned int> hc((size_t)nseg + 1);
+    if (!read_back(hc.data(), cnt.p, hc.size() * sizeof(unsigned int), s, st)) return failed();
+    if (hc[nseg] != 0) {
         st.code = FMM_EDEVICE;
-        st.msg = "M2L plan: " + std::to_string(hc[4]) + " V-list entries outside the interaction offsets";
+        st.msg = "M2L plan: " + std::to_string(hc[nseg]) + " V-list entries outside the interaction offsets";
         return failed();
     }
-    for (int q = 0; q < 4; ++q) t->m2l_class_off[q + 1] = t->m2l_class_off[q] + (int)hc[q];
+    t->m2l_seg_off.assign((size_t)nseg + 1, 0);
+    for (int q = 0; q < nseg; ++q) t->m2l_seg_off[q + 1] = t->m2l_seg_off[q] + (int)hc[q];
     t->d.m2l_targets = targets;
     t->d.vslot = vslot;
     t->m2l_plan = true;

@@ -51,9 +51,10 @@ struct AtreeDev {
     // Adjoint near field: target-centric units over all of U, one per 64-particle tile
     // {leaf cell, first, count, log2 TP}, heaviest first (made on the first adjoint call).
     int4 *bwd_units = nullptr;
-    // M2L on MFMA (made on the first evaluation with p <= 16): the cells of level >= 2
-    // grouped by parity class (x bit | y bit << 1), and per such cell (index - level_off[2])
-    // the source cell of each of its class's 27 interaction offsets, -1 where V holds none.
+    // Translations on MFMA (made on the first evaluation with p <= 16): the cells of level
+    // >= 2 grouped by level and, inside a level, by parity class (x bit | y bit << 1), and
+    // per such cell (index - level_off[2]) the source cell of each of its class's 27
+    // interaction offsets, -1 where V holds none.
     int *m2l_targets = nullptr;
     int *vslot = nullptr;
 };
@@ -125,7 +126,7 @@ struct fmm_atree {
     int stage_shift = 0;
     int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
     bool m2l_plan = false;    // d.m2l_targets and d.vslot made
-    int m2l_class_off[5] = {};  // class starts in d.m2l_targets
+    std::vector<int> m2l_seg_off;  // segment 4 (level - 2) + class: start in d.m2l_targets
     int validate = 0;         // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf
     int *d_flag = nullptr;    // device result of that check
     std::vector<int> level_off;   // max_depth + 2 entries
