@@ -63,8 +63,8 @@ enum {
                                  1: everything serialised on the main stream;
                                  2 (default): per call from the tree's predicted far/near time
                                  ratio: serialised in the mixed form when the far field is
-                                 predicted the longer part (where overlapping measured slower on
-                                 one GPU), concurrent otherwise and in FP64 */
+                                 predicted more than 2.5 times the near field (where overlapping
+                                 measured slower on one GPU), concurrent otherwise and in FP64 */
     FMM_OPT_COARSE_LEVEL = 2, /* L_c: levels <= L_c of the up/down sweeps run in FP64 on the far-
                                  field stream (default 3, range 1..depth); those of them with at
                                  most 256 cells (levels <= 4) in one single-workgroup kernel, the
@@ -81,8 +81,9 @@ enum {
     FMM_OPT_NEAR_OCCUPANCY = 8, /* 1..8: in a concurrent call the forward near-field kernel keeps at
                                   most this many wavefronts per SIMD resident (by reserving LDS),
                                   leaving room for the far field beside it; 0 = no cap; -1 (default)
-                                  = per call from the predicted far/near time ratio (mixed: 5 or
-                                  none; FP64: 2 or none) */
+                                  = per call from the tree (mixed: 3 for leaves of more than 2500
+                                  near-field pairs per particle, else by the predicted far/near
+                                  time ratio 6, 5, 4 or none; FP64: 2 or none) */
     FMM_OPT_VALIDATE = 9      /* 1: every evaluation first checks the circulations (and an adjoint
                                  call its dL/du) for NaN and infinities on the device and returns
                                  FMM_EINVAL, naming the lowest particle index, before any other

@@ -239,36 +239,41 @@ double far_near_ratio(const fmm_tree *t)
 }
 
 // Whether a call runs the far chain beside the near field (FMM_OPT_SCHEDULE 0), after it
-// (1), or by the model (2, the default): on one GPU both are throughput work on the same
-// CUs, and in the mixed form overlapping measured slower than serialising whenever the far
-// field is the longer part (uniform 2^20 particles at depths 7-9: -0.07 to -0.23 of the
-// far time; 2^22 at depth 9: -0.02), so such calls are serialised.  FP64 calls overlap (the
-// FP64 near field leaves issue slots that the far chain uses: 0.78 against 0.90 ms on the
-// 1024^2 lattice).
+// (1), or by the model (2, the default): both are throughput work on the same CUs.  In the
+// mixed form, with the near field capped as below, overlapping measured faster than
+// serialising up to a predicted far/near ratio of about 2.5 (uniform 2^18-2^22 particles,
+// ratios 1.2-2.2: -7% to -15%; ratio 3.0: +2%), so only calls beyond it are serialised.
+// FP64 calls overlap (the FP64 near field leaves issue slots that the far chain uses).
+constexpr double kSerialRatio = 2.5;
 bool call_overlaps(const fmm_tree *t, int precision)
 {
     if (t->schedule != 2) return t->schedule == 0;
     if (precision == FMM_FP64 || t->depth < 2) return true;
-    return far_near_ratio(t) <= 1.0;
+    return far_near_ratio(t) <= kSerialRatio;
 }
 
-// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY).  Automatic, from the
-// predicted far/near time ratio:
-//  - mixed: capping the near field at 5 wavefronts per SIMD slows it by ~12-18% and lets
-//    the far chain run beside it; measured on uniform and clustered workloads that pays
-//    when the far field takes between 0.12 and 1 times the near field (below, the far
-//    field is too short to hide anything; above, the call is serialised);
-//  - FP64: the near field (at most 4 wavefronts per SIMD) capped at 2 when the far field
-//    is the longer part (ratio >= 1): the 1024^2 lattice, depth 8, p = 12, coarse levels
-//    <= 5 took 0.78 ms against 0.90 uncapped or serialised (caps 1, 3, 4: 1.04, 1.02,
-//    0.95 ms); with a short far field (2^24 patches) every cap was slower than none.
+// Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY), automatic from the tree:
+//  - mixed, leaves of more than ~2500 near-field pairs per particle (2^22-2^24 patch
+//    particles at depths 8-9): 3 wavefronts per SIMD, at which the near field itself runs
+//    faster (2^24 patches at depth 9: 28.5 ms against 32.4 uncapped; 2^23: 8.1 against 9.2);
+//  - mixed, by the predicted far/near ratio r (the far chain takes the slots the cap
+//    leaves): r < 0.12 none, r < 0.9 six (2^24 patches at depth 10: 8.13 ms against 8.40
+//    at five and 8.61 uncapped), 0.9 <= r <= 1.1 five, above four (uniform 2^20-2^22
+//    particles at depths 7-10: four within 0.01 ms of the fastest cap);
+//  - FP64 (at most 4 wavefronts per SIMD): 2 when the far field is the longer part (r >= 1:
+//    the 1024^2 lattice, depth 8, p = 12, coarse levels <= 5 took 0.78 ms against 0.90
+//    uncapped or serialised), else none.
 int choose_occupancy(const fmm_tree *t, int precision, bool overlap)
 {
     if (!overlap || t->depth < 2) return 0;
     if (t->near_occupancy >= 0) return t->near_occupancy;
-    const double ratio = far_near_ratio(t);
-    if (precision == FMM_FP64) return ratio >= 1.0 ? 2 : 0;
-    return (ratio >= 0.12 && ratio <= 1.0) ? 5 : 0;
+    const double r = far_near_ratio(t);
+    if (precision == FMM_FP64) return r >= 1.0 ? 2 : 0;
+    if ((double)t->p2p_pairs >= 2500.0 * (double)t->n) return 3;
+    if (r < 0.12) return 0;
+    if (r < 0.9) return 6;
+    if (r <= 1.1) return 5;
+    return 4;
 }
 
 struct Timing {

@@ -247,6 +247,38 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
                   scale, dense, n, near, slots);
 }
 
+// Sum over the 64 lanes of each of NC values (NC = 32 or 64) by recursive halving: at
+// offset o a lane keeps the half of its values that its lane bit o selects and adds its
+// partner's copy of that half.  Returns the total of value lane >> 1 (NC = 32; lanes 2c
+// and 2c + 1 both hold it) or of value lane (NC = 64).  Shuffles only: no LDS, so the
+// kernel fits beside near-field workgroups that hold the LDS.
+template <typename TC, int NC, int W, int O>
+__device__ __forceinline__ void lane_halve(TC (&v)[NC], int lane)
+{
+    if constexpr (O >= 1) {
+        if constexpr (W > 1) {
+            const bool hi = (lane & O) != 0;
+#pragma unroll
+            for (int k = 0; k < W / 2; ++k) {
+                const TC send = hi ? v[k] : v[k + W / 2];
+                const TC keep = hi ? v[k + W / 2] : v[k];
+                v[k] = keep + __shfl_xor(send, O);
+            }
+            lane_halve<TC, NC, W / 2, O / 2>(v, lane);
+        } else {
+            v[0] += __shfl_xor(v[0], O);
+            lane_halve<TC, NC, 1, O / 2>(v, lane);
+        }
+    }
+}
+template <typename TC, int NC>
+__device__ __forceinline__ TC lane_reduce_scatter(TC (&v)[NC], int lane)
+{
+    static_assert(NC == 32 || NC == 64, "32 or 64 values");
+    lane_halve<TC, NC, NC, 32>(v, lane);
+    return v[0];
+}
+
 template <typename TR, typename TC, int PMAX>
 __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves, int nleaves,
                                                   const int *__restrict__ leaf_start,
@@ -257,7 +289,6 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
                                                   int p, c2<TC> *__restrict__ out, int nxcd)
 {
     constexpr int NC = 2 * PMAX;             // partial sums per lane (re, im interleaved)
-    __shared__ TC red[64][NC + 1];
     const int lane = threadIdx.x;
     // each XCD takes a contiguous run of leaves, so the staging windows its circulation
     // reads fall in stay in its own L2
@@ -296,21 +327,15 @@ __global__ __launch_bounds__(64) void p2m_kernel(const int *__restrict__ leaves,
             }
         }
     }
+    TC v[NC];
 #pragma unroll
     for (int m = 0; m < PMAX; ++m) {
-        red[lane][2 * m] = acc[m].x;
-        red[lane][2 * m + 1] = acc[m].y;
+        v[2 * m] = acc[m].x;
+        v[2 * m + 1] = acc[m].y;
     }
-    __syncthreads();
-    // lane -> column col of the 2p partial sums, rows r0, r0 + 1, ... (NC lanes per row set)
-    const int col = lane % NC;
-    const int r0 = (lane / NC) * NC;
-    const int nrow = NC < 64 ? NC : 64;
-    TC sum = 0;
-    for (int r = 0; r < nrow; ++r) sum += red[r0 + r][col];
-    if (NC < 64) sum += __shfl_xor(sum, 32);
-    if (lane < 2 * p) ((TC *)out)[(int64_t)leaf * 2 * p + lane] = sum;
-    __syncthreads();  // red is reused by the next leaf
+    const TC sum = lane_reduce_scatter<TC, NC>(v, lane);
+    const int c = NC == 64 ? lane : lane >> 1;  // the value this lane holds
+    if ((NC == 64 || (lane & 1) == 0) && c < 2 * p) ((TC *)out)[(int64_t)leaf * 2 * p + c] = sum;
     }
 }
 
