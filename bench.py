@@ -399,6 +399,9 @@ def main():
     ap.add_argument("--bwd-steps", type=int, default=3)
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed headline region (for kernel profiling of exactly that work)")
+    ap.add_argument("--headline-precision", choices=["mixed", "fp64"], default="mixed",
+                    help="with --headline-only: the precision of the timed evaluations (fp64: the FP64 leg's "
+                         "near-field kernel, for its counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a device-to-device copy of MIB MiB ten times (HBM counter calibration)")
     ap.add_argument("--cost-model", action="store_true",
@@ -482,17 +485,22 @@ def main():
         per = {kk: (v / st["calls"] if st["calls"] else None) for kk, v in st.items() if kk != "calls"}
         return ms, per
 
+    hp = args.headline_precision if args.headline_only else "mixed"
     # warmup
-    run(args.warmup)
+    run(args.warmup, hp)
     torch.cuda.synchronize()
     log("[bench] warmup done")
     # timed region: overlapped schedule
-    ms, stages = timed(args.steps)
-    log(f"[bench] mixed overlap: {ms:.3f} ms/step, stages {stages}")
+    ms, stages = timed(args.steps, hp)
+    log(f"[bench] {hp} overlap: {ms:.3f} ms/step, stages {stages}")
     if args.headline_only:
-        rl = p2p_roofline("p2p_near_kernel<float>", info["p2p_pairs"], plan, stages["p2p"], PEAK_FP32_VECTOR_TFLOPS,
-                          ISSUABLE_FP32_VECTOR_TFLOPS)
-        print(json.dumps({"ms_per_step": round(ms, 4), "value": round(w.n / (ms * 1e-3) / 1e6, 3),
+        if hp == "fp64":
+            rl = p2p_roofline("p2p_near_kernel<double>", info["p2p_pairs"], plan, stages["p2p"],
+                              PEAK_FP64_VECTOR_TFLOPS, PEAK_FP64_VECTOR_TFLOPS)
+        else:
+            rl = p2p_roofline("p2p_near_kernel<float>", info["p2p_pairs"], plan, stages["p2p"],
+                              PEAK_FP32_VECTOR_TFLOPS, ISSUABLE_FP32_VECTOR_TFLOPS)
+        print(json.dumps({"precision": hp, "ms_per_step": round(ms, 4), "value": round(w.n / (ms * 1e-3) / 1e6, 3),
                           "p2p_avg_ms": round(stages["p2p"], 4), "p2p_tflops": rl["achieved"],
                           "p2p_executed_tflops": rl["executed"]["achieved"], "kernel_sources": kernel_sources_hash(),
                           "steps": args.steps, "warmup": args.warmup}), flush=True)
