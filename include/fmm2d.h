@@ -82,8 +82,9 @@ enum {
                                   most this many wavefronts per SIMD resident (by reserving LDS),
                                   leaving room for the far field beside it; 0 = no cap; -1 (default)
                                   = per call from the tree (mixed: 3 for leaves of more than 2500
-                                  near-field pairs per particle, else by the predicted far/near
-                                  time ratio 6, 5, 4 or none; FP64: 2 or none) */
+                                  near-field pairs per particle with at least 64K near-field work
+                                  entries, else by the predicted far/near time ratio 6, 5, 4 or
+                                  none; FP64: 2 or none) */
     FMM_OPT_VALIDATE = 9      /* 1: every evaluation first checks the circulations (and an adjoint
                                  call its dL/du) for NaN and infinities on the device and returns
                                  FMM_EINVAL, naming the lowest particle index, before any other

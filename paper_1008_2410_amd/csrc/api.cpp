@@ -253,9 +253,11 @@ bool call_overlaps(const fmm_tree *t, int precision)
 }
 
 // Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY), automatic from the tree:
-//  - mixed, leaves of more than ~2500 near-field pairs per particle (2^22-2^24 patch
-//    particles at depths 8-9): 3 wavefronts per SIMD, at which the near field itself runs
-//    faster (2^24 patches at depth 9: 28.5 ms against 32.4 uncapped; 2^23: 8.1 against 9.2);
+//  - mixed, leaves of more than ~2500 near-field pairs per particle and a work list of at
+//    least 64K entries (2^22-2^24 patch particles at depths 8-9): 3 wavefronts per SIMD, at
+//    which the near field itself runs faster (2^24 patches at depth 9: 28.5 ms against 32.4
+//    uncapped; 2^23: 8.1 against 9.1).  With fewer entries the cap idles the chip (uniform
+//    2^22 particles at depth 6, 20K entries: 9.5 ms at cap 3 against 7.6 uncapped);
 //  - mixed, by the predicted far/near ratio r (the far chain takes the slots the cap
 //    leaves): r < 0.12 none, r < 0.9 six (2^24 patches at depth 10: 8.13 ms against 8.40
 //    at five and 8.61 uncapped), 0.9 <= r <= 1.1 five, above four (uniform 2^20-2^22
@@ -269,7 +271,8 @@ int choose_occupancy(const fmm_tree *t, int precision, bool overlap)
     if (t->near_occupancy >= 0) return t->near_occupancy;
     const double r = far_near_ratio(t);
     if (precision == FMM_FP64) return r >= 1.0 ? 2 : 0;
-    if ((double)t->p2p_pairs >= 2500.0 * (double)t->n) return 3;
+    const int64_t entries = use_mutual(t) ? t->nnear_work : t->nunits;
+    if ((double)t->p2p_pairs >= 2500.0 * (double)t->n && entries >= 65536) return 3;
     if (r < 0.12) return 0;
     if (r < 0.9) return 6;
     if (r <= 1.1) return 5;
