@@ -732,33 +732,33 @@ int run_backward(fmm_tree *t, const double *gamma, double sigma, int p, int prec
     t->occupancy_in_use = 0;  // the adjoint's near field is not capped
     const double alpha = record_alpha(sigma, precision);
     const int is_double = precision == FMM_FP64;
-    const FarArgs fc = far_args(t, ws, p, precision, false);
+    FarArgs fc = far_args(t, ws, p, precision, false);
+    fc.gam = nullptr;  // P2M of the charges c reads the staging array: it starts before pack
     const FarArgs fq = far_args(t, ws, p, precision, true);
     Timing tm;
     if ((rc = tm.init(t))) return rc;
 
+    // The two far chains (the charges c: the derivative of their local expansion; the
+    // charges q: the transpose pass A^T q = -A q) are independent: with the two streams the
+    // chain of c runs on the side stream from the staged circulations on, beside the packing
+    // and then the chain of q on the main stream, and the near field follows both.  (Beside
+    // the adjoint's near field, which holds every wavefront slot, they would wait for it to
+    // drain.)
     tm.mark(0, ms);
     launch_stage_in(t, gamma, ms);
-    launch_pack(t, is_double, ws.gam, ms);
-    launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ws.stage, ms);  // stage: free until finalize
-    tm.mark(1, ms);
-    // The two far chains (the charges c: the derivative of their local expansion; the
-    // charges q: the transpose pass A^T q = -A q) are independent: with the two streams they
-    // run beside each other, the q chain on the side stream, the c chain on the main stream,
-    // and the near field follows them.  (Beside the adjoint's near field, which holds every
-    // wavefront slot, they would wait for it to drain.)
     if (overlap) {
         HIP_TRY(hipEventRecord(t->ev_fork, ms));
         HIP_TRY(hipStreamWaitEvent(ss, t->ev_fork, 0));
     }
     tm.mark(2, ss);
-    launch_far_chain(fq, ss);
+    launch_far_chain(fc, ss);
     tm.mark(3, ss);
-    launch_far_chain(fc, ms);
-    if (overlap) {
-        HIP_TRY(hipEventRecord(t->ev_join, ss));
-        HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
-    }
+    if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
+    launch_pack(t, is_double, ws.gam, ms);
+    launch_pack_adjoint(t, cot, scale, ws.adj, ws.rec2, is_double, ws.stage, ms);  // stage: free until finalize
+    tm.mark(1, ms);
+    launch_far_chain(fq, ms);
+    if (overlap) HIP_TRY(hipStreamWaitEvent(ms, t->ev_join, 0));
     tm.mark(4, ms);
     launch_p2p_backward(t, pos, ws.gam, is_double ? (const void *)ws.adj : ws.rec2, is_double, alpha, ws.bwd_near,
                         ws.bwd_b, need_src ? ws.bwd_src : nullptr, ms);
