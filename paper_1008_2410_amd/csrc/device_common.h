@@ -110,7 +110,17 @@ template <typename T> struct SoaRec {
 __device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builtin_amdgcn_exp2f(-s); }
 __device__ __forceinline__ double one_minus_exp(double s) { return -expm1(-s); }
 __device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
-__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+// FP64: the hardware reciprocal estimate refined by two Newton steps r += r (1 - s r), each
+// doubling the correct bits (within an ulp of 1/s, not correctly rounded): 5 instructions
+// against about 10 for the IEEE division, on a positive normal s (s >= tiny).
+__device__ __forceinline__ double recip(double s)
+{
+    double r = __builtin_amdgcn_rcp(s);
+    double e = fma(-s, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-s, r, 1.0);
+    return fma(r, e, r);
+}
 // Added to every s: a pair at distance 0 (the particle itself) then gives g = 0 and a
 // finite Gamma/s (for |Gamma| < 1e18 in FP32), hence exactly zero, while any s above
 // ~1e-13 (FP32) or ~1e-284 (FP64) is unchanged.
