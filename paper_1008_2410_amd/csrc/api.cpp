@@ -262,7 +262,7 @@ bool call_overlaps(const fmm_tree *t, int precision)
 //    leaves): r < 0.12 none, r < 0.9 six (2^24 patches at depth 10: 8.13 ms against 8.40
 //    at five and 8.61 uncapped), 0.9 <= r <= 1.1 five, above four (uniform 2^20-2^22
 //    particles at depths 7-10: four within 0.01 ms of the fastest cap);
-//  - FP64 (at most 4 wavefronts per SIMD): 2 when the far field is the longer part (r >= 1:
+//  - FP64 (at most 5 wavefronts per SIMD): 2 when the far field is the longer part (r >= 1:
 //    the 1024^2 lattice, depth 8, p = 12, coarse levels <= 5 took 0.78 ms against 0.90
 //    uncapped or serialised), else none.
 int choose_occupancy(const fmm_tree *t, int precision, bool overlap)

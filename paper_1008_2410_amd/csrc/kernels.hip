@@ -235,7 +235,7 @@ __device__ __forceinline__ void near_entry(const int4 u, rec_t<T> *tile_a, rec_t
 }
 
 template <typename T>
-__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void p2p_near_kernel(
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 5) void p2p_near_kernel(
     const int4 *__restrict__ work, const c2<T> *__restrict__ pos, const T *__restrict__ gam,
     const int *__restrict__ leaf_start, const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
     int nside, T step, float cut_leaf2, double scale, int dense, int64_t n, double2 *__restrict__ near,
