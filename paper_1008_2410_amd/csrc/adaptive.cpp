@@ -20,7 +20,8 @@ namespace {
 
 void free_ws(AtreeWs &w)
 {
-    hipFree(w.rec);
+    hipFree(w.gam);
+    hipFree(w.stage);
     hipFree(w.gamma);
     hipFree(w.near);
     hipFree(w.slots);
@@ -60,6 +61,7 @@ void free_atree(fmm_atree *t)
             hipFree(p);
     }
     if (t->wsp.use_count() == 1) free_ws(*t->wsp);
+    for (void *q : t->d_pos) hipFree(q);
     if (t->d_flag) hipFree(t->d_flag);
     if (t->ev_fork) hipEventDestroy(t->ev_fork);
     if (t->ev_join) hipEventDestroy(t->ev_join);
@@ -213,13 +215,26 @@ struct Busy {
     }
 };
 
+// The tree's offsets z - c_leaf in the near field's precision, made on first use.
+int ensure_coords(fmm_atree *t, int precision, hipStream_t s)
+{
+    const int k = precision == FMM_FP64;
+    if (t->d_pos[k]) return FMM_OK;
+    int rc = dev_alloc((char **)&t->d_pos[k], (size_t)t->n * (k ? sizeof(double2) : sizeof(float2)),
+                       "leaf offsets of the particles");
+    if (rc) return rc;
+    launch_atree_coords(t, k, t->d_pos[k], s);
+    HIP_TRY(hipGetLastError());
+    return FMM_OK;
+}
+
 int ensure_ws(fmm_atree *t, int p, int precision)
 {
     AtreeWs &w = *t->wsp;
     const size_t n = (size_t)t->n;
     const size_t coef = (size_t)t->ncells * p + kCoefPad;
     int rc;
-    if (w.rec && w.p == p && w.precision == precision) {
+    if (w.gam && w.p == p && w.precision == precision) {
         if (coef <= w.coef_cap) return FMM_OK;
         // a workspace handed over by fmm_atree_rebuild from a tree with fewer cells
         HIP_TRY(hipDeviceSynchronize());
@@ -234,11 +249,13 @@ int ensure_ws(fmm_atree *t, int p, int precision)
         w.coef_cap = coef;
         return FMM_OK;
     }
-    if (w.rec) {
+    if (w.gam) {
         HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the old workspace
         free_ws(w);
     }
-    if ((rc = dev_alloc((char **)&w.rec, n * (precision == FMM_FP64 ? sizeof(double4) : sizeof(float4)), "records")) ||
+    if ((rc = dev_alloc((char **)&w.gam, n * (precision == FMM_FP64 ? sizeof(double) : sizeof(float)),
+                        "circulations in the near field's precision")) ||
+        (rc = dev_alloc(&w.stage, n, "totals")) ||
         (rc = dev_alloc(&w.gamma, n, "circulations")) || (rc = dev_alloc(&w.near, n, "near field")) ||
         (rc = dev_alloc((char **)&w.slots, 9 * n * (precision == FMM_FP64 ? sizeof(double2) : sizeof(float2)),
                         "mutual near-field slots")) ||
@@ -375,8 +392,8 @@ int run(fmm_atree *t, const double *gamma, double sigma, int p, int precision, v
     if (!guard.ok) return fail(FMM_ESTATE, "tree handle in use by another thread");
     HIP_TRY(hipSetDevice(t->device));
     int rc = validate_inputs(t, gamma, nullptr, (hipStream_t)main_stream);
-    if (rc || (rc = ensure_ws(t, p, precision))) return rc;
     hipStream_t ms = (hipStream_t)main_stream;
+    if (rc || (rc = ensure_ws(t, p, precision)) || (rc = ensure_coords(t, precision, ms))) return rc;
     hipStream_t ss = side_stream ? (hipStream_t)side_stream : t->own_side;
     const Tables *tabs = nullptr;
     if ((rc = ensure_m2l_plan(t, p, ms, tabs))) return rc;
@@ -416,7 +433,7 @@ int run_backward(fmm_atree *t, const double *gamma, double sigma, int p, int pre
     }
     const Tables *tabs = nullptr;
     if ((rc = ensure_ws(t, p, precision)) || (rc = ensure_ws_backward(t, src)) ||
-        (rc = ensure_m2l_plan(t, p, ms, tabs)))
+        (rc = ensure_coords(t, precision, ms)) || (rc = ensure_m2l_plan(t, p, ms, tabs)))
         return rc;
     const AtreeCall c{t, p, precision == FMM_FP64, record_alpha(sigma, precision), 0, tabs};
     launch_atree_pack(c, gamma, ms);

@@ -28,28 +28,34 @@ __device__ __forceinline__ double2 cinv(double2 a)
 
 // Records {alpha (z - c_leaf), Gamma, 0} for the near field and the circulations in
 // sorted order for the expansions.
-// The circulation of sorted particle i comes from its staging slot gpos2[i] (the
-// circulations staged by bucket beforehand).
+// The circulation of sorted particle i from its staging slot gpos2[i] (the circulations
+// staged by bucket beforehand): in the near field's precision for its records, in FP64
+// for the expansions.
 template <typename T>
 __global__ __launch_bounds__(256) void at_pack_kernel(int n, int nxcd, const int *__restrict__ gpos2,
-                                                       const int *__restrict__ leaf_of, const int4 *__restrict__ cell,
-                                                       const double2 *__restrict__ xy,
-                                                       const double *__restrict__ gamma_st, double x0, double y0,
-                                                       double side, double alpha, rec_t<T> *__restrict__ rec,
+                                                       const double *__restrict__ gamma_st, T *__restrict__ gam,
                                                        double *__restrict__ gamma_sorted)
 {
     const int i = xcd_block(nxcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double g = gamma_st[gpos2[i]];
+    gam[i] = (T)g;
+    gamma_sorted[i] = g;
+}
+
+// The offsets z - c_leaf of the sorted particles from their leaves' centres, in the near
+// field's precision (made once per tree and precision): the near field's records are
+// these offsets scaled by alpha on load (SoaRec) and the circulations.
+template <typename T>
+__global__ __launch_bounds__(256) void at_coords_kernel(int n, const int *__restrict__ leaf_of,
+                                                         const int4 *__restrict__ cell, const double2 *__restrict__ xy,
+                                                         double x0, double y0, double side, c2<T> *__restrict__ pos)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     const double2 c = cell_centre(x0, y0, side, cell[leaf_of[i]]);
     const double2 z = xy[i];
-    const double g = gamma_st[gpos2[i]];
-    rec_t<T> r;
-    r.x = (T)(alpha * (z.x - c.x));
-    r.y = (T)(alpha * (z.y - c.y));
-    r.z = (T)g;
-    r.w = (T)0;
-    rec[i] = r;
-    gamma_sorted[i] = g;
+    pos[i] = mk<T>((T)(z.x - c.x), (T)(z.y - c.y));
 }
 
 // One step of a wavefront butterfly over all N coefficients (independent shuffles).
@@ -436,7 +442,7 @@ __device__ __forceinline__ void at_target_unit(const int4 u, rec_t<T> *tile, con
                                                const int2 *__restrict__ range, const int *__restrict__ u_off,
                                                const int *__restrict__ u_idx, const int *__restrict__ tile_start,
                                                const double4 *__restrict__ tile_box,
-                                               const rec_t<T> *__restrict__ rec, double x0, double y0, double side,
+                                               const SoaRec<T> &rec, double x0, double y0, double side,
                                                double alpha, double cut, double scale, int dense,
                                                double2 *__restrict__ near)
 {
@@ -447,7 +453,7 @@ __device__ __forceinline__ void at_target_unit(const int4 u, rec_t<T> *tile, con
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
-    const rec_t<T> ri = rec[i];
+    const rec_t<T> ri = rec(i);
     const int A = u.x;
     const int4 cla = cell[A];
     const double2 ca = cell_centre(x0, y0, side, cla);
@@ -467,7 +473,7 @@ __device__ __forceinline__ void at_target_unit(const int4 u, rec_t<T> *tile, con
         for (int base = r.x; base < r.x + r.y; base += 64, ++tt) {
             const int len = min(64, r.x + r.y - base);
             __syncthreads();
-            if (lane < len) tile[lane] = rec[base + lane];
+            if (lane < len) tile[lane] = rec(base + lane);
             const double4 sb = tile_box[tt];
             const double gx = fmax(0.0, fmax(sb.x - tb.z, tb.x - sb.z));
             const double gy = fmax(0.0, fmax(sb.y - tb.w, tb.y - sb.w));
@@ -498,16 +504,17 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 8 : 4) void at_near_kernel(
     const int4 *__restrict__ work, const int4 *__restrict__ cell, const int2 *__restrict__ range,
     const int *__restrict__ u_off, const int *__restrict__ u_idx, const int *__restrict__ tile_start,
     const double4 *__restrict__ tile_box, const int *__restrict__ leaf_start, const int *__restrict__ leaf_tile,
-    const float4 *__restrict__ tile_box_leaf, const rec_t<T> *__restrict__ rec, double x0, double y0, double side,
-    double alpha, double cut, double scale, int dense, int64_t n, double2 *__restrict__ near,
-    c2<T> *__restrict__ slots)
+    const float4 *__restrict__ tile_box_leaf, const c2<T> *__restrict__ pos, const T *__restrict__ gam, double x0,
+    double y0, double side, double alpha, double cut, double scale, int dense, int64_t n,
+    double2 *__restrict__ near, c2<T> *__restrict__ slots)
 {
     __shared__ rec_t<T> tile_a[128], tile_b[128];
+    const SoaRec<T> rec{pos, gam, (T)alpha};  // records alpha (z - c_leaf), Gamma
     const int4 u = work[blockIdx.x];
     if (u.w & kMutualItem) {
         const double step = alpha * ldexp(side, -(u.w >> 9));
-        mutual_item<T>(u, tile_a, tile_b, rec, leaf_start, leaf_tile, tile_box_leaf, (T)step,
-                       (float)(cut / (step * step)), n, slots);
+        mutual_item_src<T, SoaRec<T>>(u, tile_a, tile_b, rec, leaf_start, leaf_tile, tile_box_leaf, (T)step,
+                                      (float)(cut / (step * step)), n, slots);
     } else {
         at_target_unit<T>(u, tile_a, cell, range, u_off, u_idx, tile_start, tile_box, rec, x0, y0, side, alpha, cut,
                           scale, dense, near);
@@ -612,7 +619,7 @@ __device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c
                                                  const int *__restrict__ u_off, const int *__restrict__ u_idx,
                                                  const int *__restrict__ tile_start,
                                                  const double4 *__restrict__ tile_box,
-                                                 const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qt,
+                                                 const SoaRec<T> &rec, const c2<T> *__restrict__ qt,
                                                  double x0, double y0, double side, double alpha, double cut,
                                                  T lambda, double4 *__restrict__ out_pa, double *__restrict__ out_b,
                                                  double4 *__restrict__ out_src)
@@ -624,7 +631,7 @@ __device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c
     const int t = lane & (tp - 1);
     const int k = lane >> logtp;
     const int i = u.y + min(t, u.z - 1);
-    const rec_t<T> ri = rec[i];
+    const rec_t<T> ri = rec(i);
     const int A = u.x;
     const int4 cla = cell[A];
     const double2 ca = cell_centre(x0, y0, side, cla);
@@ -643,7 +650,7 @@ __device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c
             const int len = min(64, r.x + r.y - base);
             __syncthreads();
             if (lane < len) {
-                tile[lane] = rec[base + lane];
+                tile[lane] = rec(base + lane);
                 qtile[lane] = qt[base + lane];
             }
             const double4 sb = tile_box[tt];
@@ -679,12 +686,13 @@ template <typename T, bool SRC>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void at_backward_kernel(
     const int4 *__restrict__ units, const int4 *__restrict__ cell, const int2 *__restrict__ range,
     const int *__restrict__ u_off, const int *__restrict__ u_idx, const int *__restrict__ tile_start,
-    const double4 *__restrict__ tile_box, const rec_t<T> *__restrict__ rec, const c2<T> *__restrict__ qt, double x0,
-    double y0, double side, double alpha, double cut, T lambda, double4 *__restrict__ out_pa,
-    double *__restrict__ out_b, double4 *__restrict__ out_src)
+    const double4 *__restrict__ tile_box, const c2<T> *__restrict__ pos, const T *__restrict__ gam,
+    const c2<T> *__restrict__ qt, double x0, double y0, double side, double alpha, double cut, T lambda,
+    double4 *__restrict__ out_pa, double *__restrict__ out_b, double4 *__restrict__ out_src)
 {
     __shared__ rec_t<T> tile[64];
     __shared__ c2<T> qtile[64];
+    const SoaRec<T> rec{pos, gam, (T)alpha};
     at_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, cell, range, u_off, u_idx, tile_start, tile_box, rec, qt,
                              x0, y0, side, alpha, cut, lambda, out_pa, out_b, out_src);
 }
@@ -796,12 +804,22 @@ void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s)
     launch_stage_rows(n, t->stage_shift, t->d.gpos1, gamma, t->d.st1, s);
     const unsigned g = xcd_grid(n, 256, kXcds);
     if (c.is_double)
-        at_pack_kernel<double><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.leaf_of, t->d.cell, t->d.xy, t->d.st1,
-                                                 t->x0, t->y0, t->side, c.alpha, (double4 *)t->wsp->rec,
+        at_pack_kernel<double><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.st1, (double *)t->wsp->gam,
                                                  t->wsp->gamma);
     else
-        at_pack_kernel<float><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.leaf_of, t->d.cell, t->d.xy, t->d.st1,
-                                                t->x0, t->y0, t->side, c.alpha, (float4 *)t->wsp->rec, t->wsp->gamma);
+        at_pack_kernel<float><<<g, 256, 0, s>>>(n, kXcds, t->d.gpos2, t->d.st1, (float *)t->wsp->gam,
+                                                t->wsp->gamma);
+}
+
+void launch_atree_coords(const fmm_atree *t, int is_double, void *pos, hipStream_t s)
+{
+    const int n = (int)t->n;
+    if (is_double)
+        at_coords_kernel<double><<<blocks(n, 256), 256, 0, s>>>(n, t->d.leaf_of, t->d.cell, t->d.xy, t->x0, t->y0,
+                                                                t->side, (double2 *)pos);
+    else
+        at_coords_kernel<float><<<blocks(n, 256), 256, 0, s>>>(n, t->d.leaf_of, t->d.cell, t->d.xy, t->x0, t->y0,
+                                                               t->side, (float2 *)pos);
 }
 
 // One gather-GEMM launch over up to four target lists (classes).
@@ -927,12 +945,14 @@ void launch_atree_near(const AtreeCall &c, hipStream_t s)
     if (c.is_double)
         at_near_kernel<double><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
-            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const double4 *)t->wsp->rec, t->x0, t->y0, t->side,
+            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const double2 *)t->d_pos[1],
+            (const double *)t->wsp->gam, t->x0, t->y0, t->side,
             c.alpha, cut, scale, t->dense_leaf, t->n, t->wsp->near, (double2 *)t->wsp->slots);
     else
         at_near_kernel<float><<<(unsigned)t->nwork, 64, dyn, s>>>(
             t->d.work, t->d.cell, t->d.range, t->d.u_off, t->d.u_idx, t->d.tile_start, t->d.tile_box,
-            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const float4 *)t->wsp->rec, t->x0, t->y0, t->side,
+            t->d.leaf_start, t->d.leaf_tile, t->d.tile_box_leaf, (const float2 *)t->d_pos[0],
+            (const float *)t->wsp->gam, t->x0, t->y0, t->side,
             c.alpha, cut, scale, t->dense_leaf, t->n, t->wsp->near, (float2 *)t->wsp->slots);
 }
 
@@ -942,10 +962,10 @@ void launch_atree_finalize(const AtreeCall &c, double *uv, double *uv_near, doub
     const fmm_atree *t = c.t;
     const int n = (int)t->n;
     const double scale = c.alpha * kInv2Pi;
-    // uv alone: the totals go to the records (free once the near field and the far chain
-    // are done; n double2 or more), then to user order: through the staging windows once
-    // the output fills the last-level cache, else in sorted order and scattered
-    double2 *staged = uv && !uv_near && !uv_far ? (double2 *)t->wsp->rec : nullptr;
+    // uv alone: the totals go to the staging array (n double2), then to user order:
+    // through the staging windows once the output fills the last-level cache, else in
+    // sorted order and scattered
+    double2 *staged = uv && !uv_near && !uv_far ? t->wsp->stage : nullptr;
     const bool windowed = staged && outputs_windowed(n, sizeof(double2));
     const int *gp = windowed ? t->d.gpos2 : nullptr;
     double *uv_direct = staged ? nullptr : uv;
@@ -991,12 +1011,14 @@ void launch_atree_backward_near(const AtreeCall &c, bool src, hipStream_t s)
     if (c.is_double) {
         auto k = src ? at_backward_kernel<double, true> : at_backward_kernel<double, false>;
         k<<<g, 64, 0, s>>>(d.bwd_units, d.cell, d.range, d.u_off, d.u_idx, d.tile_start, d.tile_box,
-                           (const double4 *)w.rec, (const double2 *)w.qt, t->x0, t->y0, t->side, c.alpha, cut, 1.0,
+                           (const double2 *)t->d_pos[1], (const double *)w.gam, (const double2 *)w.qt, t->x0,
+                           t->y0, t->side, c.alpha, cut, 1.0,
                            w.pa, w.pb, src ? w.psrc : nullptr);
     } else {
         auto k = src ? at_backward_kernel<float, true> : at_backward_kernel<float, false>;
         k<<<g, 64, 0, s>>>(d.bwd_units, d.cell, d.range, d.u_off, d.u_idx, d.tile_start, d.tile_box,
-                           (const float4 *)w.rec, (const float2 *)w.qt, t->x0, t->y0, t->side, c.alpha, cut,
+                           (const float2 *)t->d_pos[0], (const float *)w.gam, (const float2 *)w.qt, t->x0,
+                           t->y0, t->side, c.alpha, cut,
                            0.69314718055994530942f, w.pa, w.pb, src ? w.psrc : nullptr);
     }
 }

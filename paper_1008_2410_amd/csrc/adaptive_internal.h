@@ -94,7 +94,8 @@ __host__ __device__ inline int64_t at_unit_cost(int64_t nsrc, int len)
 struct AtreeWs {
     int p = 0, precision = -1;
     size_t coef_cap = 0;        // elements of each expansion array (mp, lo, mp2, lo2)
-    void *rec = nullptr;        // float4 or double4 records {alpha (z - c_leaf), Gamma, 0}
+    void *gam = nullptr;        // circulations, sorted, in the near field's precision (its records' Gamma)
+    double2 *stage = nullptr;   // totals on their way to user order
     double *gamma = nullptr;    // circulations, sorted
     double2 *near = nullptr;    // near-field (u, v), sorted
     void *slots = nullptr;      // mutual form: 9 x n sums (dY, dX), float2 or double2
@@ -126,6 +127,7 @@ struct fmm_atree {
     int stage_shift = 0;
     int near_occupancy = -1;  // FMM_OPT_NEAR_OCCUPANCY: -1 automatic, 0 no cap, 1..8 the cap
     bool m2l_plan = false;    // d.m2l_targets and d.vslot made
+    void *d_pos[2] = {};      // offsets z - c_leaf of the sorted particles, float2 / double2 (made on first use)
     std::vector<int> m2l_seg_off;  // segment 4 (level - 2) + class: start in d.m2l_targets
     int validate = 0;         // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf
     int *d_flag = nullptr;    // device result of that check
@@ -166,6 +168,8 @@ int build_atree_adjoint_units(fmm_atree *t, hipStream_t s, std::string &err);
 int build_atree_m2l_plan(fmm_atree *t, const int4 *entries, hipStream_t s, std::string &err);
 
 void launch_atree_pack(const AtreeCall &c, const double *gamma, hipStream_t s);
+// the particles' offsets from their leaves' centres in the near field's precision (d_pos)
+void launch_atree_coords(const fmm_atree *t, int is_double, void *pos, hipStream_t s);
 // adjoint false: the far field of the charges c (mp, lo); true: of the adjoint charges
 // q (mp2, lo2)
 void launch_atree_far(const AtreeCall &c, hipStream_t s, bool adjoint = false);

@@ -81,15 +81,11 @@ template <typename R> struct RecScalar;
 template <> struct RecScalar<float4> { using type = float; };
 template <> struct RecScalar<double4> { using type = double; };
 
-// Where the near-field kernels read a particle's record from:
-//   AosRec: an array of records {X, Y, Gamma, 0} (the adaptive tree);
-//   SoaRec: leaf-unit coordinates xi = (z - c_leaf)/w, kept with the tree, scaled on load
-//           by alpha w, and the circulations in tree order, gathered per call (the uniform
-//           tree: only the circulations change between calls).
-template <typename T> struct AosRec {
-    const rec_t<T> *__restrict__ r;
-    __device__ __forceinline__ rec_t<T> operator()(int64_t i) const { return r[i]; }
-};
+// Where the near-field kernels read a particle's record {X, Y, Gamma, 0} from: the
+// particles' coordinates relative to their leaf's centre, kept with the tree and scaled on
+// load (the uniform tree: leaf-unit coordinates xi = (z - c_leaf)/w scaled by alpha w; the
+// adaptive tree, whose leaves have several widths: z - c_leaf scaled by alpha), and the
+// circulations in tree order, gathered per call (only they change between calls).
 template <typename T> struct SoaRec {
     const c2<T> *__restrict__ pos;
     const T *__restrict__ gam;
@@ -422,16 +418,6 @@ __device__ __forceinline__ void mutual_item_src(const int4 it, rec_t<T> *tile_a,
                                      cut_leaf2, slot_s, slot_r);
 }
 
-// The mutual item over an array of records (the adaptive tree).
-template <typename T>
-__device__ __forceinline__ void mutual_item(const int4 it, rec_t<T> *tile_a, rec_t<T> *tile_b,
-                                            const rec_t<T> *__restrict__ rec, const int *__restrict__ leaf_start,
-                                            const int *__restrict__ tile_start, const float4 *__restrict__ tile_box,
-                                            T step, float cut_leaf2, int64_t n, c2<T> *__restrict__ slots)
-{
-    mutual_item_src<T, AosRec<T>>(it, tile_a, tile_b, AosRec<T>{rec}, leaf_start, tile_start, tile_box, step,
-                                  cut_leaf2, n, slots);
-}
 
 // ---------------------------------------------------------------------------------
 // Adjoint near field (shared by the uniform and the adaptive tree)
