@@ -135,9 +135,16 @@ int fmm_build_tree_host(const double *xy, int64_t n, int depth, const double *ro
  * Builds a new tree for xy as fmm_build_tree does, with the depth and the FMM_OPT_*
  * options of `prev`, and hands prev's evaluation workspace to it; prev is then destroyed.
  * A time-stepping loop that rebuilds this way allocates the workspace once instead of
- * once per tree.
- *   prev      tree of the same n on the current device; destroyed on success (after a
- *             device synchronisation, as fmm_destroy_tree), unchanged on error.
+ * once per tree.  The rebuild holds one tree's arrays at a time: it synchronises the
+ * device, its temporaries use the workspace's per-call region (so no call on a tree
+ * sharing that workspace may run meanwhile), and prev's arrays are released as soon as
+ * the positions have passed their checks, before the new tree's are allocated.
+ *   prev      tree of the same n on the current device, or one left without arrays by a
+ *             failed rebuild; destroyed on success.  On an error found before the build
+ *             starts (NULL or busy prev, other n or device) or by the position checks
+ *             (FMM_ERANGE, FMM_EINVAL) prev is unchanged.  On a later error (FMM_ENOMEM,
+ *             FMM_EDEVICE) prev keeps its workspace and options but has no arrays: every
+ *             call on it but fmm_rebuild_tree and fmm_destroy_tree then returns FMM_ESTATE.
  *   xy, n, root_box, stream, out   as fmm_build_tree; n must equal prev's (FMM_EINVAL).
  * FMM_ESTATE for a NULL prev or one in use by another call. */
 int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, const double *root_box, void *stream,

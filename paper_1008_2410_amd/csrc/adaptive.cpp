@@ -511,6 +511,7 @@ extern "C" int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int ma
         free_atree(t);
         return rc;
     }
+    trim_pool(t->device);  // the build's temporaries
     *out = t;
     return FMM_OK;
 }
@@ -953,5 +954,7 @@ extern "C" void fmm_atree_destroy(fmm_atree *t)
 {
     if (!t) return;
     hipSetDevice(t->device);
+    const int dev = t->device;
     free_atree(t);
+    trim_pool(dev);
 }

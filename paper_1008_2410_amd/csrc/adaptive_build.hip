@@ -773,8 +773,8 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
     Buf<uint32_t> ucnt, wcnt, vcnt;
     if (!st.check(werr.alloc(1, s), "adaptive tree build") ||
         !st.check(hipMemsetAsync(werr.p, 0, sizeof(int), s), "adaptive tree build") ||
-        !st.check(ucnt.alloc(K + 1, s), "adaptive tree lists") || !st.check(wcnt.alloc(K + 1, s), "adaptive tree lists") ||
-        !st.check(vcnt.alloc(K + 1, s), "adaptive tree lists"))
+        !st.check(ucnt.alloc(K + 1, s, true), "adaptive tree lists") || !st.check(wcnt.alloc(K + 1, s, true), "adaptive tree lists") ||
+        !st.check(vcnt.alloc(K + 1, s, true), "adaptive tree lists"))
         return failed();
     ak_vlist<false><<<grid_for(K + 1, 256), 256, 0, s>>>(cs.cell, cs.parent, cs.child, cs.coll, K, vcnt.p, nullptr,
                                                          nullptr);
@@ -793,7 +793,7 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
     d.w_off = (int *)wcnt.release();
     Buf<uint32_t> wown;
     if (!alloc_to(d.v_idx, nv, s, st, "V list") || !alloc_to(d.u_idx, nu, s, st, "U list") ||
-        !alloc_to(d.w_idx, nw, s, st, "W list") || !st.check(wown.alloc(nw, s), "W list"))
+        !alloc_to(d.w_idx, nw, s, st, "W list") || !st.check(wown.alloc(nw, s, true), "W list"))
         return failed();
     ak_vlist<true><<<grid_for(K + 1, 256), 256, 0, s>>>(cs.cell, cs.parent, cs.child, cs.coll, K, nullptr, d.v_off,
                                                         d.v_idx);
@@ -803,7 +803,7 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
     {
         Buf<uint32_t> xcnt;
         Buf<uint64_t> xkey;
-        if (!st.check(xcnt.alloc(K + 1, s), "X list") ||
+        if (!st.check(xcnt.alloc(K + 1, s, true), "X list") ||
             !st.check(hipMemsetAsync(xcnt.p, 0, (K + 1) * sizeof(uint32_t), s), "X list") ||
             !st.check(xkey.alloc(nw, s), "X list"))
             return failed();
@@ -847,7 +847,7 @@ int build_atree_device(fmm_atree *t, const double *xy, const double *root_box, h
     uint32_t ntiles = 0;
     {
         Buf<uint32_t> nt;
-        if (!st.check(nt.alloc((int64_t)NL + 1, s), "tiles")) return failed();
+        if (!st.check(nt.alloc((int64_t)NL + 1, s, true), "tiles")) return failed();
         ak_leaf_ntiles<<<grid_for((int64_t)NL + 1, 256), 256, 0, s>>>(leaves.p, cs.range, (int)NL, nt.p);
         if (!scan_exclusive(nt.p, nt.p, (int64_t)NL + 1, &ntiles, s, st)) return failed();
         d.leaf_tile = (int *)nt.release();  // NL + 1 entries, the last = ntiles

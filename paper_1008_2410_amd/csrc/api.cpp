@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <numeric>
 #include <string>
@@ -12,6 +13,7 @@
 
 #include "../../include/fmm2d.h"
 #include "api_common.h"
+#include "build_prims.h"
 #include "fmm_internal.h"
 
 using namespace fmm;
@@ -44,25 +46,40 @@ void free_workspace(Workspace &ws, hipStream_t s)
     ws = Workspace{};
 }
 
-void free_tree(fmm_tree *t)
+// The tree's device arrays (not its workspace, streams or events), freed in the order of
+// stream fs; the caller has finished the work that used them.  Arrays of the device build
+// come from the stream-ordered pool, those of the host build from hipMalloc; the
+// near-field plan and the leaf-unit coordinates are always pooled.
+void release_tree_arrays(fmm_tree *t, hipStream_t fs)
 {
-    // arrays of the device build come from the stream-ordered pool (freed without a
-    // device synchronisation), those of the host build from hipMalloc; the near-field
-    // plan is always pooled
-    hipStream_t fs = t->own_side;  // the caller has finished the work on the tree
-    auto release = [fs](void *p, bool pooled) {
+    auto release = [fs](auto *&p, bool pooled) {
         if (!p) return;
-        if (pooled) hipFreeAsync(p, fs);
-        else hipFree(p);
+        if (pooled) hipFreeAsync((void *)p, fs);
+        else hipFree((void *)p);
+        p = nullptr;
     };
-    for (void *p : {(void *)t->d_perm, (void *)t->d_gpos1, (void *)t->d_gpos2, (void *)t->d_st1, (void *)t->d_leaf_of,
-                    (void *)t->d_xy, (void *)t->d_leaf_start, (void *)t->d_counts, (void *)t->d_lists,
-                    (void *)t->d_units, (void *)t->d_tile_start, (void *)t->d_tile_box})
-        release(p, t->pooled);
+    release(t->d_perm, t->pooled);
+    release(t->d_gpos1, t->pooled);
+    release(t->d_gpos2, t->pooled);
+    release(t->d_st1, t->pooled);
+    release(t->d_leaf_of, t->pooled);
+    release(t->d_xy, t->pooled);
+    release(t->d_leaf_start, t->pooled);
+    release(t->d_counts, t->pooled);
+    release(t->d_lists, t->pooled);
+    release(t->d_units, t->pooled);
+    release(t->d_tile_start, t->pooled);
+    release(t->d_tile_box, t->pooled);
     release(t->d_near_work, true);
     release(t->d_leaf_mask, true);
     release(t->d_pos[0], true);
     release(t->d_pos[1], true);
+}
+
+void free_tree(fmm_tree *t)
+{
+    hipStream_t fs = t->own_side;  // the caller has finished the work on the tree
+    release_tree_arrays(t, fs);
     hipFree(t->d_flag);
     if (t->wsp.use_count() == 1) free_workspace(*t->wsp, fs);
     if (t->own_side) hipStreamDestroy(t->own_side);
@@ -145,6 +162,7 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
         const size_t o_b = a256(32 * nn), o_src = a256(o_b + 8 * nn);
         const size_t bytes = std::max(9 * nn * (precision == FMM_FP64 ? 16 : 8), o_src + 32 * nn);
         if ((rc = dev_alloc_async((char **)&ws.sums, bytes, "near-field sums", s))) return rc;
+        ws.sums_bytes = bytes;
         ws.slots = ws.sums;
         ws.bwd_near = (double4 *)ws.sums;
         ws.bwd_b = (double *)((char *)ws.sums + o_b);
@@ -173,9 +191,18 @@ int ensure_workspace(fmm_tree *t, int p, int precision, bool backward, hipStream
     return FMM_OK;
 }
 
-int check_eval_args(fmm_tree *t, const double *gamma, double sigma, int p, int precision)
+// A handle whose arrays are there (see fmm_tree::released).
+int check_tree(const fmm_tree *t)
 {
     if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (t->released)
+        return fail(FMM_ESTATE, "the tree's arrays were released by a failed rebuild: rebuild or destroy it");
+    return FMM_OK;
+}
+
+int check_eval_args(fmm_tree *t, const double *gamma, double sigma, int p, int precision)
+{
+    if (int rc = check_tree(t)) return rc;
     if (!gamma) return fail(FMM_EINVAL, "gamma is NULL");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FMM_EINVAL, "sigma must be finite and > 0");
     if (p < 1 || p > kMaxP) return fail(FMM_EINVAL, "p must be in [1, 32]");
@@ -479,9 +506,10 @@ int finish_tree(fmm_tree *t, hipStream_t s)
 namespace {
 
 // The device build; the options of `opts` (a tree being replaced) are taken over before
-// the near-field plan is made, since that plan depends on them.
+// the near-field plan is made, since that plan depends on them.  arena: device memory
+// idle during the build that its temporaries may use; after_checks: see build_tree_device.
 int build_device(const double *xy, int64_t n, int depth, const double *root_box, void *stream, const fmm_tree *opts,
-                 fmm_tree **out)
+                 fmm_tree **out, BuildArena *arena = nullptr, const std::function<void()> &after_checks = {})
 {
     fmm_tree *t = nullptr;
     int rc = new_tree(xy, n, depth, root_box, out, t);
@@ -498,16 +526,20 @@ int build_device(const double *xy, int64_t n, int depth, const double *root_box,
     hipStream_t s = (hipStream_t)stream;
     std::string err;
     int64_t bad = -1;
-    rc = build_tree_device(t, xy, root_box, s, err, bad);
-    if (!rc) rc = finish_tree(t, s);
-    else {
-        if (bad >= 0) err += " (particle " + std::to_string(bad) + ")";
-        fail(rc, err);
+    {
+        BuildArenaScope scope(arena);
+        rc = build_tree_device(t, xy, root_box, s, err, bad, after_checks);
+        if (!rc) rc = finish_tree(t, s);
+        else {
+            if (bad >= 0) err += " (particle " + std::to_string(bad) + ")";
+            fail(rc, err);
+        }
     }
     if (rc) {
         free_tree(t);
         return rc;
     }
+    if (!arena) trim_pool(t->device);  // the temporaries came from the pool
     *out = t;
     return FMM_OK;
 }
@@ -532,10 +564,24 @@ extern "C" int fmm_rebuild_tree(fmm_tree *prev, const double *xy, int64_t n, con
     if (dev != prev->device) return fail(FMM_EINVAL, "the current device is not the tree's");
     BusyGuard guard(prev);
     if (!guard.ok) return fail(FMM_ESTATE, "tree is in use by another call");
+    // Earlier calls on prev, or on a tree sharing its workspace, may still use the
+    // workspace and prev's arrays.
+    HIP_TRY(hipDeviceSynchronize());
+    // One tree's arrays at a time: the build's temporaries go to the workspace's per-call
+    // region (idle between calls), and prev's arrays are released once the positions have
+    // passed their checks, before the new ones are allocated.
+    BuildArena arena;
+    arena.base = (char *)prev->wsp->sums;
+    arena.cap = prev->wsp->sums ? prev->wsp->sums_bytes : 0;
+    hipStream_t s = (hipStream_t)stream;
+    auto release_prev = [prev, s]() {
+        release_tree_arrays(prev, s);
+        prev->released = true;
+    };
     fmm_tree *t = nullptr;
-    int rc = build_device(xy, n, prev->depth, root_box, stream, prev, &t);
+    int rc = build_device(xy, n, prev->depth, root_box, stream, prev, &t, &arena, release_prev);
     if (rc) return rc;
-    hipError_t e = hipDeviceSynchronize();  // work of earlier calls on prev may still use its workspace
+    hipError_t e = hipDeviceSynchronize();  // the build used the workspace
     if (e != hipSuccess) {
         free_tree(t);
         return hip_fail(e, "hipDeviceSynchronize");
@@ -630,7 +676,7 @@ extern "C" int fmm_share_workspace(fmm_tree *t, fmm_tree *from)
 extern "C" int fmm_tree_info(const fmm_tree *t, int64_t *n, int *depth, double *root_box, int64_t *p2p_pairs,
                              int64_t *m2l_pairs, int64_t *nonempty_leaves, int64_t *max_leaf)
 {
-    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (int rc = check_tree(t)) return rc;
     if (n) *n = t->n;
     if (depth) *depth = t->depth;
     if (root_box) {
@@ -651,7 +697,7 @@ void launch_widen_perm(const fmm_tree *t, int64_t *perm, int32_t *leaf, hipStrea
 
 extern "C" int fmm_tree_levels(const fmm_tree *t, int64_t *nonempty, int max_levels)
 {
-    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (int rc = check_tree(t)) return rc;
     if (!nonempty || max_levels < 1) return fail(FMM_EINVAL, "nonempty is NULL or max_levels < 1");
     std::vector<int> h((size_t)level_base(std::min(t->depth, 1) + 1));
     for (int l = 0; l < max_levels; ++l) nonempty[l] = 0;
@@ -667,7 +713,7 @@ extern "C" int fmm_tree_levels(const fmm_tree *t, int64_t *nonempty, int max_lev
 
 extern "C" int fmm_tree_permutation(const fmm_tree *t, int64_t *perm, int32_t *leaf, void *stream)
 {
-    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (int rc = check_tree(t)) return rc;
     if (!perm) return fail(FMM_EINVAL, "perm is NULL");
     HIP_TRY(hipSetDevice(t->device));
     launch_widen_perm(t, perm, leaf, (hipStream_t)stream);
@@ -839,6 +885,7 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
             return fail(FMM_EINVAL, "near mutual must be 0 or 1");
         if (key == FMM_OPT_DENSE_LEAF && (value < 1 || value > (int64_t(1) << 30)))
             return fail(FMM_EINVAL, "dense leaf must be in [1, 2^30]");
+        if (int rc = check_tree(t)) return rc;  // the plan is made from the tree's arrays
         HIP_TRY(hipSetDevice(t->device));
         HIP_TRY(hipDeviceSynchronize());  // the plan's arrays may be in use
         if (key == FMM_OPT_NEAR_MUTUAL) t->near_mutual = (int)value;
@@ -870,7 +917,7 @@ extern "C" int fmm_set_option(fmm_tree *t, int key, int64_t value)
 extern "C" int fmm_near_plan_info(const fmm_tree *t, int64_t *mutual_items, int64_t *mutual_pairs,
                                   int64_t *target_units)
 {
-    if (!t) return fail(FMM_ESTATE, "null tree handle");
+    if (int rc = check_tree(t)) return rc;
     const bool m = use_mutual(t);
     if (mutual_items) *mutual_items = m ? t->nmut : 0;
     if (mutual_pairs) *mutual_pairs = m ? t->mutual_pairs : 0;
@@ -932,7 +979,9 @@ extern "C" void fmm_destroy_tree(fmm_tree *t)
     if (!t) return;
     hipSetDevice(t->device);
     hipDeviceSynchronize();
+    const int dev = t->device;
     free_tree(t);
+    trim_pool(dev);
 }
 
 int fmm::fail(int code, const std::string &msg)
@@ -954,6 +1003,14 @@ void fmm::retain_pool(int device)
     }
     (void)hipGetLastError();
     done.fetch_or(uint64_t(1) << device);
+}
+
+void fmm::trim_pool(int device)
+{
+    hipMemPool_t pool;
+    if (hipDeviceSynchronize() == hipSuccess && hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess)
+        (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
 }
 
 double fmm::record_alpha(double sigma, int precision)

@@ -57,6 +57,10 @@ int dev_alloc_async(T **p, size_t count, const char *what, hipStream_t s)
 // them at every synchronisation, so that trees built and destroyed in a loop (time
 // stepping) allocate from the pool.  Once per device.
 void retain_pool(int device);
+// Return the pool's unused memory to the device (after a fresh build, whose temporaries
+// are freed, and when a tree is destroyed), so that what the pool holds follows what the
+// library's trees and workspaces hold.  Synchronises the device first.
+void trim_pool(int device);
 
 template <typename T>
 int upload(T **p, const std::vector<T> &h, const char *what)

@@ -8,12 +8,51 @@
 #include <algorithm>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/fmm2d.h"
 
 namespace fmm {
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+// A region of device memory that is idle during a build (the per-call region of the
+// evaluation workspace that a rebuilt tree takes over), lent to the build's temporaries
+// as a stack: a block is taken at the top and the top moves back down when the topmost
+// blocks have been given back.  All of a build's work runs on one stream, so a block
+// given back while kernels that use it are still queued is only reused by kernels queued
+// after them.  Requests that do not fit go to the stream-ordered pool.
+struct BuildArena {
+    char *base = nullptr;
+    size_t cap = 0;
+    struct Block {
+        size_t off, end;
+        bool live;
+    };
+    std::vector<Block> stack;
+    void *take(size_t bytes)
+    {
+        const size_t off = stack.empty() ? 0 : (stack.back().end + 255) / 256 * 256;
+        if (!base || off + bytes > cap) return nullptr;
+        stack.push_back({off, off + bytes, true});
+        return base + off;
+    }
+    void give(void *p)
+    {
+        for (Block &b : stack)
+            if (base + b.off == (char *)p) b.live = false;
+        while (!stack.empty() && !stack.back().live) stack.pop_back();
+    }
+};
+
+// The arena of the build running on this host thread (null: temporaries from the pool).
+inline thread_local BuildArena *t_build_arena = nullptr;
+
+struct BuildArenaScope {
+    BuildArena *prev;
+    explicit BuildArenaScope(BuildArena *a) : prev(t_build_arena) { t_build_arena = a; }
+    ~BuildArenaScope() { t_build_arena = prev; }
+};
 
 // Device buffer owned for the duration of a build step.
 template <typename T>
@@ -22,15 +61,29 @@ struct Buf {
     // temporary can be released while kernels that use it are still queued
     T *p = nullptr;
     hipStream_t s = nullptr;
+    BuildArena *arena = nullptr;  // the block came from this arena
     ~Buf()
     {
-        if (p) (void)hipFreeAsync(p, s);
+        if (!p) return;
+        if (arena) arena->give(p);
+        else (void)hipFreeAsync(p, s);
     }
-    hipError_t alloc(int64_t count, hipStream_t stream)
+    // kept: the buffer outlives the build (handed to the tree by release()), so it never
+    // comes from the arena
+    hipError_t alloc(int64_t count, hipStream_t stream, bool kept = false)
     {
         s = stream;
-        return hipMallocAsync((void **)&p, (size_t)std::max<int64_t>(count, 1) * sizeof(T), stream);
+        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        if (!kept && t_build_arena) {
+            if (void *q = t_build_arena->take(bytes)) {
+                p = (T *)q;
+                arena = t_build_arena;
+                return hipSuccess;
+            }
+        }
+        return hipMallocAsync((void **)&p, bytes, stream);
     }
+    // hands the buffer over (allocated with kept = true)
     T *release()
     {
         T *q = p;

@@ -6,6 +6,7 @@
 
 #include <array>
 #include <atomic>
+#include <functional>
 #include <memory>
 #include <cstdint>
 #include <string>
@@ -92,6 +93,7 @@ struct Workspace {
     // slots (9 x n float2 or double2) or the adjoint's near sums (bwd_near, bwd_b, bwd_src),
     // never live in the same call.
     void *sums = nullptr;
+    size_t sums_bytes = 0;
     void *slots = nullptr;        // = sums
 };
 
@@ -114,6 +116,9 @@ struct fmm_tree {
     int timing = 0;
     int validate = 0;    // FMM_OPT_VALIDATE: check circulations (and dL/du) for NaN / Inf first
     std::atomic<int> busy{0};
+    // the tree's arrays were released by a rebuild that failed after the position checks:
+    // only fmm_rebuild_tree and fmm_destroy_tree accept the handle
+    bool released = false;
 
     // host statistics
     int64_t p2p_pairs = 0, m2l_pairs = 0, nonempty_leaves = 0, max_leaf = 0;
@@ -191,8 +196,11 @@ struct FarArgs {
 // Launchers (kernels.hip).  All are asynchronous on `s`.
 // Stages 1-3 on the device (tree_build.hip); the near-field plan from the device leaf
 // offsets (used by both builds).  FMM_* status; err / bad_index describe a failure.
+// after_checks (if set) runs once the positions have passed their checks (inside the
+// root cell, finite), before the sorted arrays are allocated: a rebuild releases the old
+// tree's arrays there.
 int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
-                      int64_t &bad_index);
+                      int64_t &bad_index, const std::function<void()> &after_checks = {});
 int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err);
 
 // Pass 1 of the circulations into tree order (the staging array, all P2M needs), then

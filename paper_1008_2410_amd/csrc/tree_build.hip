@@ -706,7 +706,7 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
     Buf<uint32_t> nent;
     Buf<uint16_t> mask;
     Buf<unsigned long long> stats;
-    if (!st.check(nent.alloc(nleaf + 1, s), "near-field plan") || !st.check(mask.alloc(nleaf, s), "near-field plan") ||
+    if (!st.check(nent.alloc(nleaf + 1, s), "near-field plan") || !st.check(mask.alloc(nleaf, s, true), "near-field plan") ||
         !st.check(stats.alloc(4, s), "near-field plan") ||
         !st.check(hipMemsetAsync(stats.p, 0, 4 * sizeof(unsigned long long), s), "near-field plan")) {
         err = st.msg;
@@ -727,7 +727,7 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
     Buf<int4> work, sorted;
     Buf<uint64_t> key;
     Buf<uint32_t> val;
-    if (!st.check(work.alloc(total, s), "near-field plan") || !st.check(sorted.alloc(total, s), "near-field plan") ||
+    if (!st.check(work.alloc(total, s), "near-field plan") || !st.check(sorted.alloc(total, s, true), "near-field plan") ||
         !st.check(key.alloc(total, s), "near-field plan") || !st.check(val.alloc(total, s), "near-field plan")) {
         err = st.msg;
         return st.code;
@@ -757,7 +757,7 @@ int build_near_plan_device(fmm_tree *t, hipStream_t s, std::string &err)
 // offending particle for FMM_EINVAL / FMM_ERANGE.
 // ---------------------------------------------------------------------------------
 int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hipStream_t s, std::string &err,
-                      int64_t &bad_index)
+                      int64_t &bad_index, const std::function<void()> &after_checks)
 {
     t->pooled = true;
     Status st;
@@ -813,6 +813,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
             return (hf & 2) ? FMM_EINVAL : FMM_ERANGE;
         }
     }
+    if (after_checks) after_checks();
     if (!radix_sort(key.p, val.p, n, 2 * L + 12, s, st)) return failed();
     if (!st.check(hipMallocAsync((void **)&t->d_perm, n * sizeof(int), s), "permutation") ||
         !st.check(hipMallocAsync((void **)&t->d_leaf_of, n * sizeof(int), s), "leaf ids") ||
@@ -828,7 +829,7 @@ int build_tree_device(fmm_tree *t, const double *xy, const double *root_box, hip
     // Tiles and their boxes.
     uint32_t ntiles = 0;
     Buf<uint32_t> tstart;
-    if (!st.check(tstart.alloc(nleaf + 1, s), "tile offsets")) return failed();
+    if (!st.check(tstart.alloc(nleaf + 1, s, true), "tile offsets")) return failed();
     k_leaf_tiles<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(t->d_leaf_start, nleaf, tstart.p);
     if (!scan_exclusive(tstart.p, tstart.p, nleaf + 1, &ntiles, s, st)) return failed();
     Buf<int> tile_leaf;

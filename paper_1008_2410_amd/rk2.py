@@ -77,10 +77,11 @@ def _rebuilt(tree, xy, depth, root_box, stats: RK2Stats, adaptive=None):
     return tree
 
 
-def _stage(tree, x_base, h, gamma, sigma, p, precision, stats: RK2Stats):
-    """x_base + h u over `tree` (one fmm_transport_step), timed as a velocity evaluation."""
+def _stage(tree, x_base, h, gamma, sigma, p, precision, stats: RK2Stats, out=None):
+    """x_base + h u over `tree` (one fmm_transport_step, into `out` when given), timed as a
+    velocity evaluation."""
     t0 = time.perf_counter()
-    out = tree.transport_step(gamma, sigma, p, precision, x_base, h)
+    out = tree.transport_step(gamma, sigma, p, precision, x_base, h, out)
     torch.cuda.synchronize(x_base.device)
     stats.velocity += time.perf_counter() - t0
     stats.evals += 1
@@ -125,7 +126,9 @@ def rk2_backward(checkpoints, gamma: torch.Tensor, sigma: float, depth: int, p: 
         for k, x in enumerate(reversed(checkpoints)):
             t0 = time.perf_counter()
             tree0 = _rebuilt(tree0, x, depth, root_box, stats, adaptive)
-            xm = _stage(tree0, x, 0.5 * dt, g, sigma, p, precision, stats)
+            # the midpoint is only read by the build of its tree (which keeps its own sorted
+            # copy), so it lives in lam_half until the first product overwrites it
+            xm = _stage(tree0, x, 0.5 * dt, g, sigma, p, precision, stats, out=lam_half)
             first = treem is None
             treem = _rebuilt(treem, xm, depth, root_box, stats, adaptive)
             if first:

@@ -182,3 +182,57 @@ def test_rebuild_errors_leave_the_tree(fmm_mod):
     rc = lib.fmm_rebuild_tree(None, ctypes.c_void_p(xy.data_ptr()), n, None, None, ctypes.byref(out))
     assert rc == _lib.FMM_ESTATE
     tree.close()
+
+
+def _pool_bytes(attr):
+    """An attribute of the device's default stream-ordered pool (the library's arrays)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    pool = ctypes.c_void_p()
+    assert hip.hipDeviceGetDefaultMemPool(ctypes.byref(pool), 0) == 0
+    v = ctypes.c_uint64()
+    assert hip.hipMemPoolGetAttribute(pool, ctypes.c_int(attr), ctypes.byref(v)) == 0
+    return hip, pool, v.value
+
+
+def test_rebuild_holds_one_tree(fmm_mod):
+    """A rebuild with a workspace releases the old tree's arrays before it allocates the
+    new ones and keeps its temporaries in the workspace's per-call region: the library's
+    device memory never grows by more than a small part of one tree's arrays while the
+    tree is rebuilt (building the new tree beside the old one, with temporaries from the
+    pool, would add about twice a tree's arrays).  Outputs after the rebuild as from a
+    fresh tree (bit for bit)."""
+    import ctypes
+    used_cur, used_high = 7, 8   # hipMemPoolAttrUsedMemCurrent, hipMemPoolAttrUsedMemHigh
+    r = np.random.Generator(np.random.PCG64(31))
+    n, depth, p, sigma = 1 << 18, 7, 12, 0.002
+    x0 = _t(r.random((n, 2)))
+    x1 = _t(np.clip(r.random((n, 2)) ** 1.5, 0.0, 1.0))
+    g = _t(r.standard_normal(n))
+    dl = _t(r.standard_normal((n, 2)))
+    box = (0.0, 0.0, 1.0)
+    tree = fmm_mod.Tree(x0, depth, box)
+    tree.velocity(g, sigma, p, "mixed")
+    tree.velocity_backward(g, sigma, p, "mixed", dl, need_src=True)
+    import torch
+    torch.cuda.synchronize()
+    hip, pool, before = _pool_bytes(used_cur)
+    other = fmm_mod.Tree(x1, depth, box)
+    torch.cuda.synchronize()
+    tree_bytes = _pool_bytes(used_cur)[2] - before
+    other.close()
+    torch.cuda.synchronize()
+    assert tree_bytes > 20 * n   # the sorted positions, permutations and staging alone
+    zero = ctypes.c_uint64(0)
+    if hip.hipMemPoolSetAttribute(pool, ctypes.c_int(used_high), ctypes.byref(zero)) != 0:
+        pytest.skip("the pool's high-water mark cannot be reset on this runtime")
+    before = _pool_bytes(used_cur)[2]
+    assert _pool_bytes(used_high)[2] <= before + (1 << 20)
+    tree.rebuild(x1, box)
+    torch.cuda.synchronize()
+    growth = _pool_bytes(used_high)[2] - before
+    assert growth < 0.25 * tree_bytes, (growth, tree_bytes)
+    fresh = fmm_mod.Tree(x1, depth, box)
+    _same_tree_outputs(tree, fresh, g, sigma, p, dl)
+    fresh.close()
+    tree.close()
