@@ -656,16 +656,19 @@ __device__ __forceinline__ void at_backward_unit(const int4 u, rec_t<T> *tile, c
             const double4 sb = tile_box[tt];
             const double gx = fmax(0.0, fmax(sb.x - tb.z, tb.x - sb.z));
             const double gy = fmax(0.0, fmax(sb.y - tb.w, tb.y - sb.w));
-            const bool far = (gx * gx + gy * gy) * a2 >= cut;
+            // beyond the exponential's cut: point-vortex terms; beyond twice the series cut: no
+            // per-pair series test
+            const double g2 = (gx * gx + gy * gy) * a2;
+            const int cls = g2 >= cut ? 2 : g2 >= 2.0 * (double)series_cut<T>() / (double)lambda ? 1 : 0;
             __syncthreads();
             switch (logtp) {
-            case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-            default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+            case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+            default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
             }
         }
 #pragma unroll

@@ -439,8 +439,10 @@ template <> __device__ __forceinline__ double series_cut<double>() { return 1e-3
 // acc: Phi (2); A as its real part and its imaginary part divided by -2 (the factor is
 // applied in finalize); B; with SRC also the source-position sums with the adjoint
 // charges, At = sum q_j conj(dz')^2 (lambda e s' - g)/s'^2 (2) and Bt = sum q_j e (2).
-// conj(dz')^2 = (dx'^2 - dy'^2) - 2i dx' dy' reuses dy'^2 from s'.
-template <typename T, bool FAR, bool SRC>
+// conj(dz')^2 = (dx'^2 - dy'^2) - 2i dx' dy' reuses dy'^2 from s'.  SERIES false: the
+// pair is known to lie beyond the series cut (its tile's bounding boxes say so), and the
+// test is left out.
+template <typename T, bool FAR, bool SRC, bool SERIES = true>
 __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj, T tx, T ty, T lambda,
                                              T (&acc)[SRC ? 9 : 5])
 {
@@ -475,14 +477,18 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
     }
     T e, g;
     exp_pair(s, e, g);
-    T gr = g * r;
+    // g/s': in FP32 as r - e r (one fused multiply-add, as the forward's kernel); in FP64
+    // from the accurate g of exp_pair
+    T gr;
+    if constexpr (sizeof(T) == 4) gr = fma(-e, r, r);
+    else gr = g * r;
     T h = (lambda * e - gr) * r;  // lambda e/s' - g/s'^2
     // x = lambda s' is the natural exponent |dz|^2/(2 sigma^2).  For small x, 1 - e
     // cancels; there g/s' and (lambda e s' - g)/s'^2 come from their series
     //   g/s' = lambda (1 - x/2 + x^2/6 - x^3/24 + x^4/120),
     //   (lambda e s' - g)/s'^2 = lambda^2 (-1/2 + x/3 - x^2/8 + x^3/30 - x^4/144).
     // (The test is on s' against the cut divided by lambda, a loop invariant.)
-    if (s < series_cut<T>() / lambda) {
+    if (SERIES && s < series_cut<T>() / lambda) {
         const T x = lambda * s;
         gr = lambda * fma(x, fma(x, fma(x, fma(x, (T)(1.0 / 120), (T)(-1.0 / 24)), (T)(1.0 / 6)), (T)-0.5), (T)1);
         h = lambda * lambda *
@@ -514,24 +520,28 @@ __device__ __forceinline__ void p2p_bwd_pair(const rec_t<T> &rj, const c2<T> qj,
     }
 }
 
-template <typename T, int K, bool FAR, bool SRC>
+template <typename T, int K, bool FAR, bool SRC, bool SERIES = true>
 __device__ __forceinline__ void p2p_bwd_tile(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
                                              T lambda, T (&acc)[SRC ? 9 : 5])
 {
     if (len == 64) {
 #pragma unroll 4
         for (int it = 0; it < 64 / K; ++it)
-            p2p_bwd_pair<T, FAR, SRC>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc);
+            p2p_bwd_pair<T, FAR, SRC, SERIES>(tile[k + it * K], qtile[k + it * K], tx, ty, lambda, acc);
     } else {
-        for (int j = k; j < len; j += K) p2p_bwd_pair<T, FAR, SRC>(tile[j], qtile[j], tx, ty, lambda, acc);
+        for (int j = k; j < len; j += K) p2p_bwd_pair<T, FAR, SRC, SERIES>(tile[j], qtile[j], tx, ty, lambda, acc);
     }
 }
 
+// cls 2: every pair of the tile is beyond the exponential's cut (point-vortex terms);
+// 1: beyond the series cut (no per-pair test; units of one or two lanes per target,
+// which carry nearly all pairs, so the other unrolled variants stay few); 0: the full form.
 template <typename T, int K, bool SRC>
 __device__ __forceinline__ void p2p_bwd_tile_any(const rec_t<T> *tile, const c2<T> *qtile, int len, int k, T tx, T ty,
-                                                 T lambda, T (&acc)[SRC ? 9 : 5], bool far)
+                                                 T lambda, T (&acc)[SRC ? 9 : 5], int cls)
 {
-    if (far) p2p_bwd_tile<T, K, true, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
+    if (cls == 2) p2p_bwd_tile<T, K, true, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
+    else if (K <= 2 && cls == 1) p2p_bwd_tile<T, K, false, SRC, false>(tile, qtile, len, k, tx, ty, lambda, acc);
     else p2p_bwd_tile<T, K, false, SRC>(tile, qtile, len, k, tx, ty, lambda, acc);
 }
 

@@ -1054,8 +1054,9 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
                                                   const int *__restrict__ leaf_start,
                                                   const int *__restrict__ tile_start,
                                                   const float4 *__restrict__ tile_box, int nside, T step,
-                                                  float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
-                                                  double *__restrict__ out_b, double4 *__restrict__ out_src)
+                                                  float cut_leaf2, float series_leaf2, T lambda,
+                                                  double4 *__restrict__ out_pa, double *__restrict__ out_b,
+                                                  double4 *__restrict__ out_src)
 {
     constexpr int NA = SRC ? 9 : 5;
     const int lane = threadIdx.x;
@@ -1087,16 +1088,17 @@ __device__ __forceinline__ void p2p_backward_unit(const int4 u, rec_t<T> *tile, 
                     tile[lane] = rec(base + lane);
                     qtile[lane] = qv[base + lane];
                 }
-                const bool far = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]) >= cut_leaf2;
+                const float gap2 = box_gap2(tbox, (float)-dx, (float)-dy, tile_box[tt]);
+                const int cls = gap2 >= cut_leaf2 ? 2 : gap2 >= series_leaf2 ? 1 : 0;
                 __syncthreads();
                 switch (logtp) {
-                case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
-                default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, far); break;
+                case 6: p2p_bwd_tile_any<T, 1, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                case 5: p2p_bwd_tile_any<T, 2, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                case 4: p2p_bwd_tile_any<T, 4, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                case 3: p2p_bwd_tile_any<T, 8, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                case 2: p2p_bwd_tile_any<T, 16, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                case 1: p2p_bwd_tile_any<T, 32, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
+                default: p2p_bwd_tile_any<T, 64, SRC>(tile, qtile, len, k, tx, ty, lambda, acc, cls); break;
                 }
             }
 #pragma unroll
@@ -1118,14 +1120,14 @@ template <typename T, bool SRC>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? (SRC ? 5 : 6) : 2) void p2p_backward_kernel(
     const int4 *__restrict__ units, const c2<T> *__restrict__ pos, const T *__restrict__ gam,
     const c2<T> *__restrict__ qv, const int *__restrict__ leaf_start, const int *__restrict__ tile_start,
-    const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2, T lambda, double4 *__restrict__ out_pa,
-    double *__restrict__ out_b, double4 *__restrict__ out_src)
+    const float4 *__restrict__ tile_box, int nside, T step, float cut_leaf2, float series_leaf2, T lambda,
+    double4 *__restrict__ out_pa, double *__restrict__ out_b, double4 *__restrict__ out_src)
 {
     __shared__ rec_t<T> tile[64];
     __shared__ c2<T> qtile[64];
     const SoaRec<T> rec{pos, gam, step};
     p2p_backward_unit<T, SRC>(units[blockIdx.x], tile, qtile, rec, qv, leaf_start, tile_start, tile_box, nside, step,
-                              cut_leaf2, lambda, out_pa, out_b, out_src);
+                              cut_leaf2, series_leaf2, lambda, out_pa, out_b, out_src);
 }
 
 // Adjoint finalize: far parts from the q-field locals (Phi_far, by L2P) and the c-field
@@ -1564,27 +1566,31 @@ void launch_p2p_backward(const fmm_tree *t, const void *pos, const void *gam, co
     const double cut = is_double ? 39.0 : 27.0;
     const float cut_leaf2 = (float)(cut / (step * step));
     const unsigned grid = (unsigned)t->nunits;
-    const float ln2 = (float)0.69314718055994530942;
+    const double ln2 = 0.69314718055994530942;
+    // the series of the pair code applies below s' = (0.125 / ln 2) in FP32 (natural exponent
+    // 0.125) and 1e-3 in FP64; tiles whose boxes are twice that apart skip the test
+    const double series_s = is_double ? 1e-3 : 0.125 / ln2;
+    const float series_leaf2 = (float)(2.0 * series_s / (step * step));
     if (is_double) {
         if (out_src)
             p2p_backward_kernel<double, true><<<grid, 64, 0, s>>>(
-                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv,
-                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, out_src);
+                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv, t->d_leaf_start,
+                t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, series_leaf2, 1.0, out_pa, out_b, out_src);
         else
             p2p_backward_kernel<double, false><<<grid, 64, 0, s>>>(
-                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv,
-                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, 1.0, out_pa, out_b, nullptr);
+                t->d_units, (const double2 *)pos, (const double *)gam, (const double2 *)qv, t->d_leaf_start,
+                t->d_tile_start, t->d_tile_box, nside, step, cut_leaf2, series_leaf2, 1.0, out_pa, out_b, nullptr);
     } else {
         if (out_src)
             p2p_backward_kernel<float, true><<<grid, 64, 0, s>>>(
-                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv,
-                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
-                out_src);
+                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv, t->d_leaf_start,
+                t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, series_leaf2, (float)ln2, out_pa,
+                out_b, out_src);
         else
             p2p_backward_kernel<float, false><<<grid, 64, 0, s>>>(
-                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv,
-                t->d_leaf_start, t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, ln2, out_pa, out_b,
-                nullptr);
+                t->d_units, (const float2 *)pos, (const float *)gam, (const float2 *)qv, t->d_leaf_start,
+                t->d_tile_start, t->d_tile_box, nside, (float)step, cut_leaf2, series_leaf2, (float)ln2, out_pa,
+                out_b, nullptr);
     }
 }
 
