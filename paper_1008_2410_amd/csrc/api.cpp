@@ -279,6 +279,16 @@ bool call_overlaps(const fmm_tree *t, int precision)
     return far_near_ratio(t) <= kSerialRatio;
 }
 
+// In an overlapped call whose far chain is predicted clearly longer than the near field
+// (r >= 1.4), the near field starts once P2M is done: beside the near field's workgroups
+// P2M gets few slots, and the whole far chain waits for it (the 1024^2 lattice, depth 8,
+// p = 12, coarse levels <= 5, r = 2.2: FP64 0.730 -> 0.705 ms, mixed 0.597 -> 0.573; uniform
+// 2^20 particles at depths 7-9, r = 1.45-2.25: 0.23 ms less over the 12 points).  Nearer
+// r = 1, P2M beside the near field costs less than the delay (uniform 2^22 particles at
+// depth 10, r = 1.22: 3.65 against 3.88 ms with the wait), and far below it much less
+// (2^24 patches, depth 10: 8.17 against 8.34 ms).
+bool p2m_first(const fmm_tree *t) { return t->depth >= 2 && far_near_ratio(t) >= 1.4; }
+
 // Near-field occupancy cap of a call (FMM_OPT_NEAR_OCCUPANCY), automatic from the tree:
 //  - mixed, leaves of more than ~2500 near-field pairs per particle and a work list of at
 //    least 64K entries (2^22-2^24 patch particles at depths 8-9): 3 wavefronts per SIMD, at
@@ -434,7 +444,16 @@ int run_forward(fmm_tree *t, const double *gamma, double sigma, int p, int preci
     launch_pack(t, is_double, ws.gam, ms);
     tm.mark(1, ms);
     tm.mark(2, ss);
-    launch_far_chain(a, ss);
+    if (overlap && p2m_first(t)) {
+        // the far chain is the longer part: P2M, its first and widest kernel, runs beside
+        // pack alone instead of being starved by the near field's workgroups
+        launch_p2m(a, ss);
+        HIP_TRY(hipEventRecord(t->ev_fork, ss));
+        launch_far_chain(a, ss, false);
+        HIP_TRY(hipStreamWaitEvent(ms, t->ev_fork, 0));
+    } else {
+        launch_far_chain(a, ss);
+    }
     tm.mark(3, ss);
     if (overlap) HIP_TRY(hipEventRecord(t->ev_join, ss));
     void *slots = use_mutual(t) ? ws.slots : nullptr;
