@@ -117,9 +117,10 @@ enum {
  * a particle outside [x0, x0 + side]^2 gives FMM_ERANGE, a non-finite one FMM_EINVAL
  * (the message names the lowest offending index).
  * The build runs on the device (binning, a stable radix sort by leaf and sub-leaf
- * Morton key, leaf offsets, cell lists, work lists) and synchronises `stream`; the tree
- * owns its device buffers, and workspace for each (p, precision) is allocated on first
- * use and kept until fmm_destroy_tree.
+ * Morton key, leaf offsets, cell lists, work lists) and synchronises `stream`; then, the
+ * device synchronised, its temporaries' memory goes back from the stream-ordered pool to
+ * the device.  The tree owns its device buffers, and workspace for each (p, precision)
+ * is allocated on first use and kept until fmm_destroy_tree.
  */
 int fmm_build_tree(const double *xy, int64_t n, int depth, const double *root_box, void *stream,
                    fmm_tree **out);
@@ -312,7 +313,8 @@ int fmm_get_timings(fmm_tree *tree, double *ms, int64_t *calls);
  * the recorded events.  FMM_ESTATE when no such call is pending. */
 int fmm_get_timeline(fmm_tree *tree, double *ms, int count);
 
-/* Free a tree and its device memory (synchronises the device first).  NULL is a no-op. */
+/* Free a tree and its device memory (synchronises the device first); the memory goes
+ * back from the stream-ordered pool to the device.  NULL is a no-op. */
 void fmm_destroy_tree(fmm_tree *tree);
 
 /* Message for the last failed call on this host thread ("" if none). */

@@ -68,7 +68,8 @@ enum {
  * side (1 + 2^-20) max(range x, range y).  Returns FMM_EINVAL for bad arguments or a
  * non-finite position, FMM_ERANGE (naming the particle) for a particle outside root_box,
  * FMM_ENOMEM / FMM_EDEVICE on allocation or runtime failures.  *out owns its device
- * memory until fmm_atree_destroy. */
+ * memory until fmm_atree_destroy.  The device is synchronised at the end, and the
+ * temporaries' memory goes back from the stream-ordered pool to the device. */
 int fmm_atree_build(const double *xy, int64_t n, int max_leaf, int max_depth, const double *root_box, void *stream,
                     fmm_atree **out);
 
@@ -160,8 +161,9 @@ int fmm_atree_transport_vjp(fmm_atree *tree, const double *gamma, double sigma, 
                             const double *lam, double h, int flags, void *main_stream, void *side_stream,
                             double *dl_dgamma, double *dl_dx);
 
-/* Frees the tree and its device memory (after the device work using it is done);
- * NULL is ignored. */
+/* Frees the tree and its device memory (after the device work using it is done; the
+ * device is synchronised and the memory goes back from the stream-ordered pool to the
+ * device); NULL is ignored. */
 void fmm_atree_destroy(fmm_atree *tree);
 
 #ifdef __cplusplus
