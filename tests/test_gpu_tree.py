@@ -236,3 +236,25 @@ def test_rebuild_holds_one_tree(fmm_mod):
     _same_tree_outputs(tree, fresh, g, sigma, p, dl)
     fresh.close()
     tree.close()
+
+
+def test_rebuild_without_workspace(fmm_mod):
+    """A rebuild before any evaluation (no workspace yet, so the build's temporaries come
+    from the pool) gives the tree a fresh build gives, bit for bit; so does a second
+    rebuild after an evaluation (temporaries in the workspace's per-call region)."""
+    r = np.random.Generator(np.random.PCG64(41))
+    n, depth, p, sigma = 30000, 5, 10, 0.004
+    box = (0.0, 0.0, 1.0)
+    x0, x1, x2 = (_t(r.random((n, 2))) for _ in range(3))
+    g = _t(r.standard_normal(n))
+    dl = _t(r.standard_normal((n, 2)))
+    tree = fmm_mod.Tree(x0, depth, box)
+    tree.rebuild(x1, box)
+    fresh = fmm_mod.Tree(x1, depth, box)
+    _same_tree_outputs(tree, fresh, g, sigma, p, dl)
+    fresh.close()
+    tree.rebuild(x2, box)
+    fresh = fmm_mod.Tree(x2, depth, box)
+    _same_tree_outputs(tree, fresh, g, sigma, p, dl)
+    fresh.close()
+    tree.close()
