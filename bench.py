@@ -90,6 +90,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def adjoint_only_leg(torch, dev, tree, w, gamma, info, args):
+    """The adjoint of the headline configuration alone (mixed, dL/dGamma and dL/dx_eval for a
+    seeded cotangent): warm-up calls, then `steps` timed calls with the stage events, and the
+    rate of the adjoint near field (target-centric: every ordered near pair evaluated once,
+    about 19 VALU operations and two transcendentals each)."""
+    from paper_1008_2410_amd import _lib
+    dl = torch.empty((w.n, 2), dtype=torch.float64, device=dev).normal_(generator=torch.Generator(dev).manual_seed(0))
+    for _ in range(args.warmup):
+        tree.velocity_backward(gamma, w.sigma, w.p, "mixed", dl)
+    tree.set_option(_lib.FMM_OPT_TIMING, 1)
+    tree.timings()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        tree.velocity_backward(gamma, w.sigma, w.p, "mixed", dl)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = tree.timings()
+    tree.set_option(_lib.FMM_OPT_TIMING, 0)
+    stages = {k: round(v / st["calls"], 4) for k, v in st.items() if k != "calls"}
+    pairs = info["p2p_pairs"]
+    print(json.dumps({"adjoint": "mixed", "ms_per_step": round(ms, 4), "stages_ms": stages,
+                      "near_kernel": "p2p_backward_kernel<float, false>", "pairs_per_launch": pairs,
+                      "pair_evaluations_per_s": round(pairs / (stages["p2p"] * 1e-3), 1),
+                      "kernel_sources": kernel_sources_hash(), "steps": args.steps, "warmup": args.warmup}),
+          flush=True)
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -402,6 +432,9 @@ def main():
                     help="CPU oracle leg on the first N/4^k particles at depth L-k (default 0: the whole workload)")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--bwd-steps", type=int, default=3)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the timed adjoint of the headline configuration (mixed; dL/dGamma and dL/dx_eval), "
+                         "for kernel profiling of exactly that work")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed headline region (for kernel profiling of exactly that work)")
     ap.add_argument("--headline-precision", choices=["mixed", "fp64"], default="mixed",
@@ -469,6 +502,9 @@ def main():
     plan = tree.near_plan()
     log(f"[bench] tree built on the device in {t_build:.3f} s: {info}; near-field plan {plan}")
     out = torch.empty((w.n, 2), dtype=torch.float64, device=dev)
+    if args.adjoint_only:
+        adjoint_only_leg(torch, dev, tree, w, gamma, info, args)
+        return
 
     def run(k, precision="mixed"):
         for _ in range(k):
