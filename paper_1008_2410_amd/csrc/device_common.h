@@ -141,16 +141,16 @@ __device__ __forceinline__ double one_minus_exp(double s)
     return g;
 }
 __device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
-// FP64: the hardware reciprocal estimate refined by two Newton steps r += r (1 - s r), each
-// doubling the correct bits (within an ulp of 1/s, not correctly rounded): 5 instructions
-// against about 10 for the IEEE division, on a positive normal s (s >= tiny).
+// FP64: the hardware reciprocal estimate (relative error below 2^-24, measured) refined by
+// one cubic step r + r (d + d^2), d = 1 - s r, which triples the correct bits: within an ulp
+// of 1/s (equal to the IEEE quotient on 4M sampled s in [1e-3, 1e6], measured; not
+// guaranteed correctly rounded), 4 instructions against 5 for two Newton steps and about 10
+// for the division, on a positive normal s (s >= tiny).
 __device__ __forceinline__ double recip(double s)
 {
-    double r = __builtin_amdgcn_rcp(s);
-    double e = fma(-s, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-s, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(s);
+    const double d = fma(-s, r, 1.0);
+    return fma(r, fma(d, d, d), r);
 }
 // Added to every s: a pair at distance 0 (the particle itself) then gives g = 0 and a
 // finite Gamma/s (for |Gamma| < 1e18 in FP32), hence exactly zero, while any s above
