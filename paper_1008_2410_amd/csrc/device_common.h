@@ -106,28 +106,27 @@ template <typename T> struct SoaRec {
 __device__ __forceinline__ float one_minus_exp(float s) { return 1.0f - __builtin_amdgcn_exp2f(-s); }
 // FP64 e = exp(-s) and g = 1 - e for s >= 0, g without cancellation: Cody-Waite reduction
 // s = k ln2 + r, |r| <= ln2/2 (ln2 as a high part with 21 trailing zero bits, so that k ln2_hi
-// is exact, plus the rest), the Taylor series of expm1(-r) to degree 13 (truncation below
-// 2^-56 of |expm1(-r)|), then e = 2^-k (1 + em1) and g = (1 - 2^-k) - 2^-k em1, where
-// 1 - 2^-k is exact.  Within about 2 ulp of both; 2^-k underflows to 0 for large s (e = 0,
-// g = 1).  Branch-free, 22 instructions.
+// is exact, plus the rest), expm1(x) = x p(x) at x = -r with p of degree 10 (the Taylor series
+// of expm1(x)/x economized by Chebyshev polynomials on |x| <= 0.3467, in exact rational
+// arithmetic, coefficients rounded to double: within 2.3e-17 of p), then e = 2^-k (1 + em1)
+// and g = (1 - 2^-k) - 2^-k em1, where 1 - 2^-k is exact.  Within about 2 ulp of both; 2^-k
+// underflows to 0 for large s (e = 0, g = 1).  Branch-free, 20 instructions.
 __device__ __forceinline__ void exp_pair(double s, double &e, double &g)
 {
     constexpr double kInvLn2 = 1.4426950408889634, kLn2Hi = 6.93147180369123816490e-01,
                      kLn2Lo = 1.90821492927058770002e-10;
     const double k = rint(s * kInvLn2);
     const double x = -fma(-k, kLn2Lo, fma(-k, kLn2Hi, s));  // -(s - k ln2)
-    double p = 1.0 / 6227020800.0;                          // 1/13!
-    p = fma(p, x, 1.0 / 479001600.0);
-    p = fma(p, x, 1.0 / 39916800.0);
-    p = fma(p, x, 1.0 / 3628800.0);
-    p = fma(p, x, 1.0 / 362880.0);
-    p = fma(p, x, 1.0 / 40320.0);
-    p = fma(p, x, 1.0 / 5040.0);
-    p = fma(p, x, 1.0 / 720.0);
-    p = fma(p, x, 1.0 / 120.0);
-    p = fma(p, x, 1.0 / 24.0);
-    p = fma(p, x, 1.0 / 6.0);
-    p = fma(p, x, 0.5);
+    double p = 2.5110080609180445e-08;
+    p = fma(p, x, 2.7626408708679167e-07);
+    p = fma(p, x, 2.7557240802111588e-06);
+    p = fma(p, x, 2.4801504223004426e-05);
+    p = fma(p, x, 0.000198412698901562);
+    p = fma(p, x, 0.0013888888932586684);
+    p = fma(p, x, 0.00833333333331956);
+    p = fma(p, x, 0.04166666666657286);
+    p = fma(p, x, 0.1666666666666668);
+    p = fma(p, x, 0.5000000000000006);
     p = fma(p, x, 1.0);
     const double em1 = p * x;  // expm1(-r)
     const double t = ldexp(1.0, -(int)k);
